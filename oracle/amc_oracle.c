@@ -1,0 +1,821 @@
+/*
+ * amc_oracle.c -- CPU oracle for absorbing-frequency centrality (AFC).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, single-threaded,
+ * obviously-correct FP64 statement of what the GPU library computes.  Only the
+ * test-suite, the package smoke check and the benchmark's CPU-baseline leg may
+ * load it; the product path never does.  It shares no source, header, helper
+ * or generated table with the GPU library: its Philox generator, its
+ * shortest-path code, its betweenness, its centre selection and its chain
+ * algebra are all written here from their published definitions.
+ *
+ * Paper: W. Bao, E. Kontou, C. Vogiatzis, "Betweenness-Central Nodes Under
+ * Uncertainty: An Absorbing Markov Chain Approach".  Section / equation
+ * citations below refer to that paper.
+ *
+ * Readings of points the paper leaves open (each is listed in the design
+ * notes of the repository):
+ *   - realizations are drawn with Philox4x32-10 keyed by the 64-bit seed; the
+ *     edge (u<v) of realization r uses counter (r, u, v, 0), the exogenous stop
+ *     coin of anchor i uses counter (r, i, 0xFFFFFFFF, 1);
+ *   - uniforms are mapped to events with integers only: an event of
+ *     probability p fires when the 32-bit draw is below floor(p * 2^32);
+ *     integer weights in [lo, hi] are lo + ((x * (hi-lo+1)) >> 32);
+ *   - every realization serves every anchor (one realization count R = M);
+ *   - the deterministic tie rule is "smallest index inside a relative tie
+ *     band": v is a co-maximiser of a set when max - B_v <= tau*max(max, 1);
+ *   - the floor on an empty absorption column is eta (default 0.1/sqrt(R)).
+ *
+ * Parity pins: every exported function below is pinned by the CPU tests
+ * (tests/test_oracle_*.py) against closed forms, brute force, the values the
+ * paper prints for its worked examples, or an independent library.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_NOMEM (-2)
+#define OR_E_SIGMA (-4)
+#define OR_E_SINGULAR (-5)
+
+#define OR_WEIGHT_UNIT 0
+#define OR_WEIGHT_UNIFORM 1
+#define OR_WEIGHT_FIXED 2
+
+#define OR_INF UINT64_MAX
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the */
+/* round keys bumped by the Weyl constants between rounds.                   */
+/* ------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    int round;
+    for (round = 0; round < 10; ++round) {
+        uint64_t p0, p1;
+        uint32_t y0, y1, y2, y3;
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        y1 = (uint32_t)p1;
+        y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* An event of probability p fires for a uniform 32-bit draw x iff x < T(p),
+ * T(p) = floor(p * 2^32) clamped to [0, 2^32].  Multiplying by 2^32 and the
+ * floor are exact in binary64, so T is a pure function of p. */
+uint64_t or_prob_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return 4294967296ull;
+    return (uint64_t)floor(p * 4294967296.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Base graph: undirected, simple, canonical edge list (u < v, sorted).     */
+/* Section 3.1: base topology G(V,E).                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int32_t *eu, *ev;      /* canonical edges, eu[e] < ev[e]         */
+    int64_t *off;                /* adjacency offsets, length n+1           */
+    int32_t *nbr;                /* neighbour of each adjacency slot        */
+    int64_t *eid;                /* edge id of each adjacency slot          */
+} or_graph;
+
+static void or_graph_free(or_graph *g)
+{
+    free(g->off); free(g->nbr); free(g->eid);
+    g->off = NULL; g->nbr = NULL; g->eid = NULL;
+}
+
+/* Builds adjacency lists of the base graph.  Rejects self-loops, vertices out
+ * of range, non-canonical (u >= v) and repeated edges. */
+static int or_graph_init(or_graph *g, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev)
+{
+    int64_t e, *fill;
+    int32_t v;
+    memset(g, 0, sizeof(*g));
+    if (n < 1 || m < 0) return OR_E_ARG;
+    for (e = 0; e < m; ++e) {
+        if (eu[e] < 0 || ev[e] >= n || eu[e] >= ev[e]) return OR_E_ARG;
+        if (e > 0 && (eu[e - 1] > eu[e] || (eu[e - 1] == eu[e] && ev[e - 1] >= ev[e]))) return OR_E_ARG;
+    }
+    g->n = n; g->m = m; g->eu = eu; g->ev = ev;
+    g->off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    g->nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    g->eid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
+    fill = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!g->off || !g->nbr || !g->eid || !fill) { free(fill); or_graph_free(g); return OR_E_NOMEM; }
+    for (e = 0; e < m; ++e) { g->off[eu[e] + 1]++; g->off[ev[e] + 1]++; }
+    for (v = 0; v < n; ++v) g->off[v + 1] += g->off[v];
+    for (e = 0; e < m; ++e) {
+        int32_t a = eu[e], b = ev[e];
+        g->nbr[g->off[a] + fill[a]] = b; g->eid[g->off[a] + fill[a]] = e; fill[a]++;
+        g->nbr[g->off[b] + fill[b]] = a; g->eid[g->off[b] + fill[b]] = e; fill[b]++;
+    }
+    free(fill);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One network state (Section 3.1): which edges survive and their positive   */
+/* integer weights.  Alg. 1 "sample omega" with the integer-only mapping.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double p_fail;               /* failure probability of every edge       */
+    const double *p_fail_edge;   /* optional per-edge failure probabilities */
+    int32_t weight_kind;         /* OR_WEIGHT_*                             */
+    uint32_t w_lo, w_hi;         /* range of OR_WEIGHT_UNIFORM              */
+    const uint32_t *w0;          /* weights of OR_WEIGHT_FIXED              */
+} or_model;
+
+int or_realize(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
+               uint64_t seed, uint32_t r, uint8_t *alive, uint32_t *w)
+{
+    int64_t e;
+    uint32_t key[2];
+    (void)n;
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    for (e = 0; e < m; ++e) {
+        uint32_t ctr[4], x[4];
+        double p = mod->p_fail_edge ? mod->p_fail_edge[e] : mod->p_fail;
+        ctr[0] = r; ctr[1] = (uint32_t)eu[e]; ctr[2] = (uint32_t)ev[e]; ctr[3] = 0;
+        or_philox4x32_10(ctr, key, x);
+        alive[e] = ((uint64_t)x[0] >= or_prob_threshold(p)) ? 1 : 0;
+        if (mod->weight_kind == OR_WEIGHT_UNIT) {
+            w[e] = 1;
+        } else if (mod->weight_kind == OR_WEIGHT_UNIFORM) {
+            uint64_t span = (uint64_t)mod->w_hi - (uint64_t)mod->w_lo + 1u;
+            w[e] = mod->w_lo + (uint32_t)(((uint64_t)x[1] * span) >> 32);
+        } else {
+            w[e] = mod->w0[e];
+        }
+    }
+    return OR_OK;
+}
+
+/* Exogenous stop coin of anchor i in realization r (Alg. 1: the draw omega
+ * includes the stopping event; its probability is alpha). */
+int or_stop_coin(uint64_t seed, uint32_t r, int32_t i, double alpha)
+{
+    uint32_t ctr[4], key[2], x[4];
+    key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
+    ctr[0] = r; ctr[1] = (uint32_t)i; ctr[2] = 0xFFFFFFFFu; ctr[3] = 1u;
+    or_philox4x32_10(ctr, key, x);
+    return (uint64_t)x[0] < or_prob_threshold(alpha);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-source shortest paths with path counts on a realization H         */
+/* (Section 3.1: d_H(s,t) and sigma_st(H)).  Unit weights: breadth-first     */
+/* search; integer weights: Dijkstra with a binary heap.  sigma is an exact  */
+/* uint64; an addition that would wrap returns OR_E_SIGMA.  `order` receives */
+/* the reached vertices in non-decreasing distance.                          */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint64_t key; int32_t v; } or_heap_item;
+
+static void heap_push(or_heap_item *h, int64_t *size, uint64_t key, int32_t v)
+{
+    int64_t i = (*size)++;
+    h[i].key = key; h[i].v = v;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].key <= h[i].key) break;
+        { or_heap_item t = h[p]; h[p] = h[i]; h[i] = t; }
+        i = p;
+    }
+}
+
+static or_heap_item heap_pop(or_heap_item *h, int64_t *size)
+{
+    or_heap_item top = h[0];
+    int64_t i = 0;
+    h[0] = h[--(*size)];
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, s = i;
+        if (l < *size && h[l].key < h[s].key) s = l;
+        if (r < *size && h[r].key < h[s].key) s = r;
+        if (s == i) break;
+        { or_heap_item t = h[s]; h[s] = h[i]; h[i] = t; }
+        i = s;
+    }
+    return top;
+}
+
+static int add_sigma(uint64_t *dst, uint64_t add)
+{
+    if (*dst > UINT64_MAX - add) return OR_E_SIGMA;
+    *dst += add;
+    return OR_OK;
+}
+
+static int or_sssp_graph(const or_graph *g, const uint8_t *alive, const uint32_t *w, int unit, int32_t s,
+                         uint64_t *dist, uint64_t *sigma, int32_t *order, int32_t *n_order)
+{
+    int32_t n = g->n, v, cnt = 0;
+    for (v = 0; v < n; ++v) { dist[v] = OR_INF; sigma[v] = 0; }
+    dist[s] = 0; sigma[s] = 1;
+    if (unit) {
+        int32_t head = 0;
+        order[cnt++] = s;
+        while (head < cnt) {
+            int32_t x = order[head++];
+            int64_t k;
+            for (k = g->off[x]; k < g->off[x + 1]; ++k) {
+                int32_t y = g->nbr[k];
+                if (!alive[g->eid[k]]) continue;
+                if (dist[y] == OR_INF) { dist[y] = dist[x] + 1; order[cnt++] = y; }
+                if (dist[y] == dist[x] + 1) {
+                    if (add_sigma(&sigma[y], sigma[x]) != OR_OK) return OR_E_SIGMA;
+                }
+            }
+        }
+    } else {
+        int64_t hsize = 0;
+        uint8_t *done = (uint8_t *)calloc((size_t)n, 1);
+        or_heap_item *heap = (or_heap_item *)malloc(sizeof(or_heap_item) * (size_t)(2 * g->m + 2));
+        if (!done || !heap) { free(done); free(heap); return OR_E_NOMEM; }
+        heap_push(heap, &hsize, 0, s);
+        while (hsize > 0) {
+            or_heap_item it = heap_pop(heap, &hsize);
+            int32_t x = it.v;
+            int64_t k;
+            if (done[x] || it.key != dist[x]) continue;
+            done[x] = 1;
+            order[cnt++] = x;
+            for (k = g->off[x]; k < g->off[x + 1]; ++k) {
+                int32_t y = g->nbr[k];
+                uint64_t nd;
+                if (!alive[g->eid[k]]) continue;
+                nd = dist[x] + (uint64_t)w[g->eid[k]];
+                if (nd < dist[y]) {
+                    dist[y] = nd; sigma[y] = sigma[x];
+                    heap_push(heap, &hsize, nd, y);
+                } else if (nd == dist[y]) {
+                    if (add_sigma(&sigma[y], sigma[x]) != OR_OK) { free(done); free(heap); return OR_E_SIGMA; }
+                }
+            }
+        }
+        free(done); free(heap);
+    }
+    *n_order = cnt;
+    return OR_OK;
+}
+
+/* Dependencies of source s (Brandes' accumulation of the pair terms of the
+ * Section 3.1 definition): vertices are taken in non-increasing distance and
+ * each one w passes (sigma_v / sigma_w) * (1 + delta_w) to every predecessor v,
+ * i.e. every v joined to w by a surviving edge with d_v + w_vw = d_w. */
+static void or_dependency(const or_graph *g, const uint8_t *alive, const uint32_t *w, int unit,
+                          const uint64_t *dist, const uint64_t *sigma, const int32_t *order,
+                          int32_t n_order, double *delta)
+{
+    int32_t v, k;
+    for (v = 0; v < g->n; ++v) delta[v] = 0.0;
+    for (k = n_order - 1; k >= 0; --k) {
+        int32_t x = order[k];
+        int64_t j;
+        for (j = g->off[x]; j < g->off[x + 1]; ++j) {
+            int32_t y = g->nbr[j];
+            uint64_t wt;
+            if (!alive[g->eid[j]]) continue;
+            wt = unit ? 1u : (uint64_t)w[g->eid[j]];
+            if (dist[y] != OR_INF && dist[y] + wt == dist[x])
+                delta[y] += ((double)sigma[y] / (double)sigma[x]) * (1.0 + delta[x]);
+        }
+    }
+}
+
+/* Exported single-source dump (for the distance / path-count / dependency
+ * parity checks). */
+int or_sssp(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const uint8_t *alive,
+            const uint32_t *w, int unit, int32_t s, uint64_t *dist, uint64_t *sigma, double *delta)
+{
+    or_graph g;
+    int32_t *order, n_order = 0;
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    if (s < 0 || s >= n) { or_graph_free(&g); return OR_E_ARG; }
+    order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!order) { or_graph_free(&g); return OR_E_NOMEM; }
+    rc = or_sssp_graph(&g, alive, w, unit, s, dist, sigma, order, &n_order);
+    if (rc == OR_OK && delta) or_dependency(&g, alive, w, unit, dist, sigma, order, n_order, delta);
+    free(order); or_graph_free(&g);
+    return rc;
+}
+
+/* Non-normalised weighted betweenness B_v(H) of Section 3.1 (ordered pairs,
+ * unreachable pairs contribute 0), by summing the dependencies of every
+ * source s (delta_s(v), v != s). */
+static int or_brandes_graph(const or_graph *g, const uint8_t *alive, const uint32_t *w, int unit,
+                            double *B, uint64_t *dist, uint64_t *sigma, int32_t *order, double *delta)
+{
+    int32_t s, v, n = g->n;
+    for (v = 0; v < n; ++v) B[v] = 0.0;
+    for (s = 0; s < n; ++s) {
+        int32_t n_order = 0;
+        int rc = or_sssp_graph(g, alive, w, unit, s, dist, sigma, order, &n_order);
+        if (rc != OR_OK) return rc;
+        or_dependency(g, alive, w, unit, dist, sigma, order, n_order, delta);
+        for (v = 0; v < n; ++v)
+            if (v != s) B[v] += delta[v];
+    }
+    return OR_OK;
+}
+
+int or_betweenness(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const uint8_t *alive,
+                   const uint32_t *w, int unit, double *B)
+{
+    or_graph g;
+    uint64_t *dist, *sigma;
+    int32_t *order;
+    double *delta;
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    dist = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    sigma = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    delta = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!dist || !sigma || !order || !delta) rc = OR_E_NOMEM;
+    else rc = or_brandes_graph(&g, alive, w, unit, B, dist, sigma, order, delta);
+    free(dist); free(sigma); free(order); free(delta); or_graph_free(&g);
+    return rc;
+}
+
+/* The same B_v(H) written as the definition of Section 3.1: for every ordered
+ * pair (s,t), s != t, both != v, with d(s,t) finite, add the fraction of the
+ * shortest s-t paths that run through v, sigma_sv * sigma_vt / sigma_st when
+ * d(s,v) + d(v,t) = d(s,t) and 0 otherwise.  O(n^3); used to pin the Brandes
+ * form on small graphs. */
+int or_betweenness_pairs(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const uint8_t *alive,
+                         const uint32_t *w, int unit, double *B)
+{
+    or_graph g;
+    uint64_t *D, *S;
+    int32_t *order, s, t, v;
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    D = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * (size_t)n);
+    S = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * (size_t)n);
+    order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!D || !S || !order) { free(D); free(S); free(order); or_graph_free(&g); return OR_E_NOMEM; }
+    for (s = 0; s < n && rc == OR_OK; ++s) {
+        int32_t n_order;
+        rc = or_sssp_graph(&g, alive, w, unit, s, D + (size_t)s * n, S + (size_t)s * n, order, &n_order);
+    }
+    for (v = 0; v < n && rc == OR_OK; ++v) {
+        double acc = 0.0;
+        for (s = 0; s < n; ++s) {
+            uint64_t dsv;
+            if (s == v) continue;
+            dsv = D[(size_t)s * n + v];
+            if (dsv == OR_INF) continue;
+            for (t = 0; t < n; ++t) {
+                uint64_t dst, dvt;
+                if (t == v || t == s) continue;
+                dst = D[(size_t)s * n + t];
+                dvt = D[(size_t)v * n + t];
+                if (dst == OR_INF || dvt == OR_INF) continue;
+                if (dsv + dvt == dst)
+                    acc += (double)S[(size_t)s * n + v] * (double)S[(size_t)v * n + t] / (double)S[(size_t)s * n + t];
+            }
+        }
+        B[v] = acc;
+    }
+    free(D); free(S); free(order); or_graph_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Components K(i;H) (Section 3.2): comp[v] = smallest vertex index of the   */
+/* component containing v, size[v] = |K(v;H)|.                              */
+/* ------------------------------------------------------------------------ */
+static int or_components_graph(const or_graph *g, const uint8_t *alive, int32_t *comp, int32_t *size,
+                               int32_t *queue)
+{
+    int32_t n = g->n, v;
+    for (v = 0; v < n; ++v) comp[v] = -1;
+    for (v = 0; v < n; ++v) {
+        int32_t head = 0, cnt = 0, k;
+        if (comp[v] >= 0) continue;
+        comp[v] = v; queue[cnt++] = v;
+        while (head < cnt) {
+            int32_t x = queue[head++];
+            int64_t j;
+            for (j = g->off[x]; j < g->off[x + 1]; ++j) {
+                int32_t y = g->nbr[j];
+                if (!alive[g->eid[j]] || comp[y] >= 0) continue;
+                comp[y] = v; queue[cnt++] = y;
+            }
+        }
+        for (k = 0; k < cnt; ++k) size[queue[k]] = cnt;
+    }
+    return OR_OK;
+}
+
+int or_components(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const uint8_t *alive,
+                  int32_t *comp, int32_t *size)
+{
+    or_graph g;
+    int32_t *queue;
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!queue) { or_graph_free(&g); return OR_E_NOMEM; }
+    rc = or_components_graph(&g, alive, comp, size, queue);
+    free(queue); or_graph_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tie-broken argmax (eq. central-node, eq. local-center and the canonical   */
+/* smallest-index selector of the corollary on deterministic tie-breaking).  */
+/* Among the members of a set, v is a co-maximiser when                      */
+/*   max_B - B_v <= tau * max(max_B, 1);                                     */
+/* the smallest-index co-maximiser is returned (-1 for an empty set).  With  */
+/* exact arithmetic and tau -> 0 this is the paper's rule.  `near` counts    */
+/* members whose gap lies in [band/4, 4*band], where rounding could matter.  */
+/* ------------------------------------------------------------------------ */
+int32_t or_band_argmax(int32_t n, const double *B, const uint8_t *member, double tau, int64_t *near)
+{
+    int32_t v, best = -1;
+    double bmax = 0.0, band;
+    int any = 0;
+    for (v = 0; v < n; ++v) {
+        if (!member[v]) continue;
+        if (!any || B[v] > bmax) bmax = B[v];
+        any = 1;
+    }
+    if (!any) return -1;
+    band = tau * (bmax > 1.0 ? bmax : 1.0);
+    for (v = 0; v < n; ++v) {
+        double gap;
+        if (!member[v]) continue;
+        gap = bmax - B[v];
+        if (gap <= band && best < 0) best = v;
+        if (near && band > 0.0 && gap >= 0.25 * band && gap <= 4.0 * band) (*near)++;
+    }
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Row-wise Monte Carlo sweep (Alg. 1 SampleNext for every anchor, Alg. 2    */
+/* counting).  Realization r in [r_begin, r_begin + R) is drawn once and     */
+/* serves every anchor i: next(r,i) = bottom if the stop coin fires or       */
+/* |K(i;H_r)| < k_min, else the tie-broken centre of K(i;H_r).  The pool-    */
+/* constrained selector of Section 7.1 (k = infinity) takes the tie-broken   */
+/* argmax over K(i;H_r) intersected with W, bottom when that is empty.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    uint32_t R;
+    uint32_t r_begin;
+    double alpha;
+    uint32_t k_min;
+    double tau;
+    const uint8_t *pool_mask;    /* length n, NULL when no pool            */
+} or_query;
+
+typedef struct {
+    uint32_t *counts;            /* n x (n+1), column n is bottom          */
+    uint32_t *counts_w;          /* n x (n+1) or NULL                      */
+    int32_t *center_global;      /* R or NULL                              */
+    int32_t *next_table;         /* R x n or NULL (-1 = bottom)            */
+    int32_t *next_table_w;       /* R x n or NULL                          */
+    double *bsum;                /* n or NULL: sum over r of B(H_r)        */
+    uint64_t stats[8];           /* units, sum n_K, sum A_K, sum D_K,      */
+                                 /* near-band count, 0, 0, 0               */
+} or_sweep_out;
+
+int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
+             const or_query *q, or_sweep_out *out)
+{
+    or_graph g;
+    uint8_t *alive = NULL, *member = NULL;
+    uint32_t *w = NULL;
+    uint64_t *dist = NULL, *sigma = NULL;
+    int32_t *order = NULL, *comp = NULL, *size = NULL, *cc = NULL, *cw = NULL;
+    double *B = NULL, *delta = NULL;
+    int64_t *k_alive = NULL, *k_deg = NULL;
+    uint32_t rr;
+    int32_t v, i;
+    int unit = (mod->weight_kind == OR_WEIGHT_UNIT);
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    memset(out->stats, 0, sizeof(out->stats));
+    alive = (uint8_t *)malloc((size_t)m + 1);
+    member = (uint8_t *)malloc((size_t)n);
+    w = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)m + 1));
+    dist = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    sigma = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    size = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    cc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    cw = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    B = (double *)malloc(sizeof(double) * (size_t)n);
+    delta = (double *)malloc(sizeof(double) * (size_t)n);
+    k_alive = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    k_deg = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!alive || !member || !w || !dist || !sigma || !order || !comp || !size || !cc || !cw || !B || !delta ||
+        !k_alive || !k_deg) { rc = OR_E_NOMEM; goto done; }
+
+    for (rr = 0; rr < q->R; ++rr) {
+        uint32_t r = q->r_begin + rr;
+        int32_t cg;
+        int64_t e;
+        or_realize(n, m, eu, ev, mod, q->seed, r, alive, w);
+        rc = or_brandes_graph(&g, alive, w, unit, B, dist, sigma, order, delta);
+        if (rc != OR_OK) goto done;
+        or_components_graph(&g, alive, comp, size, order);
+
+        /* global centre c(H) (eq. central-node) */
+        for (v = 0; v < n; ++v) member[v] = 1;
+        cg = or_band_argmax(n, B, member, q->tau, (int64_t *)&out->stats[4]);
+        if (out->center_global) out->center_global[rr] = cg;
+
+        /* component centres (eq. local-center) and pool-constrained centres */
+        for (v = 0; v < n; ++v) { cc[v] = -1; cw[v] = -1; }
+        for (v = 0; v < n; ++v) {
+            int32_t c = comp[v], u;
+            if (cc[c] >= 0 || v != c) continue;          /* once per component, at its label */
+            for (u = 0; u < n; ++u) member[u] = (comp[u] == c);
+            cc[c] = or_band_argmax(n, B, member, q->tau, (int64_t *)&out->stats[4]);
+            if (q->pool_mask) {
+                for (u = 0; u < n; ++u) member[u] = (comp[u] == c) && q->pool_mask[u];
+                cw[c] = or_band_argmax(n, B, member, q->tau, (int64_t *)&out->stats[4]);
+            }
+        }
+
+        /* anchors: Alg. 1 for every i, counted as in Alg. 2 */
+        for (i = 0; i < n; ++i) {
+            int coin = or_stop_coin(q->seed, r, i, q->alpha);
+            int valid = !coin && (uint32_t)size[i] >= q->k_min;
+            int32_t nx = valid ? cc[comp[i]] : -1;
+            out->counts[(size_t)i * (n + 1) + (nx >= 0 ? nx : n)] += 1u;
+            if (out->next_table) out->next_table[(size_t)rr * n + i] = nx;
+            if (out->counts_w) {
+                int32_t nw = (valid && q->pool_mask) ? cw[comp[i]] : -1;
+                out->counts_w[(size_t)i * (n + 1) + (nw >= 0 ? nw : n)] += 1u;
+                if (out->next_table_w) out->next_table_w[(size_t)rr * n + i] = nw;
+            }
+        }
+        if (out->bsum)
+            for (v = 0; v < n; ++v) out->bsum[v] += B[v];
+
+        /* work accounting per (r, s): n_K = |K(s)|, A_K = surviving directed
+         * slots inside K(s), D_K = base directed slots of K(s)'s vertices */
+        for (v = 0; v < n; ++v) { k_alive[v] = 0; k_deg[v] = 0; }
+        for (v = 0; v < n; ++v) k_deg[comp[v]] += g.off[v + 1] - g.off[v];
+        for (e = 0; e < m; ++e)
+            if (alive[e]) k_alive[comp[eu[e]]] += 2;
+        for (v = 0; v < n; ++v) {
+            out->stats[0] += 1;
+            out->stats[1] += (uint64_t)size[v];
+            out->stats[2] += (uint64_t)k_alive[comp[v]];
+            out->stats[3] += (uint64_t)k_deg[comp[v]];
+        }
+    }
+done:
+    free(alive); free(member); free(w); free(dist); free(sigma); free(order); free(comp); free(size);
+    free(cc); free(cw); free(B); free(delta); free(k_alive); free(k_deg);
+    or_graph_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chain algebra (Section 4, eq. amc ... eq. afc-def).                       */
+/* ------------------------------------------------------------------------ */
+
+/* Empirical kernel of Alg. 2 with the stabilisation of Section 8.2: P_ij =
+ * C_ij / R; when an anchor never absorbed (C_i,bottom = 0) and eta > 0, the
+ * absorption entry is floored to eta and the row renormalised, i.e. the
+ * transient entries are scaled by (1 - eta). */
+int or_counts_to_kernel(int32_t n, const uint32_t *counts, uint32_t R, double eta, double *Q, double *r)
+{
+    int32_t i, j;
+    if (n < 1 || R == 0) return OR_E_ARG;
+    for (i = 0; i < n; ++i) {
+        const uint32_t *row = counts + (size_t)i * (n + 1);
+        if (row[n] == 0 && eta > 0.0) {
+            for (j = 0; j < n; ++j) Q[(size_t)i * n + j] = (1.0 - eta) * ((double)row[j] / (double)R);
+            r[i] = eta;
+        } else {
+            for (j = 0; j < n; ++j) Q[(size_t)i * n + j] = (double)row[j] / (double)R;
+            r[i] = (double)row[n] / (double)R;
+        }
+    }
+    return OR_OK;
+}
+
+/* Fundamental matrix N = (I - Q)^{-1} (eq. fundamental) by LU factorisation
+ * with partial pivoting and one forward/back substitution per unit column. */
+int or_fundamental(int32_t n, const double *Q, double *N)
+{
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    int32_t *piv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t i, j, k, c;
+    int rc = OR_OK;
+    if (!A || !piv || !x) { free(A); free(piv); free(x); return OR_E_NOMEM; }
+    for (i = 0; i < n; ++i)
+        for (j = 0; j < n; ++j) A[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - Q[(size_t)i * n + j];
+    for (k = 0; k < n; ++k) {
+        int32_t p = k;
+        double amax = fabs(A[(size_t)k * n + k]);
+        for (i = k + 1; i < n; ++i)
+            if (fabs(A[(size_t)i * n + k]) > amax) { amax = fabs(A[(size_t)i * n + k]); p = i; }
+        if (amax == 0.0) { rc = OR_E_SINGULAR; goto out; }
+        piv[k] = p;
+        if (p != k)
+            for (j = 0; j < n; ++j) {
+                double t = A[(size_t)k * n + j]; A[(size_t)k * n + j] = A[(size_t)p * n + j]; A[(size_t)p * n + j] = t;
+            }
+        for (i = k + 1; i < n; ++i) {
+            double l = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+            A[(size_t)i * n + k] = l;
+            for (j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+        }
+    }
+    for (c = 0; c < n; ++c) {
+        for (i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+        for (k = 0; k < n; ++k)                       /* apply the row swaps */
+            if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+        for (i = 1; i < n; ++i)                       /* L y = P e_c */
+            for (k = 0; k < i; ++k) x[i] -= A[(size_t)i * n + k] * x[k];
+        for (i = n - 1; i >= 0; --i) {                /* U x = y */
+            for (k = i + 1; k < n; ++k) x[i] -= A[(size_t)i * n + k] * x[k];
+            x[i] /= A[(size_t)i * n + i];
+        }
+        for (i = 0; i < n; ++i) N[(size_t)i * n + c] = x[i];
+    }
+out:
+    free(A); free(piv); free(x);
+    return rc;
+}
+
+/* Visits mu(s) = sN (eq. visits), E_s[T] = mu 1 (eq. expected-length) and
+ * AFC b(s) = mu / mu 1 (eq. afc-def). */
+void or_visits(int32_t n, const double *N, const double *s, double *mu, double *ET, double *b)
+{
+    int32_t i, j;
+    double tot = 0.0;
+    for (j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (i = 0; i < n; ++i) acc += s[i] * N[(size_t)i * n + j];
+        mu[j] = acc;
+    }
+    for (j = 0; j < n; ++j) tot += mu[j];
+    *ET = tot;
+    for (j = 0; j < n; ++j) b[j] = mu[j] / tot;
+}
+
+/* Top-k of b by decreasing value, ties to the smaller index. */
+static void or_topk(int32_t n, const double *b, int32_t k, int32_t *top)
+{
+    int32_t t, v;
+    uint8_t *taken = (uint8_t *)calloc((size_t)n, 1);
+    for (t = 0; t < k; ++t) {
+        int32_t best = -1;
+        for (v = 0; v < n; ++v)
+            if (!taken[v] && (best < 0 || b[v] > b[best])) best = v;
+        top[t] = best; taken[best] = 1;
+    }
+    free(taken);
+}
+
+/* Visit-gap certificates of Section 5.5.  For the pair (u, v):
+ *   G_uv = mu_u - mu_v (eq. pm-gap);
+ *   crude threshold 2 * epsbar / r_min^2;
+ *   sharp threshold (epsbar / r_min) * max_i |N_iu - N_iv| (eq. sharp-gap).
+ * The order u > v is certified when G_uv exceeds the threshold. */
+void or_pair_certificate(int32_t n, const double *N, const double *mu, double epsbar, double r_min,
+                         int32_t u, int32_t v, double *gap, double *crude, double *sharp)
+{
+    int32_t i;
+    double mx = 0.0;
+    for (i = 0; i < n; ++i) {
+        double d = fabs(N[(size_t)i * n + u] - N[(size_t)i * n + v]);
+        if (d > mx) mx = d;
+    }
+    *gap = mu[u] - mu[v];
+    *crude = 2.0 * epsbar / (r_min * r_min);
+    *sharp = epsbar / r_min * mx;
+}
+
+/* The whole tail for one query (Sections 4, 5.5, 6.4, 7.1-7.2, 8.2-8.3).     */
+typedef struct {
+    double eta;                  /* floor on an empty absorption column     */
+    const double *s;             /* initial distribution (length n)         */
+    const double *f;             /* node reward f (length n) or NULL        */
+    const uint8_t *pool_mask;    /* W (length n) or NULL                    */
+    double eps;                  /* row-wise radius of every entry          */
+    double r_lower;              /* leak lower bound                         */
+    int32_t cert_topk;           /* size of the nominal Top-k, 0 = none     */
+} or_tail_in;
+
+typedef struct {
+    double *Q, *r, *N;           /* n*n, n, n*n                             */
+    double *mu, *b;              /* n, n                                     */
+    double ET, b_f;
+    double *b_w, *xi;            /* n, n   (pool kernel)                     */
+    double ET_w, m_w, b_w_f;
+    double *b_w_bar;             /* n: b_w / m_w on W, 0 off W              */
+    int32_t *top;                /* cert_topk                                */
+    double *cert_gap, *cert_sharp;  /* cert_topk x (n - cert_topk)           */
+    int32_t *cert_v;             /* the complement, in increasing index     */
+    double cert_crude, epsbar, epsbar_supp;
+    double cert_crude_supp;
+    double *cert_sharp_supp;     /* cert_topk x (n - cert_topk)             */
+    int32_t admissible;          /* nominal kernel inside the set: r_i >= r_lower */
+} or_tail_out;
+
+int or_tail(int32_t n, const uint32_t *counts, const uint32_t *counts_w, uint32_t R, const or_tail_in *in,
+            or_tail_out *out)
+{
+    int32_t i, j, k = in->cert_topk;
+    int rc = or_counts_to_kernel(n, counts, R, in->eta, out->Q, out->r);
+    if (rc != OR_OK) return rc;
+    rc = or_fundamental(n, out->Q, out->N);
+    if (rc != OR_OK) return rc;
+    or_visits(n, out->N, in->s, out->mu, &out->ET, out->b);
+    out->b_f = 0.0;
+    if (in->f)
+        for (j = 0; j < n; ++j) out->b_f += out->b[j] * in->f[j];   /* eq. mr-inner-product */
+
+    out->admissible = 1;
+    for (i = 0; i < n; ++i)
+        if (out->r[i] < in->r_lower) out->admissible = 0;
+    out->epsbar = (double)n * in->eps;                /* dense radii: epsbar = max_i sum_j eps_ij */
+    {
+        int32_t supp_max = 0;
+        for (i = 0; i < n; ++i) {
+            int32_t c = 0;
+            for (j = 0; j < n; ++j) c += (out->Q[(size_t)i * n + j] > 0.0);
+            if (c > supp_max) supp_max = c;
+        }
+        out->epsbar_supp = (double)supp_max * in->eps;
+    }
+    out->cert_crude = 2.0 * out->epsbar / (in->r_lower * in->r_lower);
+    out->cert_crude_supp = 2.0 * out->epsbar_supp / (in->r_lower * in->r_lower);
+    if (k > 0 && k < n) {
+        int32_t a, c = 0, v;
+        uint8_t *intop = (uint8_t *)calloc((size_t)n, 1);
+        or_topk(n, out->b, k, out->top);
+        for (a = 0; a < k; ++a) intop[out->top[a]] = 1;
+        for (v = 0; v < n; ++v)
+            if (!intop[v]) out->cert_v[c++] = v;
+        for (a = 0; a < k; ++a)
+            for (c = 0; c < n - k; ++c) {
+                double gap, crude, sharp;
+                or_pair_certificate(n, out->N, out->mu, out->epsbar, in->r_lower, out->top[a], out->cert_v[c],
+                                    &gap, &crude, &sharp);
+                out->cert_gap[(size_t)a * (n - k) + c] = gap;
+                out->cert_sharp[(size_t)a * (n - k) + c] = sharp;
+                if (out->cert_sharp_supp)
+                    out->cert_sharp_supp[(size_t)a * (n - k) + c] = sharp / out->epsbar * out->epsbar_supp;
+            }
+        free(intop);
+    }
+
+    if (counts_w && in->pool_mask) {                   /* constrained kernel P^W (Section 7) */
+        double *Qw = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+        double *rw = (double *)malloc(sizeof(double) * (size_t)n);
+        double *Nw = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+        double *muw = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!Qw || !rw || !Nw || !muw) { free(Qw); free(rw); free(Nw); free(muw); return OR_E_NOMEM; }
+        for (i = 0; i < n; ++i)                         /* eq. settopk-xi, raw frequencies */
+            out->xi[i] = 1.0 - (double)counts_w[(size_t)i * (n + 1) + n] / (double)R;
+        rc = or_counts_to_kernel(n, counts_w, R, in->eta, Qw, rw);
+        if (rc == OR_OK) rc = or_fundamental(n, Qw, Nw);
+        if (rc == OR_OK) {
+            or_visits(n, Nw, in->s, muw, &out->ET_w, out->b_w);
+            out->m_w = 0.0; out->b_w_f = 0.0;
+            for (j = 0; j < n; ++j) {
+                if (in->pool_mask[j]) out->m_w += out->b_w[j];      /* eq. settopk-bPsi */
+                if (in->f) out->b_w_f += out->b_w[j] * in->f[j];
+            }
+            for (j = 0; j < n; ++j)
+                out->b_w_bar[j] = (in->pool_mask[j] && out->m_w > 0.0) ? out->b_w[j] / out->m_w : 0.0;
+        }
+        free(Qw); free(rw); free(Nw); free(muw);
+    }
+    return rc;
+}
