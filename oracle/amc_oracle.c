@@ -789,8 +789,12 @@ int or_tail(int32_t n, const uint32_t *counts, const uint32_t *counts_w, uint32_
                                     &gap, &crude, &sharp);
                 out->cert_gap[(size_t)a * (n - k) + c] = gap;
                 out->cert_sharp[(size_t)a * (n - k) + c] = sharp;
-                if (out->cert_sharp_supp)
-                    out->cert_sharp_supp[(size_t)a * (n - k) + c] = sharp / out->epsbar * out->epsbar_supp;
+                if (out->cert_sharp_supp) {      /* eq. sharp-gap with the support-restricted radii */
+                    double g2, c2, s2;
+                    or_pair_certificate(n, out->N, out->mu, out->epsbar_supp, in->r_lower, out->top[a],
+                                        out->cert_v[c], &g2, &c2, &s2);
+                    out->cert_sharp_supp[(size_t)a * (n - k) + c] = s2;
+                }
             }
         free(intop);
     }

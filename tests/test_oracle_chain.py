@@ -169,3 +169,22 @@ def test_tail_rewards_pool_feasibility_identities():
                 assert out["cert_gap"][a, c] == pytest.approx(mu[u] - mu[v], abs=1e-15)
                 assert out["cert_sharp"][a, c] == pytest.approx(n * 1e-3 / 0.05 * np.abs(N[:, u] - N[:, v]).max(),
                                                                 rel=1e-14)
+
+
+def test_support_restricted_threshold_without_radius():
+    """eps = 0 certifies every strict nominal order; the support-restricted
+    threshold uses epsbar_supp = eps * max_i |supp Q_i| in eq. sharp-gap."""
+    rng = np.random.default_rng(8)
+    n, R = 12, 300
+    C = np.stack([rng.multinomial(R, rng.dirichlet(np.ones(n + 1) * 0.5)) for _ in range(n)]).astype(np.uint32)
+    out = O.tail(C, R, eps=0.0, r_lower=0.05, cert_topk=3)
+    assert np.all(out["cert_sharp"] == 0.0) and np.all(out["cert_sharp_supp"] == 0.0)
+    out = O.tail(C, R, eps=2e-3, r_lower=0.05, cert_topk=3)
+    Q = out["Q"]
+    supp = int((Q > 0).sum(1).max())
+    assert out["epsbar_supp"] == pytest.approx(supp * 2e-3)
+    N = out["N"]
+    for a, u in enumerate(out["top"]):
+        for c, v in enumerate(out["cert_v"]):
+            assert out["cert_sharp_supp"][a, c] == pytest.approx(supp * 2e-3 / 0.05 * np.abs(N[:, u] - N[:, v]).max(),
+                                                                 rel=1e-13)
