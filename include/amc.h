@@ -1,0 +1,213 @@
+/*
+ * amc.h -- C-ABI of the MI355X engine for absorbing-frequency centrality (AFC).
+ *
+ * Paper: W. Bao, E. Kontou, C. Vogiatzis, "Betweenness-Central Nodes Under
+ * Uncertainty: An Absorbing Markov Chain Approach".
+ *
+ * The library estimates the absorbing Markov chain (AMC) on reported local
+ * betweenness centres by the row-wise Monte Carlo construction of Alg. 1 /
+ * Alg. 2 and turns the estimated kernel into AFC and its companions:
+ *
+ *   for every realization r and every anchor i:
+ *     next(r,i) = bottom              if the exogenous stop coin fires
+ *                                     or |K(i;H_r)| < k_min        (Section 3.2)
+ *               = c_loc(i;H_r)        the tie-broken maximiser of the
+ *                                     betweenness B(H_r) over K(i;H_r)
+ *                                                       (eq. local-center)
+ *   counts C[i][j] = #{r : next(r,i) = j}                       (Alg. 2)
+ *   N = (I - Q)^{-1}, mu = sN, E_s[T] = mu 1, b = mu / mu 1
+ *                                    (eqs. fundamental, visits, afc-def)
+ *
+ * Conventions shared by every call:
+ *   - Vertices are 0 .. n-1.  The base graph is undirected and simple and is
+ *     passed as a canonical edge list: eu[e] < ev[e] and the pairs strictly
+ *     increasing in lexicographic order.  Anything else is AMC_E_INVALID_ARG.
+ *   - Realization r of the network state (Section 3.1) is a pure function of
+ *     (seed, r): edge (u,v) survives and draws its integer weight from the
+ *     Philox4x32-10 block of counter (r, u, v, 0) and key (seed mod 2^32,
+ *     seed >> 32); the stop coin of anchor i uses counter (r, i, 2^32-1, 1).
+ *     An event of probability p fires when the first 32-bit word is below
+ *     floor(p * 2^32); an integer weight uniform on [lo, hi] is
+ *     lo + ((x1 * (hi - lo + 1)) >> 32).
+ *   - Ties (Corollary on deterministic tie-breaking): inside a vertex set the
+ *     reported vertex is the smallest index v with
+ *     max_B - B_v <= tie_tau * max(max_B, 1).
+ *   - Pointers in the structs below are host pointers unless stated.  Inputs
+ *     are read during the call and never retained.  Result buffers are owned
+ *     by the caller and must stay valid until amc_run returns (or until
+ *     amc_wait / a successful amc_poll for amc_submit).
+ *   - Every call returns AMC_OK (0) or a negative status; no exception
+ *     crosses the ABI.  A failed call leaves result buffers unspecified.
+ */
+#ifndef AMC_H
+#define AMC_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define AMC_API __attribute__((visibility("default")))
+#else
+#define AMC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define AMC_OK 0
+#define AMC_E_INVALID_ARG (-1)    /* bad size, range, edge list or option   */
+#define AMC_E_OOM (-2)            /* device or host allocation failed       */
+#define AMC_E_HIP (-3)            /* a HIP runtime call failed              */
+#define AMC_E_SIGMA_OVERFLOW (-4) /* a shortest-path count exceeded 2^64-1  */
+#define AMC_E_SINGULAR (-5)       /* I - Q singular (row never absorbs, no floor) */
+#define AMC_E_ADMISSION (-6)      /* query footprint exceeds the context budget */
+#define AMC_E_NOT_READY (-7)      /* amc_poll: the request is still running */
+#define AMC_E_UNSUPPORTED (-8)    /* the shape exceeds an engine limit      */
+
+/* ------------------------------------------------------------ weight law */
+#define AMC_WEIGHT_UNIT 0         /* every surviving edge has weight 1 (BFS)   */
+#define AMC_WEIGHT_UNIFORM_INT 1  /* integer weight uniform on [w_lo, w_hi]    */
+#define AMC_WEIGHT_FIXED 2        /* the graph's own integer weights w0        */
+
+/* --------------------------------------------------------- sweep mode */
+#define AMC_MODE_AUTO 0           /* pick from the shape (autotuner)           */
+#define AMC_MODE_WAVE 1           /* graph staged in LDS, one wavefront per (r, s) */
+#define AMC_MODE_BLOCK 2          /* one workgroup per (r, s), frontier queues */
+
+/* ----------------------------------------------------------- query flags */
+#define AMC_WANT_N (1u << 0)          /* copy the fundamental matrix N           */
+#define AMC_WANT_BSUM (1u << 1)       /* sum over r of B(H_r)                     */
+#define AMC_WANT_NEXT_TABLE (1u << 2) /* next(r,i) for every r, i                 */
+#define AMC_WANT_CENTER (1u << 3)     /* global centre c(H_r) (eq. central-node)  */
+#define AMC_WANT_DEBUG (1u << 4)      /* d, sigma, delta of listed (r, s) pairs   */
+#define AMC_SKIP_TAIL (1u << 5)       /* counts only, no chain algebra            */
+#define AMC_PLAIN_LAUNCH (1u << 6)    /* one kernel launch per realization        */
+
+typedef struct amc_ctx amc_ctx;
+typedef struct amc_graph amc_graph;
+typedef struct amc_request amc_request;
+
+/* Network-state law (Section 3.1: availability set and positive weights). */
+typedef struct amc_model {
+    double p_fail;              /* failure probability of every edge, in [0,1]   */
+    const double *p_fail_edge;  /* optional per-edge failure probabilities (m)   */
+    int32_t weight_kind;        /* AMC_WEIGHT_*                                   */
+    uint32_t w_lo, w_hi;        /* AMC_WEIGHT_UNIFORM_INT: 1 <= w_lo <= w_hi <= 65535 */
+} amc_model;
+
+/* One estimation query (Alg. 2 plus the post-processing of Section 8.3). */
+typedef struct amc_query {
+    uint64_t seed;              /* realization key                                 */
+    uint32_t R;                 /* realizations in this call (samples per row), >= 1 */
+    uint32_t r_begin;           /* first realization index (split runs / resume)   */
+    double alpha;               /* exogenous stop probability, in (0, 1]            */
+    uint32_t k_min;             /* smallest valid component size (Section 3.2)      */
+    double tie_tau;             /* tie band; < 0 selects 1e-9                       */
+    double floor_eta;           /* floor on an empty absorption column; < 0 selects
+                                   0.1/sqrt(R); 0 disables (Section 8.2)            */
+    const double *s;            /* initial distribution (n) or NULL for uniform     */
+    const int32_t *pool;        /* candidate pool W (Section 7.1) or NULL           */
+    int32_t pool_size;
+    const double *reward;       /* node values f (n) or NULL (eq. mr-inner-product) */
+    double eps;                 /* row-wise radius of every entry eps_ij (Section 5.1) */
+    double r_lower;             /* leak lower bound of every row, in (0, 1]         */
+    int32_t cert_topk;          /* nominal Top-k whose boundary pairs are certified (0 = none) */
+    uint32_t flags;             /* AMC_WANT_* / AMC_SKIP_TAIL / AMC_PLAIN_LAUNCH     */
+    int32_t mode;               /* AMC_MODE_*                                        */
+    int32_t tile;               /* sources per work item; 0 = chosen by the engine   */
+    int32_t waves;              /* wavefronts per workgroup; 0 = chosen by the engine */
+    const uint32_t *debug_pairs; /* AMC_WANT_DEBUG: n_debug pairs (r, s), r absolute */
+    int32_t n_debug;            /* at most 64                                        */
+} amc_query;
+
+/* Counters of one run.  units = R n (one (r, s) pass each); sum_nK, sum_AK and
+ * sum_DK add, over every (r, s), the reached vertices |K(s;H_r)|, the surviving
+ * directed adjacency slots inside K(s;H_r) and the base directed slots of its
+ * vertices. near_band counts set members whose gap to the set maximum lies in
+ * [band/4, 4 band]. */
+typedef struct amc_stats {
+    uint64_t units, sum_nK, sum_AK, sum_DK, near_band;
+    double sweep_ms;            /* HIP-event time of the sweep kernel(s) on the context stream */
+    double tail_ms;             /* HIP-event time of the tail kernels                          */
+    int32_t mode, waves, tile, blocks, lds_bytes, launches;
+} amc_stats;
+
+/* Caller-owned host buffers; NULL pointers are skipped. */
+typedef struct amc_result {
+    uint32_t *counts;           /* n x (n+1), column n = bottom (required)      */
+    uint32_t *counts_w;         /* n x (n+1) counts of the pool kernel P^W       */
+    int32_t *center_global;     /* R: c(H_r) (AMC_WANT_CENTER)                   */
+    int32_t *next_table;        /* R x n, -1 = bottom (AMC_WANT_NEXT_TABLE)      */
+    int32_t *next_table_w;      /* R x n, pool kernel                            */
+    double *bsum;               /* n: sum_r B(H_r) (AMC_WANT_BSUM)               */
+    double *Q, *r;              /* n x n, n: stabilised kernel                   */
+    double *N;                  /* n x n (AMC_WANT_N)                            */
+    double *mu, *b;             /* n, n                                          */
+    double *b_w, *xi, *b_w_bar; /* n each: AFC, feasibility and within-pool profile of P^W */
+    int32_t *top;               /* cert_topk: nominal Top-k by b (ties to the smaller index) */
+    int32_t *cert_v;            /* n - cert_topk: the complement, increasing     */
+    double *cert_gap;           /* cert_topk x (n-cert_topk): G_uv (eq. pm-gap)  */
+    double *cert_sharp;         /* same shape: sharp thresholds (eq. sharp-gap)  */
+    double *cert_sharp_supp;    /* same shape, support-restricted radii          */
+    uint32_t *dbg_dist;         /* n_debug x n (0xFFFFFFFF = unreachable)        */
+    uint64_t *dbg_sigma;        /* n_debug x n                                    */
+    double *dbg_delta;          /* n_debug x n                                    */
+    /* scalars written by the call */
+    double E_T, b_f;            /* E_s[T] and b . f                                */
+    double E_T_w, m_w, b_w_f;   /* pool kernel: E_s[T], pool mass m_W (eq. settopk-bPsi), b^W . f */
+    double cert_crude, epsbar;  /* 2 epsbar / r_lower^2 and epsbar = n eps        */
+    double cert_crude_supp, epsbar_supp; /* support-restricted variants           */
+    int32_t admissible;         /* 1 when every r_i >= r_lower                    */
+    amc_stats stats;
+} amc_result;
+
+/* Context: one device, one stream, an HBM budget for admission (0 = free HBM). */
+AMC_API int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **out);
+AMC_API void amc_ctx_destroy(amc_ctx *ctx);
+/* Launch on a caller stream (a hipStream_t, e.g. a torch stream); NULL = own stream. */
+AMC_API int amc_ctx_set_stream(amc_ctx *ctx, void *hip_stream);
+/* The context stream (hipStream_t), for callers that time or order work on it. */
+AMC_API void *amc_ctx_stream(amc_ctx *ctx);
+
+/* Stage a base graph G(V,E) (Section 3.1) on the device.  n >= 1, m >= 0,
+ * canonical edge list as above; w0 (m) is required for AMC_WEIGHT_FIXED and
+ * may be NULL otherwise.  Limits: n <= 65535, w0[e] in [1, 65535]. */
+AMC_API int amc_graph_create(amc_ctx *ctx, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                     const uint32_t *w0, amc_graph **out);
+AMC_API void amc_graph_destroy(amc_graph *g);
+
+/* Device bytes a query needs beyond the staged graph. */
+AMC_API int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *bytes);
+
+/* Synchronous estimation: sweep (Alg. 1 for every anchor over R realizations,
+ * counted as in Alg. 2) followed, unless AMC_SKIP_TAIL, by the tail. */
+AMC_API int amc_run(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, amc_result *out);
+
+/* Asynchronous estimation through the context's serving loop: the query is
+ * admitted when its footprint fits the budget and a slot is free, runs
+ * overlapped with other admitted queries, and completes into `out`.
+ * Returns AMC_E_ADMISSION at once if the footprint can never fit. */
+AMC_API int amc_submit(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, amc_result *out,
+               amc_request **req);
+AMC_API int amc_poll(amc_request *req);        /* AMC_E_NOT_READY, or the final status */
+AMC_API int amc_wait(amc_request *req);        /* blocks; returns the final status     */
+AMC_API void amc_request_destroy(amc_request *req);
+/* Serving timestamps of a finished request, seconds on a monotonic clock:
+ * t[0] submit, t[1] admitted, t[2] finished. */
+AMC_API int amc_request_times(amc_request *req, double t[3]);
+
+/* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
+ * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
+ * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,
+ * r_lower, cert_topk; counts-related fields of `out` are ignored. */
+AMC_API int amc_chain(amc_ctx *ctx, int32_t n, const double *Q, const amc_query *q, amc_result *out);
+
+AMC_API const char *amc_strerror(int status);
+AMC_API int amc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMC_H */

@@ -1,0 +1,340 @@
+"""ctypes binding of the C-ABI in ``include/amc.h`` (argument marshalling only).
+
+Every step of the estimation runs in the HIP library ``lib/libamc.so``; this
+module only converts numpy arrays to pointers and back.  Importing it does not
+load the library; the first call does, and raises ``RuntimeError`` when the
+library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libamc.so")
+
+OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NOT_READY, E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED = 0, 1, 2
+MODE_AUTO, MODE_WAVE, MODE_BLOCK = 0, 1, 2
+WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH = \
+    1, 2, 4, 8, 16, 32, 64
+
+EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
+           "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
+           "amc_request_destroy", "amc_request_times", "amc_chain", "amc_strerror", "amc_version"]
+
+_P = C.POINTER
+
+
+class AmcError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        msg = _lib_or_none().amc_strerror(rc).decode() if _lib_or_none() else str(rc)
+        super().__init__(f"{what}: {msg} ({rc})")
+        self.rc = rc
+
+
+class Model(C.Structure):
+    _fields_ = [("p_fail", C.c_double), ("p_fail_edge", _P(C.c_double)), ("weight_kind", C.c_int32),
+                ("w_lo", C.c_uint32), ("w_hi", C.c_uint32)]
+
+
+class Query(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("R", C.c_uint32), ("r_begin", C.c_uint32), ("alpha", C.c_double),
+                ("k_min", C.c_uint32), ("tie_tau", C.c_double), ("floor_eta", C.c_double), ("s", _P(C.c_double)),
+                ("pool", _P(C.c_int32)), ("pool_size", C.c_int32), ("reward", _P(C.c_double)), ("eps", C.c_double),
+                ("r_lower", C.c_double), ("cert_topk", C.c_int32), ("flags", C.c_uint32), ("mode", C.c_int32),
+                ("tile", C.c_int32), ("waves", C.c_int32), ("debug_pairs", _P(C.c_uint32)), ("n_debug", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("units", C.c_uint64), ("sum_nK", C.c_uint64), ("sum_AK", C.c_uint64), ("sum_DK", C.c_uint64),
+                ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
+                ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
+                ("launches", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("counts", _P(C.c_uint32)), ("counts_w", _P(C.c_uint32)), ("center_global", _P(C.c_int32)),
+                ("next_table", _P(C.c_int32)), ("next_table_w", _P(C.c_int32)), ("bsum", _P(C.c_double)),
+                ("Q", _P(C.c_double)), ("r", _P(C.c_double)), ("N", _P(C.c_double)), ("mu", _P(C.c_double)),
+                ("b", _P(C.c_double)), ("b_w", _P(C.c_double)), ("xi", _P(C.c_double)), ("b_w_bar", _P(C.c_double)),
+                ("top", _P(C.c_int32)), ("cert_v", _P(C.c_int32)), ("cert_gap", _P(C.c_double)),
+                ("cert_sharp", _P(C.c_double)), ("cert_sharp_supp", _P(C.c_double)), ("dbg_dist", _P(C.c_uint32)),
+                ("dbg_sigma", _P(C.c_uint64)), ("dbg_delta", _P(C.c_double)), ("E_T", C.c_double),
+                ("b_f", C.c_double), ("E_T_w", C.c_double), ("m_w", C.c_double), ("b_w_f", C.c_double),
+                ("cert_crude", C.c_double), ("epsbar", C.c_double), ("cert_crude_supp", C.c_double),
+                ("epsbar_supp", C.c_double), ("admissible", C.c_int32), ("stats", Stats)]
+
+
+_lib = None
+
+
+def _lib_or_none():
+    return _lib
+
+
+def lib():
+    """Loads libamc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.amc_ctx_create.argtypes = [C.c_int, C.c_uint64, _P(vp)]
+        L.amc_ctx_destroy.argtypes = [vp]
+        L.amc_ctx_destroy.restype = None
+        L.amc_ctx_set_stream.argtypes = [vp, vp]
+        L.amc_ctx_stream.argtypes = [vp]
+        L.amc_ctx_stream.restype = vp
+        L.amc_graph_create.argtypes = [vp, C.c_int32, C.c_int64, _P(C.c_int32), _P(C.c_int32), _P(C.c_uint32),
+                                       _P(vp)]
+        L.amc_graph_destroy.argtypes = [vp]
+        L.amc_graph_destroy.restype = None
+        L.amc_footprint.argtypes = [vp, _P(Query), _P(C.c_uint64)]
+        L.amc_run.argtypes = [vp, vp, _P(Model), _P(Query), _P(Result)]
+        L.amc_submit.argtypes = [vp, vp, _P(Model), _P(Query), _P(Result), _P(vp)]
+        L.amc_poll.argtypes = [vp]
+        L.amc_wait.argtypes = [vp]
+        L.amc_request_destroy.argtypes = [vp]
+        L.amc_request_destroy.restype = None
+        L.amc_request_times.argtypes = [vp, _P(C.c_double)]
+        L.amc_chain.argtypes = [vp, C.c_int32, _P(C.c_double), _P(Query), _P(Result)]
+        L.amc_strerror.argtypes = [C.c_int]
+        L.amc_strerror.restype = C.c_char_p
+        L.amc_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return None if a is None else a.ctypes.data_as(_P(ct))
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise AmcError(rc, what)
+
+
+class Context:
+    """amc_ctx: one device, one stream, an HBM budget for the serving loop."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().amc_ctx_create(int(device), int(budget_bytes), C.byref(h)), "amc_ctx_create")
+        self.h = h
+
+    def set_stream(self, stream_handle: int | None):
+        _check(lib().amc_ctx_set_stream(self.h, C.c_void_p(stream_handle or 0)), "amc_ctx_set_stream")
+
+    def stream(self) -> int:
+        return lib().amc_ctx_stream(self.h) or 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().amc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """amc_graph: a base graph G(V,E) staged on the device (canonical edge list)."""
+
+    def __init__(self, ctx: Context, n: int, eu, ev, w0=None):
+        self.ctx = ctx
+        self.n = int(n)
+        self.eu = np.ascontiguousarray(eu, dtype=np.int32)
+        self.ev = np.ascontiguousarray(ev, dtype=np.int32)
+        self.m = len(self.eu)
+        self.w0 = None if w0 is None else np.ascontiguousarray(w0, dtype=np.uint32)
+        h = C.c_void_p()
+        _check(lib().amc_graph_create(ctx.h, self.n, self.m, _ptr(self.eu, C.c_int32), _ptr(self.ev, C.c_int32),
+                                      _ptr(self.w0, C.c_uint32), C.byref(h)), "amc_graph_create")
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, ctx, g):
+        return cls(ctx, g.n, g.eu, g.ev, g.w0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().amc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_WEIGHTS = {"unit": WEIGHT_UNIT, "uniform": WEIGHT_UNIFORM_INT, "fixed": WEIGHT_FIXED}
+
+
+def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=None):
+    keep = []
+    m = Model()
+    m.p_fail = float(p_fail)
+    if p_fail_edge is not None:
+        pe = np.ascontiguousarray(p_fail_edge, dtype=np.float64)
+        keep.append(pe)
+        m.p_fail_edge = _ptr(pe, C.c_double)
+    m.weight_kind = _WEIGHTS[weight] if isinstance(weight, str) else int(weight)
+    m.w_lo, m.w_hi = int(w_lo), int(w_hi)
+    return m, keep
+
+
+def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, floor_eta=-1.0, s=None, pool=None,
+               reward=None, eps=0.0, r_lower=0.05, cert_topk=0, flags=0, mode=MODE_AUTO, tile=0, waves=0,
+               debug_pairs=None):
+    keep = []
+    q = Query()
+    q.seed, q.R, q.r_begin = int(seed), int(R), int(r_begin)
+    q.alpha, q.k_min, q.tie_tau, q.floor_eta = float(alpha), int(k_min), float(tie_tau), float(floor_eta)
+    if s is not None:
+        sa = np.ascontiguousarray(s, dtype=np.float64)
+        keep.append(sa)
+        q.s = _ptr(sa, C.c_double)
+    if pool is not None:
+        pa = np.ascontiguousarray(pool, dtype=np.int32)
+        keep.append(pa)
+        q.pool = _ptr(pa, C.c_int32)
+        q.pool_size = len(pa)
+    if reward is not None:
+        ra = np.ascontiguousarray(reward, dtype=np.float64)
+        keep.append(ra)
+        q.reward = _ptr(ra, C.c_double)
+    q.eps, q.r_lower, q.cert_topk, q.flags = float(eps), float(r_lower), int(cert_topk), int(flags)
+    q.mode, q.tile, q.waves = int(mode), int(tile), int(waves)
+    if debug_pairs is not None and len(debug_pairs):
+        dp = np.ascontiguousarray(np.asarray(debug_pairs, dtype=np.uint32).reshape(-1, 2))
+        keep.append(dp)
+        q.debug_pairs = _ptr(dp, C.c_uint32)
+        q.n_debug = len(dp)
+        q.flags |= WANT_DEBUG
+    return q, keep
+
+
+def _alloc_result(n, q: Query):
+    R = int(q.R)
+    k = int(q.cert_topk)
+    pool = q.pool_size > 0
+    arr = {"counts": np.zeros((n, n + 1), np.uint32)}
+    if pool:
+        arr["counts_w"] = np.zeros((n, n + 1), np.uint32)
+    if q.flags & WANT_CENTER:
+        arr["center_global"] = np.zeros(R, np.int32)
+    if q.flags & WANT_NEXT_TABLE:
+        arr["next_table"] = np.zeros((R, n), np.int32)
+        if pool:
+            arr["next_table_w"] = np.zeros((R, n), np.int32)
+    if q.flags & WANT_BSUM:
+        arr["bsum"] = np.zeros(n, np.float64)
+    if not (q.flags & SKIP_TAIL):
+        arr.update(Q=np.zeros((n, n)), r=np.zeros(n), mu=np.zeros(n), b=np.zeros(n))
+        if q.flags & WANT_N:
+            arr["N"] = np.zeros((n, n))
+        if pool:
+            arr.update(b_w=np.zeros(n), xi=np.zeros(n), b_w_bar=np.zeros(n))
+        if k > 0:
+            arr.update(top=np.zeros(k, np.int32), cert_v=np.zeros(n - k, np.int32),
+                       cert_gap=np.zeros((k, n - k)), cert_sharp=np.zeros((k, n - k)),
+                       cert_sharp_supp=np.zeros((k, n - k)))
+    if q.n_debug > 0:
+        arr.update(dbg_dist=np.zeros((q.n_debug, n), np.uint32), dbg_sigma=np.zeros((q.n_debug, n), np.uint64),
+                   dbg_delta=np.zeros((q.n_debug, n)))
+    res = Result()
+    types = {np.dtype(np.uint32): C.c_uint32, np.dtype(np.int32): C.c_int32, np.dtype(np.float64): C.c_double,
+             np.dtype(np.uint64): C.c_uint64}
+    for key, a in arr.items():
+        setattr(res, key, _ptr(a, types[a.dtype]))
+    return res, arr
+
+
+def _collect(res: Result, arr: dict) -> dict:
+    out = dict(arr)
+    for key in ("E_T", "b_f", "E_T_w", "m_w", "b_w_f", "cert_crude", "epsbar", "cert_crude_supp", "epsbar_supp"):
+        out[key] = float(getattr(res, key))
+    out["admissible"] = bool(res.admissible)
+    st = res.stats
+    out["stats"] = {f: getattr(st, f) for f, _ in Stats._fields_}
+    return out
+
+
+def run(ctx: Context, graph: Graph, model: dict, **query) -> dict:
+    """amc_run: the sweep (Alg. 1 for every anchor over R realizations, counted
+    as in Alg. 2) and the tail; returns numpy arrays and scalars."""
+    m, keep_m = make_model(**model)
+    q, keep_q = make_query(graph.n, **query)
+    res, arr = _alloc_result(graph.n, q)
+    _check(lib().amc_run(ctx.h, graph.h, C.byref(m), C.byref(q), C.byref(res)), "amc_run")
+    del keep_m, keep_q
+    return _collect(res, arr)
+
+
+class Request:
+    """amc_request: a query submitted to the serving loop."""
+
+    def __init__(self, ctx, graph, model: dict, **query):
+        self._m, self._keep_m = make_model(**model)
+        self._q, self._keep_q = make_query(graph.n, **query)
+        self._res, self._arr = _alloc_result(graph.n, self._q)
+        self.graph = graph
+        h = C.c_void_p()
+        _check(lib().amc_submit(ctx.h, graph.h, C.byref(self._m), C.byref(self._q), C.byref(self._res),
+                                C.byref(h)), "amc_submit")
+        self.h = h
+
+    def poll(self) -> bool:
+        rc = lib().amc_poll(self.h)
+        if rc == E_NOT_READY:
+            return False
+        _check(rc, "amc_poll")
+        return True
+
+    def wait(self) -> dict:
+        _check(lib().amc_wait(self.h), "amc_wait")
+        return _collect(self._res, self._arr)
+
+    def times(self):
+        t = (C.c_double * 3)()
+        _check(lib().amc_request_times(self.h, t), "amc_request_times")
+        return tuple(t)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().amc_request_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chain(ctx: Context, Q, **query) -> dict:
+    """amc_chain: the tail alone on a given transient block Q."""
+    Qa = np.ascontiguousarray(Q, dtype=np.float64)
+    n = Qa.shape[0]
+    q, keep = make_query(n, **query)
+    res, arr = _alloc_result(n, q)
+    _check(lib().amc_chain(ctx.h, n, _ptr(Qa, C.c_double), C.byref(q), C.byref(res)), "amc_chain")
+    out = _collect(res, arr)
+    del keep
+    return out
+
+
+def footprint(graph: Graph, **query) -> int:
+    q, keep = make_query(graph.n, **query)
+    b = C.c_uint64()
+    _check(lib().amc_footprint(graph.h, C.byref(q), C.byref(b)), "amc_footprint")
+    return int(b.value)

@@ -1,0 +1,149 @@
+// amc_dev.hpp -- device-side building blocks shared by the sweep and tail
+// kernels of the MI355X (gfx950) AFC engine.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach".
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amc {
+
+// ---------------------------------------------------------------------------
+// Counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// Each round multiplies words 0 and 2 by the two Philox multipliers, xors the
+// high halves with the other words and the round key; the key is advanced by
+// the two Weyl increments between rounds.  The "one Philox call per (r, edge)"
+// keying means no realized graph is ever stored: any (r, e) is recomputed.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ u32x4 philox10(u32x4 c, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t pa = (uint64_t)kMulA * c.x;
+        const uint64_t pb = (uint64_t)kMulB * c.z;
+        const u32x4 o = {(uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb, (uint32_t)(pa >> 32) ^ c.w ^ k1,
+                         (uint32_t)pa};
+        c = o;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Parameters of one sweep launch (device pointers unless noted).
+// ---------------------------------------------------------------------------
+struct SweepParams {
+    // base graph G(V,E) in CSR form (both directions of every edge)
+    int32_t n;
+    int64_t m;
+    const int32_t *rp_base;     // n+1
+    const uint16_t *col;        // 2m neighbour of each slot
+    const int32_t *slot_edge;   // 2m edge id of each slot
+    const int32_t *eu, *ev;     // m canonical endpoints (Philox counters)
+    const uint32_t *w0;         // m fixed weights or nullptr
+    // network-state law
+    uint64_t t_fail;            // failure threshold floor(p 2^32) of every edge
+    const uint64_t *t_fail_edge;// per-edge thresholds or nullptr
+    int32_t weight_kind;        // 0 unit, 1 uniform integer, 2 fixed
+    uint32_t w_lo, w_span;      // uniform integer law: lo + ((x * span) >> 32)
+    // query
+    uint32_t key0, key1;        // Philox key = seed
+    uint32_t r_begin;           // absolute index of realization 0 of this query
+    uint64_t t_alpha;           // stop-coin threshold floor(alpha 2^32)
+    uint32_t k_min;
+    double tau;                 // tie band
+    const uint8_t *pool;        // n membership of W or nullptr
+    // work decomposition: item = (r_local, tile), r-major
+    int32_t tile;               // sources per item
+    int32_t tiles_per_r;
+    uint32_t n_items;           // items in this launch
+    uint32_t item_base;         // absolute item index of local item 0
+    int32_t static_items;       // 1: item = item_base + blockIdx.x (one per block)
+    unsigned int *work_ctr;     // dynamic item counter (static_items == 0)
+    // LDS carve-up (bytes), computed on the host
+    uint32_t adj_cap;           // capacity of the realized adjacency in slots
+    uint32_t wave_bytes;        // per-wavefront private region
+    // outputs
+    uint32_t *counts, *counts_w;
+    int32_t *center_global, *next_table, *next_table_w;
+    double *bsum;
+    unsigned long long *stats;  // [units, sum_nK, sum_AK, sum_DK, near_band]
+    int *err;                   // bit 0: sigma overflow
+    // partial-B exchange when a realization spans several items
+    double *Bg;                 // R x n
+    int32_t *compg, *sizeg;     // R x n
+    unsigned int *done;         // R
+    // per-(r, s) dumps for the parity checks
+    const uint32_t *dbg_pairs;  // n_dbg x (r, s)
+    int32_t n_dbg;
+    uint32_t *dbg_dist;
+    unsigned long long *dbg_sigma;
+    double *dbg_delta;
+};
+
+constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps
+constexpr int kMaxWaves = 16;
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+// ---------------------------------------------------------------------------
+// Orders the LDS traffic of one wavefront: every LDS access issued before the
+// call completes before any issued after it (LDS requests of one wavefront are
+// serviced in order once they are all issued), and the compiler may not move
+// memory operations across it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lo = __builtin_amdgcn_mbcnt_lo(~0u, 0u);
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, lo);
+    return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double as_f64(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long as_u64(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+}  // namespace amc

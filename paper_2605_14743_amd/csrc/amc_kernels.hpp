@@ -1,0 +1,37 @@
+// amc_kernels.hpp -- host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "amc_dev.hpp"
+
+namespace amc {
+
+// LDS-resident sweep (one wavefront per (r, s)).
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, int waves, uint32_t *wave_bytes);
+hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, int blocks, int waves, uint32_t lds,
+                             hipStream_t st);
+
+// Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
+uint32_t lds_bytes_block(int n, int threads);
+size_t block_scratch_words(int n, int64_t m);
+hipError_t launch_sweep_block(const SweepParams &P, bool weighted, int blocks, int threads, uint32_t lds,
+                              uint32_t *scratch, hipStream_t st);
+
+// Tail.
+hipError_t fill_u32(void *p, size_t count, uint32_t v, hipStream_t st);
+hipError_t tail_kernel_from_counts(int n, const uint32_t *counts, uint32_t R, double eta, double *Q, double *r,
+                                   double *A, hipStream_t st);
+hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipStream_t st);
+hipError_t tail_invert(int n, double *A, int *err, hipStream_t st);
+hipError_t tail_visits(int n, const double *N, const double *s, double *mu, double *b, const double *f,
+                       const uint8_t *pool, double *b_bar, const double *r, double r_lower, int topk, int32_t *top,
+                       double *scal, hipStream_t st);
+hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, const double *mu,
+                             const int32_t *top, int32_t *cv, double eps, double r_lower, double *gap,
+                             double *sharp, double *sharp_supp, int *support, hipStream_t st);
+hipError_t tail_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi, hipStream_t st);
+
+}  // namespace amc

@@ -1,0 +1,77 @@
+// amc_runtime.hpp -- host-side state behind the opaque handles of amc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "amc.h"
+
+namespace amc {
+
+// Stream-ordered device allocations of one query, released together.
+struct DevArena {
+    hipStream_t stream = nullptr;    // allocation stream
+    bool async = false;              // stream-ordered allocator available
+    std::vector<void *> ptrs;
+    int alloc(size_t bytes, void **out);
+    void release();
+};
+
+struct Plan {
+    int mode = 0;
+    bool weighted = false;
+    int group = 8;                  // lanes per vertex in the LDS mode
+    int waves = 0, threads = 0;
+    uint32_t lds = 0, wave_bytes = 0, adj_cap = 0;
+    int tile = 0, tiles_per_r = 1;
+    uint64_t items = 0;
+    int blocks = 0;
+};
+
+struct Server;
+
+}  // namespace amc
+
+struct amc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own = nullptr;
+    uint64_t budget = 0;
+    int cu_count = 0;
+    int max_lds = 65536;
+    bool async_alloc = false;
+    std::mutex mu;                   // serialises amc_run / amc_chain on the context stream
+    std::mutex server_mu;
+    amc::Server *server = nullptr;
+};
+
+struct amc_graph {
+    amc_ctx *ctx = nullptr;
+    int32_t n = 0;
+    int64_t m = 0;
+    std::vector<int32_t> eu, ev, rp;
+    std::vector<uint32_t> w0;
+    int32_t max_deg = 0;
+    int32_t *d_rp = nullptr;
+    uint16_t *d_col = nullptr;
+    int32_t *d_sedge = nullptr;
+    int32_t *d_eu = nullptr, *d_ev = nullptr;
+    uint32_t *d_w0 = nullptr;
+    amc::DevArena arena;
+};
+
+namespace amc {
+
+int validate(const amc_graph *g, const amc_model *md, const amc_query *q);
+int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, Plan *pl);
+uint64_t prob_threshold(double p);
+int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, amc_result *out,
+              hipStream_t st);
+void server_stop(amc_ctx *ctx);
+
+}  // namespace amc

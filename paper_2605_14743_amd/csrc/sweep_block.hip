@@ -1,0 +1,383 @@
+// sweep_block.hip -- realization x source sweep for graphs beyond the LDS
+// mode: one workgroup per (realization, source), frontier queues in LDS,
+// the realized adjacency in a per-workgroup global scratch (L2-resident).
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach".
+//
+// Per work item (realization r, tile of sources) the workgroup realizes the
+// edges of r (Section 3.1) into its scratch, then runs the sources one after
+// another.  A source is a level-synchronous traversal: the current frontier
+// (vertices at the same distance, settled) is spread over groups of G lanes;
+// each group pulls the exact path count of its vertex from its predecessors
+// and relaxes the vertex's edges; newly reached vertices are appended to the
+// queue with one LDS atomic per wavefront (ballot + prefix).  With integer
+// weights the unsettled reached vertices wait in a fringe and the next
+// distance is the fringe minimum (distance buckets).  The reverse pass walks
+// the equal-distance segments backwards and accumulates the dependencies of
+// the Section 3.1 betweenness into B(H_r) held in LDS; the reduction and the
+// counting are the same as in the LDS mode.
+#include "amc_dev.hpp"
+#include "amc_kernels.hpp"
+#include "sweep_common.hpp"
+
+namespace amc {
+
+constexpr int kBG = 4;   // lanes per vertex in the block mode
+
+// Appends the lanes with `pred` set to a queue whose tail is *ctr (LDS): one
+// atomic per wavefront; returns each appending lane's slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred) {
+    const uint64_t mask = __ballot(pred);
+    uint32_t pos = 0;
+    if (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(mask));
+        base = __builtin_amdgcn_readlane(base, leader);
+        pos = base + (uint32_t)__popcll(mask & lanemask_lt());
+    }
+    return pos;
+}
+
+struct BlockLayout {
+    uint32_t dist, sig, ord, aux, B, comp, csize, total;
+};
+
+__host__ __device__ inline BlockLayout block_layout(int n) {
+    BlockLayout L;
+    const uint32_t un = (uint32_t)n;
+    L.dist = 0;
+    L.sig = (4u * un + 7u) & ~7u;
+    L.ord = L.sig + 8u * un;
+    L.aux = L.ord + 2u * un;
+    L.B = (L.aux + 2u * un + 7u) & ~7u;
+    L.comp = L.B + 8u * un;
+    L.csize = L.comp + 2u * un;
+    L.total = (L.csize + 2u * un + 15u) & ~15u;
+    return L;
+}
+
+template <bool WEIGHTED>
+__device__ void block_source(const SweepParams &P, const uint32_t *rp, const uint32_t *adj, double *B,
+                             uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctl,
+                             uint32_t *tmp, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
+    const int n = P.n;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int sub = tid % kBG, grp = tid / kBG, ngrp = nthr / kBG;
+    // ctl[0]: queue / fringe tail, ctl[1]: scratch scalar
+    for (int v = tid; v < n; v += nthr) dist[v] = kInf;
+    __syncthreads();
+    if (tid == 0) {
+        dist[s] = 0u;
+        sig[s] = 1ull;
+        ord[0] = (uint16_t)s;
+        ctl[0] = WEIGHTED ? 0u : 1u;
+    }
+    __syncthreads();
+    int f_lo = 0, ord_end = 1, nseg = 0;
+    uint32_t D = 0;
+    for (;;) {
+        if (tid == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
+        ++nseg;
+        // one frontier sweep; groups of kBG lanes per vertex
+        for (int base = f_lo; base < ord_end; base += ngrp) {
+            const int idx = base + grp;
+            const bool mine = idx < ord_end;
+            unsigned long long acc = 0ull;
+            int v = 0;
+            uint32_t beg = 0, end = 0;
+            if (mine) {
+                v = ord[idx];
+                beg = rp[v];
+                end = rp[v + 1];
+            }
+            // iterate in lockstep across the wavefront so the append can ballot
+            const uint32_t len = end - beg;
+            const uint32_t trips = len > (uint32_t)sub ? (len - (uint32_t)sub + kBG - 1) / kBG : 0u;
+            uint32_t maxtrips = trips;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const uint32_t o = __shfl_xor(maxtrips, off, 64);
+                maxtrips = o > maxtrips ? o : maxtrips;
+            }
+            for (uint32_t t = 0; t < maxtrips; ++t) {
+                bool found = false;
+                uint32_t u = 0;
+                if (t < trips) {
+                    const uint32_t a = adj[beg + (uint32_t)sub + t * kBG];
+                    u = a & 0xFFFFu;
+                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
+                    const uint32_t du = dist[u];
+                    if (du + w == D) {
+                        const unsigned long long x = acc + sig[u];
+                        ovf |= x < acc;
+                        acc = x;
+                    } else if (D + w < du) {
+                        found = atomicMin(&dist[u], D + w) == kInf;
+                    }
+                }
+                const uint32_t pos = wave_append(&ctl[0], found);
+                if (found) {
+                    if (WEIGHTED) aux[pos] = (uint16_t)u;
+                    else ord[pos] = (uint16_t)u;
+                }
+            }
+#pragma unroll
+            for (int off = 1; off < kBG; off <<= 1) {
+                const unsigned long long o = __shfl_xor(acc, off, 64);
+                const unsigned long long x = acc + o;
+                ovf |= x < acc;
+                acc = x;
+            }
+            if (mine && sub == 0 && v != s) sig[v] = acc;
+        }
+        __syncthreads();
+        if (!WEIGHTED) {
+            const int new_end = (int)ctl[0];
+            __syncthreads();
+            if (new_end == ord_end) break;
+            f_lo = ord_end;
+            ord_end = new_end;
+            D += 1u;
+        } else {
+            const int fr = (int)ctl[0];
+            if (fr == 0) break;
+            // next distance: minimum over the fringe
+            uint32_t mn = kInf;
+            for (int k = tid; k < fr; k += nthr) {
+                const uint32_t dk = dist[aux[k]];
+                mn = dk < mn ? dk : mn;
+            }
+            mn = wave_min_u32(mn);
+            if (lane == 0) tmp[wave] = mn;
+            __syncthreads();
+            mn = tmp[0];
+            for (int w = 1; w < nwaves; ++w) mn = tmp[w] < mn ? tmp[w] : mn;
+            __syncthreads();
+            // partition chunk by chunk: every read of a chunk precedes the
+            // barrier, every write follows it, and writes land at or below
+            // the read positions of this or earlier chunks
+            int settled = 0, kept = 0;
+            for (int k0 = 0; k0 < fr; k0 += nthr) {
+                const int k = k0 + tid;
+                const bool valid = k < fr;
+                const uint32_t x = valid ? aux[k] : 0u;
+                const bool is_s = valid && dist[x] == mn;
+                const bool is_k = valid && !is_s;
+                const uint64_t ms = __ballot(is_s), mk = __ballot(is_k);
+                if (lane == 0) {
+                    tmp[wave] = (uint32_t)__popcll(ms);
+                    tmp[kMaxWaves + wave] = (uint32_t)__popcll(mk);
+                }
+                __syncthreads();
+                int ps = settled, pk = kept, ts = 0, tk = 0;
+                for (int w = 0; w < nwaves; ++w) {
+                    if (w < wave) {
+                        ps += (int)tmp[w];
+                        pk += (int)tmp[kMaxWaves + w];
+                    }
+                    ts += (int)tmp[w];
+                    tk += (int)tmp[kMaxWaves + w];
+                }
+                const uint64_t lt = lanemask_lt();
+                if (is_s) ord[ord_end + ps + __popcll(ms & lt)] = (uint16_t)x;
+                if (is_k) aux[pk + __popcll(mk & lt)] = (uint16_t)x;
+                settled += ts;
+                kept += tk;
+                __syncthreads();
+            }
+            if (tid == 0) ctl[0] = (uint32_t)kept;
+            __syncthreads();
+            f_lo = ord_end;
+            ord_end += settled;
+            D = mn;
+        }
+    }
+    // component of s and its size
+    {
+        int mn = n;
+        for (int k = tid; k < ord_end; k += nthr) mn = min(mn, (int)ord[k]);
+        mn = wave_min_i32(mn);
+        if (lane == 0) tmp[wave] = (uint32_t)mn;
+        __syncthreads();
+        int c = (int)tmp[0];
+        for (int w = 1; w < nwaves; ++w) c = min(c, (int)tmp[w]);
+        comp_out = c;
+        size_out = ord_end;
+        __syncthreads();
+    }
+    if (dbg_slot >= 0) {
+        for (int v = tid; v < n; v += nthr) {
+            const uint32_t d = dist[v];
+            P.dbg_dist[(size_t)dbg_slot * n + v] = d == kInf ? 0xFFFFFFFFu : d;
+            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == kInf ? 0ull : sig[v];
+            P.dbg_delta[(size_t)dbg_slot * n + v] = 0.0;
+        }
+        __syncthreads();
+    }
+    // reverse pass over the equal-distance segments
+    for (int k = nseg - 1; k >= 0; --k) {
+        const int lo = aux[n - 1 - k];
+        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
+        for (int base = lo; base < hi; base += ngrp) {
+            const int idx = base + grp;
+            const bool mine = idx < hi;
+            double sum = 0.0;
+            int v = 0;
+            if (mine) {
+                v = ord[idx];
+                const uint32_t dv = dist[v];
+                const uint32_t beg = rp[v], end = rp[v + 1];
+                for (uint32_t j = beg + (uint32_t)sub; j < end; j += kBG) {
+                    const uint32_t a = adj[j];
+                    const uint32_t u = a & 0xFFFFu;
+                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
+                    if (dist[u] == dv + w) sum += as_f64(sig[u]);
+                }
+            }
+#pragma unroll
+            for (int off = 1; off < kBG; off <<= 1) sum += __shfl_xor(sum, off, 64);
+            if (mine && sub == 0) {
+                const double sv = (double)sig[v];
+                const double delta = sv * sum;
+                sig[v] = as_u64((1.0 + delta) / sv);
+                if (v != s) B[v] += delta;
+                if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool WEIGHTED>
+__global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32_t *scratch, size_t scratch_words) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ uint32_t scan_tmp[2 * kMaxWaves];
+    __shared__ uint32_t ctl[4];
+    __shared__ double red_f[kMaxWaves];
+    __shared__ int red_i[kMaxWaves];
+    __shared__ int item_sh;
+    __shared__ int last_sh;
+
+    const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
+    const int n = P.n;
+    const BlockLayout L = block_layout(n);
+    uint32_t *dist = (uint32_t *)(smem + L.dist);
+    unsigned long long *sig = (unsigned long long *)(smem + L.sig);
+    uint16_t *ord = (uint16_t *)(smem + L.ord);
+    uint16_t *aux = (uint16_t *)(smem + L.aux);
+    double *B = (double *)(smem + L.B);
+    uint16_t *comp = (uint16_t *)(smem + L.comp);
+    uint16_t *csize = (uint16_t *)(smem + L.csize);
+    // per-workgroup global scratch: realized rp (n+1), adjacency (2m),
+    // component centres and slot counts (4 n)
+    uint32_t *gs = scratch + (size_t)blockIdx.x * scratch_words;
+    uint32_t *rp = gs;
+    uint32_t *adj = rp + (n + 1);
+    ReduceScratch RS;
+    RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
+    RS.wmax = RS.cmax + n;
+    uint32_t *tail4 = adj + 2 * (size_t)P.m;
+    RS.ccen = (int32_t *)tail4;
+    RS.wcen = RS.ccen + n;
+    RS.kal = (uint32_t *)(RS.wcen + n);
+    RS.kba = RS.kal + n;
+
+    unsigned long long acc_stats[5] = {0, 0, 0, 0, 0};
+    bool ovf = false;
+    uint32_t local = 0;
+    for (;;) {
+        if (P.static_items) {
+            if (local > 0) break;
+            local = 1;
+            item_sh = (int)blockIdx.x;
+        } else {
+            if (tid == 0) item_sh = (int)atomicAdd(P.work_ctr, 1u);
+            __syncthreads();
+        }
+        const int it = item_sh;
+        __syncthreads();
+        if ((uint32_t)it >= P.n_items) break;
+        const uint32_t item = P.item_base + (uint32_t)it;
+        const uint32_t r_local = item / (uint32_t)P.tiles_per_r;
+        const int t = (int)(item % (uint32_t)P.tiles_per_r);
+        const uint32_t r = P.r_begin + r_local;
+
+        stage_realization(P, r, rp, adj, (uint16_t *)smem, scan_tmp);
+        for (int v = tid; v < n; v += nthr) B[v] = 0.0;
+        __syncthreads();
+
+        const int s_lo = t * P.tile, s_hi = min(n, s_lo + P.tile);
+        for (int s = s_lo; s < s_hi; ++s) {
+            int cs = 0, sz = 0;
+            const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
+            block_source<WEIGHTED>(P, rp, adj, B, dist, sig, ord, aux, ctl, scan_tmp, s, slot, cs, sz, ovf);
+            if (tid == 0) {
+                comp[s] = (uint16_t)cs;
+                csize[s] = (uint16_t)(sz & 0xFFFF);
+            }
+        }
+        __syncthreads();
+        if (P.tiles_per_r == 1) {
+            reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+        } else {
+            double *Bg = P.Bg + (size_t)r_local * n;
+            for (int v = tid; v < n; v += nthr)
+                if (B[v] != 0.0) unsafeAtomicAdd(&Bg[v], B[v]);
+            for (int s = s_lo + tid; s < s_hi; s += nthr) {
+                P.compg[(size_t)r_local * n + s] = comp[s];
+                P.sizeg[(size_t)r_local * n + s] = csize[s];
+            }
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) last_sh = (atomicAdd(&P.done[r_local], 1u) == (unsigned)(P.tiles_per_r - 1));
+            __syncthreads();
+            if (last_sh) {
+                __threadfence();
+                for (int v = tid; v < n; v += nthr) {
+                    B[v] = __hip_atomic_load(&Bg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    comp[v] = (uint16_t)__hip_atomic_load(&P.compg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    csize[v] = (uint16_t)__hip_atomic_load(&P.sizeg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __syncthreads();
+                reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+            }
+            __syncthreads();
+        }
+    }
+    if (ovf) atomicOr(P.err, 1);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const unsigned long long v = wave_sum_u64(acc_stats[k]);
+        if (lane == 0 && v) atomicAdd(&P.stats[k], v);
+    }
+}
+
+uint32_t lds_bytes_block(int n, int threads) {
+    (void)threads;
+    return block_layout(n).total;
+}
+
+size_t block_scratch_words(int n, int64_t m) { return (size_t)(n + 1) + 2 * (size_t)m + 4 * (size_t)n + 64; }
+
+hipError_t launch_sweep_block(const SweepParams &P, bool weighted, int blocks, int threads, uint32_t lds,
+                              uint32_t *scratch, hipStream_t st) {
+    const size_t words = block_scratch_words(P.n, P.m);
+    if (weighted) {
+        auto k = sweep_block_kernel<true>;
+        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, st, P, scratch, words);
+    } else {
+        auto k = sweep_block_kernel<false>;
+        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, st, P, scratch, words);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace amc

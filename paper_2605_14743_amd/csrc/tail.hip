@@ -1,0 +1,409 @@
+// tail.hip -- FP64 chain algebra on the device: the estimated kernel, the
+// fundamental matrix N = (I - Q)^{-1}, visits, AFC, rewards, the
+// pool-constrained kernel and the visit-gap certificates.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach" (Section 4, Section 5.5,
+// Section 6.4, Section 7, Section 8.2).
+//
+// I - Q is strictly diagonally dominant by rows whenever every row absorbs
+// (row i: (1 - Q_ii) - sum_{j != i} Q_ij = r_i > 0), so the inverse is taken
+// by blocked Gauss-Jordan elimination without pivoting (growth factor at most
+// 2 for such matrices).
+#include "amc_dev.hpp"
+#include "amc_kernels.hpp"
+
+namespace amc {
+
+constexpr int NB = 32;      // Gauss-Jordan panel width
+constexpr int TT = 64;      // trailing-update tile edge
+
+// Empirical kernel of Alg. 2 plus the floor of Section 8.2: when row i never
+// absorbed and eta > 0, P_i,bottom := eta and the transient part is scaled by
+// (1 - eta).  Also writes A = I - Q.
+__global__ void k_counts_to_kernel(int n, const uint32_t *counts, uint32_t R, double eta, double *Q, double *r,
+                                   double *A) {
+    const int i = blockIdx.x;
+    const uint32_t *row = counts + (size_t)i * (n + 1);
+    const bool fl = row[n] == 0u && eta > 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double q = (double)row[j] / (double)R;
+        const double v = fl ? (1.0 - eta) * q : q;
+        Q[(size_t)i * n + j] = v;
+        A[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - v;
+    }
+    if (threadIdx.x == 0) r[i] = fl ? eta : (double)row[n] / (double)R;
+}
+
+// A = I - Q for a given Q; r = 1 - Q 1.
+__global__ void k_from_Q(int n, const double *Q, double *r, double *A) {
+    const int i = blockIdx.x;
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double v = Q[(size_t)i * n + j];
+        A[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - v;
+        acc += v;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) r[i] = 1.0 - part[0];
+}
+
+// (a) invert the diagonal block A[k0:k1, k0:k1] in place (unblocked
+// Gauss-Jordan without pivoting); flags a zero pivot.
+__global__ void k_gj_diag(int n, double *A, int k0, int *err) {
+    __shared__ double M[NB][NB + 1];
+    const int kb = min(NB, n - k0);
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+        const int i = t / NB, j = t % NB;
+        M[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int p = 0; p < kb; ++p) {
+        const double piv = M[p][p];
+        __syncthreads();
+        if (piv == 0.0) {
+            if (threadIdx.x == 0) atomicOr(err, 2);
+            return;
+        }
+        const double d = 1.0 / piv;
+        // row p scaled (except column p)
+        for (int j = threadIdx.x; j < kb; j += blockDim.x)
+            if (j != p) M[p][j] *= d;
+        __syncthreads();
+        for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
+            const int i = t / kb, j = t % kb;
+            if (i != p && j != p) M[i][j] -= M[i][p] * M[p][j];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kb; i += blockDim.x)
+            if (i != p) M[i][p] = -M[i][p] * d;
+        if (threadIdx.x == 0) M[p][p] = d;
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
+        const int i = t / kb, j = t % kb;
+        A[(size_t)(k0 + i) * n + k0 + j] = M[i][j];
+    }
+}
+
+// (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block.
+__global__ void k_gj_rowpanel(int n, double *A, int k0) {
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double X[NB][TT + 1];
+    const int kb = min(NB, n - k0);
+    const int j0 = blockIdx.x * TT;
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+        const int i = t / NB, j = t % NB;
+        Dv[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+    }
+    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
+        const int i = t / TT, j = t % TT;
+        const int c = j0 + j;
+        X[i][j] = (i < kb && c < n) ? A[(size_t)(k0 + i) * n + c] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
+        const int i = t / TT, j = t % TT;
+        const int c = j0 + j;
+        if (i >= kb || c >= n || (c >= k0 && c < k0 + kb)) continue;
+        double acc = 0.0;
+        for (int p = 0; p < kb; ++p) acc += Dv[i][p] * X[p][j];
+        A[(size_t)(k0 + i) * n + c] = acc;
+    }
+}
+
+// (c) trailing update: A[i, j] -= A[i, k] A[k, j] for i, j outside the block
+// (A[k, j] already holds the row panel of step (b)).
+__global__ __launch_bounds__(256) void k_gj_update(int n, double *A, int k0) {
+    __shared__ double Ap[TT][NB + 1];
+    __shared__ double Bp[NB][TT + 1];
+    const int kb = min(NB, n - k0);
+    const int i0 = blockIdx.y * TT, j0 = blockIdx.x * TT;
+    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
+        const int i = t / NB, p = t % NB;
+        Ap[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
+    }
+    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
+        const int p = t / TT, j = t % TT;
+        Bp[p][j] = (p < kb && j0 + j < n) ? A[(size_t)(k0 + p) * n + j0 + j] : 0.0;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int p = 0; p < kb; ++p) {
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = Ap[ty + 16 * a][p];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = Bp[p][tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + ty + 16 * a;
+        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = j0 + tx + 16 * b;
+            if (j >= n || (j >= k0 && j < k0 + kb)) continue;
+            A[(size_t)i * n + j] -= acc[a][b];
+        }
+    }
+}
+
+// (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block.
+__global__ void k_gj_colpanel(int n, double *A, int k0) {
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double X[TT][NB + 1];
+    const int kb = min(NB, n - k0);
+    const int i0 = blockIdx.x * TT;
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+        const int i = t / NB, j = t % NB;
+        Dv[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+    }
+    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
+        const int i = t / NB, p = t % NB;
+        X[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
+        const int i = t / NB, j = t % NB;
+        const int row = i0 + i;
+        if (row >= n || j >= kb || (row >= k0 && row < k0 + kb)) continue;
+        double acc = 0.0;
+        for (int p = 0; p < kb; ++p) acc += X[i][p] * Dv[p][j];
+        A[(size_t)row * n + k0 + j] = -acc;
+    }
+}
+
+// mu = s N (eq. visits): one thread per column, rows summed in order.
+__global__ void k_visits(int n, const double *N, const double *s, double *mu) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += s[i] * N[(size_t)i * n + j];
+    mu[j] = acc;
+}
+
+// Single-workgroup reductions: E_s[T] = mu 1, b = mu / E_s[T], b . f, pool mass,
+// within-pool profile, Top-k of b (ties to the smaller index), admissibility.
+// scal: [0] E_T, [1] b_f, [2] m_w, [3] admissible
+__global__ void k_afc(int n, const double *mu, double *b, const double *f, const uint8_t *pool, double *b_bar,
+                      const double *r, double r_lower, int topk, int32_t *top, double *scal) {
+    __shared__ double red[1024];
+    __shared__ int redi[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double acc = 0.0;
+    for (int j = tid; j < n; j += nt) acc += mu[j];
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double ET = red[0];
+    __syncthreads();
+    double bf = 0.0, mw = 0.0;
+    int adm = 1;
+    for (int j = tid; j < n; j += nt) {
+        const double bj = mu[j] / ET;
+        b[j] = bj;
+        if (f) bf += bj * f[j];
+        if (pool && pool[j]) mw += bj;
+        if (r && r[j] < r_lower) adm = 0;
+    }
+    red[tid] = bf;
+    redi[tid] = adm;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[tid] += red[tid + s];
+            redi[tid] = min(redi[tid], redi[tid + s]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        scal[0] = ET;
+        scal[1] = red[0];
+        scal[3] = (double)redi[0];
+    }
+    __syncthreads();
+    red[tid] = mw;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double mtot = red[0];
+    if (tid == 0) scal[2] = mtot;
+    if (pool && b_bar)
+        for (int j = tid; j < n; j += nt) b_bar[j] = (pool[j] && mtot > 0.0) ? b[j] / mtot : 0.0;
+    __syncthreads();
+    // Top-k by repeated selection
+    for (int t = 0; t < topk; ++t) {
+        double best = -1.0;
+        int bi = 0x7FFFFFFF;
+        for (int j = tid; j < n; j += nt) {
+            bool taken = false;
+            for (int q = 0; q < t; ++q) taken |= (top[q] == j);
+            if (taken) continue;
+            const double bj = b[j];
+            if (bj > best || (bj == best && j < bi)) {
+                best = bj;
+                bi = j;
+            }
+        }
+        red[tid] = best;
+        redi[tid] = bi;
+        __syncthreads();
+        for (int s = nt / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double o = red[tid + s];
+                const int oi = redi[tid + s];
+                if (o > red[tid] || (o == red[tid] && oi < redi[tid])) {
+                    red[tid] = o;
+                    redi[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) top[t] = redi[0];
+        __syncthreads();
+    }
+}
+
+// Complement of the Top-k in increasing index order (single workgroup).
+__global__ void k_complement(int n, int topk, const int32_t *top, int32_t *cv) {
+    if (threadIdx.x != 0) return;
+    int c = 0;
+    for (int v = 0; v < n; ++v) {
+        bool in = false;
+        for (int q = 0; q < topk; ++q) in |= (top[q] == v);
+        if (!in) cv[c++] = v;
+    }
+}
+
+// Largest row support max_i #{j : Q_ij > 0} (support-restricted radii).
+__global__ void k_support(int n, const double *Q, int *out) {
+    __shared__ int part[256];
+    const int i = blockIdx.x;
+    int c = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) c += Q[(size_t)i * n + j] > 0.0;
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, part[0]);
+}
+
+// Visit-gap certificates (eq. pm-gap, eq. sharp-gap) for every boundary pair
+// (u in Top-k, v outside): one thread per v.  Dense radii eps_ij = eps give
+// epsbar = n eps; the support-restricted radii eps 1{Q_ij > 0} give
+// epsbar_supp = eps max_i |supp Q_i|.
+__global__ void k_certificates(int n, int topk, const double *N, const double *mu, const int32_t *top,
+                               const int32_t *cv, double eps, double r_lower, const int *support, double *gap,
+                               double *sharp, double *sharp_supp) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = n - topk;
+    if (c >= nc) return;
+    const double coef = (double)n * eps / r_lower;
+    const double coef_supp = (double)(*support) * eps / r_lower;
+    const int v = cv[c];
+    double mx[16];
+    for (int a = 0; a < topk; ++a) mx[a] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double nv = N[(size_t)i * n + v];
+        for (int a = 0; a < topk; ++a) {
+            const double d = fabs(N[(size_t)i * n + top[a]] - nv);
+            mx[a] = d > mx[a] ? d : mx[a];
+        }
+    }
+    for (int a = 0; a < topk; ++a) {
+        gap[(size_t)a * nc + c] = mu[top[a]] - mu[v];
+        sharp[(size_t)a * nc + c] = coef * mx[a];
+        if (sharp_supp) sharp_supp[(size_t)a * nc + c] = coef_supp * mx[a];
+    }
+}
+
+__global__ void k_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) xi[i] = 1.0 - (double)counts_w[(size_t)i * (n + 1) + n] / (double)R;
+}
+
+__global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t v) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t fill_u32(void *p, size_t count, uint32_t v, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t tail_kernel_from_counts(int n, const uint32_t *counts, uint32_t R, double eta, double *Q, double *r,
+                                   double *A, hipStream_t st) {
+    hipLaunchKernelGGL(k_counts_to_kernel, dim3(n), dim3(256), 0, st, n, counts, R, eta, Q, r, A);
+    return hipGetLastError();
+}
+
+hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipStream_t st) {
+    hipLaunchKernelGGL(k_from_Q, dim3(n), dim3(256), 0, st, n, Q, r, A);
+    return hipGetLastError();
+}
+
+hipError_t tail_invert(int n, double *A, int *err, hipStream_t st) {
+    const int tiles = (n + TT - 1) / TT;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, n, A, k0, err);
+        hipLaunchKernelGGL(k_gj_rowpanel, dim3(tiles), dim3(256), 0, st, n, A, k0);
+        hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles), dim3(256), 0, st, n, A, k0);
+        hipLaunchKernelGGL(k_gj_colpanel, dim3(tiles), dim3(256), 0, st, n, A, k0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t tail_visits(int n, const double *N, const double *s, double *mu, double *b, const double *f,
+                       const uint8_t *pool, double *b_bar, const double *r, double r_lower, int topk, int32_t *top,
+                       double *scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256), dim3(256), 0, st, n, N, s, mu);
+    hipLaunchKernelGGL(k_afc, dim3(1), dim3(1024), 0, st, n, mu, b, f, pool, b_bar, r, r_lower, topk, top, scal);
+    return hipGetLastError();
+}
+
+hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, const double *mu,
+                             const int32_t *top, int32_t *cv, double eps, double r_lower, double *gap,
+                             double *sharp, double *sharp_supp, int *support, hipStream_t st) {
+    hipLaunchKernelGGL(k_support, dim3(n), dim3(256), 0, st, n, Q, support);
+    if (topk > 0 && topk < n) {
+        hipLaunchKernelGGL(k_complement, dim3(1), dim3(64), 0, st, n, topk, top, cv);
+        hipLaunchKernelGGL(k_certificates, dim3((n - topk + 127) / 128), dim3(128), 0, st, n, topk, N, mu, top, cv,
+                           eps, r_lower, support, gap, sharp, sharp_supp);
+    }
+    return hipGetLastError();
+}
+
+hipError_t tail_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi, hipStream_t st) {
+    hipLaunchKernelGGL(k_xi, dim3((n + 255) / 256), dim3(256), 0, st, n, counts_w, R, xi);
+    return hipGetLastError();
+}
+
+}  // namespace amc

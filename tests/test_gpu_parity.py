@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bit-exact: distances, path counts, global centres, next-state tables, counts
+and the work counters.  Floating point: B (summed over realizations) within
+1e-12 relative; N, mu, b, rewards and certificate thresholds within 1e-12 of
+the vector (row) max norm.  Both sides take the argmax decision in FP64 with
+the same tie band.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14743_amd import amc
+from paper_2605_14743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = amc.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_run(ctx, g, model, **q):
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
+    say(f"[gpu] run n={g.n} m={g.m} model={ {k: v for k, v in model.items() if k != 'p_fail_edge'} } "
+        f"q={ {k: v for k, v in q.items() if k not in ('pool', 'reward', 's', 'debug_pairs')} }")
+    try:
+        return amc.run(ctx, G, model, **q)
+    finally:
+        G.close()
+
+
+def oracle_model(model, g):
+    d = dict(model)
+    if d.get("weight") == "fixed":
+        d["w0"] = g.w0
+    return d
+
+
+def assert_close_norm(x, y, tol=TOL, what=""):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    scale = max(np.abs(y).max(initial=0.0), 1e-300)
+    err = np.abs(x - y).max(initial=0.0)
+    assert err <= tol * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def assert_rel(x, y, tol=TOL, what=""):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    err = np.abs(x - y)
+    assert np.all(err <= tol * np.maximum(np.abs(y), 1e-300) + 1e-300), \
+        f"{what}: worst rel err {np.max(err / np.maximum(np.abs(y), 1e-300)):.3e}"
+
+
+def check_sweep(res, ref, n, what=""):
+    assert np.array_equal(res["counts"], ref["counts"]), f"{what}: counts differ"
+    if "center_global" in res:
+        assert np.array_equal(res["center_global"], ref["center_global"]), f"{what}: centres differ"
+    if "next_table" in res:
+        assert np.array_equal(res["next_table"], ref["next_table"]), f"{what}: next table differs"
+    if "counts_w" in ref:
+        assert np.array_equal(res["counts_w"], ref["counts_w"]), f"{what}: pool counts differ"
+    if "next_table_w" in res and "next_table_w" in ref:
+        assert np.array_equal(res["next_table_w"], ref["next_table_w"])
+    if "bsum" in res:
+        assert_rel(res["bsum"], ref["bsum"], what=f"{what} bsum")
+    st, rst = res["stats"], ref["stats"]
+    for k in ("units", "sum_nK", "sum_AK", "sum_DK"):
+        assert st[k] == rst[k], f"{what}: stat {k} {st[k]} != {rst[k]}"
+
+
+FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.WANT_N
+
+
+# --------------------------------------------------------------------------- config 1: full size, all modes
+@pytest.mark.parametrize("mode,extra", [(amc.MODE_WAVE, {}), (amc.MODE_BLOCK, {}),
+                                        (amc.MODE_WAVE, {"tile": 3}), (amc.MODE_WAVE, {"flags": amc.PLAIN_LAUNCH}),
+                                        (amc.MODE_BLOCK, {"tile": 7})])
+def test_er20_full_against_oracle(ctx, mode, extra):
+    wl = W.config_er20()
+    g = wl.graph
+    model = wl.model()
+    flags = FLAGS | extra.pop("flags", 0)
+    res = gpu_run(ctx, g, model, seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, flags=flags, mode=mode,
+                  cert_topk=5, eps=1e-3, r_lower=0.05, **extra)
+    ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, want_next=True,
+                  **oracle_model(model, g))
+    check_sweep(res, ref, g.n, "er20")
+    t = O.tail(ref["counts"], wl.R, eps=1e-3, r_lower=0.05, cert_topk=5)
+    assert_close_norm(res["Q"], t["Q"], 0.0, "Q")          # same operations: exact
+    assert_close_norm(res["N"], t["N"], what="N")
+    assert_close_norm(res["mu"], t["mu"], what="mu")
+    assert_close_norm(res["b"], t["b"], what="b")
+    assert abs(res["E_T"] - t["ET"]) <= TOL * t["ET"]
+    assert np.array_equal(res["top"], t["top"]) and np.array_equal(res["cert_v"], t["cert_v"])
+    assert_close_norm(res["cert_gap"], t["cert_gap"], what="gap")
+    assert_close_norm(res["cert_sharp"], t["cert_sharp"], what="sharp")
+    assert_close_norm(res["cert_sharp_supp"], t["cert_sharp_supp"], what="sharp_supp")
+    assert res["cert_crude"] == pytest.approx(t["cert_crude"], rel=1e-15)
+    assert res["epsbar_supp"] == pytest.approx(t["epsbar_supp"], rel=1e-15)
+    assert res["admissible"] == t["admissible"]
+    st = res["stats"]
+    assert st["mode"] == mode
+
+
+def test_debug_dump_distances_sigma_delta(ctx):
+    wl = W.config_er20()
+    g = wl.graph
+    pairs = [(0, 0), (3, 7), (999, 19), (500, 11)]
+    for mode in (amc.MODE_WAVE, amc.MODE_BLOCK):
+        res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, mode=mode,
+                      flags=amc.SKIP_TAIL, debug_pairs=pairs)
+        for k, (r, s) in enumerate(pairs):
+            alive, w = O.realize(g.n, g.eu, g.ev, wl.seed, r, **wl.model())
+            d, sg, dl = O.sssp(g.n, g.eu, g.ev, alive, w, False, s)
+            dd = np.where(d == np.iinfo(np.uint64).max, 0xFFFFFFFF, d).astype(np.uint32)
+            assert np.array_equal(res["dbg_dist"][k], dd), (mode, r, s)
+            assert np.array_equal(res["dbg_sigma"][k], sg), (mode, r, s)
+            assert_rel(res["dbg_delta"][k], dl, what=f"delta {mode} {(r, s)}")
+
+
+# --------------------------------------------------------------------------- edge cases
+def _case(ctx, g, model, R, **q):
+    flags = q.pop("flags", FLAGS)
+    res = gpu_run(ctx, g, model, R=R, flags=flags, **q)
+    ref = O.sweep(g.n, g.eu, g.ev, R=R, want_next=True, pool=q.get("pool"), seed=q.get("seed", 0),
+                  r_begin=q.get("r_begin", 0), alpha=q.get("alpha", 0.15), k_min=q.get("k_min", 5),
+                  **oracle_model(model, g))
+    check_sweep(res, ref, g.n, str(q))
+    return res, ref
+
+
+@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_BLOCK])
+def test_edge_cases(ctx, mode):
+    one = W.canonical(1, [])
+    _case(ctx, one, {"p_fail": 0.1}, 5, mode=mode, k_min=1)
+    empty = W.canonical(7, [])
+    _case(ctx, empty, {"p_fail": 0.5}, 9, mode=mode, k_min=1)
+    g = W.er_graph(40, 0.1, 3)
+    _case(ctx, g, {"p_fail": 1.0, "weight": "uniform", "w_lo": 1, "w_hi": 3}, 7, mode=mode)          # all fail
+    _case(ctx, g, {"p_fail": 0.0, "weight": "unit"}, 3, mode=mode, k_min=41)                      # k_min > n
+    _case(ctx, g, {"p_fail": 0.2, "weight": "uniform", "w_lo": 2, "w_hi": 2}, 11, mode=mode, alpha=1.0)
+    _case(ctx, g, {"p_fail": 0.2, "weight": "uniform", "w_lo": 1, "w_hi": 65535}, 5, mode=mode, seed=2 ** 40 + 7,
+          r_begin=4000000000)
+    path = W.canonical(60, [(i, i + 1) for i in range(59)])                                       # deep, one vertex per level
+    _case(ctx, path, {"p_fail": 0.02, "weight": "uniform", "w_lo": 1, "w_hi": 4}, 6, mode=mode, k_min=2)
+    cr, pf = W.crossroads()
+    _case(ctx, cr, {"p_fail": 0.0, "p_fail_edge": pf}, 300, mode=mode, alpha=0.1, k_min=3)
+    pw = W.powerlaw_weighted_graph(77, 254, 2.5, 3.0, 31, 0)
+    _case(ctx, pw, {"p_fail": 0.1, "weight": "fixed"}, 40, mode=mode, pool=np.array([0, 5, 9, 33, 70]))
+
+
+def test_sigma_overflow_reported(ctx):
+    a = 35
+    idx = lambda i, j: i * a + j
+    pairs = [(idx(i, j), idx(i, j + 1)) for i in range(a) for j in range(a - 1)]
+    pairs += [(idx(i, j), idx(i + 1, j)) for i in range(a - 1) for j in range(a)]
+    g = W.canonical(a * a, pairs)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    say("[gpu] sigma overflow grid 35x35")
+    with pytest.raises(amc.AmcError) as ei:
+        amc.run(ctx, G, {"p_fail": 0.0}, R=1, flags=amc.SKIP_TAIL)
+    assert ei.value.rc == amc.E_SIGMA_OVERFLOW
+    G.close()
+    a = 34
+    pairs = [(i * a + j, i * a + j + 1) for i in range(a) for j in range(a - 1)]
+    pairs += [(i * a + j, (i + 1) * a + j) for i in range(a - 1) for j in range(a)]
+    g = W.canonical(a * a, pairs)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    say("[gpu] sigma no overflow grid 34x34")
+    res = amc.run(ctx, G, {"p_fail": 0.0}, R=1, flags=amc.SKIP_TAIL, debug_pairs=[(0, 0)])
+    assert int(res["dbg_sigma"][0][-1]) == 7219428434016265740    # C(66, 33)
+    G.close()
+
+
+def test_invalid_arguments(ctx):
+    g = W.er_graph(10, 0.4, 1)
+    with pytest.raises(amc.AmcError) as ei:
+        amc.Graph(ctx, g.n, g.ev, g.eu)                      # not canonical
+    assert ei.value.rc == amc.E_INVALID_ARG
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    for bad in ({"model": {"p_fail": 1.5}}, {"model": {"p_fail": 0.1}, "R": 0},
+                {"model": {"p_fail": 0.1}, "alpha": 0.0},
+                {"model": {"p_fail": 0.1, "weight": "uniform", "w_lo": 0, "w_hi": 3}},
+                {"model": {"p_fail": 0.1}, "s": np.full(10, 0.2)},
+                {"model": {"p_fail": 0.1}, "pool": np.array([10])},
+                {"model": {"p_fail": 0.1, "weight": "fixed"}}):
+        bad = dict(bad)
+        model = bad.pop("model")
+        bad.setdefault("R", 4)
+        with pytest.raises(amc.AmcError) as ei:
+            amc.run(ctx, G, model, **bad)
+        assert ei.value.rc == amc.E_INVALID_ARG, bad
+    G.close()
+
+
+# --------------------------------------------------------------------------- configs 2 and 3 on sampled realizations
+def test_ws1000_sampled_realizations(ctx):
+    wl = W.config_ws1000()
+    g = wl.graph
+    for r0, R in ((0, 3), (7777, 2)):
+        res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
+                      flags=FLAGS, cert_topk=5)
+        ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
+                      want_next=True, **wl.model())
+        check_sweep(res, ref, g.n, f"ws1000 r0={r0}")
+        t = O.tail(ref["counts"], R, cert_topk=5)
+        assert_close_norm(res["b"], t["b"], what="b")
+        assert_close_norm(res["N"], t["N"], what="N")
+
+
+def test_er5000_sampled_realizations_with_pool(ctx):
+    wl = W.config_er5000()
+    g = wl.graph
+    R = 2
+    res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, pool=wl.pool)
+    assert res["stats"]["mode"] == amc.MODE_BLOCK
+    ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
+                  want_next=True, pool=wl.pool, **wl.model())
+    check_sweep(res, ref, g.n, "er5000")
+
+
+# --------------------------------------------------------------------------- systems properties
+def test_split_ranges_and_determinism(ctx):
+    wl = W.config_er20()
+    g = wl.graph
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    kw = dict(seed=5, alpha=0.15, k_min=5, flags=amc.WANT_NEXT_TABLE | amc.SKIP_TAIL)
+    say("[gpu] split ranges")
+    full = amc.run(ctx, G, wl.model(), R=300, **kw)
+    a = amc.run(ctx, G, wl.model(), R=120, r_begin=0, **kw)
+    b = amc.run(ctx, G, wl.model(), R=180, r_begin=120, **kw)
+    again = amc.run(ctx, G, wl.model(), R=300, **kw)
+    assert np.array_equal(full["counts"], a["counts"] + b["counts"])
+    assert np.array_equal(full["next_table"], np.vstack([a["next_table"], b["next_table"]]))
+    assert np.array_equal(full["counts"], again["counts"])
+    assert np.array_equal(full["next_table"], again["next_table"])
+    G.close()
+
+
+# --------------------------------------------------------------------------- tail alone (amc_chain)
+def test_chain_appendix_b(ctx, golden):
+    ref = golden("appendix_b.json")
+    Q0 = np.array(ref["Q0"])
+    say("[gpu] chain appendix B")
+    res = amc.chain(ctx, Q0, s=np.array(ref["s"]), flags=amc.WANT_N, eps=ref["eps_entry"], r_lower=ref["r_min"],
+                    cert_topk=1)
+    o = O.chain(Q0, np.array(ref["s"]))
+    assert_close_norm(res["N"], o["N"], what="N")
+    assert_close_norm(res["mu"], o["mu"], what="mu")
+    assert np.allclose(res["mu"], ref["mu"], atol=5e-5)
+    # top-1 is vertex 2 (index 1): boundary pairs (2,1) and (2,3)
+    assert list(res["top"]) == [1]
+    g21, _, s21 = O.pair_certificate(o["N"], o["mu"], ref["epsbar"], ref["r_min"], 1, 0)
+    assert res["cert_gap"][0, 0] == pytest.approx(g21, abs=1e-15)
+    assert res["cert_sharp"][0, 0] == pytest.approx(s21, rel=1e-12)
+    assert res["cert_sharp"][0, 0] == pytest.approx(ref["sharp_thresholds"]["2,1"], abs=5e-5)
+    assert res["cert_crude"] == pytest.approx(ref["crude_threshold"], abs=5e-5)
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 33, 64, 97, 300])
+def test_chain_random_kernels(ctx, n):
+    rng = np.random.default_rng(n)
+    Q = rng.random((n, n)) * (rng.random((n, n)) < 0.4)
+    rr = 0.1 + 0.4 * rng.random(n)
+    Q = Q / np.maximum(Q.sum(1, keepdims=True), 1e-300) * (1 - rr)[:, None]
+    s = rng.dirichlet(np.ones(n))
+    f = rng.random(n)
+    say(f"[gpu] chain random n={n}")
+    res = amc.chain(ctx, Q, s=s, reward=f, flags=amc.WANT_N, eps=1e-4, r_lower=0.1, cert_topk=min(3, n - 1))
+    o = O.chain(Q, s)
+    assert_close_norm(res["N"], o["N"], what="N")
+    assert_close_norm(res["b"], o["b"], what="b")
+    assert res["E_T"] == pytest.approx(o["ET"], rel=TOL)
+    assert res["b_f"] == pytest.approx(float(o["b"] @ f), rel=1e-12)
