@@ -68,7 +68,7 @@ def run_bench(args):
     ctx = amc.Context(0)
     G = amc.Graph(ctx, g.n, g.eu, g.ev)
     q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
-             r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile)
+             r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group)
     model = wl.model()
     for _ in range(args.warmup):
         amc.run(ctx, G, model, **q)
@@ -105,7 +105,8 @@ def run_bench(args):
         "config": {"workload": wl.name, "graph": "watts_strogatz(n=1000,k=10,beta=0.1,seed=0)", "n": g.n,
                    "m": g.m, "realizations": wl.R, "p_fail": wl.p_fail, "weights": "uniform{1..10}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
-                   "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"]},
+                   "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"], "group": st["group"],
+                   "adj_bytes": st["adj_bytes"]},
         "sweep_kernel_ms": k_ms,
         "tail_ms": float(np.mean(tail_ms)),
         "teps": teps,
@@ -185,6 +186,7 @@ def main():
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
     ap.add_argument("--serve", action="store_true")

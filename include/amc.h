@@ -117,6 +117,7 @@ typedef struct amc_query {
     int32_t mode;               /* AMC_MODE_*                                        */
     int32_t tile;               /* sources per work item; 0 = chosen by the engine   */
     int32_t waves;              /* wavefronts per workgroup; 0 = chosen by the engine */
+    int32_t group;              /* lanes per vertex in AMC_MODE_WAVE (1, 4, 8, 16); 0 = engine */
     const uint32_t *debug_pairs; /* AMC_WANT_DEBUG: n_debug pairs (r, s), r absolute */
     int32_t n_debug;            /* at most 64                                        */
 } amc_query;
@@ -130,7 +131,7 @@ typedef struct amc_stats {
     uint64_t units, sum_nK, sum_AK, sum_DK, near_band;
     double sweep_ms;            /* HIP-event time of the sweep kernel(s) on the context stream */
     double tail_ms;             /* HIP-event time of the tail kernels                          */
-    int32_t mode, waves, tile, blocks, lds_bytes, launches;
+    int32_t mode, waves, tile, blocks, lds_bytes, launches, group, adj_bytes;
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */

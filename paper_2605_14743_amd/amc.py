@@ -46,14 +46,15 @@ class Query(C.Structure):
                 ("k_min", C.c_uint32), ("tie_tau", C.c_double), ("floor_eta", C.c_double), ("s", _P(C.c_double)),
                 ("pool", _P(C.c_int32)), ("pool_size", C.c_int32), ("reward", _P(C.c_double)), ("eps", C.c_double),
                 ("r_lower", C.c_double), ("cert_topk", C.c_int32), ("flags", C.c_uint32), ("mode", C.c_int32),
-                ("tile", C.c_int32), ("waves", C.c_int32), ("debug_pairs", _P(C.c_uint32)), ("n_debug", C.c_int32)]
+                ("tile", C.c_int32), ("waves", C.c_int32), ("group", C.c_int32), ("debug_pairs", _P(C.c_uint32)),
+                ("n_debug", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("units", C.c_uint64), ("sum_nK", C.c_uint64), ("sum_AK", C.c_uint64), ("sum_DK", C.c_uint64),
                 ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
                 ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
-                ("launches", C.c_int32)]
+                ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -193,7 +194,7 @@ def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=N
 
 
 def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, floor_eta=-1.0, s=None, pool=None,
-               reward=None, eps=0.0, r_lower=0.05, cert_topk=0, flags=0, mode=MODE_AUTO, tile=0, waves=0,
+               reward=None, eps=0.0, r_lower=0.05, cert_topk=0, flags=0, mode=MODE_AUTO, tile=0, waves=0, group=0,
                debug_pairs=None):
     keep = []
     q = Query()
@@ -213,7 +214,7 @@ def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, 
         keep.append(ra)
         q.reward = _ptr(ra, C.c_double)
     q.eps, q.r_lower, q.cert_topk, q.flags = float(eps), float(r_lower), int(cert_topk), int(flags)
-    q.mode, q.tile, q.waves = int(mode), int(tile), int(waves)
+    q.mode, q.tile, q.waves, q.group = int(mode), int(tile), int(waves), int(group)
     if debug_pairs is not None and len(debug_pairs):
         dp = np.ascontiguousarray(np.asarray(debug_pairs, dtype=np.uint32).reshape(-1, 2))
         keep.append(dp)

@@ -272,6 +272,7 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
         if (q->debug_pairs[2 * k + 1] >= (uint32_t)n) return AMC_E_INVALID_ARG;
     if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_BLOCK) return AMC_E_INVALID_ARG;
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
+    if (q->group != 0 && q->group != 1 && q->group != 4 && q->group != 8 && q->group != 16) return AMC_E_INVALID_ARG;
     // longest possible distance must stay below the "unreached" sentinel
     const uint64_t wmax = md->weight_kind == AMC_WEIGHT_UNIT ? 1u
                           : md->weight_kind == AMC_WEIGHT_UNIFORM_INT
@@ -292,16 +293,31 @@ uint64_t prob_threshold(double p) {
 // per-source mode is used.
 int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, Plan *pl) {
     const int n = g->n;
-    const uint32_t adj_cap = (uint32_t)(2 * g->m);
+    const uint32_t adj_cap = (uint32_t)(2 * g->m) + kAdjPad;
     pl->weighted = md->weight_kind != AMC_WEIGHT_UNIT;
     const double avg_deg = n > 0 ? 2.0 * (double)g->m / n : 0.0;
-    pl->group = avg_deg <= 5.0 ? 4 : (avg_deg <= 14.0 ? 8 : 16);
+    (void)avg_deg;
+    pl->group = q->group > 0 ? q->group : 1;
+    // adjacency entry: neighbour in the low bits, weight above; 16 bits when both fit
+    uint32_t nbits = 1;
+    while ((1u << nbits) < (uint32_t)n) ++nbits;
+    const uint64_t wmax = md->weight_kind == AMC_WEIGHT_UNIT ? 1u
+                          : md->weight_kind == AMC_WEIGHT_UNIFORM_INT
+                              ? md->w_hi
+                              : (g->w0.empty() ? 1u : *std::max_element(g->w0.begin(), g->w0.end()));
+    if (nbits < 16 && wmax < (1ull << (16 - nbits))) {
+        pl->adj_bytes = 2;
+        pl->shift = nbits;
+    } else {
+        pl->adj_bytes = 4;
+        pl->shift = 16;
+    }
     int best_w = 0;
     uint32_t best_lds = 0, best_wb = 0;
     const int want_w = q->waves > 0 ? q->waves : kMaxWaves;
     for (int w = 2; w <= want_w; ++w) {
         uint32_t wb = 0;
-        const uint32_t lds = lds_bytes_wave(n, adj_cap, w, &wb);
+        const uint32_t lds = lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, &wb);
         if (lds > (uint32_t)ctx->max_lds) break;
         if ((uint64_t)wb * w < std::max<uint64_t>(2ull * (uint64_t)g->m, 32ull * (uint64_t)n)) continue;
         best_w = w;
@@ -621,7 +637,7 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
         for (uint32_t rl = 0; rl < R; ++rl) {
             P.item_base = rl * (uint32_t)pl.tiles_per_r;
             if (pl.mode == AMC_MODE_WAVE)
-                HIPCHK(launch_sweep_wave(P, pl.weighted, pl.group, pl.tiles_per_r, pl.waves, pl.lds, st));
+                HIPCHK(launch_sweep_wave(P, pl.weighted, pl.group, pl.adj_bytes, pl.shift, pl.tiles_per_r, pl.waves, pl.lds, st));
             else
                 HIPCHK(launch_sweep_block(P, pl.weighted, pl.tiles_per_r, pl.threads, pl.lds, bscratch, st));
             ++launches;
@@ -631,7 +647,7 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
         P.n_items = (uint32_t)pl.items;
         P.item_base = 0;
         if (pl.mode == AMC_MODE_WAVE)
-            HIPCHK(launch_sweep_wave(P, pl.weighted, pl.group, pl.blocks, pl.waves, pl.lds, st));
+            HIPCHK(launch_sweep_wave(P, pl.weighted, pl.group, pl.adj_bytes, pl.shift, pl.blocks, pl.waves, pl.lds, st));
         else
             HIPCHK(launch_sweep_block(P, pl.weighted, pl.blocks, pl.threads, pl.lds, bscratch, st));
         launches = 1;
@@ -668,6 +684,8 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
     out->stats.blocks = (q->flags & AMC_PLAIN_LAUNCH) ? pl.tiles_per_r : pl.blocks;
     out->stats.lds_bytes = (int32_t)pl.lds;
     out->stats.launches = launches;
+    out->stats.group = pl.group;
+    out->stats.adj_bytes = (int32_t)pl.adj_bytes;
     out->stats.tail_ms = 0.0;
     if (!(q->flags & AMC_SKIP_TAIL)) {
         const double eta = q->floor_eta < 0.0 ? 0.1 / std::sqrt((double)R) : q->floor_eta;

@@ -91,6 +91,7 @@ struct SweepParams {
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps
 constexpr int kMaxWaves = 16;
+constexpr uint32_t kAdjPad = 8;          // zero entries after the realized adjacency
 
 // ---------------------------------------------------------------------------
 // Wavefront helpers (wave64).
@@ -141,6 +142,81 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// ---------------------------------------------------------------------------
+// DPP lane exchanges (VALU only, no LDS traffic).  All callers run with the
+// whole wavefront active.
+//   0xB1 quad_perm [1,0,3,2]  (lane ^ 1)      0x4E quad_perm [2,3,0,1] (lane ^ 2)
+//   0x141 row_half_mirror (7 - lane in 8)     0x140 row_mirror (15 - lane in 16)
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+    const uint32_t lo = dpp32<CTRL>((uint32_t)v), hi = dpp32<CTRL>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum over aligned groups of G lanes (G in 1, 4, 8, 16); every lane of a group
+// receives the group total.  `ovf` records a wrap of the uint64 sum.
+template <int G>
+__device__ __forceinline__ unsigned long long group_sum_u64(unsigned long long x, bool &ovf) {
+    unsigned long long y, t;
+    if (G >= 2) { y = dpp64<0xB1>(x); t = x + y; ovf |= t < x; x = t; }
+    if (G >= 4) { y = dpp64<0x4E>(x); t = x + y; ovf |= t < x; x = t; }
+    if (G >= 8) { y = dpp64<0x141>(x); t = x + y; ovf |= t < x; x = t; }
+    if (G >= 16) { y = dpp64<0x140>(x); t = x + y; ovf |= t < x; x = t; }
+    return x;
+}
+template <int G>
+__device__ __forceinline__ double group_sum_f64(double x) {
+    if (G >= 2) x += __longlong_as_double((long long)dpp64<0xB1>((unsigned long long)__double_as_longlong(x)));
+    if (G >= 4) x += __longlong_as_double((long long)dpp64<0x4E>((unsigned long long)__double_as_longlong(x)));
+    if (G >= 8) x += __longlong_as_double((long long)dpp64<0x141>((unsigned long long)__double_as_longlong(x)));
+    if (G >= 16) x += __longlong_as_double((long long)dpp64<0x140>((unsigned long long)__double_as_longlong(x)));
+    return x;
+}
+// Minimum / maximum over the wavefront, returned uniformly.
+__device__ __forceinline__ uint32_t wave_min_fast(uint32_t x) {
+    uint32_t y;
+    y = dpp32<0xB1>(x); x = y < x ? y : x;
+    y = dpp32<0x4E>(x); x = y < x ? y : x;
+    y = dpp32<0x141>(x); x = y < x ? y : x;
+    y = dpp32<0x140>(x); x = y < x ? y : x;
+    const uint32_t a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 16);
+    const uint32_t c = __builtin_amdgcn_readlane(x, 32), d = __builtin_amdgcn_readlane(x, 48);
+    const uint32_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
+}
+__device__ __forceinline__ uint32_t wave_max_fast(uint32_t x) {
+    uint32_t y;
+    y = dpp32<0xB1>(x); x = y > x ? y : x;
+    y = dpp32<0x4E>(x); x = y > x ? y : x;
+    y = dpp32<0x141>(x); x = y > x ? y : x;
+    y = dpp32<0x140>(x); x = y > x ? y : x;
+    const uint32_t a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 16);
+    const uint32_t c = __builtin_amdgcn_readlane(x, 32), d = __builtin_amdgcn_readlane(x, 48);
+    const uint32_t ab = a > b ? a : b, cd = c > d ? c : d;
+    return ab > cd ? ab : cd;
+}
+
+// Appends the lanes with `pred` set to a queue whose tail is *ctr (LDS): one
+// LDS atomic per wavefront; returns each appending lane's slot.  Called with
+// the whole wavefront active.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred) {
+    const uint64_t mask = __ballot(pred);
+    uint32_t pos = 0;
+    if (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(mask));
+        base = __builtin_amdgcn_readlane(base, leader);
+        pos = base + (uint32_t)__popcll(mask & lanemask_lt());
+    }
+    return pos;
 }
 
 __device__ __forceinline__ double as_f64(unsigned long long b) { return __longlong_as_double((long long)b); }

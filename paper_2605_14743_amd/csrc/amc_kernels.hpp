@@ -10,9 +10,9 @@
 namespace amc {
 
 // LDS-resident sweep (one wavefront per (r, s)).
-uint32_t lds_bytes_wave(int n, uint32_t adj_cap, int waves, uint32_t *wave_bytes);
-hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, int blocks, int waves, uint32_t lds,
-                             hipStream_t st);
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
+hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, uint32_t adj_bytes, uint32_t shift,
+                             int blocks, int waves, uint32_t lds, hipStream_t st);
 
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);

@@ -26,6 +26,8 @@ struct Plan {
     int mode = 0;
     bool weighted = false;
     int group = 8;                  // lanes per vertex in the LDS mode
+    uint32_t adj_bytes = 4;         // LDS adjacency entry: 2 (packed) or 4 bytes
+    uint32_t shift = 16;            // neighbour bits of an adjacency entry
     int waves = 0, threads = 0;
     uint32_t lds = 0, wave_bytes = 0, adj_cap = 0;
     int tile = 0, tiles_per_r = 1;

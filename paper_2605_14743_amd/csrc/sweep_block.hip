@@ -25,21 +25,6 @@ namespace amc {
 
 constexpr int kBG = 4;   // lanes per vertex in the block mode
 
-// Appends the lanes with `pred` set to a queue whose tail is *ctr (LDS): one
-// atomic per wavefront; returns each appending lane's slot.
-__device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred) {
-    const uint64_t mask = __ballot(pred);
-    uint32_t pos = 0;
-    if (mask) {
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(mask));
-        base = __builtin_amdgcn_readlane(base, leader);
-        pos = base + (uint32_t)__popcll(mask & lanemask_lt());
-    }
-    return pos;
-}
-
 struct BlockLayout {
     uint32_t dist, sig, ord, aux, B, comp, csize, total;
 };
@@ -270,15 +255,15 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32
     double *B = (double *)(smem + L.B);
     uint16_t *comp = (uint16_t *)(smem + L.comp);
     uint16_t *csize = (uint16_t *)(smem + L.csize);
-    // per-workgroup global scratch: realized rp (n+1), adjacency (2m),
-    // component centres and slot counts (4 n)
+    // per-workgroup global scratch: realized rp (n+1), adjacency (2m plus
+    // padding), component centres and slot counts (4 n)
     uint32_t *gs = scratch + (size_t)blockIdx.x * scratch_words;
     uint32_t *rp = gs;
     uint32_t *adj = rp + (n + 1);
     ReduceScratch RS;
     RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
     RS.wmax = RS.cmax + n;
-    uint32_t *tail4 = adj + 2 * (size_t)P.m;
+    uint32_t *tail4 = adj + 2 * (size_t)P.m + kAdjPad;
     RS.ccen = (int32_t *)tail4;
     RS.wcen = RS.ccen + n;
     RS.kal = (uint32_t *)(RS.wcen + n);
@@ -304,7 +289,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32
         const int t = (int)(item % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
 
-        stage_realization(P, r, rp, adj, (uint16_t *)smem, scan_tmp);
+        stage_realization(P, r, rp, adj, 16u, (uint16_t *)smem, scan_tmp);
         for (int v = tid; v < n; v += nthr) B[v] = 0.0;
         __syncthreads();
 
@@ -361,7 +346,9 @@ uint32_t lds_bytes_block(int n, int threads) {
     return block_layout(n).total;
 }
 
-size_t block_scratch_words(int n, int64_t m) { return (size_t)(n + 1) + 2 * (size_t)m + 4 * (size_t)n + 64; }
+size_t block_scratch_words(int n, int64_t m) {
+    return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 4 * (size_t)n + 64;
+}
 
 hipError_t launch_sweep_block(const SweepParams &P, bool weighted, int blocks, int threads, uint32_t lds,
                               uint32_t *scratch, hipStream_t st) {

@@ -47,10 +47,11 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint3
 
 // Realizes every base edge of realization r (Section 3.1) and builds the
 // compacted adjacency of H_r: rp[v] .. rp[v+1] index adj, each entry holds
-// (weight << 16) | neighbour.  `ew` is scratch for the per-edge weights
+// (weight << shift) | neighbour.  `ew` is scratch for the per-edge weights
 // (0 = the edge failed).
-__device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint32_t *rp, uint32_t *adj, uint16_t *ew,
-                                  uint32_t *scan_tmp) {
+template <typename ADJ>
+__device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint32_t *rp, ADJ *adj, uint32_t shift,
+                                         uint16_t *ew, uint32_t *scan_tmp) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int n = P.n;
     for (int64_t e = tid; e < P.m; e += nthr) {
@@ -75,10 +76,11 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint3
         rp[v] = pos;
         for (int j = P.rp_base[v]; j < P.rp_base[v + 1]; ++j) {
             const uint32_t w = ew[P.slot_edge[j]];
-            if (w) adj[pos++] = (w << 16) | (uint32_t)P.col[j];
+            if (w) adj[pos++] = (ADJ)((w << shift) | (uint32_t)P.col[j]);
         }
     }
     if (tid == 0) rp[n] = total;
+    if (tid < (int)kAdjPad) adj[total + tid] = (ADJ)0;   // padding read by unpredicated loads
     __syncthreads();
 }
 

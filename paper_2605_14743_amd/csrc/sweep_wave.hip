@@ -32,16 +32,18 @@ namespace amc {
 //   ord[n]   settled vertices in non-decreasing distance
 //   aux[n]   front: unsettled reached vertices (integer weights only);
 //            back:  start of each equal-distance segment of ord
-// G lanes cooperate on one vertex's adjacency.
+// G lanes cooperate on one vertex's adjacency; an adjacency entry holds the
+// neighbour in its low `shift` bits and the weight above them.
 // ---------------------------------------------------------------------------
-template <bool WEIGHTED, int G>
-__device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint32_t *adj, double *B, uint32_t *dist,
-                            unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctr, int s,
-                            int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
+template <bool WEIGHTED, int G, typename ADJ>
+__device__ void wave_source(const SweepParams &P, const uint32_t *rp, const ADJ *adj, uint32_t shift, double *B,
+                            uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctr,
+                            int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
     const int n = P.n;
     const int lane = threadIdx.x & 63;
     const int sub = lane % G;
     constexpr int VPI = 64 / G;   // vertices per wave iteration
+    const uint32_t nmask = (1u << shift) - 1u;
 
     for (int v = lane; v < n; v += 64) dist[v] = kInf;
     wave_sync();
@@ -55,44 +57,50 @@ __device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint
 
     int f_lo = 0, ord_end = 1, nseg = 0;
     uint32_t D = 0;
+    uint32_t kmin = kInf;   // lane minimum over the fringe entries kept by the last partition
     // ------------------------------------------------------------ forward
     for (;;) {
         if (lane == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
         ++nseg;
+        uint32_t lmin = kInf;  // lane minimum over successful relaxations
         for (int base = f_lo; base < ord_end; base += VPI) {
             const int idx = base + lane / G;
             const bool mine = idx < ord_end;
-            unsigned long long acc = 0ull;
             int v = 0;
+            uint32_t beg = 0, len = 0;
             if (mine) {
                 v = ord[idx];
-                const uint32_t beg = rp[v], end = rp[v + 1];
-                for (uint32_t j = beg + sub; j < end; j += G) {
-                    const uint32_t a = adj[j];
-                    const uint32_t u = a & 0xFFFFu;
-                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
+                beg = rp[v];
+                len = rp[v + 1] - beg;
+            }
+            const uint32_t trips = len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u;
+            const uint32_t maxtrips = wave_max_fast(trips);
+            unsigned long long acc = 0ull;
+            for (uint32_t t = 0; t < maxtrips; ++t) {
+                bool found = false;
+                uint32_t u = 0;
+                if (t < trips) {
+                    const uint32_t a = adj[beg + (uint32_t)sub + t * G];
+                    u = a & nmask;
+                    const uint32_t w = WEIGHTED ? (a >> shift) : 1u;
                     const uint32_t du = dist[u];
                     if (du + w == D) {                       // u precedes v: pull sigma_u
-                        const unsigned long long t = acc + sig[u];
-                        ovf |= t < acc;
-                        acc = t;
+                        const unsigned long long x = acc + sig[u];
+                        ovf |= x < acc;
+                        acc = x;
                     } else if (D + w < du) {                 // relax the edge v -> u
                         const uint32_t old = atomicMin(&dist[u], D + w);
-                        if (old == kInf) {                   // first discovery of u
-                            const uint32_t pos = atomicAdd(ctr, 1u);
-                            if (WEIGHTED) aux[pos] = (uint16_t)u;
-                            else ord[pos] = (uint16_t)u;
-                        }
+                        if (old > D + w) lmin = (D + w) < lmin ? (D + w) : lmin;
+                        found = old == kInf;                 // first discovery of u
                     }
                 }
+                const uint32_t pos = wave_append(ctr, found);
+                if (found) {
+                    if (WEIGHTED) aux[pos] = (uint16_t)u;
+                    else ord[pos] = (uint16_t)u;
+                }
             }
-#pragma unroll
-            for (int off = 1; off < G; off <<= 1) {
-                const unsigned long long o = __shfl_xor(acc, off, 64);
-                const unsigned long long t = acc + o;
-                ovf |= t < acc;
-                acc = t;
-            }
+            acc = group_sum_u64<G>(acc, ovf);
             if (mine && sub == 0 && v != s) sig[v] = acc;
         }
         wave_sync();
@@ -105,22 +113,22 @@ __device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint
         } else {
             const int fr = (int)*ctr;
             if (fr == 0) break;
-            uint32_t mn = kInf;
-            for (int k = lane; k < fr; k += 64) {
-                const uint32_t dk = dist[aux[k]];
-                mn = dk < mn ? dk : mn;
-            }
-            mn = wave_min_u32(mn);
+            // the fringe minimum: every current fringe distance is either a
+            // value kept at the last partition or a successful relaxation
+            const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
             // move the vertices at the new minimum distance to ord, keep the
             // rest (compacted in place: writes never pass the read position)
             int settled = 0, kept = 0;
+            kmin = kInf;
             const uint64_t lt = lanemask_lt();
             for (int k0 = 0; k0 < fr; k0 += 64) {
                 const int k = k0 + lane;
                 const bool valid = k < fr;
                 const uint32_t x = valid ? aux[k] : 0u;
-                const bool is_s = valid && dist[x] == mn;
+                const uint32_t dx = valid ? dist[x] : kInf;
+                const bool is_s = valid && dx == mn;
                 const bool is_k = valid && !is_s;
+                if (is_k) kmin = dx < kmin ? dx : kmin;
                 const uint64_t ms = __ballot(is_s), mk = __ballot(is_k);
                 if (is_s) ord[ord_end + settled + __popcll(ms & lt)] = (uint16_t)x;
                 if (is_k) aux[kept + __popcll(mk & lt)] = (uint16_t)x;
@@ -137,9 +145,9 @@ __device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint
 
     // component of s: smallest reached index, and its size
     {
-        int mn = n;
-        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (int)ord[k]);
-        comp_out = wave_min_i32(mn);
+        uint32_t mn = (uint32_t)n;
+        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)ord[k]);
+        comp_out = (int)wave_min_fast(mn);
         size_out = ord_end;
     }
     if (dbg_slot >= 0) {
@@ -167,18 +175,17 @@ __device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint
                 const uint32_t beg = rp[v], end = rp[v + 1];
                 for (uint32_t j = beg + sub; j < end; j += G) {
                     const uint32_t a = adj[j];
-                    const uint32_t u = a & 0xFFFFu;
-                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
+                    const uint32_t u = a & nmask;
+                    const uint32_t w = WEIGHTED ? (a >> shift) : 1u;
                     if (dist[u] == dv + w) sum += as_f64(sig[u]);   // u succeeds v: c_u
                 }
             }
-#pragma unroll
-            for (int off = 1; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
+            sum = group_sum_f64<G>(sum);
             if (mine && sub == 0) {
                 const double sv = (double)sig[v];
                 const double delta = sv * sum;
                 sig[v] = as_u64((1.0 + delta) / sv);
-                if (v != s) atomicAdd(&B[v], delta);
+                if (v != s) unsafeAtomicAdd(&B[v], delta);
                 if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
             }
         }
@@ -186,23 +193,246 @@ __device__ void wave_source(const SweepParams &P, const uint32_t *rp, const uint
     }
 }
 
-// Byte offsets of the LDS carve-up (mirrors lds_layout_wave on the host).
+// ---------------------------------------------------------------------------
+// Lane-per-vertex variant of wave_source: each lane owns one frontier vertex
+// and walks its adjacency U slots at a time, issuing the U neighbour loads
+// (and the U distance loads) back to back so that their LDS latencies
+// overlap; the path count of the vertex accumulates in the lane itself.  The
+// U appends of a block share one LDS atomic per wavefront.
+// ---------------------------------------------------------------------------
+template <int U>
+__device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[U], uint32_t (&pos)[U]) {
+    uint64_t m[U];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        m[k] = __ballot(found[k]);
+        tot += (uint32_t)__popcll(m[k]);
+    }
+    if (tot == 0) return;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(ctr, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        pos[k] = base + (uint32_t)__popcll(m[k] & lt);
+        base += (uint32_t)__popcll(m[k]);
+    }
+}
+
+template <bool WEIGHTED, int U, typename ADJ>
+__device__ void wave_source_lane(const SweepParams &P, const uint32_t *rp, const ADJ *adj, uint32_t shift,
+                                 double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux,
+                                 uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
+    const int n = P.n;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nmask = (1u << shift) - 1u;
+
+    for (int v = lane; v < n; v += 64) dist[v] = kInf;
+    wave_sync();
+    if (lane == 0) {
+        dist[s] = 0u;
+        sig[s] = 1ull;
+        ord[0] = (uint16_t)s;
+        *ctr = WEIGHTED ? 0u : 1u;
+    }
+    wave_sync();
+
+    int f_lo = 0, ord_end = 1, nseg = 0;
+    uint32_t D = 0;
+    uint32_t kmin = kInf;
+    // ------------------------------------------------------------ forward
+    for (;;) {
+        if (lane == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
+        ++nseg;
+        uint32_t lmin = kInf;
+        for (int base = f_lo; base < ord_end; base += 64) {
+            const int idx = base + lane;
+            const bool mine = idx < ord_end;
+            int v = 0;
+            uint32_t beg = 0, len = 0;
+            if (mine) {
+                v = ord[idx];
+                beg = rp[v];
+                len = rp[v + 1] - beg;
+            }
+            const uint32_t maxlen = wave_max_fast(len);
+            unsigned long long acc = 0ull;
+            for (uint32_t off = 0; off < maxlen; off += U) {
+                uint32_t u[U], w[U], du[U];
+                bool found[U];
+                // the adjacency carries kAdjPad zero entries past its end, so
+                // these loads need no predication; masked results are dropped
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t a = (uint32_t)adj[beg + off + k];
+                    u[k] = a & nmask;
+                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
+#pragma unroll
+                for (int k = 0; k < U; ++k) du[k] = w[k] ? du[k] : kInf;
+                bool pred[U], rel[U];
+                unsigned long long sg[U];
+                uint32_t old[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    pred[k] = w[k] != 0u && du[k] + w[k] == D;          // u precedes v: pull sigma_u
+                    rel[k] = w[k] != 0u && D + w[k] < du[k];            // relax the edge v -> u
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
+#pragma unroll
+                for (int k = 0; k < U; ++k) old[k] = rel[k] ? atomicMin(&dist[u[k]], D + w[k]) : 0u;
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const unsigned long long x = acc + sg[k];
+                    ovf |= x < acc;
+                    acc = x;
+                    const uint32_t cand = (rel[k] && old[k] > D + w[k]) ? D + w[k] : kInf;
+                    lmin = cand < lmin ? cand : lmin;
+                    found[k] = rel[k] && old[k] == kInf;                // first discovery of u
+                }
+                uint32_t pos[U];
+                append_block<U>(ctr, found, pos);
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    if (found[k]) {
+                        if (WEIGHTED) aux[pos[k]] = (uint16_t)u[k];
+                        else ord[pos[k]] = (uint16_t)u[k];
+                    }
+            }
+            if (mine && v != s) sig[v] = acc;
+        }
+        wave_sync();
+        if (!WEIGHTED) {
+            const int new_end = (int)*ctr;
+            if (new_end == ord_end) break;
+            f_lo = ord_end;
+            ord_end = new_end;
+            D += 1u;
+        } else {
+            const int fr = (int)*ctr;
+            if (fr == 0) break;
+            const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
+            int settled = 0, kept = 0;
+            kmin = kInf;
+            const uint64_t lt = lanemask_lt();
+            for (int k0 = 0; k0 < fr; k0 += 64 * U) {
+                uint32_t x[U], dx[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    const int k = k0 + 64 * c + lane;
+                    x[c] = k < fr ? (uint32_t)aux[k] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int c = 0; c < U; ++c) dx[c] = x[c] != 0xFFFFFFFFu ? dist[x[c]] : kInf;
+                // all reads of the U chunks precede their writes (positions
+                // never pass the read positions)
+                wave_sync();
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    const bool valid = x[c] != 0xFFFFFFFFu;
+                    const bool is_s = valid && dx[c] == mn;
+                    const bool is_k = valid && !is_s;
+                    if (is_k) kmin = dx[c] < kmin ? dx[c] : kmin;
+                    const uint64_t ms = __ballot(is_s), mk = __ballot(is_k);
+                    if (is_s) ord[ord_end + settled + __popcll(ms & lt)] = (uint16_t)x[c];
+                    if (is_k) aux[kept + __popcll(mk & lt)] = (uint16_t)x[c];
+                    settled += __popcll(ms);
+                    kept += __popcll(mk);
+                }
+            }
+            if (lane == 0) *ctr = (uint32_t)kept;
+            wave_sync();
+            f_lo = ord_end;
+            ord_end += settled;
+            D = mn;
+        }
+    }
+
+    {
+        uint32_t mn = (uint32_t)n;
+        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)ord[k]);
+        comp_out = (int)wave_min_fast(mn);
+        size_out = ord_end;
+    }
+    if (dbg_slot >= 0) {
+        for (int v = lane; v < n; v += 64) {
+            const uint32_t d = dist[v];
+            P.dbg_dist[(size_t)dbg_slot * n + v] = d == kInf ? 0xFFFFFFFFu : d;
+            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == kInf ? 0ull : sig[v];
+            P.dbg_delta[(size_t)dbg_slot * n + v] = 0.0;
+        }
+        wave_sync();
+    }
+
+    // ------------------------------------------------------------ backward
+    for (int k = nseg - 1; k >= 0; --k) {
+        const int lo = aux[n - 1 - k];
+        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
+        for (int base = lo; base < hi; base += 64) {
+            const int idx = base + lane;
+            const bool mine = idx < hi;
+            int v = 0;
+            uint32_t beg = 0, len = 0, dv = 0;
+            if (mine) {
+                v = ord[idx];
+                beg = rp[v];
+                len = rp[v + 1] - beg;
+                dv = dist[v];
+            }
+            double sum = 0.0;
+            for (uint32_t off = 0; off < len; off += U) {
+                uint32_t u[U], w[U], du[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t a = (uint32_t)adj[beg + off + k];
+                    u[k] = a & nmask;
+                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
+#pragma unroll
+                for (int k = 0; k < U; ++k) du[k] = w[k] ? du[k] : kInf;
+                double cu[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) cu[k] = (w[k] && du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
+#pragma unroll
+                for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
+            }
+            if (mine) {
+                const double sv = (double)sig[v];
+                const double delta = sv * sum;
+                sig[v] = as_u64((1.0 + delta) / sv);
+                if (v != s) unsafeAtomicAdd(&B[v], delta);
+                if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Byte offsets of the LDS carve-up (mirrors lds_bytes_wave on the host).
 struct WaveLayout {
     uint32_t rp, adj, B, comp, csize, waves;
 };
-__device__ __forceinline__ WaveLayout wave_layout(int n, uint32_t adj_cap) {
+__host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint32_t adj_bytes) {
     WaveLayout L;
+    const uint32_t un = (uint32_t)n;
     L.rp = 0;
-    L.adj = L.rp + 4u * (uint32_t)(n + 1);
-    L.B = (L.adj + 4u * adj_cap + 7u) & ~7u;
-    L.comp = L.B + 8u * (uint32_t)n;
-    L.csize = L.comp + 4u * (uint32_t)n;
-    L.waves = (L.csize + 4u * (uint32_t)n + 15u) & ~15u;
+    L.adj = L.rp + 4u * (un + 1u);
+    L.B = (L.adj + adj_bytes * adj_cap + 7u) & ~7u;
+    L.comp = L.B + 8u * un;
+    L.csize = L.comp + 2u * un;
+    L.waves = (L.csize + 2u * un + 15u) & ~15u;
     return L;
 }
 
-template <bool WEIGHTED, int G>
-__global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
+template <bool WEIGHTED, int G, typename ADJ>
+__global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_t shift) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -213,16 +443,19 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
     const int n = P.n;
-    const WaveLayout L = wave_layout(n, P.adj_cap);
+    const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
     uint32_t *rp = (uint32_t *)(smem + L.rp);
-    uint32_t *adj = (uint32_t *)(smem + L.adj);
+    ADJ *adj = (ADJ *)(smem + L.adj);
     double *B = (double *)(smem + L.B);
-    int32_t *comp = (int32_t *)(smem + L.comp);
-    int32_t *csize = (int32_t *)(smem + L.csize);
+    uint16_t *comp = (uint16_t *)(smem + L.comp);
+    uint16_t *csize = (uint16_t *)(smem + L.csize);
     unsigned char *wbase = smem + L.waves;
-    uint32_t *dist = (uint32_t *)(wbase + (size_t)wave * P.wave_bytes);
-    unsigned long long *sig = (unsigned long long *)(((uintptr_t)(dist + n) + 7u) & ~(uintptr_t)7u);
-    uint16_t *ord = (uint16_t *)(sig + n);
+    // byte offsets from the LDS base keep every pointer in the LDS address space
+    unsigned char *wmine = wbase + wave * P.wave_bytes;
+    const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
+    uint32_t *dist = (uint32_t *)wmine;
+    unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
+    uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
     uint16_t *aux = ord + n;
     ReduceScratch RS;
     RS.cmax = (unsigned long long *)wbase;
@@ -252,7 +485,7 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
         const int t = (int)(item % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
 
-        stage_realization(P, r, rp, adj, (uint16_t *)wbase, scan_tmp);
+        stage_realization(P, r, rp, adj, shift, (uint16_t *)wbase, scan_tmp);
         for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
         __syncthreads();
 
@@ -260,10 +493,15 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
         for (int s = s_lo + wave; s < s_hi; s += nwaves) {
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            wave_source<WEIGHTED, G>(P, rp, adj, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs, sz, ovf);
+            if constexpr (G == 1)
+                wave_source_lane<WEIGHTED, 4, ADJ>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot,
+                                                   cs, sz, ovf);
+            else
+                wave_source<WEIGHTED, G, ADJ>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs,
+                                              sz, ovf);
             if (lane == 0) {
-                comp[s] = cs;
-                csize[s] = sz;
+                comp[s] = (uint16_t)cs;
+                csize[s] = (uint16_t)sz;
             }
         }
         __syncthreads();
@@ -288,10 +526,10 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
                 __threadfence();
                 for (int v = tid; v < n; v += blockDim.x) {
                     B[v] = __hip_atomic_load(&Bg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    comp[v] = __hip_atomic_load(&P.compg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                    csize[v] = __hip_atomic_load(&P.sizeg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    comp[v] = (uint16_t)__hip_atomic_load(&P.compg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    csize[v] = (uint16_t)__hip_atomic_load(&P.sizeg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __syncthreads();
                 reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
@@ -311,37 +549,42 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P) {
 // ---------------------------------------------------------------------------
 // Host-side launch (compiled into the same object).
 // ---------------------------------------------------------------------------
-uint32_t lds_bytes_wave(int n, uint32_t adj_cap, int waves, uint32_t *wave_bytes) {
-    const uint32_t per_wave = ((4u * (uint32_t)n + 7u) & ~7u) + 8u * (uint32_t)n + 2u * (uint32_t)n + 2u * (uint32_t)n;
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes) {
+    const uint32_t un = (uint32_t)n;
+    const uint32_t per_wave = ((4u * un + 7u) & ~7u) + 8u * un + 2u * un + 2u * un;
     const uint32_t wb = (per_wave + 15u) & ~15u;
-    const uint32_t head = (((((4u * (uint32_t)(n + 1) + 4u * adj_cap) + 7u) & ~7u) + 16u * (uint32_t)n) + 15u) & ~15u;
     if (wave_bytes) *wave_bytes = wb;
-    return head + wb * (uint32_t)waves;
+    return wave_layout(n, adj_cap, adj_bytes).waves + wb * (uint32_t)waves;
 }
 
-template <bool W, int G>
-static hipError_t launch_t(const SweepParams &P, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    auto k = sweep_wave_kernel<W, G>;
+template <bool W, int G, typename ADJ>
+static hipError_t launch_t(const SweepParams &P, uint32_t shift, int blocks, int waves, uint32_t lds,
+                           hipStream_t st) {
+    auto k = sweep_wave_kernel<W, G, ADJ>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * waves), lds, st, P);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * waves), lds, st, P, shift);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, int blocks, int waves, uint32_t lds,
-                             hipStream_t st) {
-    if (weighted) {
-        switch (group) {
-            case 4: return launch_t<true, 4>(P, blocks, waves, lds, st);
-            case 16: return launch_t<true, 16>(P, blocks, waves, lds, st);
-            default: return launch_t<true, 8>(P, blocks, waves, lds, st);
-        }
-    }
+template <bool W, typename ADJ>
+static hipError_t launch_g(const SweepParams &P, int group, uint32_t shift, int blocks, int waves, uint32_t lds,
+                           hipStream_t st) {
     switch (group) {
-        case 4: return launch_t<false, 4>(P, blocks, waves, lds, st);
-        case 16: return launch_t<false, 16>(P, blocks, waves, lds, st);
-        default: return launch_t<false, 8>(P, blocks, waves, lds, st);
+        case 1: return launch_t<W, 1, ADJ>(P, shift, blocks, waves, lds, st);
+        case 4: return launch_t<W, 4, ADJ>(P, shift, blocks, waves, lds, st);
+        case 16: return launch_t<W, 16, ADJ>(P, shift, blocks, waves, lds, st);
+        default: return launch_t<W, 8, ADJ>(P, shift, blocks, waves, lds, st);
     }
+}
+
+hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, uint32_t adj_bytes, uint32_t shift,
+                             int blocks, int waves, uint32_t lds, hipStream_t st) {
+    if (adj_bytes == 2)
+        return weighted ? launch_g<true, uint16_t>(P, group, shift, blocks, waves, lds, st)
+                        : launch_g<false, uint16_t>(P, group, shift, blocks, waves, lds, st);
+    return weighted ? launch_g<true, uint32_t>(P, group, shift, blocks, waves, lds, st)
+                    : launch_g<false, uint32_t>(P, group, shift, blocks, waves, lds, st);
 }
 
 }  // namespace amc

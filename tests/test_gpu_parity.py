@@ -88,7 +88,8 @@ FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.WANT_N
 # --------------------------------------------------------------------------- config 1: full size, all modes
 @pytest.mark.parametrize("mode,extra", [(amc.MODE_WAVE, {}), (amc.MODE_BLOCK, {}),
                                         (amc.MODE_WAVE, {"tile": 3}), (amc.MODE_WAVE, {"flags": amc.PLAIN_LAUNCH}),
-                                        (amc.MODE_BLOCK, {"tile": 7})])
+                                        (amc.MODE_BLOCK, {"tile": 7}), (amc.MODE_WAVE, {"group": 4}),
+                                        (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"group": 16})])
 def test_er20_full_against_oracle(ctx, mode, extra):
     wl = W.config_er20()
     g = wl.graph
@@ -143,8 +144,18 @@ def _case(ctx, g, model, R, **q):
     return res, ref
 
 
-@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_BLOCK])
+@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_BLOCK, "wave-g8"])
 def test_edge_cases(ctx, mode):
+    if mode == "wave-g8":
+        global _case
+        base_case = _case
+
+        def _case(ctx_, g_, model_, R_, **q_):
+            return base_case(ctx_, g_, model_, R_, group=8, **q_)
+        try:
+            return test_edge_cases(ctx, amc.MODE_WAVE)
+        finally:
+            _case = base_case
     one = W.canonical(1, [])
     _case(ctx, one, {"p_fail": 0.1}, 5, mode=mode, k_min=1)
     empty = W.canonical(7, [])
