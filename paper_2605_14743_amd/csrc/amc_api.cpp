@@ -87,7 +87,7 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
     c->cu_count = prop.multiProcessorCount;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
-    c->max_lds = lds - 1024;   // headroom for the kernels' static LDS
+    c->max_lds = lds - 512;    // headroom for the kernels' static LDS
     int pools = 0;
     if (hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) != hipSuccess) pools = 0;
     c->async_alloc = pools != 0;
@@ -305,7 +305,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
                           : md->weight_kind == AMC_WEIGHT_UNIFORM_INT
                               ? md->w_hi
                               : (g->w0.empty() ? 1u : *std::max_element(g->w0.begin(), g->w0.end()));
-    if (nbits < 16 && wmax < (1ull << (16 - nbits))) {
+    if (nbits < 16 && wmax < (1ull << (16 - nbits)) && adj_cap <= 65535u) {
         pl->adj_bytes = 2;
         pl->shift = nbits;
     } else {

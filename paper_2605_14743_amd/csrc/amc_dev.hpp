@@ -90,6 +90,10 @@ struct SweepParams {
 };
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps
+// Weight given to an adjacency slot past a vertex's list: for every distance
+// d <= kInf and every reached distance D < kInf, d + kNoEdge != D,
+// D + kNoEdge > d and d != D + kNoEdge, and no sum exceeds 2^31.
+constexpr uint32_t kNoEdge = kInf + 1u;
 constexpr int kMaxWaves = 16;
 constexpr uint32_t kAdjPad = 8;          // zero entries after the realized adjacency
 

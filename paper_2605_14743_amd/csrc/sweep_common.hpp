@@ -49,8 +49,8 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint3
 // compacted adjacency of H_r: rp[v] .. rp[v+1] index adj, each entry holds
 // (weight << shift) | neighbour.  `ew` is scratch for the per-edge weights
 // (0 = the edge failed).
-template <typename ADJ>
-__device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint32_t *rp, ADJ *adj, uint32_t shift,
+template <typename RP, typename ADJ>
+__device__ inline void stage_realization(const SweepParams &P, uint32_t r, RP *rp, ADJ *adj, uint32_t shift,
                                          uint16_t *ew, uint32_t *scan_tmp) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int n = P.n;
@@ -73,13 +73,13 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint3
     uint32_t total;
     uint32_t pos = block_exclusive_scan(cnt, scan_tmp, total);
     for (int v = v0; v < v1; ++v) {
-        rp[v] = pos;
+        rp[v] = (RP)pos;
         for (int j = P.rp_base[v]; j < P.rp_base[v + 1]; ++j) {
             const uint32_t w = ew[P.slot_edge[j]];
             if (w) adj[pos++] = (ADJ)((w << shift) | (uint32_t)P.col[j]);
         }
     }
-    if (tid == 0) rp[n] = total;
+    if (tid == 0) rp[n] = (RP)total;
     if (tid < (int)kAdjPad) adj[total + tid] = (ADJ)0;   // padding read by unpredicated loads
     __syncthreads();
 }
@@ -89,8 +89,8 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, uint3
 // `comp`/`csize` give each vertex's component label (smallest index) and
 // size; the scratch arrays hold n entries each (LDS or global memory).
 // ---------------------------------------------------------------------------
-template <typename CT>
-__device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local, uint32_t r, const uint32_t *rp,
+template <typename RP, typename CT>
+__device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local, uint32_t r, const RP *rp,
                                    const double *B, const CT *comp, const CT *csize, const ReduceScratch &S,
                                    double *red_f, int *red_i, unsigned long long *acc_stats) {
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
@@ -116,7 +116,7 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
         const unsigned long long bb = as_u64(B[v]);
         atomicMax(&cmax[c], bb);
         if (P.pool && P.pool[v]) atomicMax(&wmax[c], bb);
-        atomicAdd(&kal[c], rp[v + 1] - rp[v]);
+        atomicAdd(&kal[c], (uint32_t)rp[v + 1] - (uint32_t)rp[v]);
         atomicAdd(&kba[c], (uint32_t)(P.rp_base[v + 1] - P.rp_base[v]));
         gm = B[v] > gm ? B[v] : gm;
     }

@@ -36,7 +36,7 @@ namespace amc {
 // neighbour in its low `shift` bits and the weight above them.
 // ---------------------------------------------------------------------------
 template <bool WEIGHTED, int G, typename ADJ>
-__device__ void wave_source(const SweepParams &P, const uint32_t *rp, const ADJ *adj, uint32_t shift, double *B,
+__device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
                             uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctr,
                             int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
     const int n = P.n;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 }
 
 template <bool WEIGHTED, int U, typename ADJ>
-__device__ void wave_source_lane(const SweepParams &P, const uint32_t *rp, const ADJ *adj, uint32_t shift,
+__device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
                                  double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux,
                                  uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
     const int n = P.n;
@@ -264,23 +264,23 @@ __device__ void wave_source_lane(const SweepParams &P, const uint32_t *rp, const
                 bool found[U];
                 // the adjacency carries kAdjPad zero entries past its end, so
                 // these loads need no predication; masked results are dropped
+                // a slot past the vertex's adjacency gets weight kNoEdge, which
+                // fails both tests below (du + kNoEdge > D, D + kNoEdge > du)
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const uint32_t a = (uint32_t)adj[beg + off + k];
                     u[k] = a & nmask;
-                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : 0u;
+                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
-#pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = w[k] ? du[k] : kInf;
                 bool pred[U], rel[U];
                 unsigned long long sg[U];
                 uint32_t old[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    pred[k] = w[k] != 0u && du[k] + w[k] == D;          // u precedes v: pull sigma_u
-                    rel[k] = w[k] != 0u && D + w[k] < du[k];            // relax the edge v -> u
+                    pred[k] = du[k] + w[k] == D;                        // u precedes v: pull sigma_u
+                    rel[k] = D + w[k] < du[k];                          // relax the edge v -> u
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
@@ -391,15 +391,13 @@ __device__ void wave_source_lane(const SweepParams &P, const uint32_t *rp, const
                 for (int k = 0; k < U; ++k) {
                     const uint32_t a = (uint32_t)adj[beg + off + k];
                     u[k] = a & nmask;
-                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : 0u;
+                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
-#pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = w[k] ? du[k] : kInf;
                 double cu[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) cu[k] = (w[k] && du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
+                for (int k = 0; k < U; ++k) cu[k] = (du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
 #pragma unroll
                 for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
             }
@@ -423,7 +421,7 @@ __host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint3
     WaveLayout L;
     const uint32_t un = (uint32_t)n;
     L.rp = 0;
-    L.adj = L.rp + 4u * (un + 1u);
+    L.adj = (L.rp + adj_bytes * (un + 1u) + 3u) & ~3u;
     L.B = (L.adj + adj_bytes * adj_cap + 7u) & ~7u;
     L.comp = L.B + 8u * un;
     L.csize = L.comp + 2u * un;
@@ -444,7 +442,7 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
     const int n = P.n;
     const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
-    uint32_t *rp = (uint32_t *)(smem + L.rp);
+    ADJ *rp = (ADJ *)(smem + L.rp);
     ADJ *adj = (ADJ *)(smem + L.adj);
     double *B = (double *)(smem + L.B);
     uint16_t *comp = (uint16_t *)(smem + L.comp);
