@@ -131,9 +131,47 @@ def run_bench(args):
                             "batched_over_plain": value / pv}
     if args.cpu_s > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_s)
+    tr = traffic_record()
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["sweep_bytes_per_launch"]
+        out["roofline"]["traffic_source"] = tr["source"]
+    if args.copy_mib > 0:
+        # calibration kernel for the HBM byte counters: a plain device copy of
+        # known size on the same stream
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = args.copy_mib << 20
     G.close()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources the sweep kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_14743_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record():
+    """HBM bytes per sweep launch from the committed counter profile, or None
+    when the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "sweep_wave_ws1000_R10000_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec
 
 
 def run_serve(args):
@@ -189,6 +227,8 @@ def main():
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
+    ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
+                    help="also run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--queries", type=int, default=64)
     ap.add_argument("--rate", type=float, default=200.0)

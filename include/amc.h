@@ -117,7 +117,9 @@ typedef struct amc_query {
     int32_t mode;               /* AMC_MODE_*                                        */
     int32_t tile;               /* sources per work item; 0 = chosen by the engine   */
     int32_t waves;              /* wavefronts per workgroup; 0 = chosen by the engine */
-    int32_t group;              /* lanes per vertex in AMC_MODE_WAVE (1, 4, 8, 16); 0 = engine */
+    int32_t group;              /* AMC_MODE_WAVE vertex mapping: 1 / 2 / 3 = one lane per vertex with
+                                   4 / 2 / 8 adjacency slots in flight; 4, 8, 16 = lanes per vertex;
+                                   0 = engine */
     const uint32_t *debug_pairs; /* AMC_WANT_DEBUG: n_debug pairs (r, s), r absolute */
     int32_t n_debug;            /* at most 64                                        */
 } amc_query;

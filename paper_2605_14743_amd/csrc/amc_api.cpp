@@ -272,7 +272,7 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
         if (q->debug_pairs[2 * k + 1] >= (uint32_t)n) return AMC_E_INVALID_ARG;
     if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_BLOCK) return AMC_E_INVALID_ARG;
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
-    if (q->group != 0 && q->group != 1 && q->group != 4 && q->group != 8 && q->group != 16) return AMC_E_INVALID_ARG;
+    if (q->group < 0 || q->group > 16 || (q->group > 4 && q->group != 8 && q->group != 16)) return AMC_E_INVALID_ARG;
     // longest possible distance must stay below the "unreached" sentinel
     const uint64_t wmax = md->weight_kind == AMC_WEIGHT_UNIT ? 1u
                           : md->weight_kind == AMC_WEIGHT_UNIFORM_INT

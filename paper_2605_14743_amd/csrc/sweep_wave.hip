@@ -491,9 +491,9 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_
         for (int s = s_lo + wave; s < s_hi; s += nwaves) {
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            if constexpr (G == 1)
-                wave_source_lane<WEIGHTED, 4, ADJ>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot,
-                                                   cs, sz, ovf);
+            if constexpr (G == 1 || G == 2 || G == 3)    // lane per vertex, unroll 4 / 2 / 8
+                wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ>(
+                    P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs, sz, ovf);
             else
                 wave_source<WEIGHTED, G, ADJ>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs,
                                               sz, ovf);
@@ -570,6 +570,8 @@ static hipError_t launch_g(const SweepParams &P, int group, uint32_t shift, int 
                            hipStream_t st) {
     switch (group) {
         case 1: return launch_t<W, 1, ADJ>(P, shift, blocks, waves, lds, st);
+        case 2: return launch_t<W, 2, ADJ>(P, shift, blocks, waves, lds, st);
+        case 3: return launch_t<W, 3, ADJ>(P, shift, blocks, waves, lds, st);
         case 4: return launch_t<W, 4, ADJ>(P, shift, blocks, waves, lds, st);
         case 16: return launch_t<W, 16, ADJ>(P, shift, blocks, waves, lds, st);
         default: return launch_t<W, 8, ADJ>(P, shift, blocks, waves, lds, st);

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol include/amc.h declares
+(no compute call: these run on hosts without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_14743_amd import amc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "amc.h")).read()
+    return sorted(set(re.findall(r"AMC_API\s+[^;(]*?\b(amc_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_list():
+    assert declared() == sorted(amc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(amc.LIB_PATH):
+        pytest.skip("libamc.so not built")
+    lib = ctypes.CDLL(amc.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", amc.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert exported == set(declared()), exported ^ set(declared())
+
+
+def test_strerror_and_version_without_gpu():
+    if not os.path.exists(amc.LIB_PATH):
+        pytest.skip("libamc.so not built")
+    L = amc.lib()
+    for rc in (amc.OK, amc.E_INVALID_ARG, amc.E_OOM, amc.E_HIP, amc.E_SIGMA_OVERFLOW, amc.E_SINGULAR,
+               amc.E_ADMISSION, amc.E_NOT_READY, amc.E_UNSUPPORTED, -99):
+        assert isinstance(L.amc_strerror(rc), bytes)
+    assert L.amc_version() >= 100
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the ABI structs have the sizes a C compiler gives."""
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "amc.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(amc_model), sizeof(amc_query), sizeof(amc_stats), sizeof(amc_result));
+  printf("%zu %zu %zu\n", offsetof(amc_query, flags), offsetof(amc_result, E_T), offsetof(amc_result, stats));
+  return 0;
+}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "s")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(x) for x in lines[0].split()]
+    offs = [int(x) for x in lines[1].split()]
+    assert sizes == [ctypes.sizeof(amc.Model), ctypes.sizeof(amc.Query), ctypes.sizeof(amc.Stats),
+                     ctypes.sizeof(amc.Result)]
+    assert offs == [amc.Query.flags.offset, amc.Result.E_T.offset, amc.Result.stats.offset]
