@@ -61,14 +61,15 @@ def run_bench(args):
     from paper_2605_14743_amd import amc
     from paper_2605_14743_amd import workloads as W
 
-    wl = W.config_ws1000()
+    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20}[args.workload]()
     g = wl.graph
     if args.R:
         wl.R = args.R
     ctx = amc.Context(0)
-    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
     q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
-             r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group)
+             r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group,
+             pool=wl.pool, reward=wl.reward)
     model = wl.model()
     for _ in range(args.warmup):
         amc.run(ctx, G, model, **q)
@@ -102,8 +103,9 @@ def run_bench(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "graph": "watts_strogatz(n=1000,k=10,beta=0.1,seed=0)", "n": g.n,
-                   "m": g.m, "realizations": wl.R, "p_fail": wl.p_fail, "weights": "uniform{1..10}",
+        "config": {"workload": wl.name, "graph": g.name, "n": g.n,
+                   "m": g.m, "realizations": wl.R, "p_fail": wl.p_fail,
+                   "weights": wl.weight if wl.weight != "uniform" else f"uniform{{{wl.w_lo}..{wl.w_hi}}}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
                    "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"], "group": st["group"],
                    "adj_bytes": st["adj_bytes"]},
@@ -131,7 +133,7 @@ def run_bench(args):
                             "batched_over_plain": value / pv}
     if args.cpu_s > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_s)
-    tr = traffic_record()
+    tr = traffic_record() if args.workload == "ws1000" and not args.R else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["sweep_bytes_per_launch"]
         out["roofline"]["traffic_source"] = tr["source"]
@@ -218,6 +220,8 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="ws1000", choices=["ws1000", "er5000", "er20"],
+                    help="ws1000 is the benchmark line; the others are for measurement notes")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--R", type=int, default=0, help="override the realization count (testing only)")

@@ -87,6 +87,7 @@ extern "C" {
 typedef struct amc_ctx amc_ctx;
 typedef struct amc_graph amc_graph;
 typedef struct amc_request amc_request;
+typedef struct amc_batch amc_batch;
 
 /* Network-state law (Section 3.1: availability set and positive weights). */
 typedef struct amc_model {
@@ -199,6 +200,21 @@ AMC_API void amc_request_destroy(amc_request *req);
 /* Serving timestamps of a finished request, seconds on a monotonic clock:
  * t[0] submit, t[1] admitted, t[2] finished. */
 AMC_API int amc_request_times(amc_request *req, double t[3]);
+
+/* Persistent fused batch (Alg. 2 for several queries at once).  The queries
+ * are grouped by kernel variant; each group is one persistent launch whose
+ * work queue holds every member's (realization, source tile) items, largest
+ * queries first.  The device sequence (counter resets, sweeps, tails) is
+ * captured once into a hipGraph; amc_batch_run replays it and fills
+ * results[0 .. count-1] exactly as count separate amc_run calls would (the
+ * per-query sweep_ms is the time of the whole replay).  Inputs are copied at
+ * creation.  AMC_PLAIN_LAUNCH is not accepted here. */
+AMC_API int amc_batch_create(amc_ctx *ctx, int32_t count, const amc_graph *const *graphs, const amc_model *models,
+                             const amc_query *queries, amc_batch **out);
+AMC_API int amc_batch_run(amc_batch *b, amc_result *results);
+/* Number of fused launches and of work items of a batch. */
+AMC_API int amc_batch_info(amc_batch *b, int32_t *n_launches, int32_t *items);
+AMC_API void amc_batch_destroy(amc_batch *b);
 
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as

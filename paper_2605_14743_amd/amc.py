@@ -24,7 +24,8 @@ WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LA
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
-           "amc_request_destroy", "amc_request_times", "amc_chain", "amc_strerror", "amc_version"]
+           "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
+           "amc_batch_destroy", "amc_chain", "amc_strerror", "amc_version"]
 
 _P = C.POINTER
 
@@ -104,6 +105,11 @@ def lib():
         L.amc_request_destroy.restype = None
         L.amc_request_times.argtypes = [vp, _P(C.c_double)]
         L.amc_chain.argtypes = [vp, C.c_int32, _P(C.c_double), _P(Query), _P(Result)]
+        L.amc_batch_create.argtypes = [vp, C.c_int32, _P(vp), _P(Model), _P(Query), _P(vp)]
+        L.amc_batch_run.argtypes = [vp, _P(Result)]
+        L.amc_batch_info.argtypes = [vp, _P(C.c_int32), _P(C.c_int32)]
+        L.amc_batch_destroy.argtypes = [vp]
+        L.amc_batch_destroy.restype = None
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -313,6 +319,55 @@ class Request:
     def close(self):
         if getattr(self, "h", None):
             lib().amc_request_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """amc_batch: several queries in persistent fused launches, replayed from one hipGraph."""
+
+    def __init__(self, ctx: Context, items):
+        """items: sequence of (Graph, model dict, query dict)."""
+        self.graphs = [g for g, _, _ in items]
+        n = len(items)
+        self._models = (Model * n)()
+        self._queries = (Query * n)()
+        self._keep = []
+        for k, (g, model, query) in enumerate(items):
+            m, km = make_model(**model)
+            q, kq = make_query(g.n, **query)
+            self._models[k] = m
+            self._queries[k] = q
+            self._keep += km + kq
+        handles = (C.c_void_p * n)(*[g.h for g in self.graphs])
+        h = C.c_void_p()
+        _check(lib().amc_batch_create(ctx.h, n, handles, self._models, self._queries, C.byref(h)), "amc_batch_create")
+        self.h = h
+
+    def run(self) -> list:
+        n = len(self.graphs)
+        res = (Result * n)()
+        arrs = []
+        for k, g in enumerate(self.graphs):
+            r, a = _alloc_result(g.n, self._queries[k])
+            res[k] = r
+            arrs.append(a)
+        _check(lib().amc_batch_run(self.h, res), "amc_batch_run")
+        return [_collect(res[k], arrs[k]) for k in range(n)]
+
+    def info(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().amc_batch_info(self.h, C.byref(a), C.byref(b)), "amc_batch_info")
+        return {"launches": a.value, "items": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().amc_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -64,13 +64,10 @@ struct SweepParams {
     // work decomposition: item = (r_local, tile), r-major
     int32_t tile;               // sources per item
     int32_t tiles_per_r;
-    uint32_t n_items;           // items in this launch
-    uint32_t item_base;         // absolute item index of local item 0
-    int32_t static_items;       // 1: item = item_base + blockIdx.x (one per block)
-    unsigned int *work_ctr;     // dynamic item counter (static_items == 0)
     // LDS carve-up (bytes), computed on the host
     uint32_t adj_cap;           // capacity of the realized adjacency in slots
     uint32_t wave_bytes;        // per-wavefront private region
+    uint32_t shift;             // neighbour bits of a realized adjacency entry
     // outputs
     uint32_t *counts, *counts_w;
     int32_t *center_global, *next_table, *next_table_w;
@@ -88,6 +85,28 @@ struct SweepParams {
     unsigned long long *dbg_sigma;
     double *dbg_delta;
 };
+
+// One sweep launch serves one or several queries: the launch's work items are
+// the concatenation of every query's (r, tile) items; item_start[q] is the
+// first item of query q (item_start[nq] = total).
+struct LaunchCtl {
+    const SweepParams *descs;   // nq query descriptors (device)
+    const uint32_t *item_start; // nq + 1 (device)
+    int32_t nq;
+    uint32_t n_items;           // items fetched by this launch
+    uint32_t item_base;         // item index of fetch 0
+    int32_t static_items;       // 1: block b takes item item_base + b; 0: work counter
+    unsigned int *work_ctr;
+    uint32_t *bscratch;         // block mode: per-workgroup global scratch
+    uint32_t bscratch_words;
+};
+
+// The query owning global item `item` (uniform scalar search).
+__device__ __forceinline__ int item_query(const LaunchCtl &L, uint32_t item) {
+    int q = 0;
+    while (q + 1 < L.nq && item >= L.item_start[q + 1]) ++q;
+    return q;
+}
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps
 // Weight given to an adjacency slot past a vertex's list: for every distance

@@ -11,14 +11,17 @@ namespace amc {
 
 // LDS-resident sweep (one wavefront per (r, s)).
 uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
-hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, uint32_t adj_bytes, uint32_t shift,
-                             int blocks, int waves, uint32_t lds, hipStream_t st);
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                             uint32_t lds, hipStream_t st);
 
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);
 size_t block_scratch_words(int n, int64_t m);
-hipError_t launch_sweep_block(const SweepParams &P, bool weighted, int blocks, int threads, uint32_t lds,
-                              uint32_t *scratch, hipStream_t st);
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
+                              hipStream_t st);
+
+hipError_t set_sweep_wave_attrs(int max_lds);
+hipError_t set_sweep_block_attrs(int max_lds);
 
 // Tail.
 hipError_t fill_u32(void *p, size_t count, uint32_t v, hipStream_t st);

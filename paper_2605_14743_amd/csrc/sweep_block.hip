@@ -236,7 +236,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
 }
 
 template <bool WEIGHTED>
-__global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32_t *scratch, size_t scratch_words) {
+__global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[2 * kMaxWaves];
     __shared__ uint32_t ctl[4];
@@ -246,48 +246,56 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32
     __shared__ int last_sh;
 
     const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
-    const int n = P.n;
-    const BlockLayout L = block_layout(n);
-    uint32_t *dist = (uint32_t *)(smem + L.dist);
-    unsigned long long *sig = (unsigned long long *)(smem + L.sig);
-    uint16_t *ord = (uint16_t *)(smem + L.ord);
-    uint16_t *aux = (uint16_t *)(smem + L.aux);
-    double *B = (double *)(smem + L.B);
-    uint16_t *comp = (uint16_t *)(smem + L.comp);
-    uint16_t *csize = (uint16_t *)(smem + L.csize);
-    // per-workgroup global scratch: realized rp (n+1), adjacency (2m plus
-    // padding), component centres and slot counts (4 n)
-    uint32_t *gs = scratch + (size_t)blockIdx.x * scratch_words;
-    uint32_t *rp = gs;
-    uint32_t *adj = rp + (n + 1);
-    ReduceScratch RS;
-    RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
-    RS.wmax = RS.cmax + n;
-    uint32_t *tail4 = adj + 2 * (size_t)P.m + kAdjPad;
-    RS.ccen = (int32_t *)tail4;
-    RS.wcen = RS.ccen + n;
-    RS.kal = (uint32_t *)(RS.wcen + n);
-    RS.kba = RS.kal + n;
-
     unsigned long long acc_stats[5] = {0, 0, 0, 0, 0};
     bool ovf = false;
+    int q_prev = -1;
     uint32_t local = 0;
     for (;;) {
-        if (P.static_items) {
+        if (LC.static_items) {
             if (local > 0) break;
             local = 1;
             item_sh = (int)blockIdx.x;
         } else {
-            if (tid == 0) item_sh = (int)atomicAdd(P.work_ctr, 1u);
+            if (tid == 0) item_sh = (int)atomicAdd(LC.work_ctr, 1u);
             __syncthreads();
         }
         const int it = item_sh;
         __syncthreads();
-        if ((uint32_t)it >= P.n_items) break;
-        const uint32_t item = P.item_base + (uint32_t)it;
-        const uint32_t r_local = item / (uint32_t)P.tiles_per_r;
-        const int t = (int)(item % (uint32_t)P.tiles_per_r);
+        if ((uint32_t)it >= LC.n_items) break;
+        const uint32_t item = LC.item_base + (uint32_t)it;
+        const int q = item_query(LC, item);
+        const SweepParams &P = LC.descs[q];
+        if (q != q_prev) {
+            if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
+            q_prev = q;
+        }
+        const uint32_t qitem = item - LC.item_start[q];
+        const uint32_t r_local = qitem / (uint32_t)P.tiles_per_r;
+        const int t = (int)(qitem % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
+
+        const int n = P.n;
+        const BlockLayout L = block_layout(n);
+        uint32_t *dist = (uint32_t *)(smem + L.dist);
+        unsigned long long *sig = (unsigned long long *)(smem + L.sig);
+        uint16_t *ord = (uint16_t *)(smem + L.ord);
+        uint16_t *aux = (uint16_t *)(smem + L.aux);
+        double *B = (double *)(smem + L.B);
+        uint16_t *comp = (uint16_t *)(smem + L.comp);
+        uint16_t *csize = (uint16_t *)(smem + L.csize);
+        // per-workgroup global scratch: realized rp (n+1), adjacency (2m plus
+        // padding), component centres and slot counts (4 n)
+        uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
+        uint32_t *rp = gs;
+        uint32_t *adj = rp + (n + 1);
+        ReduceScratch RS;
+        RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
+        RS.wmax = RS.cmax + n;
+        uint32_t *tail4 = adj + 2 * (size_t)P.m + kAdjPad;
+        RS.ccen = (int32_t *)tail4;
+        RS.wcen = RS.ccen + n;
+        RS.kal = (uint32_t *)(RS.wcen + n);
+        RS.kba = RS.kal + n;
 
         stage_realization(P, r, rp, adj, 16u, (uint16_t *)smem, scan_tmp);
         for (int v = tid; v < n; v += nthr) B[v] = 0.0;
@@ -333,12 +341,8 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(SweepParams P, uint32
             __syncthreads();
         }
     }
-    if (ovf) atomicOr(P.err, 1);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const unsigned long long v = wave_sum_u64(acc_stats[k]);
-        if (lane == 0 && v) atomicAdd(&P.stats[k], v);
-    }
+    if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
+    (void)lane;
 }
 
 uint32_t lds_bytes_block(int n, int threads) {
@@ -350,21 +354,21 @@ size_t block_scratch_words(int n, int64_t m) {
     return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 4 * (size_t)n + 64;
 }
 
-hipError_t launch_sweep_block(const SweepParams &P, bool weighted, int blocks, int threads, uint32_t lds,
-                              uint32_t *scratch, hipStream_t st) {
-    const size_t words = block_scratch_words(P.n, P.m);
-    if (weighted) {
-        auto k = sweep_block_kernel<true>;
-        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, st, P, scratch, words);
-    } else {
-        auto k = sweep_block_kernel<false>;
-        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, st, P, scratch, words);
-    }
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
+                              hipStream_t st) {
+    if (weighted)
+        hipLaunchKernelGGL(sweep_block_kernel<true>, dim3(blocks), dim3(threads), lds, st, LC);
+    else
+        hipLaunchKernelGGL(sweep_block_kernel<false>, dim3(blocks), dim3(threads), lds, st, LC);
     return hipGetLastError();
+}
+
+hipError_t set_sweep_block_attrs(int max_lds) {
+    hipError_t e = hipFuncSetAttribute((const void *)sweep_block_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)sweep_block_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               max_lds);
 }
 
 }  // namespace amc

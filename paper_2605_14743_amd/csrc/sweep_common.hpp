@@ -186,6 +186,20 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     __syncthreads();
 }
 
+// Adds a workgroup's counters to its query's totals and clears them.
+__device__ inline void flush_stats(const SweepParams &P, unsigned long long (&acc)[5], bool &ovf) {
+    const int lane = threadIdx.x & 63;
+    const bool any_ovf = __ballot(ovf) != 0ull;
+    if (any_ovf && lane == 0) atomicOr(P.err, 1);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const unsigned long long v = wave_sum_u64(acc[k]);
+        if (lane == 0 && v) atomicAdd(&P.stats[k], v);
+        acc[k] = 0;
+    }
+    ovf = false;
+}
+
 // Lookup of a (r, s) pair in the dump list; -1 when absent.
 __device__ __forceinline__ int debug_slot(const SweepParams &P, uint32_t r, int s) {
     for (int k = 0; k < P.n_dbg; ++k)

@@ -430,7 +430,7 @@ __host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint3
 }
 
 template <bool WEIGHTED, int G, typename ADJ>
-__global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_t shift) {
+__global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -440,48 +440,57 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_
     __shared__ int last_sh;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    const int n = P.n;
-    const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
-    ADJ *rp = (ADJ *)(smem + L.rp);
-    ADJ *adj = (ADJ *)(smem + L.adj);
-    double *B = (double *)(smem + L.B);
-    uint16_t *comp = (uint16_t *)(smem + L.comp);
-    uint16_t *csize = (uint16_t *)(smem + L.csize);
-    unsigned char *wbase = smem + L.waves;
-    // byte offsets from the LDS base keep every pointer in the LDS address space
-    unsigned char *wmine = wbase + wave * P.wave_bytes;
-    const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
-    uint32_t *dist = (uint32_t *)wmine;
-    unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
-    uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
-    uint16_t *aux = ord + n;
-    ReduceScratch RS;
-    RS.cmax = (unsigned long long *)wbase;
-    RS.wmax = RS.cmax + n;
-    RS.ccen = (int32_t *)(RS.wmax + n);
-    RS.wcen = RS.ccen + n;
-    RS.kal = (uint32_t *)(RS.wcen + n);
-    RS.kba = RS.kal + n;
-
     unsigned long long acc_stats[5] = {0, 0, 0, 0, 0};
     bool ovf = false;
+    int q_prev = -1;
     uint32_t local = 0;
     for (;;) {
-        if (P.static_items) {
+        if (LC.static_items) {
             if (local > 0) break;
             local = 1;
             item_sh = (int)blockIdx.x;
         } else {
-            if (tid == 0) item_sh = (int)atomicAdd(P.work_ctr, 1u);
+            if (tid == 0) item_sh = (int)atomicAdd(LC.work_ctr, 1u);
             __syncthreads();
         }
         const int it = item_sh;
         __syncthreads();
-        if ((uint32_t)it >= P.n_items) break;
-        const uint32_t item = P.item_base + (uint32_t)it;
-        const uint32_t r_local = item / (uint32_t)P.tiles_per_r;
-        const int t = (int)(item % (uint32_t)P.tiles_per_r);
+        if ((uint32_t)it >= LC.n_items) break;
+        const uint32_t item = LC.item_base + (uint32_t)it;
+        const int q = item_query(LC, item);
+        const SweepParams &P = LC.descs[q];
+        if (q != q_prev) {   // counters belong to the query that produced them
+            if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
+            q_prev = q;
+        }
+        const uint32_t qitem = item - LC.item_start[q];
+        const uint32_t r_local = qitem / (uint32_t)P.tiles_per_r;
+        const int t = (int)(qitem % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
+        const uint32_t shift = P.shift;
+
+        const int n = P.n;
+        const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+        ADJ *rp = (ADJ *)(smem + L.rp);
+        ADJ *adj = (ADJ *)(smem + L.adj);
+        double *B = (double *)(smem + L.B);
+        uint16_t *comp = (uint16_t *)(smem + L.comp);
+        uint16_t *csize = (uint16_t *)(smem + L.csize);
+        unsigned char *wbase = smem + L.waves;
+        // byte offsets from the LDS base keep every pointer in the LDS address space
+        unsigned char *wmine = wbase + wave * P.wave_bytes;
+        const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
+        uint32_t *dist = (uint32_t *)wmine;
+        unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
+        uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+        uint16_t *aux = ord + n;
+        ReduceScratch RS;
+        RS.cmax = (unsigned long long *)wbase;
+        RS.wmax = RS.cmax + n;
+        RS.ccen = (int32_t *)(RS.wmax + n);
+        RS.wcen = RS.ccen + n;
+        RS.kal = (uint32_t *)(RS.wcen + n);
+        RS.kba = RS.kal + n;
 
         stage_realization(P, r, rp, adj, shift, (uint16_t *)wbase, scan_tmp);
         for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
@@ -535,13 +544,7 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(SweepParams P, uint32_
             __syncthreads();
         }
     }
-    // flush counters
-    if (ovf) atomicOr(P.err, 1);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const unsigned long long v = wave_sum_u64(acc_stats[k]);
-        if (lane == 0 && v) atomicAdd(&P.stats[k], v);
-    }
+    if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,35 +559,52 @@ uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, 
 }
 
 template <bool W, int G, typename ADJ>
-static hipError_t launch_t(const SweepParams &P, uint32_t shift, int blocks, int waves, uint32_t lds,
-                           hipStream_t st) {
-    auto k = sweep_wave_kernel<W, G, ADJ>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * waves), lds, st, P, shift);
+static hipError_t launch_t(const LaunchCtl &LC, int blocks, int waves, uint32_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ>), dim3(blocks), dim3(64 * waves), lds, st, LC);
     return hipGetLastError();
 }
 
 template <bool W, typename ADJ>
-static hipError_t launch_g(const SweepParams &P, int group, uint32_t shift, int blocks, int waves, uint32_t lds,
-                           hipStream_t st) {
+static hipError_t attrs_g(int max_lds) {
+    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ>, (const void *)sweep_wave_kernel<W, 2, ADJ>,
+                        (const void *)sweep_wave_kernel<W, 3, ADJ>, (const void *)sweep_wave_kernel<W, 4, ADJ>,
+                        (const void *)sweep_wave_kernel<W, 8, ADJ>, (const void *)sweep_wave_kernel<W, 16, ADJ>};
+    for (const void *k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Allows every LDS-mode instantiation the device's dynamic LDS (set once per
+// context, outside any stream capture).
+hipError_t set_sweep_wave_attrs(int max_lds) {
+    hipError_t e;
+    if ((e = attrs_g<true, uint16_t>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<false, uint16_t>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<true, uint32_t>(max_lds)) != hipSuccess) return e;
+    return attrs_g<false, uint32_t>(max_lds);
+}
+
+template <bool W, typename ADJ>
+static hipError_t launch_g(const LaunchCtl &LC, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
     switch (group) {
-        case 1: return launch_t<W, 1, ADJ>(P, shift, blocks, waves, lds, st);
-        case 2: return launch_t<W, 2, ADJ>(P, shift, blocks, waves, lds, st);
-        case 3: return launch_t<W, 3, ADJ>(P, shift, blocks, waves, lds, st);
-        case 4: return launch_t<W, 4, ADJ>(P, shift, blocks, waves, lds, st);
-        case 16: return launch_t<W, 16, ADJ>(P, shift, blocks, waves, lds, st);
-        default: return launch_t<W, 8, ADJ>(P, shift, blocks, waves, lds, st);
+        case 1: return launch_t<W, 1, ADJ>(LC, blocks, waves, lds, st);
+        case 2: return launch_t<W, 2, ADJ>(LC, blocks, waves, lds, st);
+        case 3: return launch_t<W, 3, ADJ>(LC, blocks, waves, lds, st);
+        case 4: return launch_t<W, 4, ADJ>(LC, blocks, waves, lds, st);
+        case 16: return launch_t<W, 16, ADJ>(LC, blocks, waves, lds, st);
+        default: return launch_t<W, 8, ADJ>(LC, blocks, waves, lds, st);
     }
 }
 
-hipError_t launch_sweep_wave(const SweepParams &P, bool weighted, int group, uint32_t adj_bytes, uint32_t shift,
-                             int blocks, int waves, uint32_t lds, hipStream_t st) {
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                             uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_g<true, uint16_t>(P, group, shift, blocks, waves, lds, st)
-                        : launch_g<false, uint16_t>(P, group, shift, blocks, waves, lds, st);
-    return weighted ? launch_g<true, uint32_t>(P, group, shift, blocks, waves, lds, st)
-                    : launch_g<false, uint32_t>(P, group, shift, blocks, waves, lds, st);
+        return weighted ? launch_g<true, uint16_t>(LC, group, blocks, waves, lds, st)
+                        : launch_g<false, uint16_t>(LC, group, blocks, waves, lds, st);
+    return weighted ? launch_g<true, uint32_t>(LC, group, blocks, waves, lds, st)
+                    : launch_g<false, uint32_t>(LC, group, blocks, waves, lds, st);
 }
 
 }  // namespace amc

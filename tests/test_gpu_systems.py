@@ -1,0 +1,115 @@
+"""GPU systems checks: the persistent fused batch (hipGraph replays) and the
+serving loop give, for every query, exactly what a standalone amc_run gives."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2605_14743_amd import amc
+from paper_2605_14743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = amc.Context(0)
+    yield c
+    c.close()
+
+
+def mixed_items(ctx, count, R, seed=0):
+    wls = W.config_mixed_batch(count=count, R=R, seed=seed)
+    # keep the graphs small enough for a quick test, mixing both sweep modes
+    out = []
+    for k, wl in enumerate(wls):
+        g = wl.graph
+        if g.n > 1400 and k % 3:
+            g = W.er_graph(300 + 37 * k, 6.0 / (300 + 37 * k), 900 + k)
+            wl.graph = g
+        if k == 2:                                   # too large for the LDS mode: workgroup per source
+            g = W.er_graph(3500, 10.0 / 3499, 77)
+            wl.graph = g
+            wl.R = 8
+        G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
+        q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, eps=wl.eps, r_lower=wl.r_lower,
+                 cert_topk=3, flags=FLAGS)
+        if k == 3:
+            q["pool"] = np.arange(0, g.n, 7, dtype=np.int32)
+        out.append((G, wl.model(), q))
+    return out
+
+
+def same(a, b, what):
+    for key in ("counts", "next_table", "center_global", "counts_w"):
+        if key in a:
+            assert np.array_equal(a[key], b[key]), f"{what}: {key}"
+    assert np.allclose(a["bsum"], b["bsum"], rtol=1e-12, atol=0), f"{what}: bsum"
+    for key in ("b", "mu", "Q"):
+        assert np.allclose(a[key], b[key], rtol=0, atol=1e-13 * max(1.0, np.abs(b[key]).max())), f"{what}: {key}"
+    for key in ("units", "sum_nK", "sum_AK", "sum_DK"):
+        assert a["stats"][key] == b["stats"][key], f"{what}: {key}"
+
+
+def test_batch_matches_standalone_runs_over_replays(ctx):
+    items = mixed_items(ctx, 12, 96)
+    say(f"[gpu] batch of {len(items)} graphs, n = {[G.n for G, _, _ in items]}")
+    ref = [amc.run(ctx, G, model, **q) for G, model, q in items]
+    modes = {r["stats"]["mode"] for r in ref}
+    assert modes == {amc.MODE_WAVE, amc.MODE_BLOCK}
+    B = amc.Batch(ctx, items)
+    info = B.info()
+    assert info["launches"] >= 2
+    for rep in range(3):                                  # replays, with eager work between them
+        got = B.run()
+        for k, (a, b) in enumerate(zip(got, ref)):
+            same(a, b, f"replay {rep} query {k}")
+        amc.run(ctx, items[0][0], items[0][1], **items[0][2])
+    B.close()
+    for G, _, _ in items:
+        G.close()
+
+
+def test_serving_results_equal_standalone(ctx):
+    items = mixed_items(ctx, 10, 64, seed=3)
+    ref = [amc.run(ctx, G, model, **q) for G, model, q in items]
+    say("[gpu] serving mix")
+    reqs = [amc.Request(ctx, G, model, **q) for G, model, q in items]
+    got = [r.wait() for r in reqs]
+    for k, (a, b) in enumerate(zip(got, ref)):
+        same(a, b, f"served query {k}")
+    times = [r.times() for r in reqs]
+    assert all(t[0] <= t[1] <= t[2] for t in times)
+    for r in reqs:
+        r.close()
+    for G, _, _ in items:
+        G.close()
+
+
+def test_serving_admission_by_footprint():
+    small = amc.Context(0, budget_bytes=64 << 20)     # 64 MiB budget
+    g = W.er_graph(3000, 8.0 / 2999, 4)
+    G = amc.Graph(small, g.n, g.eu, g.ev)
+    with pytest.raises(amc.AmcError) as ei:           # n^2 tail matrices alone exceed the budget
+        amc.Request(small, G, {"p_fail": 0.1}, R=8)
+    assert ei.value.rc == amc.E_ADMISSION
+    h = W.er_graph(200, 0.03, 5)
+    H = amc.Graph(small, h.n, h.eu, h.ev)
+    fp = amc.footprint(H, R=64)
+    assert fp < (64 << 20)
+    reqs = [amc.Request(small, H, {"p_fail": 0.1}, R=64, seed=s) for s in range(6)]
+    outs = [r.wait() for r in reqs]
+    assert all(o["counts"].sum() == 64 * 200 for o in outs)
+    for r in reqs:
+        r.close()
+    G.close()
+    H.close()
+    small.close()
