@@ -176,6 +176,61 @@ def traffic_record():
     return rec
 
 
+def run_batch(args):
+    """Uneven-size batch (64 graphs by default) in persistent fused launches
+    replayed from one hipGraph; value = realization-sources/s of a replay."""
+    import torch
+
+    from paper_2605_14743_amd import amc
+    from paper_2605_14743_amd import workloads as W
+
+    wls = W.config_mixed_batch(count=args.batch_count, R=args.R or 2048, seed=0)
+    ctx = amc.Context(0)
+    graphs = [amc.Graph(ctx, wl.graph.n, wl.graph.eu, wl.graph.ev, wl.graph.w0) for wl in wls]
+    items = [(G, wl.model(), dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, eps=wl.eps,
+                                  r_lower=wl.r_lower, cert_topk=5)) for G, wl in zip(graphs, wls)]
+    tuned = 0
+    if args.tune:
+        t0 = time.perf_counter()
+        for G, model, q in items:
+            amc.tune(ctx, G, model, probe_R=8, **{k: v for k, v in q.items() if k != "R"}, R=8)
+            tuned += 1
+        print(f"# tuned {tuned} graphs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    B = amc.Batch(ctx, items)
+    t_build = time.perf_counter() - t0
+    print(f"# batch built in {t_build:.1f} s: {B.info()}", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        t1 = time.perf_counter()
+        B.run()
+        print(f"# warm-up replay {k}: {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        res = B.run()
+        print(f"# replay {k}: {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / args.steps
+    units = sum(wl.R * wl.graph.n for wl in wls)
+    st = [r["stats"] for r in res]
+    ab = sum(algorithmic_bytes(x) for x in st)
+    graph_ms = st[0]["sweep_ms"]
+    out = {"metric": "realization-sources/sec", "value": units / dt, "unit": "realization-sources/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"mixed-batch-{len(wls)}", "graphs": len(wls),
+                      "n_range": [min(w.graph.n for w in wls), max(w.graph.n for w in wls)],
+                      "realizations_each": wls[0].R, "units": units, "tuned": tuned, **B.info()},
+           "graph_replay_ms": graph_ms, "build_s": t_build,
+           "teps": sum(x["sum_AK"] for x in st) / 2 / (graph_ms * 1e-3),
+           "algorithmic_GBps": ab / (graph_ms * 1e-3) / 1e9}
+    B.close()
+    for G in graphs:
+        G.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args):
     """Poisson trace of mixed-size queries through amc_submit (continuous
     batching); reports throughput and p50/p99 latency."""
@@ -234,6 +289,9 @@ def main():
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="run the mixed-size batch instead")
+    ap.add_argument("--batch-count", dest="batch_count", type=int, default=64)
+    ap.add_argument("--tune", action="store_true", help="autotune every graph before building the batch")
     ap.add_argument("--queries", type=int, default=64)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--n-hi", dest="n_hi", type=int, default=4000)
@@ -248,6 +306,8 @@ def main():
         sys.exit(2)
     if args.serve:
         run_serve(args)
+    elif args.batch:
+        run_batch(args)
     else:
         run_bench(args)
 

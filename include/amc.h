@@ -216,6 +216,21 @@ AMC_API int amc_batch_run(amc_batch *b, amc_result *results);
 AMC_API int amc_batch_info(amc_batch *b, int32_t *n_launches, int32_t *items);
 AMC_API void amc_batch_destroy(amc_batch *b);
 
+/* Autotuner: times the feasible sweep configurations (LDS mode with each
+ * vertex mapping, workgroup-per-source mode) on probe_R realizations of this
+ * graph and query, and records the fastest for the graph's shape (n, m,
+ * weight law, largest weight) in the context.  Later calls with mode, group
+ * and waves left at 0 use it.  With the environment variable AMC_TUNE_CACHE
+ * naming a file, choices are loaded from it at context creation and appended
+ * to it here. */
+typedef struct amc_tune_result {
+    int32_t mode, group, waves;     /* chosen configuration                     */
+    double units_per_s;             /* its probe rate, realization-sources / s  */
+    int32_t candidates;             /* configurations timed                     */
+} amc_tune_result;
+AMC_API int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, uint32_t probe_R,
+                     amc_tune_result *out);
+
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
  * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,

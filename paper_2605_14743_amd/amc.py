@@ -25,7 +25,7 @@ WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LA
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
-           "amc_batch_destroy", "amc_chain", "amc_strerror", "amc_version"]
+           "amc_batch_destroy", "amc_tune", "amc_chain", "amc_strerror", "amc_version"]
 
 _P = C.POINTER
 
@@ -49,6 +49,11 @@ class Query(C.Structure):
                 ("r_lower", C.c_double), ("cert_topk", C.c_int32), ("flags", C.c_uint32), ("mode", C.c_int32),
                 ("tile", C.c_int32), ("waves", C.c_int32), ("group", C.c_int32), ("debug_pairs", _P(C.c_uint32)),
                 ("n_debug", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("group", C.c_int32), ("waves", C.c_int32), ("units_per_s", C.c_double),
+                ("candidates", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -110,6 +115,7 @@ def lib():
         L.amc_batch_info.argtypes = [vp, _P(C.c_int32), _P(C.c_int32)]
         L.amc_batch_destroy.argtypes = [vp]
         L.amc_batch_destroy.restype = None
+        L.amc_tune.argtypes = [vp, vp, _P(Model), _P(Query), C.c_uint32, _P(TuneResult)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -387,6 +393,16 @@ def chain(ctx: Context, Q, **query) -> dict:
     out = _collect(res, arr)
     del keep
     return out
+
+
+def tune(ctx: Context, graph: Graph, model: dict, probe_R: int = 16, **query) -> dict:
+    """amc_tune: times the feasible sweep configurations and records the fastest."""
+    m, keep_m = make_model(**model)
+    q, keep_q = make_query(graph.n, **query)
+    out = TuneResult()
+    _check(lib().amc_tune(ctx.h, graph.h, C.byref(m), C.byref(q), int(probe_R), C.byref(out)), "amc_tune")
+    del keep_m, keep_q
+    return {f: getattr(out, f) for f, _ in TuneResult._fields_}
 
 
 def footprint(graph: Graph, **query) -> int:

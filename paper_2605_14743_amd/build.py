@@ -19,7 +19,8 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libamc.so")
 ARCH = "gfx950"
 
-SOURCES = ["amc_api.cpp", "query.cpp", "batch.cpp", "server.cpp", "sweep_wave.hip", "sweep_block.hip", "tail.hip"]
+SOURCES = ["amc_api.cpp", "query.cpp", "batch.cpp", "server.cpp", "tune.cpp", "sweep_wave.hip", "sweep_block.hip",
+           "tail.hip"]
 
 
 def hipcc() -> str:

@@ -104,6 +104,7 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
         return AMC_E_HIP;
     }
     c->stream = c->own;
+    tune_load(c);
     *out = c;
     return AMC_OK;
 }
@@ -296,13 +297,28 @@ uint64_t prob_threshold(double p) {
 // Launch configuration.  The LDS mode needs the realized adjacency, B and
 // at least two wavefront states in one workgroup; otherwise the workgroup-
 // per-source mode is used.
-int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, Plan *pl) {
+int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q_in, Plan *pl) {
     const int n = g->n;
+    // a tuned choice for this graph shape fills the fields the caller left open
+    amc_query qt = *q_in;
+    const amc_query *q = &qt;
+    if (qt.mode == AMC_MODE_AUTO && qt.group == 0 && qt.waves == 0) {
+        amc_ctx *mc = const_cast<amc_ctx *>(ctx);
+        std::lock_guard<std::mutex> lk(mc->tune_mu);
+        auto it = mc->tune.find(tune_key(g, md));
+        if (it != mc->tune.end()) {
+            qt.mode = it->second.mode;
+            qt.group = it->second.group;
+            qt.waves = it->second.waves;
+        }
+    }
     const uint32_t adj_cap = (uint32_t)(2 * g->m) + kAdjPad;
     pl->weighted = md->weight_kind != AMC_WEIGHT_UNIT;
     const double avg_deg = n > 0 ? 2.0 * (double)g->m / n : 0.0;
+    // default mapping (measured on MI355X): several lanes per vertex pay off
+    // only for small graphs, where many sources share the LDS
     (void)avg_deg;
-    pl->group = q->group > 0 ? q->group : 1;
+    pl->group = q->group > 0 ? q->group : (n <= 400 ? 8 : 1);
     // adjacency entry: neighbour in the low bits, weight above; 16 bits when both fit
     uint32_t nbits = 1;
     while ((1u << nbits) < (uint32_t)n) ++nbits;

@@ -5,6 +5,9 @@
 
 #include <condition_variable>
 #include <deque>
+#include <map>
+#include <string>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -37,6 +40,13 @@ struct Plan {
 
 struct Server;
 
+// Shape key of the autotuner cache: n, m, weight law, largest weight.
+using TuneKey = std::tuple<int32_t, int64_t, int32_t, uint32_t>;
+struct TuneChoice {
+    int32_t mode, group, waves;
+    double units_per_s;
+};
+
 }  // namespace amc
 
 struct amc_ctx {
@@ -50,6 +60,9 @@ struct amc_ctx {
     std::mutex mu;                   // serialises amc_run / amc_chain on the context stream
     std::mutex server_mu;
     amc::Server *server = nullptr;
+    std::mutex tune_mu;
+    std::map<amc::TuneKey, amc::TuneChoice> tune;
+    std::string tune_path;
 };
 
 struct amc_graph {
@@ -72,6 +85,8 @@ namespace amc {
 int validate(const amc_graph *g, const amc_model *md, const amc_query *q);
 int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, Plan *pl);
 uint64_t prob_threshold(double p);
+TuneKey tune_key(const amc_graph *g, const amc_model *md);
+void tune_load(amc_ctx *ctx);
 int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, amc_result *out,
               hipStream_t st);
 void server_stop(amc_ctx *ctx);

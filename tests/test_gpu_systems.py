@@ -113,3 +113,31 @@ def test_serving_admission_by_footprint():
     G.close()
     H.close()
     small.close()
+
+
+def test_autotuner_choice_is_used_and_exact(ctx, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("AMC_TUNE_CACHE", str(cache))
+    c2 = amc.Context(0)                      # reads (empty) cache at creation
+    g = W.ws_graph(600, 8, 0.1, 11)
+    G = amc.Graph(c2, g.n, g.eu, g.ev)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    say("[gpu] autotune ws600")
+    t = amc.tune(c2, G, model, probe_R=24, R=24, seed=3)
+    assert t["candidates"] >= 2 and t["units_per_s"] > 0
+    res = amc.run(c2, G, model, R=40, seed=3, flags=FLAGS | amc.SKIP_TAIL)
+    assert res["stats"]["mode"] == t["mode"]
+    if t["mode"] == amc.MODE_WAVE:
+        assert res["stats"]["group"] == t["group"]
+    ref = amc.run(c2, G, model, R=40, seed=3, flags=FLAGS | amc.SKIP_TAIL, mode=amc.MODE_BLOCK)
+    assert np.array_equal(res["counts"], ref["counts"]) and np.array_equal(res["next_table"], ref["next_table"])
+    line = cache.read_text().split()
+    assert [int(x) for x in line[:3]] == [g.n, g.m, 1]
+    G.close()
+    c2.close()
+    c3 = amc.Context(0)                      # a new context picks the stored choice up
+    H = amc.Graph(c3, g.n, g.eu, g.ev)
+    res3 = amc.run(c3, H, model, R=8, seed=3, flags=amc.SKIP_TAIL)
+    assert res3["stats"]["mode"] == t["mode"]
+    H.close()
+    c3.close()
