@@ -74,6 +74,8 @@ extern "C" {
 #define AMC_MODE_AUTO 0           /* pick from the shape (autotuner)           */
 #define AMC_MODE_WAVE 1           /* graph staged in LDS, one wavefront per (r, s) */
 #define AMC_MODE_BLOCK 2          /* one workgroup per (r, s), frontier queues */
+#define AMC_MODE_WAVE_L2 3        /* one wavefront per (r, s); realized graph and B in an
+                                     L2-resident per-workgroup scratch, LDS for per-source state */
 
 /* ----------------------------------------------------------- query flags */
 #define AMC_WANT_N (1u << 0)          /* copy the fundamental matrix N           */
@@ -118,7 +120,7 @@ typedef struct amc_query {
     int32_t mode;               /* AMC_MODE_*                                        */
     int32_t tile;               /* sources per work item; 0 = chosen by the engine   */
     int32_t waves;              /* wavefronts per workgroup; 0 = chosen by the engine */
-    int32_t group;              /* AMC_MODE_WAVE vertex mapping: 1 / 2 / 3 = one lane per vertex with
+    int32_t group;              /* AMC_MODE_WAVE / _WAVE_L2 vertex mapping: 1 / 2 / 3 = one lane per vertex with
                                    4 / 2 / 8 adjacency slots in flight; 4, 8, 16 = lanes per vertex;
                                    0 = engine */
     const uint32_t *debug_pairs; /* AMC_WANT_DEBUG: n_debug pairs (r, s), r absolute */

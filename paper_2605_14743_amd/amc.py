@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libamc.so")
 OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NOT_READY, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED = 0, 1, 2
-MODE_AUTO, MODE_WAVE, MODE_BLOCK = 0, 1, 2
+MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH = \
     1, 2, 4, 8, 16, 32, 64
 

@@ -276,7 +276,7 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     if (q->n_debug < 0 || q->n_debug > 64 || (q->n_debug > 0 && !q->debug_pairs)) return AMC_E_INVALID_ARG;
     for (int k = 0; k < q->n_debug; ++k)
         if (q->debug_pairs[2 * k + 1] >= (uint32_t)n) return AMC_E_INVALID_ARG;
-    if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_BLOCK) return AMC_E_INVALID_ARG;
+    if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_WAVE_L2) return AMC_E_INVALID_ARG;
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
     if (q->group < 0 || q->group > 16 || (q->group > 4 && q->group != 8 && q->group != 16)) return AMC_E_INVALID_ARG;
     // longest possible distance must stay below the "unreached" sentinel
@@ -335,7 +335,10 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     }
     int best_w = 0;
     uint32_t best_lds = 0, best_wb = 0;
-    const int want_w = q->waves > 0 ? q->waves : kMaxWaves;
+    // the 8-slot lane mapping is built for at most 8 wavefronts per workgroup
+    const int max_w = pl->group == 3 ? 8 : kMaxWaves;
+    if (q->waves > max_w && q->mode != AMC_MODE_BLOCK) return AMC_E_UNSUPPORTED;
+    const int want_w = q->waves > 0 ? q->waves : max_w;
     for (int w = 2; w <= want_w; ++w) {
         uint32_t wb = 0;
         const uint32_t lds = lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, &wb);
@@ -346,16 +349,47 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         best_wb = wb;
     }
     const bool wave_ok = best_w >= 2 && (q->waves == 0 || best_w == q->waves);
+    // L2 mode: the whole LDS goes to the wavefronts' private regions
+    int l2_w = 0;
+    uint32_t l2_lds = 0, l2_wb = 0;
+    for (int w = 2; w <= want_w; ++w) {
+        uint32_t wb = 0;
+        const uint32_t lds = lds_bytes_wave_l2(n, w, &wb);
+        if (lds > (uint32_t)ctx->max_lds) break;
+        if ((uint64_t)wb * w < std::max<uint64_t>(2ull * (uint64_t)g->m, 32ull * (uint64_t)n)) continue;
+        l2_w = w;
+        l2_lds = lds;
+        l2_wb = wb;
+    }
+    const bool l2_ok = l2_w >= 2 && (q->waves == 0 || l2_w == q->waves);
     int mode = q->mode;
-    if (mode == AMC_MODE_AUTO) mode = wave_ok ? AMC_MODE_WAVE : AMC_MODE_BLOCK;
+    if (mode == AMC_MODE_AUTO) {
+        // measured on MI355X (degree 8): L2 mode wins once the realized graph
+        // leaves room for fewer than 4 wavefronts in LDS mode; with only two
+        // wavefronts left even there, the workgroup-per-source mode is as fast
+        // for weighted graphs beyond n = 4000 and faster for unit weights
+        const bool l2_good = l2_ok && (l2_w >= 3 || (pl->weighted && n <= 4000));
+        if (wave_ok && (best_w >= 4 || !l2_good || l2_w <= best_w)) mode = AMC_MODE_WAVE;
+        else if (l2_good) mode = AMC_MODE_WAVE_L2;
+        else mode = AMC_MODE_BLOCK;
+    }
     if (mode == AMC_MODE_WAVE && !wave_ok) return AMC_E_UNSUPPORTED;
+    if (mode == AMC_MODE_WAVE_L2 && !l2_ok) return AMC_E_UNSUPPORTED;
     pl->mode = mode;
+    pl->scratch_words = 0;
     if (mode == AMC_MODE_WAVE) {
         pl->waves = best_w;
         pl->lds = best_lds;
         pl->wave_bytes = best_wb;
         pl->threads = 64 * best_w;
         pl->adj_cap = adj_cap;
+    } else if (mode == AMC_MODE_WAVE_L2) {
+        pl->waves = l2_w;
+        pl->lds = l2_lds;
+        pl->wave_bytes = l2_wb;
+        pl->threads = 64 * l2_w;
+        pl->adj_cap = adj_cap;
+        pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
     } else {
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
         pl->lds = lds_bytes_block(n, pl->threads);
@@ -364,13 +398,15 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;
+        pl->scratch_words = (uint32_t)block_scratch_words(n, g->m);
     }
     // sources per work item: whole realizations when there are enough of
     // them to fill the device, otherwise split the sources
-    const uint32_t blocks_per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl->lds, 1u));
+    uint32_t blocks_per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl->lds, 1u));
+    if (mode != AMC_MODE_WAVE) blocks_per_cu = std::min(blocks_per_cu, kMaxScratchBlocksPerCu);
     const uint64_t slots = (uint64_t)ctx->cu_count * blocks_per_cu;
     int tile = q->tile;
-    if (q->flags & AMC_PLAIN_LAUNCH) tile = mode == AMC_MODE_WAVE ? pl->waves : 1;
+    if (q->flags & AMC_PLAIN_LAUNCH) tile = mode == AMC_MODE_BLOCK ? 1 : pl->waves;
     if (tile <= 0) {
         if ((uint64_t)q->R >= 2 * slots) {
             tile = n;
@@ -378,7 +414,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
             const uint64_t want_items = 2 * slots;
             const uint64_t per_r = std::min<uint64_t>((uint64_t)n, (want_items + q->R - 1) / q->R);
             tile = (int)((n + per_r - 1) / per_r);
-            if (mode == AMC_MODE_WAVE) tile = std::max(tile, pl->waves);
+            if (mode != AMC_MODE_BLOCK) tile = std::max(tile, pl->waves);
         }
     }
     tile = std::min(tile, n);
@@ -406,7 +442,10 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     // partial-B exchange when realizations are split (upper bound)
     b += (8 + 4 + 4) * R * n + 4 * R;
     if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + 3 * 8 * 16 * n;
-    b += 4 * (uint64_t)g->ctx->cu_count * (n + 1 + 2 * (uint64_t)g->m + 4 * n + 96);   // block-mode scratch
+    // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
+    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m),
+                                           l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u));
+    b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;
     *bytes = b;
     return AMC_OK;

@@ -97,7 +97,7 @@ struct LaunchCtl {
     uint32_t item_base;         // item index of fetch 0
     int32_t static_items;       // 1: block b takes item item_base + b; 0: work counter
     unsigned int *work_ctr;
-    uint32_t *bscratch;         // block mode: per-workgroup global scratch
+    uint32_t *bscratch;         // workgroup-per-source and L2 modes: per-workgroup global scratch
     uint32_t bscratch_words;
 };
 
@@ -244,5 +244,40 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred) {
 
 __device__ __forceinline__ double as_f64(unsigned long long b) { return __longlong_as_double((long long)b); }
 __device__ __forceinline__ unsigned long long as_u64(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+// A pointer the compiler treats as global memory (addrspace 1), so loads and
+// stores through it are global_* rather than flat instructions (flat accesses
+// also count against the LDS wait counter and serialise with LDS traffic).
+template <typename T>
+__device__ __forceinline__ T *to_global(T *p) {
+    return (T *)((__attribute__((address_space(1))) T *)p);
+}
+
+// Adds into a double in global memory with a global (not flat) atomic: a flat
+// atomic would also hold the LDS wait counter of the issuing wavefront.
+__device__ __forceinline__ void global_add_f64(double *p, double v) {
+    (void)__builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double *)p, v);
+}
+
+// Plain store through a global (not flat) pointer.
+template <typename T>
+__device__ __forceinline__ void st_global(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
+// B(H_r)[v] += delta: an LDS atomic (LDS mode) or a global one (L2 mode).
+template <bool GB>
+__device__ __forceinline__ void add_B(double *B, int v, double delta) {
+    if constexpr (GB) global_add_f64(&B[v], delta);
+    else unsafeAtomicAdd(&B[v], delta);
+}
+
+// Load that bypasses the CU's vector L1 when COH: values produced by device
+// atomics (performed at L2) or by other workgroups.
+template <bool COH, typename T>
+__device__ __forceinline__ T ld_coh(const T *p) {
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
 
 }  // namespace amc

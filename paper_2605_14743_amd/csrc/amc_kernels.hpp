@@ -9,10 +9,13 @@
 
 namespace amc {
 
-// LDS-resident sweep (one wavefront per (r, s)).
+// One wavefront per (r, s): LDS mode (realized graph in LDS) and L2 mode
+// (realized graph, B and labels in a per-workgroup global scratch).
 uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                             uint32_t lds, hipStream_t st);
+uint32_t lds_bytes_wave_l2(int n, int waves, uint32_t *wave_bytes);
+size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes);
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, int group, uint32_t adj_bytes, int blocks,
+                             int waves, uint32_t lds, hipStream_t st);
 
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);

@@ -25,6 +25,9 @@ struct DevArena {
     void release();
 };
 
+// Workgroups per CU of the modes that give every workgroup a global scratch.
+constexpr uint32_t kMaxScratchBlocksPerCu = 4;
+
 struct Plan {
     int mode = 0;
     bool weighted = false;
@@ -36,6 +39,7 @@ struct Plan {
     int tile = 0, tiles_per_r = 1;
     uint64_t items = 0;
     int blocks = 0;
+    uint32_t scratch_words = 0;     // per-workgroup global scratch (block and L2 modes)
 };
 
 struct Server;

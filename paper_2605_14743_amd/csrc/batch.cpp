@@ -121,8 +121,17 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
     std::vector<Key> keys;
     for (int i = 0; i < count; ++i) {
         const Plan &pl = b->runs[i]->pl;
-        Key k{pl.mode, pl.weighted ? 1 : 0, pl.mode == AMC_MODE_WAVE ? pl.group : 0, (int)pl.adj_bytes,
-              pl.mode == AMC_MODE_WAVE ? wave_bucket(pl.waves) : pl.threads / 64};
+        const bool per_wave = pl.mode != AMC_MODE_BLOCK;
+        // a member may run with fewer wavefronts than planned as long as the
+        // wavefront regions still hold the staging and reduction scratch
+        int w = pl.threads / 64;
+        if (per_wave) {
+            w = wave_bucket(pl.waves);
+            const uint64_t need = std::max<uint64_t>(2ull * (uint64_t)b->runs[i]->g->m,
+                                                     32ull * (uint64_t)b->runs[i]->g->n);
+            if ((uint64_t)pl.wave_bytes * (uint64_t)w < need) w = pl.waves;
+        }
+        Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w};
         size_t gi = 0;
         while (gi < keys.size() && !(keys[gi] == k)) ++gi;
         if (gi == keys.size()) {
@@ -148,16 +157,15 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         });
         for (int i : G.members) {
             QueryRun &R = *b->runs[i];
-            if (G.pl.mode == AMC_MODE_WAVE) {
+            if (G.pl.mode == AMC_MODE_WAVE || G.pl.mode == AMC_MODE_WAVE_L2) {
                 R.pl.waves = G.pl.waves;
                 R.pl.threads = G.pl.threads;
-                R.pl.lds = lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, &R.pl.wave_bytes);
-                G.pl.lds = std::max(G.pl.lds, R.pl.lds);
-            } else {
-                G.pl.lds = std::max(G.pl.lds, R.pl.lds);
-                G.bscratch_words = std::max<uint32_t>(G.bscratch_words,
-                                                      (uint32_t)block_scratch_words(R.g->n, R.g->m));
+                R.pl.lds = G.pl.mode == AMC_MODE_WAVE
+                               ? lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, &R.pl.wave_bytes)
+                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, &R.pl.wave_bytes);
             }
+            G.pl.lds = std::max(G.pl.lds, R.pl.lds);
+            G.bscratch_words = std::max<uint32_t>(G.bscratch_words, R.pl.scratch_words);
             R.pl.blocks = 0;   // the group launch owns the workgroups
             RCHK(qr_alloc(R, s0));
             cost_total += R.pl.items;
@@ -180,8 +188,9 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         RCHK(b->A.alloc(16, &p));
         G.work_ctr = (unsigned int *)p;
         const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(G.pl.lds, 1u));
-        G.blocks = (int)std::min<uint64_t>(G.items, (uint64_t)ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
-        if (G.pl.mode == AMC_MODE_BLOCK) {
+        const uint32_t cap = G.bscratch_words > 0 ? kMaxScratchBlocksPerCu : 8u;
+        G.blocks = (int)std::min<uint64_t>(G.items, (uint64_t)ctx->cu_count * std::min<uint32_t>(per_cu, cap));
+        if (G.bscratch_words > 0) {
             RCHK(b->A.alloc(4 * (size_t)G.bscratch_words * G.blocks, &p));
             G.bscratch = (uint32_t *)p;
         }
@@ -216,10 +225,10 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         LC.work_ctr = G.work_ctr;
         LC.bscratch = G.bscratch;
         LC.bscratch_words = G.bscratch_words;
-        hipError_t e = G.pl.mode == AMC_MODE_WAVE
-                           ? launch_sweep_wave(LC, G.pl.weighted, G.pl.group, G.pl.adj_bytes, G.blocks, G.pl.waves,
-                                               G.pl.lds, st)
-                           : launch_sweep_block(LC, G.pl.weighted, G.blocks, G.pl.threads, G.pl.lds, st);
+        hipError_t e = G.pl.mode == AMC_MODE_BLOCK
+                           ? launch_sweep_block(LC, G.pl.weighted, G.blocks, G.pl.threads, G.pl.lds, st)
+                           : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.group,
+                                               G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);
         if (e != hipSuccess) {
             rc = AMC_E_HIP;
             break;

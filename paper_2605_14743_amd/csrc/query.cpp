@@ -156,9 +156,9 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
         RCHK(A.alloc(8 * (size_t)q->n_debug * n, &p)); P.dbg_sigma = (unsigned long long *)p;
         RCHK(A.alloc(8 * (size_t)q->n_debug * n, &p)); P.dbg_delta = (double *)p;
     }
-    if (R.pl.mode == AMC_MODE_BLOCK) {
+    if (R.pl.scratch_words > 0) {
         const int nb = (q->flags & AMC_PLAIN_LAUNCH) ? R.pl.tiles_per_r : R.pl.blocks;
-        R.bscratch_words = (uint32_t)block_scratch_words(n, g->m);
+        R.bscratch_words = R.pl.scratch_words;
         RCHK(A.alloc(4 * (size_t)R.bscratch_words * nb, &p));
         R.bscratch = (uint32_t *)p;
     }
@@ -243,8 +243,9 @@ int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
 }
 
 static hipError_t launch_plan(const Plan &pl, const LaunchCtl &LC, int blocks, hipStream_t st) {
-    if (pl.mode == AMC_MODE_WAVE)
-        return launch_sweep_wave(LC, pl.weighted, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st);
+    if (pl.mode == AMC_MODE_WAVE || pl.mode == AMC_MODE_WAVE_L2)
+        return launch_sweep_wave(LC, pl.weighted, pl.mode == AMC_MODE_WAVE_L2, pl.group, pl.adj_bytes, blocks,
+                                 pl.waves, pl.lds, st);
     return launch_sweep_block(LC, pl.weighted, blocks, pl.threads, pl.lds, st);
 }
 

@@ -87,9 +87,11 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, RP *r
 // ---------------------------------------------------------------------------
 // Reduction of one realization (all sources done): centres, coins, counts.
 // `comp`/`csize` give each vertex's component label (smallest index) and
-// size; the scratch arrays hold n entries each (LDS or global memory).
+// size; the scratch arrays hold n entries each (LDS or global memory).  With
+// COH, B, comp and csize are global arrays written by device atomics or by
+// other workgroups and are read past the vector L1.
 // ---------------------------------------------------------------------------
-template <typename RP, typename CT>
+template <typename RP, typename CT, bool COH = false>
 __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local, uint32_t r, const RP *rp,
                                    const double *B, const CT *comp, const CT *csize, const ReduceScratch &S,
                                    double *red_f, int *red_i, unsigned long long *acc_stats) {
@@ -112,13 +114,14 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     __syncthreads();
     double gm = 0.0;
     for (int v = tid; v < n; v += nthr) {
-        const int c = comp[v];
-        const unsigned long long bb = as_u64(B[v]);
+        const int c = (int)ld_coh<COH>(&comp[v]);
+        const double bv = ld_coh<COH>(&B[v]);
+        const unsigned long long bb = as_u64(bv);
         atomicMax(&cmax[c], bb);
         if (P.pool && P.pool[v]) atomicMax(&wmax[c], bb);
         atomicAdd(&kal[c], (uint32_t)rp[v + 1] - (uint32_t)rp[v]);
         atomicAdd(&kba[c], (uint32_t)(P.rp_base[v + 1] - P.rp_base[v]));
-        gm = B[v] > gm ? B[v] : gm;
+        gm = bv > gm ? bv : gm;
     }
     gm = wave_max_f64(gm);
     if (lane == 0) red_f[wave] = gm;
@@ -129,8 +132,8 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     int gbest = 0x7FFFFFFF;
     unsigned long long near = 0;
     for (int v = tid; v < n; v += nthr) {
-        const int c = comp[v];
-        const double bv = B[v];
+        const int c = (int)ld_coh<COH>(&comp[v]);
+        const double bv = ld_coh<COH>(&B[v]);
         const double mx = as_f64(cmax[c]);
         const double band = P.tau * (mx > 1.0 ? mx : 1.0);
         const double gap = mx - bv;
@@ -159,10 +162,11 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     // anchors: Alg. 1 for every i, counted as in Alg. 2
     unsigned long long s_nk = 0, s_ak = 0, s_dk = 0, units = 0;
     for (int i = tid; i < n; i += nthr) {
-        const int c = comp[i];
+        const int c = (int)ld_coh<COH>(&comp[i]);
+        const uint32_t sz = (uint32_t)ld_coh<COH>(&csize[i]);
         const u32x4 x = philox10({r, (uint32_t)i, 0xFFFFFFFFu, 1u}, P.key0, P.key1);
         const bool coin = (uint64_t)x.x < P.t_alpha;
-        const bool valid = !coin && (uint32_t)csize[i] >= P.k_min;
+        const bool valid = !coin && sz >= P.k_min;
         const int nx = valid ? ccen[c] : -1;
         atomicAdd(&P.counts[(size_t)i * (n + 1) + (nx >= 0 ? nx : n)], 1u);
         if (P.next_table) P.next_table[(size_t)r_local * n + i] = nx;
@@ -172,12 +176,12 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
             if (P.next_table_w) P.next_table_w[(size_t)r_local * n + i] = nw;
         }
         units += 1;
-        s_nk += (unsigned long long)csize[i];
+        s_nk += (unsigned long long)sz;
         s_ak += kal[c];
         s_dk += kba[c];
     }
     if (P.bsum)
-        for (int v = tid; v < n; v += nthr) unsafeAtomicAdd(&P.bsum[v], B[v]);
+        for (int v = tid; v < n; v += nthr) unsafeAtomicAdd(&P.bsum[v], ld_coh<COH>(&B[v]));
     acc_stats[0] += units;
     acc_stats[1] += s_nk;
     acc_stats[2] += s_ak;

@@ -35,7 +35,7 @@ namespace amc {
 // G lanes cooperate on one vertex's adjacency; an adjacency entry holds the
 // neighbour in its low `shift` bits and the weight above them.
 // ---------------------------------------------------------------------------
-template <bool WEIGHTED, int G, typename ADJ>
+template <bool WEIGHTED, int G, typename ADJ, bool GB>
 __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
                             uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctr,
                             int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
@@ -185,7 +185,7 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
                 const double sv = (double)sig[v];
                 const double delta = sv * sum;
                 sig[v] = as_u64((1.0 + delta) / sv);
-                if (v != s) unsafeAtomicAdd(&B[v], delta);
+                if (v != s) add_B<GB>(B, v, delta);
                 if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
             }
         }
@@ -221,7 +221,7 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
     }
 }
 
-template <bool WEIGHTED, int U, typename ADJ>
+template <bool WEIGHTED, int U, typename ADJ, bool GB>
 __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
                                  double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux,
                                  uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
@@ -405,7 +405,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 const double sv = (double)sig[v];
                 const double delta = sv * sum;
                 sig[v] = as_u64((1.0 + delta) / sv);
-                if (v != s) unsafeAtomicAdd(&B[v], delta);
+                if (v != s) add_B<GB>(B, v, delta);
                 if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
             }
         }
@@ -429,8 +429,33 @@ __host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint3
     return L;
 }
 
-template <bool WEIGHTED, int G, typename ADJ>
-__global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
+// L2 mode: the realized graph, B(H_r) and the component labels of one
+// workgroup live in its global scratch (small enough to stay in L2); the LDS
+// holds only the wavefronts' private regions.
+struct L2Layout {
+    uint32_t rp, adj, B, comp, csize, total;
+};
+__host__ __device__ inline L2Layout l2_layout(int n, uint32_t adj_cap, uint32_t adj_bytes) {
+    L2Layout L;
+    const uint32_t un = (uint32_t)n;
+    L.rp = 0;
+    L.adj = (adj_bytes * (un + 1u) + 3u) & ~3u;
+    L.B = (L.adj + adj_bytes * adj_cap + 7u) & ~7u;
+    L.comp = L.B + 8u * un;
+    L.csize = L.comp + 4u * un;
+    L.total = (L.csize + 4u * un + 255u) & ~255u;
+    return L;
+}
+
+// Persistent sweep.  GL = false: LDS mode (realized graph, B(H_r) and the
+// component labels in LDS next to the wavefronts' regions).  GL = true: L2
+// mode (those in the workgroup's global scratch, B accumulated with device
+// atomics), which leaves the whole LDS to per-source state and so keeps more
+// sources in flight on graphs whose realized adjacency would crowd the LDS.
+// The 8-slot lane mapping needs more than the 128 VGPRs a 1024-thread
+// workgroup allows; it is limited to 8 wavefronts per workgroup.
+template <bool WEIGHTED, int G, typename ADJ, bool GL>
+__global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -468,15 +493,35 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
         const int t = (int)(qitem % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
         const uint32_t shift = P.shift;
-
         const int n = P.n;
-        const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
-        ADJ *rp = (ADJ *)(smem + L.rp);
-        ADJ *adj = (ADJ *)(smem + L.adj);
-        double *B = (double *)(smem + L.B);
-        uint16_t *comp = (uint16_t *)(smem + L.comp);
-        uint16_t *csize = (uint16_t *)(smem + L.csize);
-        unsigned char *wbase = smem + L.waves;
+        const bool split = P.tiles_per_r > 1;
+
+        ADJ *rp, *adj;
+        double *B;
+        unsigned char *wbase;
+        // component labels / sizes of the sources: LDS u16 (LDS mode) or
+        // global int32 (L2 mode)
+        uint16_t *comp16 = nullptr, *csize16 = nullptr;
+        int32_t *comp32 = nullptr, *csize32 = nullptr;
+        if constexpr (GL) {
+            const L2Layout L = l2_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+            unsigned char *gs = (unsigned char *)(LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words);
+            rp = to_global((ADJ *)(gs + L.rp));
+            adj = to_global((ADJ *)(gs + L.adj));
+            // a split realization accumulates straight into its exchange rows
+            B = to_global(split ? P.Bg + (size_t)r_local * n : (double *)(gs + L.B));
+            comp32 = to_global(split ? P.compg + (size_t)r_local * n : (int32_t *)(gs + L.comp));
+            csize32 = to_global(split ? P.sizeg + (size_t)r_local * n : (int32_t *)(gs + L.csize));
+            wbase = smem;
+        } else {
+            const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+            rp = (ADJ *)(smem + L.rp);
+            adj = (ADJ *)(smem + L.adj);
+            B = (double *)(smem + L.B);
+            comp16 = (uint16_t *)(smem + L.comp);
+            csize16 = (uint16_t *)(smem + L.csize);
+            wbase = smem + L.waves;
+        }
         // byte offsets from the LDS base keep every pointer in the LDS address space
         unsigned char *wmine = wbase + wave * P.wave_bytes;
         const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
@@ -493,7 +538,15 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
         RS.kba = RS.kal + n;
 
         stage_realization(P, r, rp, adj, shift, (uint16_t *)wbase, scan_tmp);
-        for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
+        if constexpr (GL) {
+            if (!split)
+                for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
+            // the realized graph and the cleared B are complete at L2 before
+            // any wavefront reads them or adds into B
+            __threadfence();
+        } else {
+            for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
+        }
         __syncthreads();
 
         const int s_lo = t * P.tile, s_hi = min(n, s_lo + P.tile);
@@ -501,20 +554,44 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
             if constexpr (G == 1 || G == 2 || G == 3)    // lane per vertex, unroll 4 / 2 / 8
-                wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ>(
+                wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GL>(
                     P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs, sz, ovf);
             else
-                wave_source<WEIGHTED, G, ADJ>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs,
+                wave_source<WEIGHTED, G, ADJ, GL>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs,
                                               sz, ovf);
             if (lane == 0) {
-                comp[s] = (uint16_t)cs;
-                csize[s] = (uint16_t)sz;
+                if constexpr (GL) {
+                    st_global(&comp32[s], (int32_t)cs);
+                    st_global(&csize32[s], (int32_t)sz);
+                } else {
+                    comp16[s] = (uint16_t)cs;
+                    csize16[s] = (uint16_t)sz;
+                }
             }
+        }
+        if constexpr (GL) {
+            // every B atomic and label store of this item has reached L2
+            __threadfence();
+            __syncthreads();
+            if (!split) {
+                reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
+                                                       acc_stats);
+            } else {
+                if (tid == 0) last_sh = (atomicAdd(&P.done[r_local], 1u) == (unsigned)(P.tiles_per_r - 1));
+                __syncthreads();
+                if (last_sh) {
+                    __threadfence();
+                    reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
+                                                           acc_stats);
+                }
+                __syncthreads();
+            }
+            continue;
         }
         __syncthreads();
 
-        if (P.tiles_per_r == 1) {
-            reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+        if (!split) {
+            reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats);
         } else {
             // publish this tile's partial B and component labels; the last
             // tile of the realization to finish performs the reduction
@@ -522,8 +599,8 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
             for (int v = tid; v < n; v += blockDim.x)
                 if (B[v] != 0.0) unsafeAtomicAdd(&Bg[v], B[v]);
             for (int s = s_lo + tid; s < s_hi; s += blockDim.x) {
-                P.compg[(size_t)r_local * n + s] = comp[s];
-                P.sizeg[(size_t)r_local * n + s] = csize[s];
+                P.compg[(size_t)r_local * n + s] = comp16[s];
+                P.sizeg[(size_t)r_local * n + s] = csize16[s];
             }
             __threadfence();
             __syncthreads();
@@ -533,13 +610,13 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
                 __threadfence();
                 for (int v = tid; v < n; v += blockDim.x) {
                     B[v] = __hip_atomic_load(&Bg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    comp[v] = (uint16_t)__hip_atomic_load(&P.compg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                    csize[v] = (uint16_t)__hip_atomic_load(&P.sizeg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    comp16[v] = (uint16_t)__hip_atomic_load(&P.compg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                    csize16[v] = (uint16_t)__hip_atomic_load(&P.sizeg[(size_t)r_local * n + v], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __syncthreads();
-                reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+                reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats);
             }
             __syncthreads();
         }
@@ -550,25 +627,40 @@ __global__ __launch_bounds__(1024) void sweep_wave_kernel(LaunchCtl LC) {
 // ---------------------------------------------------------------------------
 // Host-side launch (compiled into the same object).
 // ---------------------------------------------------------------------------
-uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes) {
+static uint32_t wave_private_bytes(int n) {
     const uint32_t un = (uint32_t)n;
     const uint32_t per_wave = ((4u * un + 7u) & ~7u) + 8u * un + 2u * un + 2u * un;
-    const uint32_t wb = (per_wave + 15u) & ~15u;
+    return (per_wave + 15u) & ~15u;
+}
+
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes) {
+    const uint32_t wb = wave_private_bytes(n);
     if (wave_bytes) *wave_bytes = wb;
     return wave_layout(n, adj_cap, adj_bytes).waves + wb * (uint32_t)waves;
 }
 
-template <bool W, int G, typename ADJ>
+uint32_t lds_bytes_wave_l2(int n, int waves, uint32_t *wave_bytes) {
+    const uint32_t wb = wave_private_bytes(n);
+    if (wave_bytes) *wave_bytes = wb;
+    return wb * (uint32_t)waves;
+}
+
+size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes) {
+    return l2_layout(n, adj_cap, adj_bytes).total / 4u;
+}
+
+template <bool W, int G, typename ADJ, bool GL>
 static hipError_t launch_t(const LaunchCtl &LC, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ>), dim3(blocks), dim3(64 * waves), lds, st, LC);
+    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ, GL>), dim3(blocks), dim3(64 * waves), lds, st, LC);
     return hipGetLastError();
 }
 
-template <bool W, typename ADJ>
+template <bool W, typename ADJ, bool GL>
 static hipError_t attrs_g(int max_lds) {
-    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ>, (const void *)sweep_wave_kernel<W, 2, ADJ>,
-                        (const void *)sweep_wave_kernel<W, 3, ADJ>, (const void *)sweep_wave_kernel<W, 4, ADJ>,
-                        (const void *)sweep_wave_kernel<W, 8, ADJ>, (const void *)sweep_wave_kernel<W, 16, ADJ>};
+    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL>, (const void *)sweep_wave_kernel<W, 2, ADJ, GL>,
+                        (const void *)sweep_wave_kernel<W, 3, ADJ, GL>, (const void *)sweep_wave_kernel<W, 4, ADJ, GL>,
+                        (const void *)sweep_wave_kernel<W, 8, ADJ, GL>,
+                        (const void *)sweep_wave_kernel<W, 16, ADJ, GL>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
@@ -576,35 +668,49 @@ static hipError_t attrs_g(int max_lds) {
     return hipSuccess;
 }
 
-// Allows every LDS-mode instantiation the device's dynamic LDS (set once per
-// context, outside any stream capture).
-hipError_t set_sweep_wave_attrs(int max_lds) {
+template <bool GL>
+static hipError_t attrs_all(int max_lds) {
     hipError_t e;
-    if ((e = attrs_g<true, uint16_t>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_g<false, uint16_t>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_g<true, uint32_t>(max_lds)) != hipSuccess) return e;
-    return attrs_g<false, uint32_t>(max_lds);
+    if ((e = attrs_g<true, uint16_t, GL>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<false, uint16_t, GL>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<true, uint32_t, GL>(max_lds)) != hipSuccess) return e;
+    return attrs_g<false, uint32_t, GL>(max_lds);
 }
 
-template <bool W, typename ADJ>
+// Allows every LDS-mode and L2-mode instantiation the device's dynamic LDS
+// (set once per context, outside any stream capture).
+hipError_t set_sweep_wave_attrs(int max_lds) {
+    const hipError_t e = attrs_all<false>(max_lds);
+    if (e != hipSuccess) return e;
+    return attrs_all<true>(max_lds);
+}
+
+template <bool W, typename ADJ, bool GL>
 static hipError_t launch_g(const LaunchCtl &LC, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
     switch (group) {
-        case 1: return launch_t<W, 1, ADJ>(LC, blocks, waves, lds, st);
-        case 2: return launch_t<W, 2, ADJ>(LC, blocks, waves, lds, st);
-        case 3: return launch_t<W, 3, ADJ>(LC, blocks, waves, lds, st);
-        case 4: return launch_t<W, 4, ADJ>(LC, blocks, waves, lds, st);
-        case 16: return launch_t<W, 16, ADJ>(LC, blocks, waves, lds, st);
-        default: return launch_t<W, 8, ADJ>(LC, blocks, waves, lds, st);
+        case 1: return launch_t<W, 1, ADJ, GL>(LC, blocks, waves, lds, st);
+        case 2: return launch_t<W, 2, ADJ, GL>(LC, blocks, waves, lds, st);
+        case 3: return launch_t<W, 3, ADJ, GL>(LC, blocks, waves, lds, st);
+        case 4: return launch_t<W, 4, ADJ, GL>(LC, blocks, waves, lds, st);
+        case 16: return launch_t<W, 16, ADJ, GL>(LC, blocks, waves, lds, st);
+        default: return launch_t<W, 8, ADJ, GL>(LC, blocks, waves, lds, st);
     }
 }
 
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                             uint32_t lds, hipStream_t st) {
+template <bool GL>
+static hipError_t launch_w(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                           uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_g<true, uint16_t>(LC, group, blocks, waves, lds, st)
-                        : launch_g<false, uint16_t>(LC, group, blocks, waves, lds, st);
-    return weighted ? launch_g<true, uint32_t>(LC, group, blocks, waves, lds, st)
-                    : launch_g<false, uint32_t>(LC, group, blocks, waves, lds, st);
+        return weighted ? launch_g<true, uint16_t, GL>(LC, group, blocks, waves, lds, st)
+                        : launch_g<false, uint16_t, GL>(LC, group, blocks, waves, lds, st);
+    return weighted ? launch_g<true, uint32_t, GL>(LC, group, blocks, waves, lds, st)
+                    : launch_g<false, uint32_t, GL>(LC, group, blocks, waves, lds, st);
+}
+
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, int group, uint32_t adj_bytes, int blocks,
+                             int waves, uint32_t lds, hipStream_t st) {
+    return l2 ? launch_w<true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
+              : launch_w<false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
 }
 
 }  // namespace amc

@@ -36,8 +36,14 @@ void tune_load(amc_ctx *ctx) {
     long long m;
     unsigned wmax;
     double rate;
-    while (std::fscanf(f, "%d %lld %d %u %d %d %d %lf", &n, &m, &wk, &wmax, &mode, &group, &waves, &rate) == 8)
-        ctx->tune[TuneKey{n, (int64_t)m, wk, wmax}] = TuneChoice{mode, group, waves, rate};
+    while (std::fscanf(f, "%d %lld %d %u %d %d %d %lf", &n, &m, &wk, &wmax, &mode, &group, &waves, &rate) == 8) {
+        // entries the planner could not honour are ignored
+        const bool mode_ok = mode == AMC_MODE_WAVE || mode == AMC_MODE_BLOCK || mode == AMC_MODE_WAVE_L2;
+        const bool group_ok = group == 0 || group == 1 || group == 2 || group == 3 || group == 4 || group == 8 ||
+                              group == 16;
+        if (mode_ok && group_ok && waves >= 0 && waves <= 16)
+            ctx->tune[TuneKey{n, (int64_t)m, wk, wmax}] = TuneChoice{mode, group, waves, rate};
+    }
     std::fclose(f);
 }
 
@@ -51,8 +57,9 @@ extern "C" int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model
     struct Cand {
         int mode, group;
     };
-    const Cand cands[] = {{AMC_MODE_WAVE, 1}, {AMC_MODE_WAVE, 2}, {AMC_MODE_WAVE, 8}, {AMC_MODE_WAVE, 16},
-                          {AMC_MODE_BLOCK, 0}};
+    const Cand cands[] = {{AMC_MODE_WAVE, 1},    {AMC_MODE_WAVE, 2},    {AMC_MODE_WAVE, 3},
+                          {AMC_MODE_WAVE, 8},    {AMC_MODE_WAVE, 16},   {AMC_MODE_WAVE_L2, 1},
+                          {AMC_MODE_WAVE_L2, 3}, {AMC_MODE_WAVE_L2, 8}, {AMC_MODE_BLOCK, 0}};
     amc_query pq = *q;
     pq.R = probe_R;
     pq.flags = AMC_SKIP_TAIL;
@@ -80,7 +87,7 @@ extern "C" int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model
         if (rc != AMC_OK) return rc;
         ++tried;
         const double rate = (double)probe_R * g->n / (res.stats.sweep_ms * 1e-3);
-        if (rate > best.units_per_s) best = TuneChoice{c.mode, c.mode == AMC_MODE_WAVE ? c.group : 0,
+        if (rate > best.units_per_s) best = TuneChoice{c.mode, c.mode == AMC_MODE_BLOCK ? 0 : c.group,
                                                        res.stats.waves, rate};
     }
     if (tried == 0) return AMC_E_UNSUPPORTED;

@@ -89,7 +89,10 @@ FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.WANT_N
 @pytest.mark.parametrize("mode,extra", [(amc.MODE_WAVE, {}), (amc.MODE_BLOCK, {}),
                                         (amc.MODE_WAVE, {"tile": 3}), (amc.MODE_WAVE, {"flags": amc.PLAIN_LAUNCH}),
                                         (amc.MODE_BLOCK, {"tile": 7}), (amc.MODE_WAVE, {"group": 4}),
-                                        (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"group": 16})])
+                                        (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"group": 16}),
+                                        (amc.MODE_WAVE, {"group": 3}), (amc.MODE_WAVE_L2, {}),
+                                        (amc.MODE_WAVE_L2, {"tile": 3}), (amc.MODE_WAVE_L2, {"group": 8}),
+                                        (amc.MODE_WAVE_L2, {"flags": amc.PLAIN_LAUNCH})])
 def test_er20_full_against_oracle(ctx, mode, extra):
     wl = W.config_er20()
     g = wl.graph
@@ -121,7 +124,7 @@ def test_debug_dump_distances_sigma_delta(ctx):
     wl = W.config_er20()
     g = wl.graph
     pairs = [(0, 0), (3, 7), (999, 19), (500, 11)]
-    for mode in (amc.MODE_WAVE, amc.MODE_BLOCK):
+    for mode in (amc.MODE_WAVE, amc.MODE_BLOCK, amc.MODE_WAVE_L2):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, mode=mode,
                       flags=amc.SKIP_TAIL, debug_pairs=pairs)
         for k, (r, s) in enumerate(pairs):
@@ -144,7 +147,7 @@ def _case(ctx, g, model, R, **q):
     return res, ref
 
 
-@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_BLOCK, "wave-g8"])
+@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_BLOCK, amc.MODE_WAVE_L2, "wave-g8"])
 def test_edge_cases(ctx, mode):
     if mode == "wave-g8":
         global _case
@@ -237,12 +240,32 @@ def test_er5000_sampled_realizations_with_pool(ctx):
     wl = W.config_er5000()
     g = wl.graph
     R = 2
-    res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
-                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, pool=wl.pool)
-    assert res["stats"]["mode"] == amc.MODE_BLOCK
     ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
                   want_next=True, pool=wl.pool, **wl.model())
-    check_sweep(res, ref, g.n, "er5000")
+    for mode in (amc.MODE_BLOCK, amc.MODE_WAVE_L2):
+        res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
+                      flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, pool=wl.pool,
+                      mode=mode)
+        assert res["stats"]["mode"] == mode
+        check_sweep(res, ref, g.n, f"er5000 mode {mode}")
+
+
+def test_weighted_n2400_l2_mode_sampled(ctx):
+    # a graph whose realized adjacency leaves room for only two wavefronts in
+    # LDS mode: the planner takes the L2 mode; two realizations split over
+    # several work items each
+    g = W.er_graph(2400, 8.0 / 2399, 2400)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    res = gpu_run(ctx, g, model, seed=3, R=2, r_begin=77, flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER |
+                  amc.WANT_BSUM | amc.SKIP_TAIL)
+    assert res["stats"]["mode"] == amc.MODE_WAVE_L2
+    assert res["stats"]["tile"] < g.n
+    ref = O.sweep(g.n, g.eu, g.ev, seed=3, R=2, r_begin=77, want_next=True, **model)
+    check_sweep(res, ref, g.n, "er2400 L2")
+    res1 = gpu_run(ctx, g, model, seed=3, R=2, r_begin=77, mode=amc.MODE_WAVE_L2, tile=g.n, group=3,
+                   flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL)
+    assert res1["stats"]["tile"] == g.n
+    check_sweep(res1, ref, g.n, "er2400 L2 whole realizations")
 
 
 # --------------------------------------------------------------------------- systems properties

@@ -28,23 +28,29 @@ def ctx():
 
 def mixed_items(ctx, count, R, seed=0):
     wls = W.config_mixed_batch(count=count, R=R, seed=seed)
-    # keep the graphs small enough for a quick test, mixing both sweep modes
+    # keep the graphs small enough for a quick test, mixing the three sweep modes
     out = []
     for k, wl in enumerate(wls):
         g = wl.graph
+        model = wl.model()
         if g.n > 1400 and k % 3:
             g = W.er_graph(300 + 37 * k, 6.0 / (300 + 37 * k), 900 + k)
             wl.graph = g
-        if k == 2:                                   # too large for the LDS mode: workgroup per source
+        if k == 2:                                   # realized graph crowds the LDS: L2 mode
             g = W.er_graph(3500, 10.0 / 3499, 77)
             wl.graph = g
             wl.R = 8
+        if k == 4:                                   # unit weights, n = 4600: workgroup per source
+            g = W.er_graph(4600, 8.0 / 4599, 78)
+            wl.graph = g
+            wl.R = 4
+            model = {"p_fail": 0.1, "weight": "unit"}
         G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
         q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, eps=wl.eps, r_lower=wl.r_lower,
                  cert_topk=3, flags=FLAGS)
         if k == 3:
             q["pool"] = np.arange(0, g.n, 7, dtype=np.int32)
-        out.append((G, wl.model(), q))
+        out.append((G, model, q))
     return out
 
 
@@ -64,7 +70,7 @@ def test_batch_matches_standalone_runs_over_replays(ctx):
     say(f"[gpu] batch of {len(items)} graphs, n = {[G.n for G, _, _ in items]}")
     ref = [amc.run(ctx, G, model, **q) for G, model, q in items]
     modes = {r["stats"]["mode"] for r in ref}
-    assert modes == {amc.MODE_WAVE, amc.MODE_BLOCK}
+    assert modes == {amc.MODE_WAVE, amc.MODE_BLOCK, amc.MODE_WAVE_L2}
     B = amc.Batch(ctx, items)
     info = B.info()
     assert info["launches"] >= 2
@@ -127,7 +133,7 @@ def test_autotuner_choice_is_used_and_exact(ctx, tmp_path, monkeypatch):
     assert t["candidates"] >= 2 and t["units_per_s"] > 0
     res = amc.run(c2, G, model, R=40, seed=3, flags=FLAGS | amc.SKIP_TAIL)
     assert res["stats"]["mode"] == t["mode"]
-    if t["mode"] == amc.MODE_WAVE:
+    if t["mode"] != amc.MODE_BLOCK:
         assert res["stats"]["group"] == t["group"]
     ref = amc.run(c2, G, model, R=40, seed=3, flags=FLAGS | amc.SKIP_TAIL, mode=amc.MODE_BLOCK)
     assert np.array_equal(res["counts"], ref["counts"]) and np.array_equal(res["next_table"], ref["next_table"])
