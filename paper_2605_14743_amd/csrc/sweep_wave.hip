@@ -259,16 +259,35 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             }
             const uint32_t maxlen = wave_max_fast(len);
             unsigned long long acc = 0ull;
+            // the adjacency carries kAdjPad zero entries past its end (and, in
+            // the L2 mode, the rest of the workgroup scratch), so these loads
+            // need no predication; masked results are dropped.  In the L2
+            // mode the next block of U entries is loaded while the current
+            // one is used (global latency); LDS loads are issued in place.
+            uint32_t nxt[U];
+            if constexpr (GB) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + k];
+            }
             for (uint32_t off = 0; off < maxlen; off += U) {
-                uint32_t u[U], w[U], du[U];
+                uint32_t u[U], w[U], du[U], cur[U];
                 bool found[U];
-                // the adjacency carries kAdjPad zero entries past its end, so
-                // these loads need no predication; masked results are dropped
+                if constexpr (GB) {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+                    if (off + U < maxlen) {
+#pragma unroll
+                        for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + off + U + k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[beg + off + k];
+                }
                 // a slot past the vertex's adjacency gets weight kNoEdge, which
                 // fails both tests below (du + kNoEdge > D, D + kNoEdge > du)
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const uint32_t a = (uint32_t)adj[beg + off + k];
+                    const uint32_t a = cur[k];
                     u[k] = a & nmask;
                     w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
@@ -385,11 +404,27 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 dv = dist[v];
             }
             double sum = 0.0;
+            uint32_t nxt[U];
+            if constexpr (GB) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + k];
+            }
             for (uint32_t off = 0; off < len; off += U) {
-                uint32_t u[U], w[U], du[U];
+                uint32_t u[U], w[U], du[U], cur[U];
+                if constexpr (GB) {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+                    if (off + U < len) {
+#pragma unroll
+                        for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + off + U + k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[beg + off + k];
+                }
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const uint32_t a = (uint32_t)adj[beg + off + k];
+                    const uint32_t a = cur[k];
                     u[k] = a & nmask;
                     w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
