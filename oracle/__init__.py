@@ -61,20 +61,22 @@ class _Model(C.Structure):
 
 class _Query(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("R", C.c_uint32), ("r_begin", C.c_uint32), ("alpha", C.c_double),
-                ("k_min", C.c_uint32), ("tau", C.c_double), ("pool_mask", C.POINTER(C.c_uint8))]
+                ("k_min", C.c_uint32), ("tau", C.c_double), ("pool_mask", C.POINTER(C.c_uint8)),
+                ("topk", C.c_int32), ("gamma", C.POINTER(C.c_double))]
 
 
 class _SweepOut(C.Structure):
     _fields_ = [("counts", C.POINTER(C.c_uint32)), ("counts_w", C.POINTER(C.c_uint32)),
                 ("center_global", C.POINTER(C.c_int32)), ("next_table", C.POINTER(C.c_int32)),
                 ("next_table_w", C.POINTER(C.c_int32)), ("bsum", C.POINTER(C.c_double)),
-                ("stats", C.c_uint64 * 8)]
+                ("stats", C.c_uint64 * 8), ("psi", C.POINTER(C.c_double)), ("psi_w", C.POINTER(C.c_double))]
 
 
 class _TailIn(C.Structure):
     _fields_ = [("eta", C.c_double), ("s", C.POINTER(C.c_double)), ("f", C.POINTER(C.c_double)),
                 ("pool_mask", C.POINTER(C.c_uint8)), ("eps", C.c_double), ("r_lower", C.c_double),
-                ("cert_topk", C.c_int32)]
+                ("cert_topk", C.c_int32), ("psi", C.POINTER(C.c_double)), ("psi_w", C.POINTER(C.c_double)),
+                ("fb_node", C.c_int32), ("fb_mask", C.POINTER(C.c_uint8))]
 
 
 class _TailOut(C.Structure):
@@ -86,7 +88,10 @@ class _TailOut(C.Structure):
                 ("cert_gap", C.POINTER(C.c_double)), ("cert_sharp", C.POINTER(C.c_double)),
                 ("cert_v", C.POINTER(C.c_int32)), ("cert_crude", C.c_double), ("epsbar", C.c_double),
                 ("epsbar_supp", C.c_double), ("cert_crude_supp", C.c_double),
-                ("cert_sharp_supp", C.POINTER(C.c_double)), ("admissible", C.c_int32)]
+                ("cert_sharp_supp", C.POINTER(C.c_double)), ("admissible", C.c_int32),
+                ("psi_hat", C.POINTER(C.c_double)), ("psi_w_hat", C.POINTER(C.c_double)), ("b_k", C.c_double),
+                ("b_kw", C.c_double), ("b_fb", C.POINTER(C.c_double)), ("b_cens", C.POINTER(C.c_double)),
+                ("ET_fb", C.c_double), ("m_w_fb", C.c_double), ("c_fb", C.c_double)]
 
 
 def _declare(L):
@@ -231,13 +236,20 @@ def band_argmax(B, member, tau=1e-9):
 
 # --------------------------------------------------------------------------- sweep
 def sweep(n, eu, ev, *, seed, R, r_begin=0, alpha=0.15, k_min=5, tau=1e-9, pool=None, want_next=False,
-          want_bsum=True, want_center=True, **model):
-    """Alg. 1 for every anchor over realizations [r_begin, r_begin + R), counted as in Alg. 2."""
+          want_bsum=True, want_center=True, topk=0, gamma=None, **model):
+    """Alg. 1 for every anchor over realizations [r_begin, r_begin + R), counted as in Alg. 2.
+    With topk > 0 also the Top-k step-reward sums psi / psi_w (Sections 6.2-6.3) and the
+    finite-k pool selector (Section 7.1)."""
     eu, ev = _edges(eu, ev)
     mod, keep = _model(**model)
     q = _Query()
     q.seed, q.R, q.r_begin = int(seed), int(R), int(r_begin)
     q.alpha, q.k_min, q.tau = float(alpha), int(k_min), float(tau)
+    q.topk = int(topk)
+    g_arr = None
+    if gamma is not None:
+        g_arr = np.ascontiguousarray(gamma, dtype=np.float64)
+        q.gamma = _ptr(g_arr, C.c_double)
     mask = None
     if pool is not None:
         mask = np.zeros(n, dtype=np.uint8)
@@ -261,11 +273,17 @@ def sweep(n, eu, ev, *, seed, R, r_begin=0, alpha=0.15, k_min=5, tau=1e-9, pool=
     if want_bsum:
         res["bsum"] = np.zeros(n, dtype=np.float64)
         o.bsum = _ptr(res["bsum"], C.c_double)
+    if topk > 0:
+        res["psi"] = np.zeros(n, dtype=np.float64)
+        o.psi = _ptr(res["psi"], C.c_double)
+        if pool is not None:
+            res["psi_w"] = np.zeros(n, dtype=np.float64)
+            o.psi_w = _ptr(res["psi_w"], C.c_double)
     _check(lib().or_sweep(n, len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), C.byref(mod), C.byref(q),
                           C.byref(o)), "sweep")
     st = list(o.stats)
     res["stats"] = {"units": st[0], "sum_nK": st[1], "sum_AK": st[2], "sum_DK": st[3], "near_band": st[4]}
-    del keep
+    del keep, g_arr
     return res
 
 
@@ -318,8 +336,10 @@ def pair_certificate(N, mu, epsbar, r_min, u, v):
     return float(g.value), float(c.value), float(s.value)
 
 
-def tail(counts, R, *, eta=None, s=None, f=None, pool=None, counts_w=None, eps=0.0, r_lower=0.05, cert_topk=0):
-    """Counts -> stabilised kernel -> N, mu, E[T], b, rewards, pool kernel, certificates."""
+def tail(counts, R, *, eta=None, s=None, f=None, pool=None, counts_w=None, eps=0.0, r_lower=0.05, cert_topk=0,
+         psi=None, psi_w=None, fb_node=-1, fb_set=None):
+    """Counts -> stabilised kernel -> N, mu, E[T], b, rewards, pool kernel, certificates; with
+    psi / psi_w the valued Top-k reward-AFCs, with fb_node the fallback kernel and censoring."""
     counts = np.ascontiguousarray(counts, dtype=np.uint32)
     n = counts.shape[0]
     if eta is None:
@@ -337,6 +357,18 @@ def tail(counts, R, *, eta=None, s=None, f=None, pool=None, counts_w=None, eps=0
         mask = np.zeros(n, dtype=np.uint8)
         mask[np.asarray(pool, dtype=np.int64)] = 1
         ti.pool_mask = _ptr(mask, C.c_uint8)
+    keep = []
+    for name, arr in (("psi", psi), ("psi_w", psi_w)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            keep.append(a)
+            setattr(ti, name, _ptr(a, C.c_double))
+    ti.fb_node = int(fb_node)
+    fbm = None
+    if fb_set is not None:
+        fbm = np.zeros(n, dtype=np.uint8)
+        fbm[np.asarray(fb_set, dtype=np.int64)] = 1
+        ti.fb_mask = _ptr(fbm, C.c_uint8)
     k = int(cert_topk)
     out = {"Q": np.zeros((n, n)), "r": np.zeros(n), "N": np.zeros((n, n)), "mu": np.zeros(n), "b": np.zeros(n),
            "b_w": np.zeros(n), "xi": np.zeros(n), "b_w_bar": np.zeros(n), "top": np.zeros(max(k, 1), np.int32),
@@ -347,13 +379,18 @@ def tail(counts, R, *, eta=None, s=None, f=None, pool=None, counts_w=None, eps=0
         setattr(to, key, _ptr(out[key], C.c_double))
     to.top = _ptr(out["top"], C.c_int32)
     to.cert_v = _ptr(out["cert_v"], C.c_int32)
+    for key in ("psi_hat", "psi_w_hat", "b_fb", "b_cens"):
+        out[key] = np.zeros(n)
+        setattr(to, key, _ptr(out[key], C.c_double))
     cw = None
     if counts_w is not None:
         cw = np.ascontiguousarray(counts_w, dtype=np.uint32)
     _check(lib().or_tail(n, _ptr(counts, C.c_uint32), _ptr(cw, C.c_uint32), int(R), C.byref(ti), C.byref(to)),
            "tail")
-    for key in ("ET", "b_f", "ET_w", "m_w", "b_w_f", "cert_crude", "epsbar", "epsbar_supp", "cert_crude_supp"):
+    for key in ("ET", "b_f", "ET_w", "m_w", "b_w_f", "cert_crude", "epsbar", "epsbar_supp", "cert_crude_supp",
+                "b_k", "b_kw", "ET_fb", "m_w_fb", "c_fb"):
         out[key] = float(getattr(to, key))
+    del keep, fbm
     out["admissible"] = bool(to.admissible)
     out["top"] = out["top"][:k]
     out["cert_v"] = out["cert_v"][:n - k] if k > 0 else out["cert_v"][:0]
@@ -362,5 +399,12 @@ def tail(counts, R, *, eta=None, s=None, f=None, pool=None, counts_w=None, eps=0
             out[key] = out[key][:0, :0]
     if pool is None:
         for key in ("b_w", "xi", "b_w_bar"):
+            out[key] = None
+    if psi is None:
+        out["psi_hat"] = None
+    if psi_w is None:
+        out["psi_w_hat"] = None
+    if fb_node < 0 or pool is None or counts_w is None:
+        for key in ("b_fb", "b_cens", "ET_fb", "m_w_fb", "c_fb"):
             out[key] = None
     return out

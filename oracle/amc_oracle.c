@@ -480,8 +480,16 @@ int32_t or_band_argmax(int32_t n, const double *B, const uint8_t *member, double
 /* counting).  Realization r in [r_begin, r_begin + R) is drawn once and     */
 /* serves every anchor i: next(r,i) = bottom if the stop coin fires or       */
 /* |K(i;H_r)| < k_min, else the tie-broken centre of K(i;H_r).  The pool-    */
-/* constrained selector of Section 7.1 (k = infinity) takes the tie-broken   */
-/* argmax over K(i;H_r) intersected with W, bottom when that is empty.       */
+/* constrained selector of Section 7.1 takes, with k = infinity (topk = 0),  */
+/* the tie-broken argmax over K(i;H_r) intersected with W, bottom when that  */
+/* is empty; with a finite k it takes the highest-ranked member of W among   */
+/* the local Top-k set (eq. local-topk).                                      */
+/*                                                                            */
+/* Finite k: the ranking pi_{K,H} of a component is the tie rule applied     */
+/* repeatedly, i.e. pi(t) is the band argmax over the members not ranked     */
+/* before t.  C_k(i) (eq. realized-topk-set) is the first min(k, |K|) of them */
+/* on a valid draw, empty otherwise, and the step rewards of Sections 6.2 and */
+/* 6.3 add up gamma over C_k(i) and over C_k(i) intersected with W.           */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     uint64_t seed;
@@ -491,6 +499,8 @@ typedef struct {
     uint32_t k_min;
     double tau;
     const uint8_t *pool_mask;    /* length n, NULL when no pool            */
+    int32_t topk;                /* 0: k = infinity; else the Top-k size   */
+    const double *gamma;         /* node values (length n) or NULL for 1   */
 } or_query;
 
 typedef struct {
@@ -502,6 +512,8 @@ typedef struct {
     double *bsum;                /* n or NULL: sum over r of B(H_r)        */
     uint64_t stats[8];           /* units, sum n_K, sum A_K, sum D_K,      */
                                  /* near-band count, 0, 0, 0               */
+    double *psi, *psi_w;         /* n each or NULL (topk > 0): sum over r  */
+                                 /* of the Top-k step rewards               */
 } or_sweep_out;
 
 int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
@@ -514,6 +526,9 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
     int32_t *order = NULL, *comp = NULL, *size = NULL, *cc = NULL, *cw = NULL;
     double *B = NULL, *delta = NULL;
     int64_t *k_alive = NULL, *k_deg = NULL;
+    int32_t *fw = NULL;
+    uint8_t *ranked = NULL;
+    double *gs = NULL, *gw = NULL;
     uint32_t rr;
     int32_t v, i;
     int unit = (mod->weight_kind == OR_WEIGHT_UNIT);
@@ -534,8 +549,12 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
     delta = (double *)malloc(sizeof(double) * (size_t)n);
     k_alive = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     k_deg = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    fw = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    ranked = (uint8_t *)malloc((size_t)n);
+    gs = (double *)malloc(sizeof(double) * (size_t)n);
+    gw = (double *)malloc(sizeof(double) * (size_t)n);
     if (!alive || !member || !w || !dist || !sigma || !order || !comp || !size || !cc || !cw || !B || !delta ||
-        !k_alive || !k_deg) { rc = OR_E_NOMEM; goto done; }
+        !k_alive || !k_deg || !fw || !ranked || !gs || !gw) { rc = OR_E_NOMEM; goto done; }
 
     for (rr = 0; rr < q->R; ++rr) {
         uint32_t r = q->r_begin + rr;
@@ -564,6 +583,30 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
             }
         }
 
+        /* finite k: rank each component by repeated band argmax and keep, per
+         * component label, the gamma mass of its Top-k set, of that set's
+         * pool members, and its highest-ranked pool member */
+        if (q->topk > 0) {
+            for (v = 0; v < n; ++v) { ranked[v] = 0; gs[v] = 0.0; gw[v] = 0.0; fw[v] = -1; }
+            for (v = 0; v < n; ++v) {
+                int32_t c = comp[v], u, t;
+                if (v != c) continue;
+                for (t = 0; t < q->topk && t < size[v]; ++t) {
+                    int32_t pick;
+                    double gv;
+                    for (u = 0; u < n; ++u) member[u] = (comp[u] == c) && !ranked[u];
+                    pick = or_band_argmax(n, B, member, q->tau, NULL);
+                    ranked[pick] = 1;
+                    gv = q->gamma ? q->gamma[pick] : 1.0;
+                    gs[c] += gv;
+                    if (q->pool_mask && q->pool_mask[pick]) {
+                        gw[c] += gv;
+                        if (fw[c] < 0) fw[c] = pick;
+                    }
+                }
+            }
+        }
+
         /* anchors: Alg. 1 for every i, counted as in Alg. 2 */
         for (i = 0; i < n; ++i) {
             int coin = or_stop_coin(q->seed, r, i, q->alpha);
@@ -571,8 +614,12 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
             int32_t nx = valid ? cc[comp[i]] : -1;
             out->counts[(size_t)i * (n + 1) + (nx >= 0 ? nx : n)] += 1u;
             if (out->next_table) out->next_table[(size_t)rr * n + i] = nx;
+            if (q->topk > 0 && valid) {
+                if (out->psi) out->psi[i] += gs[comp[i]];
+                if (out->psi_w) out->psi_w[i] += gw[comp[i]];
+            }
             if (out->counts_w) {
-                int32_t nw = (valid && q->pool_mask) ? cw[comp[i]] : -1;
+                int32_t nw = (valid && q->pool_mask) ? (q->topk > 0 ? fw[comp[i]] : cw[comp[i]]) : -1;
                 out->counts_w[(size_t)i * (n + 1) + (nw >= 0 ? nw : n)] += 1u;
                 if (out->next_table_w) out->next_table_w[(size_t)rr * n + i] = nw;
             }
@@ -596,6 +643,7 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
 done:
     free(alive); free(member); free(w); free(dist); free(sigma); free(order); free(comp); free(size);
     free(cc); free(cw); free(B); free(delta); free(k_alive); free(k_deg);
+    free(fw); free(ranked); free(gs); free(gw);
     or_graph_free(&g);
     return rc;
 }
@@ -729,6 +777,9 @@ typedef struct {
     double eps;                  /* row-wise radius of every entry          */
     double r_lower;              /* leak lower bound                         */
     int32_t cert_topk;           /* size of the nominal Top-k, 0 = none     */
+    const double *psi, *psi_w;   /* Top-k step-reward sums over R draws or NULL */
+    int32_t fb_node;             /* fallback representative v_fb, -1 = none */
+    const uint8_t *fb_mask;      /* fallback set V_fb (length n) or NULL    */
 } or_tail_in;
 
 typedef struct {
@@ -745,6 +796,10 @@ typedef struct {
     double cert_crude_supp;
     double *cert_sharp_supp;     /* cert_topk x (n - cert_topk)             */
     int32_t admissible;          /* nominal kernel inside the set: r_i >= r_lower */
+    double *psi_hat, *psi_w_hat; /* n each: estimated expected step rewards  */
+    double b_k, b_kw;            /* valued Top-k reward-AFCs (eq. mr-afc-def, eq. mr-pool-afc) */
+    double *b_fb, *b_cens;       /* n each: fallback-kernel AFC, censored profile */
+    double ET_fb, m_w_fb, c_fb;  /* fallback kernel: E[T], pool mass, non-fallback mass */
 } or_tail_out;
 
 int or_tail(int32_t n, const uint32_t *counts, const uint32_t *counts_w, uint32_t R, const or_tail_in *in,
@@ -797,6 +852,64 @@ int or_tail(int32_t n, const uint32_t *counts, const uint32_t *counts_w, uint32_
                 }
             }
         free(intop);
+    }
+
+    /* reward-AFC of a step reward (Proposition on reward-AFC): s N psi / s N 1
+     * = mu . psi / E[T], with psi estimated by its average over the R draws */
+    out->b_k = 0.0;
+    out->b_kw = 0.0;
+    if (in->psi) {
+        for (j = 0; j < n; ++j) {
+            double ph = in->psi[j] / (double)R;
+            if (out->psi_hat) out->psi_hat[j] = ph;
+            out->b_k += out->mu[j] * ph;
+        }
+        out->b_k /= out->ET;
+    }
+    if (in->psi_w) {
+        for (j = 0; j < n; ++j) {
+            double ph = in->psi_w[j] / (double)R;
+            if (out->psi_w_hat) out->psi_w_hat[j] = ph;
+            out->b_kw += out->mu[j] * ph;
+        }
+        out->b_kw /= out->ET;
+    }
+
+    /* fallback kernel P^{W,fb} (Section 7.3): valid draws whose selection is
+     * empty move to v_fb instead of absorbing; with the same counts, the
+     * valid-but-empty draws of row i are C^W_i,bottom - C_i,bottom.  Then
+     * the censored profile of Section 7.4 renormalises b^{W,fb} off V_fb. */
+    if (counts_w && in->pool_mask && in->fb_node >= 0 && out->b_fb) {
+        uint32_t *cf = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * (size_t)(n + 1));
+        double *Qf = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+        double *rf = (double *)malloc(sizeof(double) * (size_t)n);
+        double *Nf = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+        double *muf = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!cf || !Qf || !rf || !Nf || !muf) { free(cf); free(Qf); free(rf); free(Nf); free(muf); return OR_E_NOMEM; }
+        for (i = 0; i < n; ++i) {
+            const uint32_t *rw = counts_w + (size_t)i * (n + 1);
+            uint32_t *rowf = cf + (size_t)i * (n + 1);
+            for (j = 0; j < n; ++j) rowf[j] = rw[j];
+            rowf[in->fb_node] += rw[n] - counts[(size_t)i * (n + 1) + n];
+            rowf[n] = counts[(size_t)i * (n + 1) + n];
+        }
+        rc = or_counts_to_kernel(n, cf, R, in->eta, Qf, rf);
+        if (rc == OR_OK) rc = or_fundamental(n, Qf, Nf);
+        if (rc == OR_OK) {
+            or_visits(n, Nf, in->s, muf, &out->ET_fb, out->b_fb);
+            out->m_w_fb = 0.0;
+            out->c_fb = 0.0;
+            for (j = 0; j < n; ++j) {
+                if (in->pool_mask[j]) out->m_w_fb += out->b_fb[j];
+                if (!(in->fb_mask && in->fb_mask[j])) out->c_fb += out->b_fb[j];
+            }
+            if (out->b_cens)
+                for (j = 0; j < n; ++j)
+                    out->b_cens[j] = (!(in->fb_mask && in->fb_mask[j]) && out->c_fb > 0.0) ? out->b_fb[j] / out->c_fb
+                                                                                         : 0.0;
+        }
+        free(cf); free(Qf); free(rf); free(Nf); free(muf);
+        if (rc != OR_OK) return rc;
     }
 
     if (counts_w && in->pool_mask) {                   /* constrained kernel P^W (Section 7) */
