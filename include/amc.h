@@ -85,6 +85,7 @@ extern "C" {
 #define AMC_WANT_DEBUG (1u << 4)      /* d, sigma, delta of listed (r, s) pairs   */
 #define AMC_SKIP_TAIL (1u << 5)       /* counts only, no chain algebra            */
 #define AMC_PLAIN_LAUNCH (1u << 6)    /* one kernel launch per realization        */
+#define AMC_FALLBACK (1u << 7)        /* fallback kernel P^{W,fb} with v_fb = fb_node */
 
 typedef struct amc_ctx amc_ctx;
 typedef struct amc_graph amc_graph;
@@ -125,7 +126,29 @@ typedef struct amc_query {
                                    0 = engine */
     const uint32_t *debug_pairs; /* AMC_WANT_DEBUG: n_debug pairs (r, s), r absolute */
     int32_t n_debug;            /* at most 64                                        */
+    /* Finite-k local Top-k (Section 3.3, eq. local-topk).  topk = 0 keeps k
+     * infinite: the pool selector takes the tie-broken maximiser of B over
+     * K(i;H_r) ∩ W.  With 1 <= topk <= AMC_MAX_TOPK (and n <= AMC_MAX_TOPK_N)
+     * every component is ranked by applying the tie rule repeatedly (the
+     * maximiser, then the maximiser of the rest, ...); C_k(i) is the first
+     * min(k, |K|) ranked vertices on a valid draw, empty otherwise
+     * (eq. realized-topk-set).  The run then reports the Top-k step rewards
+     * psi_i = E_i[sum of gamma over C_k(i)] and psi_W,i = E_i[sum of gamma over
+     * C_k(i) ∩ W] (Sections 6.2-6.3) with their reward-AFCs, and the pool
+     * selector becomes the highest-ranked member of C_k(i) ∩ W (Section 7.1). */
+    int32_t topk;
+    const double *gamma;        /* node values gamma (n, >= 0) or NULL for 1         */
+    /* Fallback kernel P^{W,fb} (Section 7.3) and censoring (Section 7.4),
+     * with AMC_FALLBACK: fb_node = v_fb (needs a pool), fb_set = V_fb
+     * (fb_set_size vertices, disjoint from W, containing fb_node; NULL =
+     * {fb_node}). */
+    int32_t fb_node;
+    const int32_t *fb_set;
+    int32_t fb_set_size;
 } amc_query;
+
+#define AMC_MAX_TOPK 64
+#define AMC_MAX_TOPK_N 7000
 
 /* Counters of one run.  units = R n (one (r, s) pass each); sum_nK, sum_AK and
  * sum_DK add, over every (r, s), the reached vertices |K(s;H_r)|, the surviving
@@ -137,6 +160,7 @@ typedef struct amc_stats {
     double sweep_ms;            /* HIP-event time of the sweep kernel(s) on the context stream */
     double tail_ms;             /* HIP-event time of the tail kernels                          */
     int32_t mode, waves, tile, blocks, lds_bytes, launches, group, adj_bytes;
+    double topk_ms;             /* HIP-event time of the finite-k Top-k stage (topk > 0) */
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */
@@ -166,6 +190,14 @@ typedef struct amc_result {
     double cert_crude_supp, epsbar_supp; /* support-restricted variants           */
     int32_t admissible;         /* 1 when every r_i >= r_lower                    */
     amc_stats stats;
+    /* finite-k Top-k rows (topk > 0) */
+    double *psi;                /* n: estimated Top-k step reward psi_i (sum over draws / R) */
+    double *psi_w;              /* n: pool-restricted step reward (needs a pool)  */
+    double b_k, b_kw;           /* reward-AFCs s N psi / s N 1 (eq. mr-afc-def, eq. mr-pool-afc) */
+    /* fallback kernel (AMC_FALLBACK) */
+    double *b_fb;               /* n: AFC of P^{W,fb}                             */
+    double *b_cens;             /* n: censored profile, 0 on V_fb (Section 7.4)   */
+    double E_T_fb, m_w_fb, c_fb;/* E_s[T], pool mass and mass off V_fb under P^{W,fb} */
 } amc_result;
 
 /* Context: one device, one stream, an HBM budget for admission (0 = free HBM). */

@@ -19,8 +19,9 @@ OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NO
     0, -1, -2, -3, -4, -5, -6, -7, -8
 WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED = 0, 1, 2
 MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
-WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH = \
-    1, 2, 4, 8, 16, 32, 64
+WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK = \
+    1, 2, 4, 8, 16, 32, 64, 128
+MAX_TOPK, MAX_TOPK_N = 64, 7000
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
@@ -48,7 +49,8 @@ class Query(C.Structure):
                 ("pool", _P(C.c_int32)), ("pool_size", C.c_int32), ("reward", _P(C.c_double)), ("eps", C.c_double),
                 ("r_lower", C.c_double), ("cert_topk", C.c_int32), ("flags", C.c_uint32), ("mode", C.c_int32),
                 ("tile", C.c_int32), ("waves", C.c_int32), ("group", C.c_int32), ("debug_pairs", _P(C.c_uint32)),
-                ("n_debug", C.c_int32)]
+                ("n_debug", C.c_int32), ("topk", C.c_int32), ("gamma", _P(C.c_double)), ("fb_node", C.c_int32),
+                ("fb_set", _P(C.c_int32)), ("fb_set_size", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -60,7 +62,7 @@ class Stats(C.Structure):
     _fields_ = [("units", C.c_uint64), ("sum_nK", C.c_uint64), ("sum_AK", C.c_uint64), ("sum_DK", C.c_uint64),
                 ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
                 ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
-                ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32)]
+                ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32), ("topk_ms", C.c_double)]
 
 
 class Result(C.Structure):
@@ -73,7 +75,10 @@ class Result(C.Structure):
                 ("dbg_sigma", _P(C.c_uint64)), ("dbg_delta", _P(C.c_double)), ("E_T", C.c_double),
                 ("b_f", C.c_double), ("E_T_w", C.c_double), ("m_w", C.c_double), ("b_w_f", C.c_double),
                 ("cert_crude", C.c_double), ("epsbar", C.c_double), ("cert_crude_supp", C.c_double),
-                ("epsbar_supp", C.c_double), ("admissible", C.c_int32), ("stats", Stats)]
+                ("epsbar_supp", C.c_double), ("admissible", C.c_int32), ("stats", Stats),
+                ("psi", _P(C.c_double)), ("psi_w", _P(C.c_double)), ("b_k", C.c_double), ("b_kw", C.c_double),
+                ("b_fb", _P(C.c_double)), ("b_cens", _P(C.c_double)), ("E_T_fb", C.c_double), ("m_w_fb", C.c_double),
+                ("c_fb", C.c_double)]
 
 
 _lib = None
@@ -207,7 +212,7 @@ def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=N
 
 def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, floor_eta=-1.0, s=None, pool=None,
                reward=None, eps=0.0, r_lower=0.05, cert_topk=0, flags=0, mode=MODE_AUTO, tile=0, waves=0, group=0,
-               debug_pairs=None):
+               debug_pairs=None, topk=0, gamma=None, fb_node=None, fb_set=None):
     keep = []
     q = Query()
     q.seed, q.R, q.r_begin = int(seed), int(R), int(r_begin)
@@ -233,6 +238,19 @@ def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, 
         q.debug_pairs = _ptr(dp, C.c_uint32)
         q.n_debug = len(dp)
         q.flags |= WANT_DEBUG
+    q.topk = int(topk)
+    if gamma is not None:
+        ga = np.ascontiguousarray(gamma, dtype=np.float64)
+        keep.append(ga)
+        q.gamma = _ptr(ga, C.c_double)
+    if fb_node is not None:
+        q.flags |= FALLBACK
+        q.fb_node = int(fb_node)
+        if fb_set is not None:
+            fa = np.ascontiguousarray(fb_set, dtype=np.int32)
+            keep.append(fa)
+            q.fb_set = _ptr(fa, C.c_int32)
+            q.fb_set_size = len(fa)
     return q, keep
 
 
@@ -264,6 +282,12 @@ def _alloc_result(n, q: Query):
     if q.n_debug > 0:
         arr.update(dbg_dist=np.zeros((q.n_debug, n), np.uint32), dbg_sigma=np.zeros((q.n_debug, n), np.uint64),
                    dbg_delta=np.zeros((q.n_debug, n)))
+    if q.topk > 0:
+        arr["psi"] = np.zeros(n)
+        if pool:
+            arr["psi_w"] = np.zeros(n)
+    if (q.flags & FALLBACK) and not (q.flags & SKIP_TAIL):
+        arr.update(b_fb=np.zeros(n), b_cens=np.zeros(n))
     res = Result()
     types = {np.dtype(np.uint32): C.c_uint32, np.dtype(np.int32): C.c_int32, np.dtype(np.float64): C.c_double,
              np.dtype(np.uint64): C.c_uint64}
@@ -274,7 +298,8 @@ def _alloc_result(n, q: Query):
 
 def _collect(res: Result, arr: dict) -> dict:
     out = dict(arr)
-    for key in ("E_T", "b_f", "E_T_w", "m_w", "b_w_f", "cert_crude", "epsbar", "cert_crude_supp", "epsbar_supp"):
+    for key in ("E_T", "b_f", "E_T_w", "m_w", "b_w_f", "cert_crude", "epsbar", "cert_crude_supp", "epsbar_supp",
+                "b_k", "b_kw", "E_T_fb", "m_w_fb", "c_fb"):
         out[key] = float(getattr(res, key))
     out["admissible"] = bool(res.admissible)
     st = res.stats

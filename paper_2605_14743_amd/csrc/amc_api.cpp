@@ -94,7 +94,8 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(free_b * 0.9);
-    if (set_sweep_wave_attrs(c->max_lds) != hipSuccess || set_sweep_block_attrs(c->max_lds) != hipSuccess) {
+    if (set_sweep_wave_attrs(c->max_lds) != hipSuccess || set_sweep_block_attrs(c->max_lds) != hipSuccess ||
+        set_topk_attrs(c->max_lds) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return AMC_E_HIP;
@@ -240,6 +241,33 @@ extern "C" int amc_version(void) { return 100; }
 // ---------------------------------------------------------------------------
 namespace amc {
 
+void QueryInputs::capture(amc_query &q, int n) {
+    if (q.s) {
+        s.assign(q.s, q.s + n);
+        q.s = s.data();
+    }
+    if (q.reward) {
+        reward.assign(q.reward, q.reward + n);
+        q.reward = reward.data();
+    }
+    if (q.gamma) {
+        gamma.assign(q.gamma, q.gamma + n);
+        q.gamma = gamma.data();
+    }
+    if (q.pool_size > 0) {
+        pool.assign(q.pool, q.pool + q.pool_size);
+        q.pool = pool.data();
+    }
+    if (q.fb_set_size > 0) {
+        fb_set.assign(q.fb_set, q.fb_set + q.fb_set_size);
+        q.fb_set = fb_set.data();
+    }
+    if (q.n_debug > 0) {
+        dbg.assign(q.debug_pairs, q.debug_pairs + 2 * q.n_debug);
+        q.debug_pairs = dbg.data();
+    }
+}
+
 int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     if (!g || !md || !q) return AMC_E_INVALID_ARG;
     const int n = g->n;
@@ -276,6 +304,29 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     if (q->n_debug < 0 || q->n_debug > 64 || (q->n_debug > 0 && !q->debug_pairs)) return AMC_E_INVALID_ARG;
     for (int k = 0; k < q->n_debug; ++k)
         if (q->debug_pairs[2 * k + 1] >= (uint32_t)n) return AMC_E_INVALID_ARG;
+    if (q->topk < 0 || q->topk > AMC_MAX_TOPK) return AMC_E_INVALID_ARG;
+    if (q->topk > 0 && n > AMC_MAX_TOPK_N) return AMC_E_UNSUPPORTED;
+    if (q->gamma)
+        for (int i = 0; i < n; ++i)
+            if (!(q->gamma[i] >= 0.0) || !std::isfinite(q->gamma[i])) return AMC_E_INVALID_ARG;
+    if (q->flags & AMC_FALLBACK) {
+        if (q->fb_node < 0 || q->fb_node >= n) return AMC_E_INVALID_ARG;
+        // a fallback needs a pool, and V_fb holds v_fb and no pool member
+        if (q->pool_size <= 0) return AMC_E_INVALID_ARG;
+        if (q->fb_set_size < 0 || (q->fb_set_size > 0 && !q->fb_set)) return AMC_E_INVALID_ARG;
+        std::vector<uint8_t> inW((size_t)n, 0), inF((size_t)n, 0);
+        for (int k = 0; k < q->pool_size; ++k) inW[q->pool[k]] = 1;
+        inF[q->fb_node] = 1;
+        for (int k = 0; k < q->fb_set_size; ++k) {
+            if (q->fb_set[k] < 0 || q->fb_set[k] >= n) return AMC_E_INVALID_ARG;
+            inF[q->fb_set[k]] = 1;
+        }
+        bool has_node = q->fb_set_size == 0;
+        for (int k = 0; k < q->fb_set_size; ++k) has_node |= q->fb_set[k] == q->fb_node;
+        if (!has_node) return AMC_E_INVALID_ARG;
+        for (int v = 0; v < n; ++v)
+            if (inW[v] && inF[v]) return AMC_E_INVALID_ARG;
+    }
     if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_WAVE_L2) return AMC_E_INVALID_ARG;
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
     if (q->group < 0 || q->group > 16 || (q->group > 4 && q->group != 8 && q->group != 16)) return AMC_E_INVALID_ARG;
@@ -447,6 +498,9 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
                                            l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u));
     b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;
+    if (q->topk > 0) b += 32 * n + 8 * n;                                  // step rewards, gamma
+    if ((q->flags & AMC_FALLBACK) && !(q->flags & AMC_SKIP_TAIL))        // fallback kernel
+        b += 4 * n * (n + 1) + 2 * 8 * n * n + 5 * 8 * n + 4096;
     *bytes = b;
     return AMC_OK;
 }

@@ -74,16 +74,37 @@ struct SweepParams {
     double *bsum;
     unsigned long long *stats;  // [units, sum_nK, sum_AK, sum_DK, near_band]
     int *err;                   // bit 0: sigma overflow
-    // partial-B exchange when a realization spans several items
+    // partial-B exchange when a realization spans several items; with
+    // keep_rows every realization's B(H_r) and labels are left here for the
+    // finite-k Top-k stage
     double *Bg;                 // R x n
     int32_t *compg, *sizeg;     // R x n
     unsigned int *done;         // R
+    int32_t keep_rows;
     // per-(r, s) dumps for the parity checks
     const uint32_t *dbg_pairs;  // n_dbg x (r, s)
     int32_t n_dbg;
     uint32_t *dbg_dist;
     unsigned long long *dbg_sigma;
     double *dbg_delta;
+};
+
+// Finite-k Top-k stage of one query (one workgroup per realization).
+struct TopkArgs {
+    int32_t n;
+    uint32_t R, r_begin;
+    uint32_t key0, key1;
+    uint64_t t_alpha;
+    uint32_t k_min;
+    double tau;
+    int32_t topk;
+    const double *Bg;           // R x n: B(H_r)
+    const int32_t *compg, *sizeg;
+    const uint8_t *pool;        // n or nullptr
+    const double *gamma;        // n or nullptr (unit values)
+    double *psi, *psi_w;        // n: step-reward sums (psi_w nullptr without a pool)
+    uint32_t *counts_w;         // n x (n+1) finite-k pool selector counts, or nullptr
+    int32_t *next_table_w;      // R x n or nullptr
 };
 
 // One sweep launch serves one or several queries: the launch's work items are

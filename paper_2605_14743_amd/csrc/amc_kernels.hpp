@@ -26,6 +26,18 @@ hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, in
 hipError_t set_sweep_wave_attrs(int max_lds);
 hipError_t set_sweep_block_attrs(int max_lds);
 
+// Finite-k Top-k stage and its tail pieces.
+hipError_t set_topk_attrs(int max_lds);
+uint32_t topk_lds(int n);
+hipError_t launch_topk_reduce(const TopkArgs &A, int blocks, hipStream_t st);
+hipError_t tail_div(int n, const double *x, double d, double *y, hipStream_t st);
+hipError_t tail_reward_afc(int n, const double *mu, const double *scal, const double *psi, double *out,
+                           hipStream_t st);
+hipError_t tail_fb_counts(int n, const uint32_t *counts, const uint32_t *counts_w, int fb, uint32_t *cf,
+                          hipStream_t st);
+hipError_t tail_censor(int n, const double *b, const uint8_t *fb_mask, double *b_cens, double *c_out,
+                       hipStream_t st);
+
 // Tail.
 hipError_t fill_u32(void *p, size_t count, uint32_t v, hipStream_t st);
 hipError_t tail_kernel_from_counts(int n, const uint32_t *counts, uint32_t R, double eta, double *Q, double *r,

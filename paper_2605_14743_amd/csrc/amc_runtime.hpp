@@ -42,6 +42,15 @@ struct Plan {
     uint32_t scratch_words = 0;     // per-workgroup global scratch (block and L2 modes)
 };
 
+// Private copies of the arrays a query points to (inputs are never retained):
+// capture() copies them and redirects the query's pointers to the copies.
+struct QueryInputs {
+    std::vector<double> s, reward, gamma;
+    std::vector<int32_t> pool, fb_set;
+    std::vector<uint32_t> dbg;
+    void capture(amc_query &q, int n);
+};
+
 struct Server;
 
 // Shape key of the autotuner cache: n, m, weight law, largest weight.

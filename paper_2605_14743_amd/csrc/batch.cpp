@@ -235,6 +235,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         }
         for (int i : G.members) {
             b->runs[i]->launches = 1;
+            if (rc == AMC_OK) rc = qr_enqueue_post(*b->runs[i], st);
             if (rc == AMC_OK) rc = qr_enqueue_tail(*b->runs[i], st, false);
         }
     }

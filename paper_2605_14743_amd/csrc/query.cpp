@@ -48,23 +48,7 @@ int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, 
         R.md.p_fail_edge = R.p_fail_edge.data();
     }
     R.q = *q;
-    const int n = g->n;
-    if (q->s) {
-        R.s.assign(q->s, q->s + n);
-        R.q.s = R.s.data();
-    }
-    if (q->reward) {
-        R.reward.assign(q->reward, q->reward + n);
-        R.q.reward = R.reward.data();
-    }
-    if (q->pool_size > 0) {
-        R.pool.assign(q->pool, q->pool + q->pool_size);
-        R.q.pool = R.pool.data();
-    }
-    if (q->n_debug > 0) {
-        R.dbg.assign(q->debug_pairs, q->debug_pairs + 2 * q->n_debug);
-        R.q.debug_pairs = R.dbg.data();
-    }
+    R.in.capture(R.q, g->n);
     RCHK(plan(ctx, g, &R.md, &R.q, &R.pl));
     R.eta = q->floor_eta < 0.0 ? 0.1 / std::sqrt((double)q->R) : q->floor_eta;
     return AMC_OK;
@@ -120,7 +104,7 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
     RCHK(A.alloc(4 * cnt, &p)); P.counts = (uint32_t *)p;
     if (q->pool_size > 0) {
         RCHK(A.alloc(4 * cnt, &p));
-        P.counts_w = (uint32_t *)p;
+        R.cw = (uint32_t *)p;
     }
     if (q->flags & AMC_WANT_CENTER) {
         RCHK(A.alloc(4 * (size_t)Rn, &p));
@@ -131,7 +115,7 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
         P.next_table = (int32_t *)p;
         if (q->pool_size > 0) {
             RCHK(A.alloc(4 * (size_t)Rn * n, &p));
-            P.next_table_w = (int32_t *)p;
+            R.ntw = (int32_t *)p;
         }
     }
     if (q->flags & AMC_WANT_BSUM) {
@@ -142,7 +126,25 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
     RCHK(A.alloc(16, &p)); R.d_err = (int *)p;
     P.err = R.d_err;
     RCHK(A.alloc(16, &p)); R.work_ctr = (unsigned int *)p;
-    if (R.pl.tiles_per_r > 1) {
+    // with k = infinity the sweep applies the pool selector itself; with a
+    // finite k the Top-k stage does, from the B(H_r) rows the sweep keeps
+    if (q->topk == 0) {
+        P.counts_w = R.cw;
+        P.next_table_w = R.ntw;
+    } else {
+        P.keep_rows = 1;
+        RCHK(A.alloc(8 * (size_t)n, &p)); R.T.psi = (double *)p;
+        RCHK(A.alloc(8 * (size_t)n, &p)); R.T.psi_hat = (double *)p;
+        if (q->pool_size > 0) {
+            RCHK(A.alloc(8 * (size_t)n, &p)); R.T.psi_w = (double *)p;
+            RCHK(A.alloc(8 * (size_t)n, &p)); R.T.psi_w_hat = (double *)p;
+        }
+        if (q->gamma) {
+            RCHK(dev_copy_in(A, q->gamma, 8 * (size_t)n, st, &p));
+            R.T.gamma = (double *)p;
+        }
+    }
+    if (R.pl.tiles_per_r > 1 || P.keep_rows) {
         RCHK(A.alloc(8 * (size_t)Rn * n, &p)); P.Bg = (double *)p;
         RCHK(A.alloc(4 * (size_t)Rn * n, &p)); P.compg = (int32_t *)p;
         RCHK(A.alloc(4 * (size_t)Rn * n, &p)); P.sizeg = (int32_t *)p;
@@ -200,6 +202,31 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
             RCHK(A.alloc(8 * pairs, &p)); T.sharp = (double *)p;
             RCHK(A.alloc(8 * pairs, &p)); T.sharp_supp = (double *)p;
         }
+        if (q->topk > 0) {
+            RCHK(A.alloc(8 * 8, &p));
+            T.scal_k = (double *)p;
+        }
+        if (q->flags & AMC_FALLBACK) {
+            std::vector<uint8_t> fm((size_t)n, 0);
+            fm[q->fb_node] = 1;
+            for (int k = 0; k < q->fb_set_size; ++k) fm[q->fb_set[k]] = 1;
+            RCHK(dev_copy_in(A, fm.data(), (size_t)n, st, &p));
+            T.fb_mask = (uint8_t *)p;
+            HIPCHK(hipStreamSynchronize(st));   // fm is a local vector
+            RCHK(A.alloc(4 * (size_t)n * (n + 1), &p)); T.counts_fb = (uint32_t *)p;
+            RCHK(A.alloc(8 * nn, &p)); T.Qf = (double *)p;
+            RCHK(A.alloc(8 * nn, &p)); T.Nf = (double *)p;
+            RCHK(A.alloc(8 * (size_t)n, &p)); T.rf = (double *)p;
+            RCHK(A.alloc(8 * (size_t)n, &p)); T.muf = (double *)p;
+            RCHK(A.alloc(8 * (size_t)n, &p)); T.bf = (double *)p;
+            RCHK(A.alloc(8 * (size_t)n, &p)); T.bcens = (double *)p;
+            RCHK(A.alloc(8 * 8, &p)); T.scal_f = (double *)p;
+            RCHK(A.alloc(4 * 16, &p)); T.top_f = (int32_t *)p;
+            if (!T.scal_k) {
+                RCHK(A.alloc(8 * 8, &p));
+                T.scal_k = (double *)p;
+            }
+        }
         if (q->pool_size > 0) {
             RCHK(A.alloc(8 * nn, &p)); T.Qw = (double *)p;
             RCHK(A.alloc(8 * nn, &p)); T.Nw = (double *)p;
@@ -224,7 +251,9 @@ int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
     const uint32_t Rn = R.q.R;
     const size_t cnt = (size_t)n * (n + 1);
     HIPCHK(fill_u32(P.counts, cnt, 0u, st));
-    if (P.counts_w) HIPCHK(fill_u32(P.counts_w, cnt, 0u, st));
+    if (R.cw) HIPCHK(fill_u32(R.cw, cnt, 0u, st));
+    if (R.T.psi) HIPCHK(fill_u32(R.T.psi, 2 * (size_t)n, 0u, st));
+    if (R.T.psi_w) HIPCHK(fill_u32(R.T.psi_w, 2 * (size_t)n, 0u, st));
     if (P.bsum) HIPCHK(fill_u32(P.bsum, 2 * (size_t)n, 0u, st));
     HIPCHK(fill_u32(P.stats, 16, 0u, st));
     HIPCHK(fill_u32(R.d_err, 4, 0u, st));
@@ -289,6 +318,39 @@ static int tail_chain(int n, const uint32_t *d_counts, uint32_t Rn, double eta, 
     return AMC_OK;
 }
 
+// Finite-k Top-k stage (after the sweep): ranks every realization's
+// components and accumulates the step rewards and the pool selector.
+int qr_enqueue_post(QueryRun &R, hipStream_t st) {
+    if (!R.g || R.q.topk == 0) return AMC_OK;
+    const SweepParams &P = R.P;
+    TopkArgs A;
+    A.n = R.g->n;
+    A.R = R.q.R;
+    A.r_begin = R.q.r_begin;
+    A.key0 = P.key0;
+    A.key1 = P.key1;
+    A.t_alpha = P.t_alpha;
+    A.k_min = P.k_min;
+    A.tau = P.tau;
+    A.topk = R.q.topk;
+    A.Bg = P.Bg;
+    A.compg = P.compg;
+    A.sizeg = P.sizeg;
+    A.pool = P.pool;
+    A.gamma = R.T.gamma;
+    A.psi = R.T.psi;
+    A.psi_w = R.T.psi_w;
+    A.counts_w = R.cw;
+    A.next_table_w = R.ntw;
+    const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)R.ctx->max_lds / std::max<uint32_t>(topk_lds(A.n), 1u));
+    const int blocks = (int)std::min<uint64_t>(A.R, (uint64_t)R.ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
+    HIPCHK(launch_topk_reduce(A, blocks, st));
+    // estimated expected step rewards: the sums over the R draws / R
+    HIPCHK(tail_div(A.n, R.T.psi, (double)A.R, R.T.psi_hat, st));
+    if (R.T.psi_w) HIPCHK(tail_div(A.n, R.T.psi_w, (double)A.R, R.T.psi_w_hat, st));
+    return AMC_OK;
+}
+
 int qr_enqueue_tail(QueryRun &R, hipStream_t st, bool from_Q) {
     if (R.q.flags & AMC_SKIP_TAIL) return AMC_OK;
     TailBufs &T = R.T;
@@ -298,10 +360,22 @@ int qr_enqueue_tail(QueryRun &R, hipStream_t st, bool from_Q) {
                     q.cert_topk, T.top, T.scal, R.d_err, from_Q, st));
     HIPCHK(tail_certificates(n, q.cert_topk, T.Q, T.N, T.mu, T.top, T.cv, q.eps, q.r_lower, T.gap, T.sharp,
                              T.sharp_supp, T.support, st));
-    if (R.P.counts_w && R.P.pool) {   // constrained kernel P^W (Section 7), same pipeline
-        HIPCHK(tail_xi(n, R.P.counts_w, q.R, T.xi, st));
-        RCHK(tail_chain(n, R.P.counts_w, q.R, R.eta, T.Qw, T.rw, T.Nw, T.muw, T.bw, T.s, T.f, R.P.pool, T.bbar, 0.0,
+    if (R.cw && R.P.pool) {   // constrained kernel P^W (Section 7), same pipeline
+        HIPCHK(tail_xi(n, R.cw, q.R, T.xi, st));
+        RCHK(tail_chain(n, R.cw, q.R, R.eta, T.Qw, T.rw, T.Nw, T.muw, T.bw, T.s, T.f, R.P.pool, T.bbar, 0.0,
                         0, T.top_w, T.scal_w, R.d_err, false, st));
+    }
+    // reward-AFCs of the Top-k step rewards (Sections 6.2-6.3)
+    if (R.g && q.topk > 0) {
+        HIPCHK(tail_reward_afc(n, T.mu, T.scal, T.psi_hat, &T.scal_k[0], st));
+        if (T.psi_w_hat) HIPCHK(tail_reward_afc(n, T.mu, T.scal, T.psi_w_hat, &T.scal_k[1], st));
+    }
+    // fallback kernel P^{W,fb} (Section 7.3) and the censored profile (Section 7.4)
+    if (T.counts_fb) {
+        HIPCHK(tail_fb_counts(n, R.P.counts, R.cw, q.fb_node, T.counts_fb, st));
+        RCHK(tail_chain(n, T.counts_fb, q.R, R.eta, T.Qf, T.rf, T.Nf, T.muf, T.bf, T.s, T.f, R.P.pool, nullptr, 0.0,
+                        0, T.top_f, T.scal_f, R.d_err, false, st));
+        HIPCHK(tail_censor(n, T.bf, T.fb_mask, T.bcens, &T.scal_k[2], st));
     }
     return AMC_OK;
 }
@@ -321,11 +395,13 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
     if (R.g) {
         const size_t cnt = (size_t)n * (n + 1);
         RCHK(copy_out(out->counts, P.counts, 4 * cnt, st));
-        if (P.counts_w) RCHK(copy_out(out->counts_w, P.counts_w, 4 * cnt, st));
+        if (R.cw) RCHK(copy_out(out->counts_w, R.cw, 4 * cnt, st));
         if (P.center_global) RCHK(copy_out(out->center_global, P.center_global, 4 * (size_t)Rn, st));
         if (P.next_table) RCHK(copy_out(out->next_table, P.next_table, 4 * (size_t)Rn * n, st));
-        if (P.next_table_w) RCHK(copy_out(out->next_table_w, P.next_table_w, 4 * (size_t)Rn * n, st));
+        if (R.ntw && out->next_table_w) RCHK(copy_out(out->next_table_w, R.ntw, 4 * (size_t)Rn * n, st));
         if (P.bsum) RCHK(copy_out(out->bsum, P.bsum, 8 * (size_t)n, st));
+        if (R.T.psi_hat && out->psi) RCHK(copy_out(out->psi, R.T.psi_hat, 8 * (size_t)n, st));
+        if (R.T.psi_w_hat && out->psi_w) RCHK(copy_out(out->psi_w, R.T.psi_w_hat, 8 * (size_t)n, st));
         if (P.dbg_dist) {
             RCHK(copy_out(out->dbg_dist, P.dbg_dist, 4 * (size_t)q.n_debug * n, st));
             RCHK(copy_out(out->dbg_sigma, P.dbg_sigma, 8 * (size_t)q.n_debug * n, st));
@@ -372,7 +448,23 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
             RCHK(copy_out(out->xi, T.xi, 8 * (size_t)n, st));
             RCHK(copy_out(hw, T.scal_w, 8 * 4, st));
         }
+        double hk[8] = {0}, hf[8] = {0};
+        if (T.scal_k) RCHK(copy_out(hk, T.scal_k, 8 * 4, st));
+        if (T.counts_fb) {
+            if (out->b_fb) RCHK(copy_out(out->b_fb, T.bf, 8 * (size_t)n, st));
+            if (out->b_cens) RCHK(copy_out(out->b_cens, T.bcens, 8 * (size_t)n, st));
+            RCHK(copy_out(hf, T.scal_f, 8 * 4, st));
+        }
         HIPCHK(hipStreamSynchronize(st));
+        if (R.g && q.topk > 0) {
+            out->b_k = hk[0];
+            out->b_kw = T.psi_w_hat ? hk[1] : 0.0;
+        }
+        if (T.counts_fb) {
+            out->E_T_fb = hf[0];
+            out->m_w_fb = hf[2];
+            out->c_fb = hk[2];
+        }
         out->E_T = hs[0];
         out->b_f = q.reward ? hs[1] : 0.0;
         out->admissible = hs[3] > 0.5 ? 1 : 0;
@@ -401,6 +493,7 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
               hipStream_t st) {
     if (!out || !out->counts) return AMC_E_INVALID_ARG;
     if (q && q->pool_size > 0 && !out->counts_w) return AMC_E_INVALID_ARG;
+    if (q && q->topk > 0 && (!out->psi || (q->pool_size > 0 && !out->psi_w))) return AMC_E_INVALID_ARG;
     QueryRun R;
     RCHK(qr_init(R, ctx, g, md, q));
     struct Guard {
@@ -409,25 +502,29 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
         ~Guard() { qr_release(r, s); }
     } guard{R, st};
     RCHK(qr_alloc(R, st));
-    hipEvent_t ev[3];
+    hipEvent_t ev[4];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
-            for (int k = 0; k < 3; ++k) (void)hipEventDestroy(e[k]);
+            for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
         }
     } evg{ev};
     RCHK(qr_enqueue_reset(R, st));
     HIPCHK(hipEventRecord(ev[0], st));
     RCHK(qr_enqueue_sweep(R, st));
     HIPCHK(hipEventRecord(ev[1], st));
-    RCHK(qr_enqueue_tail(R, st, false));
+    RCHK(qr_enqueue_post(R, st));
     HIPCHK(hipEventRecord(ev[2], st));
+    RCHK(qr_enqueue_tail(R, st, false));
+    HIPCHK(hipEventRecord(ev[3], st));
     RCHK(qr_finish(R, out, st));
-    float ms_sweep = 0.f, ms_tail = 0.f;
+    float ms_sweep = 0.f, ms_post = 0.f, ms_tail = 0.f;
     HIPCHK(hipEventElapsedTime(&ms_sweep, ev[0], ev[1]));
-    HIPCHK(hipEventElapsedTime(&ms_tail, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&ms_post, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&ms_tail, ev[2], ev[3]));
     out->stats.sweep_ms = ms_sweep;
+    out->stats.topk_ms = q->topk > 0 ? ms_post : 0.0;
     out->stats.tail_ms = (q->flags & AMC_SKIP_TAIL) ? 0.0 : ms_tail;
     return AMC_OK;
 }
@@ -471,8 +568,9 @@ extern "C" int amc_chain(amc_ctx *ctx, int32_t n, const double *Q, const amc_que
     R.ctx = ctx;
     R.n_chain = n;
     R.q = *q;
-    R.q.flags &= ~(uint32_t)AMC_SKIP_TAIL;
+    R.q.flags &= ~(uint32_t)(AMC_SKIP_TAIL | AMC_FALLBACK);
     R.q.pool_size = 0;
+    R.q.topk = 0;
     R.q.R = 1;
     struct Guard {
         QueryRun &r;

@@ -18,6 +18,15 @@ struct TailBufs {
     double *Qw = nullptr, *Nw = nullptr, *rw = nullptr, *muw = nullptr, *bw = nullptr, *bbar = nullptr;
     double *xi = nullptr, *scal_w = nullptr;
     int32_t *top_w = nullptr;
+    // finite-k Top-k rewards and the fallback kernel P^{W,fb}
+    double *psi = nullptr, *psi_w = nullptr;      // sums over draws (sweep stage)
+    double *gamma = nullptr;
+    double *psi_hat = nullptr, *psi_w_hat = nullptr, *scal_k = nullptr;
+    uint32_t *counts_fb = nullptr;
+    uint8_t *fb_mask = nullptr;
+    double *Qf = nullptr, *Nf = nullptr, *rf = nullptr, *muf = nullptr, *bf = nullptr, *bcens = nullptr;
+    double *scal_f = nullptr;
+    int32_t *top_f = nullptr;
 };
 
 struct QueryRun {
@@ -26,9 +35,8 @@ struct QueryRun {
     int n_chain = 0;                       // amc_chain: size of the given kernel
     amc_model md{};
     amc_query q{};
-    std::vector<double> p_fail_edge, s, reward;
-    std::vector<int32_t> pool;
-    std::vector<uint32_t> dbg;
+    std::vector<double> p_fail_edge;
+    QueryInputs in;
     std::vector<uint64_t> t_fail_edge;
     std::vector<uint8_t> mask;
     Plan pl;
@@ -42,6 +50,8 @@ struct QueryRun {
     uint32_t bscratch_words = 0;
     int *d_err = nullptr;
     int launches = 0;
+    uint32_t *cw = nullptr;                // pool-selector counts (sweep or Top-k stage)
+    int32_t *ntw = nullptr;                // pool-selector table
     TailBufs T;
 };
 
@@ -49,6 +59,7 @@ int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, 
 int qr_alloc(QueryRun &R, hipStream_t st);
 int qr_enqueue_reset(QueryRun &R, hipStream_t st);
 int qr_enqueue_sweep(QueryRun &R, hipStream_t st);
+int qr_enqueue_post(QueryRun &R, hipStream_t st);
 int qr_enqueue_tail(QueryRun &R, hipStream_t st, bool from_Q);
 int qr_finish(QueryRun &R, amc_result *out, hipStream_t st);
 void qr_release(QueryRun &R, hipStream_t st);

@@ -34,9 +34,7 @@ struct Request {
     amc_model model{};
     std::vector<double> p_fail_edge;
     amc_query q{};
-    std::vector<double> s, reward;
-    std::vector<int32_t> pool;
-    std::vector<uint32_t> dbg;
+    QueryInputs in;
     amc_result *out = nullptr;
     uint64_t footprint = 0;
     int status = AMC_E_NOT_READY;
@@ -159,6 +157,7 @@ extern "C" int amc_submit(amc_ctx *ctx, const amc_graph *g, const amc_model *mod
     int rc = validate(g, model, q);
     if (rc != AMC_OK) return rc;
     if (!out->counts || (q->pool_size > 0 && !out->counts_w)) return AMC_E_INVALID_ARG;
+    if (q->topk > 0 && (!out->psi || (q->pool_size > 0 && !out->psi_w))) return AMC_E_INVALID_ARG;
     auto r = std::make_shared<Request>();
     r->ctx = ctx;
     r->g = g;
@@ -168,23 +167,7 @@ extern "C" int amc_submit(amc_ctx *ctx, const amc_graph *g, const amc_model *mod
         r->model.p_fail_edge = r->p_fail_edge.data();
     }
     r->q = *q;
-    const int n = g->n;
-    if (q->s) {
-        r->s.assign(q->s, q->s + n);
-        r->q.s = r->s.data();
-    }
-    if (q->reward) {
-        r->reward.assign(q->reward, q->reward + n);
-        r->q.reward = r->reward.data();
-    }
-    if (q->pool_size > 0) {
-        r->pool.assign(q->pool, q->pool + q->pool_size);
-        r->q.pool = r->pool.data();
-    }
-    if (q->n_debug > 0) {
-        r->dbg.assign(q->debug_pairs, q->debug_pairs + 2 * q->n_debug);
-        r->q.debug_pairs = r->dbg.data();
-    }
+    r->in.capture(r->q, g->n);
     r->out = out;
     rc = amc_footprint(g, q, &r->footprint);
     if (rc != AMC_OK) return rc;

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         }
         __syncthreads();
         if (P.tiles_per_r == 1) {
-            reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+            reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats, true);
         } else {
             double *Bg = P.Bg + (size_t)r_local * n;
             for (int v = tid; v < n; v += nthr)
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
                                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __syncthreads();
-                reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats);
+                reduce_realization(P, r_local, r, rp, B, comp, csize, RS, red_f, red_i, acc_stats, false);
             }
             __syncthreads();
         }

@@ -94,7 +94,7 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, RP *r
 template <typename RP, typename CT, bool COH = false>
 __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local, uint32_t r, const RP *rp,
                                    const double *B, const CT *comp, const CT *csize, const ReduceScratch &S,
-                                   double *red_f, int *red_i, unsigned long long *acc_stats) {
+                                   double *red_f, int *red_i, unsigned long long *acc_stats, bool write_rows) {
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
     const int n = P.n;
     unsigned long long *cmax = S.cmax;   // B >= 0: max on the bit pattern
@@ -182,6 +182,14 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     }
     if (P.bsum)
         for (int v = tid; v < n; v += nthr) unsafeAtomicAdd(&P.bsum[v], ld_coh<COH>(&B[v]));
+    // B(H_r) and the labels for the finite-k Top-k stage (rows a split
+    // realization has already assembled there are left as they are)
+    if (P.keep_rows && write_rows)
+        for (int v = tid; v < n; v += nthr) {
+            P.Bg[(size_t)r_local * n + v] = ld_coh<COH>(&B[v]);
+            P.compg[(size_t)r_local * n + v] = (int32_t)ld_coh<COH>(&comp[v]);
+            P.sizeg[(size_t)r_local * n + v] = (int32_t)ld_coh<COH>(&csize[v]);
+        }
     acc_stats[0] += units;
     acc_stats[1] += s_nk;
     acc_stats[2] += s_ak;

@@ -610,14 +610,14 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             __syncthreads();
             if (!split) {
                 reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
-                                                       acc_stats);
+                                                       acc_stats, true);
             } else {
                 if (tid == 0) last_sh = (atomicAdd(&P.done[r_local], 1u) == (unsigned)(P.tiles_per_r - 1));
                 __syncthreads();
                 if (last_sh) {
                     __threadfence();
                     reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
-                                                           acc_stats);
+                                                           acc_stats, false);
                 }
                 __syncthreads();
             }
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
         __syncthreads();
 
         if (!split) {
-            reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats);
+            reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats, true);
         } else {
             // publish this tile's partial B and component labels; the last
             // tile of the realization to finish performs the reduction
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __syncthreads();
-                reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats);
+                reduce_realization(P, r_local, r, rp, B, comp16, csize16, RS, red_f, red_i, acc_stats, false);
             }
             __syncthreads();
         }

@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol include/amc.h declares
 (no compute call: these run on hosts without a GPU)."""
 import ctypes
+import ctypes as C
 import os
 import re
 import subprocess
@@ -43,26 +44,25 @@ def test_strerror_and_version_without_gpu():
 
 
 def test_struct_layouts_match_header():
-    """ctypes mirrors of the ABI structs have the sizes a C compiler gives."""
-    src = r'''
-#include <stdio.h>
-#include <stddef.h>
-#include "amc.h"
-int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(amc_model), sizeof(amc_query), sizeof(amc_stats), sizeof(amc_result));
-  printf("%zu %zu %zu\n", offsetof(amc_query, flags), offsetof(amc_result, E_T), offsetof(amc_result, stats));
-  return 0;
-}
-'''
+    """ctypes mirrors of the ABI structs have the sizes and field offsets a C compiler gives."""
+    structs = {"amc_model": amc.Model, "amc_query": amc.Query, "amc_stats": amc.Stats, "amc_result": amc.Result,
+               "amc_tune_result": amc.TuneResult}
+    lines = []
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"amc.h\"\nint main(void) {\n" + "\n".join(lines) + \
+        "\n  return 0;\n}\n"
     import tempfile
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "s")
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
-        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
-    sizes = [int(x) for x in lines[0].split()]
-    offs = [int(x) for x in lines[1].split()]
-    assert sizes == [ctypes.sizeof(amc.Model), ctypes.sizeof(amc.Query), ctypes.sizeof(amc.Stats),
-                     ctypes.sizeof(amc.Result)]
-    assert offs == [amc.Query.flags.offset, amc.Result.E_T.offset, amc.Result.stats.offset]
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(ln.split() for ln in out if ln.strip())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"

@@ -50,6 +50,8 @@ def mixed_items(ctx, count, R, seed=0):
                  cert_topk=3, flags=FLAGS)
         if k == 3:
             q["pool"] = np.arange(0, g.n, 7, dtype=np.int32)
+        if k == 5:                                   # finite-k Top-k rewards and selector
+            q.update(topk=3, pool=np.arange(1, g.n, 5, dtype=np.int32), gamma=np.linspace(0.5, 2.0, g.n))
         out.append((G, model, q))
     return out
 
@@ -59,6 +61,9 @@ def same(a, b, what):
         if key in a:
             assert np.array_equal(a[key], b[key]), f"{what}: {key}"
     assert np.allclose(a["bsum"], b["bsum"], rtol=1e-12, atol=0), f"{what}: bsum"
+    for key in ("psi", "psi_w"):
+        if key in a:
+            assert np.allclose(a[key], b[key], rtol=1e-12, atol=0), f"{what}: {key}"
     for key in ("b", "mu", "Q"):
         assert np.allclose(a[key], b[key], rtol=0, atol=1e-13 * max(1.0, np.abs(b[key]).max())), f"{what}: {key}"
     for key in ("units", "sum_nK", "sum_AK", "sum_DK"):
