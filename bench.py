@@ -70,17 +70,23 @@ def run_bench(args):
     q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
              r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group,
              pool=wl.pool, reward=wl.reward)
+    if args.topk > 0:
+        # finite-k local Top-k rows: a pool of 50 nodes with values U[0.5, 2]
+        pool = wl.pool if wl.pool is not None else W.pool(g.n, 50, 1)
+        gamma = wl.reward if wl.reward is not None else W.rewards(g.n, pool, 0.5, 2.0, 1)
+        q.update(topk=args.topk, pool=pool, gamma=gamma)
     model = wl.model()
     for _ in range(args.warmup):
         amc.run(ctx, G, model, **q)
     torch.cuda.synchronize()
-    sweep_ms, tail_ms = [], []
+    sweep_ms, tail_ms, topk_ms = [], [], []
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
         last = amc.run(ctx, G, model, **q)
         sweep_ms.append(last["stats"]["sweep_ms"])
         tail_ms.append(last["stats"]["tail_ms"])
+        topk_ms.append(last["stats"]["topk_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = last["stats"]
@@ -116,6 +122,14 @@ def run_bench(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": ab, "units_per_launch": st["units"]},
     }
+    if args.topk > 0:
+        # the Top-k stage reads every realization's B row and labels once
+        # (16 B per vertex) and adds one step reward per valid anchor
+        tk = float(np.mean(topk_ms))
+        tb = 16.0 * wl.R * g.n
+        out["topk_stage"] = {"k": args.topk, "pool": int(len(q["pool"])), "ms": tk, "bytes_read": tb,
+                             "GBps": tb / (tk * 1e-3) / 1e9, "b_k": last["b_k"], "b_kw": last["b_kw"],
+                             "share_of_step": tk / (dt / args.steps * 1e3)}
     if args.plain_R > 0:
         qp = dict(q, R=args.plain_R, flags=amc.PLAIN_LAUNCH | amc.SKIP_TAIL)
         amc.run(ctx, G, model, **qp)
@@ -150,16 +164,18 @@ def run_bench(args):
     print(json.dumps(out), flush=True)
 
 
+SWEEP_SOURCES = ("amc_dev.hpp", "sweep_common.hpp", "sweep_wave.hip")
+
+
 def kernel_source_digest() -> str:
-    """Digest of the HIP sources the sweep kernel is built from."""
+    """Digest of the sources the LDS-mode sweep kernel is built from."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_14743_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -286,6 +302,7 @@ def main():
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
+    ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true")
