@@ -94,6 +94,17 @@ class _TailOut(C.Structure):
                 ("ET_fb", C.c_double), ("m_w_fb", C.c_double), ("c_fb", C.c_double)]
 
 
+class _TrajQuery(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("episodes", C.c_int32), ("x0", C.POINTER(C.c_int32)), ("alpha", C.c_double),
+                ("k_min", C.c_uint32), ("tau", C.c_double), ("max_steps", C.c_int32), ("f", C.POINTER(C.c_double))]
+
+
+class _TrajOut(C.Structure):
+    _fields_ = [("lengths", C.POINTER(C.c_int32)), ("paths", C.POINTER(C.c_int32)),
+                ("visits", C.POINTER(C.c_uint64)), ("reward_f", C.c_double), ("switches", C.c_uint64),
+                ("total_steps", C.c_uint64), ("truncated", C.c_int32)]
+
+
 def _declare(L):
     P = C.POINTER
     L.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -122,6 +133,8 @@ def _declare(L):
                                       C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
     L.or_pair_certificate.restype = None
     L.or_tail.argtypes = [C.c_int32, P(C.c_uint32), P(C.c_uint32), C.c_uint32, P(_TailIn), P(_TailOut)]
+    L.or_trajectories.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32), P(_Model), P(_TrajQuery),
+                                  P(_TrajOut)]
 
 
 def _ptr(a, ctype):
@@ -284,6 +297,35 @@ def sweep(n, eu, ev, *, seed, R, r_begin=0, alpha=0.15, k_min=5, tau=1e-9, pool=
     st = list(o.stats)
     res["stats"] = {"units": st[0], "sum_nK": st[1], "sum_AK": st[2], "sum_DK": st[3], "near_band": st[4]}
     del keep, g_arr
+    return res
+
+
+def trajectories(n, eu, ev, *, seed, x0, alpha=0.15, k_min=5, tau=1e-9, max_steps=1024, f=None, want_paths=False,
+                 **model):
+    """Episodes of the network process (Section 4.3): lengths, visits, node-reward and switch totals."""
+    eu, ev = _edges(eu, ev)
+    mod, keep = _model(**model)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    E = len(x0)
+    q = _TrajQuery()
+    q.seed, q.episodes, q.x0 = int(seed), E, _ptr(x0, C.c_int32)
+    q.alpha, q.k_min, q.tau, q.max_steps = float(alpha), int(k_min), float(tau), int(max_steps)
+    fa = None
+    if f is not None:
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        q.f = _ptr(fa, C.c_double)
+    res = {"lengths": np.zeros(E, np.int32), "visits": np.zeros(n, np.uint64)}
+    o = _TrajOut()
+    o.lengths = _ptr(res["lengths"], C.c_int32)
+    o.visits = _ptr(res["visits"], C.c_uint64)
+    if want_paths:
+        res["paths"] = np.zeros((E, max_steps), np.int32)
+        o.paths = _ptr(res["paths"], C.c_int32)
+    _check(lib().or_trajectories(n, len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), C.byref(mod), C.byref(q),
+                                 C.byref(o)), "trajectories")
+    res.update(reward_f=float(o.reward_f), switches=int(o.switches), total_steps=int(o.total_steps),
+               truncated=int(o.truncated))
+    del keep, fa
     return res
 
 

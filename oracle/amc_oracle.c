@@ -145,8 +145,11 @@ typedef struct {
     const uint32_t *w0;          /* weights of OR_WEIGHT_FIXED              */
 } or_model;
 
-int or_realize(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
-               uint64_t seed, uint32_t r, uint8_t *alive, uint32_t *w)
+/* Realization with counter words (r, u, v, stream): stream 0 is the row-wise
+ * sweep's realization r; the trajectory simulator uses r = episode and
+ * stream = 2 + step (see or_trajectories). */
+static int or_realize_stream(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
+                             uint64_t seed, uint32_t r, uint32_t stream, uint8_t *alive, uint32_t *w)
 {
     int64_t e;
     uint32_t key[2];
@@ -156,7 +159,7 @@ int or_realize(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const
     for (e = 0; e < m; ++e) {
         uint32_t ctr[4], x[4];
         double p = mod->p_fail_edge ? mod->p_fail_edge[e] : mod->p_fail;
-        ctr[0] = r; ctr[1] = (uint32_t)eu[e]; ctr[2] = (uint32_t)ev[e]; ctr[3] = 0;
+        ctr[0] = r; ctr[1] = (uint32_t)eu[e]; ctr[2] = (uint32_t)ev[e]; ctr[3] = stream;
         or_philox4x32_10(ctr, key, x);
         alive[e] = ((uint64_t)x[0] >= or_prob_threshold(p)) ? 1 : 0;
         if (mod->weight_kind == OR_WEIGHT_UNIT) {
@@ -171,15 +174,27 @@ int or_realize(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const
     return OR_OK;
 }
 
-/* Exogenous stop coin of anchor i in realization r (Alg. 1: the draw omega
- * includes the stopping event; its probability is alpha). */
-int or_stop_coin(uint64_t seed, uint32_t r, int32_t i, double alpha)
+int or_realize(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
+               uint64_t seed, uint32_t r, uint8_t *alive, uint32_t *w)
+{
+    return or_realize_stream(n, m, eu, ev, mod, seed, r, 0u, alive, w);
+}
+
+/* Exogenous stop coin of anchor i (Alg. 1: the draw omega includes the
+ * stopping event; its probability is alpha), counter (r, i, 2^32-1, stream):
+ * stream 1 in the row-wise sweep, 2 + step on a trajectory. */
+static int or_stop_coin_stream(uint64_t seed, uint32_t r, int32_t i, uint32_t stream, double alpha)
 {
     uint32_t ctr[4], key[2], x[4];
     key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
-    ctr[0] = r; ctr[1] = (uint32_t)i; ctr[2] = 0xFFFFFFFFu; ctr[3] = 1u;
+    ctr[0] = r; ctr[1] = (uint32_t)i; ctr[2] = 0xFFFFFFFFu; ctr[3] = stream;
     or_philox4x32_10(ctr, key, x);
     return (uint64_t)x[0] < or_prob_threshold(alpha);
+}
+
+int or_stop_coin(uint64_t seed, uint32_t r, int32_t i, double alpha)
+{
+    return or_stop_coin_stream(seed, r, i, 1u, alpha);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -644,6 +659,108 @@ done:
     free(alive); free(member); free(w); free(dist); free(sigma); free(order); free(comp); free(size);
     free(cc); free(cw); free(B); free(delta); free(k_alive); free(k_deg);
     free(fw); free(ranked); free(gs); free(gw);
+    or_graph_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trajectory simulator (Section 4.3): episodes of the stochastic network    */
+/* process itself.  Episode e starts at X_0 = x0[e]; at step t the anchor    */
+/* X_t draws a fresh network state and stop coin, counters (e, u, v, 2 + t)  */
+/* for edge (u, v) and (e, X_t, 2^32-1, 2 + t) for the coin; the step is     */
+/* invalid (X_{t+1} = bottom) when the coin fires or |K(X_t;H)| < k_min,      */
+/* otherwise X_{t+1} = c_loc(X_t;H).  T = number of pre-absorption states.    */
+/* Outputs feed the length-biased estimators of Definition on length-biased   */
+/* sampling: visits(v) / sum T estimates b_v (Proposition on uniform-step     */
+/* equivalence), sum f(X_t) / sum T the node-reward AFC, and the switch count */
+/* the transition reward 1{X_{t+1} in V, X_{t+1} != X_t} (Section 6.4).       */
+/* Episodes that reach max_steps pre-absorption states are truncated.         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    int32_t episodes;
+    const int32_t *x0;           /* episodes                                  */
+    double alpha;
+    uint32_t k_min;
+    double tau;
+    int32_t max_steps;
+    const double *f;             /* node reward (length n) or NULL            */
+} or_traj_query;
+
+typedef struct {
+    int32_t *lengths;            /* episodes: T_e                             */
+    int32_t *paths;              /* episodes x max_steps (-1 past T_e) or NULL */
+    uint64_t *visits;            /* n                                         */
+    double reward_f;             /* sum over episodes and t < T of f(X_t)     */
+    uint64_t switches;
+    uint64_t total_steps;
+    int32_t truncated;
+} or_traj_out;
+
+int or_trajectories(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const or_model *mod,
+                    const or_traj_query *q, or_traj_out *out)
+{
+    or_graph g;
+    uint8_t *alive = NULL, *member = NULL;
+    uint32_t *w = NULL;
+    uint64_t *dist = NULL, *sigma = NULL;
+    int32_t *order = NULL, *comp = NULL, *size = NULL;
+    double *B = NULL, *delta = NULL;
+    int32_t e, v;
+    int unit = (mod->weight_kind == OR_WEIGHT_UNIT);
+    int rc = or_graph_init(&g, n, m, eu, ev);
+    if (rc != OR_OK) return rc;
+    alive = (uint8_t *)malloc((size_t)m + 1);
+    member = (uint8_t *)malloc((size_t)n);
+    w = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)m + 1));
+    dist = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    sigma = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    size = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    B = (double *)malloc(sizeof(double) * (size_t)n);
+    delta = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!alive || !member || !w || !dist || !sigma || !order || !comp || !size || !B || !delta) {
+        rc = OR_E_NOMEM;
+        goto done;
+    }
+    memset(out->visits, 0, sizeof(uint64_t) * (size_t)n);
+    out->reward_f = 0.0;
+    out->switches = 0;
+    out->total_steps = 0;
+    out->truncated = 0;
+    for (e = 0; e < q->episodes; ++e) {
+        int32_t x = q->x0[e], t = 0;
+        for (;;) {
+            int32_t nx = -1;
+            uint32_t stream = 2u + (uint32_t)t;
+            if (out->paths) out->paths[(size_t)e * q->max_steps + t] = x;
+            out->visits[x] += 1;
+            if (q->f) out->reward_f += q->f[x];
+            ++t;
+            if (!or_stop_coin_stream(q->seed, (uint32_t)e, x, stream, q->alpha)) {
+                or_realize_stream(n, m, eu, ev, mod, q->seed, (uint32_t)e, stream, alive, w);
+                rc = or_brandes_graph(&g, alive, w, unit, B, dist, sigma, order, delta);
+                if (rc != OR_OK) goto done;
+                or_components_graph(&g, alive, comp, size, order);
+                if ((uint32_t)size[x] >= q->k_min) {
+                    for (v = 0; v < n; ++v) member[v] = (comp[v] == comp[x]);
+                    nx = or_band_argmax(n, B, member, q->tau, NULL);
+                }
+            }
+            if (nx >= 0 && nx != x) out->switches += 1;
+            if (nx < 0) break;
+            if (t == q->max_steps) { out->truncated += 1; break; }
+            x = nx;
+        }
+        out->lengths[e] = t;
+        out->total_steps += (uint64_t)t;
+        if (out->paths)
+            for (v = t; v < q->max_steps; ++v) out->paths[(size_t)e * q->max_steps + v] = -1;
+    }
+done:
+    free(alive); free(member); free(w); free(dist); free(sigma); free(order); free(comp); free(size);
+    free(B); free(delta);
     or_graph_free(&g);
     return rc;
 }
