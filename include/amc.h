@@ -265,6 +265,49 @@ typedef struct amc_tune_result {
 AMC_API int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, uint32_t probe_R,
                      amc_tune_result *out);
 
+/* Trajectory simulator (Section 4.3): episodes of the network process itself.
+ * Episode e starts at x0[e]; at step t the anchor X_t draws its stop coin and
+ * a fresh network state from the Philox counters (e, X_t, 2^32-1, 2 + t) and
+ * (e, u, v, 2 + t) (disjoint from the row-wise counters), the step is invalid
+ * when the coin fires or |K(X_t;H)| < k_min (X_{t+1} = bottom), otherwise
+ * X_{t+1} = c_loc(X_t;H) with the same tie rule as amc_run.  T_e counts the
+ * pre-absorption states X_0 .. X_{T-1}; an episode reaching max_steps of them
+ * is cut there and counted as truncated.  The outputs give the length-biased
+ * estimators of the uniform-step equivalence: b_hat_v = visits_v / sum T
+ * estimates b_v(s) for s the law of x0, survival_t = #{T_e > t} / sum T the
+ * weights w_t of the survival-weighted decomposition, reward_f / sum T the
+ * node-reward AFC b . f, and switches / sum T the switching-rate reward.
+ * Runs in the LDS sweep mode only (AMC_E_UNSUPPORTED beyond it). */
+#define AMC_WANT_PATHS (1u << 0)
+typedef struct amc_traj_query {
+    uint64_t seed;
+    int32_t episodes;           /* >= 1                                       */
+    const int32_t *x0;          /* episodes start states in [0, n)            */
+    double alpha;               /* stop probability, in (0, 1]                */
+    uint32_t k_min;
+    double tie_tau;             /* < 0 selects 1e-9                           */
+    int32_t max_steps;          /* >= 1: cap on pre-absorption states          */
+    const double *f;            /* node reward (n, >= 0) or NULL               */
+    uint32_t flags;             /* AMC_WANT_PATHS                              */
+    int32_t group, waves;       /* LDS-mode vertex mapping / wavefronts, 0 = engine */
+} amc_traj_query;
+
+typedef struct amc_traj_result {
+    int32_t *lengths;           /* episodes: T_e (required)                   */
+    int32_t *paths;             /* episodes x max_steps, -1 past T_e (AMC_WANT_PATHS) */
+    uint64_t *visits;           /* n (required)                               */
+    double *b_hat;              /* n: visits / sum T                           */
+    double *survival;           /* max_steps: #{T_e > t} / sum T               */
+    double reward_f;            /* sum over episodes and t < T_e of f(X_t)     */
+    uint64_t switches;          /* steps with X_{t+1} in V and X_{t+1} != X_t  */
+    uint64_t total_steps;       /* sum T_e                                     */
+    uint64_t sources;           /* single-source passes run (throughput unit)  */
+    int32_t truncated;
+    double sweep_ms;            /* HIP-event time of the trajectory kernel     */
+} amc_traj_result;
+AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_traj_query *q,
+                             amc_traj_result *out);
+
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
  * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,

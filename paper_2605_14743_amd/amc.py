@@ -26,7 +26,8 @@ MAX_TOPK, MAX_TOPK_N = 64, 7000
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
-           "amc_batch_destroy", "amc_tune", "amc_chain", "amc_strerror", "amc_version"]
+           "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_chain", "amc_strerror", "amc_version"]
+WANT_PATHS = 1
 
 _P = C.POINTER
 
@@ -51,6 +52,19 @@ class Query(C.Structure):
                 ("tile", C.c_int32), ("waves", C.c_int32), ("group", C.c_int32), ("debug_pairs", _P(C.c_uint32)),
                 ("n_debug", C.c_int32), ("topk", C.c_int32), ("gamma", _P(C.c_double)), ("fb_node", C.c_int32),
                 ("fb_set", _P(C.c_int32)), ("fb_set_size", C.c_int32)]
+
+
+class TrajQuery(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("episodes", C.c_int32), ("x0", _P(C.c_int32)), ("alpha", C.c_double),
+                ("k_min", C.c_uint32), ("tie_tau", C.c_double), ("max_steps", C.c_int32), ("f", _P(C.c_double)),
+                ("flags", C.c_uint32), ("group", C.c_int32), ("waves", C.c_int32)]
+
+
+class TrajResult(C.Structure):
+    _fields_ = [("lengths", _P(C.c_int32)), ("paths", _P(C.c_int32)), ("visits", _P(C.c_uint64)),
+                ("b_hat", _P(C.c_double)), ("survival", _P(C.c_double)), ("reward_f", C.c_double),
+                ("switches", C.c_uint64), ("total_steps", C.c_uint64), ("sources", C.c_uint64),
+                ("truncated", C.c_int32), ("sweep_ms", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -121,6 +135,7 @@ def lib():
         L.amc_batch_destroy.argtypes = [vp]
         L.amc_batch_destroy.restype = None
         L.amc_tune.argtypes = [vp, vp, _P(Model), _P(Query), C.c_uint32, _P(TuneResult)]
+        L.amc_trajectories.argtypes = [vp, vp, _P(Model), _P(TrajQuery), _P(TrajResult)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -435,3 +450,38 @@ def footprint(graph: Graph, **query) -> int:
     b = C.c_uint64()
     _check(lib().amc_footprint(graph.h, C.byref(q), C.byref(b)), "amc_footprint")
     return int(b.value)
+
+
+def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0.15, k_min=5, tie_tau=-1.0,
+                 max_steps=1024, f=None, want_paths=False, group=0, waves=0) -> dict:
+    """amc_trajectories: episodes of the network process (Section 4.3) and the
+    length-biased estimators (b_hat, survival weights, node-reward total)."""
+    m, keep_m = make_model(**model)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    E = len(x0)
+    n = graph.n
+    q = TrajQuery()
+    q.seed, q.episodes, q.x0 = int(seed), E, _ptr(x0, C.c_int32)
+    q.alpha, q.k_min, q.tie_tau, q.max_steps = float(alpha), int(k_min), float(tie_tau), int(max_steps)
+    fa = None
+    if f is not None:
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        q.f = _ptr(fa, C.c_double)
+    q.flags = WANT_PATHS if want_paths else 0
+    q.group, q.waves = int(group), int(waves)
+    arr = {"lengths": np.zeros(E, np.int32), "visits": np.zeros(n, np.uint64), "b_hat": np.zeros(n),
+           "survival": np.zeros(max(int(max_steps), 1))}
+    if want_paths:
+        arr["paths"] = np.zeros((E, int(max_steps)), np.int32)
+    res = TrajResult()
+    types = {np.dtype(np.int32): C.c_int32, np.dtype(np.uint64): C.c_uint64, np.dtype(np.float64): C.c_double}
+    for key, a in arr.items():
+        setattr(res, key, _ptr(a, types[a.dtype]))
+    _check(lib().amc_trajectories(ctx.h, graph.h, C.byref(m), C.byref(q), C.byref(res)), "amc_trajectories")
+    out = dict(arr)
+    for key in ("reward_f", "sweep_ms"):
+        out[key] = float(getattr(res, key))
+    for key in ("switches", "total_steps", "sources", "truncated"):
+        out[key] = int(getattr(res, key))
+    del keep_m, fa
+    return out

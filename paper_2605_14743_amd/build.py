@@ -20,7 +20,7 @@ LIB = os.path.join(LIBDIR, "libamc.so")
 ARCH = "gfx950"
 
 SOURCES = ["amc_api.cpp", "query.cpp", "batch.cpp", "server.cpp", "tune.cpp", "sweep_wave.hip", "sweep_block.hip",
-           "tail.hip", "topk.hip"]
+           "tail.hip", "topk.hip", "traj.hip", "traj_host.cpp"]
 
 
 def hipcc() -> str:
@@ -38,7 +38,7 @@ def common_flags() -> list[str]:
 
 
 def _compile(src: str, obj_dir: str) -> str:
-    obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(obj_dir, src + ".o")
     cmd = [hipcc()] + common_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

@@ -95,7 +95,7 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
     (void)hipMemGetInfo(&free_b, &total_b);
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(free_b * 0.9);
     if (set_sweep_wave_attrs(c->max_lds) != hipSuccess || set_sweep_block_attrs(c->max_lds) != hipSuccess ||
-        set_topk_attrs(c->max_lds) != hipSuccess) {
+        set_topk_attrs(c->max_lds) != hipSuccess || set_traj_attrs(c->max_lds) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return AMC_E_HIP;

@@ -107,6 +107,22 @@ struct TopkArgs {
     int32_t *next_table_w;      // R x n or nullptr
 };
 
+// Trajectory simulator (one workgroup per episode).
+struct TrajArgs {
+    const SweepParams *desc;    // graph, law, key, k_min, tau, LDS carve-up (device)
+    int32_t episodes;
+    const int32_t *x0;          // episodes
+    int32_t max_steps;
+    const double *f;            // node reward (n) or nullptr
+    int32_t *lengths;           // episodes
+    int32_t *paths;             // episodes x max_steps or nullptr
+    unsigned long long *visits; // n
+    double *reward;             // sum of f(X_t)
+    unsigned long long *ctr;    // switches, total steps, truncated, sources run
+    unsigned int *work;
+    int *err;
+};
+
 // One sweep launch serves one or several queries: the launch's work items are
 // the concatenation of every query's (r, tile) items; item_start[q] is the
 // first item of query q (item_start[nq] = total).

@@ -26,6 +26,14 @@ hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, in
 hipError_t set_sweep_wave_attrs(int max_lds);
 hipError_t set_sweep_block_attrs(int max_lds);
 
+// Trajectory simulator (LDS mode only).
+hipError_t set_traj_attrs(int max_lds);
+hipError_t launch_traj(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                       uint32_t lds, hipStream_t st);
+hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,
+                          const unsigned long long *visits, const unsigned long long *ctr, uint32_t *hist,
+                          double *b_hat, double *survival, hipStream_t st);
+
 // Finite-k Top-k stage and its tail pieces.
 hipError_t set_topk_attrs(int max_lds);
 uint32_t topk_lds(int n);

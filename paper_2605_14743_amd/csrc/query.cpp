@@ -54,14 +54,16 @@ int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, 
     return AMC_OK;
 }
 
-int qr_alloc(QueryRun &R, hipStream_t st) {
+// The descriptor fields every sweep-like launch reads: base graph, network
+// law, key, anchor rules and the planned carve-up (uploads the per-edge
+// thresholds and the pool mask).
+int qr_fill_desc(QueryRun &R, hipStream_t st) {
     DevArena &A = R.A;
     A.stream = st;
     A.async = R.ctx->async_alloc;
     const amc_graph *g = R.g;
     const amc_query *q = &R.q;
     const int n = g->n;
-    const uint32_t Rn = q->R;
     void *p;
     SweepParams &P = R.P;
     std::memset(&P, 0, sizeof(P));
@@ -100,6 +102,18 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
     P.adj_cap = R.pl.adj_cap;
     P.wave_bytes = R.pl.wave_bytes;
     P.shift = R.pl.shift;
+    return AMC_OK;
+}
+
+int qr_alloc(QueryRun &R, hipStream_t st) {
+    RCHK(qr_fill_desc(R, st));
+    DevArena &A = R.A;
+    const amc_graph *g = R.g;
+    const amc_query *q = &R.q;
+    const int n = g->n;
+    const uint32_t Rn = q->R;
+    void *p;
+    SweepParams &P = R.P;
     const size_t cnt = (size_t)n * (n + 1);
     RCHK(A.alloc(4 * cnt, &p)); P.counts = (uint32_t *)p;
     if (q->pool_size > 0) {

@@ -56,6 +56,7 @@ struct QueryRun {
 };
 
 int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q);
+int qr_fill_desc(QueryRun &R, hipStream_t st);
 int qr_alloc(QueryRun &R, hipStream_t st);
 int qr_enqueue_reset(QueryRun &R, hipStream_t st);
 int qr_enqueue_sweep(QueryRun &R, hipStream_t st);

@@ -48,14 +48,15 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint3
 // Realizes every base edge of realization r (Section 3.1) and builds the
 // compacted adjacency of H_r: rp[v] .. rp[v+1] index adj, each entry holds
 // (weight << shift) | neighbour.  `ew` is scratch for the per-edge weights
-// (0 = the edge failed).
+// (0 = the edge failed).  Edge (u, v) draws from counter (r, u, v, stream):
+// stream 0 for the row-wise sweep, 2 + step for a trajectory step.
 template <typename RP, typename ADJ>
 __device__ inline void stage_realization(const SweepParams &P, uint32_t r, RP *rp, ADJ *adj, uint32_t shift,
-                                         uint16_t *ew, uint32_t *scan_tmp) {
+                                         uint16_t *ew, uint32_t *scan_tmp, uint32_t stream = 0u) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int n = P.n;
     for (int64_t e = tid; e < P.m; e += nthr) {
-        const u32x4 x = philox10({r, (uint32_t)P.eu[e], (uint32_t)P.ev[e], 0u}, P.key0, P.key1);
+        const u32x4 x = philox10({r, (uint32_t)P.eu[e], (uint32_t)P.ev[e], stream}, P.key0, P.key1);
         const uint64_t t = P.t_fail_edge ? P.t_fail_edge[e] : P.t_fail;
         uint32_t w;
         if (P.weight_kind == 0) w = 1u;

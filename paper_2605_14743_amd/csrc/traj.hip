@@ -1,0 +1,222 @@
+// traj.hip -- trajectory simulator of the network process (Section 4.3).
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach".
+//
+// A persistent kernel whose work items are episodes.  One workgroup runs an
+// episode to absorption: at step t the anchor X_t draws its stop coin and a
+// fresh network state (counters (e, X_t, 2^32-1, 2 + t) and (e, u, v, 2 + t)),
+// the realized graph is staged in LDS, wavefront 0 runs the source X_t (which
+// also yields the component K(X_t;H)), and when |K| >= k_min every wavefront
+// takes further sources of K; the band maximiser of B over K is X_{t+1}.
+// Visits, lengths, node rewards and switches feed the length-biased
+// estimators of the uniform-step equivalence.
+#include "amc_dev.hpp"
+#include "amc_kernels.hpp"
+#include "sweep_common.hpp"
+#include "wave_source.hpp"
+
+namespace amc {
+
+template <bool WEIGHTED, int G, typename ADJ>
+__global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ uint32_t scan_tmp[kMaxWaves];
+    __shared__ uint32_t wctr[kMaxWaves];
+    __shared__ double red_f[kMaxWaves];
+    __shared__ int red_i[kMaxWaves];
+    __shared__ int ep_sh, size_sh, nx_sh;
+
+    const SweepParams &P = *T.desc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6, nt = blockDim.x;
+    const int n = P.n;
+    const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+    ADJ *rp = (ADJ *)(smem + L.rp);
+    ADJ *adj = (ADJ *)(smem + L.adj);
+    double *B = (double *)(smem + L.B);
+    uint16_t *list = (uint16_t *)(smem + L.comp);        // K(X_t;H), in wavefront 0's visit order
+    unsigned char *wbase = smem + L.waves;
+    unsigned char *wmine = wbase + wave * P.wave_bytes;
+    const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
+    uint32_t *dist = (uint32_t *)wmine;
+    unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
+    uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+    uint16_t *aux = ord + n;
+
+    bool ovf = false;
+    double rew = 0.0;
+    unsigned long long sw = 0, tot = 0, trunc = 0, units = 0;
+    for (;;) {
+        if (tid == 0) ep_sh = (int)atomicAdd(T.work, 1u);
+        __syncthreads();
+        const int e = ep_sh;
+        __syncthreads();
+        if (e >= T.episodes) break;
+        int x = T.x0[e];
+        int t = 0;
+        for (;;) {
+            if (tid == 0) {                                  // X_t is a pre-absorption state
+                atomicAdd(&T.visits[x], 1ull);
+                if (T.f) rew += T.f[x];
+                if (T.paths) T.paths[(size_t)e * T.max_steps + t] = x;
+            }
+            ++t;
+            const uint32_t stream = 2u + (uint32_t)(t - 1);
+            const u32x4 c = philox10({(uint32_t)e, (uint32_t)x, 0xFFFFFFFFu, stream}, P.key0, P.key1);
+            int nx = -1;
+            if ((uint64_t)c.x >= P.t_alpha) {                // no stop: a fresh network state
+                stage_realization(P, (uint32_t)e, rp, adj, P.shift, (uint16_t *)wbase, scan_tmp, stream);
+                for (int v = tid; v < n; v += nt) B[v] = 0.0;
+                __syncthreads();
+                if (wave == 0) {
+                    int cs = 0, sz = 0;
+                    run_source<WEIGHTED, G, ADJ, false>(P, rp, adj, P.shift, B, dist, sig, ord, aux, &wctr[0], x, -1,
+                                                        cs, sz, ovf);
+                    for (int k = lane; k < sz; k += 64) list[k] = ord[k];
+                    if (lane == 0) size_sh = sz;
+                }
+                __syncthreads();
+                const int sz = size_sh;
+                if ((uint32_t)sz >= P.k_min) {
+                    for (int k = 1 + wave; k < sz; k += nwaves) {
+                        int cs = 0, zz = 0;
+                        run_source<WEIGHTED, G, ADJ, false>(P, rp, adj, P.shift, B, dist, sig, ord, aux,
+                                                            &wctr[wave], (int)list[k], -1, cs, zz, ovf);
+                    }
+                    __syncthreads();
+                    // tie-broken maximiser of B over K(X_t;H) (eq. local-center)
+                    double mx = 0.0;
+                    for (int k = tid; k < sz; k += nt) mx = fmax(mx, B[list[k]]);
+                    mx = wave_max_f64(mx);
+                    if (lane == 0) red_f[wave] = mx;
+                    __syncthreads();
+                    mx = red_f[0];
+                    for (int w = 1; w < nwaves; ++w) mx = fmax(mx, red_f[w]);
+                    const double band = P.tau * (mx > 1.0 ? mx : 1.0);
+                    int best = 0x7FFFFFFF;
+                    for (int k = tid; k < sz; k += nt) {
+                        const int v = list[k];
+                        if (mx - B[v] <= band && v < best) best = v;
+                    }
+                    best = wave_min_i32(best);
+                    if (lane == 0) red_i[wave] = best;
+                    __syncthreads();
+                    if (tid == 0) {
+                        int b = red_i[0];
+                        for (int w = 1; w < nwaves; ++w) b = min(b, red_i[w]);
+                        nx_sh = b;
+                    }
+                    __syncthreads();
+                    nx = nx_sh;
+                    units += (unsigned long long)sz;
+                } else {
+                    units += 1ull;
+                }
+            }
+            if (tid == 0 && nx >= 0 && nx != x) sw += 1;
+            if (nx < 0) break;
+            if (t == T.max_steps) {
+                trunc += 1;
+                break;
+            }
+            x = nx;
+        }
+        if (tid == 0) {
+            T.lengths[e] = t;
+            tot += (unsigned long long)t;
+        }
+        if (T.paths)
+            for (int k = t + tid; k < T.max_steps; k += nt) T.paths[(size_t)e * T.max_steps + k] = -1;
+        __syncthreads();
+    }
+    const bool any_ovf = __ballot(ovf) != 0ull;
+    if (lane == 0 && any_ovf) atomicOr(T.err, 1);
+    if (tid == 0) {
+        if (T.f) global_add_f64(T.reward, rew);
+        atomicAdd(&T.ctr[0], sw);
+        atomicAdd(&T.ctr[1], tot);
+        atomicAdd(&T.ctr[2], trunc);
+        atomicAdd(&T.ctr[3], units);
+    }
+}
+
+// Length-biased estimators (Definition of the length-biased uniform step and
+// its corollary): b_v = visits_v / sum T, w_t = #{e : T_e > t} / sum T.
+__global__ void k_traj_hist(int episodes, const int32_t *lengths, uint32_t *hist) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < episodes) atomicAdd(&hist[lengths[e]], 1u);
+}
+
+__global__ void k_traj_estimates(int n, int max_steps, const unsigned long long *visits,
+                                 const unsigned long long *ctr, const uint32_t *hist, double *b_hat,
+                                 double *survival) {
+    const double tot = (double)ctr[1];
+    for (int v = threadIdx.x; v < n; v += blockDim.x) b_hat[v] = tot > 0.0 ? (double)visits[v] / tot : 0.0;
+    if (threadIdx.x == 0) {
+        // #{T_e > t} by a suffix sum of the length histogram (lengths <= max_steps)
+        unsigned long long above = 0;
+        for (int t = max_steps; t >= 1; --t) {
+            above += hist[t];
+            survival[t - 1] = tot > 0.0 ? (double)above / tot : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <bool W, int G, typename ADJ>
+static hipError_t launch_tt(const TrajArgs &T, int blocks, int waves, uint32_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((traj_kernel<W, G, ADJ>), dim3(blocks), dim3(64 * waves), lds, st, T);
+    return hipGetLastError();
+}
+
+template <bool W, typename ADJ>
+static hipError_t launch_tg(const TrajArgs &T, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
+    switch (group) {
+        case 1: return launch_tt<W, 1, ADJ>(T, blocks, waves, lds, st);
+        case 2: return launch_tt<W, 2, ADJ>(T, blocks, waves, lds, st);
+        case 3: return launch_tt<W, 3, ADJ>(T, blocks, waves, lds, st);
+        case 4: return launch_tt<W, 4, ADJ>(T, blocks, waves, lds, st);
+        case 16: return launch_tt<W, 16, ADJ>(T, blocks, waves, lds, st);
+        default: return launch_tt<W, 8, ADJ>(T, blocks, waves, lds, st);
+    }
+}
+
+template <bool W, typename ADJ>
+static hipError_t attrs_t(int max_lds) {
+    const void *ks[] = {(const void *)traj_kernel<W, 1, ADJ>, (const void *)traj_kernel<W, 2, ADJ>,
+                        (const void *)traj_kernel<W, 3, ADJ>, (const void *)traj_kernel<W, 4, ADJ>,
+                        (const void *)traj_kernel<W, 8, ADJ>, (const void *)traj_kernel<W, 16, ADJ>};
+    for (const void *k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t set_traj_attrs(int max_lds) {
+    hipError_t e;
+    if ((e = attrs_t<true, uint16_t>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_t<false, uint16_t>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_t<true, uint32_t>(max_lds)) != hipSuccess) return e;
+    return attrs_t<false, uint32_t>(max_lds);
+}
+
+hipError_t launch_traj(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                       uint32_t lds, hipStream_t st) {
+    if (adj_bytes == 2)
+        return weighted ? launch_tg<true, uint16_t>(T, group, blocks, waves, lds, st)
+                        : launch_tg<false, uint16_t>(T, group, blocks, waves, lds, st);
+    return weighted ? launch_tg<true, uint32_t>(T, group, blocks, waves, lds, st)
+                    : launch_tg<false, uint32_t>(T, group, blocks, waves, lds, st);
+}
+
+hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,
+                          const unsigned long long *visits, const unsigned long long *ctr, uint32_t *hist,
+                          double *b_hat, double *survival, hipStream_t st) {
+    hipLaunchKernelGGL(k_traj_hist, dim3((episodes + 255) / 256), dim3(256), 0, st, episodes, lengths, hist);
+    hipLaunchKernelGGL(k_traj_estimates, dim3(1), dim3(256), 0, st, n, max_steps, visits, ctr, hist, b_hat,
+                       survival);
+    return hipGetLastError();
+}
+
+}  // namespace amc

@@ -1,0 +1,148 @@
+// traj_host.cpp -- host side of the trajectory simulator (Section 4.3): argument
+// checks, the LDS-mode plan, device buffers, one persistent launch and the
+// length-biased estimators.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach".
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "amc_kernels.hpp"
+#include "query.hpp"
+
+using namespace amc;
+
+#define HIPCHK(expr)                          \
+    do {                                      \
+        if ((expr) != hipSuccess) {           \
+            (void)hipGetLastError();          \
+            return AMC_E_HIP;                 \
+        }                                     \
+    } while (0)
+#define RCHK(expr)                            \
+    do {                                      \
+        int rc_ = (expr);                     \
+        if (rc_ != AMC_OK) return rc_;        \
+    } while (0)
+
+extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_traj_query *tq,
+                                amc_traj_result *out) {
+    if (!ctx || !g || g->ctx != ctx || !model || !tq || !out || !out->lengths || !out->visits)
+        return AMC_E_INVALID_ARG;
+    const int n = g->n;
+    if (tq->episodes < 1 || !tq->x0 || tq->max_steps < 1 || (tq->flags & ~AMC_WANT_PATHS)) return AMC_E_INVALID_ARG;
+    if ((tq->flags & AMC_WANT_PATHS) && !out->paths) return AMC_E_INVALID_ARG;
+    for (int e = 0; e < tq->episodes; ++e)
+        if (tq->x0[e] < 0 || tq->x0[e] >= n) return AMC_E_INVALID_ARG;
+    if (tq->f)
+        for (int v = 0; v < n; ++v)
+            if (!(tq->f[v] >= 0.0) || !std::isfinite(tq->f[v])) return AMC_E_INVALID_ARG;
+    // the anchor rules and the sweep configuration go through the query checks
+    amc_query q;
+    std::memset(&q, 0, sizeof(q));
+    q.seed = tq->seed;
+    q.R = 1;
+    q.alpha = tq->alpha;
+    q.k_min = tq->k_min;
+    q.tie_tau = tq->tie_tau;
+    q.floor_eta = -1.0;
+    q.r_lower = 0.05;
+    q.flags = AMC_SKIP_TAIL;
+    q.mode = AMC_MODE_WAVE;
+    q.group = tq->group;
+    q.waves = tq->waves;
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return AMC_E_HIP;
+    hipStream_t st = ctx->stream;
+    QueryRun R;
+    RCHK(qr_init(R, ctx, g, model, &q));
+    struct Guard {
+        QueryRun &r;
+        hipStream_t s;
+        ~Guard() { qr_release(r, s); }
+    } guard{R, st};
+    RCHK(qr_fill_desc(R, st));
+    DevArena &A = R.A;
+    const int E = tq->episodes, S = tq->max_steps;
+    void *p;
+    TrajArgs T;
+    std::memset(&T, 0, sizeof(T));
+    RCHK(A.alloc(sizeof(SweepParams), &p));
+    HIPCHK(hipMemcpyAsync(p, &R.P, sizeof(SweepParams), hipMemcpyHostToDevice, st));
+    T.desc = (const SweepParams *)p;
+    T.episodes = E;
+    T.max_steps = S;
+    RCHK(A.alloc(4 * (size_t)E, &p));
+    HIPCHK(hipMemcpyAsync(p, tq->x0, 4 * (size_t)E, hipMemcpyHostToDevice, st));
+    T.x0 = (const int32_t *)p;
+    if (tq->f) {
+        RCHK(A.alloc(8 * (size_t)n, &p));
+        HIPCHK(hipMemcpyAsync(p, tq->f, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+        T.f = (const double *)p;
+    }
+    RCHK(A.alloc(4 * (size_t)E, &p)); T.lengths = (int32_t *)p;
+    if (tq->flags & AMC_WANT_PATHS) {
+        RCHK(A.alloc(4 * (size_t)E * S, &p));
+        T.paths = (int32_t *)p;
+    }
+    RCHK(A.alloc(8 * (size_t)n, &p)); T.visits = (unsigned long long *)p;
+    RCHK(A.alloc(8, &p)); T.reward = (double *)p;
+    RCHK(A.alloc(8 * 4, &p)); T.ctr = (unsigned long long *)p;
+    RCHK(A.alloc(16, &p)); T.work = (unsigned int *)p;
+    RCHK(A.alloc(16, &p)); T.err = (int *)p;
+    uint32_t *hist;
+    double *b_hat, *surv;
+    RCHK(A.alloc(4 * ((size_t)S + 1), &p)); hist = (uint32_t *)p;
+    RCHK(A.alloc(8 * (size_t)n, &p)); b_hat = (double *)p;
+    RCHK(A.alloc(8 * (size_t)S, &p)); surv = (double *)p;
+    HIPCHK(fill_u32(T.visits, 2 * (size_t)n, 0u, st));
+    HIPCHK(fill_u32(T.reward, 2, 0u, st));
+    HIPCHK(fill_u32(T.ctr, 8, 0u, st));
+    HIPCHK(fill_u32(T.work, 4, 0u, st));
+    HIPCHK(fill_u32(T.err, 4, 0u, st));
+    HIPCHK(fill_u32(hist, (size_t)S + 1, 0u, st));
+
+    const Plan &pl = R.pl;
+    const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl.lds, 1u));
+    const int blocks = (int)std::min<uint64_t>((uint64_t)E, (uint64_t)ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
+    hipEvent_t ev[2];
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    HIPCHK(hipEventRecord(ev[0], st));
+    HIPCHK(launch_traj(T, pl.weighted, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st));
+    HIPCHK(hipEventRecord(ev[1], st));
+    HIPCHK(traj_estimates(n, E, S, T.lengths, T.visits, T.ctr, hist, b_hat, surv, st));
+
+    int herr = 0;
+    unsigned long long hc[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(&herr, T.err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hc, T.ctr, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&out->reward_f, T.reward, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(out->lengths, T.lengths, 4 * (size_t)E, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(out->visits, T.visits, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    if (T.paths) HIPCHK(hipMemcpyAsync(out->paths, T.paths, 4 * (size_t)E * S, hipMemcpyDeviceToHost, st));
+    if (out->b_hat) HIPCHK(hipMemcpyAsync(out->b_hat, b_hat, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    if (out->survival) HIPCHK(hipMemcpyAsync(out->survival, surv, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr & 1) return AMC_E_SIGMA_OVERFLOW;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    if (!tq->f) out->reward_f = 0.0;
+    out->switches = hc[0];
+    out->total_steps = hc[1];
+    out->truncated = (int32_t)hc[2];
+    out->sources = hc[3];
+    out->sweep_ms = ms;
+    return AMC_OK;
+}

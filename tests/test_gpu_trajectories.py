@@ -1,0 +1,106 @@
+"""GPU parity of the trajectory simulator (Section 4.3) against the CPU oracle,
+through the C-ABI: episode paths, lengths, visits, switches, truncation and
+the survival weights bit-exact; the node-reward total within 1e-12."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14743_amd import amc
+from paper_2605_14743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = amc.Context(0)
+    yield c
+    c.close()
+
+
+def both(ctx, g, model, *, x0, seed=0, alpha=0.15, k_min=5, max_steps=64, f=None, **gq):
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
+    say(f"[gpu] trajectories n={g.n} E={len(x0)} max_steps={max_steps} {gq}")
+    try:
+        res = amc.trajectories(ctx, G, model, seed=seed, x0=x0, alpha=alpha, k_min=k_min, max_steps=max_steps, f=f,
+                               want_paths=True, **gq)
+    finally:
+        G.close()
+    om = dict(model)
+    if om.get("weight") == "fixed":
+        om["w0"] = g.w0
+    ref = O.trajectories(g.n, g.eu, g.ev, seed=seed, x0=x0, alpha=alpha, k_min=k_min, max_steps=max_steps, f=f,
+                         want_paths=True, **om)
+    return res, ref
+
+
+def check(res, ref, what):
+    assert np.array_equal(res["paths"], ref["paths"]), f"{what}: paths"
+    assert np.array_equal(res["lengths"], ref["lengths"]), f"{what}: lengths"
+    assert np.array_equal(res["visits"], ref["visits"]), f"{what}: visits"
+    for key in ("switches", "total_steps", "truncated"):
+        assert res[key] == ref[key], f"{what}: {key}"
+    tot = ref["total_steps"]
+    assert np.array_equal(res["b_hat"], ref["visits"] / tot), f"{what}: b_hat"
+    surv = np.array([(ref["lengths"] > t).sum() for t in range(len(res["survival"]))]) / tot
+    assert np.array_equal(res["survival"], surv), f"{what}: survival"
+    if ref["reward_f"]:
+        assert res["reward_f"] == pytest.approx(ref["reward_f"], rel=1e-12)
+
+
+@pytest.mark.parametrize("group", [0, 1, 3, 8])
+def test_er20_trajectories(ctx, group):
+    wl = W.config_er20()
+    g = wl.graph
+    x0 = np.arange(600) % g.n
+    f = np.linspace(0.5, 2.0, g.n)
+    res, ref = both(ctx, g, wl.model(), x0=x0, seed=11, f=f, group=group)
+    check(res, ref, f"er20 group {group}")
+    assert res["sources"] > res["total_steps"]
+
+
+def test_unit_weights_truncation_and_crossroads(ctx):
+    g = W.er_graph(60, 0.06, 3)
+    x0 = np.arange(300) % g.n
+    res, ref = both(ctx, g, {"p_fail": 0.05, "weight": "unit"}, x0=x0, seed=4, alpha=0.05, k_min=2, max_steps=6)
+    check(res, ref, "er60 unit, truncated")
+    assert res["truncated"] > 0
+    cr, pf = W.crossroads()
+    x0 = np.arange(2000) % cr.n
+    res, ref = both(ctx, cr, {"p_fail": 0.0, "p_fail_edge": pf, "weight": "unit"}, x0=x0, seed=8, alpha=0.1,
+                    k_min=3, max_steps=256)
+    check(res, ref, "crossroads")
+
+
+def test_ws1000_sampled_episodes(ctx):
+    wl = W.config_ws1000()
+    g = wl.graph
+    res, ref = both(ctx, g, wl.model(), x0=np.array([0, 17, 512, 999]), seed=wl.seed, alpha=wl.alpha,
+                    k_min=wl.k_min, max_steps=6)
+    check(res, ref, "ws1000")
+
+
+def test_trajectory_arguments(ctx):
+    g = W.er_graph(12, 0.4, 1)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    for bad in ({"x0": [0, 12]}, {"x0": [-1]}, {"x0": [1], "max_steps": 0}, {"x0": [1], "alpha": 0.0},
+                {"x0": [1], "f": -np.ones(12)}):
+        kw = dict(bad)
+        x0 = kw.pop("x0")
+        with pytest.raises(amc.AmcError) as ei:
+            amc.trajectories(ctx, G, {"p_fail": 0.1}, x0=x0, **kw)
+        assert ei.value.rc == amc.E_INVALID_ARG, bad
+    G.close()
+    big = W.config_er5000().graph                       # beyond the LDS mode
+    H = amc.Graph(ctx, big.n, big.eu, big.ev)
+    with pytest.raises(amc.AmcError) as ei:
+        amc.trajectories(ctx, H, {"p_fail": 0.1, "weight": "unit"}, x0=[0])
+    assert ei.value.rc == amc.E_UNSUPPORTED
+    H.close()
