@@ -164,7 +164,7 @@ def run_bench(args):
     print(json.dumps(out), flush=True)
 
 
-SWEEP_SOURCES = ("amc_dev.hpp", "sweep_common.hpp", "sweep_wave.hip")
+SWEEP_SOURCES = ("amc_dev.hpp", "sweep_common.hpp", "wave_source.hpp", "sweep_wave.hip")
 
 
 def kernel_source_digest() -> str:
@@ -247,6 +247,46 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_traj(args):
+    """Trajectory simulator (episodes of the network process, Section 4.3) on
+    the workload graph, with the row-wise b beside the length-biased b_hat."""
+    import torch
+
+    from paper_2605_14743_amd import amc
+    from paper_2605_14743_amd import workloads as W
+
+    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20}[args.workload]()
+    g = wl.graph
+    ctx = amc.Context(0)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
+    E = args.traj
+    x0 = np.arange(E) % g.n                                      # uniform s, stratified
+    kw = dict(seed=wl.seed + 1, x0=x0, alpha=wl.alpha, k_min=wl.k_min, max_steps=args.max_steps)
+    amc.trajectories(ctx, G, wl.model(), **dict(kw, x0=x0[:min(E, 256)]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = amc.trajectories(ctx, G, wl.model(), **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# trajectories: {E} episodes in {dt:.2f} s", file=sys.stderr, flush=True)
+    R = args.R or wl.R
+    row = amc.run(ctx, G, wl.model(), seed=wl.seed, R=R, alpha=wl.alpha, k_min=wl.k_min)
+    diff = np.abs(tr["b_hat"] - row["b"])
+    out = {
+        "metric": "episodes/sec", "value": E / dt, "unit": "episodes/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}-trajectories", "episodes": E, "max_steps": args.max_steps},
+        "kernel_ms": tr["sweep_ms"], "realization_sources_per_s": tr["sources"] / (tr["sweep_ms"] * 1e-3),
+        "steps": tr["total_steps"], "mean_T": tr["total_steps"] / E, "truncated": tr["truncated"],
+        "row_wise_R": R, "row_wise_E_T": row["E_T"],
+        "b_hat_vs_row_b": {"max_abs": float(diff.max()), "l1": float(diff.sum()),
+                           "b_row_max": float(row["b"].max())},
+    }
+    G.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args):
     """Poisson trace of mixed-size queries through amc_submit (continuous
     batching); reports throughput and p50/p99 latency."""
@@ -303,6 +343,8 @@ def main():
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
+    ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
+    ap.add_argument("--max-steps", dest="max_steps", type=int, default=512)
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true")
@@ -321,7 +363,9 @@ def main():
     if os.environ.get("WORLD_SIZE", "1") != "1":
         print("bench.py runs as a single process on one GPU", file=sys.stderr)
         sys.exit(2)
-    if args.serve:
+    if args.traj > 0:
+        run_traj(args)
+    elif args.serve:
         run_serve(args)
     elif args.batch:
         run_batch(args)
