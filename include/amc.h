@@ -69,6 +69,7 @@ extern "C" {
 #define AMC_WEIGHT_UNIT 0         /* every surviving edge has weight 1 (BFS)   */
 #define AMC_WEIGHT_UNIFORM_INT 1  /* integer weight uniform on [w_lo, w_hi]    */
 #define AMC_WEIGHT_FIXED 2        /* the graph's own integer weights w0        */
+#define AMC_WEIGHT_TABLE 3        /* per-call resampled weight from a per-edge law (Section 9.2) */
 
 /* --------------------------------------------------------- sweep mode */
 #define AMC_MODE_AUTO 0           /* pick from the shape (autotuner)           */
@@ -97,7 +98,12 @@ typedef struct amc_model {
     double p_fail;              /* failure probability of every edge, in [0,1]   */
     const double *p_fail_edge;  /* optional per-edge failure probabilities (m)   */
     int32_t weight_kind;        /* AMC_WEIGHT_*                                   */
-    uint32_t w_lo, w_hi;        /* AMC_WEIGHT_UNIFORM_INT: 1 <= w_lo <= w_hi <= 65535 */
+    uint32_t w_lo, w_hi;        /* AMC_WEIGHT_UNIFORM_INT: 1 <= w_lo <= w_hi <= 65535;
+                                   AMC_WEIGHT_TABLE: w_hi = w_max <= 255             */
+    /* AMC_WEIGHT_TABLE: m x w_max cumulative thresholds, row e nondecreasing with
+     * T[e][w_max-1] = 2^32; edge e of a realization weighs the smallest v in
+     * 1..w_max with x1 < T[e][v-1] (x1 the second word of its Philox block) */
+    const uint64_t *w_cdf;
 } amc_model;
 
 /* One estimation query (Alg. 2 plus the post-processing of Section 8.3). */

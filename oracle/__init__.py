@@ -22,8 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-WEIGHT_UNIT, WEIGHT_UNIFORM, WEIGHT_FIXED = 0, 1, 2
-_WEIGHT_KINDS = {"unit": WEIGHT_UNIT, "uniform": WEIGHT_UNIFORM, "fixed": WEIGHT_FIXED}
+WEIGHT_UNIT, WEIGHT_UNIFORM, WEIGHT_FIXED, WEIGHT_TABLE = 0, 1, 2, 3
+_WEIGHT_KINDS = {"unit": WEIGHT_UNIT, "uniform": WEIGHT_UNIFORM, "fixed": WEIGHT_FIXED, "table": WEIGHT_TABLE}
 
 OK, E_ARG, E_NOMEM, E_SIGMA, E_SINGULAR = 0, -1, -2, -4, -5
 
@@ -56,7 +56,8 @@ def lib():
 
 class _Model(C.Structure):
     _fields_ = [("p_fail", C.c_double), ("p_fail_edge", C.POINTER(C.c_double)), ("weight_kind", C.c_int32),
-                ("w_lo", C.c_uint32), ("w_hi", C.c_uint32), ("w0", C.POINTER(C.c_uint32))]
+                ("w_lo", C.c_uint32), ("w_hi", C.c_uint32), ("w0", C.POINTER(C.c_uint32)),
+                ("w_cdf", C.POINTER(C.c_uint64))]
 
 
 class _Query(C.Structure):
@@ -152,7 +153,7 @@ def _edges(eu, ev):
     return np.ascontiguousarray(eu, dtype=np.int32), np.ascontiguousarray(ev, dtype=np.int32)
 
 
-def _model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, w0=None, p_fail_edge=None):
+def _model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, w0=None, p_fail_edge=None, w_cdf=None):
     keep = []
     m = _Model()
     m.p_fail = float(p_fail)
@@ -166,6 +167,11 @@ def _model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, w0=None, p_fail_edge=None)
         ww = np.ascontiguousarray(w0, dtype=np.uint32)
         keep.append(ww)
         m.w0 = _ptr(ww, C.c_uint32)
+    if w_cdf is not None:
+        wc = np.ascontiguousarray(w_cdf, dtype=np.uint64)
+        keep.append(wc)
+        m.w_cdf = _ptr(wc, C.c_uint64)
+        m.w_hi = wc.shape[1]
     return m, keep
 
 

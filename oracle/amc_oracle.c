@@ -44,6 +44,7 @@
 #define OR_WEIGHT_UNIT 0
 #define OR_WEIGHT_UNIFORM 1
 #define OR_WEIGHT_FIXED 2
+#define OR_WEIGHT_TABLE 3
 
 #define OR_INF UINT64_MAX
 
@@ -141,8 +142,10 @@ typedef struct {
     double p_fail;               /* failure probability of every edge       */
     const double *p_fail_edge;   /* optional per-edge failure probabilities */
     int32_t weight_kind;         /* OR_WEIGHT_*                             */
-    uint32_t w_lo, w_hi;         /* range of OR_WEIGHT_UNIFORM              */
+    uint32_t w_lo, w_hi;         /* range of OR_WEIGHT_UNIFORM; w_hi = w_max */
+                                 /* of OR_WEIGHT_TABLE                      */
     const uint32_t *w0;          /* weights of OR_WEIGHT_FIXED              */
+    const uint64_t *w_cdf;       /* OR_WEIGHT_TABLE: m x w_max thresholds   */
 } or_model;
 
 /* Realization with counter words (r, u, v, stream): stream 0 is the row-wise
@@ -167,6 +170,14 @@ static int or_realize_stream(int32_t n, int64_t m, const int32_t *eu, const int3
         } else if (mod->weight_kind == OR_WEIGHT_UNIFORM) {
             uint64_t span = (uint64_t)mod->w_hi - (uint64_t)mod->w_lo + 1u;
             w[e] = mod->w_lo + (uint32_t)(((uint64_t)x[1] * span) >> 32);
+        } else if (mod->weight_kind == OR_WEIGHT_TABLE) {
+            /* per-call resampled weight (Section 9.2): the law of edge e is given
+             * by its cumulative thresholds T_e(v) = floor(P(w <= v) 2^32); the
+             * weight is the smallest v with x1 < T_e(v) (T_e(w_max) = 2^32) */
+            const uint64_t *T = mod->w_cdf + (size_t)e * mod->w_hi;
+            uint32_t v = 1;
+            while (v < mod->w_hi && (uint64_t)x[1] >= T[v - 1]) ++v;
+            w[e] = v;
         } else {
             w[e] = mod->w0[e];
         }

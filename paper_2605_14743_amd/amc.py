@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libamc.so")
 
 OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NOT_READY, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
-WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED = 0, 1, 2
+WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED, WEIGHT_TABLE = 0, 1, 2, 3
 MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK = \
     1, 2, 4, 8, 16, 32, 64, 128
@@ -41,7 +41,7 @@ class AmcError(RuntimeError):
 
 class Model(C.Structure):
     _fields_ = [("p_fail", C.c_double), ("p_fail_edge", _P(C.c_double)), ("weight_kind", C.c_int32),
-                ("w_lo", C.c_uint32), ("w_hi", C.c_uint32)]
+                ("w_lo", C.c_uint32), ("w_hi", C.c_uint32), ("w_cdf", _P(C.c_uint64))]
 
 
 class Query(C.Structure):
@@ -209,10 +209,10 @@ class Graph:
             pass
 
 
-_WEIGHTS = {"unit": WEIGHT_UNIT, "uniform": WEIGHT_UNIFORM_INT, "fixed": WEIGHT_FIXED}
+_WEIGHTS = {"unit": WEIGHT_UNIT, "uniform": WEIGHT_UNIFORM_INT, "fixed": WEIGHT_FIXED, "table": WEIGHT_TABLE}
 
 
-def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=None):
+def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=None, w_cdf=None):
     keep = []
     m = Model()
     m.p_fail = float(p_fail)
@@ -222,6 +222,11 @@ def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=N
         m.p_fail_edge = _ptr(pe, C.c_double)
     m.weight_kind = _WEIGHTS[weight] if isinstance(weight, str) else int(weight)
     m.w_lo, m.w_hi = int(w_lo), int(w_hi)
+    if w_cdf is not None:
+        wc = np.ascontiguousarray(w_cdf, dtype=np.uint64)
+        keep.append(wc)
+        m.w_cdf = _ptr(wc, C.c_uint64)
+        m.w_hi = int(wc.shape[1])
     return m, keep
 
 

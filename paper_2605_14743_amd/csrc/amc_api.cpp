@@ -241,6 +241,17 @@ extern "C" int amc_version(void) { return 100; }
 // ---------------------------------------------------------------------------
 namespace amc {
 
+void ModelInputs::capture(amc_model &md, int64_t m) {
+    if (md.p_fail_edge) {
+        p_fail_edge.assign(md.p_fail_edge, md.p_fail_edge + m);
+        md.p_fail_edge = p_fail_edge.data();
+    }
+    if (md.weight_kind == AMC_WEIGHT_TABLE && md.w_cdf) {
+        w_cdf.assign(md.w_cdf, md.w_cdf + (size_t)m * md.w_hi);
+        md.w_cdf = w_cdf.data();
+    }
+}
+
 void QueryInputs::capture(amc_query &q, int n) {
     if (q.s) {
         s.assign(q.s, q.s + n);
@@ -268,6 +279,16 @@ void QueryInputs::capture(amc_query &q, int n) {
     }
 }
 
+// Largest edge weight a realization can draw.
+uint64_t model_wmax(const amc_graph *g, const amc_model *md) {
+    switch (md->weight_kind) {
+        case AMC_WEIGHT_UNIT: return 1u;
+        case AMC_WEIGHT_UNIFORM_INT:
+        case AMC_WEIGHT_TABLE: return md->w_hi;
+        default: return g->w0.empty() ? 1u : *std::max_element(g->w0.begin(), g->w0.end());
+    }
+}
+
 int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     if (!g || !md || !q) return AMC_E_INVALID_ARG;
     const int n = g->n;
@@ -281,6 +302,14 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
         if (md->w_lo < 1u || md->w_hi < md->w_lo || md->w_hi > 65535u) return AMC_E_INVALID_ARG;
     } else if (md->weight_kind == AMC_WEIGHT_FIXED) {
         if (g->w0.empty() && g->m > 0) return AMC_E_INVALID_ARG;
+    } else if (md->weight_kind == AMC_WEIGHT_TABLE) {
+        if (md->w_hi < 1u || md->w_hi > 255u || (g->m > 0 && !md->w_cdf)) return AMC_E_INVALID_ARG;
+        for (int64_t e = 0; e < g->m; ++e) {
+            const uint64_t *T = md->w_cdf + (size_t)e * md->w_hi;
+            for (uint32_t v = 1; v < md->w_hi; ++v)
+                if (T[v] < T[v - 1]) return AMC_E_INVALID_ARG;
+            if (T[md->w_hi - 1] != (1ull << 32)) return AMC_E_INVALID_ARG;
+        }
     } else if (md->weight_kind != AMC_WEIGHT_UNIT) {
         return AMC_E_INVALID_ARG;
     }
@@ -331,10 +360,7 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
     if (q->group < 0 || q->group > 16 || (q->group > 4 && q->group != 8 && q->group != 16)) return AMC_E_INVALID_ARG;
     // longest possible distance must stay below the "unreached" sentinel
-    const uint64_t wmax = md->weight_kind == AMC_WEIGHT_UNIT ? 1u
-                          : md->weight_kind == AMC_WEIGHT_UNIFORM_INT
-                              ? md->w_hi
-                              : (g->w0.empty() ? 1u : *std::max_element(g->w0.begin(), g->w0.end()));
+    const uint64_t wmax = model_wmax(g, md);
     if ((uint64_t)(n - 1) * wmax >= (uint64_t)kInf - 65536u) return AMC_E_UNSUPPORTED;
     return AMC_OK;
 }
@@ -373,10 +399,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     // adjacency entry: neighbour in the low bits, weight above; 16 bits when both fit
     uint32_t nbits = 1;
     while ((1u << nbits) < (uint32_t)n) ++nbits;
-    const uint64_t wmax = md->weight_kind == AMC_WEIGHT_UNIT ? 1u
-                          : md->weight_kind == AMC_WEIGHT_UNIFORM_INT
-                              ? md->w_hi
-                              : (g->w0.empty() ? 1u : *std::max_element(g->w0.begin(), g->w0.end()));
+    const uint64_t wmax = model_wmax(g, md);
     if (nbits < 16 && wmax < (1ull << (16 - nbits)) && adj_cap <= 65535u) {
         pl->adj_bytes = 2;
         pl->shift = nbits;

@@ -52,8 +52,9 @@ struct SweepParams {
     // network-state law
     uint64_t t_fail;            // failure threshold floor(p 2^32) of every edge
     const uint64_t *t_fail_edge;// per-edge thresholds or nullptr
-    int32_t weight_kind;        // 0 unit, 1 uniform integer, 2 fixed
-    uint32_t w_lo, w_span;      // uniform integer law: lo + ((x * span) >> 32)
+    int32_t weight_kind;        // 0 unit, 1 uniform integer, 2 fixed, 3 per-edge table
+    uint32_t w_lo, w_span;      // uniform integer law: lo + ((x * span) >> 32); table: w_span = w_max
+    const uint64_t *w_cdf;      // table law: m x w_max cumulative thresholds
     // query
     uint32_t key0, key1;        // Philox key = seed
     uint32_t r_begin;           // absolute index of realization 0 of this query

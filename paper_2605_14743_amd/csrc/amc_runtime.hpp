@@ -44,6 +44,12 @@ struct Plan {
 
 // Private copies of the arrays a query points to (inputs are never retained):
 // capture() copies them and redirects the query's pointers to the copies.
+struct ModelInputs {
+    std::vector<double> p_fail_edge;
+    std::vector<uint64_t> w_cdf;
+    void capture(amc_model &md, int64_t m);
+};
+
 struct QueryInputs {
     std::vector<double> s, reward, gamma;
     std::vector<int32_t> pool, fb_set;
@@ -95,6 +101,7 @@ struct amc_graph {
 
 namespace amc {
 
+uint64_t model_wmax(const amc_graph *g, const amc_model *md);
 int validate(const amc_graph *g, const amc_model *md, const amc_query *q);
 int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, Plan *pl);
 uint64_t prob_threshold(double p);

@@ -43,10 +43,7 @@ int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, 
     R.ctx = ctx;
     R.g = g;
     R.md = *md;
-    if (md->p_fail_edge) {
-        R.p_fail_edge.assign(md->p_fail_edge, md->p_fail_edge + g->m);
-        R.md.p_fail_edge = R.p_fail_edge.data();
-    }
+    R.min.capture(R.md, g->m);
     R.q = *q;
     R.in.capture(R.q, g->n);
     RCHK(plan(ctx, g, &R.md, &R.q, &R.pl));
@@ -84,7 +81,13 @@ int qr_fill_desc(QueryRun &R, hipStream_t st) {
     }
     P.weight_kind = R.md.weight_kind;
     P.w_lo = R.md.w_lo;
-    P.w_span = R.md.weight_kind == AMC_WEIGHT_UNIFORM_INT ? R.md.w_hi - R.md.w_lo + 1u : 1u;
+    P.w_span = R.md.weight_kind == AMC_WEIGHT_UNIFORM_INT ? R.md.w_hi - R.md.w_lo + 1u
+               : R.md.weight_kind == AMC_WEIGHT_TABLE    ? R.md.w_hi
+                                                         : 1u;
+    if (R.md.weight_kind == AMC_WEIGHT_TABLE && g->m > 0) {
+        RCHK(dev_copy_in(A, R.md.w_cdf, 8 * (size_t)g->m * R.md.w_hi, st, &p));
+        P.w_cdf = (const uint64_t *)p;
+    }
     P.key0 = (uint32_t)q->seed;
     P.key1 = (uint32_t)(q->seed >> 32);
     P.r_begin = q->r_begin;

@@ -35,7 +35,7 @@ struct QueryRun {
     int n_chain = 0;                       // amc_chain: size of the given kernel
     amc_model md{};
     amc_query q{};
-    std::vector<double> p_fail_edge;
+    ModelInputs min;
     QueryInputs in;
     std::vector<uint64_t> t_fail_edge;
     std::vector<uint8_t> mask;

@@ -32,7 +32,7 @@ struct Request {
     amc_ctx *ctx = nullptr;
     const amc_graph *g = nullptr;
     amc_model model{};
-    std::vector<double> p_fail_edge;
+    ModelInputs min;
     amc_query q{};
     QueryInputs in;
     amc_result *out = nullptr;
@@ -162,10 +162,7 @@ extern "C" int amc_submit(amc_ctx *ctx, const amc_graph *g, const amc_model *mod
     r->ctx = ctx;
     r->g = g;
     r->model = *model;
-    if (model->p_fail_edge) {
-        r->p_fail_edge.assign(model->p_fail_edge, model->p_fail_edge + g->m);
-        r->model.p_fail_edge = r->p_fail_edge.data();
-    }
+    r->min.capture(r->model, g->m);
     r->q = *q;
     r->in.capture(r->q, g->n);
     r->out = out;

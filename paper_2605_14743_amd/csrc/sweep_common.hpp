@@ -61,6 +61,11 @@ __device__ inline void stage_realization(const SweepParams &P, uint32_t r, RP *r
         uint32_t w;
         if (P.weight_kind == 0) w = 1u;
         else if (P.weight_kind == 1) w = P.w_lo + __umulhi(x.y, P.w_span);
+        else if (P.weight_kind == 3) {   // smallest v with x1 < T_e(v) (Section 9.2 resampling)
+            const uint64_t *T = P.w_cdf + (size_t)e * P.w_span;
+            w = 1u;
+            while (w < P.w_span && (uint64_t)x.y >= T[w - 1]) ++w;
+        }
         else w = P.w0[e];
         ew[e] = ((uint64_t)x.x >= t) ? (uint16_t)w : (uint16_t)0;
     }

@@ -19,10 +19,7 @@
 namespace amc {
 
 TuneKey tune_key(const amc_graph *g, const amc_model *md) {
-    uint32_t wmax = 1;
-    if (md->weight_kind == AMC_WEIGHT_UNIFORM_INT) wmax = md->w_hi;
-    else if (md->weight_kind == AMC_WEIGHT_FIXED && !g->w0.empty())
-        wmax = *std::max_element(g->w0.begin(), g->w0.end());
+    const uint32_t wmax = (uint32_t)model_wmax(g, md);
     return TuneKey{g->n, g->m, md->weight_kind == AMC_WEIGHT_UNIT ? 0 : 1, wmax};
 }
 

@@ -153,6 +153,34 @@ def _connected(n, pairs) -> bool:
     return len({find(v) for v in range(n)}) == 1
 
 
+def resampled_weight_cdf(w0: np.ndarray, w_max: int, rho_mu: float, rho_sigma: float) -> np.ndarray:
+    """Per-edge law of the per-call resampled weight of the co-occurrence
+    experiment (Section 9.2): x ~ N(mu_e, sigma_e^2) with mu_e = w0 + rho_mu
+    (w_max - w0), sigma_e = rho_sigma (w_max - w0), rounded and clipped to
+    [w0, w_max].  Returned as cumulative thresholds T[e, v-1] =
+    floor(P(w <= v) 2^32) for v = 1..w_max (T[e, w_max-1] = 2^32), the integer
+    form both the library and the oracle draw from (x1 < T means w <= v)."""
+    w0 = np.asarray(w0, dtype=np.int64)
+    m = len(w0)
+    T = np.zeros((m, w_max), dtype=np.uint64)
+    for e in range(m):
+        a = int(w0[e])
+        mu = a + rho_mu * (w_max - a)
+        sd = rho_sigma * (w_max - a)
+        for v in range(1, w_max + 1):
+            if v < a:
+                c = 0.0
+            elif v >= w_max:
+                c = 1.0
+            elif sd == 0.0:
+                c = 1.0 if mu < v + 0.5 else 0.0              # round half up, no spread
+            else:
+                c = 0.5 * math.erfc(-(v + 0.5 - mu) / (sd * math.sqrt(2.0)))
+            T[e, v - 1] = min(int(math.floor(c * 4294967296.0)), 4294967296)
+        T[e, w_max - 1] = 4294967296
+    return T
+
+
 def pool(n: int, size: int, seed: int) -> np.ndarray:
     """Candidate pool W: `size` distinct vertices, sorted."""
     rng = np.random.default_rng([seed, 2])

@@ -34,7 +34,7 @@ def ctx():
 
 def gpu_run(ctx, g, model, **q):
     G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
-    say(f"[gpu] run n={g.n} m={g.m} model={ {k: v for k, v in model.items() if k != 'p_fail_edge'} } "
+    say(f"[gpu] run n={g.n} m={g.m} model={ {k: v for k, v in model.items() if k not in ('p_fail_edge', 'w_cdf')} } "
         f"q={ {k: v for k, v in q.items() if k not in ('pool', 'reward', 's', 'debug_pairs')} }")
     try:
         return amc.run(ctx, G, model, **q)
@@ -321,3 +321,36 @@ def test_chain_random_kernels(ctx, n):
     assert_close_norm(res["b"], o["b"], what="b")
     assert res["E_T"] == pytest.approx(o["ET"], rel=TOL)
     assert res["b_f"] == pytest.approx(float(o["b"] @ f), rel=1e-12)
+
+
+# --------------------------------------------------------------------------- per-call weight resampling (Section 9.2)
+@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_WAVE_L2, amc.MODE_BLOCK, "wave-g8"])
+def test_resampled_weight_table(ctx, mode):
+    g = W.powerlaw_weighted_graph(77, 254, 2.5, 3.0, 31, 0)
+    T = W.resampled_weight_cdf(g.w0, 31, 0.1, 0.2)
+    model = {"p_fail": 0.05, "weight": "table", "w_cdf": T}
+    q = dict(mode=amc.MODE_WAVE, group=8) if mode == "wave-g8" else dict(mode=mode)
+    res = gpu_run(ctx, g, model, seed=5, R=400, alpha=0.15, k_min=5, flags=FLAGS, **q)
+    ref = O.sweep(g.n, g.eu, g.ev, seed=5, R=400, alpha=0.15, k_min=5, want_next=True, **model)
+    check_sweep(res, ref, g.n, f"table law {mode}")
+    er = W.config_er20().graph
+    T2 = W.resampled_weight_cdf(np.full(er.m, 2), 9, 0.3, 0.25)
+    model2 = {"p_fail": 0.1, "weight": "table", "w_cdf": T2}
+    res = gpu_run(ctx, er, model2, seed=6, R=300, flags=FLAGS, **q)
+    ref = O.sweep(er.n, er.eu, er.ev, seed=6, R=300, want_next=True, **model2)
+    check_sweep(res, ref, er.n, f"table law er20 {mode}")
+
+
+def test_weight_table_arguments(ctx):
+    g = W.er_graph(10, 0.4, 1)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    good = W.resampled_weight_cdf(np.full(g.m, 1), 5, 0.2, 0.3)
+    bad_last = good.copy()
+    bad_last[0, -1] = 2 ** 32 - 1
+    bad_order = good.copy()
+    bad_order[1, 0], bad_order[1, 1] = good[1, 1], good[1, 0] - 1
+    for T in (bad_last, bad_order):
+        with pytest.raises(amc.AmcError) as ei:
+            amc.run(ctx, G, {"p_fail": 0.1, "weight": "table", "w_cdf": T}, R=4)
+        assert ei.value.rc == amc.E_INVALID_ARG
+    G.close()
