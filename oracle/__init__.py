@@ -63,7 +63,7 @@ class _Model(C.Structure):
 class _Query(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("R", C.c_uint32), ("r_begin", C.c_uint32), ("alpha", C.c_double),
                 ("k_min", C.c_uint32), ("tau", C.c_double), ("pool_mask", C.POINTER(C.c_uint8)),
-                ("topk", C.c_int32), ("gamma", C.POINTER(C.c_double))]
+                ("topk", C.c_int32), ("gamma", C.POINTER(C.c_double)), ("hop_radius", C.c_int32)]
 
 
 class _SweepOut(C.Structure):
@@ -255,7 +255,7 @@ def band_argmax(B, member, tau=1e-9):
 
 # --------------------------------------------------------------------------- sweep
 def sweep(n, eu, ev, *, seed, R, r_begin=0, alpha=0.15, k_min=5, tau=1e-9, pool=None, want_next=False,
-          want_bsum=True, want_center=True, topk=0, gamma=None, **model):
+          want_bsum=True, want_center=True, topk=0, gamma=None, hop_radius=0, **model):
     """Alg. 1 for every anchor over realizations [r_begin, r_begin + R), counted as in Alg. 2.
     With topk > 0 also the Top-k step-reward sums psi / psi_w (Sections 6.2-6.3) and the
     finite-k pool selector (Section 7.1)."""
@@ -265,6 +265,9 @@ def sweep(n, eu, ev, *, seed, R, r_begin=0, alpha=0.15, k_min=5, tau=1e-9, pool=
     q.seed, q.R, q.r_begin = int(seed), int(R), int(r_begin)
     q.alpha, q.k_min, q.tau = float(alpha), int(k_min), float(tau)
     q.topk = int(topk)
+    q.hop_radius = int(hop_radius)
+    if hop_radius > 0:                     # anchored steps: no realization-wide B
+        want_bsum = want_center = False
     g_arr = None
     if gamma is not None:
         g_arr = np.ascontiguousarray(gamma, dtype=np.float64)

@@ -527,7 +527,57 @@ typedef struct {
     const uint8_t *pool_mask;    /* length n, NULL when no pool            */
     int32_t topk;                /* 0: k = infinity; else the Top-k size   */
     const double *gamma;         /* node values (length n) or NULL for 1   */
+    int32_t hop_radius;          /* > 0: anchored r-hop neighbourhoods      */
 } or_query;
+
+/* Anchored r-hop neighbourhoods (Section 9.2): anchor i's step computes the
+ * betweenness of the subgraph of H_r induced by S_r(i), the vertices within
+ * `radius` surviving hops of i, reports its tie-broken maximiser (over S_r(i)
+ * ∩ W for the pool selector), and is invalid when |S_r(i)| < k_min or the
+ * coin fires.  Work counters per anchor: |S| source passes, each reaching |S|
+ * vertices, the surviving directed slots inside S and the base directed
+ * slots of S's vertices. */
+static int or_anchored_step(const or_graph *g, const int32_t *eu, const int32_t *ev, const uint8_t *alive,
+                            const uint32_t *w, int unit, int32_t i, int32_t radius, double tau,
+                            const uint8_t *pool_mask, uint8_t *inS, uint8_t *aliveS, int32_t *queue, int32_t *hop,
+                            double *B, uint64_t *dist, uint64_t *sigma, int32_t *order, double *delta,
+                            uint8_t *member, int32_t *size_out, int32_t *c_out, int32_t *cw_out, uint64_t *ak_out,
+                            uint64_t *dk_out)
+{
+    int32_t n = g->n, v, head = 0, cnt = 0, rc;
+    int64_t e, k, ak = 0, dk = 0;
+    for (v = 0; v < n; ++v) { inS[v] = 0; hop[v] = -1; }
+    hop[i] = 0; queue[cnt++] = i;
+    while (head < cnt) {                                   /* breadth-first hops over surviving edges */
+        int32_t x = queue[head++];
+        if (hop[x] == radius) continue;
+        for (k = g->off[x]; k < g->off[x + 1]; ++k) {
+            int32_t y = g->nbr[k];
+            if (!alive[g->eid[k]] || hop[y] >= 0) continue;
+            hop[y] = hop[x] + 1;
+            queue[cnt++] = y;
+        }
+    }
+    for (v = 0; v < cnt; ++v) inS[queue[v]] = 1;
+    for (e = 0; e < g->m; ++e) {
+        aliveS[e] = alive[e] && inS[eu[e]] && inS[ev[e]];
+        ak += 2 * aliveS[e];
+    }
+    for (v = 0; v < cnt; ++v) dk += g->off[queue[v] + 1] - g->off[queue[v]];
+    rc = or_brandes_graph(g, aliveS, w, unit, B, dist, sigma, order, delta);
+    if (rc != OR_OK) return rc;
+    for (v = 0; v < n; ++v) member[v] = inS[v];
+    *c_out = or_band_argmax(n, B, member, tau, NULL);
+    *cw_out = -1;
+    if (pool_mask) {
+        for (v = 0; v < n; ++v) member[v] = inS[v] && pool_mask[v];
+        *cw_out = or_band_argmax(n, B, member, tau, NULL);
+    }
+    *size_out = cnt;
+    *ak_out = (uint64_t)ak;
+    *dk_out = (uint64_t)dk;
+    return OR_OK;
+}
 
 typedef struct {
     uint32_t *counts;            /* n x (n+1), column n is bottom          */
@@ -581,6 +631,41 @@ int or_sweep(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const o
     gw = (double *)malloc(sizeof(double) * (size_t)n);
     if (!alive || !member || !w || !dist || !sigma || !order || !comp || !size || !cc || !cw || !B || !delta ||
         !k_alive || !k_deg || !fw || !ranked || !gs || !gw) { rc = OR_E_NOMEM; goto done; }
+
+    if (q->hop_radius > 0) {                               /* anchored r-hop neighbourhoods */
+        uint8_t *inS = (uint8_t *)malloc((size_t)n), *aliveS = (uint8_t *)malloc((size_t)m + 1);
+        int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!inS || !aliveS || !queue || !hop) rc = OR_E_NOMEM;
+        for (rr = 0; rr < q->R && rc == OR_OK; ++rr) {
+            uint32_t r = q->r_begin + rr;
+            or_realize(n, m, eu, ev, mod, q->seed, r, alive, w);
+            for (i = 0; i < n && rc == OR_OK; ++i) {
+                int32_t sz, c, cwi;
+                uint64_t ak, dk;
+                int coin, valid;
+                rc = or_anchored_step(&g, eu, ev, alive, w, unit, i, q->hop_radius, q->tau, q->pool_mask, inS,
+                                      aliveS, queue, hop, B, dist, sigma, order, delta, member, &sz, &c, &cwi, &ak,
+                                      &dk);
+                if (rc != OR_OK) break;
+                coin = or_stop_coin(q->seed, r, i, q->alpha);
+                valid = !coin && (uint32_t)sz >= q->k_min;
+                out->counts[(size_t)i * (n + 1) + (valid ? c : n)] += 1u;
+                if (out->next_table) out->next_table[(size_t)rr * n + i] = valid ? c : -1;
+                if (out->counts_w) {
+                    int32_t nw = (valid && cwi >= 0) ? cwi : -1;
+                    out->counts_w[(size_t)i * (n + 1) + (nw >= 0 ? nw : n)] += 1u;
+                    if (out->next_table_w) out->next_table_w[(size_t)rr * n + i] = nw;
+                }
+                out->stats[0] += (uint64_t)sz;
+                out->stats[1] += (uint64_t)sz * (uint64_t)sz;
+                out->stats[2] += (uint64_t)sz * ak;
+                out->stats[3] += (uint64_t)sz * dk;
+            }
+        }
+        free(inS); free(aliveS); free(queue); free(hop);
+        goto done;
+    }
 
     for (rr = 0; rr < q->R; ++rr) {
         uint32_t r = q->r_begin + rr;
