@@ -151,6 +151,14 @@ typedef struct amc_query {
     int32_t fb_node;
     const int32_t *fb_set;
     int32_t fb_set_size;
+    /* Anchored r-hop neighbourhoods (Section 9.2), hop_radius = r > 0: anchor
+     * i's step ranks the betweenness of the subgraph of H_r induced by S_r(i),
+     * the vertices within r surviving hops of i, and is invalid when |S_r(i)|
+     * < k_min (or the coin fires).  Each anchor then needs its own
+     * betweenness: the work counters count |S_r(i)| source passes per anchor.
+     * Not combined with topk, AMC_WANT_CENTER, AMC_WANT_BSUM, AMC_WANT_DEBUG
+     * or AMC_PLAIN_LAUNCH; runs in LDS mode only.  0 = off. */
+    int32_t hop_radius;
 } amc_query;
 
 #define AMC_MAX_TOPK 64

@@ -51,7 +51,7 @@ class Query(C.Structure):
                 ("r_lower", C.c_double), ("cert_topk", C.c_int32), ("flags", C.c_uint32), ("mode", C.c_int32),
                 ("tile", C.c_int32), ("waves", C.c_int32), ("group", C.c_int32), ("debug_pairs", _P(C.c_uint32)),
                 ("n_debug", C.c_int32), ("topk", C.c_int32), ("gamma", _P(C.c_double)), ("fb_node", C.c_int32),
-                ("fb_set", _P(C.c_int32)), ("fb_set_size", C.c_int32)]
+                ("fb_set", _P(C.c_int32)), ("fb_set_size", C.c_int32), ("hop_radius", C.c_int32)]
 
 
 class TrajQuery(C.Structure):
@@ -232,7 +232,7 @@ def make_model(p_fail=0.0, weight="unit", w_lo=1, w_hi=1, p_fail_edge=None, w0=N
 
 def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, floor_eta=-1.0, s=None, pool=None,
                reward=None, eps=0.0, r_lower=0.05, cert_topk=0, flags=0, mode=MODE_AUTO, tile=0, waves=0, group=0,
-               debug_pairs=None, topk=0, gamma=None, fb_node=None, fb_set=None):
+               debug_pairs=None, topk=0, gamma=None, fb_node=None, fb_set=None, hop_radius=0):
     keep = []
     q = Query()
     q.seed, q.R, q.r_begin = int(seed), int(R), int(r_begin)
@@ -259,6 +259,7 @@ def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, 
         q.n_debug = len(dp)
         q.flags |= WANT_DEBUG
     q.topk = int(topk)
+    q.hop_radius = int(hop_radius)
     if gamma is not None:
         ga = np.ascontiguousarray(gamma, dtype=np.float64)
         keep.append(ga)

@@ -95,7 +95,8 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
     (void)hipMemGetInfo(&free_b, &total_b);
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(free_b * 0.9);
     if (set_sweep_wave_attrs(c->max_lds) != hipSuccess || set_sweep_block_attrs(c->max_lds) != hipSuccess ||
-        set_topk_attrs(c->max_lds) != hipSuccess || set_traj_attrs(c->max_lds) != hipSuccess) {
+        set_topk_attrs(c->max_lds) != hipSuccess || set_traj_attrs(c->max_lds) != hipSuccess ||
+        set_anchored_attrs(c->max_lds) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return AMC_E_HIP;
@@ -356,6 +357,12 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
         for (int v = 0; v < n; ++v)
             if (inW[v] && inF[v]) return AMC_E_INVALID_ARG;
     }
+    if (q->hop_radius < 0) return AMC_E_INVALID_ARG;
+    if (q->hop_radius > 0) {
+        if (q->topk > 0 || (q->flags & (AMC_WANT_CENTER | AMC_WANT_BSUM | AMC_WANT_DEBUG | AMC_PLAIN_LAUNCH)) ||
+            (q->mode != AMC_MODE_AUTO && q->mode != AMC_MODE_WAVE))
+            return AMC_E_INVALID_ARG;
+    }
     if (q->mode < AMC_MODE_AUTO || q->mode > AMC_MODE_WAVE_L2) return AMC_E_INVALID_ARG;
     if (q->waves < 0 || q->waves > kMaxWaves || q->tile < 0) return AMC_E_INVALID_ARG;
     if (q->group < 0 || q->group > 16 || (q->group > 4 && q->group != 8 && q->group != 16)) return AMC_E_INVALID_ARG;
@@ -406,6 +413,49 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     } else {
         pl->adj_bytes = 4;
         pl->shift = 16;
+    }
+    pl->anchored = false;
+    if (q->hop_radius > 0) {
+        // anchored neighbourhoods: one wavefront per anchor, lane per vertex
+        int aw = 0;
+        uint32_t alds = 0, awb = 0;
+        const int cap = q->waves > 0 ? q->waves : kMaxWaves;
+        for (int w = 1; w <= cap; ++w) {
+            uint32_t wb = 0;
+            const uint32_t lds = lds_bytes_anchored(n, adj_cap, pl->adj_bytes, w, &wb);
+            if (lds > (uint32_t)ctx->max_lds) break;
+            if ((uint64_t)wb * w < 2ull * (uint64_t)g->m) continue;   // per-edge staging
+            aw = w;
+            alds = lds;
+            awb = wb;
+        }
+        if (aw == 0 || (q->waves > 0 && aw != q->waves)) return AMC_E_UNSUPPORTED;
+        pl->anchored = true;
+        pl->mode = AMC_MODE_WAVE;
+        pl->group = 1;
+        pl->waves = aw;
+        pl->threads = 64 * aw;
+        pl->lds = alds;
+        pl->wave_bytes = awb;
+        pl->adj_cap = adj_cap;
+        pl->scratch_words = 0;
+        const uint32_t bpc = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / alds);
+        const uint64_t slots = (uint64_t)ctx->cu_count * bpc;
+        int tile = q->tile;
+        if (tile <= 0) {
+            if ((uint64_t)q->R >= 2 * slots) tile = n;
+            else {
+                const uint64_t per_r = std::min<uint64_t>((uint64_t)n, (2 * slots + q->R - 1) / q->R);
+                tile = std::max((int)((n + per_r - 1) / per_r), aw);
+            }
+        }
+        tile = std::min(tile, n);
+        pl->tile = tile;
+        pl->tiles_per_r = (n + tile - 1) / tile;
+        pl->items = (uint64_t)q->R * pl->tiles_per_r;
+        if (pl->items > 0xFFFFFFFFull) return AMC_E_UNSUPPORTED;
+        pl->blocks = (int)std::min<uint64_t>(pl->items, slots);
+        return AMC_OK;
     }
     int best_w = 0;
     uint32_t best_lds = 0, best_wb = 0;

@@ -82,6 +82,7 @@ struct SweepParams {
     int32_t *compg, *sizeg;     // R x n
     unsigned int *done;         // R
     int32_t keep_rows;
+    int32_t hop_radius;         // anchored r-hop neighbourhoods (0 = off)
     // per-(r, s) dumps for the parity checks
     const uint32_t *dbg_pairs;  // n_dbg x (r, s)
     int32_t n_dbg;

@@ -26,6 +26,12 @@ hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, in
 hipError_t set_sweep_wave_attrs(int max_lds);
 hipError_t set_sweep_block_attrs(int max_lds);
 
+// Anchored r-hop neighbourhoods (LDS mode only).
+uint32_t lds_bytes_anchored(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
+hipError_t set_anchored_attrs(int max_lds);
+hipError_t launch_anchored(const LaunchCtl &LC, bool weighted, uint32_t adj_bytes, int blocks, int waves, uint32_t lds,
+                           hipStream_t st);
+
 // Trajectory simulator (LDS mode only).
 hipError_t set_traj_attrs(int max_lds);
 hipError_t launch_traj(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,

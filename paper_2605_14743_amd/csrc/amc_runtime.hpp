@@ -40,6 +40,7 @@ struct Plan {
     uint64_t items = 0;
     int blocks = 0;
     uint32_t scratch_words = 0;     // per-workgroup global scratch (block and L2 modes)
+    bool anchored = false;          // anchored r-hop neighbourhoods (own kernel)
 };
 
 // Private copies of the arrays a query points to (inputs are never retained):

@@ -112,10 +112,10 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
     }
     // group by kernel variant
     struct Key {
-        int mode, weighted, group, adj_bytes, waves;
+        int mode, weighted, group, adj_bytes, waves, anchored;
         bool operator==(const Key &o) const {
             return mode == o.mode && weighted == o.weighted && group == o.group && adj_bytes == o.adj_bytes &&
-                   waves == o.waves;
+                   waves == o.waves && anchored == o.anchored;
         }
     };
     std::vector<Key> keys;
@@ -125,13 +125,14 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         // a member may run with fewer wavefronts than planned as long as the
         // wavefront regions still hold the staging and reduction scratch
         int w = pl.threads / 64;
-        if (per_wave) {
+        if (per_wave && !pl.anchored) {
             w = wave_bucket(pl.waves);
             const uint64_t need = std::max<uint64_t>(2ull * (uint64_t)b->runs[i]->g->m,
                                                      32ull * (uint64_t)b->runs[i]->g->n);
             if ((uint64_t)pl.wave_bytes * (uint64_t)w < need) w = pl.waves;
         }
-        Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w};
+        if (pl.anchored) w = pl.waves;
+        Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w, pl.anchored ? 1 : 0};
         size_t gi = 0;
         while (gi < keys.size() && !(keys[gi] == k)) ++gi;
         if (gi == keys.size()) {
@@ -157,7 +158,9 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         });
         for (int i : G.members) {
             QueryRun &R = *b->runs[i];
-            if (G.pl.mode == AMC_MODE_WAVE || G.pl.mode == AMC_MODE_WAVE_L2) {
+            if (G.pl.anchored) {
+                R.pl.lds = lds_bytes_anchored(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, &R.pl.wave_bytes);
+            } else if (G.pl.mode == AMC_MODE_WAVE || G.pl.mode == AMC_MODE_WAVE_L2) {
                 R.pl.waves = G.pl.waves;
                 R.pl.threads = G.pl.threads;
                 R.pl.lds = G.pl.mode == AMC_MODE_WAVE
@@ -225,7 +228,9 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         LC.work_ctr = G.work_ctr;
         LC.bscratch = G.bscratch;
         LC.bscratch_words = G.bscratch_words;
-        hipError_t e = G.pl.mode == AMC_MODE_BLOCK
+        hipError_t e = G.pl.anchored
+                           ? launch_anchored(LC, G.pl.weighted, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st)
+                       : G.pl.mode == AMC_MODE_BLOCK
                            ? launch_sweep_block(LC, G.pl.weighted, G.blocks, G.pl.threads, G.pl.lds, st)
                            : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.group,
                                                G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);

@@ -105,6 +105,7 @@ int qr_fill_desc(QueryRun &R, hipStream_t st) {
     P.adj_cap = R.pl.adj_cap;
     P.wave_bytes = R.pl.wave_bytes;
     P.shift = R.pl.shift;
+    P.hop_radius = q->hop_radius;
     return AMC_OK;
 }
 
@@ -289,6 +290,7 @@ int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
 }
 
 static hipError_t launch_plan(const Plan &pl, const LaunchCtl &LC, int blocks, hipStream_t st) {
+    if (pl.anchored) return launch_anchored(LC, pl.weighted, pl.adj_bytes, blocks, pl.waves, pl.lds, st);
     if (pl.mode == AMC_MODE_WAVE || pl.mode == AMC_MODE_WAVE_L2)
         return launch_sweep_wave(LC, pl.weighted, pl.mode == AMC_MODE_WAVE_L2, pl.group, pl.adj_bytes, blocks,
                                  pl.waves, pl.lds, st);

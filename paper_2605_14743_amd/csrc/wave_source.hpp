@@ -208,10 +208,14 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
     }
 }
 
-template <bool WEIGHTED, int U, typename ADJ, bool GB>
+// With MASK the traversal stays inside the vertex set mask[v] != 0 (an induced
+// subgraph): an edge into a vertex outside it is never relaxed, so such a
+// vertex stays unreached and fails the predecessor and successor tests.
+template <bool WEIGHTED, int U, typename ADJ, bool GB, bool MASK = false>
 __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
                                  double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux,
-                                 uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
+                                 uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf,
+                                 const uint8_t *mask = nullptr) {
     const int n = P.n;
     const int lane = threadIdx.x & 63;
     const uint32_t nmask = (1u << shift) - 1u;
@@ -287,6 +291,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 for (int k = 0; k < U; ++k) {
                     pred[k] = du[k] + w[k] == D;                        // u precedes v: pull sigma_u
                     rel[k] = D + w[k] < du[k];                          // relax the edge v -> u
+                    if constexpr (MASK) rel[k] = rel[k] && mask[u[k]] != 0;
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;

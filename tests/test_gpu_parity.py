@@ -354,3 +354,35 @@ def test_weight_table_arguments(ctx):
             amc.run(ctx, G, {"p_fail": 0.1, "weight": "table", "w_cdf": T}, R=4)
         assert ei.value.rc == amc.E_INVALID_ARG
     G.close()
+
+
+# --------------------------------------------------------------------------- anchored r-hop neighbourhoods (Section 9.2)
+@pytest.mark.parametrize("radius,extra", [(1, {}), (2, {}), (3, {"tile": 5}), (2, {"waves": 3})])
+def test_anchored_neighbourhoods(ctx, radius, extra):
+    g = W.powerlaw_weighted_graph(77, 254, 2.5, 3.0, 31, 0)
+    T = W.resampled_weight_cdf(g.w0, 31, 0.1, 0.2)
+    pool = np.array([0, 3, 9, 21, 40, 66])
+    for model in ({"p_fail": 0.0, "weight": "table", "w_cdf": T}, {"p_fail": 0.1, "weight": "fixed"}):
+        res = gpu_run(ctx, g, model, seed=7, R=120, alpha=0.15, k_min=5, hop_radius=radius, pool=pool,
+                      flags=amc.WANT_NEXT_TABLE | amc.WANT_N, **extra)
+        ref = O.sweep(g.n, g.eu, g.ev, seed=7, R=120, alpha=0.15, k_min=5, hop_radius=radius, pool=pool,
+                      want_next=True, **oracle_model(model, g))
+        check_sweep(res, ref, g.n, f"anchored r={radius} {model['weight']}")
+        t = O.tail(ref["counts"], 120)
+        assert_close_norm(res["b"], t["b"], what="anchored b")
+    er = W.config_er20().graph
+    res = gpu_run(ctx, er, W.config_er20().model(), seed=2, R=200, hop_radius=radius, flags=amc.WANT_NEXT_TABLE,
+                  **extra)
+    ref = O.sweep(er.n, er.eu, er.ev, seed=2, R=200, hop_radius=radius, want_next=True, **W.config_er20().model())
+    check_sweep(res, ref, er.n, f"anchored er20 r={radius}")
+
+
+def test_anchored_arguments(ctx):
+    g = W.er_graph(10, 0.4, 1)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    for bad in ({"hop_radius": -1}, {"hop_radius": 2, "topk": 2}, {"hop_radius": 2, "flags": amc.WANT_CENTER},
+                {"hop_radius": 2, "flags": amc.WANT_BSUM}, {"hop_radius": 2, "mode": amc.MODE_BLOCK}):
+        with pytest.raises(amc.AmcError) as ei:
+            amc.run(ctx, G, {"p_fail": 0.1}, R=4, **bad)
+        assert ei.value.rc == amc.E_INVALID_ARG, bad
+    G.close()
