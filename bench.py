@@ -44,15 +44,17 @@ def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
     import oracle as O
     g = wl.graph
     R = 0
+    units = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=4, r_begin=R, alpha=wl.alpha, k_min=wl.k_min, want_bsum=False,
-                want_center=False, **wl.model())
+        res = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=4, r_begin=R, alpha=wl.alpha, k_min=wl.k_min, want_bsum=False,
+                      want_center=False, hop_radius=wl.hop_radius, **wl.model())
+        units += res["stats"]["units"]
         R += 4
     dt = time.perf_counter() - t0
-    return {"value": R * g.n / dt, "unit": "realization-sources/s", "cores": 1, "kind": "oracle",
-            "sample": f"{R} realizations x {g.n} sources of the same workload (single-threaded C oracle, "
-                      f"{dt:.1f} s)"}
+    return {"value": units / dt, "unit": "realization-sources/s", "cores": 1, "kind": "oracle",
+            "sample": f"{R} realizations of the same workload, {units} single-source passes (single-threaded C "
+                      f"oracle, {dt:.1f} s)"}
 
 
 def run_bench(args):
@@ -61,7 +63,8 @@ def run_bench(args):
     from paper_2605_14743_amd import amc
     from paper_2605_14743_amd import workloads as W
 
-    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20}[args.workload]()
+    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
+          "cooc77": W.config_cooc77}[args.workload]()
     g = wl.graph
     if args.R:
         wl.R = args.R
@@ -69,7 +72,7 @@ def run_bench(args):
     G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
     q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
              r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group,
-             pool=wl.pool, reward=wl.reward)
+             pool=wl.pool, reward=wl.reward, hop_radius=wl.hop_radius)
     if args.topk > 0:
         # finite-k local Top-k rows: a pool of 50 nodes with values U[0.5, 2]
         pool = wl.pool if wl.pool is not None else W.pool(g.n, 50, 1)
@@ -90,7 +93,7 @@ def run_bench(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = last["stats"]
-    units = wl.R * g.n
+    units = st["units"]                      # single-source passes (R n for the row-wise sweep)
     value = units * args.steps / dt
     k_ms = float(np.mean(sweep_ms))
     ab = algorithmic_bytes(st)
@@ -109,7 +112,7 @@ def run_bench(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "graph": g.name, "n": g.n,
+        "config": {"workload": wl.name, "graph": g.name, "n": g.n, "hop_radius": wl.hop_radius,
                    "m": g.m, "realizations": wl.R, "p_fail": wl.p_fail,
                    "weights": wl.weight if wl.weight != "uniform" else f"uniform{{{wl.w_lo}..{wl.w_hi}}}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
@@ -255,7 +258,8 @@ def run_traj(args):
     from paper_2605_14743_amd import amc
     from paper_2605_14743_amd import workloads as W
 
-    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20}[args.workload]()
+    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
+          "cooc77": W.config_cooc77}[args.workload]()
     g = wl.graph
     ctx = amc.Context(0)
     G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
@@ -331,7 +335,7 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="ws1000", choices=["ws1000", "er5000", "er20"],
+    ap.add_argument("--workload", default="ws1000", choices=["ws1000", "er5000", "er20", "cooc77"],
                     help="ws1000 is the benchmark line; the others are for measurement notes")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)

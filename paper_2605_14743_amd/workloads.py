@@ -236,11 +236,15 @@ class Workload:
     r_lower: float = 0.05
     cert_topk: int = 5
     name: str = ""
+    w_cdf: np.ndarray | None = None         # per-edge resampling law ("table" weights)
+    hop_radius: int = 0                      # anchored r-hop neighbourhoods
 
     def model(self) -> dict:
         d = {"p_fail": self.p_fail, "weight": self.weight, "w_lo": self.w_lo, "w_hi": self.w_hi}
         if self.weight == "fixed":
             d["w0"] = self.graph.w0
+        if self.weight == "table":
+            d["w_cdf"] = self.w_cdf
         return d
 
 
@@ -264,6 +268,16 @@ def config_er5000() -> Workload:
     W = pool(5000, 50, 0)
     return Workload(g, seed=0, R=4096, p_fail=0.1, weight="unit", pool=W, reward=rewards(5000, W, 0.5, 2.0, 0),
                     name="er5000-d8-unit-R4096-pool50")
+
+
+def config_cooc77() -> Workload:
+    """Co-occurrence stand-in (n = 77, m = 254, power-law degrees, geometric
+    weights clipped at 31) with the per-call weight resampling and anchored
+    2-hop neighbourhoods of Section 9.2 (rho_mu = 0.1, rho_sigma = 0.2; the
+    topology is fixed)."""
+    g = powerlaw_weighted_graph(77, 254, 2.5, 3.0, 31, 0)
+    return Workload(g, seed=0, R=2000, p_fail=0.0, weight="table", w_cdf=resampled_weight_cdf(g.w0, 31, 0.1, 0.2),
+                    hop_radius=2, name="cooc77-resampled-hop2-R2000")
 
 
 def config_mixed_batch(count: int = 64, R: int = 2048, seed: int = 0) -> list[Workload]:
