@@ -106,6 +106,19 @@ class _TrajOut(C.Structure):
                 ("total_steps", C.c_uint64), ("truncated", C.c_int32)]
 
 
+class _RobustIn(C.Structure):
+    _fields_ = [("s", C.POINTER(C.c_double)), ("f", C.POINTER(C.c_double)), ("samples", C.c_int32),
+                ("delta", C.c_double), ("r_min", C.c_double), ("seed", C.c_uint64)]
+
+
+class _RobustOut(C.Structure):
+    _fields_ = [("b0", C.POINTER(C.c_double)), ("b_sw", C.c_double), ("b_imp", C.c_double),
+                ("kl", C.POINTER(C.c_double)), ("tv", C.POINTER(C.c_double)), ("kl_arg", C.c_int32),
+                ("tv_arg", C.c_int32), ("b_kl", C.POINTER(C.c_double)), ("b_tv", C.POINTER(C.c_double)),
+                ("b_lin", C.POINTER(C.c_double)), ("norm_N0E", C.c_double), ("norm_N0", C.c_double),
+                ("rem_bound", C.c_double), ("rem_actual", C.c_double)]
+
+
 def _declare(L):
     P = C.POINTER
     L.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -134,6 +147,10 @@ def _declare(L):
                                       C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
     L.or_pair_certificate.restype = None
     L.or_tail.argtypes = [C.c_int32, P(C.c_uint32), P(C.c_uint32), C.c_uint32, P(_TailIn), P(_TailOut)]
+    L.or_robust.argtypes = [C.c_int32, P(C.c_double), P(_RobustIn), P(_RobustOut)]
+    L.or_perturbed_kernel.argtypes = [C.c_int32, P(C.c_double), C.c_uint64, C.c_int32, C.c_double, C.c_double,
+                                      P(C.c_double)]
+    L.or_perturbed_kernel.restype = None
     L.or_trajectories.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32), P(_Model), P(_TrajQuery),
                                   P(_TrajOut)]
 
@@ -336,6 +353,41 @@ def trajectories(n, eu, ev, *, seed, x0, alpha=0.15, k_min=5, tau=1e-9, max_step
                truncated=int(o.truncated))
     del keep, fa
     return res
+
+
+def perturbed_kernel(Q0, seed, sample, delta, r_min):
+    """Sampled admissible kernel of the robust search (multiplicative radius, row cap 1 - r_min)."""
+    Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
+    Q = np.zeros_like(Q0)
+    lib().or_perturbed_kernel(Q0.shape[0], _ptr(Q0, C.c_double), int(seed), int(sample), float(delta), float(r_min),
+                              _ptr(Q, C.c_double))
+    return Q
+
+
+def robust(Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0):
+    """Transition rewards, sampled KL / TV maximisers and the first-order sensitivity (Sections 5.4, 6.4)."""
+    Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
+    n = Q0.shape[0]
+    s_arr = np.full(n, 1.0 / n) if s is None else np.ascontiguousarray(s, dtype=np.float64)
+    ri = _RobustIn()
+    ri.s, ri.samples, ri.delta, ri.r_min, ri.seed = _ptr(s_arr, C.c_double), int(samples), float(delta), \
+        float(r_min), int(seed)
+    fa = None
+    if f is not None:
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        ri.f = _ptr(fa, C.c_double)
+    out = {"b0": np.zeros(n), "kl": np.zeros(max(samples, 1)), "tv": np.zeros(max(samples, 1)), "b_kl": np.zeros(n),
+           "b_tv": np.zeros(n), "b_lin": np.zeros(n)}
+    ro = _RobustOut()
+    for key in out:
+        setattr(ro, key, _ptr(out[key], C.c_double))
+    _check(lib().or_robust(n, _ptr(Q0, C.c_double), C.byref(ri), C.byref(ro)), "robust")
+    for key in ("b_sw", "b_imp", "norm_N0E", "norm_N0", "rem_bound", "rem_actual"):
+        out[key] = float(getattr(ro, key))
+    out["kl_arg"], out["tv_arg"] = int(ro.kl_arg), int(ro.tv_arg)
+    out["kl"], out["tv"] = out["kl"][:samples], out["tv"][:samples]
+    del fa
+    return out
 
 
 # --------------------------------------------------------------------------- chain algebra

@@ -1149,3 +1149,179 @@ int or_tail(int32_t n, const uint32_t *counts, const uint32_t *counts_w, uint32_
     }
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Robust tail on a given transient block Q0 (Sections 5.1, 5.4, 6.4 and the */
+/* robust experiment of Section 9.1).                                        */
+/*  - transition rewards (Section 6.4): switching eta(i,j) = 1{j != i} and     */
+/*    improvement eta(i,j) = (f_j - f_i)_+ for j in V (0 on absorption), with  */
+/*    psi_i = sum_j Q_ij eta(i,j) and the reward-AFC mu . psi / E[T];          */
+/*  - sampled admissible kernels: Q_ij = Q0_ij (1 + delta (2u - 1)) clipped to */
+/*    [0, 1], u uniform from Philox counter (sample, i, j, 3) as a 53-bit      */
+/*    fraction, and each row scaled down to sum 1 - r_min when it exceeds it;  */
+/*    for each sample b(P), KL(b(P) || b0) and TV = |b(P) - b0|_1 / 2;         */
+/*  - first-order sensitivity (Section 5.4) for E = Q* - Q0, Q* the KL         */
+/*    maximiser: b_lin = b0 + mu0 E N0 / (mu0 1) - b0 (mu0 E N0 1) / (mu0 1),  */
+/*    the remainder bound |N0 E|^2 |N0| / (1 - |N0 E|) and the actual          */
+/*    |N* - N0 - N0 E N0| (infinity norms).                                    */
+/* ------------------------------------------------------------------------ */
+static double or_u53(uint64_t seed, uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t ctr[4], key[2], x[4];
+    key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
+    ctr[0] = a; ctr[1] = b; ctr[2] = c; ctr[3] = 3u;
+    or_philox4x32_10(ctr, key, x);
+    return (double)((((uint64_t)x[0]) << 21) ^ (((uint64_t)x[1]) >> 11)) * (1.0 / 9007199254740992.0);
+}
+
+void or_perturbed_kernel(int32_t n, const double *Q0, uint64_t seed, int32_t sample, double delta, double r_min,
+                         double *Q)
+{
+    int32_t i, j;
+    for (i = 0; i < n; ++i) {
+        double tot = 0.0, cap = 1.0 - r_min;
+        for (j = 0; j < n; ++j) {
+            double u = or_u53(seed, (uint32_t)sample, (uint32_t)i, (uint32_t)j);
+            double f = 1.0 + delta * (2.0 * u - 1.0);
+            double q = Q0[(size_t)i * n + j] * f;
+            if (q < 0.0) q = 0.0;
+            if (q > 1.0) q = 1.0;
+            Q[(size_t)i * n + j] = q;
+            tot += q;
+        }
+        if (tot > cap)
+            for (j = 0; j < n; ++j) Q[(size_t)i * n + j] *= cap / tot;
+    }
+}
+
+static double or_inf_norm(int32_t n, const double *A)
+{
+    int32_t i, j;
+    double best = 0.0;
+    for (i = 0; i < n; ++i) {
+        double t = 0.0;
+        for (j = 0; j < n; ++j) t += fabs(A[(size_t)i * n + j]);
+        if (t > best) best = t;
+    }
+    return best;
+}
+
+static void or_matmul(int32_t n, const double *A, const double *B, double *C)
+{
+    int32_t i, j, k;
+    for (i = 0; i < n; ++i)
+        for (j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+            C[(size_t)i * n + j] = acc;
+        }
+}
+
+typedef struct {
+    const double *s;             /* n                                          */
+    const double *f;             /* n or NULL (no transition rewards)          */
+    int32_t samples;             /* sampled admissible kernels                 */
+    double delta;                /* relative radius                            */
+    double r_min;                /* leak lower bound                           */
+    uint64_t seed;
+} or_robust_in;
+
+typedef struct {
+    double *b0;                  /* n                                          */
+    double b_sw, b_imp;          /* transition reward-AFCs                      */
+    double *kl, *tv;             /* samples                                    */
+    int32_t kl_arg, tv_arg;
+    double *b_kl, *b_tv;         /* n: AFC at the maximisers                    */
+    double *b_lin;               /* n: first-order AFC for E = Q_kl - Q0        */
+    double norm_N0E, norm_N0, rem_bound, rem_actual;
+} or_robust_out;
+
+int or_robust(int32_t n, const double *Q0, const or_robust_in *in, or_robust_out *out)
+{
+    size_t nn = (size_t)n * (size_t)n;
+    double *N0 = (double *)malloc(sizeof(double) * nn), *Qs = (double *)malloc(sizeof(double) * nn);
+    double *Ns = (double *)malloc(sizeof(double) * nn), *M1 = (double *)malloc(sizeof(double) * nn);
+    double *M2 = (double *)malloc(sizeof(double) * nn);
+    double *mu0 = (double *)malloc(sizeof(double) * (size_t)n), *mus = (double *)malloc(sizeof(double) * (size_t)n);
+    double *bs = (double *)malloc(sizeof(double) * (size_t)n), *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double ET0, ETs;
+    int32_t i, j, k;
+    int rc = OR_OK;
+    if (!N0 || !Qs || !Ns || !M1 || !M2 || !mu0 || !mus || !bs || !v || !w) { rc = OR_E_NOMEM; goto done; }
+    rc = or_fundamental(n, Q0, N0);
+    if (rc != OR_OK) goto done;
+    or_visits(n, N0, in->s, mu0, &ET0, out->b0);
+    out->b_sw = 0.0;
+    out->b_imp = 0.0;
+    if (in->f) {
+        for (i = 0; i < n; ++i) {
+            double sw = 0.0, im = 0.0;
+            for (j = 0; j < n; ++j) {
+                double q = Q0[(size_t)i * n + j], d = in->f[j] - in->f[i];
+                if (j != i) sw += q;
+                if (d > 0.0) im += q * d;
+            }
+            out->b_sw += mu0[i] * sw;
+            out->b_imp += mu0[i] * im;
+        }
+        out->b_sw /= ET0;
+        out->b_imp /= ET0;
+    }
+    out->kl_arg = -1;
+    out->tv_arg = -1;
+    for (k = 0; k < in->samples; ++k) {
+        double kl = 0.0, tv = 0.0;
+        or_perturbed_kernel(n, Q0, in->seed, k, in->delta, in->r_min, Qs);
+        rc = or_fundamental(n, Qs, Ns);
+        if (rc != OR_OK) goto done;
+        or_visits(n, Ns, in->s, mus, &ETs, bs);
+        for (j = 0; j < n; ++j) {
+            if (bs[j] > 0.0) kl += bs[j] * log(bs[j] / out->b0[j]);
+            tv += fabs(bs[j] - out->b0[j]);
+        }
+        tv *= 0.5;
+        out->kl[k] = kl;
+        out->tv[k] = tv;
+        if (out->kl_arg < 0 || kl > out->kl[out->kl_arg]) {
+            out->kl_arg = k;
+            memcpy(out->b_kl, bs, sizeof(double) * (size_t)n);
+        }
+        if (out->tv_arg < 0 || tv > out->tv[out->tv_arg]) {
+            out->tv_arg = k;
+            memcpy(out->b_tv, bs, sizeof(double) * (size_t)n);
+        }
+    }
+    if (out->kl_arg >= 0) {
+        double tot = 0.0, vs = 0.0;
+        or_perturbed_kernel(n, Q0, in->seed, out->kl_arg, in->delta, in->r_min, Qs);
+        for (k = 0; k < (int32_t)nn; ++k) Qs[k] -= Q0[k];                 /* E */
+        for (j = 0; j < n; ++j) {                                          /* w = mu0 E */
+            double acc = 0.0;
+            for (i = 0; i < n; ++i) acc += mu0[i] * Qs[(size_t)i * n + j];
+            w[j] = acc;
+        }
+        for (j = 0; j < n; ++j) {                                          /* v = mu0 E N0 */
+            double acc = 0.0;
+            for (i = 0; i < n; ++i) acc += w[i] * N0[(size_t)i * n + j];
+            v[j] = acc;
+            vs += acc;
+        }
+        for (j = 0; j < n; ++j) tot += mu0[j];
+        for (j = 0; j < n; ++j) out->b_lin[j] = out->b0[j] + v[j] / tot - out->b0[j] * vs / tot;
+        or_matmul(n, N0, Qs, M1);                                          /* N0 E */
+        out->norm_N0E = or_inf_norm(n, M1);
+        out->norm_N0 = or_inf_norm(n, N0);
+        out->rem_bound = out->norm_N0E < 1.0
+                             ? out->norm_N0E * out->norm_N0E * out->norm_N0 / (1.0 - out->norm_N0E) : INFINITY;
+        or_matmul(n, M1, N0, M2);                                          /* N0 E N0 */
+        or_perturbed_kernel(n, Q0, in->seed, out->kl_arg, in->delta, in->r_min, Qs);   /* Q* again */
+        rc = or_fundamental(n, Qs, Ns);
+        if (rc != OR_OK) goto done;
+        for (k = 0; k < (int32_t)nn; ++k) Ns[k] -= N0[k] + M2[k];
+        out->rem_actual = or_inf_norm(n, Ns);
+    }
+done:
+    free(N0); free(Qs); free(Ns); free(M1); free(M2); free(mu0); free(mus); free(bs); free(v); free(w);
+    return rc;
+}
