@@ -322,6 +322,41 @@ typedef struct amc_traj_result {
 AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_traj_query *q,
                              amc_traj_result *out);
 
+/* Robust tail on a given transient block Q0 (n x n, row sums < 1), e.g. the
+ * stabilised kernel amc_run returns in `Q`:
+ *  - transition reward-AFCs (Section 6.4), with f: switching, eta(i,j) =
+ *    1{j in V, j != i}, and improvement, eta(i,j) = (f_j - f_i)_+ for j in V;
+ *  - `samples` admissible kernels of the row-wise set (Section 5.1) drawn as in
+ *    the robust experiment of Section 9.1: Q_ij = clip(Q0_ij (1 + delta
+ *    (2u - 1)), 0, 1), u the 53-bit fraction of the Philox block of counter
+ *    (sample, i, j, 3) under key `seed`, each row scaled down to sum 1 - r_min
+ *    when it exceeds it; for each, KL(b(P) || b0) and total variation
+ *    |b(P) - b0|_1 / 2, and the AFC at both maximisers;
+ *  - the first-order sensitivity of Section 5.4 for E = Q* - Q0 (Q* the KL
+ *    maximiser): b_lin, and in infinity norms |N0 E|, |N0|, the remainder
+ *    bound |N0 E|^2 |N0| / (1 - |N0 E|) (infinite when |N0 E| >= 1) and the
+ *    actual |N* - N0 - N0 E N0|.
+ * Output arrays are caller-owned host buffers (NULL = skip). */
+typedef struct amc_robust_query {
+    const double *s;            /* initial distribution (n) or NULL for uniform  */
+    const double *f;            /* node values (n, >= 0) or NULL (no transition rewards) */
+    int32_t samples;            /* 0 .. 4096                                     */
+    double delta;               /* relative radius, >= 0                          */
+    double r_min;               /* leak lower bound, in (0, 1]                    */
+    uint64_t seed;
+} amc_robust_query;
+
+typedef struct amc_robust_result {
+    double *b0;                 /* n                                             */
+    double b_sw, b_imp;
+    double *kl, *tv;            /* samples                                       */
+    int32_t kl_arg, tv_arg;     /* -1 without samples                            */
+    double *b_kl, *b_tv, *b_lin;/* n each                                        */
+    double norm_N0E, norm_N0, rem_bound, rem_actual;
+    double tail_ms;             /* HIP-event time of the whole computation        */
+} amc_robust_result;
+AMC_API int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_robust_query *q, amc_robust_result *out);
+
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
  * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,

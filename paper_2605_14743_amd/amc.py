@@ -26,7 +26,8 @@ MAX_TOPK, MAX_TOPK_N = 64, 7000
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
-           "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_chain", "amc_strerror", "amc_version"]
+           "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_chain", "amc_strerror",
+           "amc_version"]
 WANT_PATHS = 1
 
 _P = C.POINTER
@@ -65,6 +66,19 @@ class TrajResult(C.Structure):
                 ("b_hat", _P(C.c_double)), ("survival", _P(C.c_double)), ("reward_f", C.c_double),
                 ("switches", C.c_uint64), ("total_steps", C.c_uint64), ("sources", C.c_uint64),
                 ("truncated", C.c_int32), ("sweep_ms", C.c_double)]
+
+
+class RobustQuery(C.Structure):
+    _fields_ = [("s", _P(C.c_double)), ("f", _P(C.c_double)), ("samples", C.c_int32), ("delta", C.c_double),
+                ("r_min", C.c_double), ("seed", C.c_uint64)]
+
+
+class RobustResult(C.Structure):
+    _fields_ = [("b0", _P(C.c_double)), ("b_sw", C.c_double), ("b_imp", C.c_double), ("kl", _P(C.c_double)),
+                ("tv", _P(C.c_double)), ("kl_arg", C.c_int32), ("tv_arg", C.c_int32), ("b_kl", _P(C.c_double)),
+                ("b_tv", _P(C.c_double)), ("b_lin", _P(C.c_double)), ("norm_N0E", C.c_double),
+                ("norm_N0", C.c_double), ("rem_bound", C.c_double), ("rem_actual", C.c_double),
+                ("tail_ms", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -136,6 +150,7 @@ def lib():
         L.amc_batch_destroy.restype = None
         L.amc_tune.argtypes = [vp, vp, _P(Model), _P(Query), C.c_uint32, _P(TuneResult)]
         L.amc_trajectories.argtypes = [vp, vp, _P(Model), _P(TrajQuery), _P(TrajResult)]
+        L.amc_robust.argtypes = [vp, C.c_int32, _P(C.c_double), _P(RobustQuery), _P(RobustResult)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -490,4 +505,35 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
     for key in ("switches", "total_steps", "sources", "truncated"):
         out[key] = int(getattr(res, key))
     del keep_m, fa
+    return out
+
+
+def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0) -> dict:
+    """amc_robust: transition reward-AFCs, sampled admissible kernels with their KL / TV
+    maximisers, and the first-order sensitivity with its remainder (Sections 5.1, 5.4, 6.4)."""
+    Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
+    n = Q0.shape[0]
+    q = RobustQuery()
+    keep = []
+    if s is not None:
+        sa = np.ascontiguousarray(s, dtype=np.float64)
+        keep.append(sa)
+        q.s = _ptr(sa, C.c_double)
+    if f is not None:
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        keep.append(fa)
+        q.f = _ptr(fa, C.c_double)
+    q.samples, q.delta, q.r_min, q.seed = int(samples), float(delta), float(r_min), int(seed)
+    arr = {"b0": np.zeros(n), "kl": np.zeros(max(samples, 1)), "tv": np.zeros(max(samples, 1)), "b_kl": np.zeros(n),
+           "b_tv": np.zeros(n), "b_lin": np.zeros(n)}
+    res = RobustResult()
+    for key, a in arr.items():
+        setattr(res, key, _ptr(a, C.c_double))
+    _check(lib().amc_robust(ctx.h, n, _ptr(Q0, C.c_double), C.byref(q), C.byref(res)), "amc_robust")
+    out = dict(arr)
+    out["kl"], out["tv"] = out["kl"][:samples], out["tv"][:samples]
+    for key in ("b_sw", "b_imp", "norm_N0E", "norm_N0", "rem_bound", "rem_actual", "tail_ms"):
+        out[key] = float(getattr(res, key))
+    out["kl_arg"], out["tv_arg"] = int(res.kl_arg), int(res.tv_arg)
+    del keep
     return out

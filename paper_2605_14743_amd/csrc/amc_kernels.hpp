@@ -26,6 +26,21 @@ hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, in
 hipError_t set_sweep_wave_attrs(int max_lds);
 hipError_t set_sweep_block_attrs(int max_lds);
 
+// Robust tail (sampled admissible kernels, sensitivity, transition rewards).
+hipError_t robust_perturb(int n, const double *Q0, uint64_t seed, int sample, const int *sample_ptr, double delta,
+                          double r_min, double *Q, double *A, hipStream_t st);
+hipError_t robust_divergence(int n, const double *b, const double *b0, double *kl, double *tv, hipStream_t st);
+hipError_t robust_argmax(int m, const double *x, int *out, hipStream_t st);
+hipError_t robust_gather_row(int n, const double *rows, const int *idx, double *dst, hipStream_t st);
+hipError_t robust_vecmat(int n, const double *x, const double *M, double *y, hipStream_t st);
+hipError_t robust_blin(int n, const double *b0, const double *mu0, const double *v, double *b_lin, hipStream_t st);
+hipError_t robust_axpy(size_t count, const double *A, double alpha, const double *B, double beta, const double *D,
+                       double *C, hipStream_t st);
+hipError_t robust_infnorm(int n, const double *A, unsigned long long *out, hipStream_t st);
+hipError_t robust_gemm(int n, const double *A, const double *B, double *C, hipStream_t st);
+hipError_t robust_rem_bound(const unsigned long long *norms, double *out, hipStream_t st);
+hipError_t robust_trans_rewards(int n, const double *Q, const double *f, double *psw, double *pimp, hipStream_t st);
+
 // Anchored r-hop neighbourhoods (LDS mode only).
 uint32_t lds_bytes_anchored(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
 hipError_t set_anchored_attrs(int max_lds);

@@ -1,0 +1,306 @@
+// robust.hip -- robust tail on a given transient block Q0 (Sections 5.1, 5.4,
+// 6.4 and the robust experiment of Section 9.1), FP64 on the device.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach".
+//
+//  - sampled admissible kernels: Q_ij = clip(Q0_ij (1 + delta (2u - 1)), 0, 1)
+//    with u the 53-bit fraction of the Philox block of counter (sample, i, j,
+//    3), each row scaled to 1 - r_min when its sum exceeds that;
+//  - KL(b(P) || b0) and total variation for each sample, and their maximisers;
+//  - first-order sensitivity for E = Q* - Q0 (the KL maximiser): b_lin, the
+//    infinity norms |N0 E|, |N0| and |N* - N0 - N0 E N0|;
+//  - transition rewards: switching (j != i) and improvement ((f_j - f_i)_+).
+// The multiplier is formed with explicitly rounded operations so that no
+// fused multiply-add changes it.
+#include "amc_dev.hpp"
+#include "amc_kernels.hpp"
+
+namespace amc {
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b, uint32_t c, uint32_t k0, uint32_t k1) {
+    const u32x4 x = philox10({a, b, c, 3u}, k0, k1);
+    const uint64_t bits = (((uint64_t)x.x) << 21) ^ (((uint64_t)x.y) >> 11);
+    return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+// One workgroup per row: the sampled row of Q and the row of A = I - Q.  The
+// sample index is read from `sample_ptr` when given (the KL maximiser).
+__global__ void k_perturb(int n, const double *Q0, uint32_t k0, uint32_t k1, int sample, const int *sample_ptr,
+                          double delta, double r_min, double *Q, double *A) {
+    __shared__ double red[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const uint32_t smp = (uint32_t)(sample_ptr ? *sample_ptr : sample);
+    double tot = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double u = u53(smp, (uint32_t)i, (uint32_t)j, k0, k1);
+        const double f = __dadd_rn(1.0, __dmul_rn(delta, __dadd_rn(__dmul_rn(2.0, u), -1.0)));
+        double q = __dmul_rn(Q0[(size_t)i * n + j], f);
+        q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+        Q[(size_t)i * n + j] = q;
+        tot += q;
+    }
+    red[tid] = tot;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double cap = 1.0 - r_min;
+    const double sc = red[0] > cap ? cap / red[0] : 1.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double q = red[0] > cap ? Q[(size_t)i * n + j] * sc : Q[(size_t)i * n + j];
+        Q[(size_t)i * n + j] = q;
+        A[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - q;
+    }
+}
+
+// KL(b || b0) and total variation of one sample (single workgroup).
+__global__ void k_divergence(int n, const double *b, const double *b0, double *kl, double *tv) {
+    __shared__ double r1[256], r2[256];
+    const int tid = threadIdx.x;
+    double a = 0.0, t = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        if (b[j] > 0.0) a += b[j] * log(b[j] / b0[j]);
+        t += fabs(b[j] - b0[j]);
+    }
+    r1[tid] = a;
+    r2[tid] = t;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            r1[tid] += r1[tid + s];
+            r2[tid] += r2[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *kl = r1[0];
+        *tv = 0.5 * r2[0];
+    }
+}
+
+// First index of the maximum of x[0..m) (single workgroup).
+__global__ void k_argmax(int m, const double *x, int *out) {
+    __shared__ double rv[256];
+    __shared__ int ri[256];
+    const int tid = threadIdx.x;
+    double best = -INFINITY;
+    int bi = 0x7FFFFFFF;
+    for (int k = tid; k < m; k += blockDim.x)
+        if (x[k] > best || (x[k] == best && k < bi)) {
+            best = x[k];
+            bi = k;
+        }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s && (rv[tid + s] > rv[tid] || (rv[tid + s] == rv[tid] && ri[tid + s] < ri[tid]))) {
+            rv[tid] = rv[tid + s];
+            ri[tid] = ri[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *out = ri[0];
+}
+
+// dst = rows[*idx] (n entries).
+__global__ void k_gather_row(int n, const double *rows, const int *idx, double *dst) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) dst[j] = rows[(size_t)(*idx) * n + j];
+}
+
+// y = x M (row vector times matrix), one thread per column.
+__global__ void k_vecmat(int n, const double *x, const double *M, double *y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += x[i] * M[(size_t)i * n + j];
+    y[j] = acc;
+}
+
+// b_lin = b0 + v / (mu0 1) - b0 (v 1) / (mu0 1)  (single workgroup).
+__global__ void k_blin(int n, const double *b0, const double *mu0, const double *v, double *b_lin) {
+    __shared__ double r1[256], r2[256];
+    const int tid = threadIdx.x;
+    double a = 0.0, t = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        a += mu0[j];
+        t += v[j];
+    }
+    r1[tid] = a;
+    r2[tid] = t;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            r1[tid] += r1[tid + s];
+            r2[tid] += r2[tid + s];
+        }
+        __syncthreads();
+    }
+    const double tot = r1[0], vs = r2[0];
+    for (int j = tid; j < n; j += blockDim.x) b_lin[j] = b0[j] + v[j] / tot - b0[j] * vs / tot;
+}
+
+// C = A + alpha B + beta D (elementwise; D may be null).
+__global__ void k_axpy(size_t count, const double *A, double alpha, const double *B, double beta, const double *D,
+                       double *C) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+        C[k] = A[k] + alpha * B[k] + (D ? beta * D[k] : 0.0);
+}
+
+// Infinity norm (largest absolute row sum): one workgroup per row, atomic max
+// on the bit pattern (non-negative doubles order like their bits).
+__global__ void k_rowabs(int n, const double *A, unsigned long long *out) {
+    __shared__ double red[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    double acc = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) acc += fabs(A[(size_t)i * n + j]);
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) atomicMax(out, as_u64(red[0]));
+}
+
+// C = A B for n x n row-major FP64 matrices: 64 x 64 output tile per
+// workgroup of 256 threads (4 x 4 per thread), K in steps of 16 through LDS.
+__global__ __launch_bounds__(256) void k_gemm(int n, const double *A, const double *B, double *C) {
+    __shared__ double As[64][17];
+    __shared__ double Bs[16][65];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        for (int t = threadIdx.x; t < 64 * 16; t += 256) {
+            const int r = t / 16, c = t % 16;
+            As[r][c] = (i0 + r < n && k0 + c < n) ? A[(size_t)(i0 + r) * n + k0 + c] : 0.0;
+            const int r2 = t / 64, c2 = t % 64;
+            Bs[r2][c2] = (k0 + r2 < n && j0 + c2 < n) ? B[(size_t)(k0 + r2) * n + j0 + c2] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[ty + 16 * q][k];
+                b[q] = Bs[k][tx + 16 * q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + ty + 16 * p, j = j0 + tx + 16 * q;
+            if (i < n && j < n) C[(size_t)i * n + j] = acc[p][q];
+        }
+}
+
+// Transition rewards per row: switching sum_{j != i} Q_ij, improvement
+// sum_j Q_ij (f_j - f_i)_+.
+__global__ void k_trans_rewards(int n, const double *Q, const double *f, double *psw, double *pimp) {
+    __shared__ double r1[256], r2[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double q = Q[(size_t)i * n + j];
+        if (j != i) a += q;
+        const double d = f[j] - f[i];
+        if (d > 0.0) b += q * d;
+    }
+    r1[tid] = a;
+    r2[tid] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            r1[tid] += r1[tid + s];
+            r2[tid] += r2[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        psw[i] = r1[0];
+        pimp[i] = r2[0];
+    }
+}
+
+// Remainder bound of Section 5.4 from the norms [|N0 E|, |N0|]:
+// |N0 E|^2 |N0| / (1 - |N0 E|), infinite when |N0 E| >= 1.
+__global__ void k_rem_bound(const unsigned long long *norms, double *out) {
+    const double a = as_f64(norms[0]), b = as_f64(norms[1]);
+    *out = a < 1.0 ? a * a * b / (1.0 - a) : INFINITY;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t robust_rem_bound(const unsigned long long *norms, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rem_bound, dim3(1), dim3(1), 0, st, norms, out);
+    return hipGetLastError();
+}
+
+hipError_t robust_perturb(int n, const double *Q0, uint64_t seed, int sample, const int *sample_ptr, double delta,
+                          double r_min, double *Q, double *A, hipStream_t st) {
+    hipLaunchKernelGGL(k_perturb, dim3(n), dim3(256), 0, st, n, Q0, (uint32_t)seed, (uint32_t)(seed >> 32), sample,
+                       sample_ptr, delta, r_min, Q, A);
+    return hipGetLastError();
+}
+
+hipError_t robust_divergence(int n, const double *b, const double *b0, double *kl, double *tv, hipStream_t st) {
+    hipLaunchKernelGGL(k_divergence, dim3(1), dim3(256), 0, st, n, b, b0, kl, tv);
+    return hipGetLastError();
+}
+
+hipError_t robust_argmax(int m, const double *x, int *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, st, m, x, out);
+    return hipGetLastError();
+}
+
+hipError_t robust_gather_row(int n, const double *rows, const int *idx, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_row, dim3((n + 255) / 256), dim3(256), 0, st, n, rows, idx, dst);
+    return hipGetLastError();
+}
+
+hipError_t robust_vecmat(int n, const double *x, const double *M, double *y, hipStream_t st) {
+    hipLaunchKernelGGL(k_vecmat, dim3((n + 255) / 256), dim3(256), 0, st, n, x, M, y);
+    return hipGetLastError();
+}
+
+hipError_t robust_blin(int n, const double *b0, const double *mu0, const double *v, double *b_lin, hipStream_t st) {
+    hipLaunchKernelGGL(k_blin, dim3(1), dim3(256), 0, st, n, b0, mu0, v, b_lin);
+    return hipGetLastError();
+}
+
+hipError_t robust_axpy(size_t count, const double *A, double alpha, const double *B, double beta, const double *D,
+                       double *C, hipStream_t st) {
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks), dim3(256), 0, st, count, A, alpha, B, beta, D, C);
+    return hipGetLastError();
+}
+
+hipError_t robust_infnorm(int n, const double *A, unsigned long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rowabs, dim3(n), dim3(256), 0, st, n, A, out);
+    return hipGetLastError();
+}
+
+hipError_t robust_gemm(int n, const double *A, const double *B, double *C, hipStream_t st) {
+    const unsigned t = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_gemm, dim3(t, t), dim3(256), 0, st, n, A, B, C);
+    return hipGetLastError();
+}
+
+hipError_t robust_trans_rewards(int n, const double *Q, const double *f, double *psw, double *pimp, hipStream_t st) {
+    hipLaunchKernelGGL(k_trans_rewards, dim3(n), dim3(256), 0, st, n, Q, f, psw, pimp);
+    return hipGetLastError();
+}
+
+}  // namespace amc

@@ -1,0 +1,185 @@
+// robust_host.cpp -- host side of the robust tail (amc_robust): checks,
+// device buffers, the sequence of sample inversions and the sensitivity.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach" (Sections 5.1, 5.4, 6.4).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "amc_kernels.hpp"
+#include "query.hpp"
+
+using namespace amc;
+
+#define HIPCHK(expr)                          \
+    do {                                      \
+        if ((expr) != hipSuccess) {           \
+            (void)hipGetLastError();          \
+            return AMC_E_HIP;                 \
+        }                                     \
+    } while (0)
+#define RCHK(expr)                            \
+    do {                                      \
+        int rc_ = (expr);                     \
+        if (rc_ != AMC_OK) return rc_;        \
+    } while (0)
+
+extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_robust_query *q,
+                          amc_robust_result *out) {
+    if (!ctx || !Q0 || !q || !out || n < 1) return AMC_E_INVALID_ARG;
+    if (q->samples < 0 || q->samples > 4096 || !(q->delta >= 0.0) || !std::isfinite(q->delta)) return AMC_E_INVALID_ARG;
+    if (!(q->r_min > 0.0 && q->r_min <= 1.0)) return AMC_E_INVALID_ARG;
+    for (size_t k = 0; k < (size_t)n * n; ++k)
+        if (!(Q0[k] >= 0.0 && Q0[k] <= 1.0)) return AMC_E_INVALID_ARG;
+    for (int i = 0; i < n; ++i) {
+        double t = 0.0;
+        for (int j = 0; j < n; ++j) t += Q0[(size_t)i * n + j];
+        if (!(t < 1.0)) return AMC_E_INVALID_ARG;
+    }
+    std::vector<double> s_uni;
+    const double *s = q->s;
+    if (s) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!(s[i] >= 0.0)) return AMC_E_INVALID_ARG;
+            t += s[i];
+        }
+        if (std::fabs(t - 1.0) > 1e-9) return AMC_E_INVALID_ARG;
+    } else {
+        s_uni.assign((size_t)n, 1.0 / n);
+        s = s_uni.data();
+    }
+    if (q->f)
+        for (int i = 0; i < n; ++i)
+            if (!(q->f[i] >= 0.0) || !std::isfinite(q->f[i])) return AMC_E_INVALID_ARG;
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return AMC_E_HIP;
+    hipStream_t st = ctx->stream;
+    DevArena A;
+    A.stream = st;
+    A.async = ctx->async_alloc;
+    struct Guard {
+        DevArena &a;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            a.release();
+        }
+    } guard{A, st};
+    const size_t nn = (size_t)n * n;
+    const int S = q->samples;
+    void *p;
+    auto alloc = [&](size_t bytes) -> void * { return A.alloc(bytes, &p) == AMC_OK ? p : nullptr; };
+    double *dQ0 = (double *)alloc(8 * nn), *N0 = (double *)alloc(8 * nn), *W = (double *)alloc(8 * nn);
+    double *M1 = (double *)alloc(8 * nn), *M2 = (double *)alloc(8 * nn), *Qs = (double *)alloc(8 * nn);
+    double *ds = (double *)alloc(8 * (size_t)n), *mu0 = (double *)alloc(8 * (size_t)n), *b0 = (double *)alloc(8 * (size_t)n);
+    double *mus = (double *)alloc(8 * (size_t)n), *v = (double *)alloc(8 * (size_t)n), *w = (double *)alloc(8 * (size_t)n);
+    double *blin = (double *)alloc(8 * (size_t)n), *bkl = (double *)alloc(8 * (size_t)n), *btv = (double *)alloc(8 * (size_t)n);
+    double *scal = (double *)alloc(8 * 8), *scal2 = (double *)alloc(8 * 8), *rsc = (double *)alloc(8 * 8);
+    double *brows = (double *)alloc(8 * (size_t)std::max(S, 1) * n);
+    double *kl = (double *)alloc(8 * (size_t)std::max(S, 1)), *tv = (double *)alloc(8 * (size_t)std::max(S, 1));
+    double *dr = (double *)alloc(8 * (size_t)n), *psw = (double *)alloc(8 * (size_t)n), *pimp = (double *)alloc(8 * (size_t)n);
+    double *df = q->f ? (double *)alloc(8 * (size_t)n) : nullptr;
+    int32_t *top = (int32_t *)alloc(4 * 16);
+    int *args = (int *)alloc(16), *err = (int *)alloc(16);
+    unsigned long long *norms = (unsigned long long *)alloc(8 * 4);
+    if (!dQ0 || !N0 || !W || !M1 || !M2 || !Qs || !ds || !mu0 || !b0 || !mus || !v || !w || !blin || !bkl || !btv ||
+        !scal || !scal2 || !rsc || !brows || !kl || !tv || !dr || !psw || !pimp || (q->f && !df) || !top || !args ||
+        !err || !norms)
+        return AMC_E_OOM;
+    HIPCHK(hipMemcpyAsync(dQ0, Q0, 8 * nn, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ds, s, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    if (df) HIPCHK(hipMemcpyAsync(df, q->f, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(fill_u32(err, 4, 0u, st));
+    HIPCHK(fill_u32(norms, 8, 0u, st));
+    HIPCHK(fill_u32(rsc, 16, 0u, st));
+    hipEvent_t ev[2];
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    HIPCHK(hipEventRecord(ev[0], st));
+    // nominal chain: N0, mu0, b0
+    HIPCHK(tail_kernel_from_Q(n, dQ0, dr, N0, st));
+    HIPCHK(tail_invert(n, N0, err, st));
+    HIPCHK(tail_visits(n, N0, ds, mu0, b0, nullptr, nullptr, nullptr, nullptr, 0.0, 0, top, scal, st));
+    // transition rewards (Section 6.4)
+    if (df) {
+        HIPCHK(robust_trans_rewards(n, dQ0, df, psw, pimp, st));
+        HIPCHK(tail_reward_afc(n, mu0, scal, psw, &rsc[0], st));
+        HIPCHK(tail_reward_afc(n, mu0, scal, pimp, &rsc[1], st));
+    }
+    // sampled admissible kernels
+    for (int k = 0; k < S; ++k) {
+        HIPCHK(robust_perturb(n, dQ0, q->seed, k, nullptr, q->delta, q->r_min, Qs, W, st));
+        HIPCHK(tail_invert(n, W, err, st));
+        HIPCHK(tail_visits(n, W, ds, mus, brows + (size_t)k * n, nullptr, nullptr, nullptr, nullptr, 0.0, 0, top,
+                           scal2, st));
+        HIPCHK(robust_divergence(n, brows + (size_t)k * n, b0, kl + k, tv + k, st));
+    }
+    if (S > 0) {
+        HIPCHK(robust_argmax(S, kl, args, st));
+        HIPCHK(robust_argmax(S, tv, args + 1, st));
+        HIPCHK(robust_gather_row(n, brows, args, bkl, st));
+        HIPCHK(robust_gather_row(n, brows, args + 1, btv, st));
+        // first-order sensitivity for E = Q* - Q0 (Section 5.4)
+        HIPCHK(robust_perturb(n, dQ0, q->seed, 0, args, q->delta, q->r_min, Qs, W, st));
+        HIPCHK(robust_axpy(nn, Qs, -1.0, dQ0, 0.0, nullptr, M2, st));          // M2 = E
+        HIPCHK(robust_vecmat(n, mu0, M2, w, st));                              // w = mu0 E
+        HIPCHK(robust_vecmat(n, w, N0, v, st));                                // v = mu0 E N0
+        HIPCHK(robust_blin(n, b0, mu0, v, blin, st));
+        HIPCHK(robust_gemm(n, N0, M2, M1, st));                                // M1 = N0 E
+        HIPCHK(robust_infnorm(n, M1, &norms[0], st));
+        HIPCHK(robust_infnorm(n, N0, &norms[1], st));
+        HIPCHK(robust_gemm(n, M1, N0, M2, st));                                // M2 = N0 E N0
+        HIPCHK(tail_invert(n, W, err, st));                                    // W = N*
+        HIPCHK(robust_axpy(nn, W, -1.0, N0, -1.0, M2, M1, st));                // N* - N0 - N0 E N0
+        HIPCHK(robust_infnorm(n, M1, &norms[2], st));
+        HIPCHK(robust_rem_bound(norms, &rsc[2], st));
+    }
+    HIPCHK(hipEventRecord(ev[1], st));
+    int herr = 0;
+    unsigned long long hn[4] = {0, 0, 0, 0};
+    double hr[3] = {0.0, 0.0, 0.0};
+    int ha[2] = {-1, -1};
+    HIPCHK(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hn, norms, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hr, rsc, 24, hipMemcpyDeviceToHost, st));
+    if (out->b0) HIPCHK(hipMemcpyAsync(out->b0, b0, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    if (S > 0) {
+        HIPCHK(hipMemcpyAsync(ha, args, 8, hipMemcpyDeviceToHost, st));
+        if (out->kl) HIPCHK(hipMemcpyAsync(out->kl, kl, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
+        if (out->tv) HIPCHK(hipMemcpyAsync(out->tv, tv, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
+        if (out->b_kl) HIPCHK(hipMemcpyAsync(out->b_kl, bkl, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+        if (out->b_tv) HIPCHK(hipMemcpyAsync(out->b_tv, btv, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+        if (out->b_lin) HIPCHK(hipMemcpyAsync(out->b_lin, blin, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr & 2) return AMC_E_SINGULAR;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    auto f64 = [](unsigned long long b) {
+        double d;
+        std::memcpy(&d, &b, 8);
+        return d;
+    };
+    out->b_sw = q->f ? hr[0] : 0.0;
+    out->b_imp = q->f ? hr[1] : 0.0;
+    out->kl_arg = S > 0 ? ha[0] : -1;
+    out->tv_arg = S > 0 ? ha[1] : -1;
+    out->norm_N0E = S > 0 ? f64(hn[0]) : 0.0;
+    out->norm_N0 = S > 0 ? f64(hn[1]) : 0.0;
+    out->rem_actual = S > 0 ? f64(hn[2]) : 0.0;
+    out->rem_bound = S > 0 ? hr[2] : 0.0;
+    out->tail_ms = ms;
+    return AMC_OK;
+}

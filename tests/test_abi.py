@@ -47,7 +47,8 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the ABI structs have the sizes and field offsets a C compiler gives."""
     structs = {"amc_model": amc.Model, "amc_query": amc.Query, "amc_stats": amc.Stats, "amc_result": amc.Result,
                "amc_tune_result": amc.TuneResult, "amc_traj_query": amc.TrajQuery,
-               "amc_traj_result": amc.TrajResult}
+               "amc_traj_result": amc.TrajResult, "amc_robust_query": amc.RobustQuery,
+               "amc_robust_result": amc.RobustResult}
     lines = []
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
