@@ -133,6 +133,18 @@ def run_bench(args):
         out["topk_stage"] = {"k": args.topk, "pool": int(len(q["pool"])), "ms": tk, "bytes_read": tb,
                              "GBps": tb / (tk * 1e-3) / 1e9, "b_k": last["b_k"], "b_kw": last["b_kw"],
                              "share_of_step": tk / (dt / args.steps * 1e3)}
+    if args.robust > 0:
+        # robust tail on the estimated kernel: (samples + 2) Gauss-Jordan
+        # inversions (2 n^3 flops each) and two n x n products (2 n^3 each)
+        f = np.linspace(0.0, 1.0, g.n)
+        amc.robust(ctx, last["Q"], f=f, samples=2, delta=0.5, r_min=0.05, seed=1)
+        rb = amc.robust(ctx, last["Q"], f=f, samples=args.robust, delta=0.5, r_min=0.05, seed=1)
+        flops = (args.robust + 2) * 2.0 * g.n ** 3 + 2 * 2.0 * g.n ** 3
+        out["robust_tail"] = {"samples": args.robust, "ms": rb["tail_ms"], "fp64_TFLOPs": flops / (rb["tail_ms"] * 1e-3)
+                              / 1e12, "peak_fp64_TFLOPs": 78.6, "kl_max": float(rb["kl"].max()),
+                              "tv_max": float(rb["tv"].max()), "norm_N0E": rb["norm_N0E"],
+                              "rem_bound": rb["rem_bound"], "rem_actual": rb["rem_actual"],
+                              "b_switch": rb["b_sw"], "b_improve": rb["b_imp"]}
     if args.plain_R > 0:
         qp = dict(q, R=args.plain_R, flags=amc.PLAIN_LAUNCH | amc.SKIP_TAIL)
         amc.run(ctx, G, model, **qp)
@@ -348,6 +360,7 @@ def main():
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
     ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
+    ap.add_argument("--robust", type=int, default=0, help="also run the robust tail with this many sampled kernels")
     ap.add_argument("--max-steps", dest="max_steps", type=int, default=512)
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
