@@ -73,6 +73,8 @@ def run_bench(args):
     q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
              r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group,
              pool=wl.pool, reward=wl.reward, hop_radius=wl.hop_radius)
+    if args.dist32:
+        q["flags"] = amc.DIST32
     if args.topk > 0:
         # finite-k local Top-k rows: a pool of 50 nodes with values U[0.5, 2]
         pool = wl.pool if wl.pool is not None else W.pool(g.n, 50, 1)
@@ -117,7 +119,7 @@ def run_bench(args):
                    "weights": wl.weight if wl.weight != "uniform" else f"uniform{{{wl.w_lo}..{wl.w_hi}}}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
                    "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"], "group": st["group"],
-                   "adj_bytes": st["adj_bytes"]},
+                   "adj_bytes": st["adj_bytes"], "dist_bytes": st["dist_bytes"]},
         "sweep_kernel_ms": k_ms,
         "tail_ms": float(np.mean(tail_ms)),
         "teps": teps,
@@ -356,6 +358,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--dist32", action="store_true", help="32-bit distance entries (comparison runs)")
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")

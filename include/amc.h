@@ -87,6 +87,12 @@ extern "C" {
 #define AMC_SKIP_TAIL (1u << 5)       /* counts only, no chain algebra            */
 #define AMC_PLAIN_LAUNCH (1u << 6)    /* one kernel launch per realization        */
 #define AMC_FALLBACK (1u << 7)        /* fallback kernel P^{W,fb} with v_fb = fb_node */
+#define AMC_DIST32 (1u << 8)          /* per-source distance entries of 32 bits ...          */
+#define AMC_DIST16 (1u << 9)          /* ... or of 16 bits (needs n * w_max < 0xFFFF); without
+                                         either flag the planner picks the width that keeps
+                                         more sources in flight.  Results are identical.
+                                         Both flags: AMC_E_INVALID_ARG.  The workgroup-per-
+                                         source and anchored kernels keep 32-bit entries. */
 
 typedef struct amc_ctx amc_ctx;
 typedef struct amc_graph amc_graph;
@@ -175,6 +181,8 @@ typedef struct amc_stats {
     double tail_ms;             /* HIP-event time of the tail kernels                          */
     int32_t mode, waves, tile, blocks, lds_bytes, launches, group, adj_bytes;
     double topk_ms;             /* HIP-event time of the finite-k Top-k stage (topk > 0) */
+    int32_t dist_bytes;         /* bytes per distance entry of the per-source state (2 or 4) */
+    int32_t reserved;
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */

@@ -19,8 +19,8 @@ OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NO
     0, -1, -2, -3, -4, -5, -6, -7, -8
 WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED, WEIGHT_TABLE = 0, 1, 2, 3
 MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
-WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK = \
-    1, 2, 4, 8, 16, 32, 64, 128
+WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK, DIST32, DIST16 = \
+    1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 MAX_TOPK, MAX_TOPK_N = 64, 7000
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
@@ -90,7 +90,8 @@ class Stats(C.Structure):
     _fields_ = [("units", C.c_uint64), ("sum_nK", C.c_uint64), ("sum_AK", C.c_uint64), ("sum_DK", C.c_uint64),
                 ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
                 ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
-                ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32), ("topk_ms", C.c_double)]
+                ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32), ("topk_ms", C.c_double),
+                ("dist_bytes", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -358,6 +358,7 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
             if (inW[v] && inF[v]) return AMC_E_INVALID_ARG;
     }
     if (q->hop_radius < 0) return AMC_E_INVALID_ARG;
+    if ((q->flags & AMC_DIST32) && (q->flags & AMC_DIST16)) return AMC_E_INVALID_ARG;
     if (q->hop_radius > 0) {
         if (q->topk > 0 || (q->flags & (AMC_WANT_CENTER | AMC_WANT_BSUM | AMC_WANT_DEBUG | AMC_PLAIN_LAUNCH)) ||
             (q->mode != AMC_MODE_AUTO && q->mode != AMC_MODE_WAVE))
@@ -415,8 +416,13 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->shift = 16;
     }
     pl->anchored = false;
+    // 16-bit distances are possible when every finite distance plus one
+    // weight stays below 0xFFFF; the mode choice below decides
+    pl->dist16 = (uint64_t)n * wmax < 0xFFFFull && !(q->flags & AMC_DIST32);
+    if ((q->flags & AMC_DIST16) && !pl->dist16) return AMC_E_UNSUPPORTED;
     if (q->hop_radius > 0) {
         // anchored neighbourhoods: one wavefront per anchor, lane per vertex
+        if (n > kMaxWaveVertices) return AMC_E_UNSUPPORTED;
         int aw = 0;
         uint32_t alds = 0, awb = 0;
         const int cap = q->waves > 0 ? q->waves : kMaxWaves;
@@ -431,6 +437,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         }
         if (aw == 0 || (q->waves > 0 && aw != q->waves)) return AMC_E_UNSUPPORTED;
         pl->anchored = true;
+        pl->dist16 = false;
         pl->mode = AMC_MODE_WAVE;
         pl->group = 1;
         pl->waves = aw;
@@ -457,64 +464,69 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->blocks = (int)std::min<uint64_t>(pl->items, slots);
         return AMC_OK;
     }
-    int best_w = 0;
-    uint32_t best_lds = 0, best_wb = 0;
     // the 8-slot lane mapping is built for at most 8 wavefronts per workgroup
     const int max_w = pl->group == 3 ? 8 : kMaxWaves;
     if (q->waves > max_w && q->mode != AMC_MODE_BLOCK) return AMC_E_UNSUPPORTED;
-    const int want_w = q->waves > 0 ? q->waves : max_w;
-    for (int w = 2; w <= want_w; ++w) {
-        uint32_t wb = 0;
-        const uint32_t lds = lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, &wb);
-        if (lds > (uint32_t)ctx->max_lds) break;
-        if ((uint64_t)wb * w < std::max<uint64_t>(2ull * (uint64_t)g->m, 32ull * (uint64_t)n)) continue;
-        best_w = w;
-        best_lds = lds;
-        best_wb = wb;
-    }
-    const bool wave_ok = best_w >= 2 && (q->waves == 0 || best_w == q->waves);
-    // L2 mode: the whole LDS goes to the wavefronts' private regions
-    int l2_w = 0;
-    uint32_t l2_lds = 0, l2_wb = 0;
-    for (int w = 2; w <= want_w; ++w) {
-        uint32_t wb = 0;
-        const uint32_t lds = lds_bytes_wave_l2(n, w, &wb);
-        if (lds > (uint32_t)ctx->max_lds) break;
-        if ((uint64_t)wb * w < std::max<uint64_t>(2ull * (uint64_t)g->m, 32ull * (uint64_t)n)) continue;
-        l2_w = w;
-        l2_lds = lds;
-        l2_wb = wb;
-    }
-    const bool l2_ok = l2_w >= 2 && (q->waves == 0 || l2_w == q->waves);
+    const int want_w = n > kMaxWaveVertices ? 0 : (q->waves > 0 ? q->waves : max_w);
+    const uint64_t need = std::max<uint64_t>(2ull * (uint64_t)g->m, kReduceBytesPerVertex * (uint64_t)n);
+    // per-wavefront configurations [L2 mode][16-bit distances]: the most
+    // wavefronts that fit (or exactly the requested number)
+    struct Fit {
+        int w = 0;
+        uint32_t lds = 0, wb = 0;
+    } fits[2][2];
+    for (int l2 = 0; l2 < 2; ++l2)
+        for (int d16 = 0; d16 < 2; ++d16) {
+            if (d16 && !pl->dist16) continue;
+            Fit &f = fits[l2][d16];
+            for (int w = 2; w <= want_w; ++w) {
+                uint32_t wb = 0;
+                const uint32_t lds = l2 ? lds_bytes_wave_l2(n, w, d16 != 0, &wb)
+                                        : lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, d16 != 0, &wb);
+                if (lds > (uint32_t)ctx->max_lds) break;
+                if ((uint64_t)wb * w < need) continue;   // staging and reduction scratch
+                f = Fit{w, lds, wb};
+            }
+            if (q->waves > 0 && f.w != q->waves) f = Fit{};
+        }
+    // throughput of one wavefront relative to an LDS-mode wavefront with
+    // 32-bit distances (measured on MI355X, weighted ER and WS graphs, n =
+    // 1000 .. 4000): L2 mode 0.87 (adjacency reads and B atomics at L2),
+    // 16-bit distances 0.83 (compare-and-swap minima); per-source rates grow
+    // close to linearly with the wavefronts a CU holds
+    auto eff = [&](int l2, int d16) { return fits[l2][d16].w * (l2 ? 0.87 : 1.0) * (d16 ? 0.83 : 1.0); };
+    auto width = [&](int l2) {
+        if (q->flags & AMC_DIST16) return 1;
+        return eff(l2, 1) > eff(l2, 0) ? 1 : 0;
+    };
     int mode = q->mode;
     if (mode == AMC_MODE_AUTO) {
-        // measured on MI355X (degree 8): L2 mode wins once the realized graph
-        // leaves room for fewer than 4 wavefronts in LDS mode; with only two
-        // wavefronts left even there, the workgroup-per-source mode is as fast
-        // for weighted graphs beyond n = 4000 and faster for unit weights
-        const bool l2_good = l2_ok && (l2_w >= 3 || (pl->weighted && n <= 4000));
-        if (wave_ok && (best_w >= 4 || !l2_good || l2_w <= best_w)) mode = AMC_MODE_WAVE;
-        else if (l2_good) mode = AMC_MODE_WAVE_L2;
+        const double e_lds = eff(0, width(0)), e_l2 = eff(1, width(1));
+        const int w_l2 = fits[1][width(1)].w;
+        // with only two wavefronts even in L2 mode, the workgroup-per-source
+        // mode is as fast for weighted graphs beyond n = 4000 and faster for
+        // unit weights
+        if (e_lds > 0.0 && e_lds >= e_l2) mode = AMC_MODE_WAVE;
+        else if (e_l2 > 0.0 && (w_l2 >= 3 || (pl->weighted && n <= 4000))) mode = AMC_MODE_WAVE_L2;
+        else if (e_lds > 0.0) mode = AMC_MODE_WAVE;
         else mode = AMC_MODE_BLOCK;
     }
-    if (mode == AMC_MODE_WAVE && !wave_ok) return AMC_E_UNSUPPORTED;
-    if (mode == AMC_MODE_WAVE_L2 && !l2_ok) return AMC_E_UNSUPPORTED;
     pl->mode = mode;
     pl->scratch_words = 0;
-    if (mode == AMC_MODE_WAVE) {
-        pl->waves = best_w;
-        pl->lds = best_lds;
-        pl->wave_bytes = best_wb;
-        pl->threads = 64 * best_w;
+    if (mode == AMC_MODE_WAVE || mode == AMC_MODE_WAVE_L2) {
+        const int l2 = mode == AMC_MODE_WAVE_L2 ? 1 : 0;
+        const int d16 = width(l2);
+        const Fit &f = fits[l2][d16];
+        if (f.w < 2) return AMC_E_UNSUPPORTED;
+        pl->dist16 = d16 != 0;
+        pl->waves = f.w;
+        pl->lds = f.lds;
+        pl->wave_bytes = f.wb;
+        pl->threads = 64 * f.w;
         pl->adj_cap = adj_cap;
-    } else if (mode == AMC_MODE_WAVE_L2) {
-        pl->waves = l2_w;
-        pl->lds = l2_lds;
-        pl->wave_bytes = l2_wb;
-        pl->threads = 64 * l2_w;
-        pl->adj_cap = adj_cap;
-        pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
+        if (l2) pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
     } else {
+        pl->dist16 = false;
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
         pl->lds = lds_bytes_block(n, pl->threads);
         if (pl->lds > (uint32_t)ctx->max_lds) return AMC_E_UNSUPPORTED;

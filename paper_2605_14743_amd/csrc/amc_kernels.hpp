@@ -10,12 +10,13 @@
 namespace amc {
 
 // One wavefront per (r, s): LDS mode (realized graph in LDS) and L2 mode
-// (realized graph, B and labels in a per-workgroup global scratch).
-uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes);
-uint32_t lds_bytes_wave_l2(int n, int waves, uint32_t *wave_bytes);
+// (realized graph, B and labels in a per-workgroup global scratch); dist16
+// selects 16-bit distance entries in the wavefront regions.
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, bool dist16, uint32_t *wave_bytes);
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, uint32_t *wave_bytes);
 size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes);
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, int group, uint32_t adj_bytes, int blocks,
-                             int waves, uint32_t lds, hipStream_t st);
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, int group, uint32_t adj_bytes,
+                             int blocks, int waves, uint32_t lds, hipStream_t st);
 
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);
@@ -49,8 +50,8 @@ hipError_t launch_anchored(const LaunchCtl &LC, bool weighted, uint32_t adj_byte
 
 // Trajectory simulator (LDS mode only).
 hipError_t set_traj_attrs(int max_lds);
-hipError_t launch_traj(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                       uint32_t lds, hipStream_t st);
+hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int group, uint32_t adj_bytes, int blocks,
+                       int waves, uint32_t lds, hipStream_t st);
 hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,
                           const unsigned long long *visits, const unsigned long long *ctr, uint32_t *hist,
                           double *b_hat, double *survival, hipStream_t st);

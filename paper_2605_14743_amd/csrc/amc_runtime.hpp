@@ -27,6 +27,12 @@ struct DevArena {
 
 // Workgroups per CU of the modes that give every workgroup a global scratch.
 constexpr uint32_t kMaxScratchBlocksPerCu = 4;
+// The per-realization reduction borrows the wavefront regions of a workgroup:
+// two u64 and two i32 arrays over the vertices.
+constexpr uint64_t kReduceBytesPerVertex = 24;
+// Vertex ids in a wavefront region's settled order keep bit 15 for the
+// segment tags.
+constexpr int kMaxWaveVertices = 0x7FFF;
 
 struct Plan {
     int mode = 0;
@@ -41,6 +47,7 @@ struct Plan {
     int blocks = 0;
     uint32_t scratch_words = 0;     // per-workgroup global scratch (block and L2 modes)
     bool anchored = false;          // anchored r-hop neighbourhoods (own kernel)
+    bool dist16 = false;            // 16-bit distance entries in the wavefront regions
 };
 
 // Private copies of the arrays a query points to (inputs are never retained):

@@ -18,13 +18,16 @@
 
 namespace amc {
 
-// Per-wavefront region: dist u32[n] | sig u64[n] | ord u16[n] | aux u16[n] |
-// B f64[n] | list u16[n] | mask u8[n].
-__host__ __device__ inline uint32_t anchored_private_bytes(int n) {
+// Per-wavefront region: dist u32[n] | sig u64[n] | ord u16[n] | B f64[n] |
+// list u16[n] | mask u8[n].
+__host__ __device__ inline uint32_t anchored_b_offset(int n) {
     const uint32_t un = (uint32_t)n;
     const uint32_t sig_off = (4u * un + 7u) & ~7u;
-    const uint32_t b_off = (sig_off + 8u * un + 4u * un + 7u) & ~7u;
-    return (b_off + 8u * un + 2u * un + un + 15u) & ~15u;
+    return (sig_off + 8u * un + 2u * un + 7u) & ~7u;
+}
+__host__ __device__ inline uint32_t anchored_private_bytes(int n) {
+    const uint32_t un = (uint32_t)n;
+    return (anchored_b_offset(n) + 8u * un + 2u * un + un + 15u) & ~15u;
 }
 
 template <bool WEIGHTED, typename ADJ>
@@ -63,11 +66,10 @@ __global__ __launch_bounds__(1024) void anchored_kernel(LaunchCtl LC) {
         unsigned char *wbase = smem + L.waves;
         unsigned char *wmine = wbase + wave * P.wave_bytes;
         const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
-        const uint32_t b_off = (sig_off + 12u * (uint32_t)n + 7u) & ~7u;
+        const uint32_t b_off = anchored_b_offset(n);
         uint32_t *dist = (uint32_t *)wmine;
         unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
         uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
-        uint16_t *aux = ord + n;
         double *Bw = (double *)(wmine + b_off);
         uint16_t *list = (uint16_t *)(wmine + b_off + 8u * (uint32_t)n);
         uint8_t *mask = (uint8_t *)(list + n);
@@ -130,8 +132,9 @@ __global__ __launch_bounds__(1024) void anchored_kernel(LaunchCtl LC) {
             // betweenness of the induced subgraph, one source after another
             for (int k = 0; k < sz; ++k) {
                 int cs = 0, zz = 0;
-                wave_source_lane<WEIGHTED, 4, ADJ, false, true>(P, rp, adj, shift, Bw, dist, sig, ord, aux,
-                                                                &wctr[wave], (int)list[k], -1, cs, zz, ovf, mask);
+                wave_source_lane<WEIGHTED, 4, ADJ, false, uint32_t, true>(P, rp, adj, shift, Bw, dist, sig, ord,
+                                                                          &wctr[wave], (int)list[k], -1, cs, zz,
+                                                                          ovf, mask);
             }
             // tie-broken maximiser over S_r(i), and over S_r(i) ∩ W
             double mx = 0.0, mw = -1.0;

@@ -112,10 +112,10 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
     }
     // group by kernel variant
     struct Key {
-        int mode, weighted, group, adj_bytes, waves, anchored;
+        int mode, weighted, group, adj_bytes, waves, anchored, dist16;
         bool operator==(const Key &o) const {
             return mode == o.mode && weighted == o.weighted && group == o.group && adj_bytes == o.adj_bytes &&
-                   waves == o.waves && anchored == o.anchored;
+                   waves == o.waves && anchored == o.anchored && dist16 == o.dist16;
         }
     };
     std::vector<Key> keys;
@@ -128,11 +128,12 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         if (per_wave && !pl.anchored) {
             w = wave_bucket(pl.waves);
             const uint64_t need = std::max<uint64_t>(2ull * (uint64_t)b->runs[i]->g->m,
-                                                     32ull * (uint64_t)b->runs[i]->g->n);
+                                                     kReduceBytesPerVertex * (uint64_t)b->runs[i]->g->n);
             if ((uint64_t)pl.wave_bytes * (uint64_t)w < need) w = pl.waves;
         }
         if (pl.anchored) w = pl.waves;
-        Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w, pl.anchored ? 1 : 0};
+        Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w,
+              pl.anchored ? 1 : 0, pl.dist16 ? 1 : 0};
         size_t gi = 0;
         while (gi < keys.size() && !(keys[gi] == k)) ++gi;
         if (gi == keys.size()) {
@@ -164,8 +165,9 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
                 R.pl.waves = G.pl.waves;
                 R.pl.threads = G.pl.threads;
                 R.pl.lds = G.pl.mode == AMC_MODE_WAVE
-                               ? lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, &R.pl.wave_bytes)
-                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, &R.pl.wave_bytes);
+                               ? lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, R.pl.dist16,
+                                                &R.pl.wave_bytes)
+                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, R.pl.dist16, &R.pl.wave_bytes);
             }
             G.pl.lds = std::max(G.pl.lds, R.pl.lds);
             G.bscratch_words = std::max<uint32_t>(G.bscratch_words, R.pl.scratch_words);
@@ -232,8 +234,8 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
                            ? launch_anchored(LC, G.pl.weighted, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st)
                        : G.pl.mode == AMC_MODE_BLOCK
                            ? launch_sweep_block(LC, G.pl.weighted, G.blocks, G.pl.threads, G.pl.lds, st)
-                           : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.group,
-                                               G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);
+                           : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.dist16,
+                                               G.pl.group, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);
         if (e != hipSuccess) {
             rc = AMC_E_HIP;
             break;

@@ -284,7 +284,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         uint16_t *comp = (uint16_t *)(smem + L.comp);
         uint16_t *csize = (uint16_t *)(smem + L.csize);
         // per-workgroup global scratch: realized rp (n+1), adjacency (2m plus
-        // padding), component centres and slot counts (4 n)
+        // padding), component centres (2 n)
         uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
         uint32_t *rp = gs;
         uint32_t *adj = rp + (n + 1);
@@ -294,8 +294,6 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         uint32_t *tail4 = adj + 2 * (size_t)P.m + kAdjPad;
         RS.ccen = (int32_t *)tail4;
         RS.wcen = RS.ccen + n;
-        RS.kal = (uint32_t *)(RS.wcen + n);
-        RS.kba = RS.kal + n;
 
         stage_realization(P, r, rp, adj, 16u, (uint16_t *)smem, scan_tmp);
         for (int v = tid; v < n; v += nthr) B[v] = 0.0;
@@ -351,7 +349,7 @@ uint32_t lds_bytes_block(int n, int threads) {
 }
 
 size_t block_scratch_words(int n, int64_t m) {
-    return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 4 * (size_t)n + 64;
+    return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 2 * (size_t)n + 64;
 }
 
 hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,

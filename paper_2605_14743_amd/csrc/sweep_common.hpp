@@ -13,7 +13,6 @@ namespace amc {
 struct ReduceScratch {
     unsigned long long *cmax, *wmax;   // per component: max B (bit pattern), max B over the pool
     int32_t *ccen, *wcen;              // per component: centre, pool-constrained centre
-    uint32_t *kal, *kba;               // per component: surviving and base adjacency slots
 };
 
 // ---------------------------------------------------------------------------
@@ -107,17 +106,17 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
     unsigned long long *wmax = S.wmax;
     int32_t *ccen = S.ccen;
     int32_t *wcen = S.wcen;
-    uint32_t *kal = S.kal;
-    uint32_t *kba = S.kba;
     for (int v = tid; v < n; v += nthr) {
         cmax[v] = 0ull;
         wmax[v] = 0ull;
         ccen[v] = 0x7FFFFFFF;
         wcen[v] = 0x7FFFFFFF;
-        kal[v] = 0u;
-        kba[v] = 0u;
     }
     __syncthreads();
+    // work counters: every anchor i counts the surviving and the base slots
+    // of its component, i.e. vertex v's slots are counted once per member
+    // of v's component (size csize[v])
+    unsigned long long s_ak = 0, s_dk = 0;
     double gm = 0.0;
     for (int v = tid; v < n; v += nthr) {
         const int c = (int)ld_coh<COH>(&comp[v]);
@@ -125,8 +124,9 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
         const unsigned long long bb = as_u64(bv);
         atomicMax(&cmax[c], bb);
         if (P.pool && P.pool[v]) atomicMax(&wmax[c], bb);
-        atomicAdd(&kal[c], (uint32_t)rp[v + 1] - (uint32_t)rp[v]);
-        atomicAdd(&kba[c], (uint32_t)(P.rp_base[v + 1] - P.rp_base[v]));
+        const unsigned long long sz = (unsigned long long)ld_coh<COH>(&csize[v]);
+        s_ak += sz * ((uint32_t)rp[v + 1] - (uint32_t)rp[v]);
+        s_dk += sz * (unsigned long long)(P.rp_base[v + 1] - P.rp_base[v]);
         gm = bv > gm ? bv : gm;
     }
     gm = wave_max_f64(gm);
@@ -166,7 +166,7 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
         if (P.center_global) P.center_global[r_local] = b;
     }
     // anchors: Alg. 1 for every i, counted as in Alg. 2
-    unsigned long long s_nk = 0, s_ak = 0, s_dk = 0, units = 0;
+    unsigned long long s_nk = 0, units = 0;
     for (int i = tid; i < n; i += nthr) {
         const int c = (int)ld_coh<COH>(&comp[i]);
         const uint32_t sz = (uint32_t)ld_coh<COH>(&csize[i]);
@@ -183,8 +183,6 @@ __device__ inline void reduce_realization(const SweepParams &P, uint32_t r_local
         }
         units += 1;
         s_nk += (unsigned long long)sz;
-        s_ak += kal[c];
-        s_dk += kba[c];
     }
     if (P.bsum)
         for (int v = tid; v < n; v += nthr) unsafeAtomicAdd(&P.bsum[v], ld_coh<COH>(&B[v]));

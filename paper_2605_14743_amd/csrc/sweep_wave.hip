@@ -17,6 +17,8 @@
 //      local-center) and the pool-constrained centres (Section 7.1), draws
 //      every anchor's stop coin, applies k_min and counts next(r, i)
 //      (Alg. 1 for every anchor, tallied as in Alg. 2).
+#include <type_traits>
+
 #include "amc_dev.hpp"
 #include "amc_kernels.hpp"
 #include "sweep_common.hpp"
@@ -30,9 +32,11 @@ namespace amc {
 // atomics), which leaves the whole LDS to per-source state and so keeps more
 // sources in flight on graphs whose realized adjacency would crowd the LDS.
 // The 8-slot lane mapping needs more than the 128 VGPRs a 1024-thread
-// workgroup allows; it is limited to 8 wavefronts per workgroup.
-template <bool WEIGHTED, int G, typename ADJ, bool GL>
+// workgroup allows; it is limited to 8 wavefronts per workgroup.  D16: 16-bit
+// distance entries in the wavefront regions.
+template <bool WEIGHTED, int G, typename ADJ, bool GL, bool D16>
 __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchCtl LC) {
+    using DT = typename std::conditional<D16, uint16_t, uint32_t>::type;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -40,8 +44,9 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
     __shared__ int red_i[kMaxWaves];
     __shared__ int item_sh;
     __shared__ int last_sh;
+    __shared__ uint32_t src_ctr;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned long long acc_stats[5] = {0, 0, 0, 0, 0};
     bool ovf = false;
     int q_prev = -1;
@@ -101,19 +106,17 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
         }
         // byte offsets from the LDS base keep every pointer in the LDS address space
         unsigned char *wmine = wbase + wave * P.wave_bytes;
-        const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
-        uint32_t *dist = (uint32_t *)wmine;
+        const uint32_t sig_off = wave_sig_offset(n, D16);
+        DT *dist = (DT *)wmine;
         unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
         uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
-        uint16_t *aux = ord + n;
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)wbase;
         RS.wmax = RS.cmax + n;
         RS.ccen = (int32_t *)(RS.wmax + n);
         RS.wcen = RS.ccen + n;
-        RS.kal = (uint32_t *)(RS.wcen + n);
-        RS.kba = RS.kal + n;
 
+        if (tid == 0) src_ctr = 0u;
         stage_realization(P, r, rp, adj, shift, (uint16_t *)wbase, scan_tmp);
         if constexpr (GL) {
             if (!split)
@@ -126,12 +129,18 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
         }
         __syncthreads();
 
+        // sources are taken from a workgroup counter: the wavefronts of a
+        // workgroup need not spread evenly over the SIMDs
         const int s_lo = t * P.tile, s_hi = min(n, s_lo + P.tile);
-        for (int s = s_lo + wave; s < s_hi; s += nwaves) {
+        for (;;) {
+            uint32_t k = 0;
+            if (lane == 0) k = atomicAdd(&src_ctr, 1u);
+            const int s = s_lo + (int)__builtin_amdgcn_readfirstlane(k);
+            if (s >= s_hi) break;
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            run_source<WEIGHTED, G, ADJ, GL>(P, rp, adj, shift, B, dist, sig, ord, aux, &wctr[wave], s, slot, cs, sz,
-                                             ovf);
+            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, shift, B, dist, sig, ord, &wctr[wave], s, slot, cs, sz,
+                                                 ovf);
             if (lane == 0) {
                 if constexpr (GL) {
                     st_global(&comp32[s], (int32_t)cs);
@@ -200,20 +209,14 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
 // ---------------------------------------------------------------------------
 // Host-side launch (compiled into the same object).
 // ---------------------------------------------------------------------------
-static uint32_t wave_private_bytes(int n) {
-    const uint32_t un = (uint32_t)n;
-    const uint32_t per_wave = ((4u * un + 7u) & ~7u) + 8u * un + 2u * un + 2u * un;
-    return (per_wave + 15u) & ~15u;
-}
-
-uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, uint32_t *wave_bytes) {
-    const uint32_t wb = wave_private_bytes(n);
+uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, bool dist16, uint32_t *wave_bytes) {
+    const uint32_t wb = wave_private_bytes(n, dist16);
     if (wave_bytes) *wave_bytes = wb;
     return wave_layout(n, adj_cap, adj_bytes).waves + wb * (uint32_t)waves;
 }
 
-uint32_t lds_bytes_wave_l2(int n, int waves, uint32_t *wave_bytes) {
-    const uint32_t wb = wave_private_bytes(n);
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, uint32_t *wave_bytes) {
+    const uint32_t wb = wave_private_bytes(n, dist16);
     if (wave_bytes) *wave_bytes = wb;
     return wb * (uint32_t)waves;
 }
@@ -222,18 +225,20 @@ size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes) {
     return l2_layout(n, adj_cap, adj_bytes).total / 4u;
 }
 
-template <bool W, int G, typename ADJ, bool GL>
+template <bool W, int G, typename ADJ, bool GL, bool D16>
 static hipError_t launch_t(const LaunchCtl &LC, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ, GL>), dim3(blocks), dim3(64 * waves), lds, st, LC);
+    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ, GL, D16>), dim3(blocks), dim3(64 * waves), lds, st, LC);
     return hipGetLastError();
 }
 
-template <bool W, typename ADJ, bool GL>
+template <bool W, typename ADJ, bool GL, bool D16>
 static hipError_t attrs_g(int max_lds) {
-    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL>, (const void *)sweep_wave_kernel<W, 2, ADJ, GL>,
-                        (const void *)sweep_wave_kernel<W, 3, ADJ, GL>, (const void *)sweep_wave_kernel<W, 4, ADJ, GL>,
-                        (const void *)sweep_wave_kernel<W, 8, ADJ, GL>,
-                        (const void *)sweep_wave_kernel<W, 16, ADJ, GL>};
+    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL, D16>,
+                        (const void *)sweep_wave_kernel<W, 2, ADJ, GL, D16>,
+                        (const void *)sweep_wave_kernel<W, 3, ADJ, GL, D16>,
+                        (const void *)sweep_wave_kernel<W, 4, ADJ, GL, D16>,
+                        (const void *)sweep_wave_kernel<W, 8, ADJ, GL, D16>,
+                        (const void *)sweep_wave_kernel<W, 16, ADJ, GL, D16>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
@@ -241,49 +246,54 @@ static hipError_t attrs_g(int max_lds) {
     return hipSuccess;
 }
 
-template <bool GL>
+template <bool GL, bool D16>
 static hipError_t attrs_all(int max_lds) {
     hipError_t e;
-    if ((e = attrs_g<true, uint16_t, GL>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_g<false, uint16_t, GL>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_g<true, uint32_t, GL>(max_lds)) != hipSuccess) return e;
-    return attrs_g<false, uint32_t, GL>(max_lds);
+    if ((e = attrs_g<true, uint16_t, GL, D16>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<false, uint16_t, GL, D16>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_g<true, uint32_t, GL, D16>(max_lds)) != hipSuccess) return e;
+    return attrs_g<false, uint32_t, GL, D16>(max_lds);
 }
 
 // Allows every LDS-mode and L2-mode instantiation the device's dynamic LDS
 // (set once per context, outside any stream capture).
 hipError_t set_sweep_wave_attrs(int max_lds) {
-    const hipError_t e = attrs_all<false>(max_lds);
-    if (e != hipSuccess) return e;
-    return attrs_all<true>(max_lds);
+    hipError_t e;
+    if ((e = attrs_all<false, false>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_all<true, false>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_all<false, true>(max_lds)) != hipSuccess) return e;
+    return attrs_all<true, true>(max_lds);
 }
 
-template <bool W, typename ADJ, bool GL>
+template <bool W, typename ADJ, bool GL, bool D16>
 static hipError_t launch_g(const LaunchCtl &LC, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
     switch (group) {
-        case 1: return launch_t<W, 1, ADJ, GL>(LC, blocks, waves, lds, st);
-        case 2: return launch_t<W, 2, ADJ, GL>(LC, blocks, waves, lds, st);
-        case 3: return launch_t<W, 3, ADJ, GL>(LC, blocks, waves, lds, st);
-        case 4: return launch_t<W, 4, ADJ, GL>(LC, blocks, waves, lds, st);
-        case 16: return launch_t<W, 16, ADJ, GL>(LC, blocks, waves, lds, st);
-        default: return launch_t<W, 8, ADJ, GL>(LC, blocks, waves, lds, st);
+        case 1: return launch_t<W, 1, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        case 2: return launch_t<W, 2, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        case 3: return launch_t<W, 3, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        case 4: return launch_t<W, 4, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        case 16: return launch_t<W, 16, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        default: return launch_t<W, 8, ADJ, GL, D16>(LC, blocks, waves, lds, st);
     }
 }
 
-template <bool GL>
+template <bool GL, bool D16>
 static hipError_t launch_w(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
                            uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_g<true, uint16_t, GL>(LC, group, blocks, waves, lds, st)
-                        : launch_g<false, uint16_t, GL>(LC, group, blocks, waves, lds, st);
-    return weighted ? launch_g<true, uint32_t, GL>(LC, group, blocks, waves, lds, st)
-                    : launch_g<false, uint32_t, GL>(LC, group, blocks, waves, lds, st);
+        return weighted ? launch_g<true, uint16_t, GL, D16>(LC, group, blocks, waves, lds, st)
+                        : launch_g<false, uint16_t, GL, D16>(LC, group, blocks, waves, lds, st);
+    return weighted ? launch_g<true, uint32_t, GL, D16>(LC, group, blocks, waves, lds, st)
+                    : launch_g<false, uint32_t, GL, D16>(LC, group, blocks, waves, lds, st);
 }
 
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, int group, uint32_t adj_bytes, int blocks,
-                             int waves, uint32_t lds, hipStream_t st) {
-    return l2 ? launch_w<true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
-              : launch_w<false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, int group, uint32_t adj_bytes,
+                             int blocks, int waves, uint32_t lds, hipStream_t st) {
+    if (dist16)
+        return l2 ? launch_w<true, true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
+                  : launch_w<false, true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
+    return l2 ? launch_w<true, false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
+              : launch_w<false, false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
 }
 
 }  // namespace amc

@@ -11,6 +11,8 @@
 // takes further sources of K; the band maximiser of B over K is X_{t+1}.
 // Visits, lengths, node rewards and switches feed the length-biased
 // estimators of the uniform-step equivalence.
+#include <type_traits>
+
 #include "amc_dev.hpp"
 #include "amc_kernels.hpp"
 #include "sweep_common.hpp"
@@ -18,8 +20,9 @@
 
 namespace amc {
 
-template <bool WEIGHTED, int G, typename ADJ>
+template <bool WEIGHTED, int G, typename ADJ, bool D16>
 __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
+    using DT = typename std::conditional<D16, uint16_t, uint32_t>::type;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -37,11 +40,10 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     uint16_t *list = (uint16_t *)(smem + L.comp);        // K(X_t;H), in wavefront 0's visit order
     unsigned char *wbase = smem + L.waves;
     unsigned char *wmine = wbase + wave * P.wave_bytes;
-    const uint32_t sig_off = (4u * (uint32_t)n + 7u) & ~7u;
-    uint32_t *dist = (uint32_t *)wmine;
+    const uint32_t sig_off = wave_sig_offset(n, D16);
+    DT *dist = (DT *)wmine;
     unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
     uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
-    uint16_t *aux = ord + n;
 
     bool ovf = false;
     double rew = 0.0;
@@ -70,9 +72,9 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                 __syncthreads();
                 if (wave == 0) {
                     int cs = 0, sz = 0;
-                    run_source<WEIGHTED, G, ADJ, false>(P, rp, adj, P.shift, B, dist, sig, ord, aux, &wctr[0], x, -1,
-                                                        cs, sz, ovf);
-                    for (int k = lane; k < sz; k += 64) list[k] = ord[k];
+                    run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, B, dist, sig, ord, &wctr[0], x, -1, cs,
+                                                        sz, ovf);
+                    for (int k = lane; k < sz; k += 64) list[k] = ord[k] & kVertexMask;
                     if (lane == 0) size_sh = sz;
                 }
                 __syncthreads();
@@ -80,8 +82,8 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                 if ((uint32_t)sz >= P.k_min) {
                     for (int k = 1 + wave; k < sz; k += nwaves) {
                         int cs = 0, zz = 0;
-                        run_source<WEIGHTED, G, ADJ, false>(P, rp, adj, P.shift, B, dist, sig, ord, aux,
-                                                            &wctr[wave], (int)list[k], -1, cs, zz, ovf);
+                        run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, B, dist, sig, ord, &wctr[wave],
+                                                            (int)list[k], -1, cs, zz, ovf);
                     }
                     __syncthreads();
                     // tie-broken maximiser of B over K(X_t;H) (eq. local-center)
@@ -163,29 +165,29 @@ __global__ void k_traj_estimates(int n, int max_steps, const unsigned long long 
 }
 
 // ---------------------------------------------------------------------------
-template <bool W, int G, typename ADJ>
+template <bool W, int G, typename ADJ, bool D16>
 static hipError_t launch_tt(const TrajArgs &T, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((traj_kernel<W, G, ADJ>), dim3(blocks), dim3(64 * waves), lds, st, T);
+    hipLaunchKernelGGL((traj_kernel<W, G, ADJ, D16>), dim3(blocks), dim3(64 * waves), lds, st, T);
     return hipGetLastError();
 }
 
-template <bool W, typename ADJ>
+template <bool W, typename ADJ, bool D16>
 static hipError_t launch_tg(const TrajArgs &T, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
     switch (group) {
-        case 1: return launch_tt<W, 1, ADJ>(T, blocks, waves, lds, st);
-        case 2: return launch_tt<W, 2, ADJ>(T, blocks, waves, lds, st);
-        case 3: return launch_tt<W, 3, ADJ>(T, blocks, waves, lds, st);
-        case 4: return launch_tt<W, 4, ADJ>(T, blocks, waves, lds, st);
-        case 16: return launch_tt<W, 16, ADJ>(T, blocks, waves, lds, st);
-        default: return launch_tt<W, 8, ADJ>(T, blocks, waves, lds, st);
+        case 1: return launch_tt<W, 1, ADJ, D16>(T, blocks, waves, lds, st);
+        case 2: return launch_tt<W, 2, ADJ, D16>(T, blocks, waves, lds, st);
+        case 3: return launch_tt<W, 3, ADJ, D16>(T, blocks, waves, lds, st);
+        case 4: return launch_tt<W, 4, ADJ, D16>(T, blocks, waves, lds, st);
+        case 16: return launch_tt<W, 16, ADJ, D16>(T, blocks, waves, lds, st);
+        default: return launch_tt<W, 8, ADJ, D16>(T, blocks, waves, lds, st);
     }
 }
 
-template <bool W, typename ADJ>
+template <bool W, typename ADJ, bool D16>
 static hipError_t attrs_t(int max_lds) {
-    const void *ks[] = {(const void *)traj_kernel<W, 1, ADJ>, (const void *)traj_kernel<W, 2, ADJ>,
-                        (const void *)traj_kernel<W, 3, ADJ>, (const void *)traj_kernel<W, 4, ADJ>,
-                        (const void *)traj_kernel<W, 8, ADJ>, (const void *)traj_kernel<W, 16, ADJ>};
+    const void *ks[] = {(const void *)traj_kernel<W, 1, ADJ, D16>, (const void *)traj_kernel<W, 2, ADJ, D16>,
+                        (const void *)traj_kernel<W, 3, ADJ, D16>, (const void *)traj_kernel<W, 4, ADJ, D16>,
+                        (const void *)traj_kernel<W, 8, ADJ, D16>, (const void *)traj_kernel<W, 16, ADJ, D16>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
@@ -193,21 +195,35 @@ static hipError_t attrs_t(int max_lds) {
     return hipSuccess;
 }
 
-hipError_t set_traj_attrs(int max_lds) {
+template <bool D16>
+static hipError_t attrs_td(int max_lds) {
     hipError_t e;
-    if ((e = attrs_t<true, uint16_t>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_t<false, uint16_t>(max_lds)) != hipSuccess) return e;
-    if ((e = attrs_t<true, uint32_t>(max_lds)) != hipSuccess) return e;
-    return attrs_t<false, uint32_t>(max_lds);
+    if ((e = attrs_t<true, uint16_t, D16>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_t<false, uint16_t, D16>(max_lds)) != hipSuccess) return e;
+    if ((e = attrs_t<true, uint32_t, D16>(max_lds)) != hipSuccess) return e;
+    return attrs_t<false, uint32_t, D16>(max_lds);
 }
 
-hipError_t launch_traj(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                       uint32_t lds, hipStream_t st) {
+hipError_t set_traj_attrs(int max_lds) {
+    const hipError_t e = attrs_td<false>(max_lds);
+    if (e != hipSuccess) return e;
+    return attrs_td<true>(max_lds);
+}
+
+template <bool D16>
+static hipError_t launch_td(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
+                            uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_tg<true, uint16_t>(T, group, blocks, waves, lds, st)
-                        : launch_tg<false, uint16_t>(T, group, blocks, waves, lds, st);
-    return weighted ? launch_tg<true, uint32_t>(T, group, blocks, waves, lds, st)
-                    : launch_tg<false, uint32_t>(T, group, blocks, waves, lds, st);
+        return weighted ? launch_tg<true, uint16_t, D16>(T, group, blocks, waves, lds, st)
+                        : launch_tg<false, uint16_t, D16>(T, group, blocks, waves, lds, st);
+    return weighted ? launch_tg<true, uint32_t, D16>(T, group, blocks, waves, lds, st)
+                    : launch_tg<false, uint32_t, D16>(T, group, blocks, waves, lds, st);
+}
+
+hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int group, uint32_t adj_bytes, int blocks,
+                       int waves, uint32_t lds, hipStream_t st) {
+    return dist16 ? launch_td<true>(T, weighted, group, adj_bytes, blocks, waves, lds, st)
+                  : launch_td<false>(T, weighted, group, adj_bytes, blocks, waves, lds, st);
 }
 
 hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,

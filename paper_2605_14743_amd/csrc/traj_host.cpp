@@ -120,7 +120,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
         }
     } evg{ev};
     HIPCHK(hipEventRecord(ev[0], st));
-    HIPCHK(launch_traj(T, pl.weighted, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st));
+    HIPCHK(launch_traj(T, pl.weighted, pl.dist16, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st));
     HIPCHK(hipEventRecord(ev[1], st));
     HIPCHK(traj_estimates(n, E, S, T.lengths, T.visits, T.ctr, hist, b_hat, surv, st));
 

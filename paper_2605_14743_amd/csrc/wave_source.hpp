@@ -12,43 +12,189 @@ namespace amc {
 
 // ---------------------------------------------------------------------------
 // One source on one wavefront.  State (LDS, private to the wavefront):
-//   dist[n]  tentative / final distance (kInf = unreached)
+//   dist[n]  tentative / final distance (DistOps<DT>::unreached = unreached)
 //   sig[n]   exact path count sigma_s(v) (uint64); after v's dependency is
 //            known the slot holds c_v = (1 + delta_v) / sigma_v as a double,
 //            so a predecessor u gets delta_u = sigma_u * sum_{succ w} c_w
-//   ord[n]   settled vertices in non-decreasing distance
-//   aux[n]   front: unsettled reached vertices (integer weights only);
-//            back:  start of each equal-distance segment of ord
+//   ord[n]   ord[0, ord_end): settled vertices in non-decreasing distance,
+//            the first vertex of each equal-distance segment tagged with
+//            kSegMark; ord[ord_end, ord_end + fringe): the reached but
+//            unsettled vertices (integer weights only).  Settled and
+//            unsettled vertices are distinct, so the two parts fit in n.
 // G lanes cooperate on one vertex's adjacency; an adjacency entry holds the
 // neighbour in its low `shift` bits and the weight above them.
 // ---------------------------------------------------------------------------
-template <bool WEIGHTED, int G, typename ADJ, bool GB>
-__device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
-                            uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctr,
-                            int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
+constexpr uint16_t kSegMark = 0x8000u;   // vertex ids stay below 2^15
+constexpr uint16_t kVertexMask = 0x7FFFu;
+
+// Distance entries: uint32_t, or uint16_t when every finite distance plus one
+// edge weight stays below 0xFFFF (the host checks n * w_max < 0xFFFF), which
+// halves the array.  A relaxation reads the 32-bit word holding d[u]
+// (word / value), issues its atomic minimum (issue_min, returning the
+// previous word) and resolves the previous value of d[u] (resolve): the
+// lane-per-vertex code issues the minima of its U slots back to back before
+// resolving any.  fetch_min does both at once.
+template <typename DT>
+struct DistOps;
+template <>
+struct DistOps<uint32_t> {
+    static constexpr uint32_t unreached = kInf;
+    __device__ static __forceinline__ uint32_t word(const uint32_t *d, uint32_t u) { return d[u]; }
+    __device__ static __forceinline__ uint32_t value(uint32_t wd, uint32_t) { return wd; }
+    __device__ static __forceinline__ uint32_t issue_min(uint32_t *d, uint32_t u, uint32_t val, uint32_t) {
+        return atomicMin(&d[u], val);
+    }
+    __device__ static __forceinline__ uint32_t resolve(uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t prev) {
+        return prev;
+    }
+    __device__ static __forceinline__ uint32_t fetch_min(uint32_t *d, uint32_t u, uint32_t val) {
+        return atomicMin(&d[u], val);
+    }
+};
+template <>
+struct DistOps<uint16_t> {
+    static constexpr uint32_t unreached = 0xFFFFu;
+    // the array starts 4-byte aligned and is padded to a whole word
+    __device__ static __forceinline__ uint32_t *word_ptr(uint16_t *d, uint32_t u) {
+        return reinterpret_cast<uint32_t *>(d) + (u >> 1);
+    }
+    __device__ static __forceinline__ uint32_t word(const uint16_t *d, uint32_t u) {
+        return reinterpret_cast<const uint32_t *>(d)[u >> 1];
+    }
+    __device__ static __forceinline__ uint32_t value(uint32_t wd, uint32_t u) { return (wd >> ((u & 1u) * 16u)) & 0xFFFFu; }
+    __device__ static __forceinline__ uint32_t with(uint32_t wd, uint32_t u, uint32_t val) {
+        const uint32_t sh = (u & 1u) * 16u;
+        return (wd & ~(0xFFFFu << sh)) | (val << sh);
+    }
+    // compare-and-swap against the word read before (val < value(wd, u))
+    __device__ static __forceinline__ uint32_t issue_min(uint16_t *d, uint32_t u, uint32_t val, uint32_t wd) {
+        return atomicCAS(word_ptr(d, u), wd, with(wd, u, val));
+    }
+    // the word changed in between (the other half, or d[u] itself): retry
+    // from the word found until d[u] <= val or the swap goes in
+    __device__ static __forceinline__ uint32_t resolve(uint16_t *d, uint32_t u, uint32_t val, uint32_t wd,
+                                                       uint32_t prev) {
+        if (prev == wd) return value(wd, u);
+        uint32_t cur = prev;
+        for (;;) {
+            const uint32_t h = value(cur, u);
+            if (h <= val) return h;
+            const uint32_t p = atomicCAS(word_ptr(d, u), cur, with(cur, u, val));
+            if (p == cur) return h;
+            cur = p;
+        }
+    }
+    __device__ static __forceinline__ uint32_t fetch_min(uint16_t *d, uint32_t u, uint32_t val) {
+        const uint32_t wd = __hip_atomic_load(word_ptr(d, u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (value(wd, u) <= val) return value(wd, u);
+        return resolve(d, u, val, wd, issue_min(d, u, val, wd));
+    }
+};
+
+// In-place partition of the fringe ord[a, a + fr): the vertices at distance
+// mn go to ord[a, a + settled) (returned), the others to ord[a + settled,
+// a + fr); kmin gets the lane minimum over the distances of the others.
+// Chunks of 64 U entries are taken in order.  The unsettled entries of the
+// chunks already taken form one block right after the settled ones; the
+// settled entries of a new chunk take that block's first slots and the
+// entries they displace move to the slots the chunk itself was read from.
+template <int U, typename DT>
+__device__ __forceinline__ int fringe_partition(uint16_t *ord, const DT *dist, int a, int fr, uint32_t mn,
+                                                uint32_t &kmin) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanemask_lt();
+    const int end = a + fr;
+    int S = 0, K = 0;   // settled and kept entries so far
+    kmin = kInf;
+    for (int p = a; p < end; p += 64 * U) {   // p == a + S + K
+        uint32_t x[U], dx[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int k = p + 64 * c + lane;
+            x[c] = k < end ? (uint32_t)ord[k] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int c = 0; c < U; ++c) dx[c] = x[c] != 0xFFFFFFFFu ? (uint32_t)dist[x[c]] : kInf;
+        uint64_t ms[U], mk[U];
+        int s = 0, kk = 0;
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const bool valid = x[c] != 0xFFFFFFFFu;
+            const bool is_s = valid && dx[c] == mn;
+            const bool is_k = valid && !is_s;
+            if (is_k) kmin = dx[c] < kmin ? dx[c] : kmin;
+            ms[c] = __ballot(is_s);
+            mk[c] = __ballot(is_k);
+            s += __popcll(ms[c]);
+            kk += __popcll(mk[c]);
+        }
+        // entries of the kept block displaced by this chunk's settled ones
+        const int d = s < K ? s : K;
+        uint32_t y[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int j = 64 * c + lane;
+            y[c] = j < d ? (uint32_t)ord[a + S + j] : 0u;
+        }
+        wave_sync();   // every read of this chunk precedes its writes
+        int so = 0, ko = 0;
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            if ((ms[c] >> lane) & 1ull) ord[a + S + so + __popcll(ms[c] & lt)] = (uint16_t)x[c];
+            if ((mk[c] >> lane) & 1ull) ord[p + s + ko + __popcll(mk[c] & lt)] = (uint16_t)x[c];
+            so += __popcll(ms[c]);
+            ko += __popcll(mk[c]);
+        }
+        const int dst = a + S + (s > K ? s : K);
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int j = 64 * c + lane;
+            if (j < d) ord[dst + j] = (uint16_t)y[c];
+        }
+        S += s;
+        K += kk;
+        wave_sync();   // the next chunk reads the block written here
+    }
+    return S;
+}
+
+// Start of the backward batch that ends at ord index hi: the batch holds up
+// to `width` entries of one equal-distance segment, ending at hi.  e is the
+// entry at hi - width + slot (slot = lane / G), or 0 below index 0; every
+// lane of the wavefront takes part.
+__device__ __forceinline__ int batch_start(int hi, int width, uint32_t e, int G) {
+    const uint64_t mk = __ballot((e & kSegMark) != 0u);
+    if (mk == 0ull) return hi - width;
+    const int top = 63 - (int)__builtin_clzll(mk);   // highest lane holding a segment start
+    return hi - width + top / G;
+}
+
+template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT>
+__device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B, DT *dist,
+                            unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s, int dbg_slot,
+                            int &comp_out, int &size_out, bool &ovf) {
+    using DO = DistOps<DT>;
     const int n = P.n;
     const int lane = threadIdx.x & 63;
     const int sub = lane % G;
     constexpr int VPI = 64 / G;   // vertices per wave iteration
     const uint32_t nmask = (1u << shift) - 1u;
 
-    for (int v = lane; v < n; v += 64) dist[v] = kInf;
+    for (int v = lane; v < n; v += 64) dist[v] = (DT)DO::unreached;
     wave_sync();
     if (lane == 0) {
-        dist[s] = 0u;
+        dist[s] = (DT)0u;
         sig[s] = 1ull;
-        ord[0] = (uint16_t)s;
+        ord[0] = (uint16_t)s | kSegMark;
         *ctr = WEIGHTED ? 0u : 1u;
     }
     wave_sync();
 
-    int f_lo = 0, ord_end = 1, nseg = 0;
+    int f_lo = 0, ord_end = 1;
     uint32_t D = 0;
     uint32_t kmin = kInf;   // lane minimum over the fringe entries kept by the last partition
     // ------------------------------------------------------------ forward
     for (;;) {
-        if (lane == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
-        ++nseg;
         uint32_t lmin = kInf;  // lane minimum over successful relaxations
         for (int base = f_lo; base < ord_end; base += VPI) {
             const int idx = base + lane / G;
@@ -56,7 +202,7 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
             int v = 0;
             uint32_t beg = 0, len = 0;
             if (mine) {
-                v = ord[idx];
+                v = ord[idx] & kVertexMask;
                 beg = rp[v];
                 len = rp[v + 1] - beg;
             }
@@ -70,21 +216,22 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
                     const uint32_t a = adj[beg + (uint32_t)sub + t * G];
                     u = a & nmask;
                     const uint32_t w = WEIGHTED ? (a >> shift) : 1u;
-                    const uint32_t du = dist[u];
+                    const uint32_t du = (uint32_t)dist[u];
                     if (du + w == D) {                       // u precedes v: pull sigma_u
                         const unsigned long long x = acc + sig[u];
                         ovf |= x < acc;
                         acc = x;
                     } else if (D + w < du) {                 // relax the edge v -> u
-                        const uint32_t old = atomicMin(&dist[u], D + w);
+                        const uint32_t old = DO::fetch_min(dist, u, D + w);
                         if (old > D + w) lmin = (D + w) < lmin ? (D + w) : lmin;
-                        found = old == kInf;                 // first discovery of u
+                        found = old == DO::unreached;        // first discovery of u
                     }
                 }
                 const uint32_t pos = wave_append(ctr, found);
                 if (found) {
-                    if (WEIGHTED) aux[pos] = (uint16_t)u;
-                    else ord[pos] = (uint16_t)u;
+                    // unit weights: the next level starts at ord_end
+                    if (WEIGHTED) ord[ord_end + (int)pos] = (uint16_t)u;
+                    else ord[pos] = (uint16_t)u | ((int)pos == ord_end ? kSegMark : (uint16_t)0u);
                 }
             }
             acc = group_sum_u64<G>(acc, ovf);
@@ -103,26 +250,11 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
             // the fringe minimum: every current fringe distance is either a
             // value kept at the last partition or a successful relaxation
             const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
-            // move the vertices at the new minimum distance to ord, keep the
-            // rest (compacted in place: writes never pass the read position)
-            int settled = 0, kept = 0;
-            kmin = kInf;
-            const uint64_t lt = lanemask_lt();
-            for (int k0 = 0; k0 < fr; k0 += 64) {
-                const int k = k0 + lane;
-                const bool valid = k < fr;
-                const uint32_t x = valid ? aux[k] : 0u;
-                const uint32_t dx = valid ? dist[x] : kInf;
-                const bool is_s = valid && dx == mn;
-                const bool is_k = valid && !is_s;
-                if (is_k) kmin = dx < kmin ? dx : kmin;
-                const uint64_t ms = __ballot(is_s), mk = __ballot(is_k);
-                if (is_s) ord[ord_end + settled + __popcll(ms & lt)] = (uint16_t)x;
-                if (is_k) aux[kept + __popcll(mk & lt)] = (uint16_t)x;
-                settled += __popcll(ms);
-                kept += __popcll(mk);
+            const int settled = fringe_partition<1>(ord, dist, ord_end, fr, mn, kmin);
+            if (lane == 0) {
+                *ctr = (uint32_t)(fr - settled);
+                ord[ord_end] |= kSegMark;
             }
-            if (lane == 0) *ctr = (uint32_t)kept;
             wave_sync();
             f_lo = ord_end;
             ord_end += settled;
@@ -133,50 +265,50 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
     // component of s: smallest reached index, and its size
     {
         uint32_t mn = (uint32_t)n;
-        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)ord[k]);
+        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)(ord[k] & kVertexMask));
         comp_out = (int)wave_min_fast(mn);
         size_out = ord_end;
     }
     if (dbg_slot >= 0) {
         for (int v = lane; v < n; v += 64) {
-            const uint32_t d = dist[v];
-            P.dbg_dist[(size_t)dbg_slot * n + v] = d == kInf ? 0xFFFFFFFFu : d;
-            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == kInf ? 0ull : sig[v];
+            const uint32_t d = (uint32_t)dist[v];
+            P.dbg_dist[(size_t)dbg_slot * n + v] = d == DO::unreached ? 0xFFFFFFFFu : d;
+            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == DO::unreached ? 0ull : sig[v];
             P.dbg_delta[(size_t)dbg_slot * n + v] = 0.0;
         }
         wave_sync();
     }
 
     // ------------------------------------------------------------ backward
-    for (int k = nseg - 1; k >= 0; --k) {
-        const int lo = aux[n - 1 - k];
-        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
-        for (int base = lo; base < hi; base += VPI) {
-            const int idx = base + lane / G;
-            const bool mine = idx < hi;
-            double sum = 0.0;
-            int v = 0;
-            if (mine) {
-                v = ord[idx];
-                const uint32_t dv = dist[v];
-                const uint32_t beg = rp[v], end = rp[v + 1];
-                for (uint32_t j = beg + sub; j < end; j += G) {
-                    const uint32_t a = adj[j];
-                    const uint32_t u = a & nmask;
-                    const uint32_t w = WEIGHTED ? (a >> shift) : 1u;
-                    if (dist[u] == dv + w) sum += as_f64(sig[u]);   // u succeeds v: c_u
-                }
-            }
-            sum = group_sum_f64<G>(sum);
-            if (mine && sub == 0) {
-                const double sv = (double)sig[v];
-                const double delta = sv * sum;
-                sig[v] = as_u64((1.0 + delta) / sv);
-                if (v != s) add_B<GB>(B, v, delta);
-                if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
+    // batches of one segment each, from the deepest vertices up
+    for (int hi = ord_end; hi > 0;) {
+        const int idx = hi - VPI + lane / G;
+        const uint32_t e = idx >= 0 ? (uint32_t)ord[idx] : 0u;
+        const int lo = batch_start(hi, VPI, e, G);
+        const bool mine = idx >= lo;
+        double sum = 0.0;
+        int v = 0;
+        if (mine) {
+            v = (int)(e & kVertexMask);
+            const uint32_t dv = (uint32_t)dist[v];
+            const uint32_t beg = rp[v], end = rp[v + 1];
+            for (uint32_t j = beg + sub; j < end; j += G) {
+                const uint32_t a = adj[j];
+                const uint32_t u = a & nmask;
+                const uint32_t w = WEIGHTED ? (a >> shift) : 1u;
+                if ((uint32_t)dist[u] == dv + w) sum += as_f64(sig[u]);   // u succeeds v: c_u
             }
         }
+        sum = group_sum_f64<G>(sum);
+        if (mine && sub == 0) {
+            const double sv = (double)sig[v];
+            const double delta = sv * sum;
+            sig[v] = as_u64((1.0 + delta) / sv);
+            if (v != s) add_B<GB>(B, v, delta);
+            if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
+        }
         wave_sync();
+        hi = lo;
     }
 }
 
@@ -211,32 +343,31 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 // With MASK the traversal stays inside the vertex set mask[v] != 0 (an induced
 // subgraph): an edge into a vertex outside it is never relaxed, so such a
 // vertex stays unreached and fails the predecessor and successor tests.
-template <bool WEIGHTED, int U, typename ADJ, bool GB, bool MASK = false>
-__device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
-                                 double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux,
-                                 uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf,
+template <bool WEIGHTED, int U, typename ADJ, bool GB, typename DT, bool MASK = false>
+__device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
+                                 DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s,
+                                 int dbg_slot, int &comp_out, int &size_out, bool &ovf,
                                  const uint8_t *mask = nullptr) {
+    using DO = DistOps<DT>;
     const int n = P.n;
     const int lane = threadIdx.x & 63;
     const uint32_t nmask = (1u << shift) - 1u;
 
-    for (int v = lane; v < n; v += 64) dist[v] = kInf;
+    for (int v = lane; v < n; v += 64) dist[v] = (DT)DO::unreached;
     wave_sync();
     if (lane == 0) {
-        dist[s] = 0u;
+        dist[s] = (DT)0u;
         sig[s] = 1ull;
-        ord[0] = (uint16_t)s;
+        ord[0] = (uint16_t)s | kSegMark;
         *ctr = WEIGHTED ? 0u : 1u;
     }
     wave_sync();
 
-    int f_lo = 0, ord_end = 1, nseg = 0;
+    int f_lo = 0, ord_end = 1;
     uint32_t D = 0;
     uint32_t kmin = kInf;
     // ------------------------------------------------------------ forward
     for (;;) {
-        if (lane == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
-        ++nseg;
         uint32_t lmin = kInf;
         for (int base = f_lo; base < ord_end; base += 64) {
             const int idx = base + lane;
@@ -244,7 +375,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             int v = 0;
             uint32_t beg = 0, len = 0;
             if (mine) {
-                v = ord[idx];
+                v = ord[idx] & kVertexMask;
                 beg = rp[v];
                 len = rp[v + 1] - beg;
             }
@@ -261,7 +392,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + k];
             }
             for (uint32_t off = 0; off < maxlen; off += U) {
-                uint32_t u[U], w[U], du[U], cur[U];
+                uint32_t u[U], w[U], du[U], wd[U], cur[U];
                 bool found[U];
                 if constexpr (GB) {
 #pragma unroll
@@ -283,7 +414,9 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                     w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
 #pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
+                for (int k = 0; k < U; ++k) wd[k] = DO::word(dist, u[k]);
+#pragma unroll
+                for (int k = 0; k < U; ++k) du[k] = DO::value(wd[k], u[k]);
                 bool pred[U], rel[U];
                 unsigned long long sg[U];
                 uint32_t old[U];
@@ -296,7 +429,10 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
 #pragma unroll
                 for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
 #pragma unroll
-                for (int k = 0; k < U; ++k) old[k] = rel[k] ? atomicMin(&dist[u[k]], D + w[k]) : 0u;
+                for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    if (rel[k]) old[k] = DO::resolve(dist, u[k], D + w[k], wd[k], old[k]);
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const unsigned long long x = acc + sg[k];
@@ -304,15 +440,16 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                     acc = x;
                     const uint32_t cand = (rel[k] && old[k] > D + w[k]) ? D + w[k] : kInf;
                     lmin = cand < lmin ? cand : lmin;
-                    found[k] = rel[k] && old[k] == kInf;                // first discovery of u
+                    found[k] = rel[k] && old[k] == DO::unreached;       // first discovery of u
                 }
                 uint32_t pos[U];
                 append_block<U>(ctr, found, pos);
 #pragma unroll
                 for (int k = 0; k < U; ++k)
                     if (found[k]) {
-                        if (WEIGHTED) aux[pos[k]] = (uint16_t)u[k];
-                        else ord[pos[k]] = (uint16_t)u[k];
+                        // unit weights: the next level starts at ord_end
+                        if (WEIGHTED) ord[ord_end + (int)pos[k]] = (uint16_t)u[k];
+                        else ord[pos[k]] = (uint16_t)u[k] | ((int)pos[k] == ord_end ? kSegMark : (uint16_t)0u);
                     }
             }
             if (mine && v != s) sig[v] = acc;
@@ -328,35 +465,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             const int fr = (int)*ctr;
             if (fr == 0) break;
             const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
-            int settled = 0, kept = 0;
-            kmin = kInf;
-            const uint64_t lt = lanemask_lt();
-            for (int k0 = 0; k0 < fr; k0 += 64 * U) {
-                uint32_t x[U], dx[U];
-#pragma unroll
-                for (int c = 0; c < U; ++c) {
-                    const int k = k0 + 64 * c + lane;
-                    x[c] = k < fr ? (uint32_t)aux[k] : 0xFFFFFFFFu;
-                }
-#pragma unroll
-                for (int c = 0; c < U; ++c) dx[c] = x[c] != 0xFFFFFFFFu ? dist[x[c]] : kInf;
-                // all reads of the U chunks precede their writes (positions
-                // never pass the read positions)
-                wave_sync();
-#pragma unroll
-                for (int c = 0; c < U; ++c) {
-                    const bool valid = x[c] != 0xFFFFFFFFu;
-                    const bool is_s = valid && dx[c] == mn;
-                    const bool is_k = valid && !is_s;
-                    if (is_k) kmin = dx[c] < kmin ? dx[c] : kmin;
-                    const uint64_t ms = __ballot(is_s), mk = __ballot(is_k);
-                    if (is_s) ord[ord_end + settled + __popcll(ms & lt)] = (uint16_t)x[c];
-                    if (is_k) aux[kept + __popcll(mk & lt)] = (uint16_t)x[c];
-                    settled += __popcll(ms);
-                    kept += __popcll(mk);
-                }
+            const int settled = fringe_partition<U>(ord, dist, ord_end, fr, mn, kmin);
+            if (lane == 0) {
+                *ctr = (uint32_t)(fr - settled);
+                ord[ord_end] |= kSegMark;
             }
-            if (lane == 0) *ctr = (uint32_t)kept;
             wave_sync();
             f_lo = ord_end;
             ord_end += settled;
@@ -366,34 +479,35 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
 
     {
         uint32_t mn = (uint32_t)n;
-        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)ord[k]);
+        for (int k = lane; k < ord_end; k += 64) mn = min(mn, (uint32_t)(ord[k] & kVertexMask));
         comp_out = (int)wave_min_fast(mn);
         size_out = ord_end;
     }
     if (dbg_slot >= 0) {
         for (int v = lane; v < n; v += 64) {
-            const uint32_t d = dist[v];
-            P.dbg_dist[(size_t)dbg_slot * n + v] = d == kInf ? 0xFFFFFFFFu : d;
-            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == kInf ? 0ull : sig[v];
+            const uint32_t d = (uint32_t)dist[v];
+            P.dbg_dist[(size_t)dbg_slot * n + v] = d == DO::unreached ? 0xFFFFFFFFu : d;
+            P.dbg_sigma[(size_t)dbg_slot * n + v] = d == DO::unreached ? 0ull : sig[v];
             P.dbg_delta[(size_t)dbg_slot * n + v] = 0.0;
         }
         wave_sync();
     }
 
     // ------------------------------------------------------------ backward
-    for (int k = nseg - 1; k >= 0; --k) {
-        const int lo = aux[n - 1 - k];
-        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
-        for (int base = lo; base < hi; base += 64) {
-            const int idx = base + lane;
-            const bool mine = idx < hi;
+    // batches of one segment each, from the deepest vertices up
+    for (int hi = ord_end; hi > 0;) {
+        {
+            const int idx = hi - 64 + lane;
+            const uint32_t e = idx >= 0 ? (uint32_t)ord[idx] : 0u;
+            const int lo = batch_start(hi, 64, e, 1);
+            const bool mine = idx >= lo;
             int v = 0;
             uint32_t beg = 0, len = 0, dv = 0;
             if (mine) {
-                v = ord[idx];
+                v = (int)(e & kVertexMask);
                 beg = rp[v];
                 len = rp[v + 1] - beg;
-                dv = dist[v];
+                dv = (uint32_t)dist[v];
             }
             double sum = 0.0;
             uint32_t nxt[U];
@@ -421,7 +535,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                     w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
                 }
 #pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = dist[u[k]];
+                for (int k = 0; k < U; ++k) du[k] = (uint32_t)dist[u[k]];
                 double cu[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) cu[k] = (du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
@@ -435,25 +549,35 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 if (v != s) add_B<GB>(B, v, delta);
                 if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
             }
+            wave_sync();
+            hi = lo;
         }
-        wave_sync();
     }
 }
 
 // One source with the vertex mapping G: 1 / 2 / 3 = lane per vertex with 4 /
 // 2 / 8 adjacency slots in flight, otherwise G lanes per vertex.
-template <bool WEIGHTED, int G, typename ADJ, bool GB>
+template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT>
 __device__ __forceinline__ void run_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
-                                           double *B, uint32_t *dist, unsigned long long *sig, uint16_t *ord,
-                                           uint16_t *aux, uint32_t *ctr, int s, int dbg_slot, int &comp_out,
-                                           int &size_out, bool &ovf) {
+                                           double *B, DT *dist, unsigned long long *sig, uint16_t *ord,
+                                           uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out,
+                                           bool &ovf) {
     if constexpr (G == 1 || G == 2 || G == 3)
-        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB>(P, rp, adj, shift, B, dist, sig, ord,
-                                                                            aux, ctr, s, dbg_slot, comp_out,
-                                                                            size_out, ovf);
+        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB, DT>(P, rp, adj, shift, B, dist, sig,
+                                                                                ord, ctr, s, dbg_slot, comp_out,
+                                                                                size_out, ovf);
     else
-        wave_source<WEIGHTED, G, ADJ, GB>(P, rp, adj, shift, B, dist, sig, ord, aux, ctr, s, dbg_slot, comp_out,
-                                          size_out, ovf);
+        wave_source<WEIGHTED, G, ADJ, GB, DT>(P, rp, adj, shift, B, dist, sig, ord, ctr, s, dbg_slot, comp_out,
+                                              size_out, ovf);
+}
+
+// Per-wavefront region of the sweep and trajectory kernels: dist DT[n] |
+// sig u64[n] | ord u16[n].
+__host__ __device__ inline uint32_t wave_sig_offset(int n, bool dist16) {
+    return ((dist16 ? 2u : 4u) * (uint32_t)n + 7u) & ~7u;
+}
+__host__ __device__ inline uint32_t wave_private_bytes(int n, bool dist16) {
+    return (wave_sig_offset(n, dist16) + 10u * (uint32_t)n + 15u) & ~15u;
 }
 
 // Byte offsets of the LDS carve-up (mirrors lds_bytes_wave on the host).

@@ -92,7 +92,12 @@ FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.WANT_N
                                         (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"group": 16}),
                                         (amc.MODE_WAVE, {"group": 3}), (amc.MODE_WAVE_L2, {}),
                                         (amc.MODE_WAVE_L2, {"tile": 3}), (amc.MODE_WAVE_L2, {"group": 8}),
-                                        (amc.MODE_WAVE_L2, {"flags": amc.PLAIN_LAUNCH})])
+                                        (amc.MODE_WAVE_L2, {"flags": amc.PLAIN_LAUNCH}),
+                                        (amc.MODE_WAVE, {"flags": amc.DIST16}),
+                                        (amc.MODE_WAVE, {"group": 8, "flags": amc.DIST16}),
+                                        (amc.MODE_WAVE, {"group": 3, "flags": amc.DIST16}),
+                                        (amc.MODE_WAVE_L2, {"flags": amc.DIST16}),
+                                        (amc.MODE_WAVE_L2, {"tile": 3, "flags": amc.DIST16})])
 def test_er20_full_against_oracle(ctx, mode, extra):
     wl = W.config_er20()
     g = wl.graph
@@ -118,15 +123,18 @@ def test_er20_full_against_oracle(ctx, mode, extra):
     assert res["admissible"] == t["admissible"]
     st = res["stats"]
     assert st["mode"] == mode
+    if mode != amc.MODE_BLOCK:          # 16 waves fit either way: 32-bit entries unless asked otherwise
+        assert st["dist_bytes"] == (2 if flags & amc.DIST16 else 4)
 
 
 def test_debug_dump_distances_sigma_delta(ctx):
     wl = W.config_er20()
     g = wl.graph
     pairs = [(0, 0), (3, 7), (999, 19), (500, 11)]
-    for mode in (amc.MODE_WAVE, amc.MODE_BLOCK, amc.MODE_WAVE_L2):
+    for mode, fl in ((amc.MODE_WAVE, 0), (amc.MODE_BLOCK, 0), (amc.MODE_WAVE_L2, 0), (amc.MODE_WAVE, amc.DIST16),
+                     (amc.MODE_WAVE_L2, amc.DIST16)):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, mode=mode,
-                      flags=amc.SKIP_TAIL, debug_pairs=pairs)
+                      flags=amc.SKIP_TAIL | fl, debug_pairs=pairs)
         for k, (r, s) in enumerate(pairs):
             alive, w = O.realize(g.n, g.eu, g.ev, wl.seed, r, **wl.model())
             d, sg, dl = O.sssp(g.n, g.eu, g.ev, alive, w, False, s)
@@ -177,6 +185,26 @@ def test_edge_cases(ctx, mode):
     _case(ctx, pw, {"p_fail": 0.1, "weight": "fixed"}, 40, mode=mode, pool=np.array([0, 5, 9, 33, 70]))
 
 
+@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_WAVE_L2])
+def test_edge_cases_16bit_distances(ctx, mode):
+    kw = dict(mode=mode, flags=FLAGS | amc.DIST16)
+    _case(ctx, W.canonical(1, []), {"p_fail": 0.1}, 5, k_min=1, **kw)
+    _case(ctx, W.canonical(7, []), {"p_fail": 0.5}, 9, k_min=1, **kw)
+    g = W.er_graph(40, 0.1, 3)
+    _case(ctx, g, {"p_fail": 1.0, "weight": "uniform", "w_lo": 1, "w_hi": 3}, 7, **kw)
+    _case(ctx, g, {"p_fail": 0.2, "weight": "uniform", "w_lo": 1, "w_hi": 1600}, 5, **kw)      # 40 * 1600 < 0xFFFF
+    path = W.canonical(60, [(i, i + 1) for i in range(59)])          # one vertex per segment
+    _case(ctx, path, {"p_fail": 0.02, "weight": "uniform", "w_lo": 1, "w_hi": 4}, 6, k_min=2, **kw)
+    _case(ctx, path, {"p_fail": 0.0, "weight": "unit"}, 3, k_min=2, **kw)
+    cr, pf = W.crossroads()
+    _case(ctx, cr, {"p_fail": 0.0, "p_fail_edge": pf}, 300, alpha=0.1, k_min=3, **kw)
+    pw = W.powerlaw_weighted_graph(77, 254, 2.5, 3.0, 31, 0)
+    _case(ctx, pw, {"p_fail": 0.1, "weight": "fixed"}, 40, pool=np.array([0, 5, 9, 33, 70]), **kw)
+    with pytest.raises(amc.AmcError) as ei:                          # 40 * 2000 >= 0xFFFF
+        _case(ctx, g, {"p_fail": 0.2, "weight": "uniform", "w_lo": 1, "w_hi": 2000}, 5, **kw)
+    assert ei.value.rc == amc.E_UNSUPPORTED
+
+
 def test_sigma_overflow_reported(ctx):
     a = 35
     idx = lambda i, j: i * a + j
@@ -211,7 +239,8 @@ def test_invalid_arguments(ctx):
                 {"model": {"p_fail": 0.1, "weight": "uniform", "w_lo": 0, "w_hi": 3}},
                 {"model": {"p_fail": 0.1}, "s": np.full(10, 0.2)},
                 {"model": {"p_fail": 0.1}, "pool": np.array([10])},
-                {"model": {"p_fail": 0.1, "weight": "fixed"}}):
+                {"model": {"p_fail": 0.1, "weight": "fixed"}},
+                {"model": {"p_fail": 0.1}, "flags": amc.DIST16 | amc.DIST32}):
         bad = dict(bad)
         model = bad.pop("model")
         bad.setdefault("R", 4)
@@ -225,9 +254,9 @@ def test_invalid_arguments(ctx):
 def test_ws1000_sampled_realizations(ctx):
     wl = W.config_ws1000()
     g = wl.graph
-    for r0, R in ((0, 3), (7777, 2)):
+    for r0, R, fl in ((0, 3, 0), (7777, 2, 0), (7777, 2, amc.DIST16), (7777, 2, amc.DIST32)):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
-                      flags=FLAGS, cert_topk=5)
+                      flags=FLAGS | fl, cert_topk=5)
         ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
                       want_next=True, **wl.model())
         check_sweep(res, ref, g.n, f"ws1000 r0={r0}")
