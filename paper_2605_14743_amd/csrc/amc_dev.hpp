@@ -153,7 +153,7 @@ constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps
 // D + kNoEdge > d and d != D + kNoEdge, and no sum exceeds 2^31.
 constexpr uint32_t kNoEdge = kInf + 1u;
 constexpr int kMaxWaves = 16;
-constexpr uint32_t kAdjPad = 8;          // zero entries after the realized adjacency
+constexpr uint32_t kAdjPad = 24;         // zero entries after the realized adjacency
 
 // ---------------------------------------------------------------------------
 // Wavefront helpers (wave64).

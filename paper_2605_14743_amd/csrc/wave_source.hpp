@@ -6,6 +6,8 @@
 // Uncertainty: An Absorbing Markov Chain Approach" (Section 3.1).
 #pragma once
 
+#include <type_traits>
+
 #include "amc_dev.hpp"
 
 namespace amc {
@@ -313,11 +315,14 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
 }
 
 // ---------------------------------------------------------------------------
-// Lane-per-vertex variant of wave_source: each lane owns one frontier vertex
+// Lane-per-vertex variant of wave_source: a lane owns one vertex of the batch
 // and walks its adjacency U slots at a time, issuing the U neighbour loads
 // (and the U distance loads) back to back so that their LDS latencies
 // overlap; the path count of the vertex accumulates in the lane itself.  The
-// U appends of a block share one LDS atomic per wavefront.
+// U appends of a block share one LDS atomic per wavefront.  A batch of at
+// most 32 (16) vertices gives each vertex 2 (4) lanes, which take every
+// second (fourth) slot: small segments, common near the source and at the
+// far end, then finish in half (a quarter) of the blocks.
 // ---------------------------------------------------------------------------
 template <int U>
 __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[U], uint32_t (&pos)[U]) {
@@ -343,6 +348,14 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 // With MASK the traversal stays inside the vertex set mask[v] != 0 (an induced
 // subgraph): an edge into a vertex outside it is never relaxed, so such a
 // vertex stays unreached and fails the predecessor and successor tests.
+//
+// Reads past a vertex's slots: a lane reads slots sub + G t for t below the
+// wavefront's rounded-up trip count, i.e. at most max-degree + G (U + 1)
+// entries past its vertex's first slot.  Past the last vertex these land in
+// the kAdjPad zero entries and then in what follows the adjacency (LDS, or
+// the rest of the workgroup's scratch in the L2 mode, at least 16 n bytes);
+// their neighbour is masked and their weight replaced by kNoEdge, so they are
+// never used.
 template <bool WEIGHTED, int U, typename ADJ, bool GB, typename DT, bool MASK = false>
 __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
                                  DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s,
@@ -366,93 +379,105 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
     int f_lo = 0, ord_end = 1;
     uint32_t D = 0;
     uint32_t kmin = kInf;
-    // ------------------------------------------------------------ forward
-    for (;;) {
-        uint32_t lmin = kInf;
-        for (int base = f_lo; base < ord_end; base += 64) {
-            const int idx = base + lane;
-            const bool mine = idx < ord_end;
-            int v = 0;
-            uint32_t beg = 0, len = 0;
-            if (mine) {
-                v = ord[idx] & kVertexMask;
-                beg = rp[v];
-                len = rp[v + 1] - beg;
-            }
-            const uint32_t maxlen = wave_max_fast(len);
-            unsigned long long acc = 0ull;
-            // the adjacency carries kAdjPad zero entries past its end (and, in
-            // the L2 mode, the rest of the workgroup scratch), so these loads
-            // need no predication; masked results are dropped.  In the L2
-            // mode the next block of U entries is loaded while the current
-            // one is used (global latency); LDS loads are issued in place.
-            uint32_t nxt[U];
+    uint32_t lmin = kInf;
+
+    // relaxations out of the batch ord[base, min(base + 64 / G, ord_end))
+    auto relax_batch = [&](auto gtag, int base) {
+        constexpr int G = decltype(gtag)::value;
+        const int sub = G == 1 ? 0 : lane % G;
+        const int idx = base + lane / G;
+        const bool mine = idx < ord_end;
+        int v = 0;
+        uint32_t beg = 0, len = 0;
+        if (mine) {
+            v = ord[idx] & kVertexMask;
+            beg = rp[v];
+            len = rp[v + 1] - beg;
+        }
+        const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
+        const uint32_t maxtrips = wave_max_fast(trips);
+        const uint32_t first = beg + (uint32_t)sub;
+        unsigned long long acc = 0ull;
+        // the L2 mode loads the next block of U slots while the current one
+        // is used (global latency); LDS loads are issued in place
+        uint32_t nxt[U];
+        if constexpr (GB) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * k];
+        }
+        for (uint32_t off = 0; off < maxtrips; off += U) {
+            uint32_t u[U], w[U], du[U], wd[U], cur[U];
+            bool found[U];
             if constexpr (GB) {
 #pragma unroll
-                for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + k];
+                for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+                if (off + U < maxtrips) {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * (off + U + k)];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[first + G * (off + k)];
             }
-            for (uint32_t off = 0; off < maxlen; off += U) {
-                uint32_t u[U], w[U], du[U], wd[U], cur[U];
-                bool found[U];
-                if constexpr (GB) {
+            // a slot past the vertex's adjacency gets weight kNoEdge, which
+            // fails both tests below (du + kNoEdge > D, D + kNoEdge > du)
 #pragma unroll
-                    for (int k = 0; k < U; ++k) cur[k] = nxt[k];
-                    if (off + U < maxlen) {
-#pragma unroll
-                        for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + off + U + k];
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[beg + off + k];
-                }
-                // a slot past the vertex's adjacency gets weight kNoEdge, which
-                // fails both tests below (du + kNoEdge > D, D + kNoEdge > du)
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint32_t a = cur[k];
-                    u[k] = a & nmask;
-                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) wd[k] = DO::word(dist, u[k]);
-#pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = DO::value(wd[k], u[k]);
-                bool pred[U], rel[U];
-                unsigned long long sg[U];
-                uint32_t old[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    pred[k] = du[k] + w[k] == D;                        // u precedes v: pull sigma_u
-                    rel[k] = D + w[k] < du[k];                          // relax the edge v -> u
-                    if constexpr (MASK) rel[k] = rel[k] && mask[u[k]] != 0;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
-#pragma unroll
-                for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-                    if (rel[k]) old[k] = DO::resolve(dist, u[k], D + w[k], wd[k], old[k]);
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const unsigned long long x = acc + sg[k];
-                    ovf |= x < acc;
-                    acc = x;
-                    const uint32_t cand = (rel[k] && old[k] > D + w[k]) ? D + w[k] : kInf;
-                    lmin = cand < lmin ? cand : lmin;
-                    found[k] = rel[k] && old[k] == DO::unreached;       // first discovery of u
-                }
-                uint32_t pos[U];
-                append_block<U>(ctr, found, pos);
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-                    if (found[k]) {
-                        // unit weights: the next level starts at ord_end
-                        if (WEIGHTED) ord[ord_end + (int)pos[k]] = (uint16_t)u[k];
-                        else ord[pos[k]] = (uint16_t)u[k] | ((int)pos[k] == ord_end ? kSegMark : (uint16_t)0u);
-                    }
+            for (int k = 0; k < U; ++k) {
+                const uint32_t a = cur[k];
+                u[k] = a & nmask;
+                w[k] = (off + k < trips) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
             }
-            if (mine && v != s) sig[v] = acc;
+#pragma unroll
+            for (int k = 0; k < U; ++k) wd[k] = DO::word(dist, u[k]);
+#pragma unroll
+            for (int k = 0; k < U; ++k) du[k] = DO::value(wd[k], u[k]);
+            bool pred[U], rel[U];
+            unsigned long long sg[U];
+            uint32_t old[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                pred[k] = du[k] + w[k] == D;                        // u precedes v: pull sigma_u
+                rel[k] = D + w[k] < du[k];                          // relax the edge v -> u
+                if constexpr (MASK) rel[k] = rel[k] && mask[u[k]] != 0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
+#pragma unroll
+            for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (rel[k]) old[k] = DO::resolve(dist, u[k], D + w[k], wd[k], old[k]);
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const unsigned long long x = acc + sg[k];
+                ovf |= x < acc;
+                acc = x;
+                const uint32_t cand = (rel[k] && old[k] > D + w[k]) ? D + w[k] : kInf;
+                lmin = cand < lmin ? cand : lmin;
+                found[k] = rel[k] && old[k] == DO::unreached;       // first discovery of u
+            }
+            uint32_t pos[U];
+            append_block<U>(ctr, found, pos);
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (found[k]) {
+                    // unit weights: the next level starts at ord_end
+                    if (WEIGHTED) ord[ord_end + (int)pos[k]] = (uint16_t)u[k];
+                    else ord[pos[k]] = (uint16_t)u[k] | ((int)pos[k] == ord_end ? kSegMark : (uint16_t)0u);
+                }
+        }
+        if constexpr (G > 1) acc = group_sum_u64<G>(acc, ovf);
+        if (mine && sub == 0 && v != s) sig[v] = acc;
+    };
+
+    // ------------------------------------------------------------ forward
+    for (;;) {
+        lmin = kInf;
+        for (int base = f_lo; base < ord_end; base += 64) {
+            const int k = ord_end - base;
+            if (k > 32) relax_batch(std::integral_constant<int, 1>{}, base);
+            else if (k > 16) relax_batch(std::integral_constant<int, 2>{}, base);
+            else relax_batch(std::integral_constant<int, 4>{}, base);
         }
         wave_sync();
         if (!WEIGHTED) {
@@ -465,7 +490,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             const int fr = (int)*ctr;
             if (fr == 0) break;
             const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
-            const int settled = fringe_partition<U>(ord, dist, ord_end, fr, mn, kmin);
+            // chunks of 64, 128 or 64 U entries, by the fringe's length
+            int settled;
+            if (fr <= 64 || U == 1) settled = fringe_partition<1>(ord, dist, ord_end, fr, mn, kmin);
+            else if (fr <= 128 || U == 2) settled = fringe_partition<2>(ord, dist, ord_end, fr, mn, kmin);
+            else settled = fringe_partition<U>(ord, dist, ord_end, fr, mn, kmin);
             if (lane == 0) {
                 *ctr = (uint32_t)(fr - settled);
                 ord[ord_end] |= kSegMark;
@@ -493,65 +522,86 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
         wave_sync();
     }
 
+    // dependencies of the batch ord[lo, hi) (one equal-distance segment, k =
+    // hi - lo vertices); e0 is ord[hi - 64 + lane]
+    auto accumulate_batch = [&](auto gtag, int lo, int hi, uint32_t e0) {
+        constexpr int G = decltype(gtag)::value;
+        const int sub = G == 1 ? 0 : lane % G;
+        bool mine;
+        uint32_t e;
+        if constexpr (G == 1) {
+            mine = hi - 64 + lane >= lo;
+            e = e0;
+        } else {
+            const int slot = lane / G, k = hi - lo;
+            mine = slot < k;
+            e = (uint32_t)__shfl((int)e0, mine ? 64 - k + slot : 63, 64);
+        }
+        int v = 0;
+        uint32_t beg = 0, len = 0, dv = 0;
+        if (mine) {
+            v = (int)(e & kVertexMask);
+            beg = rp[v];
+            len = rp[v + 1] - beg;
+            dv = (uint32_t)dist[v];
+        }
+        const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
+        const uint32_t first = beg + (uint32_t)sub;
+        double sum = 0.0;
+        uint32_t nxt[U];
+        if constexpr (GB) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * k];
+        }
+        for (uint32_t off = 0; off < trips; off += U) {
+            uint32_t u[U], w[U], du[U], cur[U];
+            if constexpr (GB) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+                if (off + U < trips) {
+#pragma unroll
+                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * (off + U + k)];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[first + G * (off + k)];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t a = cur[k];
+                u[k] = a & nmask;
+                w[k] = (off + k < trips) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) du[k] = (uint32_t)dist[u[k]];
+            double cu[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) cu[k] = (du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
+#pragma unroll
+            for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
+        }
+        if constexpr (G > 1) sum = group_sum_f64<G>(sum);
+        if (mine && sub == 0) {
+            const double sv = (double)sig[v];
+            const double delta = sv * sum;
+            sig[v] = as_u64((1.0 + delta) / sv);
+            if (v != s) add_B<GB>(B, v, delta);
+            if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
+        }
+    };
+
     // ------------------------------------------------------------ backward
     // batches of one segment each, from the deepest vertices up
     for (int hi = ord_end; hi > 0;) {
-        {
-            const int idx = hi - 64 + lane;
-            const uint32_t e = idx >= 0 ? (uint32_t)ord[idx] : 0u;
-            const int lo = batch_start(hi, 64, e, 1);
-            const bool mine = idx >= lo;
-            int v = 0;
-            uint32_t beg = 0, len = 0, dv = 0;
-            if (mine) {
-                v = (int)(e & kVertexMask);
-                beg = rp[v];
-                len = rp[v + 1] - beg;
-                dv = (uint32_t)dist[v];
-            }
-            double sum = 0.0;
-            uint32_t nxt[U];
-            if constexpr (GB) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + k];
-            }
-            for (uint32_t off = 0; off < len; off += U) {
-                uint32_t u[U], w[U], du[U], cur[U];
-                if constexpr (GB) {
-#pragma unroll
-                    for (int k = 0; k < U; ++k) cur[k] = nxt[k];
-                    if (off + U < len) {
-#pragma unroll
-                        for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[beg + off + U + k];
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[beg + off + k];
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint32_t a = cur[k];
-                    u[k] = a & nmask;
-                    w[k] = (off + k < len) ? (WEIGHTED ? (a >> shift) : 1u) : kNoEdge;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) du[k] = (uint32_t)dist[u[k]];
-                double cu[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) cu[k] = (du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
-#pragma unroll
-                for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
-            }
-            if (mine) {
-                const double sv = (double)sig[v];
-                const double delta = sv * sum;
-                sig[v] = as_u64((1.0 + delta) / sv);
-                if (v != s) add_B<GB>(B, v, delta);
-                if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
-            }
-            wave_sync();
-            hi = lo;
-        }
+        const int idx = hi - 64 + lane;
+        const uint32_t e0 = idx >= 0 ? (uint32_t)ord[idx] : 0u;
+        const int lo = batch_start(hi, 64, e0, 1);
+        const int k = hi - lo;
+        if (k > 32) accumulate_batch(std::integral_constant<int, 1>{}, lo, hi, e0);
+        else if (k > 16) accumulate_batch(std::integral_constant<int, 2>{}, lo, hi, e0);
+        else accumulate_batch(std::integral_constant<int, 4>{}, lo, hi, e0);
+        wave_sync();
+        hi = lo;
     }
 }
 
