@@ -292,6 +292,15 @@ __device__ __forceinline__ T *to_global(T *p) {
     return (T *)((__attribute__((address_space(1))) T *)p);
 }
 
+// Element idx of an array addressed by a 32-bit byte offset from its base: a
+// global array is then read with the base in scalar registers and the offset
+// in one vector register, without 64-bit address arithmetic per lane (the
+// arrays read this way are far below 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ld_off32(const T *base, uint32_t idx) {
+    return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
+}
+
 // Adds into a double in global memory with a global (not flat) atomic: a flat
 // atomic would also hold the LDS wait counter of the issuing wavefront.
 __device__ __forceinline__ void global_add_f64(double *p, double v) {

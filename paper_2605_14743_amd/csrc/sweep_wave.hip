@@ -60,7 +60,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             if (tid == 0) item_sh = (int)atomicAdd(LC.work_ctr, 1u);
             __syncthreads();
         }
-        const int it = item_sh;
+        const int it = __builtin_amdgcn_readfirstlane(item_sh);
         __syncthreads();
         if ((uint32_t)it >= LC.n_items) break;
         const uint32_t item = LC.item_base + (uint32_t)it;

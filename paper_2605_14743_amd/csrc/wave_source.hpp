@@ -391,8 +391,8 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
         uint32_t beg = 0, len = 0;
         if (mine) {
             v = ord[idx] & kVertexMask;
-            beg = rp[v];
-            len = rp[v + 1] - beg;
+            beg = ld_off32(rp, (uint32_t)v);
+            len = ld_off32(rp, (uint32_t)v + 1u) - beg;
         }
         const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
         const uint32_t maxtrips = wave_max_fast(trips);
@@ -403,7 +403,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
         uint32_t nxt[U];
         if constexpr (GB) {
 #pragma unroll
-            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * k];
+            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)ld_off32(adj, first + G * k);
         }
         for (uint32_t off = 0; off < maxtrips; off += U) {
             uint32_t u[U], w[U], du[U], wd[U], cur[U];
@@ -413,11 +413,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 for (int k = 0; k < U; ++k) cur[k] = nxt[k];
                 if (off + U < maxtrips) {
 #pragma unroll
-                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * (off + U + k)];
+                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)ld_off32(adj, first + G * (off + U + k));
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[first + G * (off + k)];
+                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)ld_off32(adj, first + G * (off + k));
             }
             // a slot past the vertex's adjacency gets weight kNoEdge, which
             // fails both tests below (du + kNoEdge > D, D + kNoEdge > du)
@@ -441,7 +441,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 if constexpr (MASK) rel[k] = rel[k] && mask[u[k]] != 0;
             }
 #pragma unroll
-            for (int k = 0; k < U; ++k) sg[k] = pred[k] ? sig[u[k]] : 0ull;
+            for (int k = 0; k < U; ++k) {
+                // read from a vertex in range either way (no branch), keep it if u precedes v
+                const unsigned long long val = sig[pred[k] ? u[k] : (uint32_t)s];
+                sg[k] = pred[k] ? val : 0ull;
+            }
 #pragma unroll
             for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
 #pragma unroll
@@ -541,8 +545,8 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
         uint32_t beg = 0, len = 0, dv = 0;
         if (mine) {
             v = (int)(e & kVertexMask);
-            beg = rp[v];
-            len = rp[v + 1] - beg;
+            beg = ld_off32(rp, (uint32_t)v);
+            len = ld_off32(rp, (uint32_t)v + 1u) - beg;
             dv = (uint32_t)dist[v];
         }
         const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
@@ -551,7 +555,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
         uint32_t nxt[U];
         if constexpr (GB) {
 #pragma unroll
-            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * k];
+            for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)ld_off32(adj, first + G * k);
         }
         for (uint32_t off = 0; off < trips; off += U) {
             uint32_t u[U], w[U], du[U], cur[U];
@@ -560,11 +564,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 for (int k = 0; k < U; ++k) cur[k] = nxt[k];
                 if (off + U < trips) {
 #pragma unroll
-                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)adj[first + G * (off + U + k)];
+                    for (int k = 0; k < U; ++k) nxt[k] = (uint32_t)ld_off32(adj, first + G * (off + U + k));
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)adj[first + G * (off + k)];
+                for (int k = 0; k < U; ++k) cur[k] = (uint32_t)ld_off32(adj, first + G * (off + k));
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -576,7 +580,11 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             for (int k = 0; k < U; ++k) du[k] = (uint32_t)dist[u[k]];
             double cu[U];
 #pragma unroll
-            for (int k = 0; k < U; ++k) cu[k] = (du[k] == dv + w[k]) ? as_f64(sig[u[k]]) : 0.0;
+            for (int k = 0; k < U; ++k) {
+                const bool succ = du[k] == dv + w[k];
+                const unsigned long long val = sig[succ ? u[k] : (uint32_t)v];
+                cu[k] = succ ? as_f64(val) : 0.0;
+            }
 #pragma unroll
             for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
         }
