@@ -124,7 +124,7 @@ def run_bench(args):
                    "weights": wl.weight if wl.weight != "uniform" else f"uniform{{{wl.w_lo}..{wl.w_hi}}}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
                    "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"], "group": st["group"],
-                   "adj_bytes": st["adj_bytes"], "dist_bytes": st["dist_bytes"]},
+                   "adj_bytes": st["adj_bytes"], "dist_bytes": st["dist_bytes"], "b_global": st["b_global"]},
         "sweep_kernel_ms": k_ms,
         "tail_ms": float(np.mean(tail_ms)),
         "teps": teps,

@@ -182,7 +182,7 @@ typedef struct amc_stats {
     int32_t mode, waves, tile, blocks, lds_bytes, launches, group, adj_bytes;
     double topk_ms;             /* HIP-event time of the finite-k Top-k stage (topk > 0) */
     int32_t dist_bytes;         /* bytes per distance entry of the per-source state (2 or 4) */
-    int32_t reserved;
+    int32_t b_global;           /* L2 mode: 1 = B(H_r) in the L2-resident scratch, 0 = in LDS */
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */

@@ -469,19 +469,21 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     if (q->waves > max_w && q->mode != AMC_MODE_BLOCK) return AMC_E_UNSUPPORTED;
     const int want_w = n > kMaxWaveVertices ? 0 : (q->waves > 0 ? q->waves : max_w);
     const uint64_t need = std::max<uint64_t>(2ull * (uint64_t)g->m, kReduceBytesPerVertex * (uint64_t)n);
-    // per-wavefront configurations [L2 mode][16-bit distances]: the most
-    // wavefronts that fit (or exactly the requested number)
+    // per-wavefront configurations [placement][16-bit distances]: the most
+    // wavefronts that fit (or exactly the requested number).  Placement 0:
+    // LDS mode; 1: L2 mode with B(H_r) in LDS; 2: L2 mode with B in the
+    // global scratch
     struct Fit {
         int w = 0;
         uint32_t lds = 0, wb = 0;
-    } fits[2][2];
-    for (int l2 = 0; l2 < 2; ++l2)
+    } fits[3][2];
+    for (int pc = 0; pc < 3; ++pc)
         for (int d16 = 0; d16 < 2; ++d16) {
             if (d16 && !pl->dist16) continue;
-            Fit &f = fits[l2][d16];
+            Fit &f = fits[pc][d16];
             for (int w = 2; w <= want_w; ++w) {
                 uint32_t wb = 0;
-                const uint32_t lds = l2 ? lds_bytes_wave_l2(n, w, d16 != 0, &wb)
+                const uint32_t lds = pc ? lds_bytes_wave_l2(n, w, d16 != 0, pc == 2, &wb)
                                         : lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, d16 != 0, &wb);
                 if (lds > (uint32_t)ctx->max_lds) break;
                 if ((uint64_t)wb * w < need) continue;   // staging and reduction scratch
@@ -491,18 +493,21 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         }
     // throughput of one wavefront relative to an LDS-mode wavefront with
     // 32-bit distances (measured on MI355X, weighted ER and WS graphs, n =
-    // 1000 .. 4000): L2 mode 0.87 (adjacency reads and B atomics at L2),
-    // 16-bit distances 0.83 (compare-and-swap minima); per-source rates grow
-    // close to linearly with the wavefronts a CU holds
-    auto eff = [&](int l2, int d16) { return fits[l2][d16].w * (l2 ? 0.87 : 1.0) * (d16 ? 0.83 : 1.0); };
-    auto width = [&](int l2) {
+    // 1000 .. 4000): L2 mode 0.92 with B in LDS (adjacency reads at L2), 0.87
+    // with B in the global scratch (B atomics leave the L2), 16-bit distances
+    // 0.83 (compare-and-swap minima); per-source rates grow close to linearly
+    // with the wavefronts a CU holds
+    const double place_eff[3] = {1.0, 0.92, 0.87};
+    auto eff = [&](int pc, int d16) { return fits[pc][d16].w * place_eff[pc] * (d16 ? 0.83 : 1.0); };
+    auto width = [&](int pc) {
         if (q->flags & AMC_DIST16) return 1;
-        return eff(l2, 1) > eff(l2, 0) ? 1 : 0;
+        return eff(pc, 1) > eff(pc, 0) ? 1 : 0;
     };
+    const int l2_pc = eff(1, width(1)) >= eff(2, width(2)) ? 1 : 2;
     int mode = q->mode;
     if (mode == AMC_MODE_AUTO) {
-        const double e_lds = eff(0, width(0)), e_l2 = eff(1, width(1));
-        const int w_l2 = fits[1][width(1)].w;
+        const double e_lds = eff(0, width(0)), e_l2 = eff(l2_pc, width(l2_pc));
+        const int w_l2 = fits[l2_pc][width(l2_pc)].w;
         // with only two wavefronts even in L2 mode, the workgroup-per-source
         // mode is as fast for weighted graphs beyond n = 4000 and faster for
         // unit weights
@@ -513,18 +518,20 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     }
     pl->mode = mode;
     pl->scratch_words = 0;
+    pl->b_global = false;
     if (mode == AMC_MODE_WAVE || mode == AMC_MODE_WAVE_L2) {
-        const int l2 = mode == AMC_MODE_WAVE_L2 ? 1 : 0;
-        const int d16 = width(l2);
-        const Fit &f = fits[l2][d16];
+        const int pc = mode == AMC_MODE_WAVE_L2 ? l2_pc : 0;
+        const int d16 = width(pc);
+        const Fit &f = fits[pc][d16];
         if (f.w < 2) return AMC_E_UNSUPPORTED;
         pl->dist16 = d16 != 0;
+        pl->b_global = pc == 2;
         pl->waves = f.w;
         pl->lds = f.lds;
         pl->wave_bytes = f.wb;
         pl->threads = 64 * f.w;
         pl->adj_cap = adj_cap;
-        if (l2) pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
+        if (pc) pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
     } else {
         pl->dist16 = false;
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;

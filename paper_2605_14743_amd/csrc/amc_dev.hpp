@@ -83,6 +83,7 @@ struct SweepParams {
     unsigned int *done;         // R
     int32_t keep_rows;
     int32_t hop_radius;         // anchored r-hop neighbourhoods (0 = off)
+    int32_t b_global;           // L2 mode: B(H_r) in the global scratch (1) or in LDS (0)
     // per-(r, s) dumps for the parity checks
     const uint32_t *dbg_pairs;  // n_dbg x (r, s)
     int32_t n_dbg;
@@ -313,11 +314,18 @@ __device__ __forceinline__ void st_global(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
 
-// B(H_r)[v] += delta: an LDS atomic (LDS mode) or a global one (L2 mode).
-template <bool GB>
-__device__ __forceinline__ void add_B(double *B, int v, double delta) {
-    if constexpr (GB) global_add_f64(&B[v], delta);
-    else unsafeAtomicAdd(&B[v], delta);
+// Where a wavefront adds delta_s(v) into B(H_r): an LDS array (lds), or,
+// with glob set, an array in the workgroup's global scratch (gl).  Device
+// atomics on a global B leave the XCD's L2 as one fabric write each, so B
+// stays in LDS unless that costs a wavefront.  Both pointers keep their
+// address space, so each add is a plain LDS or global atomic.
+struct BAcc {
+    double *lds, *gl;
+    bool glob;
+};
+__device__ __forceinline__ void add_B(const BAcc &B, int v, double delta) {
+    if (B.glob) global_add_f64(&B.gl[v], delta);
+    else unsafeAtomicAdd(&B.lds[v], delta);
 }
 
 // Load that bypasses the CU's vector L1 when COH: values produced by device

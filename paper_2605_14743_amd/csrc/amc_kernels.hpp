@@ -13,7 +13,7 @@ namespace amc {
 // (realized graph, B and labels in a per-workgroup global scratch); dist16
 // selects 16-bit distance entries in the wavefront regions.
 uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, bool dist16, uint32_t *wave_bytes);
-uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, uint32_t *wave_bytes);
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, uint32_t *wave_bytes);
 size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes);
 hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, int group, uint32_t adj_bytes,
                              int blocks, int waves, uint32_t lds, hipStream_t st);

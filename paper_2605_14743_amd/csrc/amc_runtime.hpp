@@ -48,6 +48,7 @@ struct Plan {
     uint32_t scratch_words = 0;     // per-workgroup global scratch (block and L2 modes)
     bool anchored = false;          // anchored r-hop neighbourhoods (own kernel)
     bool dist16 = false;            // 16-bit distance entries in the wavefront regions
+    bool b_global = false;          // L2 mode: B(H_r) in the global scratch instead of LDS
 };
 
 // Private copies of the arrays a query points to (inputs are never retained):

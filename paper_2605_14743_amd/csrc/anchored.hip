@@ -71,6 +71,7 @@ __global__ __launch_bounds__(1024) void anchored_kernel(LaunchCtl LC) {
         unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
         uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
         double *Bw = (double *)(wmine + b_off);
+        const BAcc BA{Bw, nullptr, false};
         uint16_t *list = (uint16_t *)(wmine + b_off + 8u * (uint32_t)n);
         uint8_t *mask = (uint8_t *)(list + n);
 
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(1024) void anchored_kernel(LaunchCtl LC) {
             // betweenness of the induced subgraph, one source after another
             for (int k = 0; k < sz; ++k) {
                 int cs = 0, zz = 0;
-                wave_source_lane<WEIGHTED, 4, ADJ, false, uint32_t, true>(P, rp, adj, shift, Bw, dist, sig, ord,
+                wave_source_lane<WEIGHTED, 4, ADJ, false, uint32_t, true>(P, rp, adj, shift, BA, dist, sig, ord,
                                                                           &wctr[wave], (int)list[k], -1, cs, zz,
                                                                           ovf, mask);
             }

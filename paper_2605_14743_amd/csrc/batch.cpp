@@ -167,7 +167,8 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
                 R.pl.lds = G.pl.mode == AMC_MODE_WAVE
                                ? lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, R.pl.dist16,
                                                 &R.pl.wave_bytes)
-                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, R.pl.dist16, &R.pl.wave_bytes);
+                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, R.pl.dist16, R.pl.b_global,
+                                                   &R.pl.wave_bytes);
             }
             G.pl.lds = std::max(G.pl.lds, R.pl.lds);
             G.bscratch_words = std::max<uint32_t>(G.bscratch_words, R.pl.scratch_words);

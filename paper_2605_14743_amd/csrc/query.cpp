@@ -106,6 +106,7 @@ int qr_fill_desc(QueryRun &R, hipStream_t st) {
     P.wave_bytes = R.pl.wave_bytes;
     P.shift = R.pl.shift;
     P.hop_radius = q->hop_radius;
+    P.b_global = R.pl.b_global ? 1 : 0;
     return AMC_OK;
 }
 
@@ -440,6 +441,7 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
         out->stats.group = R.pl.group;
         out->stats.adj_bytes = (int32_t)R.pl.adj_bytes;
         out->stats.dist_bytes = R.pl.dist16 ? 2 : 4;
+        out->stats.b_global = R.pl.b_global ? 1 : 0;
     }
     if (!(q.flags & AMC_SKIP_TAIL)) {
         const TailBufs &T = R.T;

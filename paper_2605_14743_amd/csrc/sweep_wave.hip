@@ -28,9 +28,10 @@ namespace amc {
 
 // Persistent sweep.  GL = false: LDS mode (realized graph, B(H_r) and the
 // component labels in LDS next to the wavefronts' regions).  GL = true: L2
-// mode (those in the workgroup's global scratch, B accumulated with device
-// atomics), which leaves the whole LDS to per-source state and so keeps more
-// sources in flight on graphs whose realized adjacency would crowd the LDS.
+// mode (the realized graph and the labels in the workgroup's global scratch,
+// B(H_r) alone in LDS), which leaves almost the whole LDS to per-source state
+// and so keeps more sources in flight on graphs whose realized adjacency
+// would crowd the LDS.
 // The 8-slot lane mapping needs more than the 128 VGPRs a 1024-thread
 // workgroup allows; it is limited to 8 wavefronts per workgroup.  D16: 16-bit
 // distance entries in the wavefront regions.
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
         const bool split = P.tiles_per_r > 1;
 
         ADJ *rp, *adj;
-        double *B;
+        double *B;               // B(H_r) as the reduction reads it
+        BAcc BA{nullptr, nullptr, false};
         unsigned char *wbase;
         // component labels / sizes of the sources: LDS u16 (LDS mode) or
         // global int32 (L2 mode)
@@ -90,16 +92,20 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             unsigned char *gs = (unsigned char *)(LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words);
             rp = to_global((ADJ *)(gs + L.rp));
             adj = to_global((ADJ *)(gs + L.adj));
-            // a split realization accumulates straight into its exchange rows
-            B = to_global(split ? P.Bg + (size_t)r_local * n : (double *)(gs + L.B));
+            BA.glob = P.b_global != 0;
+            BA.lds = (double *)smem;
+            BA.gl = to_global((double *)(gs + L.B));
+            B = BA.glob ? BA.gl : BA.lds;
+            // a split realization writes its labels straight into its exchange rows
             comp32 = to_global(split ? P.compg + (size_t)r_local * n : (int32_t *)(gs + L.comp));
             csize32 = to_global(split ? P.sizeg + (size_t)r_local * n : (int32_t *)(gs + L.csize));
-            wbase = smem;
+            wbase = smem + (BA.glob ? 0u : l2_lds_b_bytes(n));
         } else {
             const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
             rp = (ADJ *)(smem + L.rp);
             adj = (ADJ *)(smem + L.adj);
             B = (double *)(smem + L.B);
+            BA.lds = B;
             comp16 = (uint16_t *)(smem + L.comp);
             csize16 = (uint16_t *)(smem + L.csize);
             wbase = smem + L.waves;
@@ -118,15 +124,14 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
 
         if (tid == 0) src_ctr = 0u;
         stage_realization(P, r, rp, adj, shift, (uint16_t *)wbase, scan_tmp);
-        if constexpr (GL) {
-            if (!split)
-                for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
-            // the realized graph and the cleared B are complete at L2 before
-            // any wavefront reads them or adds into B
-            __threadfence();
+        if (BA.glob) {
+            for (int v = tid; v < n; v += blockDim.x) st_global(&BA.gl[v], 0.0);
         } else {
-            for (int v = tid; v < n; v += blockDim.x) B[v] = 0.0;
+            for (int v = tid; v < n; v += blockDim.x) BA.lds[v] = 0.0;
         }
+        // L2 mode: the realized graph (and a global B) are complete at L2
+        // before any wavefront reads them or adds into B
+        if constexpr (GL) __threadfence();
         __syncthreads();
 
         // sources are taken from a workgroup counter: the wavefronts of a
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             if (s >= s_hi) break;
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, shift, B, dist, sig, ord, &wctr[wave], s, slot, cs, sz,
+            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, shift, BA, dist, sig, ord, &wctr[wave], s, slot, cs, sz,
                                                  ovf);
             if (lane == 0) {
                 if constexpr (GL) {
@@ -152,18 +157,27 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             }
         }
         if constexpr (GL) {
-            // every B atomic and label store of this item has reached L2
+            // every label store (and global B atomic) of this item has reached L2
             __threadfence();
             __syncthreads();
             if (!split) {
                 reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
                                                        acc_stats, true);
             } else {
+                // publish this tile's partial B; the last tile of the
+                // realization to finish gathers the row and reduces
+                double *Bg = P.Bg + (size_t)r_local * n;
+                for (int v = tid; v < n; v += blockDim.x) {
+                    const double b = ld_coh<true>(&B[v]);
+                    if (b != 0.0) unsafeAtomicAdd(&Bg[v], b);
+                }
+                __threadfence();
+                __syncthreads();
                 if (tid == 0) last_sh = (atomicAdd(&P.done[r_local], 1u) == (unsigned)(P.tiles_per_r - 1));
                 __syncthreads();
                 if (last_sh) {
                     __threadfence();
-                    reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, B, comp32, csize32, RS, red_f, red_i,
+                    reduce_realization<ADJ, int32_t, true>(P, r_local, r, rp, Bg, comp32, csize32, RS, red_f, red_i,
                                                            acc_stats, false);
                 }
                 __syncthreads();
@@ -215,10 +229,10 @@ uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, 
     return wave_layout(n, adj_cap, adj_bytes).waves + wb * (uint32_t)waves;
 }
 
-uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, uint32_t *wave_bytes) {
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, uint32_t *wave_bytes) {
     const uint32_t wb = wave_private_bytes(n, dist16);
     if (wave_bytes) *wave_bytes = wb;
-    return wb * (uint32_t)waves;
+    return (b_global ? 0u : l2_lds_b_bytes(n)) + wb * (uint32_t)waves;
 }
 
 size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes) {

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     ADJ *rp = (ADJ *)(smem + L.rp);
     ADJ *adj = (ADJ *)(smem + L.adj);
     double *B = (double *)(smem + L.B);
+    const BAcc BA{B, nullptr, false};
     uint16_t *list = (uint16_t *)(smem + L.comp);        // K(X_t;H), in wavefront 0's visit order
     unsigned char *wbase = smem + L.waves;
     unsigned char *wmine = wbase + wave * P.wave_bytes;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                 __syncthreads();
                 if (wave == 0) {
                     int cs = 0, sz = 0;
-                    run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, B, dist, sig, ord, &wctr[0], x, -1, cs,
+                    run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[0], x, -1, cs,
                                                         sz, ovf);
                     for (int k = lane; k < sz; k += 64) list[k] = ord[k] & kVertexMask;
                     if (lane == 0) size_sh = sz;
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                 if ((uint32_t)sz >= P.k_min) {
                     for (int k = 1 + wave; k < sz; k += nwaves) {
                         int cs = 0, zz = 0;
-                        run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, B, dist, sig, ord, &wctr[wave],
+                        run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[wave],
                                                             (int)list[k], -1, cs, zz, ovf);
                     }
                     __syncthreads();

@@ -172,8 +172,8 @@ __device__ __forceinline__ int batch_start(int hi, int width, uint32_t e, int G)
 }
 
 template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT>
-__device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B, DT *dist,
-                            unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s, int dbg_slot,
+__device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, const BAcc &BA,
+                            DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s, int dbg_slot,
                             int &comp_out, int &size_out, bool &ovf) {
     using DO = DistOps<DT>;
     const int n = P.n;
@@ -306,7 +306,7 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
             const double sv = (double)sig[v];
             const double delta = sv * sum;
             sig[v] = as_u64((1.0 + delta) / sv);
-            if (v != s) add_B<GB>(B, v, delta);
+            if (v != s) add_B(BA, v, delta);
             if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
         }
         wave_sync();
@@ -353,12 +353,12 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 // wavefront's rounded-up trip count, i.e. at most max-degree + G (U + 1)
 // entries past its vertex's first slot.  Past the last vertex these land in
 // the kAdjPad zero entries and then in what follows the adjacency (LDS, or
-// the rest of the workgroup's scratch in the L2 mode, at least 16 n bytes);
+// the rest of the workgroup's scratch in the L2 mode, 16 n + 64 bytes or more);
 // their neighbour is masked and their weight replaced by kNoEdge, so they are
 // never used.
 template <bool WEIGHTED, int U, typename ADJ, bool GB, typename DT, bool MASK = false>
-__device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift, double *B,
-                                 DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s,
+__device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
+                                 const BAcc &BA, DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s,
                                  int dbg_slot, int &comp_out, int &size_out, bool &ovf,
                                  const uint8_t *mask = nullptr) {
     using DO = DistOps<DT>;
@@ -593,7 +593,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             const double sv = (double)sig[v];
             const double delta = sv * sum;
             sig[v] = as_u64((1.0 + delta) / sv);
-            if (v != s) add_B<GB>(B, v, delta);
+            if (v != s) add_B(BA, v, delta);
             if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
         }
     };
@@ -617,15 +617,15 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
 // 2 / 8 adjacency slots in flight, otherwise G lanes per vertex.
 template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT>
 __device__ __forceinline__ void run_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
-                                           double *B, DT *dist, unsigned long long *sig, uint16_t *ord,
+                                           const BAcc &BA, DT *dist, unsigned long long *sig, uint16_t *ord,
                                            uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out,
                                            bool &ovf) {
     if constexpr (G == 1 || G == 2 || G == 3)
-        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB, DT>(P, rp, adj, shift, B, dist, sig,
+        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB, DT>(P, rp, adj, shift, BA, dist, sig,
                                                                                 ord, ctr, s, dbg_slot, comp_out,
                                                                                 size_out, ovf);
     else
-        wave_source<WEIGHTED, G, ADJ, GB, DT>(P, rp, adj, shift, B, dist, sig, ord, ctr, s, dbg_slot, comp_out,
+        wave_source<WEIGHTED, G, ADJ, GB, DT>(P, rp, adj, shift, BA, dist, sig, ord, ctr, s, dbg_slot, comp_out,
                                               size_out, ovf);
 }
 
@@ -654,22 +654,25 @@ __host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint3
     return L;
 }
 
-// L2 mode: the realized graph, B(H_r) and the component labels of one
-// workgroup live in its global scratch (small enough to stay in L2); the LDS
-// holds only the wavefronts' private regions.
+// L2 mode: the realized graph and the component labels of one workgroup live
+// in its global scratch (small enough to stay in L2), and so does B(H_r) when
+// the plan puts it there; otherwise the LDS holds B (l2_lds_b_bytes) before
+// the wavefronts' private regions.  The 8 n + 64 bytes past the labels bound
+// the adjacency reads past its padding (wave_source_lane).
 struct L2Layout {
-    uint32_t rp, adj, B, comp, csize, total;
+    uint32_t rp, adj, comp, csize, B, total;
 };
 __host__ __device__ inline L2Layout l2_layout(int n, uint32_t adj_cap, uint32_t adj_bytes) {
     L2Layout L;
     const uint32_t un = (uint32_t)n;
     L.rp = 0;
     L.adj = (adj_bytes * (un + 1u) + 3u) & ~3u;
-    L.B = (L.adj + adj_bytes * adj_cap + 7u) & ~7u;
-    L.comp = L.B + 8u * un;
+    L.comp = (L.adj + adj_bytes * adj_cap + 3u) & ~3u;
     L.csize = L.comp + 4u * un;
-    L.total = (L.csize + 4u * un + 255u) & ~255u;
+    L.B = (L.csize + 4u * un + 7u) & ~7u;
+    L.total = (L.B + 8u * un + 64u + 255u) & ~255u;
     return L;
 }
+__host__ __device__ inline uint32_t l2_lds_b_bytes(int n) { return (8u * (uint32_t)n + 15u) & ~15u; }
 
 }  // namespace amc

@@ -298,6 +298,22 @@ def test_weighted_n2400_l2_mode_sampled(ctx):
 
 
 # --------------------------------------------------------------------------- systems properties
+def test_weighted_n1800_l2_mode_global_b(ctx):
+    # n = 1800: B(H_r) in LDS would cost the L2 mode a wavefront, so the
+    # planner keeps B in the global scratch; split and whole realizations
+    g = W.er_graph(1800, 8.0 / 1799, 1800)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    fl = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL
+    ref = O.sweep(g.n, g.eu, g.ev, seed=4, R=2, r_begin=9, want_next=True, **model)
+    for extra in ({}, {"tile": g.n}):
+        res = gpu_run(ctx, g, model, seed=4, R=2, r_begin=9, flags=fl, **extra)
+        st = res["stats"]
+        assert st["mode"] == amc.MODE_WAVE_L2 and st["b_global"] == 1, st
+        check_sweep(res, ref, g.n, f"er1800 L2 global B {extra}")
+    res = gpu_run(ctx, W.er_graph(2400, 8.0 / 2399, 2400), model, seed=3, R=1, flags=fl)
+    assert res["stats"]["mode"] == amc.MODE_WAVE_L2 and res["stats"]["b_global"] == 0
+
+
 def test_split_ranges_and_determinism(ctx):
     wl = W.config_er20()
     g = wl.graph
