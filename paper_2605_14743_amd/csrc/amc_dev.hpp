@@ -168,6 +168,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Number of set bits of m below the calling lane (its rank among the lanes of m).
+__device__ __forceinline__ uint32_t rank_lt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const uint32_t lo = __builtin_amdgcn_mbcnt_lo(~0u, 0u);
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, lo);

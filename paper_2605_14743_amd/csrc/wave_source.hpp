@@ -104,31 +104,31 @@ template <int U, typename DT>
 __device__ __forceinline__ int fringe_partition(uint16_t *ord, const DT *dist, int a, int fr, uint32_t mn,
                                                 uint32_t &kmin) {
     const int lane = threadIdx.x & 63;
-    const uint64_t lt = lanemask_lt();
     const int end = a + fr;
     int S = 0, K = 0;   // settled and kept entries so far
     kmin = kInf;
     for (int p = a; p < end; p += 64 * U) {   // p == a + S + K
+        // sub-chunk c holds entries p + 64 c + lane; its valid lanes form a prefix of nv[c]
+        int nv[U];
         uint32_t x[U], dx[U];
 #pragma unroll
         for (int c = 0; c < U; ++c) {
-            const int k = p + 64 * c + lane;
-            x[c] = k < end ? (uint32_t)ord[k] : 0xFFFFFFFFu;
+            nv[c] = min(64, max(0, end - (p + 64 * c)));
+            x[c] = lane < nv[c] ? (uint32_t)ord[p + 64 * c + lane] : 0u;
         }
 #pragma unroll
-        for (int c = 0; c < U; ++c) dx[c] = x[c] != 0xFFFFFFFFu ? (uint32_t)dist[x[c]] : kInf;
-        uint64_t ms[U], mk[U];
+        for (int c = 0; c < U; ++c) dx[c] = lane < nv[c] ? (uint32_t)dist[x[c]] : kInf;
+        uint64_t ms[U];
         int s = 0, kk = 0;
 #pragma unroll
         for (int c = 0; c < U; ++c) {
-            const bool valid = x[c] != 0xFFFFFFFFu;
+            const bool valid = lane < nv[c];
             const bool is_s = valid && dx[c] == mn;
-            const bool is_k = valid && !is_s;
-            if (is_k) kmin = dx[c] < kmin ? dx[c] : kmin;
+            kmin = (valid && !is_s && dx[c] < kmin) ? dx[c] : kmin;
             ms[c] = __ballot(is_s);
-            mk[c] = __ballot(is_k);
-            s += __popcll(ms[c]);
-            kk += __popcll(mk[c]);
+            const int sc = __popcll(ms[c]);
+            s += sc;
+            kk += nv[c] - sc;
         }
         // entries of the kept block displaced by this chunk's settled ones
         const int d = s < K ? s : K;
@@ -139,13 +139,19 @@ __device__ __forceinline__ int fringe_partition(uint16_t *ord, const DT *dist, i
             y[c] = j < d ? (uint32_t)ord[a + S + j] : 0u;
         }
         wave_sync();   // every read of this chunk precedes its writes
+        // one store per entry: a settled one goes after the settled ones so
+        // far, a kept one after this chunk's settled ones (its rank among the
+        // kept lanes is its lane minus its rank among the settled ones)
         int so = 0, ko = 0;
 #pragma unroll
         for (int c = 0; c < U; ++c) {
-            if ((ms[c] >> lane) & 1ull) ord[a + S + so + __popcll(ms[c] & lt)] = (uint16_t)x[c];
-            if ((mk[c] >> lane) & 1ull) ord[p + s + ko + __popcll(mk[c] & lt)] = (uint16_t)x[c];
-            so += __popcll(ms[c]);
-            ko += __popcll(mk[c]);
+            const int rs = (int)rank_lt(ms[c]);
+            const bool is_s = dx[c] == mn;
+            const int dst = is_s ? a + S + so + rs : p + s + ko + (lane - rs);
+            if (lane < nv[c]) ord[dst] = (uint16_t)x[c];
+            const int sc = __popcll(ms[c]);
+            so += sc;
+            ko += nv[c] - sc;
         }
         const int dst = a + S + (s > K ? s : K);
 #pragma unroll
@@ -337,10 +343,9 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
     uint32_t base = 0;
     if ((threadIdx.x & 63) == 0) base = atomicAdd(ctr, tot);
     base = __builtin_amdgcn_readfirstlane(base);
-    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-        pos[k] = base + (uint32_t)__popcll(m[k] & lt);
+        pos[k] = base + rank_lt(m[k]);
         base += (uint32_t)__popcll(m[k]);
     }
 }
@@ -456,9 +461,12 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 const unsigned long long x = acc + sg[k];
                 ovf |= x < acc;
                 acc = x;
-                const uint32_t cand = (rel[k] && old[k] > D + w[k]) ? D + w[k] : kInf;
+                // a lane that does not relax keeps old = 0, which fails both
+                // tests (written as selects, so no branch per slot)
+                const uint32_t dw = D + w[k];
+                const uint32_t cand = old[k] > dw ? dw : kInf;
                 lmin = cand < lmin ? cand : lmin;
-                found[k] = rel[k] && old[k] == DO::unreached;       // first discovery of u
+                found[k] = old[k] == DO::unreached;                 // first discovery of u
             }
             uint32_t pos[U];
             append_block<U>(ctr, found, pos);
