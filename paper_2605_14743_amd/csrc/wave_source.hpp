@@ -94,8 +94,10 @@ struct DistOps<uint16_t> {
 };
 
 // In-place partition of the fringe ord[a, a + fr): the vertices at distance
-// mn go to ord[a, a + settled) (returned), the others to ord[a + settled,
-// a + fr); kmin gets the lane minimum over the distances of the others.
+// mn go to ord[a, a + settled) (returned; ord[a], the start of the new
+// segment, carries kSegMark), the others to ord[a + settled, a + fr); kmin
+// gets the lane minimum over the distances of the others.  The caller
+// synchronises the wavefront after the last chunk's writes.
 // Chunks of 64 U entries are taken in order.  The unsettled entries of the
 // chunks already taken form one block right after the settled ones; the
 // settled entries of a new chunk take that block's first slots and the
@@ -133,10 +135,12 @@ __device__ __forceinline__ int fringe_partition(uint16_t *ord, const DT *dist, i
         // entries of the kept block displaced by this chunk's settled ones
         const int d = s < K ? s : K;
         uint32_t y[U];
+        if (d > 0) {
 #pragma unroll
-        for (int c = 0; c < U; ++c) {
-            const int j = 64 * c + lane;
-            y[c] = j < d ? (uint32_t)ord[a + S + j] : 0u;
+            for (int c = 0; c < U; ++c) {
+                const int j = 64 * c + lane;
+                y[c] = j < d ? (uint32_t)ord[a + S + j] : 0u;
+            }
         }
         wave_sync();   // every read of this chunk precedes its writes
         // one store per entry: a settled one goes after the settled ones so
@@ -148,20 +152,24 @@ __device__ __forceinline__ int fringe_partition(uint16_t *ord, const DT *dist, i
             const int rs = (int)rank_lt(ms[c]);
             const bool is_s = dx[c] == mn;
             const int dst = is_s ? a + S + so + rs : p + s + ko + (lane - rs);
-            if (lane < nv[c]) ord[dst] = (uint16_t)x[c];
+            // the first settled entry lands at a (a kept one lands there only
+            // when no entry of the first chunk settles, and is not tagged)
+            if (lane < nv[c]) ord[dst] = (uint16_t)x[c] | ((is_s && dst == a) ? kSegMark : (uint16_t)0u);
             const int sc = __popcll(ms[c]);
             so += sc;
             ko += nv[c] - sc;
         }
-        const int dst = a + S + (s > K ? s : K);
+        if (d > 0) {
+            const int dst = a + S + (s > K ? s : K);
 #pragma unroll
-        for (int c = 0; c < U; ++c) {
-            const int j = 64 * c + lane;
-            if (j < d) ord[dst + j] = (uint16_t)y[c];
+            for (int c = 0; c < U; ++c) {
+                const int j = 64 * c + lane;
+                if (j < d) ord[dst + j] = (uint16_t)y[c];
+            }
         }
         S += s;
         K += kk;
-        wave_sync();   // the next chunk reads the block written here
+        if (p + 64 * U < end) wave_sync();   // the next chunk reads the block written here
     }
     return S;
 }
@@ -259,10 +267,7 @@ __device__ void wave_source(const SweepParams &P, const ADJ *rp, const ADJ *adj,
             // value kept at the last partition or a successful relaxation
             const uint32_t mn = wave_min_fast(lmin < kmin ? lmin : kmin);
             const int settled = fringe_partition<1>(ord, dist, ord_end, fr, mn, kmin);
-            if (lane == 0) {
-                *ctr = (uint32_t)(fr - settled);
-                ord[ord_end] |= kSegMark;
-            }
+            if (lane == 0) *ctr = (uint32_t)(fr - settled);
             wave_sync();
             f_lo = ord_end;
             ord_end += settled;
@@ -507,10 +512,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
             if (fr <= 64 || U == 1) settled = fringe_partition<1>(ord, dist, ord_end, fr, mn, kmin);
             else if (fr <= 128 || U == 2) settled = fringe_partition<2>(ord, dist, ord_end, fr, mn, kmin);
             else settled = fringe_partition<U>(ord, dist, ord_end, fr, mn, kmin);
-            if (lane == 0) {
-                *ctr = (uint32_t)(fr - settled);
-                ord[ord_end] |= kSegMark;
-            }
+            if (lane == 0) *ctr = (uint32_t)(fr - settled);
             wave_sync();
             f_lo = ord_end;
             ord_end += settled;
