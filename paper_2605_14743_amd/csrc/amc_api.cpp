@@ -507,13 +507,16 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     int mode = q->mode;
     if (mode == AMC_MODE_AUTO) {
         const double e_lds = eff(0, width(0)), e_l2 = eff(l2_pc, width(l2_pc));
-        const int w_l2 = fits[l2_pc][width(l2_pc)].w;
-        // with only two wavefronts even in L2 mode, the workgroup-per-source
-        // mode is as fast for weighted graphs beyond n = 4000 and faster for
-        // unit weights
-        if (e_lds > 0.0 && e_lds >= e_l2) mode = AMC_MODE_WAVE;
-        else if (e_l2 > 0.0 && (w_l2 >= 3 || (pl->weighted && n <= 4000))) mode = AMC_MODE_WAVE_L2;
-        else if (e_lds > 0.0) mode = AMC_MODE_WAVE;
+        const double e_best = std::max(e_lds, e_l2);
+        // the workgroup-per-source mode, where it fits, wins once few
+        // sources stay in flight (measured on MI355X, ER degree 8: unit
+        // weights n = 4000, 3 L2 wavefronts 2.4 vs 3.2 M/s; weighted n =
+        // 5000, 2 L2 wavefronts 1.05 vs 1.02 M/s)
+        const uint32_t block_lds = lds_bytes_block(n, 1024);
+        const bool block_fits = block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_lds;
+        const double block_below = pl->weighted ? 1.8 : 3.0;
+        if (e_best > 0.0 && (!block_fits || e_best >= block_below))
+            mode = e_lds >= e_l2 ? AMC_MODE_WAVE : AMC_MODE_WAVE_L2;
         else mode = AMC_MODE_BLOCK;
     }
     pl->mode = mode;

@@ -314,6 +314,18 @@ def test_weighted_n1800_l2_mode_global_b(ctx):
     assert res["stats"]["mode"] == amc.MODE_WAVE_L2 and res["stats"]["b_global"] == 0
 
 
+def test_n6000_auto_picks_a_mode_that_fits(ctx):
+    # the workgroup-per-source mode does not fit n = 6000; AUTO takes the L2
+    # mode (16-bit distances, B in the global scratch)
+    g = W.er_graph(6000, 8.0 / 5999, 6000)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    res = gpu_run(ctx, g, model, seed=8, R=1, flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.SKIP_TAIL)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_WAVE_L2 and st["dist_bytes"] == 2 and st["b_global"] == 1, st
+    ref = O.sweep(g.n, g.eu, g.ev, seed=8, R=1, want_next=True, **model)
+    check_sweep(res, ref, g.n, "er6000 auto")
+
+
 def test_split_ranges_and_determinism(ctx):
     wl = W.config_er20()
     g = wl.graph
