@@ -30,7 +30,11 @@ hipError_t set_sweep_block_attrs(int max_lds);
 // Robust tail (sampled admissible kernels, sensitivity, transition rewards).
 hipError_t robust_perturb(int n, const double *Q0, uint64_t seed, int sample, const int *sample_ptr, double delta,
                           double r_min, double *Q, double *A, hipStream_t st);
-hipError_t robust_divergence(int n, const double *b, const double *b0, double *kl, double *tv, hipStream_t st);
+hipError_t robust_perturb_batch(int n, const double *Q0, uint64_t seed, int sample0, int batch, double delta,
+                                double r_min, double *A, size_t stride, hipStream_t st);
+hipError_t robust_divergence(int n, int batch, const double *b, const double *b0, double *kl, double *tv,
+                             hipStream_t st);
+hipError_t robust_normalize_rows(int n, int batch, const double *mu, double *b, hipStream_t st);
 hipError_t robust_argmax(int m, const double *x, int *out, hipStream_t st);
 hipError_t robust_gather_row(int n, const double *rows, const int *idx, double *dst, hipStream_t st);
 hipError_t robust_vecmat(int n, const double *x, const double *M, double *y, hipStream_t st);
@@ -74,6 +78,9 @@ hipError_t tail_kernel_from_counts(int n, const uint32_t *counts, uint32_t R, do
                                    double *A, hipStream_t st);
 hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipStream_t st);
 hipError_t tail_invert(int n, double *A, int *err, hipStream_t st);
+hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st);
+hipError_t tail_visits_batched(int n, const double *N, size_t stride, int batch, const double *s, double *mu,
+                               hipStream_t st);
 hipError_t tail_visits(int n, const double *N, const double *s, double *mu, double *b, const double *f,
                        const uint8_t *pool, double *b_bar, const double *r, double r_lower, int topk, int32_t *top,
                        double *scal, hipStream_t st);

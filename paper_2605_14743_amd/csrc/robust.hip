@@ -27,17 +27,20 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b, uint32_t c, uint32
 // One workgroup per row: the sampled row of Q and the row of A = I - Q.  The
 // sample index is read from `sample_ptr` when given (the KL maximiser).
 __global__ void k_perturb(int n, const double *Q0, uint32_t k0, uint32_t k1, int sample, const int *sample_ptr,
-                          double delta, double r_min, double *Q, double *A) {
+                          double delta, double r_min, double *Q, double *A, size_t stride) {
+    // batch y: sample + y (or *sample_ptr) into A + y * stride; the rows of A
+    // hold the clipped q first, then I - Q; Q (optional) gets Q itself
     __shared__ double red[256];
     const int i = blockIdx.x, tid = threadIdx.x;
-    const uint32_t smp = (uint32_t)(sample_ptr ? *sample_ptr : sample);
+    const uint32_t smp = (uint32_t)(sample_ptr ? *sample_ptr : sample + (int)blockIdx.y);
+    A += (size_t)blockIdx.y * stride;
     double tot = 0.0;
     for (int j = tid; j < n; j += blockDim.x) {
         const double u = u53(smp, (uint32_t)i, (uint32_t)j, k0, k1);
         const double f = __dadd_rn(1.0, __dmul_rn(delta, __dadd_rn(__dmul_rn(2.0, u), -1.0)));
         double q = __dmul_rn(Q0[(size_t)i * n + j], f);
         q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
-        Q[(size_t)i * n + j] = q;
+        A[(size_t)i * n + j] = q;
         tot += q;
     }
     red[tid] = tot;
@@ -49,16 +52,18 @@ __global__ void k_perturb(int n, const double *Q0, uint32_t k0, uint32_t k1, int
     const double cap = 1.0 - r_min;
     const double sc = red[0] > cap ? cap / red[0] : 1.0;
     for (int j = tid; j < n; j += blockDim.x) {
-        const double q = red[0] > cap ? Q[(size_t)i * n + j] * sc : Q[(size_t)i * n + j];
-        Q[(size_t)i * n + j] = q;
+        const double q = red[0] > cap ? A[(size_t)i * n + j] * sc : A[(size_t)i * n + j];
+        if (Q) Q[(size_t)i * n + j] = q;
         A[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - q;
     }
 }
-
-// KL(b || b0) and total variation of one sample (single workgroup).
+// one block per sampled profile x: b + x * n against b0 into kl[x], tv[x]
 __global__ void k_divergence(int n, const double *b, const double *b0, double *kl, double *tv) {
     __shared__ double r1[256], r2[256];
     const int tid = threadIdx.x;
+    b += (size_t)blockIdx.x * n;
+    kl += blockIdx.x;
+    tv += blockIdx.x;
     double a = 0.0, t = 0.0;
     for (int j = tid; j < n; j += blockDim.x) {
         if (b[j] > 0.0) a += b[j] * log(b[j] / b0[j]);
@@ -81,6 +86,25 @@ __global__ void k_divergence(int n, const double *b, const double *b0, double *k
 }
 
 // First index of the maximum of x[0..m) (single workgroup).
+
+// b = mu / (mu 1) for the rows of a batch (one block per row)
+__global__ void k_normalize_rows(int n, const double *mu, double *b) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    mu += (size_t)blockIdx.x * n;
+    b += (size_t)blockIdx.x * n;
+    double t = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) t += mu[j];
+    red[tid] = t;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double tot = red[0];
+    for (int j = tid; j < n; j += blockDim.x) b[j] = mu[j] / tot;
+}
+
 __global__ void k_argmax(int m, const double *x, int *out) {
     __shared__ double rv[256];
     __shared__ int ri[256];
@@ -250,12 +274,25 @@ hipError_t robust_rem_bound(const unsigned long long *norms, double *out, hipStr
 hipError_t robust_perturb(int n, const double *Q0, uint64_t seed, int sample, const int *sample_ptr, double delta,
                           double r_min, double *Q, double *A, hipStream_t st) {
     hipLaunchKernelGGL(k_perturb, dim3(n), dim3(256), 0, st, n, Q0, (uint32_t)seed, (uint32_t)(seed >> 32), sample,
-                       sample_ptr, delta, r_min, Q, A);
+                       sample_ptr, delta, r_min, Q, A, (size_t)0);
     return hipGetLastError();
 }
 
-hipError_t robust_divergence(int n, const double *b, const double *b0, double *kl, double *tv, hipStream_t st) {
-    hipLaunchKernelGGL(k_divergence, dim3(1), dim3(256), 0, st, n, b, b0, kl, tv);
+hipError_t robust_perturb_batch(int n, const double *Q0, uint64_t seed, int sample0, int batch, double delta,
+                                double r_min, double *A, size_t stride, hipStream_t st) {
+    hipLaunchKernelGGL(k_perturb, dim3(n, batch), dim3(256), 0, st, n, Q0, (uint32_t)seed, (uint32_t)(seed >> 32),
+                       sample0, (const int *)nullptr, delta, r_min, (double *)nullptr, A, stride);
+    return hipGetLastError();
+}
+
+hipError_t robust_divergence(int n, int batch, const double *b, const double *b0, double *kl, double *tv,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_divergence, dim3(batch), dim3(256), 0, st, n, b, b0, kl, tv);
+    return hipGetLastError();
+}
+
+hipError_t robust_normalize_rows(int n, int batch, const double *mu, double *b, hipStream_t st) {
+    hipLaunchKernelGGL(k_normalize_rows, dim3(batch), dim3(256), 0, st, n, mu, b);
     return hipGetLastError();
 }
 

@@ -78,19 +78,24 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
     double *dQ0 = (double *)alloc(8 * nn), *N0 = (double *)alloc(8 * nn), *W = (double *)alloc(8 * nn);
     double *M1 = (double *)alloc(8 * nn), *M2 = (double *)alloc(8 * nn), *Qs = (double *)alloc(8 * nn);
     double *ds = (double *)alloc(8 * (size_t)n), *mu0 = (double *)alloc(8 * (size_t)n), *b0 = (double *)alloc(8 * (size_t)n);
-    double *mus = (double *)alloc(8 * (size_t)n), *v = (double *)alloc(8 * (size_t)n), *w = (double *)alloc(8 * (size_t)n);
+    double *v = (double *)alloc(8 * (size_t)n), *w = (double *)alloc(8 * (size_t)n);
     double *blin = (double *)alloc(8 * (size_t)n), *bkl = (double *)alloc(8 * (size_t)n), *btv = (double *)alloc(8 * (size_t)n);
-    double *scal = (double *)alloc(8 * 8), *scal2 = (double *)alloc(8 * 8), *rsc = (double *)alloc(8 * 8);
+    double *scal = (double *)alloc(8 * 8), *rsc = (double *)alloc(8 * 8);
     double *brows = (double *)alloc(8 * (size_t)std::max(S, 1) * n);
+    // sampled kernels are inverted in groups of up to 64 (at most 1 GiB of matrices)
+    int Bt = std::max(1, std::min(S, 64));
+    while (Bt > 1 && (size_t)Bt * nn * 8 > (size_t(1) << 30)) Bt /= 2;
+    double *Wb = S > 0 ? (double *)alloc(8 * nn * (size_t)Bt) : nullptr;
+    double *mub = S > 0 ? (double *)alloc(8 * (size_t)n * Bt) : nullptr;
     double *kl = (double *)alloc(8 * (size_t)std::max(S, 1)), *tv = (double *)alloc(8 * (size_t)std::max(S, 1));
     double *dr = (double *)alloc(8 * (size_t)n), *psw = (double *)alloc(8 * (size_t)n), *pimp = (double *)alloc(8 * (size_t)n);
     double *df = q->f ? (double *)alloc(8 * (size_t)n) : nullptr;
     int32_t *top = (int32_t *)alloc(4 * 16);
     int *args = (int *)alloc(16), *err = (int *)alloc(16);
     unsigned long long *norms = (unsigned long long *)alloc(8 * 4);
-    if (!dQ0 || !N0 || !W || !M1 || !M2 || !Qs || !ds || !mu0 || !b0 || !mus || !v || !w || !blin || !bkl || !btv ||
-        !scal || !scal2 || !rsc || !brows || !kl || !tv || !dr || !psw || !pimp || (q->f && !df) || !top || !args ||
-        !err || !norms)
+    if ((S > 0 && (!Wb || !mub)) || !dQ0 || !N0 || !W || !M1 || !M2 || !Qs || !ds || !mu0 || !b0 || !v || !w ||
+        !blin || !bkl || !btv || !scal || !rsc || !brows || !kl || !tv || !dr || !psw || !pimp || (q->f && !df) ||
+        !top || !args || !err || !norms)
         return AMC_E_OOM;
     HIPCHK(hipMemcpyAsync(dQ0, Q0, 8 * nn, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ds, s, 8 * (size_t)n, hipMemcpyHostToDevice, st));
@@ -118,13 +123,15 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
         HIPCHK(tail_reward_afc(n, mu0, scal, psw, &rsc[0], st));
         HIPCHK(tail_reward_afc(n, mu0, scal, pimp, &rsc[1], st));
     }
-    // sampled admissible kernels
-    for (int k = 0; k < S; ++k) {
-        HIPCHK(robust_perturb(n, dQ0, q->seed, k, nullptr, q->delta, q->r_min, Qs, W, st));
-        HIPCHK(tail_invert(n, W, err, st));
-        HIPCHK(tail_visits(n, W, ds, mus, brows + (size_t)k * n, nullptr, nullptr, nullptr, nullptr, 0.0, 0, top,
-                           scal2, st));
-        HIPCHK(robust_divergence(n, brows + (size_t)k * n, b0, kl + k, tv + k, st));
+    // sampled admissible kernels, a group at a time: I - Q_k, its inverse,
+    // mu_k = s N_k, b_k, and the divergences from b0
+    for (int k0 = 0; k0 < S; k0 += Bt) {
+        const int nb = std::min(Bt, S - k0);
+        HIPCHK(robust_perturb_batch(n, dQ0, q->seed, k0, nb, q->delta, q->r_min, Wb, nn, st));
+        HIPCHK(tail_invert_batched(n, Wb, nn, nb, err, st));
+        HIPCHK(tail_visits_batched(n, Wb, nn, nb, ds, mub, st));
+        HIPCHK(robust_normalize_rows(n, nb, mub, brows + (size_t)k0 * n, st));
+        HIPCHK(robust_divergence(n, nb, brows + (size_t)k0 * n, b0, kl + k0, tv + k0, st));
     }
     if (S > 0) {
         HIPCHK(robust_argmax(S, kl, args, st));

@@ -54,9 +54,11 @@ __global__ void k_from_Q(int n, const double *Q, double *r, double *A) {
     if (threadIdx.x == 0) r[i] = 1.0 - part[0];
 }
 
+// The four steps take a batch of matrices A + z * stride, z = blockIdx.z.
 // (a) invert the diagonal block A[k0:k1, k0:k1] in place (unblocked
 // Gauss-Jordan without pivoting); flags a zero pivot.
-__global__ void k_gj_diag(int n, double *A, int k0, int *err) {
+__global__ void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+    A += (size_t)blockIdx.z * stride;
     __shared__ double M[NB][NB + 1];
     const int kb = min(NB, n - k0);
     for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
@@ -93,7 +95,8 @@ __global__ void k_gj_diag(int n, double *A, int k0, int *err) {
 }
 
 // (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block.
-__global__ void k_gj_rowpanel(int n, double *A, int k0) {
+__global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
+    A += (size_t)blockIdx.z * stride;
     __shared__ double Dv[NB][NB + 1];
     __shared__ double X[NB][TT + 1];
     const int kb = min(NB, n - k0);
@@ -120,7 +123,8 @@ __global__ void k_gj_rowpanel(int n, double *A, int k0) {
 
 // (c) trailing update: A[i, j] -= A[i, k] A[k, j] for i, j outside the block
 // (A[k, j] already holds the row panel of step (b)).
-__global__ __launch_bounds__(256) void k_gj_update(int n, double *A, int k0) {
+__global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stride, int k0) {
+    A += (size_t)blockIdx.z * stride;
     __shared__ double Ap[TT][NB + 1];
     __shared__ double Bp[NB][TT + 1];
     const int kb = min(NB, n - k0);
@@ -165,7 +169,8 @@ __global__ __launch_bounds__(256) void k_gj_update(int n, double *A, int k0) {
 }
 
 // (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block.
-__global__ void k_gj_colpanel(int n, double *A, int k0) {
+__global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
+    A += (size_t)blockIdx.z * stride;
     __shared__ double Dv[NB][NB + 1];
     __shared__ double X[TT][NB + 1];
     const int kb = min(NB, n - k0);
@@ -189,8 +194,11 @@ __global__ void k_gj_colpanel(int n, double *A, int k0) {
     }
 }
 
-// mu = s N (eq. visits): one thread per column, rows summed in order.
-__global__ void k_visits(int n, const double *N, const double *s, double *mu) {
+// mu = s N (eq. visits): one thread per column, rows summed in order; a
+// batch of matrices N + y * stride gives mu + y * n, y = blockIdx.y.
+__global__ void k_visits(int n, const double *N, const double *s, double *mu, size_t stride) {
+    N += (size_t)blockIdx.y * stride;
+    mu += (size_t)blockIdx.y * n;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double acc = 0.0;
@@ -370,21 +378,31 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
     return hipGetLastError();
 }
 
-hipError_t tail_invert(int n, double *A, int *err, hipStream_t st) {
+hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
     const int tiles = (n + TT - 1) / TT;
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, n, A, k0, err);
-        hipLaunchKernelGGL(k_gj_rowpanel, dim3(tiles), dim3(256), 0, st, n, A, k0);
-        hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles), dim3(256), 0, st, n, A, k0);
-        hipLaunchKernelGGL(k_gj_colpanel, dim3(tiles), dim3(256), 0, st, n, A, k0);
+        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(256), 0, st, n, A, stride, k0, err);
+        hipLaunchKernelGGL(k_gj_rowpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_colpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
+    return hipGetLastError();
+}
+
+hipError_t tail_invert(int n, double *A, int *err, hipStream_t st) {
+    return tail_invert_batched(n, A, (size_t)n * n, 1, err, st);
+}
+
+hipError_t tail_visits_batched(int n, const double *N, size_t stride, int batch, const double *s, double *mu,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256, batch), dim3(256), 0, st, n, N, s, mu, stride);
     return hipGetLastError();
 }
 
 hipError_t tail_visits(int n, const double *N, const double *s, double *mu, double *b, const double *f,
                        const uint8_t *pool, double *b_bar, const double *r, double r_lower, int topk, int32_t *top,
                        double *scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256), dim3(256), 0, st, n, N, s, mu);
+    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256), dim3(256), 0, st, n, N, s, mu, (size_t)0);
     hipLaunchKernelGGL(k_afc, dim3(1), dim3(1024), 0, st, n, mu, b, f, pool, b_bar, r, r_lower, topk, top, scal);
     return hipGetLastError();
 }

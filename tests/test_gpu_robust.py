@@ -59,6 +59,16 @@ def test_random_kernels(ctx, n):
     assert g["tail_ms"] > 0.0
 
 
+def test_more_samples_than_one_group(ctx):
+    # 130 sampled kernels: inverted in groups of 64, 64 and 2
+    Q0 = random_kernel(20, 77)
+    f = np.linspace(1.0, 0.0, 20)
+    print("[gpu] robust 130 samples", flush=True)
+    g = amc.robust(ctx, Q0, f=f, samples=130, delta=0.3, r_min=0.05, seed=11)
+    o = O.robust(Q0, f=f, samples=130, delta=0.3, r_min=0.05, seed=11)
+    compare(g, o, "130 samples")
+
+
 def test_estimated_kernel_of_a_run(ctx):
     wl = W.config_er20()
     g = wl.graph
