@@ -6,12 +6,14 @@
 //
 // One workgroup takes a work item (realization r, source tile) at a time:
 //   1. realize every base edge of r with one Philox call (Section 3.1) and
-//      compact the surviving slots into an LDS adjacency (weight | neighbour);
-//   2. each wavefront runs, for its sources s, the single-source shortest
-//      paths with exact uint64 path counts (breadth-first levels for unit
-//      weights, distance buckets for integer weights >= 1) and the reverse
-//      dependency accumulation of the Section 3.1 betweenness, adding delta_s
-//      into a workgroup-wide B(H_r) in LDS;
+//      compact the surviving slots into an adjacency (weight | neighbour) in
+//      LDS (LDS mode) or in the workgroup's L2-resident scratch (L2 mode);
+//   2. each wavefront takes sources s from a workgroup counter and runs the
+//      single-source shortest paths with exact uint64 path counts
+//      (breadth-first levels for unit weights; for integer weights >= 1 one
+//      equal-distance segment per step, settled from the fringe by its
+//      minimum) and the reverse dependency accumulation of the Section 3.1
+//      betweenness, adding delta_s into a workgroup-wide B(H_r);
 //   3. once every source of r is done, the workgroup reduces B(H_r) to the
 //      global centre (eq. central-node), the component centres (eq.
 //      local-center) and the pool-constrained centres (Section 7.1), draws

@@ -1,6 +1,6 @@
 // wave_source.hpp -- one source of the realization x source sweep on one
-// wavefront, and the LDS / L2 carve-ups of a workgroup; shared by the sweep
-// kernel and the trajectory kernel.
+// wavefront, and the LDS / L2 carve-ups of a workgroup; shared by the sweep,
+// trajectory and anchored-neighbourhood kernels.
 //
 // Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
 // Uncertainty: An Absorbing Markov Chain Approach" (Section 3.1).
@@ -537,26 +537,37 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
     }
 
     // dependencies of the batch ord[lo, hi) (one equal-distance segment, k =
-    // hi - lo vertices); e0 is ord[hi - 64 + lane]
-    auto accumulate_batch = [&](auto gtag, int lo, int hi, uint32_t e0) {
+    // hi - lo vertices); e0 is ord[hi - 64 + lane] and, in the L2 mode, b0 /
+    // l0 the row offset and length of its vertex (loaded one batch ahead)
+    auto accumulate_batch = [&](auto gtag, int lo, int hi, uint32_t e0, uint32_t b0, uint32_t l0) {
         constexpr int G = decltype(gtag)::value;
         const int sub = G == 1 ? 0 : lane % G;
         bool mine;
-        uint32_t e;
+        uint32_t e, eb = b0, el = l0;
         if constexpr (G == 1) {
             mine = hi - 64 + lane >= lo;
             e = e0;
         } else {
             const int slot = lane / G, k = hi - lo;
             mine = slot < k;
-            e = (uint32_t)__shfl((int)e0, mine ? 64 - k + slot : 63, 64);
+            const int src = mine ? 64 - k + slot : 63;
+            e = (uint32_t)__shfl((int)e0, src, 64);
+            if constexpr (GB) {
+                eb = (uint32_t)__shfl((int)b0, src, 64);
+                el = (uint32_t)__shfl((int)l0, src, 64);
+            }
         }
         int v = 0;
         uint32_t beg = 0, len = 0, dv = 0;
         if (mine) {
             v = (int)(e & kVertexMask);
-            beg = ld_off32(rp, (uint32_t)v);
-            len = ld_off32(rp, (uint32_t)v + 1u) - beg;
+            if constexpr (GB) {
+                beg = eb;
+                len = el;
+            } else {
+                beg = ld_off32(rp, (uint32_t)v);
+                len = ld_off32(rp, (uint32_t)v + 1u) - beg;
+            }
             dv = (uint32_t)dist[v];
         }
         const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
@@ -609,15 +620,29 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
     };
 
     // ------------------------------------------------------------ backward
-    // batches of one segment each, from the deepest vertices up
-    for (int hi = ord_end; hi > 0;) {
+    // batches of one segment each, from the deepest vertices up.  The L2
+    // mode loads the row offsets of the entries below the batch (the next
+    // batch's candidates) before working on the batch, so that their global
+    // latency overlaps it.
+    uint32_t e_nx = 0, b_nx = 0, l_nx = 0;
+    auto prefetch = [&](int hi) {
         const int idx = hi - 64 + lane;
-        const uint32_t e0 = idx >= 0 ? (uint32_t)ord[idx] : 0u;
+        e_nx = idx >= 0 ? (uint32_t)ord[idx] : 0u;
+        if constexpr (GB) {
+            const uint32_t x = e_nx & kVertexMask;
+            b_nx = ld_off32(rp, x);
+            l_nx = ld_off32(rp, x + 1u) - b_nx;
+        }
+    };
+    prefetch(ord_end);
+    for (int hi = ord_end; hi > 0;) {
+        const uint32_t e0 = e_nx, b0 = b_nx, l0 = l_nx;
         const int lo = batch_start(hi, 64, e0, 1);
+        prefetch(lo);
         const int k = hi - lo;
-        if (k > 32) accumulate_batch(std::integral_constant<int, 1>{}, lo, hi, e0);
-        else if (k > 16) accumulate_batch(std::integral_constant<int, 2>{}, lo, hi, e0);
-        else accumulate_batch(std::integral_constant<int, 4>{}, lo, hi, e0);
+        if (k > 32) accumulate_batch(std::integral_constant<int, 1>{}, lo, hi, e0, b0, l0);
+        else if (k > 16) accumulate_batch(std::integral_constant<int, 2>{}, lo, hi, e0, b0, l0);
+        else accumulate_batch(std::integral_constant<int, 4>{}, lo, hi, e0, b0, l0);
         wave_sync();
         hi = lo;
     }
