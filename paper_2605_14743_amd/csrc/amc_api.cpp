@@ -513,7 +513,8 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         // weights n = 4000, 3 L2 wavefronts 2.4 vs 3.2 M/s; weighted n =
         // 5000, 2 L2 wavefronts 1.05 vs 1.02 M/s)
         const uint32_t block_lds = lds_bytes_block(n, 1024);
-        const bool block_fits = block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_lds;
+        const bool block_fits =
+            block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_staging_bytes(n);
         const double block_below = pl->weighted ? 1.8 : 3.0;
         if (e_best > 0.0 && (!block_fits || e_best >= block_below))
             mode = e_lds >= e_l2 ? AMC_MODE_WAVE : AMC_MODE_WAVE_L2;
@@ -540,7 +541,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
         pl->lds = lds_bytes_block(n, pl->threads);
         if (pl->lds > (uint32_t)ctx->max_lds) return AMC_E_UNSUPPORTED;
-        if (2ull * (uint64_t)g->m > pl->lds) return AMC_E_UNSUPPORTED;   // per-edge staging fits the LDS
+        if (2ull * (uint64_t)g->m > block_staging_bytes(n)) return AMC_E_UNSUPPORTED;   // per-edge staging
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;

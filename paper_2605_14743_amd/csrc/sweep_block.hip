@@ -24,9 +24,14 @@
 namespace amc {
 
 constexpr int kBG = 4;   // lanes per vertex in the block mode
+constexpr int kBU = 4;   // adjacency slots per lane and trip
 
+// LDS: dist u32[n] | sig u64[n] | ord u16[n] | aux u16[n] | B f64[n] | comp
+// u16[n] | csize u16[n] | rp u32[n+1] (the realized row offsets: every
+// frontier vertex reads its pair, so they stay on chip; the adjacency lives
+// in the workgroup's global scratch)
 struct BlockLayout {
-    uint32_t dist, sig, ord, aux, B, comp, csize, total;
+    uint32_t dist, sig, ord, aux, B, comp, csize, rp, total;
 };
 
 __host__ __device__ inline BlockLayout block_layout(int n) {
@@ -39,7 +44,8 @@ __host__ __device__ inline BlockLayout block_layout(int n) {
     L.B = (L.aux + 2u * un + 7u) & ~7u;
     L.comp = L.B + 8u * un;
     L.csize = L.comp + 2u * un;
-    L.total = (L.csize + 2u * un + 15u) & ~15u;
+    L.rp = (L.csize + 2u * un + 3u) & ~3u;
+    L.total = (L.rp + 4u * (un + 1u) + 15u) & ~15u;
     return L;
 }
 
@@ -65,7 +71,9 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
     for (;;) {
         if (tid == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
         ++nseg;
-        // one frontier sweep; groups of kBG lanes per vertex
+        // one frontier sweep; groups of kBG lanes per vertex, each lane
+        // taking kBU of its vertex's slots per trip (loads issued together,
+        // the next trip's neighbour entries fetched while this one is used)
         for (int base = f_lo; base < ord_end; base += ngrp) {
             const int idx = base + grp;
             const bool mine = idx < ord_end;
@@ -86,26 +94,52 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
                 const uint32_t o = __shfl_xor(maxtrips, off, 64);
                 maxtrips = o > maxtrips ? o : maxtrips;
             }
-            for (uint32_t t = 0; t < maxtrips; ++t) {
-                bool found = false;
-                uint32_t u = 0;
-                if (t < trips) {
-                    const uint32_t a = adj[beg + (uint32_t)sub + t * kBG];
-                    u = a & 0xFFFFu;
-                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
-                    const uint32_t du = dist[u];
-                    if (du + w == D) {
-                        const unsigned long long x = acc + sig[u];
-                        ovf |= x < acc;
-                        acc = x;
-                    } else if (D + w < du) {
-                        found = atomicMin(&dist[u], D + w) == kInf;
-                    }
+            const uint32_t first = beg + (uint32_t)sub;
+            uint32_t nxt[kBU];
+#pragma unroll
+            for (int k = 0; k < kBU; ++k) nxt[k] = adj[first + kBG * k];
+            for (uint32_t t = 0; t < maxtrips; t += kBU) {
+                uint32_t cur[kBU], u[kBU], w[kBU], du[kBU], old[kBU];
+                bool pred[kBU], rel[kBU], found[kBU];
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) cur[k] = nxt[k];
+                if (t + kBU < maxtrips) {
+#pragma unroll
+                    for (int k = 0; k < kBU; ++k) nxt[k] = adj[first + kBG * (t + kBU + k)];
                 }
-                const uint32_t pos = wave_append(&ctl[0], found);
-                if (found) {
-                    if (WEIGHTED) aux[pos] = (uint16_t)u;
-                    else ord[pos] = (uint16_t)u;
+                // a slot past the vertex's list reads vertex 0 with weight
+                // kNoEdge (fails both tests)
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) {
+                    const bool in = t + k < trips;
+                    u[k] = in ? (cur[k] & 0xFFFFu) : 0u;
+                    w[k] = in ? (WEIGHTED ? (cur[k] >> 16) : 1u) : kNoEdge;
+                }
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) du[k] = dist[u[k]];
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) {
+                    pred[k] = du[k] + w[k] == D;
+                    rel[k] = D + w[k] < du[k];
+                }
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) {
+                    // read from a vertex in range either way (no branch)
+                    const unsigned long long val = sig[pred[k] ? u[k] : (uint32_t)s];
+                    const unsigned long long x = acc + (pred[k] ? val : 0ull);
+                    ovf |= x < acc;
+                    acc = x;
+                }
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) old[k] = rel[k] ? atomicMin(&dist[u[k]], D + w[k]) : 0u;
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) {
+                    found[k] = old[k] == kInf;   // a lane that does not relax keeps 0
+                    const uint32_t pos = wave_append(&ctl[0], found[k]);
+                    if (found[k]) {
+                        if (WEIGHTED) aux[pos] = (uint16_t)u[k];
+                        else ord[pos] = (uint16_t)u[k];
+                    }
                 }
             }
 #pragma unroll
@@ -214,11 +248,22 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
                 v = ord[idx];
                 const uint32_t dv = dist[v];
                 const uint32_t beg = rp[v], end = rp[v + 1];
-                for (uint32_t j = beg + (uint32_t)sub; j < end; j += kBG) {
-                    const uint32_t a = adj[j];
-                    const uint32_t u = a & 0xFFFFu;
-                    const uint32_t w = WEIGHTED ? (a >> 16) : 1u;
-                    if (dist[u] == dv + w) sum += as_f64(sig[u]);
+                const uint32_t len = end - beg;
+                const uint32_t trips = len > (uint32_t)sub ? (len - (uint32_t)sub + kBG - 1) / kBG : 0u;
+                const uint32_t first = beg + (uint32_t)sub;
+                for (uint32_t t = 0; t < trips; t += kBU) {
+                    uint32_t a[kBU], u[kBU], du[kBU];
+#pragma unroll
+                    for (int k = 0; k < kBU; ++k) a[k] = adj[first + kBG * (t + k)];
+#pragma unroll
+                    for (int k = 0; k < kBU; ++k) u[k] = (t + k < trips) ? (a[k] & 0xFFFFu) : 0u;
+#pragma unroll
+                    for (int k = 0; k < kBU; ++k) du[k] = dist[u[k]];
+#pragma unroll
+                    for (int k = 0; k < kBU; ++k) {
+                        const uint32_t w = (t + k < trips) ? (WEIGHTED ? (a[k] >> 16) : 1u) : kNoEdge;
+                        if (du[k] == dv + w) sum += as_f64(sig[u[k]]);   // u succeeds v: c_u
+                    }
                 }
             }
 #pragma unroll
@@ -283,11 +328,11 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         double *B = (double *)(smem + L.B);
         uint16_t *comp = (uint16_t *)(smem + L.comp);
         uint16_t *csize = (uint16_t *)(smem + L.csize);
-        // per-workgroup global scratch: realized rp (n+1), adjacency (2m plus
-        // padding), component centres (2 n)
+        // per-workgroup global scratch: (n+1) words unused, adjacency (2m
+        // plus padding), component centres (2 n)
         uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
-        uint32_t *rp = gs;
-        uint32_t *adj = rp + (n + 1);
+        uint32_t *rp = (uint32_t *)(smem + L.rp);
+        uint32_t *adj = gs + (n + 1);
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
         RS.wmax = RS.cmax + n;
@@ -347,6 +392,9 @@ uint32_t lds_bytes_block(int n, int threads) {
     (void)threads;
     return block_layout(n).total;
 }
+
+// Bytes at the start of the LDS that the per-edge staging may use (below rp).
+uint32_t block_staging_bytes(int n) { return block_layout(n).rp; }
 
 size_t block_scratch_words(int n, int64_t m) {
     return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 2 * (size_t)n + 64;
