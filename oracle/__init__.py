@@ -119,6 +119,16 @@ class _RobustOut(C.Structure):
                 ("rem_bound", C.c_double), ("rem_actual", C.c_double)]
 
 
+class _BootIn(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("replicates", C.c_int32), ("level", C.c_double), ("eta", C.c_double),
+                ("s", C.POINTER(C.c_double))]
+
+
+class _BootOut(C.Structure):
+    _fields_ = [("b0", C.POINTER(C.c_double)), ("mean", C.POINTER(C.c_double)), ("sd", C.POINTER(C.c_double)),
+                ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)), ("b_rep", C.POINTER(C.c_double))]
+
+
 def _declare(L):
     P = C.POINTER
     L.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -148,6 +158,9 @@ def _declare(L):
     L.or_pair_certificate.restype = None
     L.or_tail.argtypes = [C.c_int32, P(C.c_uint32), P(C.c_uint32), C.c_uint32, P(_TailIn), P(_TailOut)]
     L.or_robust.argtypes = [C.c_int32, P(C.c_double), P(_RobustIn), P(_RobustOut)]
+    L.or_bootstrap.argtypes = [C.c_int32, C.c_uint32, P(C.c_int32), P(_BootIn), P(_BootOut)]
+    L.or_boot_counts.argtypes = [C.c_int32, C.c_uint32, P(C.c_int32), C.c_uint64, C.c_uint32, P(C.c_uint32)]
+    L.or_boot_counts.restype = None
     L.or_perturbed_kernel.argtypes = [C.c_int32, P(C.c_double), C.c_uint64, C.c_int32, C.c_double, C.c_double,
                                       P(C.c_double)]
     L.or_perturbed_kernel.restype = None
@@ -387,6 +400,35 @@ def robust(Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0):
     out["kl_arg"], out["tv_arg"] = int(ro.kl_arg), int(ro.tv_arg)
     out["kl"], out["tv"] = out["kl"][:samples], out["tv"][:samples]
     del fa
+    return out
+
+
+def boot_counts(next_table, seed, beta):
+    """Counts of bootstrap replicate beta: every row's R draws redrawn with replacement (Section 8.4)."""
+    nt = np.ascontiguousarray(next_table, dtype=np.int32)
+    R, n = nt.shape
+    counts = np.zeros((n, n + 1), dtype=np.uint32)
+    lib().or_boot_counts(n, R, _ptr(nt, C.c_int32), int(seed), int(beta), _ptr(counts, C.c_uint32))
+    return counts
+
+
+def bootstrap(next_table, *, replicates=100, level=0.95, eta=None, s=None, seed=0):
+    """Nonparametric bootstrap of b from a next table (R x n, -1 = bottom): b of the draws themselves,
+    per-node mean, standard deviation and nearest-rank percentile interval over the replicates, and
+    every replicate's b (Section 8.4)."""
+    nt = np.ascontiguousarray(next_table, dtype=np.int32)
+    R, n = nt.shape
+    s_arr = np.full(n, 1.0 / n) if s is None else np.ascontiguousarray(s, dtype=np.float64)
+    bi = _BootIn()
+    bi.seed, bi.replicates, bi.level = int(seed), int(replicates), float(level)
+    bi.eta = 0.1 / np.sqrt(R) if eta is None else float(eta)
+    bi.s = _ptr(s_arr, C.c_double)
+    out = {k: np.zeros(n) for k in ("b0", "mean", "sd", "lo", "hi")}
+    out["b_rep"] = np.zeros((replicates, n))
+    bo = _BootOut()
+    for key in out:
+        setattr(bo, key, _ptr(out[key], C.c_double))
+    _check(lib().or_bootstrap(n, R, _ptr(nt, C.c_int32), C.byref(bi), C.byref(bo)), "bootstrap")
     return out
 
 

@@ -1325,3 +1325,112 @@ done:
     free(N0); free(Qs); free(Ns); free(M1); free(M2); free(mu0); free(mus); free(bs); free(v); free(w);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Nonparametric bootstrap of the AFC profile (Section 8.4: resample each    */
+/* row's M draws with replacement and recompute b).  Replicate beta redraws, */
+/* for every row i, R draw indices uniformly from {0 .. R-1}: draw t takes   */
+/* word (t mod 4) of the Philox block at counter (beta, i, t / 4,            */
+/* 0x80000004), index = (word * R) >> 32; the replicate's counts of row i    */
+/* are those of next(index, i).  The replicate kernel is built as for the    */
+/* estimate itself (P-hat = C / R, floor eta on an empty absorption column), */
+/* and b* = s N* / (s N* 1).  Per node: mean and standard deviation (divisor */
+/* B - 1) over the B replicates, and the nearest-rank percentiles of the     */
+/* sorted values at (1 - level) / 2 and (1 + level) / 2 (rank ceil(q B)).    */
+/* ------------------------------------------------------------------------ */
+void or_boot_counts(int32_t n, uint32_t R, const int32_t *next_table, uint64_t seed, uint32_t beta,
+                    uint32_t *counts)
+{
+    uint32_t key[2], ctr[4], x[4], t;
+    int32_t i;
+    key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
+    memset(counts, 0, sizeof(uint32_t) * (size_t)n * (size_t)(n + 1));
+    for (i = 0; i < n; ++i) {
+        for (t = 0; t < R; ++t) {
+            uint32_t j;
+            int32_t nx;
+            if ((t & 3u) == 0u) {
+                ctr[0] = beta; ctr[1] = (uint32_t)i; ctr[2] = t >> 2; ctr[3] = 0x80000004u;
+                or_philox4x32_10(ctr, key, x);
+            }
+            j = (uint32_t)(((uint64_t)x[t & 3u] * (uint64_t)R) >> 32);
+            nx = next_table[(size_t)j * n + i];
+            counts[(size_t)i * (n + 1) + (nx >= 0 ? nx : n)] += 1u;
+        }
+    }
+}
+
+static int or_cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+typedef struct {
+    uint64_t seed;
+    int32_t replicates;          /* B >= 1                                     */
+    double level;                /* interval coverage in (0, 1)                */
+    double eta;                  /* floor (R10); 0 disables                    */
+    const double *s;             /* n                                          */
+} or_boot_in;
+
+typedef struct {
+    double *b0;                  /* n: AFC of the given draws                  */
+    double *mean, *sd, *lo, *hi; /* n each                                     */
+    double *b_rep;               /* B x n                                      */
+} or_boot_out;
+
+int or_bootstrap(int32_t n, uint32_t R, const int32_t *next_table, const or_boot_in *in, or_boot_out *out)
+{
+    const size_t nn = (size_t)n * (size_t)n;
+    const int32_t B = in->replicates;
+    uint32_t *counts = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * (size_t)(n + 1));
+    double *Q = (double *)malloc(sizeof(double) * nn), *N = (double *)malloc(sizeof(double) * nn);
+    double *r = (double *)malloc(sizeof(double) * (size_t)n), *mu = (double *)malloc(sizeof(double) * (size_t)n);
+    double *col = (double *)malloc(sizeof(double) * (size_t)(B > 0 ? B : 1));
+    double ET;
+    int32_t i, v, b;
+    uint32_t t;
+    int rc = OR_OK;
+    if (!counts || !Q || !N || !r || !mu || !col) { rc = OR_E_NOMEM; goto done; }
+    if (n < 1 || R == 0 || B < 1 || !(in->level > 0.0 && in->level < 1.0)) { rc = OR_E_ARG; goto done; }
+    /* the estimate itself */
+    memset(counts, 0, sizeof(uint32_t) * (size_t)n * (size_t)(n + 1));
+    for (t = 0; t < R; ++t)
+        for (i = 0; i < n; ++i) {
+            const int32_t nx = next_table[(size_t)t * n + i];
+            counts[(size_t)i * (n + 1) + (nx >= 0 ? nx : n)] += 1u;
+        }
+    or_counts_to_kernel(n, counts, R, in->eta, Q, r);
+    rc = or_fundamental(n, Q, N);
+    if (rc != OR_OK) goto done;
+    or_visits(n, N, in->s, mu, &ET, out->b0);
+    /* replicates */
+    for (b = 0; b < B; ++b) {
+        or_boot_counts(n, R, next_table, in->seed, (uint32_t)b, counts);
+        or_counts_to_kernel(n, counts, R, in->eta, Q, r);
+        rc = or_fundamental(n, Q, N);
+        if (rc != OR_OK) goto done;
+        or_visits(n, N, in->s, mu, &ET, out->b_rep + (size_t)b * n);
+    }
+    /* per-node summaries */
+    for (v = 0; v < n; ++v) {
+        double m = 0.0, ss = 0.0;
+        int32_t klo, khi;
+        for (b = 0; b < B; ++b) { col[b] = out->b_rep[(size_t)b * n + v]; m += col[b]; }
+        m /= (double)B;
+        for (b = 0; b < B; ++b) ss += (col[b] - m) * (col[b] - m);
+        out->mean[v] = m;
+        out->sd[v] = B > 1 ? sqrt(ss / (double)(B - 1)) : 0.0;
+        qsort(col, (size_t)B, sizeof(double), or_cmp_double);
+        klo = (int32_t)ceil(0.5 * (1.0 - in->level) * (double)B) - 1;
+        khi = (int32_t)ceil(0.5 * (1.0 + in->level) * (double)B) - 1;
+        if (klo < 0) klo = 0;
+        if (khi > B - 1) khi = B - 1;
+        out->lo[v] = col[klo];
+        out->hi[v] = col[khi];
+    }
+done:
+    free(counts); free(Q); free(N); free(r); free(mu); free(col);
+    return rc;
+}
