@@ -155,6 +155,17 @@ def run_bench(args):
                               "tv_max": float(rb["tv"].max()), "norm_N0E": rb["norm_N0E"],
                               "rem_bound": rb["rem_bound"], "rem_actual": rb["rem_actual"],
                               "b_switch": rb["b_sw"], "b_improve": rb["b_imp"]}
+    if args.bootstrap > 0:
+        # bootstrap of b from this run's draws (outside the timed region): B
+        # replicates of n R redrawn indices, B + 1 Gauss-Jordan inversions
+        nt = amc.run(ctx, G, model, **dict(q, flags=q.get("flags", 0) | amc.WANT_NEXT_TABLE))["next_table"]
+        amc.bootstrap(ctx, nt, replicates=2, seed=1, want_reps=False)
+        bs = amc.bootstrap(ctx, nt, replicates=args.bootstrap, seed=1, want_reps=False)
+        flops = (args.bootstrap + 1) * 2.0 * g.n ** 3
+        out["bootstrap"] = {"replicates": args.bootstrap, "ms": bs["ms"],
+                            "fp64_TFLOPs": flops / (bs["ms"] * 1e-3) / 1e12, "peak_fp64_TFLOPs": 78.6,
+                            "median_sd_over_b": float(np.median(bs["sd"] / np.maximum(bs["b0"], 1e-300))),
+                            "widest_interval": float((bs["hi"] - bs["lo"]).max())}
     if args.plain_R > 0:
         qp = dict(q, R=args.plain_R, flags=amc.PLAIN_LAUNCH | amc.SKIP_TAIL)
         amc.run(ctx, G, model, **qp)
@@ -372,6 +383,7 @@ def main():
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
     ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
     ap.add_argument("--robust", type=int, default=0, help="also run the robust tail with this many sampled kernels")
+    ap.add_argument("--bootstrap", type=int, default=0, help="also bootstrap b with this many replicates")
     ap.add_argument("--max-steps", dest="max_steps", type=int, default=512)
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")

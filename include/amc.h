@@ -365,6 +365,48 @@ typedef struct amc_robust_result {
 } amc_robust_result;
 AMC_API int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_robust_query *q, amc_robust_result *out);
 
+/* Nonparametric bootstrap of the AFC profile (Section 8.4): each row's R draws
+ * are resampled with replacement and b is recomputed, B times.
+ *
+ * next_table: host, R x n row-major int32, entry (t, i) = the next state of
+ * row i on draw t (0 .. n-1, or -1 = bottom), as amc_run writes it with
+ * AMC_WANT_NEXT_TABLE.  Draw t of row i in replicate beta (0 .. B-1) is the
+ * index j = (x * R) >> 32 with x = word (t mod 4) of Philox4x32-10 at counter
+ * (beta, i, t / 4, 0x80000004) under `seed`; the replicate counts row i's
+ * outcome at draw j.  Each replicate kernel takes the floor rule of amc_run
+ * (Section 8.2) and goes through N = (I - Q*)^-1, mu = s N, b = mu / (mu 1).
+ * Per node v, over the B replicate values: mean, sample standard deviation
+ * (divisor B - 1; 0 when B = 1) and the nearest-rank order statistics of
+ * indices ceil((1 - level) B / 2) - 1 and ceil((1 + level) B / 2) - 1 (clamped
+ * to 0 .. B-1) of the ascending values.  b0 is b of the given draws.
+ *
+ * Errors: AMC_E_INVALID_ARG for NULL pointers, n < 1, R < 1, an entry outside
+ * -1 .. n-1, replicates outside 1 .. AMC_MAX_BOOT_REPLICATES, level outside
+ * (0, 1), floor_eta >= 1, or an s that is negative or does not sum to 1;
+ * AMC_E_UNSUPPORTED for n > AMC_MAX_BOOT_N; AMC_E_SINGULAR when a kernel has a
+ * row that never absorbs and the floor is disabled; AMC_E_OOM when the device
+ * buffers (6 R n bytes for the table, up to 1 GiB of matrices, 8 B n for the
+ * replicates) do not fit.  Output arrays are caller-owned host buffers
+ * (NULL = skip). */
+#define AMC_MAX_BOOT_REPLICATES 4096
+#define AMC_MAX_BOOT_N 16383
+typedef struct amc_boot_query {
+    const double *s;            /* initial distribution (n) or NULL for uniform  */
+    double floor_eta;           /* < 0 selects 0.1/sqrt(R); 0 disables            */
+    int32_t replicates;         /* B                                             */
+    double level;               /* interval coverage, in (0, 1)                  */
+    uint64_t seed;
+} amc_boot_query;
+
+typedef struct amc_boot_result {
+    double *b0;                 /* n                                             */
+    double *mean, *sd, *lo, *hi;/* n each                                        */
+    double *b_rep;              /* B x n                                         */
+    double ms;                  /* HIP-event time of the whole computation        */
+} amc_boot_result;
+AMC_API int amc_bootstrap(amc_ctx *ctx, int32_t n, uint32_t R, const int32_t *next_table, const amc_boot_query *q,
+                          amc_boot_result *out);
+
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
  * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,

@@ -22,12 +22,13 @@ MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK, DIST32, DIST16 = \
     1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 MAX_TOPK, MAX_TOPK_N = 64, 7000
+MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
-           "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_chain", "amc_strerror",
-           "amc_version"]
+           "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_bootstrap", "amc_chain",
+           "amc_strerror", "amc_version"]
 WANT_PATHS = 1
 
 _P = C.POINTER
@@ -79,6 +80,16 @@ class RobustResult(C.Structure):
                 ("b_tv", _P(C.c_double)), ("b_lin", _P(C.c_double)), ("norm_N0E", C.c_double),
                 ("norm_N0", C.c_double), ("rem_bound", C.c_double), ("rem_actual", C.c_double),
                 ("tail_ms", C.c_double)]
+
+
+class BootQuery(C.Structure):
+    _fields_ = [("s", _P(C.c_double)), ("floor_eta", C.c_double), ("replicates", C.c_int32), ("level", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class BootResult(C.Structure):
+    _fields_ = [("b0", _P(C.c_double)), ("mean", _P(C.c_double)), ("sd", _P(C.c_double)), ("lo", _P(C.c_double)),
+                ("hi", _P(C.c_double)), ("b_rep", _P(C.c_double)), ("ms", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -152,6 +163,7 @@ def lib():
         L.amc_tune.argtypes = [vp, vp, _P(Model), _P(Query), C.c_uint32, _P(TuneResult)]
         L.amc_trajectories.argtypes = [vp, vp, _P(Model), _P(TrajQuery), _P(TrajResult)]
         L.amc_robust.argtypes = [vp, C.c_int32, _P(C.c_double), _P(RobustQuery), _P(RobustResult)]
+        L.amc_bootstrap.argtypes = [vp, C.c_int32, C.c_uint32, _P(C.c_int32), _P(BootQuery), _P(BootResult)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -536,5 +548,31 @@ def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.0
     for key in ("b_sw", "b_imp", "norm_N0E", "norm_N0", "rem_bound", "rem_actual", "tail_ms"):
         out[key] = float(getattr(res, key))
     out["kl_arg"], out["tv_arg"] = int(res.kl_arg), int(res.tv_arg)
+    del keep
+    return out
+
+
+def bootstrap(ctx: Context, next_table, *, replicates=100, level=0.95, floor_eta=-1.0, s=None, seed=0,
+              want_reps=True) -> dict:
+    """amc_bootstrap: resample each row's R draws with replacement, B times, and
+    summarise b per node (Section 8.4).  next_table is R x n (-1 = bottom)."""
+    nt = np.ascontiguousarray(next_table, dtype=np.int32)
+    R, n = nt.shape
+    q = BootQuery()
+    keep = []
+    if s is not None:
+        sa = np.ascontiguousarray(s, dtype=np.float64)
+        keep.append(sa)
+        q.s = _ptr(sa, C.c_double)
+    q.floor_eta, q.replicates, q.level, q.seed = float(floor_eta), int(replicates), float(level), int(seed)
+    arr = {k: np.zeros(n) for k in ("b0", "mean", "sd", "lo", "hi")}
+    if want_reps:
+        arr["b_rep"] = np.zeros((max(int(replicates), 1), n))
+    res = BootResult()
+    for key, a in arr.items():
+        setattr(res, key, _ptr(a, C.c_double))
+    _check(lib().amc_bootstrap(ctx.h, n, R, _ptr(nt, C.c_int32), C.byref(q), C.byref(res)), "amc_bootstrap")
+    out = dict(arr)
+    out["ms"] = float(res.ms)
     del keep
     return out

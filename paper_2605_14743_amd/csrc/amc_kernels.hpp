@@ -90,4 +90,12 @@ hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, 
                              double *sharp, double *sharp_supp, int *support, hipStream_t st);
 hipError_t tail_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi, hipStream_t st);
 
+// Bootstrap of b (Section 8.4).
+hipError_t boot_transpose(int n, uint32_t R, const int32_t *nt, uint16_t *tr, hipStream_t st);
+hipError_t boot_rows(int n, uint32_t R, const uint16_t *tr, uint64_t seed, uint32_t beta0, int batch, bool ident,
+                     double eta, double *A, size_t stride, hipStream_t st);
+size_t boot_stats_lds(int B);
+hipError_t boot_stats(int n, int B, const double *b_rep, int klo, int khi, double *mean, double *sd, double *lo,
+                      double *hi, hipStream_t st);
+
 }  // namespace amc
