@@ -166,6 +166,16 @@ def run_bench(args):
                             "fp64_TFLOPs": flops / (bs["ms"] * 1e-3) / 1e12, "peak_fp64_TFLOPs": 78.6,
                             "median_sd_over_b": float(np.median(bs["sd"] / np.maximum(bs["b0"], 1e-300))),
                             "widest_interval": float((bs["hi"] - bs["lo"]).max())}
+    if args.stability > 0:
+        # rank-stability check: Top-k by b at M = R / 2 and at 2M = R
+        qs = {k: v for k, v in q.items() if k not in ("pool", "reward", "topk", "gamma", "flags", "cert_topk")}
+        qs["R"] = max(wl.R // 2, 1)
+        if args.dist32:
+            qs["flags"] = amc.DIST32
+        sb = amc.stability(ctx, G, model, k=args.stability, **qs)
+        out["stability"] = {"k": args.stability, "M": qs["R"], "same_set": sb["same_set"], "overlap": sb["overlap"],
+                            "max_abs_diff": sb["max_abs_diff"], "sweep_ms": sb["sweep_ms"],
+                            "top_M": sb["top_M"].tolist(), "top_2M": sb["top_2M"].tolist()}
     if args.plain_R > 0:
         qp = dict(q, R=args.plain_R, flags=amc.PLAIN_LAUNCH | amc.SKIP_TAIL)
         amc.run(ctx, G, model, **qp)
@@ -384,6 +394,7 @@ def main():
     ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
     ap.add_argument("--robust", type=int, default=0, help="also run the robust tail with this many sampled kernels")
     ap.add_argument("--bootstrap", type=int, default=0, help="also bootstrap b with this many replicates")
+    ap.add_argument("--stability", type=int, default=0, help="also check the Top-k set at R/2 and R for this k")
     ap.add_argument("--max-steps", dest="max_steps", type=int, default=512)
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")

@@ -407,6 +407,32 @@ typedef struct amc_boot_result {
 AMC_API int amc_bootstrap(amc_ctx *ctx, int32_t n, uint32_t R, const int32_t *next_table, const amc_boot_query *q,
                           amc_boot_result *out);
 
+/* Rank-stability check of Section 8.4: the estimate at M = q->R realizations
+ * (r_begin .. r_begin + M - 1) and at 2M (r_begin .. r_begin + 2M - 1, the
+ * first M shared, as a rerun with the same seed draws them), each through the
+ * tail of amc_run with its own default floor (q->floor_eta < 0: 0.1/sqrt(M)
+ * and 0.1/sqrt(2M)), and whether the Top-k set by b (ties to the smaller
+ * index) is unchanged.  Costs 2M realizations of sweep: the second query
+ * starts from the first one's counts.  The query's graph-law and anchor rules
+ * (seed, alpha, k_min, tie_tau, floor_eta, s) and execution choices (mode,
+ * tile, waves, group, AMC_DIST16 / AMC_DIST32 / AMC_PLAIN_LAUNCH) apply; its
+ * other flags, reward, eps, r_lower, cert_topk and debug pairs are ignored.
+ * Errors: AMC_E_INVALID_ARG for NULL pointers, k outside 1 .. min(16, n-1),
+ * R = 0 or 2R past 2^31, r_begin + 2R past 2^32, a pool, topk > 0 or
+ * AMC_FALLBACK; otherwise those of amc_run.  Output arrays are caller-owned
+ * host buffers (NULL = skip). */
+typedef struct amc_stability_result {
+    double *b_M, *b_2M;         /* n each                                        */
+    int32_t *top_M, *top_2M;    /* k each, in decreasing b                       */
+    uint32_t *counts_2M;        /* n x (n+1) counts over the 2M realizations     */
+    int32_t same_set;           /* 1 when the two Top-k sets are equal as sets    */
+    int32_t overlap;            /* members the two sets share                     */
+    double max_abs_diff;        /* max over v of |b_2M[v] - b_M[v]|               */
+    double sweep_ms;            /* HIP-event time of the two sweeps               */
+} amc_stability_result;
+AMC_API int amc_stability(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, int32_t k,
+                          amc_stability_result *out);
+
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as
  * the tail of amc_run (Sections 4 and 5.5).  q supplies s, reward, eps,

@@ -28,7 +28,7 @@ EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_s
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
            "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_bootstrap", "amc_chain",
-           "amc_strerror", "amc_version"]
+           "amc_stability", "amc_strerror", "amc_version"]
 WANT_PATHS = 1
 
 _P = C.POINTER
@@ -90,6 +90,12 @@ class BootQuery(C.Structure):
 class BootResult(C.Structure):
     _fields_ = [("b0", _P(C.c_double)), ("mean", _P(C.c_double)), ("sd", _P(C.c_double)), ("lo", _P(C.c_double)),
                 ("hi", _P(C.c_double)), ("b_rep", _P(C.c_double)), ("ms", C.c_double)]
+
+
+class StabilityResult(C.Structure):
+    _fields_ = [("b_M", _P(C.c_double)), ("b_2M", _P(C.c_double)), ("top_M", _P(C.c_int32)),
+                ("top_2M", _P(C.c_int32)), ("counts_2M", _P(C.c_uint32)), ("same_set", C.c_int32),
+                ("overlap", C.c_int32), ("max_abs_diff", C.c_double), ("sweep_ms", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -164,6 +170,7 @@ def lib():
         L.amc_trajectories.argtypes = [vp, vp, _P(Model), _P(TrajQuery), _P(TrajResult)]
         L.amc_robust.argtypes = [vp, C.c_int32, _P(C.c_double), _P(RobustQuery), _P(RobustResult)]
         L.amc_bootstrap.argtypes = [vp, C.c_int32, C.c_uint32, _P(C.c_int32), _P(BootQuery), _P(BootResult)]
+        L.amc_stability.argtypes = [vp, vp, _P(Model), _P(Query), C.c_int32, _P(StabilityResult)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -549,6 +556,26 @@ def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.0
         out[key] = float(getattr(res, key))
     out["kl_arg"], out["tv_arg"] = int(res.kl_arg), int(res.tv_arg)
     del keep
+    return out
+
+
+def stability(ctx: Context, graph: Graph, model: dict, k: int = 5, **query) -> dict:
+    """amc_stability: the estimate at M = R and at 2M realizations and whether
+    the Top-k set by b moved (Section 8.4)."""
+    m, keep_m = make_model(**model)
+    q, keep_q = make_query(graph.n, **query)
+    n = graph.n
+    arr = {"b_M": np.zeros(n), "b_2M": np.zeros(n), "top_M": np.zeros(k, np.int32), "top_2M": np.zeros(k, np.int32),
+           "counts_2M": np.zeros((n, n + 1), np.uint32)}
+    res = StabilityResult()
+    for key, a in arr.items():
+        ct = C.c_double if a.dtype == np.float64 else (C.c_int32 if a.dtype == np.int32 else C.c_uint32)
+        setattr(res, key, _ptr(a, ct))
+    _check(lib().amc_stability(ctx.h, graph.h, C.byref(m), C.byref(q), int(k), C.byref(res)), "amc_stability")
+    out = dict(arr)
+    out["same_set"], out["overlap"] = bool(res.same_set), int(res.overlap)
+    out["max_abs_diff"], out["sweep_ms"] = float(res.max_abs_diff), float(res.sweep_ms)
+    del keep_m, keep_q
     return out
 
 
