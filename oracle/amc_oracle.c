@@ -1434,3 +1434,86 @@ done:
     free(counts); free(Q); free(N); free(r); free(mu); free(col);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Wasserstein-1 between two profiles on the shortest-path (hop) metric of the
+ * base topology (robust experiment of Section 9.1; W1 as an integral
+ * probability metric over 1-Lipschitz functions, Section 4).
+ *
+ * On a graph metric W1(p, q) is the cost of the cheapest flow that moves the
+ * surplus p - q over the edges at cost 1 per unit and edge (the transshipment
+ * form of the transport problem).  It is computed by successive shortest
+ * paths: every round runs Bellman-Ford from all nodes with remaining surplus
+ * over the residual graph (an edge carrying flow f from u to v offers v -> u at
+ * cost -1 for up to f, and u -> v at cost +1 without limit; a flow-free edge
+ * offers both directions at +1), takes the nearest node with remaining
+ * deficit (smallest index among the nearest), and pushes along the
+ * predecessor path the largest amount that neither overdraws the surplus,
+ * the deficit, nor a cancelled flow.  Augmenting along shortest paths keeps
+ * the flow optimal for the amount moved, so the final cost is W1.
+ * Returns OR_E_ARG for a disconnected graph with unbalanced components or an
+ * exhausted round budget.
+ * ---------------------------------------------------------------------- */
+int or_w1(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const double *p, const double *q, double *w1)
+{
+    double *ex = (double *)malloc(sizeof(double) * (size_t)n);
+    double *f = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *pred = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);   /* 2e + dir, -1 = none */
+    const int64_t INF = INT64_MAX / 4;
+    int64_t round, e, max_rounds = 16 * ((int64_t)n + m) + 16;
+    int32_t v;
+    int rc = OR_OK;
+    if (!ex || !f || !dist || !pred) { rc = OR_E_NOMEM; goto out; }
+    for (v = 0; v < n; ++v) ex[v] = p[v] - q[v];
+    for (round = 0;; ++round) {
+        int has_src = 0, has_snk = 0, changed, pass;
+        int32_t t = -1, s, x;
+        double th;
+        for (v = 0; v < n; ++v) { has_src |= ex[v] > 0.0; has_snk |= ex[v] < 0.0; }
+        if (!has_src || !has_snk) break;
+        if (round >= max_rounds) { rc = OR_E_ARG; goto out; }
+        for (v = 0; v < n; ++v) { dist[v] = ex[v] > 0.0 ? 0 : INF; pred[v] = -1; }
+        /* Bellman-Ford with strict improvements (no negative cycle exists in
+         * the residual graph of an optimal flow) */
+        for (pass = 0, changed = 1; changed; ++pass) {
+            if (pass > n + 1) { rc = OR_E_ARG; goto out; }
+            changed = 0;
+            for (e = 0; e < m; ++e) {
+                const int32_t a = eu[e], b = ev[e];
+                const int64_t c_ab = f[e] < 0.0 ? -1 : 1;   /* a -> b */
+                const int64_t c_ba = f[e] > 0.0 ? -1 : 1;   /* b -> a */
+                if (dist[a] < INF && dist[a] + c_ab < dist[b]) { dist[b] = dist[a] + c_ab; pred[b] = 2 * e; changed = 1; }
+                if (dist[b] < INF && dist[b] + c_ba < dist[a]) { dist[a] = dist[b] + c_ba; pred[a] = 2 * e + 1; changed = 1; }
+            }
+        }
+        for (v = 0; v < n; ++v)
+            if (ex[v] < 0.0 && dist[v] < INF && (t < 0 || dist[v] < dist[t])) t = v;
+        if (t < 0) { rc = OR_E_ARG; goto out; }              /* surplus cannot reach any deficit */
+        /* bottleneck along the path back to its source */
+        th = -ex[t];
+        for (x = t, s = t, pass = 0; pred[x] >= 0; ++pass) {
+            if (pass > n) { rc = OR_E_ARG; goto out; }
+            const int64_t a = pred[x], ee = a >> 1;
+            const int fwd = (a & 1) == 0;                     /* eu -> ev */
+            if (fwd && f[ee] < 0.0 && -f[ee] < th) th = -f[ee];
+            if (!fwd && f[ee] > 0.0 && f[ee] < th) th = f[ee];
+            x = fwd ? eu[ee] : ev[ee];
+            s = x;
+        }
+        if (ex[s] < th) th = ex[s];
+        for (x = t; pred[x] >= 0; ) {
+            const int64_t a = pred[x], ee = a >> 1;
+            const int fwd = (a & 1) == 0;
+            f[ee] += fwd ? th : -th;
+            x = fwd ? eu[ee] : ev[ee];
+        }
+        ex[s] -= th;
+        ex[t] += th;
+    }
+    *w1 = 0.0;
+    for (e = 0; e < m; ++e) *w1 += fabs(f[e]);
+out:
+    free(ex); free(f); free(dist); free(pred);
+    return rc;
+}
