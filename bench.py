@@ -150,11 +150,18 @@ def run_bench(args):
         amc.robust(ctx, last["Q"], f=f, samples=2, delta=0.5, r_min=0.05, seed=1)
         rb = amc.robust(ctx, last["Q"], f=f, samples=args.robust, delta=0.5, r_min=0.05, seed=1)
         flops = (args.robust + 2) * 2.0 * g.n ** 3 + 2 * 2.0 * g.n ** 3
+        w1 = {}
+        if g.n <= amc.MAX_W1_N:
+            # W1 on the hop metric of the base topology: one transshipment per sample
+            rw = amc.robust(ctx, last["Q"], f=f, samples=args.robust, delta=0.5, r_min=0.05, seed=1,
+                            topology=(g.eu, g.ev))
+            w1 = {"w1_max": float(rw["w1"].max()), "w1_arg": rw["w1_arg"], "kl_arg": rw["kl_arg"],
+                  "w1_ms": rw["tail_ms"] - rb["tail_ms"]}
         out["robust_tail"] = {"samples": args.robust, "ms": rb["tail_ms"], "fp64_TFLOPs": flops / (rb["tail_ms"] * 1e-3)
                               / 1e12, "peak_fp64_TFLOPs": 78.6, "kl_max": float(rb["kl"].max()),
                               "tv_max": float(rb["tv"].max()), "norm_N0E": rb["norm_N0E"],
                               "rem_bound": rb["rem_bound"], "rem_actual": rb["rem_actual"],
-                              "b_switch": rb["b_sw"], "b_improve": rb["b_imp"]}
+                              "b_switch": rb["b_sw"], "b_improve": rb["b_imp"], **w1}
     if args.bootstrap > 0:
         # bootstrap of b from this run's draws (outside the timed region): B
         # replicates of n R redrawn indices, B + 1 Gauss-Jordan inversions

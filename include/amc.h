@@ -343,8 +343,19 @@ AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *
  *  - the first-order sensitivity of Section 5.4 for E = Q* - Q0 (Q* the KL
  *    maximiser): b_lin, and in infinity norms |N0 E|, |N0|, the remainder
  *    bound |N0 E|^2 |N0| / (1 - |N0 E|) (infinite when |N0 E| >= 1) and the
- *    actual |N* - N0 - N0 E N0|.
+ *    actual |N* - N0 - N0 E N0|;
+ *  - with a base topology (m > 0 edges eu, ev, canonical as for
+ *    amc_graph_create, connected, n <= AMC_MAX_W1_N): the Wasserstein-1
+ *    distance W1(b(P), b0) of every sample on the hop metric of that topology
+ *    (robust experiment of Section 9.1), computed exactly as the cheapest
+ *    transshipment of b(P) - b0 over its edges at unit cost, and the AFC at
+ *    the W1 maximiser.
+ * Errors: AMC_E_INVALID_ARG for a bad size, range or edge list, a
+ * disconnected topology, or a Q0 row that does not absorb; AMC_E_UNSUPPORTED
+ * for n > AMC_MAX_W1_N with a topology, or when the W1 solver exceeds its
+ * iteration bounds; AMC_E_SINGULAR, AMC_E_OOM, AMC_E_HIP as for amc_run.
  * Output arrays are caller-owned host buffers (NULL = skip). */
+#define AMC_MAX_W1_N 3000
 typedef struct amc_robust_query {
     const double *s;            /* initial distribution (n) or NULL for uniform  */
     const double *f;            /* node values (n, >= 0) or NULL (no transition rewards) */
@@ -352,6 +363,8 @@ typedef struct amc_robust_query {
     double delta;               /* relative radius, >= 0                          */
     double r_min;               /* leak lower bound, in (0, 1]                    */
     uint64_t seed;
+    int64_t m;                  /* edges of the base topology for W1 (0 = no W1)  */
+    const int32_t *eu, *ev;     /* m each, eu < ev, lexicographically increasing   */
 } amc_robust_query;
 
 typedef struct amc_robust_result {
@@ -362,6 +375,9 @@ typedef struct amc_robust_result {
     double *b_kl, *b_tv, *b_lin;/* n each                                        */
     double norm_N0E, norm_N0, rem_bound, rem_actual;
     double tail_ms;             /* HIP-event time of the whole computation        */
+    double *w1;                 /* samples: W1(b(P), b0) (needs a topology)       */
+    int32_t w1_arg;             /* -1 without samples or topology                 */
+    double *b_w1;               /* n: AFC at the W1 maximiser                     */
 } amc_robust_result;
 AMC_API int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_robust_query *q, amc_robust_result *out);
 

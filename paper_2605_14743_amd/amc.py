@@ -23,6 +23,7 @@ WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LA
     1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 MAX_TOPK, MAX_TOPK_N = 64, 7000
 MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
+MAX_W1_N = 3000
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
@@ -71,7 +72,8 @@ class TrajResult(C.Structure):
 
 class RobustQuery(C.Structure):
     _fields_ = [("s", _P(C.c_double)), ("f", _P(C.c_double)), ("samples", C.c_int32), ("delta", C.c_double),
-                ("r_min", C.c_double), ("seed", C.c_uint64)]
+                ("r_min", C.c_double), ("seed", C.c_uint64), ("m", C.c_int64), ("eu", _P(C.c_int32)),
+                ("ev", _P(C.c_int32))]
 
 
 class RobustResult(C.Structure):
@@ -79,7 +81,7 @@ class RobustResult(C.Structure):
                 ("tv", _P(C.c_double)), ("kl_arg", C.c_int32), ("tv_arg", C.c_int32), ("b_kl", _P(C.c_double)),
                 ("b_tv", _P(C.c_double)), ("b_lin", _P(C.c_double)), ("norm_N0E", C.c_double),
                 ("norm_N0", C.c_double), ("rem_bound", C.c_double), ("rem_actual", C.c_double),
-                ("tail_ms", C.c_double)]
+                ("tail_ms", C.c_double), ("w1", _P(C.c_double)), ("w1_arg", C.c_int32), ("b_w1", _P(C.c_double))]
 
 
 class BootQuery(C.Structure):
@@ -528,9 +530,10 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
     return out
 
 
-def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0) -> dict:
+def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0, topology=None) -> dict:
     """amc_robust: transition reward-AFCs, sampled admissible kernels with their KL / TV
-    maximisers, and the first-order sensitivity with its remainder (Sections 5.1, 5.4, 6.4)."""
+    (and, with topology = (eu, ev), W1) maximisers, and the first-order sensitivity with its
+    remainder (Sections 5.1, 5.4, 6.4, 9.1)."""
     Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
     n = Q0.shape[0]
     q = RobustQuery()
@@ -544,17 +547,22 @@ def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.0
         keep.append(fa)
         q.f = _ptr(fa, C.c_double)
     q.samples, q.delta, q.r_min, q.seed = int(samples), float(delta), float(r_min), int(seed)
+    if topology is not None:
+        eu = np.ascontiguousarray(topology[0], dtype=np.int32)
+        ev = np.ascontiguousarray(topology[1], dtype=np.int32)
+        keep += [eu, ev]
+        q.m, q.eu, q.ev = len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32)
     arr = {"b0": np.zeros(n), "kl": np.zeros(max(samples, 1)), "tv": np.zeros(max(samples, 1)), "b_kl": np.zeros(n),
-           "b_tv": np.zeros(n), "b_lin": np.zeros(n)}
+           "b_tv": np.zeros(n), "b_lin": np.zeros(n), "w1": np.zeros(max(samples, 1)), "b_w1": np.zeros(n)}
     res = RobustResult()
     for key, a in arr.items():
         setattr(res, key, _ptr(a, C.c_double))
     _check(lib().amc_robust(ctx.h, n, _ptr(Q0, C.c_double), C.byref(q), C.byref(res)), "amc_robust")
     out = dict(arr)
-    out["kl"], out["tv"] = out["kl"][:samples], out["tv"][:samples]
+    out["kl"], out["tv"], out["w1"] = out["kl"][:samples], out["tv"][:samples], out["w1"][:samples]
     for key in ("b_sw", "b_imp", "norm_N0E", "norm_N0", "rem_bound", "rem_actual", "tail_ms"):
         out[key] = float(getattr(res, key))
-    out["kl_arg"], out["tv_arg"] = int(res.kl_arg), int(res.tv_arg)
+    out["kl_arg"], out["tv_arg"], out["w1_arg"] = int(res.kl_arg), int(res.tv_arg), int(res.w1_arg)
     del keep
     return out
 

@@ -10,6 +10,8 @@
 // (row i: (1 - Q_ii) - sum_{j != i} Q_ij = r_i > 0), so the inverse is taken
 // by blocked Gauss-Jordan elimination without pivoting (growth factor at most
 // 2 for such matrices).
+#include <algorithm>
+
 #include "amc_dev.hpp"
 #include "amc_kernels.hpp"
 
@@ -295,13 +297,17 @@ __global__ void k_afc(int n, const double *mu, double *b, const double *f, const
 
 // Complement of the Top-k in increasing index order (single workgroup).
 __global__ void k_complement(int n, int topk, const int32_t *top, int32_t *cv) {
-    if (threadIdx.x != 0) return;
-    int c = 0;
-    for (int v = 0; v < n; ++v) {
-        bool in = false;
-        for (int q = 0; q < topk; ++q) in |= (top[q] == v);
-        if (!in) cv[c++] = v;
+    // v keeps its place among the vertices outside the Top-k: v minus the
+    // members below it (members are distinct)
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    bool in = false;
+    int below = 0;
+    for (int q = 0; q < topk; ++q) {
+        in |= top[q] == v;
+        below += top[q] < v;
     }
+    if (!in) cv[v - below] = v;
 }
 
 // Largest row support max_i #{j : Q_ij > 0} (support-restricted radii).
@@ -323,29 +329,44 @@ __global__ void k_support(int n, const double *Q, int *out) {
 // (u in Top-k, v outside): one thread per v.  Dense radii eps_ij = eps give
 // epsbar = n eps; the support-restricted radii eps 1{Q_ij > 0} give
 // epsbar_supp = eps max_i |supp Q_i|.
-__global__ void k_certificates(int n, int topk, const double *N, const double *mu, const int32_t *top,
-                               const int32_t *cv, double eps, double r_lower, const int *support, double *gap,
-                               double *sharp, double *sharp_supp) {
+// Column maxima max_i |N_{i,top[a]} - N_{i,v}| over a slice of the rows,
+// combined across slices by an integer maximum on the bit patterns
+// (non-negative doubles order like their bits); mx starts at zero.
+__global__ void k_cert_colmax(int n, int topk, const double *N, const int32_t *top, const int32_t *cv,
+                              unsigned long long *mx) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int nc = n - topk;
     if (c >= nc) return;
-    const double coef = (double)n * eps / r_lower;
-    const double coef_supp = (double)(*support) * eps / r_lower;
+    const int rows = (n + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int i0 = (int)blockIdx.y * rows, i1 = min(n, i0 + rows);
     const int v = cv[c];
-    double mx[16];
-    for (int a = 0; a < topk; ++a) mx[a] = 0.0;
-    for (int i = 0; i < n; ++i) {
+    double m[16];
+    for (int a = 0; a < topk; ++a) m[a] = 0.0;
+    for (int i = i0; i < i1; ++i) {
         const double nv = N[(size_t)i * n + v];
         for (int a = 0; a < topk; ++a) {
             const double d = fabs(N[(size_t)i * n + top[a]] - nv);
-            mx[a] = d > mx[a] ? d : mx[a];
+            m[a] = d > m[a] ? d : m[a];
         }
     }
-    for (int a = 0; a < topk; ++a) {
-        gap[(size_t)a * nc + c] = mu[top[a]] - mu[v];
-        sharp[(size_t)a * nc + c] = coef * mx[a];
-        if (sharp_supp) sharp_supp[(size_t)a * nc + c] = coef_supp * mx[a];
-    }
+    for (int a = 0; a < topk; ++a)
+        if (m[a] > 0.0) atomicMax(&mx[(size_t)a * nc + c], as_u64(m[a]));
+}
+
+// gap G_uv = mu_u - mu_v (eq. pm-gap) and the sharp thresholds (eq.
+// sharp-gap) from the column maxima held in `sharp`.
+__global__ void k_certificates(int n, int topk, const double *mu, const int32_t *top, const int32_t *cv, double eps,
+                               double r_lower, const int *support, double *gap, double *sharp, double *sharp_supp) {
+    const int nc = n - topk;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)topk * nc) return;
+    const int a = (int)(idx / nc), c = (int)(idx % nc);
+    const double coef = (double)n * eps / r_lower;
+    const double coef_supp = (double)(*support) * eps / r_lower;
+    const double mx = as_f64(((const unsigned long long *)sharp)[idx]);
+    gap[idx] = mu[top[a]] - mu[cv[c]];
+    sharp[idx] = coef * mx;
+    if (sharp_supp) sharp_supp[idx] = coef_supp * mx;
 }
 
 __global__ void k_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi) {
@@ -412,9 +433,17 @@ hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, 
                              double *sharp, double *sharp_supp, int *support, hipStream_t st) {
     hipLaunchKernelGGL(k_support, dim3(n), dim3(256), 0, st, n, Q, support);
     if (topk > 0 && topk < n) {
-        hipLaunchKernelGGL(k_complement, dim3(1), dim3(64), 0, st, n, topk, top, cv);
-        hipLaunchKernelGGL(k_certificates, dim3((n - topk + 127) / 128), dim3(128), 0, st, n, topk, N, mu, top, cv,
-                           eps, r_lower, support, gap, sharp, sharp_supp);
+        const int nc = n - topk;
+        const size_t pairs = (size_t)topk * nc;
+        hipLaunchKernelGGL(k_complement, dim3((n + 255) / 256), dim3(256), 0, st, n, topk, top, cv);
+        const hipError_t e = fill_u32(sharp, 2 * pairs, 0u, st);
+        if (e != hipSuccess) return e;
+        // enough row slices to give every CU a few workgroups
+        const int cols = (nc + 63) / 64, slices = std::max(1, std::min(n / 8, 1024 / std::max(cols, 1)));
+        hipLaunchKernelGGL(k_cert_colmax, dim3(cols, slices), dim3(64), 0, st, n, topk, N, top, cv,
+                           (unsigned long long *)sharp);
+        hipLaunchKernelGGL(k_certificates, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, n, topk, mu,
+                           top, cv, eps, r_lower, support, gap, sharp, sharp_supp);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,235 @@
+// w1.hip -- Wasserstein-1 between AFC profiles on the hop metric of the base
+// topology, one workgroup per sampled profile.
+//
+// Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
+// Uncertainty: An Absorbing Markov Chain Approach" (robust experiment of
+// Section 9.1: discrepancies by W1 with the shortest-path distance of the base
+// topology as ground metric; W1 as an integral probability metric, Section 4).
+//
+// On a graph metric, W1(p, q) is the cost of the cheapest flow that moves the
+// surplus p - q over the edges at cost 1 per unit and edge.  The workgroup
+// solves that transshipment by successive shortest paths:
+//   - the residual graph: an edge carrying flow f from u to v offers v -> u at
+//     cost -1 (capacity f) and u -> v at cost +1; a flow-free edge offers both
+//     directions at +1;
+//   - labels (distance, hops) from every node with surplus, by parallel
+//     Bellman-Ford passes over the edges with 64-bit LDS minima on the packed
+//     label until a pass changes nothing (at most n + 1 passes: no residual
+//     cycle is negative while the flow is optimal for what it has moved, and
+//     the lexicographic label makes the shortest walks simple);
+//   - the nearest node with deficit (smallest index among the nearest) and
+//     its path back to a surplus node, found edge by edge through arcs that
+//     realise the label (the hop count falls by one per edge, so the walk
+//     ends within n steps);
+//   - the largest push that overdraws neither the surplus, the deficit, nor a
+//     cancelled flow.  Each push zeroes one of those exactly (x + (-x) = 0).
+// W1 is the sum of |flow| over the edges once no surplus or no deficit is
+// left.  Every loop has a bound; exceeding one sets bit 4 of *err.
+#include "amc_dev.hpp"
+#include "amc_kernels.hpp"
+
+namespace amc {
+
+namespace {
+
+constexpr int kW1Threads = 256;
+constexpr uint64_t kNoLabel = ~0ull;
+constexpr uint64_t kDistBias = 1ull << 31;
+
+__device__ __forceinline__ uint64_t w1_label(int64_t dist, uint32_t hops) {
+    return ((uint64_t)(dist + (int64_t)kDistBias) << 32) | hops;
+}
+__device__ __forceinline__ int64_t w1_dist(uint64_t key) { return (int64_t)(key >> 32) - (int64_t)kDistBias; }
+
+// cost of traversing edge e from its first endpoint (fwd) or its second
+__device__ __forceinline__ int64_t w1_cost(double fe, bool fwd) {
+    return fwd ? (fe < 0.0 ? -1 : 1) : (fe > 0.0 ? -1 : 1);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *eu, const int32_t *ev,
+                                                   const int32_t *rp, const int32_t *inc, const double *P,
+                                                   const double *q, double *fscr, double *w1, int *err) {
+    extern __shared__ double w1_smem[];
+    double *ex = w1_smem;                                   // n: remaining surplus (> 0) / deficit (< 0)
+    uint64_t *key = (uint64_t *)(ex + n);                   // n: packed (distance, hops) labels
+    int32_t *path = (int32_t *)(key + n);                   // n: arcs of the current path (2e + dir)
+    __shared__ int s_any_src, s_any_snk, s_changed, s_plen, s_src, s_stop;
+    __shared__ uint64_t s_best;
+    __shared__ uint32_t s_pick;
+    __shared__ double s_red[kW1Threads];
+    const int tid = threadIdx.x, k = blockIdx.x;
+    const double *p = P + (size_t)k * n;
+    double *f = fscr + (size_t)k * m;
+    for (int v = tid; v < n; v += kW1Threads) ex[v] = p[v] - q[v];
+    for (int e = tid; e < m; e += kW1Threads) f[e] = 0.0;
+    if (tid == 0) s_stop = 0;
+    __syncthreads();
+    const long max_rounds = 16L * ((long)n + m) + 16;
+    for (long round = 0;; ++round) {
+        if (tid == 0) {
+            s_any_src = 0;
+            s_any_snk = 0;
+        }
+        __syncthreads();
+        int src = 0, snk = 0;
+        for (int v = tid; v < n; v += kW1Threads) {
+            src |= ex[v] > 0.0;
+            snk |= ex[v] < 0.0;
+        }
+        if (src) s_any_src = 1;
+        if (snk) s_any_snk = 1;
+        __syncthreads();
+        if (!s_any_src || !s_any_snk) break;
+        if (round >= max_rounds) {
+            if (tid == 0) {
+                atomicOr(err, 4);
+                s_stop = 1;
+            }
+            break;
+        }
+        // labels from every node with surplus
+        for (int v = tid; v < n; v += kW1Threads) key[v] = ex[v] > 0.0 ? w1_label(0, 0) : kNoLabel;
+        __syncthreads();
+        int pass = 0;
+        for (;; ++pass) {
+            if (tid == 0) s_changed = 0;
+            __syncthreads();
+            bool ch = false;
+            for (int e = tid; e < m; e += kW1Threads) {
+                const int a = eu[e], b = ev[e];
+                const double fe = f[e];
+                const uint64_t ka = key[a], kb = key[b];
+                if (ka != kNoLabel) {
+                    const uint64_t c = w1_label(w1_dist(ka) + w1_cost(fe, true), (uint32_t)ka + 1u);
+                    if (c < kb && atomicMin((unsigned long long *)&key[b], (unsigned long long)c) > c) ch = true;
+                }
+                if (kb != kNoLabel) {
+                    const uint64_t c = w1_label(w1_dist(kb) + w1_cost(fe, false), (uint32_t)kb + 1u);
+                    if (c < ka && atomicMin((unsigned long long *)&key[a], (unsigned long long)c) > c) ch = true;
+                }
+            }
+            if (ch) s_changed = 1;
+            __syncthreads();
+            const int changed = s_changed;
+            __syncthreads();   // every thread has read the flag before it is cleared again
+            if (!changed) break;
+            if (pass > n + 1) {
+                if (tid == 0) {
+                    atomicOr(err, 4);
+                    s_stop = 1;
+                }
+                break;
+            }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        // the nearest deficit node, smallest index among the nearest
+        if (tid == 0) s_best = kNoLabel;
+        __syncthreads();
+        for (int v = tid; v < n; v += kW1Threads) {
+            if (ex[v] < 0.0 && key[v] != kNoLabel) {
+                const uint64_t c = ((key[v] >> 32) << 32) | (uint32_t)v;
+                atomicMin((unsigned long long *)&s_best, (unsigned long long)c);
+            }
+        }
+        __syncthreads();
+        if (s_best == kNoLabel) {   // surplus that reaches no deficit: components out of balance
+            if (tid == 0) {
+                atomicOr(err, 4);
+                s_stop = 1;
+            }
+            break;
+        }
+        const int t = (int)(uint32_t)s_best;
+        // walk back along arcs that realise the labels
+        if (tid == 0) {
+            s_plen = 0;
+            s_src = t;
+        }
+        __syncthreads();
+        for (int step = 0;; ++step) {
+            const int x = s_src;
+            const uint64_t kx = key[x];
+            if ((uint32_t)kx == 0u) break;          // hop count 0: a node with surplus
+            if (step >= n) {                        // a path has at most n - 1 edges
+                if (tid == 0) {
+                    atomicOr(err, 4);
+                    s_stop = 1;
+                }
+                break;
+            }
+            if (tid == 0) s_pick = 0xFFFFFFFFu;
+            __syncthreads();
+            for (int j = rp[x] + tid; j < rp[x + 1]; j += kW1Threads) {
+                const int e = inc[j];
+                const bool into_fwd = ev[e] == x;    // arc eu -> ev arrives at x
+                const int y = into_fwd ? eu[e] : ev[e];
+                const uint64_t ky = key[y];
+                if (ky != kNoLabel &&
+                    w1_label(w1_dist(ky) + w1_cost(f[e], into_fwd), (uint32_t)ky + 1u) == kx)
+                    atomicMin(&s_pick, (uint32_t)j);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const uint32_t j = s_pick;
+                if (j == 0xFFFFFFFFu) {
+                    atomicOr(err, 4);
+                    s_stop = 1;
+                } else {
+                    const int e = inc[j];
+                    const bool into_fwd = ev[e] == x;
+                    path[s_plen++] = 2 * e + (into_fwd ? 0 : 1);
+                    s_src = into_fwd ? eu[e] : ev[e];
+                }
+            }
+            __syncthreads();
+            if (s_stop) break;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        // push
+        if (tid == 0) {
+            const int s = s_src;
+            double th = -ex[t];
+            for (int i = 0; i < s_plen; ++i) {
+                const int e = path[i] >> 1;
+                const bool fwd = (path[i] & 1) == 0;
+                const double fe = f[e];
+                if (fwd && fe < 0.0 && -fe < th) th = -fe;
+                if (!fwd && fe > 0.0 && fe < th) th = fe;
+            }
+            if (ex[s] < th) th = ex[s];
+            for (int i = 0; i < s_plen; ++i) {
+                const int e = path[i] >> 1;
+                f[e] += (path[i] & 1) == 0 ? th : -th;
+            }
+            ex[s] -= th;
+            ex[t] += th;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = tid; e < m; e += kW1Threads) acc += fabs(f[e]);
+    s_red[tid] = acc;
+    __syncthreads();
+    for (int s = kW1Threads / 2; s > 0; s >>= 1) {
+        if (tid < s) s_red[tid] += s_red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) w1[k] = s_stop ? NAN : s_red[0];
+}
+
+size_t w1_lds_bytes(int n) { return 20 * (size_t)n; }
+
+hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *rp, const int32_t *inc,
+                     int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_w1, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, rp, inc, P, q, fscr,
+                       w1, err);
+    return hipGetLastError();
+}
+
+}  // namespace amc

@@ -1,0 +1,142 @@
+"""GPU parity of the Wasserstein-1 leg of the robust tail (amc_robust with a
+base topology; robust experiment of Section 9.1) against the oracle: W1 of
+every sampled profile from b0 within 1e-11 of the largest (two exact
+transshipment solvers that push along different shortest paths), the
+maximiser identical unless the two largest are that close, and the AFC at
+the maximiser within 1e-12 of its max norm."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14743_amd import amc
+from paper_2605_14743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = amc.Context(0)
+    yield c
+    c.close()
+
+
+def random_kernel(n, seed, leak=0.2, density=0.5):
+    rng = np.random.default_rng(seed)
+    Q = rng.random((n, n)) * (rng.random((n, n)) < density)
+    Q[np.arange(n), rng.integers(0, n, n)] += 0.1
+    return Q / Q.sum(1, keepdims=True) * (1 - leak)
+
+
+def connected_graph(n, extra, seed):
+    rng = np.random.default_rng(seed)
+    edges = {(int(rng.integers(0, v)), v) for v in range(1, n)}
+    while len(edges) < n - 1 + extra and len(edges) < n * (n - 1) // 2:
+        u, v = sorted(rng.choice(n, 2, replace=False).tolist())
+        edges.add((u, v))
+    e = np.array(sorted(edges), dtype=np.int32).reshape(-1, 2)
+    return e[:, 0], e[:, 1]
+
+
+def oracle_w1(Q0, eu, ev, samples, delta, r_min, seed, only=None):
+    n = Q0.shape[0]
+    s = np.full(n, 1.0 / n)
+    b0 = O.chain(Q0, s)["b"]
+    out = {}
+    for k in (range(samples) if only is None else only):
+        bk = O.chain(O.perturbed_kernel(Q0, seed, k, delta, r_min), s)["b"]
+        out[k] = (O.w1(n, eu, ev, bk, b0), bk)
+    return out
+
+
+def check(g, o, what):
+    w = np.array([o[k][0] for k in sorted(o)])
+    scale = max(w.max(), 1e-300)
+    assert np.abs(g["w1"] - w).max() <= 1e-11 * scale, f"{what}: w1"
+    top2 = np.sort(w)[-2:] if len(w) > 1 else w
+    if len(w) == 1 or top2[1] - top2[0] > 1e-10 * scale:
+        assert g["w1_arg"] == int(np.argmax(w)), what
+    bw = o[g["w1_arg"]][1]
+    assert np.abs(g["b_w1"] - bw).max() <= 1e-12 * np.abs(bw).max(), f"{what}: b_w1"
+
+
+@pytest.mark.parametrize("n,extra,samples", [(2, 0, 5), (7, 4, 12), (64, 40, 12), (130, 300, 12), (20, 10, 130)])
+def test_random_topologies(ctx, n, extra, samples):
+    Q0 = random_kernel(n, n)
+    eu, ev = connected_graph(n, extra, n)
+    say(f"[gpu] robust w1 n={n} m={len(eu)} samples={samples}")
+    g = amc.robust(ctx, Q0, samples=samples, delta=0.4, r_min=0.05, seed=n, topology=(eu, ev))
+    o = oracle_w1(Q0, eu, ev, samples, 0.4, 0.05, n)
+    check(g, o, f"n={n}")
+    # the KL / TV legs are unchanged by the topology
+    g0 = amc.robust(ctx, Q0, samples=samples, delta=0.4, r_min=0.05, seed=n)
+    assert np.array_equal(g0["kl"], g["kl"]) and np.array_equal(g0["tv"], g["tv"])
+    assert g0["w1_arg"] == -1
+
+
+def test_tree_topology(ctx):
+    # a path: W1 is the sum of the absolute cumulative differences
+    n = 50
+    Q0 = random_kernel(n, 5)
+    eu = np.arange(n - 1, dtype=np.int32)
+    ev = eu + 1
+    say("[gpu] robust w1 on a path")
+    g = amc.robust(ctx, Q0, samples=8, delta=0.5, r_min=0.05, seed=3, topology=(eu, ev))
+    o = oracle_w1(Q0, eu, ev, 8, 0.5, 0.05, 3)
+    check(g, o, "path")
+    for k in range(8):
+        expect = np.abs(np.cumsum(o[k][1] - g["b0"])[:-1]).sum()
+        assert g["w1"][k] == pytest.approx(expect, rel=1e-11)
+
+
+def test_ws1000_estimated_kernel(ctx):
+    # the kernel estimated from the WS(1000) run, its own base topology, 100 samples
+    wl = W.config_ws1000()
+    gr = wl.graph
+    G = amc.Graph(ctx, gr.n, gr.eu, gr.ev, gr.w0)
+    res = amc.run(ctx, G, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min)
+    G.close()
+    say("[gpu] robust w1 on the ws1000 kernel, 100 samples")
+    g = amc.robust(ctx, res["Q"], samples=100, delta=0.5, r_min=0.05, seed=1, topology=(gr.eu, gr.ev))
+    assert 0 <= g["w1_arg"] < 100 and g["w1"][g["w1_arg"]] == g["w1"].max()
+    for k in (g["w1_arg"], 17):
+        say(f"[gpu]   oracle sample {k}")
+        o = oracle_w1(res["Q"], gr.eu, gr.ev, 100, 0.5, 0.05, 1, only=[k])
+        assert g["w1"][k] == pytest.approx(o[k][0], rel=1e-11)
+    # on a graph metric the moved mass (total variation) costs at least 1 and at most the diameter per unit
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    D = shortest_path(coo_matrix((np.ones(gr.m), (gr.eu, gr.ev)), shape=(gr.n, gr.n)), directed=False,
+                      unweighted=True)
+    assert np.all(g["w1"] >= g["tv"] * (1 - 1e-12)) and np.all(g["w1"] <= D.max() * g["tv"] * (1 + 1e-12))
+
+
+def test_topology_arguments(ctx):
+    n = 6
+    Q0 = random_kernel(n, 1)
+    eu, ev = connected_graph(n, 2, 1)
+    bad = [(np.array([0, 2], np.int32), np.array([1, 3], np.int32)),      # disconnected
+           (ev, eu),                                                      # eu > ev
+           (eu[::-1].copy(), ev[::-1].copy()),                            # not increasing
+           (np.array([0, 1, 2, 3, 4, 4], np.int32), np.array([1, 2, 3, 4, 5, 6], np.int32))]   # out of range
+    for t in bad:
+        with pytest.raises(amc.AmcError) as ei:
+            amc.robust(ctx, Q0, samples=3, topology=t)
+        assert ei.value.rc == amc.E_INVALID_ARG
+    N = amc.MAX_W1_N + 1
+    Qb = np.zeros((N, N))
+    Qb[np.arange(N), (np.arange(N) + 1) % N] = 0.5
+    path = (np.arange(N - 1, dtype=np.int32), np.arange(1, N, dtype=np.int32))
+    with pytest.raises(amc.AmcError) as ei:
+        amc.robust(ctx, Qb, samples=1, topology=path)
+    assert ei.value.rc == amc.E_UNSUPPORTED
+    # no samples: nothing to measure, no maximiser
+    g = amc.robust(ctx, Q0, samples=0, topology=(eu, ev))
+    assert g["w1_arg"] == -1
