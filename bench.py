@@ -85,6 +85,11 @@ def run_bench(args):
         pool = wl.pool if wl.pool is not None else W.pool(g.n, 50, 1)
         gamma = wl.reward if wl.reward is not None else W.rewards(g.n, pool, 0.5, 2.0, 1)
         q.update(topk=args.topk, pool=pool, gamma=gamma)
+        if args.clique_pool > 0:
+            # structure-constrained selection: W = the best 3-cliques by degree
+            # sum, fallback to the smallest vertex of the first one
+            pool, fb, _ = W.clique_pool(g, args.clique_pool)
+            q.update(pool=pool, fb_node=fb, reward=None, gamma=None)
     model = wl.model()
     for _ in range(args.warmup):
         amc.run(ctx, G, model, **q)
@@ -143,6 +148,10 @@ def run_bench(args):
         out["topk_stage"] = {"k": args.topk, "pool": int(len(q["pool"])), "ms": tk, "bytes_read": tb,
                              "GBps": tb / (tk * 1e-3) / 1e9, "b_k": last["b_k"], "b_kw": last["b_kw"],
                              "share_of_step": tk / (dt / args.steps * 1e3)}
+        if args.clique_pool > 0:
+            out["topk_stage"].update({"clique_pool": args.clique_pool, "fb_node": int(q["fb_node"]),
+                                      "m_w_fb": last["m_w_fb"], "c_fb": last["c_fb"], "E_T_fb": last["E_T_fb"],
+                                      "top5_b_fb": np.argsort(-last["b_fb"], kind="stable")[:5].tolist()})
     if args.robust > 0:
         # robust tail on the estimated kernel: (samples + 2) Gauss-Jordan
         # inversions (2 n^3 flops each) and two n x n products (2 n^3 each)
@@ -175,7 +184,8 @@ def run_bench(args):
                             "widest_interval": float((bs["hi"] - bs["lo"]).max())}
     if args.stability > 0:
         # rank-stability check: Top-k by b at M = R / 2 and at 2M = R
-        qs = {k: v for k, v in q.items() if k not in ("pool", "reward", "topk", "gamma", "flags", "cert_topk")}
+        qs = {k: v for k, v in q.items()
+              if k not in ("pool", "reward", "topk", "gamma", "flags", "cert_topk", "fb_node")}
         qs["R"] = max(wl.R // 2, 1)
         if args.dist32:
             qs["flags"] = amc.DIST32
@@ -398,6 +408,8 @@ def main():
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
+    ap.add_argument("--clique-pool", dest="clique_pool", type=int, default=0,
+                    help="with --topk: pool = the best 3-cliques by degree sum, with the fallback inside it")
     ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
     ap.add_argument("--robust", type=int, default=0, help="also run the robust tail with this many sampled kernels")
     ap.add_argument("--bootstrap", type=int, default=0, help="also bootstrap b with this many replicates")

@@ -152,8 +152,10 @@ typedef struct amc_query {
     const double *gamma;        /* node values gamma (n, >= 0) or NULL for 1         */
     /* Fallback kernel P^{W,fb} (Section 7.3) and censoring (Section 7.4),
      * with AMC_FALLBACK: fb_node = v_fb (needs a pool), fb_set = V_fb
-     * (fb_set_size vertices, disjoint from W, containing fb_node; NULL =
-     * {fb_node}). */
+     * (fb_set_size vertices, disjoint from W, containing fb_node).  fb_set =
+     * NULL takes V_fb = {fb_node}, and then fb_node may lie in W, as in the
+     * structure-constrained experiment of Section 9 (v_fb = the smallest
+     * vertex of the first chosen 3-clique). */
     int32_t fb_node;
     const int32_t *fb_set;
     int32_t fb_set_size;

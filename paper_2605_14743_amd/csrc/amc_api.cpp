@@ -341,7 +341,8 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
             if (!(q->gamma[i] >= 0.0) || !std::isfinite(q->gamma[i])) return AMC_E_INVALID_ARG;
     if (q->flags & AMC_FALLBACK) {
         if (q->fb_node < 0 || q->fb_node >= n) return AMC_E_INVALID_ARG;
-        // a fallback needs a pool, and V_fb holds v_fb and no pool member
+        // a fallback needs a pool; an explicit V_fb holds v_fb and no pool
+        // member, while V_fb = {v_fb} may sit inside the pool (Section 9)
         if (q->pool_size <= 0) return AMC_E_INVALID_ARG;
         if (q->fb_set_size < 0 || (q->fb_set_size > 0 && !q->fb_set)) return AMC_E_INVALID_ARG;
         std::vector<uint8_t> inW((size_t)n, 0), inF((size_t)n, 0);
@@ -354,8 +355,9 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
         bool has_node = q->fb_set_size == 0;
         for (int k = 0; k < q->fb_set_size; ++k) has_node |= q->fb_set[k] == q->fb_node;
         if (!has_node) return AMC_E_INVALID_ARG;
-        for (int v = 0; v < n; ++v)
-            if (inW[v] && inF[v]) return AMC_E_INVALID_ARG;
+        if (q->fb_set_size > 0)
+            for (int v = 0; v < n; ++v)
+                if (inW[v] && inF[v]) return AMC_E_INVALID_ARG;
     }
     if (q->hop_radius < 0) return AMC_E_INVALID_ARG;
     if ((q->flags & AMC_DIST32) && (q->flags & AMC_DIST16)) return AMC_E_INVALID_ARG;

@@ -195,6 +195,30 @@ def rewards(n: int, members: np.ndarray, lo: float, hi: float, seed: int) -> np.
     return f
 
 
+def clique_pool(g: Graph, S: int = 8) -> tuple[np.ndarray, int, list]:
+    """Target pool of the structure-constrained experiment (Section 9): every
+    3-clique {a < b < c} of the base graph scored by its degree sum, the S
+    best taken (ties to the lexicographically smaller triple); W = their
+    union (sorted), the fallback v_fb = the smallest vertex of the first
+    chosen clique.  Returns (W, v_fb, chosen triples)."""
+    deg = g.degrees()
+    nbr = [set() for _ in range(g.n)]
+    for a, b in zip(g.eu.tolist(), g.ev.tolist()):
+        nbr[a].add(b)
+        nbr[b].add(a)
+    tri = []
+    for a, b in zip(g.eu.tolist(), g.ev.tolist()):           # a < b
+        for c in sorted(nbr[a] & nbr[b]):
+            if c > b:
+                tri.append((-int(deg[a] + deg[b] + deg[c]), a, b, c))
+    tri.sort()
+    chosen = [t[1:] for t in tri[:S]]
+    if not chosen:
+        return np.zeros(0, dtype=np.int32), -1, []
+    W = np.array(sorted({v for t in chosen for v in t}), dtype=np.int32)
+    return W, int(chosen[0][0]), chosen
+
+
 # ----------------------------------------------------------------------------- worked examples of the paper
 def two_cliques_bridge() -> Graph:
     """Two 4-cliques {1,2,3,4}, {6,7,8,9} joined by the path 1-5-6 (Fig. 1);

@@ -121,12 +121,32 @@ def test_er5000_sampled_topk(ctx):
     check(res, ref, 1, "er5000")
 
 
+@pytest.mark.parametrize("S,k", [(3, 3), (8, 20)])
+def test_clique_pool_with_fallback_inside_the_pool(ctx, S, k):
+    # structure-constrained selection (Section 9): W = the S best 3-cliques by
+    # degree sum, v_fb = the smallest vertex of the first one (inside W)
+    g = W.ws_graph(60, 6, 0.1, 3)
+    pool, fb, chosen = W.clique_pool(g, S)
+    assert len(chosen) == S and fb in pool
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 5}
+    res, ref = run_both(ctx, g, model, 400, topk=k, pool=pool, fb=fb, seed=5)
+    check(res, ref, 400, f"cliques S={S} k={k}")
+    t = O.tail(ref["counts"], 400, pool=pool, counts_w=ref["counts_w"], psi=ref["psi"], psi_w=ref["psi_w"],
+               fb_node=fb, fb_set=np.array([fb]))
+    close(res["b_w"], t["b_w"], what="b_w")
+    close(res["b_fb"], t["b_fb"], what="b_fb")
+    close(res["b_cens"], t["b_cens"], what="b_cens")
+    assert res["m_w_fb"] == pytest.approx(t["m_w_fb"], rel=TOL)
+    assert res["c_fb"] == pytest.approx(t["c_fb"], rel=TOL)
+    # every step lands in W or absorbs: the pool mass is everything off the initial spread
+    assert np.all(res["counts_w"][:, np.setdiff1d(np.arange(g.n), pool)] == 0)
+
+
 def test_topk_invalid_arguments(ctx):
     g = W.er_graph(12, 0.4, 1)
     G = amc.Graph(ctx, g.n, g.eu, g.ev)
     pool = np.array([1, 2, 3])
     for bad in ({"topk": amc.MAX_TOPK + 1}, {"topk": -1}, {"topk": 2, "gamma": -np.ones(12)},
-                {"pool": pool, "fb_node": 2},                      # v_fb inside W
                 {"fb_node": 4},                                    # fallback without a pool
                 {"pool": pool, "fb_node": 4, "fb_set": [5, 6]},    # v_fb outside V_fb
                 {"pool": pool, "fb_node": 4, "fb_set": [4, 1]},    # V_fb meets W
