@@ -45,6 +45,38 @@ def algorithmic_bytes(st: dict) -> int:
     return 8 * st["sum_DK"] + 32 * st["sum_AK"] + 64 * st["sum_nK"]
 
 
+def _cpu_worker(task):
+    """One oracle process over its own realization range (all-cores leg)."""
+    name, r0, budget_s = task
+    import oracle as O
+    from paper_2605_14743_amd import workloads as W
+    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
+          "cooc77": W.config_cooc77}[name]()
+    g = wl.graph
+    R = units = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        res = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=2, r_begin=r0 + R, alpha=wl.alpha, k_min=wl.k_min,
+                      want_bsum=False, want_center=False, hop_radius=wl.hop_radius, **wl.model())
+        units += res["stats"]["units"]
+        R += 2
+    return units, time.perf_counter() - t0
+
+
+def cpu_all_cores(name: str, procs: int, budget_s: float) -> dict:
+    """The oracle in `procs` fresh processes (spawned, never forked from this
+    GPU process) over disjoint realization ranges; rate = all units / the
+    slowest process's time."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(procs) as pool:
+        out = pool.map(_cpu_worker, [(name, 1_000_000 * (k + 1), budget_s) for k in range(procs)])
+    units = sum(u for u, _ in out)
+    dt = max(t for _, t in out)
+    return {"value": units / dt, "unit": "realization-sources/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} processes, {units} single-source passes over disjoint realization ranges "
+                      f"({dt:.1f} s)"}
+
+
 def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
     import oracle as O
     g = wl.graph
@@ -210,6 +242,8 @@ def run_bench(args):
                             "batched_over_plain": value / pv}
     if args.cpu_s > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_s)
+        if args.cpu_procs > 1:
+            out["cpu_baseline"]["all_cores"] = cpu_all_cores(args.workload, args.cpu_procs, args.cpu_s)
     tr = traffic_record() if args.workload == "ws1000" and not args.R else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["sweep_bytes_per_launch"]
@@ -407,6 +441,8 @@ def main():
     ap.add_argument("--dist32", action="store_true", help="32-bit distance entries (comparison runs)")
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
+    ap.add_argument("--cpu-procs", dest="cpu_procs", type=int, default=1,
+                    help="also time the oracle in this many processes over disjoint realization ranges")
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
     ap.add_argument("--clique-pool", dest="clique_pool", type=int, default=0,
                     help="with --topk: pool = the best 3-cliques by degree sum, with the fallback inside it")
