@@ -463,8 +463,8 @@ def main():
     ap.add_argument("--logR-hi", dest="logR_hi", type=int, default=14)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(realizations shard across GPUs by range; see the design notes).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep would shard across "
+              f"GPUs by realization range, with one all-reduce of the counts).", file=sys.stderr)
         sys.exit(2)
     if os.environ.get("WORLD_SIZE", "1") != "1":
         print("bench.py runs as a single process on one GPU", file=sys.stderr)
