@@ -13,8 +13,7 @@
  * Uncertainty: An Absorbing Markov Chain Approach".  Section / equation
  * citations below refer to that paper.
  *
- * Readings of points the paper leaves open (each is listed in the design
- * notes of the repository):
+ * Readings of points the paper leaves open:
  *   - realizations are drawn with Philox4x32-10 keyed by the 64-bit seed; the
  *     edge (u<v) of realization r uses counter (r, u, v, 0), the exogenous stop
  *     coin of anchor i uses counter (r, i, 0xFFFFFFFF, 1);
