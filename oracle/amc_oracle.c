@@ -23,7 +23,10 @@
  *   - every realization serves every anchor (one realization count R = M);
  *   - the deterministic tie rule is "smallest index inside a relative tie
  *     band": v is a co-maximiser of a set when max - B_v <= tau*max(max, 1);
- *   - the floor on an empty absorption column is eta (default 0.1/sqrt(R)).
+ *   - the floor on an empty absorption column is eta (default 0.1/sqrt(R));
+ *   - the bootstrap redraws each row's R draws from Philox4x32-10 at counter
+ *     (replicate, row, t / 4, 0x80000004), index (word * R) >> 32;
+ *   - W1 of the robust experiment uses the hop metric of the base topology.
  *
  * Parity pins: every exported function below is pinned by the CPU tests
  * (tests/test_oracle_*.py) against closed forms, brute force, the values the
