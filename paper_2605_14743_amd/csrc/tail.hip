@@ -58,42 +58,33 @@ __global__ void k_from_Q(int n, const double *Q, double *r, double *A) {
 
 // The four steps take a batch of matrices A + z * stride, z = blockIdx.z.
 // (a) invert the diagonal block A[k0:k1, k0:k1] in place (unblocked
-// Gauss-Jordan without pivoting); flags a zero pivot.
-__global__ void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+// Gauss-Jordan without pivoting); flags a zero pivot.  One thread per entry
+// of the NB x NB block (padded with the identity, which every pivot step
+// leaves unchanged), the entry kept in a register across the pivots.
+__global__ __launch_bounds__(NB * NB) void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
     A += (size_t)blockIdx.z * stride;
     __shared__ double M[NB][NB + 1];
     const int kb = min(NB, n - k0);
-    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
-        const int i = t / NB, j = t % NB;
-        M[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-    }
+    const int i = (int)threadIdx.x / NB, j = (int)threadIdx.x % NB;
+    const bool in = i < kb && j < kb;
+    double x = in ? A[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+    M[i][j] = x;
     __syncthreads();
     for (int p = 0; p < kb; ++p) {
-        const double piv = M[p][p];
-        __syncthreads();
+        const double piv = M[p][p], row = M[p][j], col = M[i][p];
+        __syncthreads();   // every read of step p is done before its writes
         if (piv == 0.0) {
             if (threadIdx.x == 0) atomicOr(err, 2);
             return;
         }
         const double d = 1.0 / piv;
-        // row p scaled (except column p)
-        for (int j = threadIdx.x; j < kb; j += blockDim.x)
-            if (j != p) M[p][j] *= d;
-        __syncthreads();
-        for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
-            const int i = t / kb, j = t % kb;
-            if (i != p && j != p) M[i][j] -= M[i][p] * M[p][j];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < kb; i += blockDim.x)
-            if (i != p) M[i][p] = -M[i][p] * d;
-        if (threadIdx.x == 0) M[p][p] = d;
+        if (i == p) x = j == p ? d : row * d;             // pivot row scaled, pivot replaced by its inverse
+        else if (j == p) x = -col * d;                    // pivot column
+        else x -= col * (row * d);                        // the rest, against the scaled pivot row
+        M[i][j] = x;
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
-        const int i = t / kb, j = t % kb;
-        A[(size_t)(k0 + i) * n + k0 + j] = M[i][j];
-    }
+    if (in) A[(size_t)(k0 + i) * n + k0 + j] = x;
 }
 
 // (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block.
@@ -402,7 +393,7 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
 hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
     const int tiles = (n + TT - 1) / TT;
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(256), 0, st, n, A, stride, k0, err);
+        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(NB * NB), 0, st, n, A, stride, k0, err);
         hipLaunchKernelGGL(k_gj_rowpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_colpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
