@@ -41,13 +41,17 @@ __device__ __forceinline__ uint64_t w1_label(int64_t dist, uint32_t hops) {
 }
 __device__ __forceinline__ int64_t w1_dist(uint64_t key) { return (int64_t)(key >> 32) - (int64_t)kDistBias; }
 
-// cost of traversing edge e from its first endpoint (fwd) or its second
-__device__ __forceinline__ int64_t w1_cost(double fe, bool fwd) {
-    return fwd ? (fe < 0.0 ? -1 : 1) : (fe > 0.0 ? -1 : 1);
-}
+// cost of traversing an edge whose flow has sign sg (-1, 0, +1) from its
+// first endpoint (fwd) or from its second
+__device__ __forceinline__ int64_t w1_cost(int sg, bool fwd) { return fwd ? (sg < 0 ? -1 : 1) : (sg > 0 ? -1 : 1); }
+__device__ __forceinline__ int w1_sign(double f) { return f > 0.0 ? 1 : (f < 0.0 ? -1 : 0); }
 
 }  // namespace
 
+// CACHED: the edge ends (packed 16 + 16 bits) and the signs of the flows sit
+// in LDS next to the per-node arrays (when 20 n + 5 m bytes fit), otherwise
+// the ends are read from HBM and the signs from the flows.
+template <bool CACHED>
 __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *eu, const int32_t *ev,
                                                    const int32_t *rp, const int32_t *inc, const double *P,
                                                    const double *q, double *fscr, double *w1, int *err) {
@@ -55,6 +59,8 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     double *ex = w1_smem;                                   // n: remaining surplus (> 0) / deficit (< 0)
     uint64_t *key = (uint64_t *)(ex + n);                   // n: packed (distance, hops) labels
     int32_t *path = (int32_t *)(key + n);                   // n: arcs of the current path (2e + dir)
+    uint32_t *ends = (uint32_t *)(path + n);                // m (CACHED): eu | ev << 16
+    int8_t *sgn = (int8_t *)(ends + (CACHED ? m : 0));      // m (CACHED): sign of the flow
     __shared__ int s_any_src, s_any_snk, s_changed, s_plen, s_src, s_stop;
     __shared__ uint64_t s_best;
     __shared__ uint32_t s_pick;
@@ -63,7 +69,16 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     const double *p = P + (size_t)k * n;
     double *f = fscr + (size_t)k * m;
     for (int v = tid; v < n; v += kW1Threads) ex[v] = p[v] - q[v];
-    for (int e = tid; e < m; e += kW1Threads) f[e] = 0.0;
+    for (int e = tid; e < m; e += kW1Threads) {
+        f[e] = 0.0;
+        if constexpr (CACHED) {
+            ends[e] = (uint32_t)eu[e] | ((uint32_t)ev[e] << 16);
+            sgn[e] = 0;
+        }
+    }
+    auto end_a = [&](int e) { return CACHED ? (int)(ends[e] & 0xFFFFu) : eu[e]; };
+    auto end_b = [&](int e) { return CACHED ? (int)(ends[e] >> 16) : ev[e]; };
+    auto sign_of = [&](int e) { return CACHED ? (int)sgn[e] : w1_sign(f[e]); };
     if (tid == 0) s_stop = 0;
     __syncthreads();
     const long max_rounds = 16L * ((long)n + m) + 16;
@@ -98,8 +113,8 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             __syncthreads();
             bool ch = false;
             for (int e = tid; e < m; e += kW1Threads) {
-                const int a = eu[e], b = ev[e];
-                const double fe = f[e];
+                const int a = end_a(e), b = end_b(e);
+                const int fe = sign_of(e);
                 const uint64_t ka = key[a], kb = key[b];
                 if (ka != kNoLabel) {
                     const uint64_t c = w1_label(w1_dist(ka) + w1_cost(fe, true), (uint32_t)ka + 1u);
@@ -164,11 +179,11 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             __syncthreads();
             for (int j = rp[x] + tid; j < rp[x + 1]; j += kW1Threads) {
                 const int e = inc[j];
-                const bool into_fwd = ev[e] == x;    // arc eu -> ev arrives at x
-                const int y = into_fwd ? eu[e] : ev[e];
+                const bool into_fwd = end_b(e) == x; // arc eu -> ev arrives at x
+                const int y = into_fwd ? end_a(e) : end_b(e);
                 const uint64_t ky = key[y];
                 if (ky != kNoLabel &&
-                    w1_label(w1_dist(ky) + w1_cost(f[e], into_fwd), (uint32_t)ky + 1u) == kx)
+                    w1_label(w1_dist(ky) + w1_cost(sign_of(e), into_fwd), (uint32_t)ky + 1u) == kx)
                     atomicMin(&s_pick, (uint32_t)j);
             }
             __syncthreads();
@@ -179,9 +194,9 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
                     s_stop = 1;
                 } else {
                     const int e = inc[j];
-                    const bool into_fwd = ev[e] == x;
+                    const bool into_fwd = end_b(e) == x;
                     path[s_plen++] = 2 * e + (into_fwd ? 0 : 1);
-                    s_src = into_fwd ? eu[e] : ev[e];
+                    s_src = into_fwd ? end_a(e) : end_b(e);
                 }
             }
             __syncthreads();
@@ -204,6 +219,7 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             for (int i = 0; i < s_plen; ++i) {
                 const int e = path[i] >> 1;
                 f[e] += (path[i] & 1) == 0 ? th : -th;
+                if constexpr (CACHED) sgn[e] = (int8_t)w1_sign(f[e]);
             }
             ex[s] -= th;
             ex[t] += th;
@@ -227,8 +243,13 @@ size_t w1_lds_bytes(int n) { return 20 * (size_t)n; }
 hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *rp, const int32_t *inc,
                      int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
                      hipStream_t st) {
-    hipLaunchKernelGGL(k_w1, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, rp, inc, P, q, fscr,
-                       w1, err);
+    const size_t cached = w1_lds_bytes(n) + 5 * (size_t)m;
+    if (cached <= 60000)
+        hipLaunchKernelGGL(k_w1<true>, dim3(batch), dim3(kW1Threads), cached, st, n, m, eu, ev, rp, inc, P, q, fscr,
+                           w1, err);
+    else
+        hipLaunchKernelGGL(k_w1<false>, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, rp, inc, P,
+                           q, fscr, w1, err);
     return hipGetLastError();
 }
 

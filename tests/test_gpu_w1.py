@@ -96,6 +96,22 @@ def test_tree_topology(ctx):
         assert g["w1"][k] == pytest.approx(expect, rel=1e-11)
 
 
+def test_long_path_past_the_lds_cache(ctx):
+    # n = 2500 on a path: 20 n + 5 m bytes exceed the LDS cache of the edges, so
+    # the ends and flow signs are read from HBM; W1 of the maximiser against the
+    # cumulative-sum closed form
+    n = 2500
+    Q0 = random_kernel(n, 9, density=0.004)
+    eu = np.arange(n - 1, dtype=np.int32)
+    ev = eu + 1
+    say("[gpu] robust w1 on a path of 2500 vertices")
+    g = amc.robust(ctx, Q0, samples=3, delta=0.5, r_min=0.05, seed=2, topology=(eu, ev))
+    k = g["w1_arg"]
+    expect = np.abs(np.cumsum(g["b_w1"] - g["b0"])[:-1]).sum()
+    assert g["w1"][k] == pytest.approx(expect, rel=1e-10)
+    assert np.all(g["w1"] >= g["tv"] * (1 - 1e-12))
+
+
 def test_ws1000_estimated_kernel(ctx):
     # the kernel estimated from the WS(1000) run, its own base topology, 100 samples
     wl = W.config_ws1000()
