@@ -375,7 +375,8 @@ def run_traj(args):
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}-trajectories", "episodes": E, "max_steps": args.max_steps},
         "kernel_ms": tr["sweep_ms"], "realization_sources_per_s": tr["sources"] / (tr["sweep_ms"] * 1e-3),
-        "steps": tr["total_steps"], "mean_T": tr["total_steps"] / E, "truncated": tr["truncated"],
+        "steps": tr["total_steps"], "mean_T": tr["total_steps"] / E, "max_T": int(tr["lengths"].max()),
+        "truncated": tr["truncated"],
         "row_wise_R": R, "row_wise_E_T": row["E_T"],
         "b_hat_vs_row_b": {"max_abs": float(diff.max()), "l1": float(diff.sum()),
                            "b_row_max": float(row["b"].max())},
