@@ -8,21 +8,25 @@
 //
 // On a graph metric, W1(p, q) is the cost of the cheapest flow that moves the
 // surplus p - q over the edges at cost 1 per unit and edge.  The workgroup
-// solves that transshipment by successive shortest paths:
+// solves that transshipment by successive shortest paths, in phases:
 //   - the residual graph: an edge carrying flow f from u to v offers v -> u at
 //     cost -1 (capacity f) and u -> v at cost +1; a flow-free edge offers both
 //     directions at +1;
-//   - labels (distance, hops) from every node with surplus, by parallel
-//     Bellman-Ford passes over the edges with 64-bit LDS minima on the packed
-//     label until a pass changes nothing (at most n + 1 passes: no residual
-//     cycle is negative while the flow is optimal for what it has moved, and
-//     the lexicographic label makes the shortest walks simple);
-//   - the nearest node with deficit (smallest index among the nearest) and
-//     its path back to a surplus node, found edge by edge through arcs that
-//     realise the label (the hop count falls by one per edge, so the walk
-//     ends within n steps);
-//   - the largest push that overdraws neither the surplus, the deficit, nor a
-//     cancelled flow.  Each push zeroes one of those exactly (x + (-x) = 0).
+//   - a phase labels every node with (distance, hops) from the nodes with
+//     surplus, by parallel Bellman-Ford passes over the edges with 64-bit LDS
+//     minima on the packed label until a pass changes nothing (at most n + 1
+//     passes: no residual cycle is negative while the flow is optimal for what
+//     it has moved, and the lexicographic label makes the shortest walks
+//     simple);
+//   - then, while a node with deficit at the smallest distance D* remains
+//     (smallest index first), its path back to a surplus node is found edge by
+//     edge through arcs that realise the labels under the current flow (the
+//     hop count falls by one per edge), and the largest push that overdraws
+//     neither the surplus, the deficit, nor a cancelled flow is made; each
+//     push zeroes one of those exactly (x + (-x) = 0).  A push along such arcs
+//     leaves the labels a feasible potential (the reverse of a realising arc
+//     realises the label back), so every later path of length D* is still a
+//     shortest one; a deficit node whose walk fails is left to the next phase.
 // W1 is the sum of |flow| over the edges once no surplus or no deficit is
 // left.  Every loop has a bound; exceeding one sets bit 4 of *err.
 #include "amc_dev.hpp"
@@ -49,8 +53,8 @@ __device__ __forceinline__ int w1_sign(double f) { return f > 0.0 ? 1 : (f < 0.0
 }  // namespace
 
 // CACHED: the edge ends (packed 16 + 16 bits) and the signs of the flows sit
-// in LDS next to the per-node arrays (when 20 n + 5 m bytes fit), otherwise
-// the ends are read from HBM and the signs from the flows.
+// in LDS next to the per-node arrays (when they fit), otherwise the ends are
+// read from HBM and the signs from the flows.
 template <bool CACHED>
 __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *eu, const int32_t *ev,
                                                    const int32_t *rp, const int32_t *inc, const double *P,
@@ -59,12 +63,13 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     double *ex = w1_smem;                                   // n: remaining surplus (> 0) / deficit (< 0)
     uint64_t *key = (uint64_t *)(ex + n);                   // n: packed (distance, hops) labels
     int32_t *path = (int32_t *)(key + n);                   // n: arcs of the current path (2e + dir)
-    uint32_t *ends = (uint32_t *)(path + n);                // m (CACHED): eu | ev << 16
+    uint8_t *tried = (uint8_t *)(path + n);                 // n: deficit nodes whose walk failed this phase
+    uint32_t *ends = (uint32_t *)(tried + ((n + 3) & ~3));  // m (CACHED): eu | ev << 16
     int8_t *sgn = (int8_t *)(ends + (CACHED ? m : 0));      // m (CACHED): sign of the flow
-    __shared__ int s_any_src, s_any_snk, s_changed, s_plen, s_src, s_stop;
+    __shared__ int s_any_src, s_any_snk, s_changed, s_plen, s_src, s_stop, s_ok;
     __shared__ uint64_t s_best;
-    __shared__ uint32_t s_pick;
-    __shared__ double s_red[kW1Threads];
+    __shared__ uint32_t s_pick, s_sink;
+    __shared__ double s_part[kW1Threads / 64];
     const int tid = threadIdx.x, k = blockIdx.x;
     const double *p = P + (size_t)k * n;
     double *f = fscr + (size_t)k * m;
@@ -81,8 +86,9 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     auto sign_of = [&](int e) { return CACHED ? (int)sgn[e] : w1_sign(f[e]); };
     if (tid == 0) s_stop = 0;
     __syncthreads();
-    const long max_rounds = 16L * ((long)n + m) + 16;
-    for (long round = 0;; ++round) {
+    const long max_phases = 16L * ((long)n + m) + 16;
+    const long max_tries = 3L * n + m + 8;                  // pushes and failed walks of one phase
+    for (long phase = 0;; ++phase) {
         if (tid == 0) {
             s_any_src = 0;
             s_any_snk = 0;
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
         if (snk) s_any_snk = 1;
         __syncthreads();
         if (!s_any_src || !s_any_snk) break;
-        if (round >= max_rounds) {
+        if (phase >= max_phases) {
             if (tid == 0) {
                 atomicOr(err, 4);
                 s_stop = 1;
@@ -105,23 +111,25 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             break;
         }
         // labels from every node with surplus
-        for (int v = tid; v < n; v += kW1Threads) key[v] = ex[v] > 0.0 ? w1_label(0, 0) : kNoLabel;
+        for (int v = tid; v < n; v += kW1Threads) {
+            key[v] = ex[v] > 0.0 ? w1_label(0, 0) : kNoLabel;
+            tried[v] = 0;
+        }
         __syncthreads();
-        int pass = 0;
-        for (;; ++pass) {
+        for (int pass = 0;; ++pass) {
             if (tid == 0) s_changed = 0;
             __syncthreads();
             bool ch = false;
             for (int e = tid; e < m; e += kW1Threads) {
                 const int a = end_a(e), b = end_b(e);
-                const int fe = sign_of(e);
+                const int sg = sign_of(e);
                 const uint64_t ka = key[a], kb = key[b];
                 if (ka != kNoLabel) {
-                    const uint64_t c = w1_label(w1_dist(ka) + w1_cost(fe, true), (uint32_t)ka + 1u);
+                    const uint64_t c = w1_label(w1_dist(ka) + w1_cost(sg, true), (uint32_t)ka + 1u);
                     if (c < kb && atomicMin((unsigned long long *)&key[b], (unsigned long long)c) > c) ch = true;
                 }
                 if (kb != kNoLabel) {
-                    const uint64_t c = w1_label(w1_dist(kb) + w1_cost(fe, false), (uint32_t)kb + 1u);
+                    const uint64_t c = w1_label(w1_dist(kb) + w1_cost(sg, false), (uint32_t)kb + 1u);
                     if (c < ka && atomicMin((unsigned long long *)&key[a], (unsigned long long)c) > c) ch = true;
                 }
             }
@@ -140,15 +148,12 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
         }
         __syncthreads();
         if (s_stop) break;
-        // the nearest deficit node, smallest index among the nearest
+        // D*: the smallest distance of a deficit node
         if (tid == 0) s_best = kNoLabel;
         __syncthreads();
-        for (int v = tid; v < n; v += kW1Threads) {
-            if (ex[v] < 0.0 && key[v] != kNoLabel) {
-                const uint64_t c = ((key[v] >> 32) << 32) | (uint32_t)v;
-                atomicMin((unsigned long long *)&s_best, (unsigned long long)c);
-            }
-        }
+        for (int v = tid; v < n; v += kW1Threads)
+            if (ex[v] < 0.0 && key[v] != kNoLabel)
+                atomicMin((unsigned long long *)&s_best, (unsigned long long)(key[v] | 0xFFFFFFFFull));
         __syncthreads();
         if (s_best == kNoLabel) {   // surplus that reaches no deficit: components out of balance
             if (tid == 0) {
@@ -157,94 +162,125 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             }
             break;
         }
-        const int t = (int)(uint32_t)s_best;
-        // walk back along arcs that realise the labels
-        if (tid == 0) {
-            s_plen = 0;
-            s_src = t;
-        }
-        __syncthreads();
-        for (int step = 0;; ++step) {
-            const int x = s_src;
-            const uint64_t kx = key[x];
-            if ((uint32_t)kx == 0u) break;          // hop count 0: a node with surplus
-            if (step >= n) {                        // a path has at most n - 1 edges
+        const uint32_t dhi = (uint32_t)(s_best >> 32);
+        int pushes = 0;
+        for (long attempt = 0;; ++attempt) {
+            if (attempt >= max_tries) {
                 if (tid == 0) {
                     atomicOr(err, 4);
                     s_stop = 1;
                 }
                 break;
             }
-            if (tid == 0) s_pick = 0xFFFFFFFFu;
+            // the next deficit node at distance D* (smallest index)
+            if (tid == 0) s_sink = 0xFFFFFFFFu;
             __syncthreads();
-            for (int j = rp[x] + tid; j < rp[x + 1]; j += kW1Threads) {
-                const int e = inc[j];
-                const bool into_fwd = end_b(e) == x; // arc eu -> ev arrives at x
-                const int y = into_fwd ? end_a(e) : end_b(e);
-                const uint64_t ky = key[y];
-                if (ky != kNoLabel &&
-                    w1_label(w1_dist(ky) + w1_cost(sign_of(e), into_fwd), (uint32_t)ky + 1u) == kx)
-                    atomicMin(&s_pick, (uint32_t)j);
+            for (int v = tid; v < n; v += kW1Threads)
+                if (ex[v] < 0.0 && !tried[v] && key[v] != kNoLabel && (uint32_t)(key[v] >> 32) == dhi)
+                    atomicMin(&s_sink, (uint32_t)v);
+            __syncthreads();
+            const uint32_t tsel = s_sink;
+            if (tsel == 0xFFFFFFFFu) break;
+            const int t = (int)tsel;
+            // walk back along arcs that realise the labels under the current flow
+            if (tid == 0) {
+                s_plen = 0;
+                s_src = t;
+                s_ok = 1;
             }
             __syncthreads();
-            if (tid == 0) {
-                const uint32_t j = s_pick;
-                if (j == 0xFFFFFFFFu) {
-                    atomicOr(err, 4);
-                    s_stop = 1;
-                } else {
+            for (int step = 0;; ++step) {
+                const int x = s_src;
+                const uint64_t kx = key[x];
+                if ((uint32_t)kx == 0u) break;          // hop count 0: a node that had surplus
+                if (step >= n) {                        // a path has at most n - 1 edges
+                    if (tid == 0) s_ok = 0;
+                    break;
+                }
+                if (tid == 0) s_pick = 0xFFFFFFFFu;
+                __syncthreads();
+                for (int j = rp[x] + tid; j < rp[x + 1]; j += kW1Threads) {
                     const int e = inc[j];
-                    const bool into_fwd = end_b(e) == x;
-                    path[s_plen++] = 2 * e + (into_fwd ? 0 : 1);
-                    s_src = into_fwd ? end_a(e) : end_b(e);
+                    const bool into_fwd = end_b(e) == x; // arc eu -> ev arrives at x
+                    const int y = into_fwd ? end_a(e) : end_b(e);
+                    const uint64_t ky = key[y];
+                    if (ky != kNoLabel &&
+                        w1_label(w1_dist(ky) + w1_cost(sign_of(e), into_fwd), (uint32_t)ky + 1u) == kx)
+                        atomicMin(&s_pick, (uint32_t)j);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    const uint32_t j = s_pick;
+                    if (j == 0xFFFFFFFFu) {
+                        s_ok = 0;
+                    } else {
+                        const int e = inc[j];
+                        const bool into_fwd = end_b(e) == x;
+                        path[s_plen++] = 2 * e + (into_fwd ? 0 : 1);
+                        s_src = into_fwd ? end_a(e) : end_b(e);
+                    }
+                }
+                __syncthreads();
+                if (!s_ok) break;
+            }
+            __syncthreads();
+            // push, or leave this deficit node to the next phase
+            if (tid == 0) {
+                const int s = s_src;
+                if (!s_ok || !(ex[s] > 0.0)) {
+                    tried[t] = 1;
+                } else {
+                    double th = -ex[t];
+                    for (int i = 0; i < s_plen; ++i) {
+                        const int e = path[i] >> 1;
+                        const bool fwd = (path[i] & 1) == 0;
+                        const double fe = f[e];
+                        if (fwd && fe < 0.0 && -fe < th) th = -fe;
+                        if (!fwd && fe > 0.0 && fe < th) th = fe;
+                    }
+                    if (ex[s] < th) th = ex[s];
+                    for (int i = 0; i < s_plen; ++i) {
+                        const int e = path[i] >> 1;
+                        f[e] += (path[i] & 1) == 0 ? th : -th;
+                        if constexpr (CACHED) sgn[e] = (int8_t)w1_sign(f[e]);
+                    }
+                    ex[s] -= th;
+                    ex[t] += th;
                 }
             }
             __syncthreads();
-            if (s_stop) break;
+            pushes += s_ok && !tried[t];
         }
         __syncthreads();
         if (s_stop) break;
-        // push
-        if (tid == 0) {
-            const int s = s_src;
-            double th = -ex[t];
-            for (int i = 0; i < s_plen; ++i) {
-                const int e = path[i] >> 1;
-                const bool fwd = (path[i] & 1) == 0;
-                const double fe = f[e];
-                if (fwd && fe < 0.0 && -fe < th) th = -fe;
-                if (!fwd && fe > 0.0 && fe < th) th = fe;
+        if (pushes == 0) {   // the first walk of a phase always succeeds
+            if (tid == 0) {
+                atomicOr(err, 4);
+                s_stop = 1;
             }
-            if (ex[s] < th) th = ex[s];
-            for (int i = 0; i < s_plen; ++i) {
-                const int e = path[i] >> 1;
-                f[e] += (path[i] & 1) == 0 ? th : -th;
-                if constexpr (CACHED) sgn[e] = (int8_t)w1_sign(f[e]);
-            }
-            ex[s] -= th;
-            ex[t] += th;
+            break;
         }
-        __syncthreads();
     }
     __syncthreads();
     double acc = 0.0;
     for (int e = tid; e < m; e += kW1Threads) acc += fabs(f[e]);
-    s_red[tid] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((tid & 63) == 0) s_part[tid >> 6] = acc;
     __syncthreads();
-    for (int s = kW1Threads / 2; s > 0; s >>= 1) {
-        if (tid < s) s_red[tid] += s_red[tid + s];
-        __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kW1Threads / 64; ++w) tot += s_part[w];
+        w1[k] = s_stop ? NAN : tot;
     }
-    if (tid == 0) w1[k] = s_stop ? NAN : s_red[0];
 }
 
-size_t w1_lds_bytes(int n) { return 20 * (size_t)n; }
+size_t w1_lds_bytes(int n) { return 20 * (size_t)n + (((size_t)n + 3) & ~(size_t)3); }
 
 hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *rp, const int32_t *inc,
                      int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
                      hipStream_t st) {
     const size_t cached = w1_lds_bytes(n) + 5 * (size_t)m;
-    if (cached <= 60000)
+    if (cached <= 64000)
         hipLaunchKernelGGL(k_w1<true>, dim3(batch), dim3(kW1Threads), cached, st, n, m, eu, ev, rp, inc, P, q, fscr,
                            w1, err);
     else
