@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 256 * 128 * 2.4        # 78,643 GB/s: 128 B per clock per CU
+VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4    # 614.4 G wave64 instructions/s: 4 SIMDs per CU, 4 cycles each
 
 
 def algorithmic_bytes(st: dict) -> int:
@@ -244,10 +245,18 @@ def run_bench(args):
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_s)
         if args.cpu_procs > 1:
             out["cpu_baseline"]["all_cores"] = cpu_all_cores(args.workload, args.cpu_procs, args.cpu_s)
-    tr = traffic_record() if args.workload == "ws1000" and not args.R else None
+    # the recorded counters belong to the default configuration of this workload
+    default_cfg = not (args.R or args.mode or args.waves or args.tile or args.group or args.dist32 or args.topk)
+    tr = traffic_record() if args.workload == "ws1000" and default_cfg else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["sweep_bytes_per_launch"]
         out["roofline"]["traffic_source"] = tr["source"]
+        if "valu_insts_per_unit" in tr:
+            # VALU issue: wave64 instructions per (r, s) from the SQ counters,
+            # against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction
+            ach = tr["valu_insts_per_unit"] * st["units"] / (k_ms * 1e-3) / 1e9
+            out["roofline"]["alu"] = {"achieved": ach, "peak": VALU_PEAK_GIPS, "unit": "G VALU wave64 instructions/s",
+                                      "frac": ach / VALU_PEAK_GIPS, "source": tr["valu_source"]}
     if args.copy_mib > 0:
         # calibration kernel for the HBM byte counters: a plain device copy of
         # known size on the same stream
