@@ -17,8 +17,11 @@
 
 namespace amc {
 
-constexpr int NB = 32;      // Gauss-Jordan panel width
+constexpr int NB = 64;      // Gauss-Jordan panel width
 constexpr int TT = 64;      // trailing-update tile edge
+constexpr int PT = 32;      // panel-kernel tile edge (keeps their LDS under 64 KB)
+constexpr int KC = 32;      // panel columns staged per pass of the trailing update
+constexpr int kDiagThreads = 1024;  // threads of the diagonal-block inversion
 
 // Empirical kernel of Alg. 2 plus the floor of Section 8.2: when row i never
 // absorbed and eta > 0, P_i,bottom := eta and the transient part is scaled by
@@ -58,54 +61,74 @@ __global__ void k_from_Q(int n, const double *Q, double *r, double *A) {
 
 // The four steps take a batch of matrices A + z * stride, z = blockIdx.z.
 // (a) invert the diagonal block A[k0:k1, k0:k1] in place (unblocked
-// Gauss-Jordan without pivoting); flags a zero pivot.  One thread per entry
-// of the NB x NB block (padded with the identity, which every pivot step
-// leaves unchanged), the entry kept in a register across the pivots.
-__global__ __launch_bounds__(NB * NB) void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+// Gauss-Jordan without pivoting); flags a zero pivot.  Each thread holds
+// NB * NB / kDiagThreads entries of the block (padded with the identity,
+// which every pivot step leaves unchanged) in registers across the pivots.
+__global__ __launch_bounds__(kDiagThreads) void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+    constexpr int PER = NB * NB / kDiagThreads;
     A += (size_t)blockIdx.z * stride;
     __shared__ double M[NB][NB + 1];
     const int kb = min(NB, n - k0);
-    const int i = (int)threadIdx.x / NB, j = (int)threadIdx.x % NB;
-    const bool in = i < kb && j < kb;
-    double x = in ? A[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-    M[i][j] = x;
+    int ii[PER], jj[PER];
+    double x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = (int)threadIdx.x + r * kDiagThreads;
+        ii[r] = t / NB;
+        jj[r] = t % NB;
+        const bool in = ii[r] < kb && jj[r] < kb;
+        x[r] = in ? A[(size_t)(k0 + ii[r]) * n + k0 + jj[r]] : (ii[r] == jj[r] ? 1.0 : 0.0);
+        M[ii[r]][jj[r]] = x[r];
+    }
     __syncthreads();
     for (int p = 0; p < kb; ++p) {
-        const double piv = M[p][p], row = M[p][j], col = M[i][p];
+        const double piv = M[p][p];
+        double row[PER], col[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            row[r] = M[p][jj[r]];
+            col[r] = M[ii[r]][p];
+        }
         __syncthreads();   // every read of step p is done before its writes
         if (piv == 0.0) {
             if (threadIdx.x == 0) atomicOr(err, 2);
             return;
         }
         const double d = 1.0 / piv;
-        if (i == p) x = j == p ? d : row * d;             // pivot row scaled, pivot replaced by its inverse
-        else if (j == p) x = -col * d;                    // pivot column
-        else x -= col * (row * d);                        // the rest, against the scaled pivot row
-        M[i][j] = x;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if (ii[r] == p) x[r] = jj[r] == p ? d : row[r] * d;   // pivot row scaled, pivot replaced by its inverse
+            else if (jj[r] == p) x[r] = -col[r] * d;             // pivot column
+            else x[r] -= col[r] * (row[r] * d);                  // the rest, against the scaled pivot row
+            M[ii[r]][jj[r]] = x[r];
+        }
         __syncthreads();
     }
-    if (in) A[(size_t)(k0 + i) * n + k0 + j] = x;
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+        if (ii[r] < kb && jj[r] < kb) A[(size_t)(k0 + ii[r]) * n + k0 + jj[r]] = x[r];
 }
 
-// (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block.
+// (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block
+// (PT columns per workgroup).
 __global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
     A += (size_t)blockIdx.z * stride;
     __shared__ double Dv[NB][NB + 1];
-    __shared__ double X[NB][TT + 1];
+    __shared__ double X[NB][PT + 1];
     const int kb = min(NB, n - k0);
-    const int j0 = blockIdx.x * TT;
+    const int j0 = blockIdx.x * PT;
     for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
         const int i = t / NB, j = t % NB;
         Dv[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
     }
-    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
-        const int i = t / TT, j = t % TT;
+    for (int t = threadIdx.x; t < NB * PT; t += blockDim.x) {
+        const int i = t / PT, j = t % PT;
         const int c = j0 + j;
         X[i][j] = (i < kb && c < n) ? A[(size_t)(k0 + i) * n + c] : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
-        const int i = t / TT, j = t % TT;
+    for (int t = threadIdx.x; t < NB * PT; t += blockDim.x) {
+        const int i = t / PT, j = t % PT;
         const int c = j0 + j;
         if (i >= kb || c >= n || (c >= k0 && c < k0 + kb)) continue;
         double acc = 0.0;
@@ -115,38 +138,43 @@ __global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
 }
 
 // (c) trailing update: A[i, j] -= A[i, k] A[k, j] for i, j outside the block
-// (A[k, j] already holds the row panel of step (b)).
+// (A[k, j] already holds the row panel of step (b)); the NB panel columns are
+// staged KC at a time.
 __global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stride, int k0) {
     A += (size_t)blockIdx.z * stride;
-    __shared__ double Ap[TT][NB + 1];
-    __shared__ double Bp[NB][TT + 1];
+    __shared__ double Ap[TT][KC + 1];
+    __shared__ double Bp[KC][TT + 1];
     const int kb = min(NB, n - k0);
     const int i0 = blockIdx.y * TT, j0 = blockIdx.x * TT;
-    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
-        const int i = t / NB, p = t % NB;
-        Ap[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
-    }
-    for (int t = threadIdx.x; t < NB * TT; t += blockDim.x) {
-        const int p = t / TT, j = t % TT;
-        Bp[p][j] = (p < kb && j0 + j < n) ? A[(size_t)(k0 + p) * n + j0 + j] : 0.0;
-    }
-    __syncthreads();
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
     double acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int p = 0; p < kb; ++p) {
-        double x[4], y[4];
+    for (int c0 = 0; c0 < kb; c0 += KC) {
+        const int kc = min(KC, kb - c0);
+        if (c0 > 0) __syncthreads();   // the previous slice is consumed
+        for (int t = threadIdx.x; t < TT * KC; t += blockDim.x) {
+            const int i = t / KC, p = t % KC;
+            Ap[i][p] = (i0 + i < n && p < kc) ? A[(size_t)(i0 + i) * n + k0 + c0 + p] : 0.0;
+        }
+        for (int t = threadIdx.x; t < KC * TT; t += blockDim.x) {
+            const int p = t / TT, j = t % TT;
+            Bp[p][j] = (p < kc && j0 + j < n) ? A[(size_t)(k0 + c0 + p) * n + j0 + j] : 0.0;
+        }
+        __syncthreads();
+        for (int p = 0; p < kc; ++p) {
+            double x[4], y[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) x[a] = Ap[ty + 16 * a][p];
+            for (int a = 0; a < 4; ++a) x[a] = Ap[ty + 16 * a][p];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) y[b] = Bp[p][tx + 16 * b];
+            for (int b = 0; b < 4; ++b) y[b] = Bp[p][tx + 16 * b];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+                for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+        }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -161,23 +189,24 @@ __global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stri
     }
 }
 
-// (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block.
+// (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block
+// (PT rows per workgroup).
 __global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
     A += (size_t)blockIdx.z * stride;
     __shared__ double Dv[NB][NB + 1];
-    __shared__ double X[TT][NB + 1];
+    __shared__ double X[PT][NB + 1];
     const int kb = min(NB, n - k0);
-    const int i0 = blockIdx.x * TT;
+    const int i0 = blockIdx.x * PT;
     for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
         const int i = t / NB, j = t % NB;
         Dv[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
     }
-    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
+    for (int t = threadIdx.x; t < PT * NB; t += blockDim.x) {
         const int i = t / NB, p = t % NB;
         X[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < TT * NB; t += blockDim.x) {
+    for (int t = threadIdx.x; t < PT * NB; t += blockDim.x) {
         const int i = t / NB, j = t % NB;
         const int row = i0 + i;
         if (row >= n || j >= kb || (row >= k0 && row < k0 + kb)) continue;
@@ -391,12 +420,12 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
 }
 
 hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
-    const int tiles = (n + TT - 1) / TT;
+    const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT;
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(NB * NB), 0, st, n, A, stride, k0, err);
-        hipLaunchKernelGGL(k_gj_rowpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, k0, err);
+        hipLaunchKernelGGL(k_gj_rowpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
-        hipLaunchKernelGGL(k_gj_colpanel, dim3(tiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
     return hipGetLastError();
 }
