@@ -189,6 +189,60 @@ __global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stri
     }
 }
 
+// (c') the same trailing update in 128 x 128 tiles (8 x 8 entries per thread,
+// half the LDS bytes per multiply-add of the 64 x 64 tiles) for batches of
+// matrices, which fill the chip with the larger tiles.
+constexpr int TB = 128;     // tile edge
+constexpr int KB = 16;      // panel columns staged per pass
+__global__ __launch_bounds__(256) void k_gj_update_big(int n, double *A, size_t stride, int k0) {
+    A += (size_t)blockIdx.z * stride;
+    __shared__ double Ap[TB][KB + 1];
+    __shared__ double Bp[KB][TB + 1];
+    const int kb = min(NB, n - k0);
+    const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    double acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int c0 = 0; c0 < kb; c0 += KB) {
+        const int kc = min(KB, kb - c0);
+        if (c0 > 0) __syncthreads();   // the previous slice is consumed
+        for (int t = threadIdx.x; t < TB * KB; t += blockDim.x) {
+            const int i = t / KB, p = t % KB;
+            Ap[i][p] = (i0 + i < n && p < kc) ? A[(size_t)(i0 + i) * n + k0 + c0 + p] : 0.0;
+        }
+        for (int t = threadIdx.x; t < KB * TB; t += blockDim.x) {
+            const int p = t / TB, j = t % TB;
+            Bp[p][j] = (p < kc && j0 + j < n) ? A[(size_t)(k0 + c0 + p) * n + j0 + j] : 0.0;
+        }
+        __syncthreads();
+        for (int p = 0; p < kc; ++p) {
+            double x[8], y[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) x[a] = Ap[ty + 16 * a][p];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) y[b] = Bp[p][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) acc[a][b] += x[a] * y[b];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int i = i0 + ty + 16 * a;
+        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int j = j0 + tx + 16 * b;
+            if (j >= n || (j >= k0 && j < k0 + kb)) continue;
+            A[(size_t)i * n + j] -= acc[a][b];
+        }
+    }
+}
+
 // (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block
 // (PT rows per workgroup).
 __global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
@@ -420,11 +474,16 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
 }
 
 hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
-    const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT;
+    const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT, btiles = (n + TB - 1) / TB;
+    // the 128-wide tiles once they still give every CU about four workgroups
+    const bool big = (size_t)btiles * btiles * batch >= 1024;
     for (int k0 = 0; k0 < n; k0 += NB) {
         hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, k0, err);
         hipLaunchKernelGGL(k_gj_rowpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
-        hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
+        if (big)
+            hipLaunchKernelGGL(k_gj_update_big, dim3(btiles, btiles, batch), dim3(256), 0, st, n, A, stride, k0);
+        else
+            hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
     return hipGetLastError();

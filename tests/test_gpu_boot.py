@@ -166,6 +166,27 @@ def test_ws1000_full_size_sampled(ctx):
     assert np.array_equal(gb["hi"], np.percentile(reps, 97.5, axis=0, method="inverted_cdf"))
 
 
+def test_n500_batched_large_tiles(ctx):
+    # n = 500, 64 replicates: the batched inversion takes its 128-wide tiles
+    # (ragged last tile of 116) -- b0 and two replicates against the oracle
+    n, R, B = 500, 200, 64
+    nt = draws_from_kernel(random_kernel(n, 21, density=0.05), R, 22)
+    say(f"[gpu] bootstrap n={n} R={R} B={B}")
+    g = amc.bootstrap(ctx, nt, replicates=B, seed=4)
+    eta = 0.1 / np.sqrt(R)
+    s = np.full(n, 1.0 / n)
+    C0 = np.zeros((n, n + 1), np.uint32)
+    for i in range(n):
+        col = nt[:, i]
+        C0[i, :n] = np.bincount(col[col >= 0], minlength=n)
+        C0[i, n] = np.count_nonzero(col < 0)
+    Q, _ = O.counts_to_kernel(C0, R, eta)
+    close(g["b0"], O.chain(Q, s)["b"], 1e-12, "b0")
+    for beta in (0, B - 1):
+        Q, _ = O.counts_to_kernel(O.boot_counts(nt, 4, beta), R, eta)
+        close(g["b_rep"][beta], O.chain(Q, s)["b"], 1e-12, f"replicate {beta}")
+
+
 def test_invalid_arguments(ctx):
     nt = np.zeros((4, 3), dtype=np.int32)
     for kw in ({"replicates": 0}, {"replicates": amc.MAX_BOOT_REPLICATES + 1}, {"level": 1.0}, {"level": 0.0},
