@@ -137,21 +137,27 @@ __global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
     }
 }
 
-// (c) trailing update: A[i, j] -= A[i, k] A[k, j] for i, j outside the block
-// (A[k, j] already holds the row panel of step (b)); the NB panel columns are
-// staged KC at a time.
-__global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stride, int k0) {
+// (c) trailing update A[i, j] -= A[i, k] A[k, j] for i, j outside the block
+// (A[k, j] already holds the row panel of step (b)), on the FP64 matrix
+// cores: a 64 x 64 tile per workgroup, each wavefront a 32 x 32 quadrant as
+// 2 x 2 blocks of v_mfma_f64_16x16x4 (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16 x 4 by 4 x 16 product and holds
+// D[4 r + l / 16][l % 16] in item r), the panel staged KC columns at a time.
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t stride, int k0) {
     A += (size_t)blockIdx.z * stride;
     __shared__ double Ap[TT][KC + 1];
     __shared__ double Bp[KC][TT + 1];
     const int kb = min(NB, n - k0);
     const int i0 = blockIdx.y * TT, j0 = blockIdx.x * TT;
-    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-    double acc[4][4];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int rw = (wave >> 1) * 32, cw = (wave & 1) * 32;     // the wavefront's quadrant
+    const int li = lane & 15, lk = lane >> 4;
+    mfma_f64x4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
     for (int c0 = 0; c0 < kb; c0 += KC) {
         const int kc = min(KC, kb - c0);
         if (c0 > 0) __syncthreads();   // the previous slice is consumed
@@ -164,83 +170,30 @@ __global__ __launch_bounds__(256) void k_gj_update(int n, double *A, size_t stri
             Bp[p][j] = (p < kc && j0 + j < n) ? A[(size_t)(k0 + c0 + p) * n + j0 + j] : 0.0;
         }
         __syncthreads();
-        for (int p = 0; p < kc; ++p) {
-            double x[4], y[4];
+        // zero padding past kc makes the last partial group of 4 exact
+        for (int p = 0; p < kc; p += 4) {
+            double af[2], bf[2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) x[a] = Ap[ty + 16 * a][p];
+            for (int a = 0; a < 2; ++a) af[a] = Ap[rw + 16 * a + li][p + lk];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) y[b] = Bp[p][tx + 16 * b];
+            for (int b = 0; b < 2; ++b) bf[b] = Bp[p + lk][cw + 16 * b + li];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ty + 16 * a;
-        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = j0 + tx + 16 * b;
-            if (j >= n || (j >= k0 && j < k0 + kb)) continue;
-            A[(size_t)i * n + j] -= acc[a][b];
-        }
-    }
-}
-
-// (c') the same trailing update in 128 x 128 tiles (8 x 8 entries per thread,
-// half the LDS bytes per multiply-add of the 64 x 64 tiles) for batches of
-// matrices, which fill the chip with the larger tiles.
-constexpr int TB = 128;     // tile edge
-constexpr int KB = 16;      // panel columns staged per pass
-__global__ __launch_bounds__(256) void k_gj_update_big(int n, double *A, size_t stride, int k0) {
-    A += (size_t)blockIdx.z * stride;
-    __shared__ double Ap[TB][KB + 1];
-    __shared__ double Bp[KB][TB + 1];
-    const int kb = min(NB, n - k0);
-    const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
-    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-    double acc[8][8];
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-    for (int c0 = 0; c0 < kb; c0 += KB) {
-        const int kc = min(KB, kb - c0);
-        if (c0 > 0) __syncthreads();   // the previous slice is consumed
-        for (int t = threadIdx.x; t < TB * KB; t += blockDim.x) {
-            const int i = t / KB, p = t % KB;
-            Ap[i][p] = (i0 + i < n && p < kc) ? A[(size_t)(i0 + i) * n + k0 + c0 + p] : 0.0;
-        }
-        for (int t = threadIdx.x; t < KB * TB; t += blockDim.x) {
-            const int p = t / TB, j = t % TB;
-            Bp[p][j] = (p < kc && j0 + j < n) ? A[(size_t)(k0 + c0 + p) * n + j0 + j] : 0.0;
-        }
-        __syncthreads();
-        for (int p = 0; p < kc; ++p) {
-            double x[8], y[8];
-#pragma unroll
-            for (int a = 0; a < 8; ++a) x[a] = Ap[ty + 16 * a][p];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) y[b] = Bp[p][tx + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-#pragma unroll
-                for (int b = 0; b < 8; ++b) acc[a][b] += x[a] * y[b];
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const int i = i0 + ty + 16 * a;
-        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int j = j0 + tx + 16 * b;
-            if (j >= n || (j >= k0 && j < k0 + kb)) continue;
-            A[(size_t)i * n + j] -= acc[a][b];
-        }
-    }
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + rw + 16 * a + 4 * r + lk, j = j0 + cw + 16 * b + li;
+                if (i >= n || j >= n || (i >= k0 && i < k0 + kb) || (j >= k0 && j < k0 + kb)) continue;
+                A[(size_t)i * n + j] -= acc[a][b][r];
+            }
 }
 
 // (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block
@@ -474,16 +427,11 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
 }
 
 hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
-    const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT, btiles = (n + TB - 1) / TB;
-    // the 128-wide tiles once they still give every CU about four workgroups
-    const bool big = (size_t)btiles * btiles * batch >= 1024;
+    const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT;
     for (int k0 = 0; k0 < n; k0 += NB) {
         hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, k0, err);
         hipLaunchKernelGGL(k_gj_rowpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
-        if (big)
-            hipLaunchKernelGGL(k_gj_update_big, dim3(btiles, btiles, batch), dim3(256), 0, st, n, A, stride, k0);
-        else
-            hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_update_mfma, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
     return hipGetLastError();
