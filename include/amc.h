@@ -185,6 +185,8 @@ typedef struct amc_stats {
     double topk_ms;             /* HIP-event time of the finite-k Top-k stage (topk > 0) */
     int32_t dist_bytes;         /* bytes per distance entry of the per-source state (2 or 4) */
     int32_t b_global;           /* L2 mode: 1 = B(H_r) in the L2-resident scratch, 0 = in LDS */
+    int32_t tail_split;         /* last realizations run split into tiles (R mod blocks), 0 = none */
+    int32_t tail_tiles;         /* tiles per such realization                                   */
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */

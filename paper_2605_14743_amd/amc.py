@@ -110,7 +110,8 @@ class Stats(C.Structure):
                 ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
                 ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
                 ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32), ("topk_ms", C.c_double),
-                ("dist_bytes", C.c_int32), ("b_global", C.c_int32)]
+                ("dist_bytes", C.c_int32), ("b_global", C.c_int32), ("tail_split", C.c_int32),
+                ("tail_tiles", C.c_int32)]
 
 
 class Result(C.Structure):

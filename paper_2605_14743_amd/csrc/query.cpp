@@ -264,6 +264,60 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
     return AMC_OK;
 }
 
+// Whole realizations leave workgroups idle at the end of the launch (the
+// partial last round, and the spread of item times): the last R mod blocks
+// realizations, plus one more round of blocks when R >= 2 blocks, run as a
+// second descriptor over the same counts and tables, each split into tiles
+// of at most n / 16 sources (their partial B rows meet in an exchange buffer
+// as in any split realization).  Items are handed out in order, so the short
+// tiles come last.
+int qr_split_tail(QueryRun &R, hipStream_t st) {
+    const amc_query &q = R.q;
+    Plan &pl = R.pl;
+    if ((q.flags & AMC_PLAIN_LAUNCH) || pl.anchored || pl.tiles_per_r != 1 || R.P.keep_rows || R.P.n_dbg)
+        return AMC_OK;
+    if (pl.mode != AMC_MODE_WAVE && pl.mode != AMC_MODE_WAVE_L2) return AMC_OK;
+    const uint32_t B = (uint32_t)pl.blocks, Rn = q.R;
+    if (B < 2 || Rn <= B) return AMC_OK;
+    // the partial last round, plus one full round when there are enough
+    // realizations, so that the items at the end are short
+    const uint32_t tail = Rn % B + (Rn >= 2 * B ? B : 0u);
+    if (tail == 0) return AMC_OK;
+    const int n = R.g->n;
+    const uint32_t want = std::max<uint32_t>(16u, (B + tail - 1) / tail);
+    int tile = (int)((n + want - 1) / want);
+    tile = std::min(std::max(tile, pl.waves), n);
+    const int tiles = (n + tile - 1) / tile;
+    if (tiles < 2) return AMC_OK;
+    DevArena &A = R.A;
+    void *p;
+    SweepParams P2 = R.P;
+    const uint32_t R0 = Rn - tail;
+    P2.r_begin = R.P.r_begin + R0;
+    P2.tile = tile;
+    P2.tiles_per_r = tiles;
+    if (P2.center_global) P2.center_global += R0;
+    if (P2.next_table) P2.next_table += (size_t)R0 * n;
+    if (P2.next_table_w) P2.next_table_w += (size_t)R0 * n;
+    RCHK(A.alloc(8 * (size_t)tail * n, &p)); P2.Bg = (double *)p;
+    RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.compg = (int32_t *)p;
+    RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.sizeg = (int32_t *)p;
+    RCHK(A.alloc(4 * (size_t)tail, &p)); P2.done = (unsigned int *)p;
+    const SweepParams descs[2] = {R.P, P2};
+    RCHK(dev_copy_in(A, descs, sizeof(descs), st, &p));
+    R.d_desc = (SweepParams *)p;
+    const uint32_t starts[3] = {0u, R0, R0 + tail * (uint32_t)tiles};
+    RCHK(dev_copy_in(A, starts, sizeof(starts), st, &p));
+    R.d_item_start = (uint32_t *)p;
+    R.P2 = P2;
+    R.split_tail = true;
+    R.tail_R = tail;
+    R.nq = 2;
+    pl.items = starts[2];
+    HIPCHK(hipStreamSynchronize(st));   // descs and starts are locals
+    return AMC_OK;
+}
+
 int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
     const SweepParams &P = R.P;
     const int n = R.g->n;
@@ -280,6 +334,10 @@ int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
     if (P.Bg) {
         HIPCHK(fill_u32(P.Bg, 2 * (size_t)Rn * n, 0u, st));
         HIPCHK(fill_u32(P.done, Rn, 0u, st));
+    }
+    if (R.split_tail) {
+        HIPCHK(fill_u32(R.P2.Bg, 2 * (size_t)R.tail_R * n, 0u, st));
+        HIPCHK(fill_u32(R.P2.done, R.tail_R, 0u, st));
     }
     if (P.dbg_dist) {
         HIPCHK(fill_u32(P.dbg_dist, (size_t)P.n_dbg * n, 0xFFFFFFFFu, st));
@@ -303,7 +361,7 @@ int qr_enqueue_sweep(QueryRun &R, hipStream_t st) {
     std::memset(&LC, 0, sizeof(LC));
     LC.descs = R.d_desc;
     LC.item_start = R.d_item_start;
-    LC.nq = 1;
+    LC.nq = R.nq;
     LC.work_ctr = R.work_ctr;
     LC.bscratch = R.bscratch;
     LC.bscratch_words = R.bscratch_words;
@@ -442,6 +500,8 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
         out->stats.adj_bytes = (int32_t)R.pl.adj_bytes;
         out->stats.dist_bytes = R.pl.dist16 ? 2 : 4;
         out->stats.b_global = R.pl.b_global ? 1 : 0;
+        out->stats.tail_split = R.split_tail ? (int32_t)R.tail_R : 0;
+        out->stats.tail_tiles = R.split_tail ? R.P2.tiles_per_r : 0;
     }
     if (!(q.flags & AMC_SKIP_TAIL)) {
         const TailBufs &T = R.T;
@@ -524,6 +584,7 @@ int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_q
         ~Guard() { qr_release(r, s); }
     } guard{R, st};
     RCHK(qr_alloc(R, st));
+    RCHK(qr_split_tail(R, st));
     hipEvent_t ev[4];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {

@@ -52,12 +52,18 @@ struct QueryRun {
     int launches = 0;
     uint32_t *cw = nullptr;                // pool-selector counts (sweep or Top-k stage)
     int32_t *ntw = nullptr;                // pool-selector table
+    // the last R mod blocks realizations split into tiles (second descriptor)
+    bool split_tail = false;
+    uint32_t tail_R = 0;
+    SweepParams P2{};
+    int nq = 1;
     TailBufs T;
 };
 
 int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q);
 int qr_fill_desc(QueryRun &R, hipStream_t st);
 int qr_alloc(QueryRun &R, hipStream_t st);
+int qr_split_tail(QueryRun &R, hipStream_t st);
 int qr_enqueue_reset(QueryRun &R, hipStream_t st);
 int qr_enqueue_sweep(QueryRun &R, hipStream_t st);
 int qr_enqueue_post(QueryRun &R, hipStream_t st);
