@@ -313,7 +313,9 @@ def make_query(n, *, seed=0, R=1, r_begin=0, alpha=0.15, k_min=5, tie_tau=-1.0, 
     return q, keep
 
 
-def _alloc_result(n, q: Query):
+def _alloc_result(n, q: Query, reuse=None):
+    """Caller-owned result buffers for one query; `reuse` (the dict a previous
+    call returned, same shapes) lends its arrays instead of fresh ones."""
     R = int(q.R)
     k = int(q.cert_topk)
     pool = q.pool_size > 0
@@ -347,6 +349,12 @@ def _alloc_result(n, q: Query):
             arr["psi_w"] = np.zeros(n)
     if (q.flags & FALLBACK) and not (q.flags & SKIP_TAIL):
         arr.update(b_fb=np.zeros(n), b_cens=np.zeros(n))
+    if reuse is not None:
+        for key, a in arr.items():
+            b = reuse.get(key)
+            if isinstance(b, np.ndarray) and b.shape == a.shape and b.dtype == a.dtype and b.flags.c_contiguous \
+                    and b.flags.writeable:
+                arr[key] = b
     res = Result()
     types = {np.dtype(np.uint32): C.c_uint32, np.dtype(np.int32): C.c_int32, np.dtype(np.float64): C.c_double,
              np.dtype(np.uint64): C.c_uint64}
@@ -366,12 +374,14 @@ def _collect(res: Result, arr: dict) -> dict:
     return out
 
 
-def run(ctx: Context, graph: Graph, model: dict, **query) -> dict:
+def run(ctx: Context, graph: Graph, model: dict, out: dict | None = None, **query) -> dict:
     """amc_run: the sweep (Alg. 1 for every anchor over R realizations, counted
-    as in Alg. 2) and the tail; returns numpy arrays and scalars."""
+    as in Alg. 2) and the tail; returns numpy arrays and scalars.  With `out`
+    (a dict an earlier call returned) its arrays of matching shape receive the
+    results again instead of fresh ones."""
     m, keep_m = make_model(**model)
     q, keep_q = make_query(graph.n, **query)
-    res, arr = _alloc_result(graph.n, q)
+    res, arr = _alloc_result(graph.n, q, out)
     _check(lib().amc_run(ctx.h, graph.h, C.byref(m), C.byref(q), C.byref(res)), "amc_run")
     del keep_m, keep_q
     return _collect(res, arr)

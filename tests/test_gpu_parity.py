@@ -366,6 +366,27 @@ def test_last_realizations_split_into_tiles(ctx, mode, graph):
     assert_close_norm(res["b"], t["b"], what="b")
 
 
+def test_result_buffers_reused(ctx):
+    # out= lends the arrays of an earlier result: same objects, same values
+    wl = W.config_er20()
+    g = wl.graph
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    kw = dict(seed=9, R=300, alpha=0.15, k_min=5, flags=amc.WANT_NEXT_TABLE, cert_topk=3, r_lower=0.05)
+    say("[gpu] result buffers reused")
+    first = amc.run(ctx, G, wl.model(), **kw)
+    keep = {k: v.copy() for k, v in first.items() if isinstance(v, np.ndarray)}
+    second = amc.run(ctx, G, wl.model(), out=first, **dict(kw, seed=10))
+    third = amc.run(ctx, G, wl.model(), out=second, **kw)
+    assert second["counts"] is first["counts"] and third["Q"] is first["Q"]
+    for k, v in keep.items():
+        assert np.array_equal(third[k], v), k
+    old_table = third["next_table"]
+    other = amc.run(ctx, G, wl.model(), out=third, **dict(kw, R=200))      # next table of another shape
+    G.close()
+    assert other["next_table"].shape == (200, g.n) and other["next_table"] is not old_table
+    assert other["counts"] is first["counts"]
+
+
 # --------------------------------------------------------------------------- tail alone (amc_chain)
 def test_chain_appendix_b(ctx, golden):
     ref = golden("appendix_b.json")
