@@ -18,10 +18,11 @@
 //     passes: no residual cycle is negative while the flow is optimal for what
 //     it has moved, and the lexicographic label makes the shortest walks
 //     simple);
-//   - then, while a node with deficit at the smallest distance D* remains
-//     (smallest index first), its path back to a surplus node is found edge by
-//     edge through arcs that realise the labels under the current flow (the
-//     hop count falls by one per edge), and the largest push that overdraws
+//   - every labelled node then keeps one arc that realises its label (the
+//     smallest arc code), and while a node with deficit at the smallest
+//     distance D* remains (smallest index first), one thread follows these
+//     arcs back to a surplus node, checking each against the current flow
+//     (the hop count falls by one per arc), and makes the largest push that overdraws
 //     neither the surplus, the deficit, nor a cancelled flow is made; each
 //     push zeroes one of those exactly (x + (-x) = 0).  A push along such arcs
 //     leaves the labels a feasible potential (the reverse of a realising arc
@@ -62,13 +63,13 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     extern __shared__ double w1_smem[];
     double *ex = w1_smem;                                   // n: remaining surplus (> 0) / deficit (< 0)
     uint64_t *key = (uint64_t *)(ex + n);                   // n: packed (distance, hops) labels
-    int32_t *path = (int32_t *)(key + n);                   // n: arcs of the current path (2e + dir)
+    int32_t *path = (int32_t *)(key + n);                   // n: predecessor arcs of the phase (2e + dir)
     uint8_t *tried = (uint8_t *)(path + n);                 // n: deficit nodes whose walk failed this phase
     uint32_t *ends = (uint32_t *)(tried + ((n + 3) & ~3));  // m (CACHED): eu | ev << 16
     int8_t *sgn = (int8_t *)(ends + (CACHED ? m : 0));      // m (CACHED): sign of the flow
-    __shared__ int s_any_src, s_any_snk, s_changed, s_plen, s_src, s_stop, s_ok;
+    __shared__ int s_any_src, s_any_snk, s_changed, s_stop, s_pushed;
     __shared__ uint64_t s_best;
-    __shared__ uint32_t s_pick, s_sink;
+    __shared__ uint32_t s_sink;
     __shared__ double s_part[kW1Threads / 64];
     const int tid = threadIdx.x, k = blockIdx.x;
     const double *p = P + (size_t)k * n;
@@ -163,6 +164,24 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             break;
         }
         const uint32_t dhi = (uint32_t)(s_best >> 32);
+        // one label-realising arc into every labelled node (the smallest arc
+        // code 2 e + dir), so that a path is followed by one thread
+        uint32_t *pred = (uint32_t *)path;
+        for (int v = tid; v < n; v += kW1Threads) pred[v] = 0xFFFFFFFFu;
+        if (tid == 0) s_pushed = 0;
+        __syncthreads();
+        for (int e = tid; e < m; e += kW1Threads) {
+            const int a = end_a(e), b = end_b(e);
+            const int sg = sign_of(e);
+            const uint64_t ka = key[a], kb = key[b];
+            if (ka != kNoLabel && kb != kNoLabel) {
+                if (w1_label(w1_dist(ka) + w1_cost(sg, true), (uint32_t)ka + 1u) == kb)
+                    atomicMin(&pred[b], 2u * (uint32_t)e);
+                if (w1_label(w1_dist(kb) + w1_cost(sg, false), (uint32_t)kb + 1u) == ka)
+                    atomicMin(&pred[a], 2u * (uint32_t)e + 1u);
+            }
+        }
+        __syncthreads();
         int pushes = 0;
         for (long attempt = 0;; ++attempt) {
             if (attempt >= max_tries) {
@@ -182,75 +201,52 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             const uint32_t tsel = s_sink;
             if (tsel == 0xFFFFFFFFu) break;
             const int t = (int)tsel;
-            // walk back along arcs that realise the labels under the current flow
+            // thread 0 follows the predecessor arcs back to a node that had
+            // surplus, checking each arc against the current flow, then pushes
             if (tid == 0) {
-                s_plen = 0;
-                s_src = t;
-                s_ok = 1;
-            }
-            __syncthreads();
-            for (int step = 0;; ++step) {
-                const int x = s_src;
-                const uint64_t kx = key[x];
-                if ((uint32_t)kx == 0u) break;          // hop count 0: a node that had surplus
-                if (step >= n) {                        // a path has at most n - 1 edges
-                    if (tid == 0) s_ok = 0;
-                    break;
-                }
-                if (tid == 0) s_pick = 0xFFFFFFFFu;
-                __syncthreads();
-                for (int j = rp[x] + tid; j < rp[x + 1]; j += kW1Threads) {
-                    const int e = inc[j];
-                    const bool into_fwd = end_b(e) == x; // arc eu -> ev arrives at x
-                    const int y = into_fwd ? end_a(e) : end_b(e);
+                bool ok = true;
+                int x = t, steps = 0;
+                double th = -ex[t];
+                while ((uint32_t)key[x] != 0u) {                 // hop count 0: a node that had surplus
+                    const uint32_t arc = pred[x];
+                    if (arc == 0xFFFFFFFFu || ++steps > n) {
+                        ok = false;
+                        break;
+                    }
+                    const int e = (int)(arc >> 1);
+                    const bool fwd = (arc & 1u) == 0u;           // eu -> ev arrives at x
+                    const int y = fwd ? end_a(e) : end_b(e);
                     const uint64_t ky = key[y];
-                    if (ky != kNoLabel &&
-                        w1_label(w1_dist(ky) + w1_cost(sign_of(e), into_fwd), (uint32_t)ky + 1u) == kx)
-                        atomicMin(&s_pick, (uint32_t)j);
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    const uint32_t j = s_pick;
-                    if (j == 0xFFFFFFFFu) {
-                        s_ok = 0;
-                    } else {
-                        const int e = inc[j];
-                        const bool into_fwd = end_b(e) == x;
-                        path[s_plen++] = 2 * e + (into_fwd ? 0 : 1);
-                        s_src = into_fwd ? end_a(e) : end_b(e);
+                    if (w1_label(w1_dist(ky) + w1_cost(sign_of(e), fwd), (uint32_t)ky + 1u) != key[x]) {
+                        ok = false;                               // a push changed this arc's cost
+                        break;
                     }
+                    const double fe = f[e];
+                    if (fwd && fe < 0.0 && -fe < th) th = -fe;
+                    if (!fwd && fe > 0.0 && fe < th) th = fe;
+                    x = y;
                 }
-                __syncthreads();
-                if (!s_ok) break;
-            }
-            __syncthreads();
-            // push, or leave this deficit node to the next phase
-            if (tid == 0) {
-                const int s = s_src;
-                if (!s_ok || !(ex[s] > 0.0)) {
-                    tried[t] = 1;
+                const int s = x;
+                if (!ok || !(ex[s] > 0.0)) {
+                    tried[t] = 1;                                 // left to the next phase
                 } else {
-                    double th = -ex[t];
-                    for (int i = 0; i < s_plen; ++i) {
-                        const int e = path[i] >> 1;
-                        const bool fwd = (path[i] & 1) == 0;
-                        const double fe = f[e];
-                        if (fwd && fe < 0.0 && -fe < th) th = -fe;
-                        if (!fwd && fe > 0.0 && fe < th) th = fe;
-                    }
                     if (ex[s] < th) th = ex[s];
-                    for (int i = 0; i < s_plen; ++i) {
-                        const int e = path[i] >> 1;
-                        f[e] += (path[i] & 1) == 0 ? th : -th;
+                    for (int z = t; z != s;) {
+                        const uint32_t arc = pred[z];
+                        const int e = (int)(arc >> 1);
+                        const bool fwd = (arc & 1u) == 0u;
+                        f[e] += fwd ? th : -th;
                         if constexpr (CACHED) sgn[e] = (int8_t)w1_sign(f[e]);
+                        z = fwd ? end_a(e) : end_b(e);
                     }
                     ex[s] -= th;
                     ex[t] += th;
+                    s_pushed = 1;
                 }
             }
             __syncthreads();
-            pushes += s_ok && !tried[t];
         }
+        pushes = s_pushed;
         __syncthreads();
         if (s_stop) break;
         if (pushes == 0) {   // the first walk of a phase always succeeds
