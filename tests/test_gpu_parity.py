@@ -343,24 +343,29 @@ def test_split_ranges_and_determinism(ctx):
     G.close()
 
 
-@pytest.mark.parametrize("mode,graph", [(amc.MODE_WAVE_L2, "er20"), (amc.MODE_WAVE_L2, "ws200"),
-                                        (amc.MODE_WAVE, "ws200")])
-def test_last_realizations_split_into_tiles(ctx, mode, graph):
+@pytest.mark.parametrize("mode,graph,extra", [(amc.MODE_WAVE_L2, "er20", {}), (amc.MODE_WAVE_L2, "ws200", {}),
+                                              (amc.MODE_WAVE, "ws200", {}),
+                                              (amc.MODE_WAVE_L2, "ws200", {"flags": amc.DIST16, "pool": True}),
+                                              (amc.MODE_WAVE, "ws200", {"pool": True})])
+def test_last_realizations_split_into_tiles(ctx, mode, graph, extra):
     # whole realizations (tile = n) with R = workgroups + 37: the last 37 run
     # split into tiles through a second descriptor over the same counts
     g = W.config_er20().graph if graph == "er20" else W.ws_graph(200, 6, 0.1, 1)
     model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 6}
     G = amc.Graph(ctx, g.n, g.eu, g.ev)
-    probe = amc.run(ctx, G, model, seed=3, R=32768, mode=mode, tile=g.n, flags=amc.SKIP_TAIL)
+    pool = np.arange(3, g.n, 7) if extra.get("pool") else None
+    probe = amc.run(ctx, G, model, seed=3, R=32768, mode=mode, tile=g.n, pool=pool,
+                    flags=amc.SKIP_TAIL | extra.get("flags", 0))          # the same plan as the run below
     G.close()
     blocks = probe["stats"]["blocks"]
     if blocks >= 32768:
         pytest.skip("more workgroup slots than the probe's realizations")
     R = blocks + 37
-    res = gpu_run(ctx, g, model, seed=3, R=R, alpha=0.15, k_min=5, flags=FLAGS, mode=mode, tile=g.n)
+    res = gpu_run(ctx, g, model, seed=3, R=R, alpha=0.15, k_min=5, flags=FLAGS | extra.get("flags", 0), mode=mode,
+                  tile=g.n, pool=pool)
     st = res["stats"]
     assert st["tail_split"] == 37 and st["tail_tiles"] >= 2, st
-    ref = O.sweep(g.n, g.eu, g.ev, seed=3, R=R, alpha=0.15, k_min=5, want_next=True, **model)
+    ref = O.sweep(g.n, g.eu, g.ev, seed=3, R=R, alpha=0.15, k_min=5, want_next=True, pool=pool, **model)
     check_sweep(res, ref, g.n, f"{graph} tail split")
     t = O.tail(ref["counts"], R)
     assert_close_norm(res["b"], t["b"], what="b")
