@@ -276,7 +276,6 @@ int qr_split_tail(QueryRun &R, hipStream_t st) {
     Plan &pl = R.pl;
     if ((q.flags & AMC_PLAIN_LAUNCH) || pl.anchored || pl.tiles_per_r != 1 || R.P.keep_rows || R.P.n_dbg)
         return AMC_OK;
-    if (pl.mode != AMC_MODE_WAVE && pl.mode != AMC_MODE_WAVE_L2) return AMC_OK;
     const uint32_t B = (uint32_t)pl.blocks, Rn = q.R;
     if (B < 2 || Rn <= B) return AMC_OK;
     // the partial last round, plus one full round when there are enough

@@ -346,7 +346,8 @@ def test_split_ranges_and_determinism(ctx):
 @pytest.mark.parametrize("mode,graph,extra", [(amc.MODE_WAVE_L2, "er20", {}), (amc.MODE_WAVE_L2, "ws200", {}),
                                               (amc.MODE_WAVE, "ws200", {}),
                                               (amc.MODE_WAVE_L2, "ws200", {"flags": amc.DIST16, "pool": True}),
-                                              (amc.MODE_WAVE, "ws200", {"pool": True})])
+                                              (amc.MODE_WAVE, "ws200", {"pool": True}),
+                                              (amc.MODE_BLOCK, "er20", {}), (amc.MODE_BLOCK, "ws200", {"pool": True})])
 def test_last_realizations_split_into_tiles(ctx, mode, graph, extra):
     # whole realizations (tile = n) with R = workgroups + 37: the last 37 run
     # split into tiles through a second descriptor over the same counts
