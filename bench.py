@@ -8,17 +8,24 @@ tail (N, mu, b, certificates), with the graph already staged in HBM.
 
 Printed as one JSON line:
   value        whole-job realization-sources/s (R n per step / step time)
-  roofline     algorithmic bytes of the sweep kernel (8 D_K + 32 A_K + 64 n_K
-               summed over every (r, s), counted exactly by the kernel) over
-               its HIP-event duration, against the 8 TB/s HBM peak; the
-               kernel keeps the realized graph and every per-source array
-               on chip, so this rate can exceed the HBM peak ("above_peak"
-               says so).  roofline.lds sets the same bytes against the LDS
-               peak (256 CUs x 128 B/clock x 2.4 GHz), where they are served
+  roofline     the resource that bounds the sweep kernel.  The traversal
+               state never leaves the chip, so HBM does not bind it: the
+               kernel is bound by VALU issue ("alu": wave64 VALU instructions
+               per (r, s) from the SQ counter profile of the same kernel
+               sources, times the units of one launch, over the launch's
+               HIP-event duration, against 256 CUs x 4 SIMDs x 2.4 GHz / 4
+               cycles).  Beside it: measured HBM bytes (FETCH_SIZE /
+               WRITE_SIZE, calibrated by a plain copy) against the 8 TB/s
+               peak, LDS-unit busy cycles against the chip's cycles, and the
+               algorithmic bytes (8 D_K + 32 A_K + 64 n_K per (r, s), counted
+               exactly by the kernel) as an HBM-equivalent rate.
   teps         surviving undirected edges of s's component per (r, s) / s
   plain_gpu    the same sweep as one kernel launch per realization
-  cpu_baseline the CPU oracle (single thread) on a bounded sample
-Options: --serve runs the Poisson serving trace instead and reports p50/p99.
+  er5000       one step of the n = 5000 unit-weight workload
+  serving      a bounded Poisson trace through the serving loop: p50 / p99
+  cpu_baseline the CPU oracle on all host cores (one process per core over
+               disjoint realization ranges) on a bounded sample
+Options: --serve runs the serving trace alone, --batch the mixed batch.
 """
 from __future__ import annotations
 
@@ -34,8 +41,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-LDS_PEAK_GBS = 256 * 128 * 2.4        # 78,643 GB/s: 128 B per clock per CU
-VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4    # 614.4 G wave64 instructions/s: 4 SIMDs per CU, 4 cycles each
+CUS, CLOCK_GHZ = 256, 2.4
+VALU_PEAK_GIPS = CUS * 4 * CLOCK_GHZ / 4    # 614.4 G wave64 instructions/s: 4 SIMDs per CU, 4 cycles each
+PLAIN_TARGET = 10.0                         # batched sweep over the one-launch-per-realization form
 
 
 def algorithmic_bytes(st: dict) -> int:
@@ -46,53 +54,206 @@ def algorithmic_bytes(st: dict) -> int:
     return 8 * st["sum_DK"] + 32 * st["sum_AK"] + 64 * st["sum_nK"]
 
 
+WORKLOADS = ("ws1000", "er5000", "er20", "cooc77")
+
+
+def _workload(name):
+    from paper_2605_14743_amd import workloads as W
+    return {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
+            "cooc77": W.config_cooc77}[name]()
+
+
 def _cpu_worker(task):
-    """One oracle process over its own realization range (all-cores leg)."""
+    """One oracle process over its own realization range."""
     name, r0, budget_s = task
     import oracle as O
-    from paper_2605_14743_amd import workloads as W
-    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
-          "cooc77": W.config_cooc77}[name]()
+    wl = _workload(name)
     g = wl.graph
     R = units = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        res = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=2, r_begin=r0 + R, alpha=wl.alpha, k_min=wl.k_min,
+        res = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=1, r_begin=r0 + R, alpha=wl.alpha, k_min=wl.k_min,
                       want_bsum=False, want_center=False, hop_radius=wl.hop_radius, **wl.model())
         units += res["stats"]["units"]
-        R += 2
-    return units, time.perf_counter() - t0
+        R += 1
+    return units, R, time.perf_counter() - t0
 
 
-def cpu_all_cores(name: str, procs: int, budget_s: float) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_cores() -> int:
+    """Host cores the oracle may use: the process's CPU set, at most 16 (one
+    GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(name: str, procs: int, budget_s: float) -> dict:
     """The oracle in `procs` fresh processes (spawned, never forked from this
     GPU process) over disjoint realization ranges; rate = all units / the
-    slowest process's time."""
+    slowest process's time.  The oracle is single-threaded C as it stands."""
     import multiprocessing as mp
     with mp.get_context("spawn").Pool(procs) as pool:
         out = pool.map(_cpu_worker, [(name, 1_000_000 * (k + 1), budget_s) for k in range(procs)])
-    units = sum(u for u, _ in out)
-    dt = max(t for _, t in out)
+    units = sum(u for u, _, _ in out)
+    reals = sum(r for _, r, _ in out)
+    dt = max(t for _, _, t in out)
     return {"value": units / dt, "unit": "realization-sources/s", "cores": procs, "kind": "oracle",
-            "sample": f"{procs} processes, {units} single-source passes over disjoint realization ranges "
-                      f"({dt:.1f} s)"}
+            "cpu_model": cpu_model(),
+            "sample": f"{reals} realizations of the {name} workload ({units} single-source passes) in {procs} "
+                      f"oracle processes over disjoint realization ranges, {dt:.1f} s"}
 
 
-def cpu_baseline(wl, budget_s: float = 12.0) -> dict:
-    import oracle as O
-    g = wl.graph
-    R = 0
-    units = 0
+# Sources each kernel's counter profile depends on: the kernel, the device
+# helpers it includes, and the planner / layout code that chooses its
+# launch shape, tiles and split of the last realizations.
+PLANNER_SOURCES = ("amc_api.cpp", "query.cpp", "amc_kernels.hpp", "amc_runtime.hpp")
+KERNEL_SOURCES = {
+    "sweep_wave": ("amc_dev.hpp", "sweep_common.hpp", "wave_source.hpp", "sweep_wave.hip") + PLANNER_SOURCES,
+    "sweep_block": ("amc_dev.hpp", "sweep_common.hpp", "sweep_block.hip") + PLANNER_SOURCES,
+}
+COUNTER_RECORDS = {"ws1000": ("sweep_wave", "sweep_wave_ws1000_R10000_counters.json"),
+                   "er5000": ("sweep_block", "sweep_block_er5000_R4096_counters.json")}
+
+
+def kernel_source_digest(kernel: str = "sweep_wave") -> str:
+    """Digest of the sources a sweep kernel and its launch plan are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_14743_amd", "csrc")
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_record(workload: str):
+    """The committed counter profile of a workload's sweep kernel (HBM bytes,
+    VALU instructions and LDS busy cycles per unit), or None when the kernel
+    or its planner has changed since the counters were taken."""
+    if workload not in COUNTER_RECORDS:
+        return None
+    kernel, fname = COUNTER_RECORDS[workload]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256") != kernel_source_digest(kernel):
+        return None
+    rec["source"] = "profiles/" + fname
+    return rec
+
+
+def roofline(st: dict, k_ms: float, rec) -> dict:
+    """Roofline of one sweep launch (units st["units"], HIP-event time k_ms).
+
+    bound "alu": wave64 VALU instructions issued per second (instructions per
+    (r, s) from the SQ_INSTS_VALU profile x units / launch time) against the
+    VALU issue peak.  Secondary: measured HBM bytes (calibrated FETCH_SIZE +
+    WRITE_SIZE) against the HBM peak, the LDS unit's busy cycles
+    (SQ_LDS_IDX_ACTIVE) against the CU cycles of the launch, and the
+    algorithmic bytes as an HBM-equivalent rate (above the HBM peak when the
+    state lives on chip)."""
+    t = k_ms * 1e-3
+    units = st["units"]
+    ab = algorithmic_bytes(st)
+    alg = {"bytes_per_launch": ab, "units_per_launch": units, "GBps": ab / t / 1e9,
+           "frac_of_hbm_peak": ab / t / 1e9 / HBM_PEAK_GBS,
+           "note": "HBM-equivalent rate of 8 D_K + 32 A_K + 64 n_K bytes per (r, s); the traversal state is "
+                   "on chip, so these bytes never cross HBM"}
+    out = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_GIPS, "unit": "G wave64 VALU instructions/s",
+           "frac": None, "traffic": None, "algorithmic": alg}
+    if rec is None:
+        out["note"] = "no counter profile of the current kernel sources"
+        return out
+    valu = rec["valu_insts_per_unit"] * units / t / 1e9
+    out.update(achieved=valu, frac=valu / VALU_PEAK_GIPS, traffic=rec["hbm_bytes_per_unit"] * units,
+               source=rec["source"])
+    hbm = rec["hbm_bytes_per_unit"] * units / t / 1e9
+    out["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
+    if "lds_idx_active_per_unit" in rec:
+        cu_cycles = CUS * CLOCK_GHZ * 1e9 * t
+        busy = rec["lds_idx_active_per_unit"] * units
+        out["lds"] = {"busy_cycles": busy, "cu_cycles": cu_cycles, "frac": busy / cu_cycles,
+                      "bank_conflict_share": rec.get("lds_bank_conflict_per_unit", 0.0) /
+                      max(rec["lds_idx_active_per_unit"], 1e-30)}
+    return out
+
+
+def run_workload(ctx, amc, wl, q, steps, warmup):
+    """`warmup` + `steps` synchronous estimations; returns the last result,
+    the mean HIP-event times and the wall time of the timed steps."""
+    import torch
+    G = amc.Graph(ctx, wl.graph.n, wl.graph.eu, wl.graph.ev, wl.graph.w0)
+    model = wl.model()
+    last = None
+    for _ in range(warmup):
+        last = amc.run(ctx, G, model, out=last, **q)
+    torch.cuda.synchronize()
+    sweep_ms, tail_ms, topk_ms = [], [], []
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        res = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=4, r_begin=R, alpha=wl.alpha, k_min=wl.k_min, want_bsum=False,
-                      want_center=False, hop_radius=wl.hop_radius, **wl.model())
-        units += res["stats"]["units"]
-        R += 4
+    for _ in range(steps):
+        # every step recomputes and copies back all results, into the host
+        # buffers the previous step used (no fresh allocation per step)
+        last = amc.run(ctx, G, model, out=last, **q)
+        sweep_ms.append(last["stats"]["sweep_ms"])
+        tail_ms.append(last["stats"]["tail_ms"])
+        topk_ms.append(last["stats"]["topk_ms"])
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": units / dt, "unit": "realization-sources/s", "cores": 1, "kind": "oracle",
-            "sample": f"{R} realizations of the same workload, {units} single-source passes (single-threaded C "
-                      f"oracle, {dt:.1f} s)"}
+    G.close()
+    return last, float(np.mean(sweep_ms)), float(np.mean(tail_ms)), float(np.mean(topk_ms)), dt
+
+
+def base_query(wl, args=None) -> dict:
+    q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
+             r_lower=wl.r_lower, pool=wl.pool, reward=wl.reward, hop_radius=wl.hop_radius)
+    if args is not None:
+        q.update(mode=args.mode, waves=args.waves, tile=args.tile, group=args.group)
+    return q
+
+
+def er5000_leg(ctx, amc) -> dict:
+    """One step of the n = 5000 unit-weight workload (R = 4096, pool of 50
+    with rewards) with its own rate, TEPS and roofline."""
+    wl = _workload("er5000")
+    last, k_ms, t_ms, _, dt = run_workload(ctx, amc, wl, base_query(wl), 1, 0)
+    st = last["stats"]
+    return {"workload": wl.name, "value": st["units"] / dt, "unit": "realization-sources/s", "ms_per_step": dt * 1e3,
+            "sweep_kernel_ms": k_ms, "tail_ms": t_ms, "teps": (st["sum_AK"] / 2) / (k_ms * 1e-3),
+            "near_band": st["near_band"],
+            "plan": {k: st[k] for k in ("mode", "waves", "tile", "blocks", "lds_bytes", "group", "dist_bytes",
+                                        "b_global", "tail_split")},
+            "roofline": roofline(st, k_ms, counter_record("er5000"))}
+
+
+def serving_leg(amc, queries: int, logR_hi: int, load: float) -> dict:
+    """Bounded serving trace: `queries` mixed-size queries (n log-uniform in
+    [50, 4000], R = 2^U{8..logR_hi}) submitted all at once to measure the
+    loop's capacity, then the same queries as a Poisson trace at `load` x
+    that capacity; latency = finish - submit."""
+    from paper_2605_14743_amd import workloads as W
+    cap = serve_trace(amc, W.serving_trace(count=queries, rate=1e9, seed=1, logR_hi=logR_hi))
+    rate = load * cap["throughput_qps"]
+    run = serve_trace(amc, W.serving_trace(count=queries, rate=rate, seed=1, logR_hi=logR_hi))
+    return {"queries": queries, "R_max": 2 ** logR_hi, "capacity_qps": cap["throughput_qps"],
+            "offered_qps": rate, "load": load, **{k: run[k] for k in ("throughput_qps", "value", "p50_ms", "p99_ms",
+                                                                       "wall_s", "max_overlap", "shared_launches")},
+            "saturated": {k: cap[k] for k in ("p50_ms", "p99_ms", "wall_s", "value", "max_overlap")}}
 
 
 def run_bench(args):
@@ -101,16 +262,12 @@ def run_bench(args):
     from paper_2605_14743_amd import amc
     from paper_2605_14743_amd import workloads as W
 
-    wl = {"ws1000": W.config_ws1000, "er5000": W.config_er5000, "er20": W.config_er20,
-          "cooc77": W.config_cooc77}[args.workload]()
+    wl = _workload(args.workload)
     g = wl.graph
     if args.R:
         wl.R = args.R
     ctx = amc.Context(0)
-    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
-    q = dict(seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, cert_topk=wl.cert_topk, eps=0.01,
-             r_lower=wl.r_lower, mode=args.mode, waves=args.waves, tile=args.tile, group=args.group,
-             pool=wl.pool, reward=wl.reward, hop_radius=wl.hop_radius)
+    q = base_query(wl, args)
     if args.dist32:
         q["flags"] = amc.DIST32
     if args.topk > 0:
@@ -124,28 +281,15 @@ def run_bench(args):
             pool, fb, _ = W.clique_pool(g, args.clique_pool)
             q.update(pool=pool, fb_node=fb, reward=None, gamma=None)
     model = wl.model()
-    last = None
-    for _ in range(args.warmup):
-        last = amc.run(ctx, G, model, out=last, **q)
-    torch.cuda.synchronize()
-    sweep_ms, tail_ms, topk_ms = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        # every step recomputes and copies back all results, into the host
-        # buffers the previous step used (no fresh allocation per step)
-        last = amc.run(ctx, G, model, out=last, **q)
-        sweep_ms.append(last["stats"]["sweep_ms"])
-        tail_ms.append(last["stats"]["tail_ms"])
-        topk_ms.append(last["stats"]["topk_ms"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    last, k_ms, tail_ms, topk_ms, dt = run_workload(ctx, amc, wl, q, args.steps, args.warmup)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
     st = last["stats"]
     units = st["units"]                      # single-source passes (R n for the row-wise sweep)
     value = units * args.steps / dt
-    k_ms = float(np.mean(sweep_ms))
-    ab = algorithmic_bytes(st)
-    achieved = ab / (k_ms * 1e-3) / 1e9
     teps = (st["sum_AK"] / 2) / (k_ms * 1e-3)
+    # the recorded counters belong to the default configuration of this workload
+    default_cfg = not (args.R or args.mode or args.waves or args.tile or args.group or args.dist32 or args.topk)
+    rec = counter_record(args.workload) if default_cfg else None
     out = {
         "metric": "realization-sources/sec",
         "value": value,
@@ -164,33 +308,32 @@ def run_bench(args):
                    "weights": wl.weight if wl.weight != "uniform" else f"uniform{{{wl.w_lo}..{wl.w_hi}}}",
                    "alpha": wl.alpha, "k_min": wl.k_min, "mode": st["mode"], "waves": st["waves"],
                    "tile": st["tile"], "blocks": st["blocks"], "lds_bytes": st["lds_bytes"], "group": st["group"],
-                   "adj_bytes": st["adj_bytes"], "dist_bytes": st["dist_bytes"], "b_global": st["b_global"]},
+                   "adj_bytes": st["adj_bytes"], "dist_bytes": st["dist_bytes"], "b_global": st["b_global"],
+                   "tail_split": st["tail_split"]},
         "sweep_kernel_ms": k_ms,
-        "tail_ms": float(np.mean(tail_ms)),
+        "tail_ms": tail_ms,
         "teps": teps,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": ab, "units_per_launch": st["units"],
-                     "above_peak": achieved > HBM_PEAK_GBS,
-                     "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / LDS_PEAK_GBS}},
+        # set members whose gap to the set maximum lies within [tau/4, 4 tau]
+        # of the tie band: where the two sides' rounding could decide a tie
+        "near_band": st["near_band"],
+        "roofline": roofline(st, k_ms, rec),
     }
     if args.topk > 0:
         # the Top-k stage reads every realization's B row and labels once
         # (16 B per vertex) and adds one step reward per valid anchor
-        tk = float(np.mean(topk_ms))
         tb = 16.0 * wl.R * g.n
-        out["topk_stage"] = {"k": args.topk, "pool": int(len(q["pool"])), "ms": tk, "bytes_read": tb,
-                             "GBps": tb / (tk * 1e-3) / 1e9, "b_k": last["b_k"], "b_kw": last["b_kw"],
-                             "share_of_step": tk / (dt / args.steps * 1e3)}
+        out["topk_stage"] = {"k": args.topk, "pool": int(len(q["pool"])), "ms": topk_ms, "bytes_read": tb,
+                             "GBps": tb / (topk_ms * 1e-3) / 1e9, "b_k": last["b_k"], "b_kw": last["b_kw"],
+                             "share_of_step": topk_ms / (dt / args.steps * 1e3)}
         if args.clique_pool > 0:
             out["topk_stage"].update({"clique_pool": args.clique_pool, "fb_node": int(q["fb_node"]),
                                       "m_w_fb": last["m_w_fb"], "c_fb": last["c_fb"], "E_T_fb": last["E_T_fb"],
                                       "top5_b_fb": np.argsort(-last["b_fb"], kind="stable")[:5].tolist()})
     if args.robust > 0:
         # robust tail on the estimated kernel: (samples + 2) Gauss-Jordan
-        # inversions (2 n^3 flops each) and two n x n products (2 n^3 each)
-        f = np.linspace(0.0, 1.0, g.n)
+        # inversions (2 n^3 flops each) and two n x n products (2 n^3 each);
+        # node values: the multi-reward value of the robust experiment
+        f = W.multi_reward(g)
         amc.robust(ctx, last["Q"], f=f, samples=2, delta=0.5, r_min=0.05, seed=1)
         rb = amc.robust(ctx, last["Q"], f=f, samples=args.robust, delta=0.5, r_min=0.05, seed=1)
         flops = (args.robust + 2) * 2.0 * g.n ** 3 + 2 * 2.0 * g.n ** 3
@@ -242,23 +385,11 @@ def run_bench(args):
         out["plain_gpu"] = {"value": pv, "unit": "realization-sources/s", "realizations": args.plain_R,
                             "launches": rp["stats"]["launches"], "sweep_ms": rp["stats"]["sweep_ms"],
                             "batched_sweep_ms_same_R": rb["stats"]["sweep_ms"],
-                            "batched_over_plain": value / pv}
-    if args.cpu_s > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_s)
-        if args.cpu_procs > 1:
-            out["cpu_baseline"]["all_cores"] = cpu_all_cores(args.workload, args.cpu_procs, args.cpu_s)
-    # the recorded counters belong to the default configuration of this workload
-    default_cfg = not (args.R or args.mode or args.waves or args.tile or args.group or args.dist32 or args.topk)
-    tr = traffic_record() if args.workload == "ws1000" and default_cfg else None
-    if tr is not None:
-        out["roofline"]["traffic"] = tr["sweep_bytes_per_launch"]
-        out["roofline"]["traffic_source"] = tr["source"]
-        if "valu_insts_per_unit" in tr:
-            # VALU issue: wave64 instructions per (r, s) from the SQ counters,
-            # against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction
-            ach = tr["valu_insts_per_unit"] * st["units"] / (k_ms * 1e-3) / 1e9
-            out["roofline"]["alu"] = {"achieved": ach, "peak": VALU_PEAK_GIPS, "unit": "G VALU wave64 instructions/s",
-                                      "frac": ach / VALU_PEAK_GIPS, "source": tr["valu_source"]}
+                            "batched_over_plain": value / pv, "target": PLAIN_TARGET,
+                            "target_met": value / pv >= PLAIN_TARGET}
+    G.close()
+    if args.er5000 and args.workload == "ws1000":
+        out["er5000"] = er5000_leg(ctx, amc)
     if args.copy_mib > 0:
         # calibration kernel for the HBM byte counters: a plain device copy of
         # known size on the same stream
@@ -267,37 +398,12 @@ def run_bench(args):
         b.copy_(a)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = args.copy_mib << 20
-    G.close()
     ctx.close()
+    if args.serve_queries > 0 and args.workload == "ws1000":
+        out["serving"] = serving_leg(amc, args.serve_queries, args.serve_logR_hi, args.serve_load)
+    if args.cpu_s > 0:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_procs or cpu_cores(), args.cpu_s)
     print(json.dumps(out), flush=True)
-
-
-SWEEP_SOURCES = ("amc_dev.hpp", "sweep_common.hpp", "wave_source.hpp", "sweep_wave.hip")
-
-
-def kernel_source_digest() -> str:
-    """Digest of the sources the LDS-mode sweep kernel is built from."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2605_14743_amd", "csrc")
-    for name in SWEEP_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def traffic_record():
-    """HBM bytes per sweep launch from the committed counter profile, or None
-    when the kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "sweep_wave_ws1000_R10000_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("kernel_source_sha256") != kernel_source_digest():
-        return None
-    return rec
 
 
 def run_batch(args):
@@ -397,16 +503,11 @@ def run_traj(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args):
-    """Poisson trace of mixed-size queries through amc_submit (continuous
-    batching); reports throughput and p50/p99 latency."""
+def serve_trace(amc, trace, ctx_budget: int = 0) -> dict:
+    """Runs a trace [(arrival_s, Workload)] through amc_submit; latency of a
+    query = its finish time - its submit time."""
     import torch
-
-    from paper_2605_14743_amd import amc
-    from paper_2605_14743_amd import workloads as W
-
-    trace = W.serving_trace(count=args.queries, rate=args.rate, seed=0, n_hi=args.n_hi, logR_hi=args.logR_hi)
-    ctx = amc.Context(0)
+    ctx = amc.Context(0, budget_bytes=ctx_budget)
     graphs = [amc.Graph(ctx, wl.graph.n, wl.graph.eu, wl.graph.ev) for _, wl in trace]
     torch.cuda.synchronize()
     reqs = []
@@ -417,24 +518,44 @@ def run_serve(args):
             time.sleep(ts - now)
         reqs.append(amc.Request(ctx, G, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min,
                                 cert_topk=5, eps=wl.eps, r_lower=wl.r_lower))
-    lat = []
+    lat, spans = [], []
     for r in reqs:
         r.wait()
         t = r.times()
         lat.append(t[2] - t[0])
+        spans.append((t[1], t[2]))
     dt = time.perf_counter() - t0
+    # most queries admitted at one time (their [admit, finish] intervals overlap)
+    ev = sorted([(a, 1) for a, _ in spans] + [(b, -1) for _, b in spans], key=lambda x: (x[0], x[1]))
+    cur = peak = 0
+    for _, d in ev:
+        cur += d
+        peak = max(peak, cur)
+    info = amc.server_info(ctx)
     units = sum(wl.R * wl.graph.n for _, wl in trace)
     lat = np.array(lat)
-    out = {"metric": "realization-sources/sec", "value": units / dt, "unit": "realization-sources/s",
-           "n_gpus": 1, "queries": len(trace), "rate": args.rate, "wall_s": dt,
+    out = {"value": units / dt, "unit": "realization-sources/s", "queries": len(trace), "wall_s": dt,
            "throughput_qps": len(trace) / dt, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-           "p99_ms": float(np.percentile(lat, 99) * 1e3), "data": "synthetic", "higher_is_better": True,
-           "config": {"workload": "poisson-serving", "n_hi": args.n_hi, "logR_hi": args.logR_hi}}
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_overlap": peak, **info}
     for r in reqs:
         r.close()
     for G in graphs:
         G.close()
     ctx.close()
+    return out
+
+
+def run_serve(args):
+    """Poisson trace of mixed-size queries through amc_submit (continuous
+    batching); reports throughput and p50/p99 latency."""
+    from paper_2605_14743_amd import amc
+    from paper_2605_14743_amd import workloads as W
+
+    trace = W.serving_trace(count=args.queries, rate=args.rate, seed=0, n_hi=args.n_hi, logR_hi=args.logR_hi)
+    res = serve_trace(amc, trace)
+    out = {"metric": "realization-sources/sec", "n_gpus": 1, "rate": args.rate, "data": "synthetic",
+           "higher_is_better": True, **res,
+           "config": {"workload": "poisson-serving", "n_hi": args.n_hi, "logR_hi": args.logR_hi}}
     print(json.dumps(out), flush=True)
 
 
@@ -453,7 +574,12 @@ def main():
     ap.add_argument("--dist32", action="store_true", help="32-bit distance entries (comparison runs)")
     ap.add_argument("--plain-R", dest="plain_R", type=int, default=200)
     ap.add_argument("--cpu-s", dest="cpu_s", type=float, default=12.0)
-    ap.add_argument("--cpu-procs", dest="cpu_procs", type=int, default=1,
+    ap.add_argument("--er5000", type=int, default=1, help="1: add one step of the n = 5000 workload")
+    ap.add_argument("--serve-queries", dest="serve_queries", type=int, default=32,
+                    help="queries of the bounded serving leg (0 = none)")
+    ap.add_argument("--serve-logR-hi", dest="serve_logR_hi", type=int, default=12)
+    ap.add_argument("--serve-load", dest="serve_load", type=float, default=0.8)
+    ap.add_argument("--cpu-procs", dest="cpu_procs", type=int, default=0,
                     help="also time the oracle in this many processes over disjoint realization ranges")
     ap.add_argument("--topk", type=int, default=0, help="also run the finite-k local Top-k rows with this k")
     ap.add_argument("--clique-pool", dest="clique_pool", type=int, default=0,

@@ -261,6 +261,23 @@ AMC_API void amc_request_destroy(amc_request *req);
  * t[0] submit, t[1] admitted, t[2] finished. */
 AMC_API int amc_request_times(amc_request *req, double t[3]);
 
+/* Counters of the context's serving loop since its start (all zero before the
+ * first amc_submit): the admission budget and the largest sum of admitted
+ * footprints (never above the budget), queries admitted and completed, the
+ * sweep launches the loop issued, how many of them carried work items of two
+ * or more queries, the most queries admitted at one time and the most
+ * queries that shared one launch. */
+typedef struct amc_server_stats {
+    uint64_t budget;            /* admission budget, bytes                       */
+    uint64_t peak_in_use;       /* largest sum of admitted footprints, bytes      */
+    uint64_t admitted, completed;
+    uint64_t launches;          /* sweep launches issued by the loop              */
+    uint64_t shared_launches;   /* launches carrying items of >= 2 queries         */
+    int32_t peak_active;        /* most queries admitted at one time              */
+    int32_t max_members;        /* most queries in one launch                     */
+} amc_server_stats;
+AMC_API int amc_server_info(amc_ctx *ctx, amc_server_stats *out);
+
 /* Persistent fused batch (Alg. 2 for several queries at once).  The queries
  * are grouped by kernel variant; each group is one persistent launch whose
  * work queue holds every member's (realization, source tile) items, largest

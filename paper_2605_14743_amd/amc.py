@@ -27,7 +27,7 @@ MAX_W1_N = 3000
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
-           "amc_request_destroy", "amc_request_times", "amc_batch_create", "amc_batch_run", "amc_batch_info",
+           "amc_request_destroy", "amc_request_times", "amc_server_info", "amc_batch_create", "amc_batch_run", "amc_batch_info",
            "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_bootstrap", "amc_chain",
            "amc_stability", "amc_strerror", "amc_version"]
 WANT_PATHS = 1
@@ -105,6 +105,12 @@ class TuneResult(C.Structure):
                 ("candidates", C.c_int32)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("budget", C.c_uint64), ("peak_in_use", C.c_uint64), ("admitted", C.c_uint64),
+                ("completed", C.c_uint64), ("launches", C.c_uint64), ("shared_launches", C.c_uint64),
+                ("peak_active", C.c_int32), ("max_members", C.c_int32)]
+
+
 class Stats(C.Structure):
     _fields_ = [("units", C.c_uint64), ("sum_nK", C.c_uint64), ("sum_AK", C.c_uint64), ("sum_DK", C.c_uint64),
                 ("near_band", C.c_uint64), ("sweep_ms", C.c_double), ("tail_ms", C.c_double), ("mode", C.c_int32),
@@ -163,6 +169,7 @@ def lib():
         L.amc_request_destroy.argtypes = [vp]
         L.amc_request_destroy.restype = None
         L.amc_request_times.argtypes = [vp, _P(C.c_double)]
+        L.amc_server_info.argtypes = [vp, _P(ServerStats)]
         L.amc_chain.argtypes = [vp, C.c_int32, _P(C.c_double), _P(Query), _P(Result)]
         L.amc_batch_create.argtypes = [vp, C.c_int32, _P(vp), _P(Model), _P(Query), _P(vp)]
         L.amc_batch_run.argtypes = [vp, _P(Result)]
@@ -385,6 +392,13 @@ def run(ctx: Context, graph: Graph, model: dict, out: dict | None = None, **quer
     _check(lib().amc_run(ctx.h, graph.h, C.byref(m), C.byref(q), C.byref(res)), "amc_run")
     del keep_m, keep_q
     return _collect(res, arr)
+
+
+def server_info(ctx: Context) -> dict:
+    """amc_server_info: counters of the context's serving loop."""
+    out = ServerStats()
+    _check(lib().amc_server_info(ctx.h, C.byref(out)), "amc_server_info")
+    return {f: getattr(out, f) for f, _ in ServerStats._fields_}
 
 
 class Request:

@@ -9,6 +9,7 @@
 // memory until its tail has finished and its results are copied out.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <memory>
@@ -53,7 +54,9 @@ struct Server {
     std::condition_variable cv;
     std::deque<std::shared_ptr<Request>> pending;
     uint64_t in_use = 0;
+    int active = 0;
     bool stop = false;
+    amc_server_stats st{};
 
     // Picks the next admissible request (caller holds mu); null if none fits.
     std::shared_ptr<Request> pick() {
@@ -79,12 +82,20 @@ struct Server {
                 cv.wait(lk, [&] { return (stop && pending.empty()) || (r = pick()) != nullptr; });
                 if (!r) return;
                 in_use += r->footprint;
+                ++active;
+                st.admitted++;
+                st.launches++;
+                st.peak_in_use = std::max(st.peak_in_use, in_use);
+                st.peak_active = std::max(st.peak_active, active);
+                st.max_members = std::max(st.max_members, 1);
             }
             r->t_admit = now_s();
             const int rc = run_query(ctx, r->g, &r->model, &r->q, r->out, streams[slot]);
             {
                 std::lock_guard<std::mutex> lk(mu);
                 in_use -= r->footprint;
+                --active;
+                st.completed++;
             }
             cv.notify_all();
             {
@@ -210,5 +221,18 @@ extern "C" int amc_request_times(amc_request *req, double t[3]) {
     t[0] = req->r->t_submit;
     t[1] = req->r->t_admit;
     t[2] = req->r->t_finish;
+    return AMC_OK;
+}
+
+extern "C" int amc_server_info(amc_ctx *ctx, amc_server_stats *out) {
+    if (!ctx || !out) return AMC_E_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->budget = ctx->budget;
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (ctx->server) {
+        std::lock_guard<std::mutex> lk2(ctx->server->mu);
+        *out = ctx->server->st;
+        out->budget = ctx->budget;
+    }
     return AMC_OK;
 }

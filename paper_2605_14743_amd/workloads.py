@@ -242,6 +242,40 @@ def crossroads() -> tuple[Graph, np.ndarray]:
     return g, p_fail
 
 
+def hop_distances(g: Graph, src: int) -> np.ndarray:
+    """Hop counts from src over the base graph's edges (-1 = unreachable)."""
+    adj = [[] for _ in range(g.n)]
+    for u, v in zip(g.eu.tolist(), g.ev.tolist()):
+        adj[u].append(v)
+        adj[v].append(u)
+    d = np.full(g.n, -1, dtype=np.int64)
+    d[src] = 0
+    frontier = [src]
+    while frontier:
+        nxt = []
+        for u in frontier:
+            for v in adj[u]:
+                if d[v] < 0:
+                    d[v] = d[u] + 1
+                    nxt.append(v)
+        frontier = nxt
+    return d
+
+
+def multi_reward(g: Graph, hubs: int = 3, R: float = 10.0, beta: float = 0.6) -> np.ndarray:
+    """Node values of the multi-reward experiment (Section 9.1): the `hubs`
+    vertices of largest base-graph degree (ties to the smaller index) carry
+    reward R each, and f(v) = max over hubs h of R beta^{d(v, h)}, d the hop
+    distance in the base graph; f(v) = 0 when no hub reaches v."""
+    deg = np.bincount(np.concatenate([g.eu, g.ev]), minlength=g.n)
+    order = sorted(range(g.n), key=lambda v: (-int(deg[v]), v))[:hubs]
+    f = np.zeros(g.n)
+    for h in order:
+        d = hop_distances(g, h)
+        f = np.maximum(f, np.where(d >= 0, R * beta ** np.maximum(d, 0), 0.0))
+    return f
+
+
 # ----------------------------------------------------------------------------- the five workloads
 @dataclasses.dataclass
 class Workload:

@@ -49,7 +49,8 @@ def test_struct_layouts_match_header():
                "amc_tune_result": amc.TuneResult, "amc_traj_query": amc.TrajQuery,
                "amc_traj_result": amc.TrajResult, "amc_robust_query": amc.RobustQuery,
                "amc_robust_result": amc.RobustResult, "amc_boot_query": amc.BootQuery,
-               "amc_boot_result": amc.BootResult, "amc_stability_result": amc.StabilityResult}
+               "amc_boot_result": amc.BootResult, "amc_stability_result": amc.StabilityResult,
+               "amc_server_stats": amc.ServerStats}
     lines = []
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')

@@ -27,31 +27,57 @@ def test_algorithmic_bytes():
     assert bench.algorithmic_bytes(st) == 8 * 10 + 32 * 7 + 64 * 3
 
 
-def test_traffic_record_follows_the_kernel_sources(tmp_path, monkeypatch):
+def test_counter_record_follows_the_kernel_and_planner_sources(tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2605_14743_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for name in bench.SWEEP_SOURCES:
+    for name in bench.KERNEL_SOURCES["sweep_wave"]:
         shutil.copy(os.path.join(ROOT, "paper_2605_14743_amd", "csrc", name), csrc / name)
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.traffic_record() is None                    # no record
-    rec = {"kernel_source_sha256": bench.kernel_source_digest(), "sweep_bytes_per_launch": 1.0e9, "source": "x"}
-    path = tmp_path / "profiles" / "sweep_wave_ws1000_R10000_traffic.json"
+    assert bench.counter_record("ws1000") is None                  # no record
+    rec = {"kernel_source_sha256": bench.kernel_source_digest("sweep_wave"), "hbm_bytes_per_unit": 170.0,
+           "valu_insts_per_unit": 17000.0, "lds_idx_active_per_unit": 8000.0}
+    path = tmp_path / "profiles" / bench.COUNTER_RECORDS["ws1000"][1]
     path.write_text(json.dumps(rec))
-    assert bench.traffic_record()["sweep_bytes_per_launch"] == 1.0e9
-    (csrc / bench.SWEEP_SOURCES[-1]).write_text("// changed\n")
-    assert bench.traffic_record() is None                    # sources changed since the counters
+    assert bench.counter_record("ws1000")["valu_insts_per_unit"] == 17000.0
+    for name in ("wave_source.hpp", "amc_api.cpp", "query.cpp"):   # kernel and planner sources
+        keep = (csrc / name).read_text()
+        (csrc / name).write_text(keep + "// changed\n")
+        assert bench.counter_record("ws1000") is None, name        # sources changed since the counters
+        (csrc / name).write_text(keep)
+        assert bench.counter_record("ws1000") is not None
 
 
-def test_committed_traffic_record_is_well_formed():
-    path = os.path.join(ROOT, "profiles", "sweep_wave_ws1000_R10000_traffic.json")
-    rec = json.load(open(path))
-    assert len(rec["kernel_source_sha256"]) == 64 and rec["sweep_bytes_per_launch"] > 0
+def test_roofline_names_the_binding_resource():
+    st = {"units": 10_000_000, "sum_DK": 10**10, "sum_AK": 10**10, "sum_nK": 10**10}
+    rec = {"valu_insts_per_unit": 17000.0, "hbm_bytes_per_unit": 176.0, "lds_idx_active_per_unit": 8000.0,
+           "lds_bank_conflict_per_unit": 3000.0, "source": "x"}
+    r = bench.roofline(st, 400.0, rec)
+    assert r["bound"] == "alu" and 0.0 < r["frac"] <= 1.0
+    assert r["achieved"] == pytest.approx(17000.0 * 1e7 / 0.4 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / bench.VALU_PEAK_GIPS)
+    assert r["traffic"] == pytest.approx(176.0 * 1e7)
+    assert r["hbm"]["frac"] < 1.0 and 0.0 < r["lds"]["frac"] < 1.0
+    assert r["algorithmic"]["bytes_per_launch"] == bench.algorithmic_bytes(st)
+    stale = bench.roofline(st, 400.0, None)
+    assert stale["bound"] == "alu" and stale["frac"] is None and stale["traffic"] is None
 
 
-def test_cpu_baseline_legs():
-    wl = W.config_er20()
-    one = bench.cpu_baseline(wl, 0.2)
-    assert one["kind"] == "oracle" and one["cores"] == 1 and one["value"] > 0
-    many = bench.cpu_all_cores("er20", 2, 0.2)
-    assert many["kind"] == "oracle" and many["cores"] == 2 and many["value"] > 0
+def test_committed_counter_records_are_well_formed():
+    found = 0
+    for kernel, fname in bench.COUNTER_RECORDS.values():
+        path = os.path.join(ROOT, "profiles", fname)
+        if not os.path.exists(path):
+            continue
+        rec = json.load(open(path))
+        assert len(rec["kernel_source_sha256"]) == 64 and rec["hbm_bytes_per_unit"] > 0
+        assert rec["valu_insts_per_unit"] > 0
+        found += 1
+    if not found:
+        pytest.skip("no counter record committed")
+
+
+def test_cpu_baseline_all_cores():
+    many = bench.cpu_baseline("er20", 2, 0.2)
+    assert many["kind"] == "oracle" and many["cores"] == 2 and many["value"] > 0 and many["cpu_model"]
+    assert 1 <= bench.cpu_cores() <= 16

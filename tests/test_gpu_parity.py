@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import par_oracle as P
 from paper_2605_14743_amd import amc
 from paper_2605_14743_amd import workloads as W
 
@@ -493,3 +494,147 @@ def test_anchored_arguments(ctx):
             amc.run(ctx, G, {"p_fail": 0.1}, R=4, **bad)
         assert ei.value.rc == amc.E_INVALID_ARG, bad
     G.close()
+
+
+# --------------------------------------------------------------------------- the benchmark's own launch plan
+# ws1000 (Watts-Strogatz n = 1000, k = 10, beta = 0.1; failure 0.05; weights
+# U{1..10}; R = 10000) as the benchmark runs it: L2 mode, whole realizations
+# (tile = n), 11 wavefronts, one lane per vertex, 16-bit adjacency entries,
+# 32-bit distances, B(H_r) in LDS; the last R mod 256 + 256 realizations split
+# into tiles.
+BENCH_PLAN = {"mode": amc.MODE_WAVE_L2, "tile": 1000, "waves": 11, "group": 1, "adj_bytes": 2, "dist_bytes": 4,
+              "b_global": 0}
+
+
+def _assert_bench_plan(st):
+    for k, v in BENCH_PLAN.items():
+        assert st[k] == v, f"plan field {k}: {st[k]} != {v} ({st})"
+
+
+def _oracle_rows(g, wl, rs):
+    """Oracle next-state rows and global centres of single realizations."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(P.workers()) as ex:
+        outs = list(ex.map(lambda r: O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=1, r_begin=int(r), alpha=wl.alpha,
+                                             k_min=wl.k_min, want_next=True, want_bsum=False, **wl.model()), rs))
+    return outs
+
+
+def test_ws1000_bench_plan_full_R_sampled(ctx):
+    # the full R = 10000 launch exactly as timed by the benchmark; sampled
+    # realizations from both the whole-realization descriptor and the split
+    # last realizations against the oracle, one realization at a time
+    wl = W.config_ws1000()
+    g = wl.graph
+    res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.SKIP_TAIL)
+    st = res["stats"]
+    _assert_bench_plan(st)
+    assert st["blocks"] == 256 and st["tail_split"] == wl.R % 256 + 256 and st["tail_tiles"] >= 16, st
+    R0 = wl.R - st["tail_split"]
+    # counts are the histogram of the next-state table
+    nt = res["next_table"]
+    hist = np.zeros((g.n, g.n + 1), dtype=np.int64)
+    cols = np.where(nt >= 0, nt, g.n)
+    np.add.at(hist, (np.broadcast_to(np.arange(g.n), nt.shape), cols), 1)
+    assert np.array_equal(hist, res["counts"].astype(np.int64))
+    assert st["units"] == wl.R * g.n
+    rs = [0, 1, 255, 256, 2500, 7777, R0 - 1, R0, R0 + 100, 9990, 9999]
+    say(f"[cpu] oracle on {len(rs)} sampled ws1000 realizations")
+    for r, o in zip(rs, _oracle_rows(g, wl, rs)):
+        assert np.array_equal(nt[r], o["next_table"][0]), f"next table row r={r}"
+        assert res["center_global"][r] == o["center_global"][0], f"centre r={r}"
+
+
+def test_ws1000_bench_plan_against_oracle(ctx):
+    # the benchmark's plan forced on R = 256 + 37 realizations: 256 whole
+    # realizations on the benchmark's instantiation, the last 37 split into
+    # tiles; everything against the oracle over the same range
+    wl = W.config_ws1000()
+    g = wl.graph
+    plan = {k: BENCH_PLAN[k] for k in ("mode", "tile", "waves", "group")}
+    R = 256 + 37
+    res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, alpha=wl.alpha, k_min=wl.k_min, flags=FLAGS, cert_topk=5,
+                  **plan)
+    st = res["stats"]
+    _assert_bench_plan(st)
+    assert st["blocks"] == 256 and st["tail_split"] == 37, st
+    say(f"[cpu] oracle on ws1000 R={R} in {P.workers()} threads")
+    ref = P.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, alpha=wl.alpha, k_min=wl.k_min, want_next=True, **wl.model())
+    check_sweep(res, ref, g.n, "ws1000 bench plan")
+    assert st["near_band"] == ref["stats"]["near_band"]
+    t = O.tail(ref["counts"], R, cert_topk=5)
+    assert_close_norm(res["N"], t["N"], what="N")
+    assert_close_norm(res["mu"], t["mu"], what="mu")
+    assert_close_norm(res["b"], t["b"], what="b")
+    assert abs(res["E_T"] - t["ET"]) <= TOL * t["ET"]
+    # whole realizations only, at spread realization indices
+    for r0 in (2500, 7777, 9990):
+        res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=2, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
+                      flags=FLAGS | amc.SKIP_TAIL, **plan)
+        _assert_bench_plan(res["stats"])
+        assert res["stats"]["tail_split"] == 0
+        ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=2, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
+                      want_next=True, **wl.model())
+        check_sweep(res, ref, g.n, f"ws1000 bench plan r0={r0}")
+
+
+# --------------------------------------------------------------------------- exact ties with nonzero betweenness
+# Vertex-transitive graphs without failures: every vertex has the same B, so
+# every realization's centres are vertex 0 (the smallest index, Corollary on
+# deterministic tie-breaking), whatever order the FP64 additions took.
+def _cycle(n):
+    return W.canonical(n, [(i, i + 1) for i in range(n - 1)] + [(0, n - 1)], name=f"C{n}")
+
+
+def _complete(n):
+    return W.canonical(n, [(i, j) for i in range(n) for j in range(i + 1, n)], name=f"K{n}")
+
+
+def _cycle_b(n):
+    """B of every vertex of the cycle C_n over ordered pairs (Section 3.1): with
+    k = floor(n / 2), k (k - 1) for odd n and (k - 1)^2 for even n (the two
+    antipodal paths share each pair's weight)."""
+    k = n // 2
+    return float(k * (k - 1)) if n % 2 else float((k - 1) ** 2)
+
+
+_TIE_GRAPHS = {"C1001": lambda: _cycle(1001), "C1000": lambda: _cycle(1000), "K40": lambda: _complete(40),
+               "ring1000": lambda: W.ws_graph(1000, 10, 0.0, 0)}
+_TIE_MODES = [(amc.MODE_WAVE, {}), (amc.MODE_WAVE, {"group": 2}), (amc.MODE_WAVE, {"group": 3}),
+              (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"tile": 333}), (amc.MODE_WAVE, {"flags": amc.DIST16}),
+              (amc.MODE_WAVE_L2, {}), (amc.MODE_WAVE_L2, {"group": 8}), (amc.MODE_WAVE_L2, {"flags": amc.DIST16}),
+              (amc.MODE_BLOCK, {})]
+_tie_ref = {}
+
+
+@pytest.mark.parametrize("weights", ["unit", "const3"])
+@pytest.mark.parametrize("graph", sorted(_TIE_GRAPHS))
+def test_symmetric_ties_every_mode(ctx, graph, weights):
+    g = _TIE_GRAPHS[graph]()
+    model = {"p_fail": 0.0, "weight": "unit"} if weights == "unit" else \
+        {"p_fail": 0.0, "weight": "uniform", "w_lo": 3, "w_hi": 3}
+    R = 24
+    kw = dict(seed=11, R=R, alpha=0.15, k_min=5)
+    key = (graph, weights)
+    if key not in _tie_ref:
+        _tie_ref[key] = P.sweep(g.n, g.eu, g.ev, want_next=True, **kw, **model)
+    ref = _tie_ref[key]
+    # the oracle itself: every valid anchor moves to vertex 0, every centre is 0
+    assert np.all(ref["center_global"] == 0)
+    assert np.all((ref["next_table"] == 0) | (ref["next_table"] == -1))
+    bv = ref["bsum"] / R
+    if graph.startswith("C"):
+        assert_rel(bv, np.full(g.n, _cycle_b(g.n)), what="cycle closed form")
+    elif graph.startswith("K"):
+        assert np.all(bv == 0.0)
+    else:
+        assert_rel(bv, np.full(g.n, bv[0]), what="ring lattice symmetry")
+    for mode, extra in _TIE_MODES:
+        extra = dict(extra)
+        fl = FLAGS | amc.SKIP_TAIL | extra.pop("flags", 0)
+        if (fl & amc.DIST16) and weights == "const3" and g.n * 3 >= 0xFFFF:
+            continue
+        res = gpu_run(ctx, g, model, flags=fl, mode=mode, **kw, **extra)
+        assert res["stats"]["mode"] == mode
+        check_sweep(res, ref, g.n, f"{graph} {weights} mode {mode} {extra}")

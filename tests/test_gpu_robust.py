@@ -95,3 +95,28 @@ def test_robust_arguments(ctx):
     with pytest.raises(amc.AmcError) as ei:
         amc.robust(ctx, bad_rows)
     assert ei.value.rc == amc.E_INVALID_ARG
+
+
+def test_multi_reward_value_of_section_9_1(ctx):
+    # the multi-reward experiment: f(v) = max over the three largest-degree
+    # hubs of 10 * 0.6^hops (0 when unreachable) on a WS(200) estimate; the
+    # node-reward AFC b . f of the run, and the switching and improvement
+    # transition reward-AFCs of the robust tail, against the oracle
+    g = W.ws_graph(200, 6, 0.1, 4)
+    f = W.multi_reward(g)
+    assert f.max() == 10.0 and np.count_nonzero(f == 10.0) == 3
+    model = {"p_fail": 0.15, "weight": "unit"}
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    print("[gpu] multi-reward ws200", flush=True)
+    res = amc.run(ctx, G, model, seed=5, R=400, reward=f)
+    G.close()
+    ref = O.sweep(g.n, g.eu, g.ev, seed=5, R=400, **model)
+    assert np.array_equal(res["counts"], ref["counts"])
+    t = O.tail(ref["counts"], 400, f=f)
+    close(res["b"], t["b"], 1e-12, "b")
+    assert res["b_f"] == pytest.approx(t["b_f"], rel=1e-12)
+    assert res["b_f"] == pytest.approx(float(t["b"] @ f), rel=1e-12)
+    gr = amc.robust(ctx, res["Q"], f=f, samples=8, delta=0.3, r_min=0.05, seed=9)
+    o = O.robust(t["Q"], f=f, samples=8, delta=0.3, r_min=0.05, seed=9)
+    compare(gr, o, "multi-reward")
+    assert gr["b_imp"] > 0.0 and gr["b_sw"] > 0.0

@@ -1,11 +1,16 @@
 """GPU systems checks: the persistent fused batch (hipGraph replays) and the
-serving loop give, for every query, exactly what a standalone amc_run gives."""
+serving loop give, for every query, exactly what a standalone amc_run gives,
+and every member of the mixes agrees with the CPU oracle (counts, next-state
+tables and centres bit-exact; sums of B within 1e-12 relative; the tail
+within 1e-12 of the max norm)."""
 import sys
 import time
 
 import numpy as np
 import pytest
 
+import oracle as O
+import par_oracle as P
 from paper_2605_14743_amd import amc
 from paper_2605_14743_amd import workloads as W
 
@@ -29,7 +34,7 @@ def ctx():
 def mixed_items(ctx, count, R, seed=0):
     wls = W.config_mixed_batch(count=count, R=R, seed=seed)
     # keep the graphs small enough for a quick test, mixing the three sweep modes
-    out = []
+    out, graphs = [], []
     for k, wl in enumerate(wls):
         g = wl.graph
         model = wl.model()
@@ -59,7 +64,31 @@ def mixed_items(ctx, count, R, seed=0):
         if k == 5:                                   # finite-k Top-k rewards and selector
             q.update(topk=3, pool=np.arange(1, g.n, 5, dtype=np.int32), gamma=np.linspace(0.5, 2.0, g.n))
         out.append((G, model, q))
-    return out
+        graphs.append(g)
+    return out, graphs
+
+
+def oracle_check(g, model, q, res, what):
+    """One member of a mix against the oracle over the same realizations."""
+    pool = q.get("pool")
+    say(f"[cpu] oracle {what}: n={g.n} R={q['R']}")
+    ref = P.sweep(g.n, g.eu, g.ev, seed=q["seed"], R=q["R"], alpha=q["alpha"], k_min=q["k_min"], want_next=True,
+                  pool=pool, topk=q.get("topk", 0), gamma=q.get("gamma"), hop_radius=q.get("hop_radius", 0),
+                  **model)
+    for key in ("counts", "counts_w", "next_table", "center_global"):
+        if key in res and key in ref:
+            assert np.array_equal(res[key], ref[key]), f"{what}: {key} differs from the oracle"
+    for key in ("bsum", "psi", "psi_w"):
+        if key in res and key in ref:
+            assert np.allclose(res[key], ref[key] / (q["R"] if key != "bsum" else 1), rtol=1e-12, atol=0), \
+                f"{what}: {key} differs from the oracle"
+    for key in ("units", "sum_nK", "sum_AK", "sum_DK"):
+        assert res["stats"][key] == ref["stats"][key], f"{what}: {key}"
+    t = O.tail(ref["counts"], q["R"], pool=pool, counts_w=ref.get("counts_w"), eps=q["eps"], r_lower=q["r_lower"],
+               cert_topk=q["cert_topk"])
+    for key in ("b", "mu"):
+        scale = np.abs(t[key]).max()
+        assert np.abs(res[key] - t[key]).max() <= 1e-12 * scale, f"{what}: {key} differs from the oracle"
 
 
 def same(a, b, what):
@@ -78,7 +107,7 @@ def same(a, b, what):
 
 
 def test_batch_matches_standalone_runs_over_replays(ctx):
-    items = mixed_items(ctx, 12, 96)
+    items, graphs = mixed_items(ctx, 12, 96)
     say(f"[gpu] batch of {len(items)} graphs, n = {[G.n for G, _, _ in items]}")
     ref = [amc.run(ctx, G, model, **q) for G, model, q in items]
     modes = {r["stats"]["mode"] for r in ref}
@@ -92,12 +121,14 @@ def test_batch_matches_standalone_runs_over_replays(ctx):
             same(a, b, f"replay {rep} query {k}")
         amc.run(ctx, items[0][0], items[0][1], **items[0][2])
     B.close()
+    for k, ((G, model, q), g) in enumerate(zip(items, graphs)):
+        oracle_check(g, model, q, got[k], f"batch member {k}")
     for G, _, _ in items:
         G.close()
 
 
 def test_serving_results_equal_standalone(ctx):
-    items = mixed_items(ctx, 10, 64, seed=3)
+    items, graphs = mixed_items(ctx, 10, 64, seed=3)
     ref = [amc.run(ctx, G, model, **q) for G, model, q in items]
     say("[gpu] serving mix")
     reqs = [amc.Request(ctx, G, model, **q) for G, model, q in items]
@@ -106,6 +137,8 @@ def test_serving_results_equal_standalone(ctx):
         same(a, b, f"served query {k}")
     times = [r.times() for r in reqs]
     assert all(t[0] <= t[1] <= t[2] for t in times)
+    for k, ((G, model, q), g) in enumerate(zip(items, graphs)):
+        oracle_check(g, model, q, got[k], f"served member {k}")
     for r in reqs:
         r.close()
     for G, _, _ in items:

@@ -256,3 +256,19 @@ def test_band_rule_on_rounding_ties():
     assert O.band_argmax(B, np.array([1, 1, 0, 0, 0], np.uint8))[0] == 0
     assert O.band_argmax(B, np.array([0, 0, 1, 1, 1], np.uint8))[0] == 2
     assert O.band_argmax(B, np.array([0, 0, 1, 1, 1], np.uint8), tau=1e-15)[0] == 3
+
+
+@pytest.mark.parametrize("n", [5, 6, 9, 12])
+def test_closed_form_cycle(n):
+    """Cycle C_n, ordered pairs: with k = floor(n/2), every vertex has B =
+    k(k-1) for odd n; for even n the antipodal pairs split over two paths,
+    giving (k-1)^2.  Checked against brute-force path enumeration as well."""
+    c = W.canonical(n, [(i, i + 1) for i in range(n - 1)] + [(0, n - 1)])
+    B = O.betweenness(n, c.eu, c.ev)
+    k = n // 2
+    want = k * (k - 1) if n % 2 else (k - 1) ** 2
+    assert np.allclose(B, want, rtol=1e-14, atol=0)
+    one = np.ones(c.m, np.uint8)
+    ex, _, _ = brute_force(n, c.eu, c.ev, one, np.ones(c.m, np.uint32))
+    assert [float(x) for x in ex] == [float(want)] * n
+    assert O.band_argmax(B, np.ones(n, np.uint8))[0] == 0
