@@ -599,7 +599,9 @@ def _cycle_b(n):
     return float(k * (k - 1)) if n % 2 else float((k - 1) ** 2)
 
 
-_TIE_GRAPHS = {"C1001": lambda: _cycle(1001), "C1000": lambda: _cycle(1000), "K40": lambda: _complete(40),
+# K_29 is the largest complete graph whose per-edge staging (one byte per
+# edge) fits the workgroup-per-source mode's 28 n bytes of LDS
+_TIE_GRAPHS = {"C1001": lambda: _cycle(1001), "C1000": lambda: _cycle(1000), "K29": lambda: _complete(29),
                "ring1000": lambda: W.ws_graph(1000, 10, 0.0, 0)}
 _TIE_MODES = [(amc.MODE_WAVE, {}), (amc.MODE_WAVE, {"group": 2}), (amc.MODE_WAVE, {"group": 3}),
               (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"tile": 333}), (amc.MODE_WAVE, {"flags": amc.DIST16}),
