@@ -64,6 +64,7 @@ extern "C" {
 #define AMC_E_ADMISSION (-6)      /* query footprint exceeds the context budget */
 #define AMC_E_NOT_READY (-7)      /* amc_poll: the request is still running */
 #define AMC_E_UNSUPPORTED (-8)    /* the shape exceeds an engine limit      */
+#define AMC_E_SCRATCH (-9)        /* amc_sweep_static: the query needs more than the static scratch */
 
 /* ------------------------------------------------------------ weight law */
 #define AMC_WEIGHT_UNIT 0         /* every surviving edge has weight 1 (BFS)   */
@@ -469,6 +470,40 @@ typedef struct amc_stability_result {
 } amc_stability_result;
 AMC_API int amc_stability(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q, int32_t k,
                           amc_stability_result *out);
+
+/* Sweep without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It computes what amc_run computes with AMC_SKIP_TAIL --
+ * the counts C (and, with d_center, the global centres c(H_r)) over the
+ * realizations r_begin .. r_begin + R - 1, in the same launch plan -- into
+ * caller-owned DEVICE buffers:
+ *   d_counts  n x (n+1) uint32, row-major, column n = bottom (required;
+ *             overwritten, not accumulated into)
+ *   d_center  R int32 or NULL
+ *   stats     host, or NULL: the run's counters and plan (sweep_ms from the
+ *             context's events)
+ * Every device buffer the sweep needs beyond these (descriptors, work and
+ * statistics counters, error flags, the per-workgroup scratch of the L2 and
+ * workgroup-per-source modes, the partial-B exchange of split realizations)
+ * is carved from one file-scope device array of AMC_STATIC_SCRATCH_BYTES that
+ * each device holds from the library's first context on it until the process
+ * ends; no allocator is called.  Calls on one device share that array and
+ * keep the last call's contents there (each call clears what it needs); the
+ * library serialises them per device, so calls never overlap on one device
+ * within a process -- a caller that drives the same device from several
+ * threads waits.  The call returns when the sweep has finished on the
+ * context stream.
+ * Accepted queries: no pool, topk, fallback, debug pairs, hop_radius,
+ * per-edge failure probabilities or AMC_WEIGHT_TABLE; flags only AMC_DIST16,
+ * AMC_DIST32 and AMC_SKIP_TAIL (s, reward, eps, r_lower and cert_topk are
+ * ignored: there is no tail).  Errors: AMC_E_INVALID_ARG for the above and
+ * for what amc_run rejects; AMC_E_SCRATCH when the plan needs more scratch
+ * than the array holds (checked before anything is launched); AMC_E_HIP when
+ * the array's address could not be obtained on this device; otherwise those
+ * of amc_run. */
+#define AMC_STATIC_SCRATCH_BYTES (64u << 20)
+AMC_API int amc_sweep_static(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q,
+                             uint32_t *d_counts, int32_t *d_center, amc_stats *stats);
 
 /* Chain algebra alone on a given transient block Q (n x n, row sums < 1) with
  * absorption r = 1 - Q 1: N, mu, E_T, b, rewards and certificates exactly as

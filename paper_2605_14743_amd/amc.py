@@ -15,8 +15,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libamc.so")
 
-OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NOT_READY, E_UNSUPPORTED = \
-    0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, E_INVALID_ARG, E_OOM, E_HIP, E_SIGMA_OVERFLOW, E_SINGULAR, E_ADMISSION, E_NOT_READY, E_UNSUPPORTED, E_SCRATCH = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED, WEIGHT_TABLE = 0, 1, 2, 3
 MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK, DIST32, DIST16 = \
@@ -24,12 +24,13 @@ WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LA
 MAX_TOPK, MAX_TOPK_N = 64, 7000
 MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
 MAX_W1_N = 3000
+STATIC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",
            "amc_graph_destroy", "amc_footprint", "amc_run", "amc_submit", "amc_poll", "amc_wait",
            "amc_request_destroy", "amc_request_times", "amc_server_info", "amc_batch_create", "amc_batch_run", "amc_batch_info",
            "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_bootstrap", "amc_chain",
-           "amc_stability", "amc_strerror", "amc_version"]
+           "amc_stability", "amc_sweep_static", "amc_strerror", "amc_version"]
 WANT_PATHS = 1
 
 _P = C.POINTER
@@ -181,6 +182,7 @@ def lib():
         L.amc_robust.argtypes = [vp, C.c_int32, _P(C.c_double), _P(RobustQuery), _P(RobustResult)]
         L.amc_bootstrap.argtypes = [vp, C.c_int32, C.c_uint32, _P(C.c_int32), _P(BootQuery), _P(BootResult)]
         L.amc_stability.argtypes = [vp, vp, _P(Model), _P(Query), C.c_int32, _P(StabilityResult)]
+        L.amc_sweep_static.argtypes = [vp, vp, _P(Model), _P(Query), vp, vp, _P(Stats)]
         L.amc_strerror.argtypes = [C.c_int]
         L.amc_strerror.restype = C.c_char_p
         L.amc_version.argtypes = []
@@ -399,6 +401,20 @@ def server_info(ctx: Context) -> dict:
     out = ServerStats()
     _check(lib().amc_server_info(ctx.h, C.byref(out)), "amc_server_info")
     return {f: getattr(out, f) for f, _ in ServerStats._fields_}
+
+
+def sweep_static(ctx: Context, graph: Graph, model: dict, d_counts: int, d_center: int | None = None,
+                 **query) -> dict:
+    """amc_sweep_static: the sweep into caller-owned device buffers (addresses
+    d_counts: n x (n+1) uint32, d_center: R int32 or None) without any device
+    allocation; returns the run's counters and plan."""
+    m, keep_m = make_model(**model)
+    q, keep_q = make_query(graph.n, **query)
+    st = Stats()
+    _check(lib().amc_sweep_static(ctx.h, graph.h, C.byref(m), C.byref(q), C.c_void_p(int(d_counts)),
+                                  C.c_void_p(int(d_center) if d_center else 0), C.byref(st)), "amc_sweep_static")
+    del keep_m, keep_q
+    return {f: getattr(st, f) for f, _ in Stats._fields_}
 
 
 class Request:

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = ["amc_api.cpp", "query.cpp", "batch.cpp", "server.cpp", "tune.cpp", "sweep_wave.hip", "sweep_block.hip",
            "tail.hip", "topk.hip", "traj.hip", "traj_host.cpp", "anchored.hip", "robust.hip", "robust_host.cpp",
-           "w1.hip", "boot.hip", "boot_host.cpp", "stability.cpp"]
+           "w1.hip", "boot.hip", "boot_host.cpp", "stability.cpp", "noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -30,6 +30,12 @@ int DevArena::alloc(size_t bytes, void **out) {
     if (bytes == 0) return AMC_OK;
     void *p = nullptr;
     const size_t sz = (bytes + 255) & ~(size_t)255;
+    if (fixed) {
+        if (sz > fixed_cap - fixed_used) return AMC_E_SCRATCH;
+        *out = fixed + fixed_used;
+        fixed_used += sz;
+        return AMC_OK;
+    }
     const hipError_t e = (stream && async) ? hipMallocAsync(&p, sz, stream) : hipMalloc(&p, sz);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -41,6 +47,10 @@ int DevArena::alloc(size_t bytes, void **out) {
 }
 
 void DevArena::release() {
+    if (fixed) {
+        fixed_used = 0;
+        return;
+    }
     for (void *p : ptrs) {
         if (stream && async) (void)hipFreeAsync(p, stream);
         else (void)hipFree(p);
@@ -106,6 +116,16 @@ extern "C" int amc_ctx_create(int device, uint64_t hbm_budget_bytes, amc_ctx **o
         return AMC_E_HIP;
     }
     c->stream = c->own;
+    if (hipEventCreate(&c->static_ev[0]) != hipSuccess || hipEventCreate(&c->static_ev[1]) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->static_ev[0]) (void)hipEventDestroy(c->static_ev[0]);
+        (void)hipStreamDestroy(c->own);
+        delete c;
+        return AMC_E_HIP;
+    }
+    // the no-allocation entry point's scratch: its address on this device
+    // (a failure only disables amc_sweep_static, which then reports it)
+    (void)static_scratch_init(device);
     tune_load(c);
     *out = c;
     return AMC_OK;
@@ -116,6 +136,8 @@ extern "C" void amc_ctx_destroy(amc_ctx *ctx) {
     server_stop(ctx);
     (void)hipSetDevice(ctx->device);
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    for (hipEvent_t e : ctx->static_ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -231,6 +253,7 @@ extern "C" const char *amc_strerror(int status) {
         case AMC_E_ADMISSION: return "query footprint exceeds the context budget";
         case AMC_E_NOT_READY: return "request not finished";
         case AMC_E_UNSUPPORTED: return "shape exceeds an engine limit";
+        case AMC_E_SCRATCH: return "the no-allocation scratch array is too small for this query";
         default: return "unknown status";
     }
 }

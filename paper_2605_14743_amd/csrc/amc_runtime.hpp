@@ -16,11 +16,16 @@
 
 namespace amc {
 
-// Stream-ordered device allocations of one query, released together.
+// Stream-ordered device allocations of one query, released together.  With
+// `fixed` set, alloc() carves 256-byte aligned pieces out of that caller-given
+// device region instead (no allocator call of any kind; AMC_E_SCRATCH when
+// the region is full) and release() forgets them.
 struct DevArena {
     hipStream_t stream = nullptr;    // allocation stream
     bool async = false;              // stream-ordered allocator available
     std::vector<void *> ptrs;
+    char *fixed = nullptr;
+    size_t fixed_cap = 0, fixed_used = 0;
     int alloc(size_t bytes, void **out);
     void release();
 };
@@ -91,6 +96,7 @@ struct amc_ctx {
     std::mutex tune_mu;
     std::map<amc::TuneKey, amc::TuneChoice> tune;
     std::string tune_path;
+    hipEvent_t static_ev[2] = {nullptr, nullptr};   // timing events of amc_sweep_static (made at creation)
 };
 
 struct amc_graph {
@@ -119,5 +125,8 @@ void tune_load(amc_ctx *ctx);
 int run_query(amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q, amc_result *out,
               hipStream_t st);
 void server_stop(amc_ctx *ctx);
+// Looks up, once per device (the device current), the address of that
+// device's copy of the no-allocation scratch array.
+int static_scratch_init(int device);
 
 }  // namespace amc

@@ -120,12 +120,17 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
     void *p;
     SweepParams &P = R.P;
     const size_t cnt = (size_t)n * (n + 1);
-    RCHK(A.alloc(4 * cnt, &p)); P.counts = (uint32_t *)p;
+    if (R.ext_counts) P.counts = R.ext_counts;
+    else {
+        RCHK(A.alloc(4 * cnt, &p));
+        P.counts = (uint32_t *)p;
+    }
     if (q->pool_size > 0) {
         RCHK(A.alloc(4 * cnt, &p));
         R.cw = (uint32_t *)p;
     }
-    if (q->flags & AMC_WANT_CENTER) {
+    if (R.ext_center) P.center_global = R.ext_center;
+    else if (q->flags & AMC_WANT_CENTER) {
         RCHK(A.alloc(4 * (size_t)Rn, &p));
         P.center_global = (int32_t *)p;
     }

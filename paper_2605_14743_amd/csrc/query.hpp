@@ -58,6 +58,9 @@ struct QueryRun {
     SweepParams P2{};
     int nq = 1;
     TailBufs T;
+    // caller-owned device outputs used instead of allocated ones (no-allocation entry point)
+    uint32_t *ext_counts = nullptr;
+    int32_t *ext_center = nullptr;
 };
 
 int qr_init(QueryRun &R, amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_query *q);
