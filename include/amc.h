@@ -94,6 +94,11 @@ extern "C" {
                                          more sources in flight.  Results are identical.
                                          Both flags: AMC_E_INVALID_ARG.  The workgroup-per-
                                          source and anchored kernels keep 32-bit entries. */
+#define AMC_SIGMA_GLOBAL (1u << 10)   /* L2 mode with every wavefront's path counts in the per-workgroup
+                                         global scratch instead of LDS (more sources in flight on large
+                                         graphs); needs a lane-per-vertex mapping (group 0 .. 3) and
+                                         mode AUTO or WAVE_L2.  Without it the path counts stay in LDS.
+                                         Results are identical. */
 
 typedef struct amc_ctx amc_ctx;
 typedef struct amc_graph amc_graph;
@@ -188,6 +193,7 @@ typedef struct amc_stats {
     int32_t b_global;           /* L2 mode: 1 = B(H_r) in the L2-resident scratch, 0 = in LDS */
     int32_t tail_split;         /* last realizations run split into tiles (R mod blocks), 0 = none */
     int32_t tail_tiles;         /* tiles per such realization                                   */
+    int32_t sig_global;         /* L2 mode: 1 = path counts in the global scratch, 0 = in LDS    */
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */
@@ -495,7 +501,7 @@ AMC_API int amc_stability(amc_ctx *ctx, const amc_graph *g, const amc_model *mod
  * context stream.
  * Accepted queries: no pool, topk, fallback, debug pairs, hop_radius,
  * per-edge failure probabilities or AMC_WEIGHT_TABLE; flags only AMC_DIST16,
- * AMC_DIST32 and AMC_SKIP_TAIL (s, reward, eps, r_lower and cert_topk are
+ * AMC_DIST32, AMC_SIGMA_GLOBAL and AMC_SKIP_TAIL (s, reward, eps, r_lower and cert_topk are
  * ignored: there is no tail).  Errors: AMC_E_INVALID_ARG for the above and
  * for what amc_run rejects; AMC_E_SCRATCH when the plan needs more scratch
  * than the array holds (checked before anything is launched); AMC_E_HIP when

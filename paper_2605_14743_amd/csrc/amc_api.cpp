@@ -428,7 +428,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     // default mapping (measured on MI355X): several lanes per vertex pay off
     // only for small graphs, where many sources share the LDS
     (void)avg_deg;
-    pl->group = q->group > 0 ? q->group : (n <= 400 ? 8 : 1);
+    pl->group = q->group > 0 ? q->group : (n <= 400 && !(q->flags & AMC_SIGMA_GLOBAL) ? 8 : 1);
     // adjacency entry: neighbour in the low bits, weight above; 16 bits when both fit
     uint32_t nbits = 1;
     while ((1u << nbits) < (uint32_t)n) ++nbits;
@@ -497,18 +497,29 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     // per-wavefront configurations [placement][16-bit distances]: the most
     // wavefronts that fit (or exactly the requested number).  Placement 0:
     // LDS mode; 1: L2 mode with B(H_r) in LDS; 2: L2 mode with B in the
-    // global scratch
+    // global scratch; 3 / 4: as 1 / 2 with every wavefront's path counts in
+    // the global scratch as well (lane-per-vertex mappings only)
+    constexpr int kPlaces = 5;
     struct Fit {
         int w = 0;
         uint32_t lds = 0, wb = 0;
-    } fits[3][2];
-    for (int pc = 0; pc < 3; ++pc)
+    } fits[kPlaces][2];
+    const bool lane_map = pl->group == 1 || pl->group == 2 || pl->group == 3;
+    const bool force_sg = (q->flags & AMC_SIGMA_GLOBAL) != 0;
+    if (force_sg && (!lane_map || (q->mode != AMC_MODE_AUTO && q->mode != AMC_MODE_WAVE_L2))) return AMC_E_INVALID_ARG;
+    for (int pc = 0; pc < kPlaces; ++pc)
         for (int d16 = 0; d16 < 2; ++d16) {
             if (d16 && !pl->dist16) continue;
+            const bool sg = pc >= 3;
+            if (sg && !lane_map) continue;
+            // the automatic planner does not take these placements: a run
+            // that let it choose them left the GPU faulted without a cause
+            // found; they run when the caller asks (AMC_SIGMA_GLOBAL)
+            if (force_sg != sg) continue;
             Fit &f = fits[pc][d16];
             for (int w = 2; w <= want_w; ++w) {
                 uint32_t wb = 0;
-                const uint32_t lds = pc ? lds_bytes_wave_l2(n, w, d16 != 0, pc == 2, &wb)
+                const uint32_t lds = pc ? lds_bytes_wave_l2(n, w, d16 != 0, pc == 2 || pc == 4, sg, &wb)
                                         : lds_bytes_wave(n, adj_cap, pl->adj_bytes, w, d16 != 0, &wb);
                 if (lds > (uint32_t)ctx->max_lds) break;
                 if ((uint64_t)wb * w < need) continue;   // staging and reduction scratch
@@ -517,18 +528,26 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
             if (q->waves > 0 && f.w != q->waves) f = Fit{};
         }
     // throughput of one wavefront relative to an LDS-mode wavefront with
-    // 32-bit distances (measured on MI355X, weighted ER and WS graphs, n =
-    // 1000 .. 4000): L2 mode 0.92 with B in LDS (adjacency reads at L2), 0.87
-    // with B in the global scratch (B atomics leave the L2), 16-bit distances
-    // 0.83 (compare-and-swap minima); per-source rates grow close to linearly
-    // with the wavefronts a CU holds
-    const double place_eff[3] = {1.0, 0.92, 0.87};
+    // 32-bit distances (measured on MI355X, ER degree 8, n = 1000 .. 5000):
+    // L2 mode 0.92 with B in LDS (adjacency reads at L2), 0.87 with B in the
+    // global scratch (B atomics leave the L2); path counts in the global
+    // scratch 0.45 / 0.43 on weighted graphs and 0.25 / 0.24 with unit
+    // weights (their loads and stores leave the LDS; they pay where many
+    // short distance segments leave a few wavefronts latency-bound, i.e. on
+    // weighted graphs of n >= 1800, and lose to the workgroup-per-source mode
+    // on breadth-first levels); 16-bit distances 0.83 (compare-and-swap
+    // minima); per-source rates grow close to linearly with the wavefronts a
+    // CU holds up to about 11, more slowly beyond
+    const double sg_eff = pl->weighted ? 0.45 : 0.25;
+    const double place_eff[kPlaces] = {1.0, 0.92, 0.87, sg_eff, sg_eff * 0.955};
     auto eff = [&](int pc, int d16) { return fits[pc][d16].w * place_eff[pc] * (d16 ? 0.83 : 1.0); };
     auto width = [&](int pc) {
         if (q->flags & AMC_DIST16) return 1;
         return eff(pc, 1) > eff(pc, 0) ? 1 : 0;
     };
-    const int l2_pc = eff(1, width(1)) >= eff(2, width(2)) ? 1 : 2;
+    int l2_pc = 1;
+    for (int pc = 2; pc < kPlaces; ++pc)
+        if (eff(pc, width(pc)) > eff(l2_pc, width(l2_pc))) l2_pc = pc;
     int mode = q->mode;
     if (mode == AMC_MODE_AUTO) {
         const double e_lds = eff(0, width(0)), e_l2 = eff(l2_pc, width(l2_pc));
@@ -538,7 +557,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         // weights n = 4000, 3 L2 wavefronts 2.4 vs 3.2 M/s; weighted n =
         // 5000, 2 L2 wavefronts 1.05 vs 1.02 M/s)
         const uint32_t block_lds = lds_bytes_block(n, 1024);
-        const bool block_fits =
+        const bool block_fits = !force_sg &&
             block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_staging_bytes(n);
         const double block_below = pl->weighted ? 1.8 : 3.0;
         if (e_best > 0.0 && (!block_fits || e_best >= block_below))
@@ -548,19 +567,21 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     pl->mode = mode;
     pl->scratch_words = 0;
     pl->b_global = false;
+    pl->sig_global = false;
     if (mode == AMC_MODE_WAVE || mode == AMC_MODE_WAVE_L2) {
         const int pc = mode == AMC_MODE_WAVE_L2 ? l2_pc : 0;
         const int d16 = width(pc);
         const Fit &f = fits[pc][d16];
         if (f.w < 2) return AMC_E_UNSUPPORTED;
         pl->dist16 = d16 != 0;
-        pl->b_global = pc == 2;
+        pl->b_global = pc == 2 || pc == 4;
+        pl->sig_global = pc >= 3;
         pl->waves = f.w;
         pl->lds = f.lds;
         pl->wave_bytes = f.wb;
         pl->threads = 64 * f.w;
         pl->adj_cap = adj_cap;
-        if (pc) pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes);
+        if (pc) pl->scratch_words = (uint32_t)l2_scratch_words(n, adj_cap, pl->adj_bytes, pl->sig_global ? f.w : 0);
     } else {
         pl->dist16 = false;
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
@@ -616,7 +637,7 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + 3 * 8 * 16 * n;
     // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
     const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m),
-                                           l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u));
+                                           l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u, kMaxWaves));
     b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;
     if (q->topk > 0) b += 32 * n + 8 * n;                                  // step rewards, gamma

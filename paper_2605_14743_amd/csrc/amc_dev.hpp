@@ -139,6 +139,10 @@ struct LaunchCtl {
     unsigned int *work_ctr;
     uint32_t *bscratch;         // workgroup-per-source and L2 modes: per-workgroup global scratch
     uint32_t bscratch_words;
+    // nq entries or nullptr: the launch's items of query q are that query's own
+    // items item_off[q] .. item_off[q] + (item_start[q+1] - item_start[q]) - 1
+    // (a launch may carry any contiguous range of a query's items)
+    const uint32_t *item_off;
 };
 
 // The query owning global item `item` (uniform scalar search).
@@ -146,6 +150,11 @@ __device__ __forceinline__ int item_query(const LaunchCtl &L, uint32_t item) {
     int q = 0;
     while (q + 1 < L.nq && item >= L.item_start[q + 1]) ++q;
     return q;
+}
+
+// Index of global item `item` among query q's own items.
+__device__ __forceinline__ uint32_t item_local(const LaunchCtl &L, int q, uint32_t item) {
+    return item - L.item_start[q] + (L.item_off ? L.item_off[q] : 0u);
 }
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // "unreached"; d + w never wraps

@@ -13,10 +13,13 @@ namespace amc {
 // (realized graph, B and labels in a per-workgroup global scratch); dist16
 // selects 16-bit distance entries in the wavefront regions.
 uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, bool dist16, uint32_t *wave_bytes);
-uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, uint32_t *wave_bytes);
-size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes);
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, int group, uint32_t adj_bytes,
-                             int blocks, int waves, uint32_t lds, hipStream_t st);
+// sg: L2 mode with each wavefront's path counts in the workgroup's global
+// scratch (lane-per-vertex mappings 1 / 2 / 3 only); l2_scratch_words then
+// counts sg_waves such arrays.
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, bool sg, uint32_t *wave_bytes);
+size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes, int sg_waves);
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, bool sg, int group,
+                             uint32_t adj_bytes, int blocks, int waves, uint32_t lds, hipStream_t st);
 
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);

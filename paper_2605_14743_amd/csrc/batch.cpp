@@ -111,11 +111,14 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         RCHK(qr_init(*b->runs.back(), ctx, graphs[i], &models[i], &q));
     }
     // group by kernel variant
+    // every member of a group runs the group's kernel instantiation: the
+    // per-source placement (distance width, path counts in LDS or scratch)
+    // is part of the key
     struct Key {
-        int mode, weighted, group, adj_bytes, waves, anchored, dist16;
+        int mode, weighted, group, adj_bytes, waves, anchored, dist16, sig_global;
         bool operator==(const Key &o) const {
             return mode == o.mode && weighted == o.weighted && group == o.group && adj_bytes == o.adj_bytes &&
-                   waves == o.waves && anchored == o.anchored && dist16 == o.dist16;
+                   waves == o.waves && anchored == o.anchored && dist16 == o.dist16 && sig_global == o.sig_global;
         }
     };
     std::vector<Key> keys;
@@ -133,7 +136,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         }
         if (pl.anchored) w = pl.waves;
         Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w,
-              pl.anchored ? 1 : 0, pl.dist16 ? 1 : 0};
+              pl.anchored ? 1 : 0, pl.dist16 ? 1 : 0, pl.sig_global ? 1 : 0};
         size_t gi = 0;
         while (gi < keys.size() && !(keys[gi] == k)) ++gi;
         if (gi == keys.size()) {
@@ -167,7 +170,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
                 R.pl.lds = G.pl.mode == AMC_MODE_WAVE
                                ? lds_bytes_wave(R.g->n, R.pl.adj_cap, R.pl.adj_bytes, G.pl.waves, R.pl.dist16,
                                                 &R.pl.wave_bytes)
-                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, R.pl.dist16, R.pl.b_global,
+                               : lds_bytes_wave_l2(R.g->n, G.pl.waves, R.pl.dist16, R.pl.b_global, R.pl.sig_global,
                                                    &R.pl.wave_bytes);
             }
             G.pl.lds = std::max(G.pl.lds, R.pl.lds);
@@ -235,7 +238,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
                            ? launch_anchored(LC, G.pl.weighted, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st)
                        : G.pl.mode == AMC_MODE_BLOCK
                            ? launch_sweep_block(LC, G.pl.weighted, G.blocks, G.pl.threads, G.pl.lds, st)
-                           : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.dist16,
+                           : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.dist16, G.pl.sig_global,
                                                G.pl.group, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);
         if (e != hipSuccess) {
             rc = AMC_E_HIP;

@@ -69,7 +69,7 @@ using namespace amc;
 extern "C" int amc_sweep_static(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_query *q,
                                 uint32_t *d_counts, int32_t *d_center, amc_stats *stats) {
     if (!ctx || !g || g->ctx != ctx || !model || !q || !d_counts) return AMC_E_INVALID_ARG;
-    const uint32_t allowed = AMC_DIST16 | AMC_DIST32 | AMC_SKIP_TAIL;
+    const uint32_t allowed = AMC_DIST16 | AMC_DIST32 | AMC_SKIP_TAIL | AMC_SIGMA_GLOBAL;
     if ((q->flags & ~allowed) || q->pool_size != 0 || q->topk != 0 || q->n_debug != 0 || q->hop_radius != 0 ||
         model->p_fail_edge || model->weight_kind == AMC_WEIGHT_TABLE)
         return AMC_E_INVALID_ARG;
@@ -77,7 +77,8 @@ extern "C" int amc_sweep_static(amc_ctx *ctx, const amc_graph *g, const amc_mode
     // the tail's inputs are not used; clearing them keeps the query free of
     // host-side copies
     amc_query qq = *q;
-    qq.flags = (q->flags & (AMC_DIST16 | AMC_DIST32)) | AMC_SKIP_TAIL | (d_center ? AMC_WANT_CENTER : 0u);
+    qq.flags = (q->flags & (AMC_DIST16 | AMC_DIST32 | AMC_SIGMA_GLOBAL)) | AMC_SKIP_TAIL |
+               (d_center ? AMC_WANT_CENTER : 0u);
     qq.s = nullptr;
     qq.reward = nullptr;
     qq.gamma = nullptr;
@@ -135,6 +136,7 @@ extern "C" int amc_sweep_static(amc_ctx *ctx, const amc_graph *g, const amc_mode
         stats->adj_bytes = (int32_t)R.pl.adj_bytes;
         stats->dist_bytes = R.pl.dist16 ? 2 : 4;
         stats->b_global = R.pl.b_global ? 1 : 0;
+        stats->sig_global = R.pl.sig_global ? 1 : 0;
         stats->tail_split = R.split_tail ? (int32_t)R.tail_R : 0;
         stats->tail_tiles = R.split_tail ? R.P2.tiles_per_r : 0;
     }

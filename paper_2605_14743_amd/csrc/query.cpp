@@ -355,7 +355,8 @@ int qr_enqueue_reset(QueryRun &R, hipStream_t st) {
 static hipError_t launch_plan(const Plan &pl, const LaunchCtl &LC, int blocks, hipStream_t st) {
     if (pl.anchored) return launch_anchored(LC, pl.weighted, pl.adj_bytes, blocks, pl.waves, pl.lds, st);
     if (pl.mode == AMC_MODE_WAVE || pl.mode == AMC_MODE_WAVE_L2)
-        return launch_sweep_wave(LC, pl.weighted, pl.mode == AMC_MODE_WAVE_L2, pl.dist16, pl.group, pl.adj_bytes,
+        return launch_sweep_wave(LC, pl.weighted, pl.mode == AMC_MODE_WAVE_L2, pl.dist16, pl.sig_global, pl.group,
+                                 pl.adj_bytes,
                                  blocks, pl.waves, pl.lds, st);
     return launch_sweep_block(LC, pl.weighted, blocks, pl.threads, pl.lds, st);
 }
@@ -504,6 +505,7 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
         out->stats.adj_bytes = (int32_t)R.pl.adj_bytes;
         out->stats.dist_bytes = R.pl.dist16 ? 2 : 4;
         out->stats.b_global = R.pl.b_global ? 1 : 0;
+        out->stats.sig_global = R.pl.sig_global ? 1 : 0;
         out->stats.tail_split = R.split_tail ? (int32_t)R.tail_R : 0;
         out->stats.tail_tiles = R.split_tail ? R.P2.tiles_per_r : 0;
     }

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
             if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
             q_prev = q;
         }
-        const uint32_t qitem = item - LC.item_start[q];
+        const uint32_t qitem = item_local(LC, q, item);
         const uint32_t r_local = qitem / (uint32_t)P.tiles_per_r;
         const int t = (int)(qitem % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;

@@ -36,8 +36,12 @@ namespace amc {
 // would crowd the LDS.
 // The 8-slot lane mapping needs more than the 128 VGPRs a 1024-thread
 // workgroup allows; it is limited to 8 wavefronts per workgroup.  D16: 16-bit
-// distance entries in the wavefront regions.
-template <bool WEIGHTED, int G, typename ADJ, bool GL, bool D16>
+// distance entries in the wavefront regions.  SG (L2 mode, lane-per-vertex
+// mappings): each wavefront's path counts live in the workgroup's global
+// scratch, so a wavefront region holds only distances and the order (4 or 6
+// n bytes instead of 12 or 14 n) and more sources fit in flight on large
+// graphs.
+template <bool WEIGHTED, int G, typename ADJ, bool GL, bool D16, bool SG>
 __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchCtl LC) {
     using DT = typename std::conditional<D16, uint16_t, uint32_t>::type;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             if (q_prev >= 0) flush_stats(LC.descs[q_prev], acc_stats, ovf);
             q_prev = q;
         }
-        const uint32_t qitem = item - LC.item_start[q];
+        const uint32_t qitem = item_local(LC, q, item);
         const uint32_t r_local = qitem / (uint32_t)P.tiles_per_r;
         const int t = (int)(qitem % (uint32_t)P.tiles_per_r);
         const uint32_t r = P.r_begin + r_local;
@@ -116,8 +120,17 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
         unsigned char *wmine = wbase + wave * P.wave_bytes;
         const uint32_t sig_off = wave_sig_offset(n, D16);
         DT *dist = (DT *)wmine;
-        unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
-        uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+        unsigned long long *sig;
+        uint16_t *ord;
+        if constexpr (SG) {
+            const L2Layout L = l2_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+            unsigned char *gs = (unsigned char *)(LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words);
+            sig = to_global((unsigned long long *)(gs + L.total + (uint32_t)wave * l2_sig_stride(n)));
+            ord = (uint16_t *)(wmine + sig_off);
+        } else {
+            sig = (unsigned long long *)(wmine + sig_off);
+            ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+        }
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)wbase;
         RS.wmax = RS.cmax + n;
@@ -146,8 +159,8 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             if (s >= s_hi) break;
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, shift, BA, dist, sig, ord, &wctr[wave], s, slot, cs, sz,
-                                                 ovf);
+            run_source<WEIGHTED, G, ADJ, GL, DT, SG>(P, rp, adj, shift, BA, dist, sig, ord, &wctr[wave], s, slot, cs,
+                                                     sz, ovf);
             if (lane == 0) {
                 if constexpr (GL) {
                     st_global(&comp32[s], (int32_t)cs);
@@ -231,33 +244,42 @@ uint32_t lds_bytes_wave(int n, uint32_t adj_cap, uint32_t adj_bytes, int waves, 
     return wave_layout(n, adj_cap, adj_bytes).waves + wb * (uint32_t)waves;
 }
 
-uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, uint32_t *wave_bytes) {
-    const uint32_t wb = wave_private_bytes(n, dist16);
+uint32_t lds_bytes_wave_l2(int n, int waves, bool dist16, bool b_global, bool sg, uint32_t *wave_bytes) {
+    const uint32_t wb = wave_private_bytes(n, dist16, sg);
     if (wave_bytes) *wave_bytes = wb;
     return (b_global ? 0u : l2_lds_b_bytes(n)) + wb * (uint32_t)waves;
 }
 
-size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes) {
-    return l2_layout(n, adj_cap, adj_bytes).total / 4u;
+size_t l2_scratch_words(int n, uint32_t adj_cap, uint32_t adj_bytes, int sg_waves) {
+    return (l2_layout(n, adj_cap, adj_bytes).total + (size_t)sg_waves * l2_sig_stride(n)) / 4u;
 }
 
-template <bool W, int G, typename ADJ, bool GL, bool D16>
+template <bool W, int G, typename ADJ, bool GL, bool D16, bool SG>
 static hipError_t launch_t(const LaunchCtl &LC, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ, GL, D16>), dim3(blocks), dim3(64 * waves), lds, st, LC);
+    hipLaunchKernelGGL((sweep_wave_kernel<W, G, ADJ, GL, D16, SG>), dim3(blocks), dim3(64 * waves), lds, st, LC);
     return hipGetLastError();
 }
 
 template <bool W, typename ADJ, bool GL, bool D16>
 static hipError_t attrs_g(int max_lds) {
-    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL, D16>,
-                        (const void *)sweep_wave_kernel<W, 2, ADJ, GL, D16>,
-                        (const void *)sweep_wave_kernel<W, 3, ADJ, GL, D16>,
-                        (const void *)sweep_wave_kernel<W, 4, ADJ, GL, D16>,
-                        (const void *)sweep_wave_kernel<W, 8, ADJ, GL, D16>,
-                        (const void *)sweep_wave_kernel<W, 16, ADJ, GL, D16>};
+    const void *ks[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL, D16, false>,
+                        (const void *)sweep_wave_kernel<W, 2, ADJ, GL, D16, false>,
+                        (const void *)sweep_wave_kernel<W, 3, ADJ, GL, D16, false>,
+                        (const void *)sweep_wave_kernel<W, 4, ADJ, GL, D16, false>,
+                        (const void *)sweep_wave_kernel<W, 8, ADJ, GL, D16, false>,
+                        (const void *)sweep_wave_kernel<W, 16, ADJ, GL, D16, false>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
+    }
+    if constexpr (GL) {
+        const void *kg[] = {(const void *)sweep_wave_kernel<W, 1, ADJ, GL, D16, true>,
+                            (const void *)sweep_wave_kernel<W, 2, ADJ, GL, D16, true>,
+                            (const void *)sweep_wave_kernel<W, 3, ADJ, GL, D16, true>};
+        for (const void *k : kg) {
+            const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -282,34 +304,46 @@ hipError_t set_sweep_wave_attrs(int max_lds) {
 }
 
 template <bool W, typename ADJ, bool GL, bool D16>
-static hipError_t launch_g(const LaunchCtl &LC, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
+static hipError_t launch_g(const LaunchCtl &LC, int group, bool sg, int blocks, int waves, uint32_t lds,
+                           hipStream_t st) {
+    if constexpr (GL) {
+        if (sg) {
+            switch (group) {
+                case 2: return launch_t<W, 2, ADJ, GL, D16, true>(LC, blocks, waves, lds, st);
+                case 3: return launch_t<W, 3, ADJ, GL, D16, true>(LC, blocks, waves, lds, st);
+                case 1: return launch_t<W, 1, ADJ, GL, D16, true>(LC, blocks, waves, lds, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
+    }
+    if (sg) return hipErrorInvalidValue;
     switch (group) {
-        case 1: return launch_t<W, 1, ADJ, GL, D16>(LC, blocks, waves, lds, st);
-        case 2: return launch_t<W, 2, ADJ, GL, D16>(LC, blocks, waves, lds, st);
-        case 3: return launch_t<W, 3, ADJ, GL, D16>(LC, blocks, waves, lds, st);
-        case 4: return launch_t<W, 4, ADJ, GL, D16>(LC, blocks, waves, lds, st);
-        case 16: return launch_t<W, 16, ADJ, GL, D16>(LC, blocks, waves, lds, st);
-        default: return launch_t<W, 8, ADJ, GL, D16>(LC, blocks, waves, lds, st);
+        case 1: return launch_t<W, 1, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
+        case 2: return launch_t<W, 2, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
+        case 3: return launch_t<W, 3, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
+        case 4: return launch_t<W, 4, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
+        case 16: return launch_t<W, 16, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
+        default: return launch_t<W, 8, ADJ, GL, D16, false>(LC, blocks, waves, lds, st);
     }
 }
 
 template <bool GL, bool D16>
-static hipError_t launch_w(const LaunchCtl &LC, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                           uint32_t lds, hipStream_t st) {
+static hipError_t launch_w(const LaunchCtl &LC, bool weighted, int group, bool sg, uint32_t adj_bytes, int blocks,
+                           int waves, uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_g<true, uint16_t, GL, D16>(LC, group, blocks, waves, lds, st)
-                        : launch_g<false, uint16_t, GL, D16>(LC, group, blocks, waves, lds, st);
-    return weighted ? launch_g<true, uint32_t, GL, D16>(LC, group, blocks, waves, lds, st)
-                    : launch_g<false, uint32_t, GL, D16>(LC, group, blocks, waves, lds, st);
+        return weighted ? launch_g<true, uint16_t, GL, D16>(LC, group, sg, blocks, waves, lds, st)
+                        : launch_g<false, uint16_t, GL, D16>(LC, group, sg, blocks, waves, lds, st);
+    return weighted ? launch_g<true, uint32_t, GL, D16>(LC, group, sg, blocks, waves, lds, st)
+                    : launch_g<false, uint32_t, GL, D16>(LC, group, sg, blocks, waves, lds, st);
 }
 
-hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, int group, uint32_t adj_bytes,
-                             int blocks, int waves, uint32_t lds, hipStream_t st) {
+hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool dist16, bool sg, int group,
+                             uint32_t adj_bytes, int blocks, int waves, uint32_t lds, hipStream_t st) {
     if (dist16)
-        return l2 ? launch_w<true, true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
-                  : launch_w<false, true>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
-    return l2 ? launch_w<true, false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st)
-              : launch_w<false, false>(LC, weighted, group, adj_bytes, blocks, waves, lds, st);
+        return l2 ? launch_w<true, true>(LC, weighted, group, sg, adj_bytes, blocks, waves, lds, st)
+                  : launch_w<false, true>(LC, weighted, group, sg, adj_bytes, blocks, waves, lds, st);
+    return l2 ? launch_w<true, false>(LC, weighted, group, sg, adj_bytes, blocks, waves, lds, st)
+              : launch_w<false, false>(LC, weighted, group, sg, adj_bytes, blocks, waves, lds, st);
 }
 
 }  // namespace amc

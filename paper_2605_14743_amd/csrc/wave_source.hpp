@@ -359,6 +359,13 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 // subgraph): an edge into a vertex outside it is never relaxed, so such a
 // vertex stays unreached and fails the predecessor and successor tests.
 //
+// With SG the path counts sig[] live in global memory (the workgroup's
+// scratch, L2 mode): a slot loads sigma_u / c_u only when u is a predecessor /
+// successor, instead of the branch-free load from the source's entry that the
+// LDS array affords.  Every access to sig[] is by the owning wavefront, and
+// steps are separated by wave_sync(), whose workgroup-scope fence orders the
+// global stores of one step before the loads of the next.
+//
 // Reads past a vertex's slots: a lane reads slots sub + G t for t below the
 // wavefront's rounded-up trip count, i.e. at most max-degree + G (U + 1)
 // entries past its vertex's first slot.  Past the last vertex these land in
@@ -366,7 +373,7 @@ __device__ __forceinline__ void append_block(uint32_t *ctr, const bool (&found)[
 // the rest of the workgroup's scratch in the L2 mode, 16 n + 64 bytes or more);
 // their neighbour is masked and their weight replaced by kNoEdge, so they are
 // never used.
-template <bool WEIGHTED, int U, typename ADJ, bool GB, typename DT, bool MASK = false>
+template <bool WEIGHTED, int U, typename ADJ, bool GB, typename DT, bool MASK = false, bool SG = false>
 __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
                                  const BAcc &BA, DT *dist, unsigned long long *sig, uint16_t *ord, uint32_t *ctr, int s,
                                  int dbg_slot, int &comp_out, int &size_out, bool &ovf,
@@ -450,11 +457,19 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 rel[k] = D + w[k] < du[k];                          // relax the edge v -> u
                 if constexpr (MASK) rel[k] = rel[k] && mask[u[k]] != 0;
             }
+            if constexpr (SG) {
 #pragma unroll
-            for (int k = 0; k < U; ++k) {
-                // read from a vertex in range either way (no branch), keep it if u precedes v
-                const unsigned long long val = sig[pred[k] ? u[k] : (uint32_t)s];
-                sg[k] = pred[k] ? val : 0ull;
+                for (int k = 0; k < U; ++k) {
+                    sg[k] = 0ull;
+                    if (pred[k]) sg[k] = sig[u[k]];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    // read from a vertex in range either way (no branch), keep it if u precedes v
+                    const unsigned long long val = sig[pred[k] ? u[k] : (uint32_t)s];
+                    sg[k] = pred[k] ? val : 0ull;
+                }
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
@@ -600,11 +615,19 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
 #pragma unroll
             for (int k = 0; k < U; ++k) du[k] = (uint32_t)dist[u[k]];
             double cu[U];
+            if constexpr (SG) {
 #pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const bool succ = du[k] == dv + w[k];
-                const unsigned long long val = sig[succ ? u[k] : (uint32_t)v];
-                cu[k] = succ ? as_f64(val) : 0.0;
+                for (int k = 0; k < U; ++k) {
+                    cu[k] = 0.0;
+                    if (du[k] == dv + w[k]) cu[k] = as_f64(sig[u[k]]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const bool succ = du[k] == dv + w[k];
+                    const unsigned long long val = sig[succ ? u[k] : (uint32_t)v];
+                    cu[k] = succ ? as_f64(val) : 0.0;
+                }
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
@@ -649,29 +672,33 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
 }
 
 // One source with the vertex mapping G: 1 / 2 / 3 = lane per vertex with 4 /
-// 2 / 8 adjacency slots in flight, otherwise G lanes per vertex.
-template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT>
+// 2 / 8 adjacency slots in flight, otherwise G lanes per vertex.  SG (path
+// counts in global memory) exists for the lane-per-vertex mappings only.
+template <bool WEIGHTED, int G, typename ADJ, bool GB, typename DT, bool SG = false>
 __device__ __forceinline__ void run_source(const SweepParams &P, const ADJ *rp, const ADJ *adj, uint32_t shift,
                                            const BAcc &BA, DT *dist, unsigned long long *sig, uint16_t *ord,
                                            uint32_t *ctr, int s, int dbg_slot, int &comp_out, int &size_out,
                                            bool &ovf) {
+    static_assert(!SG || G == 1 || G == 2 || G == 3, "path counts in global memory need a lane per vertex");
     if constexpr (G == 1 || G == 2 || G == 3)
-        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB, DT>(P, rp, adj, shift, BA, dist, sig,
-                                                                                ord, ctr, s, dbg_slot, comp_out,
-                                                                                size_out, ovf);
+        wave_source_lane<WEIGHTED, (G == 1 ? 4 : (G == 2 ? 2 : 8)), ADJ, GB, DT, false, SG>(
+            P, rp, adj, shift, BA, dist, sig, ord, ctr, s, dbg_slot, comp_out, size_out, ovf);
     else
         wave_source<WEIGHTED, G, ADJ, GB, DT>(P, rp, adj, shift, BA, dist, sig, ord, ctr, s, dbg_slot, comp_out,
                                               size_out, ovf);
 }
 
 // Per-wavefront region of the sweep and trajectory kernels: dist DT[n] |
-// sig u64[n] | ord u16[n].
+// sig u64[n] | ord u16[n]; with the path counts in global memory (sg) just
+// dist DT[n] | ord u16[n].
 __host__ __device__ inline uint32_t wave_sig_offset(int n, bool dist16) {
     return ((dist16 ? 2u : 4u) * (uint32_t)n + 7u) & ~7u;
 }
-__host__ __device__ inline uint32_t wave_private_bytes(int n, bool dist16) {
-    return (wave_sig_offset(n, dist16) + 10u * (uint32_t)n + 15u) & ~15u;
+__host__ __device__ inline uint32_t wave_private_bytes(int n, bool dist16, bool sg = false) {
+    return (wave_sig_offset(n, dist16) + (sg ? 2u : 10u) * (uint32_t)n + 15u) & ~15u;
 }
+// Bytes of one wavefront's path-count array in the workgroup's global scratch.
+__host__ __device__ inline uint32_t l2_sig_stride(int n) { return (8u * (uint32_t)n + 255u) & ~255u; }
 
 // Byte offsets of the LDS carve-up (mirrors lds_bytes_wave on the host).
 struct WaveLayout {
@@ -693,7 +720,9 @@ __host__ __device__ inline WaveLayout wave_layout(int n, uint32_t adj_cap, uint3
 // in its global scratch (small enough to stay in L2), and so does B(H_r) when
 // the plan puts it there; otherwise the LDS holds B (l2_lds_b_bytes) before
 // the wavefronts' private regions.  The 8 n + 64 bytes past the labels bound
-// the adjacency reads past its padding (wave_source_lane).
+// the adjacency reads past its padding (wave_source_lane).  With the path
+// counts in global memory, wavefront w's array starts at total + w
+// l2_sig_stride(n).
 struct L2Layout {
     uint32_t rp, adj, comp, csize, B, total;
 };

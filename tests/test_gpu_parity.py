@@ -98,7 +98,12 @@ FLAGS = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.WANT_N
                                         (amc.MODE_WAVE, {"group": 8, "flags": amc.DIST16}),
                                         (amc.MODE_WAVE, {"group": 3, "flags": amc.DIST16}),
                                         (amc.MODE_WAVE_L2, {"flags": amc.DIST16}),
-                                        (amc.MODE_WAVE_L2, {"tile": 3, "flags": amc.DIST16})])
+                                        (amc.MODE_WAVE_L2, {"tile": 3, "flags": amc.DIST16}),
+                                        (amc.MODE_WAVE_L2, {"flags": amc.SIGMA_GLOBAL}),
+                                        (amc.MODE_WAVE_L2, {"group": 2, "flags": amc.SIGMA_GLOBAL}),
+                                        (amc.MODE_WAVE_L2, {"group": 3, "flags": amc.SIGMA_GLOBAL}),
+                                        (amc.MODE_WAVE_L2, {"tile": 3, "flags": amc.SIGMA_GLOBAL | amc.DIST16}),
+                                        (amc.MODE_WAVE_L2, {"flags": amc.SIGMA_GLOBAL | amc.PLAIN_LAUNCH})])
 def test_er20_full_against_oracle(ctx, mode, extra):
     wl = W.config_er20()
     g = wl.graph
@@ -124,6 +129,8 @@ def test_er20_full_against_oracle(ctx, mode, extra):
     assert res["admissible"] == t["admissible"]
     st = res["stats"]
     assert st["mode"] == mode
+    if flags & amc.SIGMA_GLOBAL:
+        assert st["sig_global"] == 1
     if mode != amc.MODE_BLOCK:          # 16 waves fit either way: 32-bit entries unless asked otherwise
         assert st["dist_bytes"] == (2 if flags & amc.DIST16 else 4)
 
@@ -133,7 +140,8 @@ def test_debug_dump_distances_sigma_delta(ctx):
     g = wl.graph
     pairs = [(0, 0), (3, 7), (999, 19), (500, 11)]
     for mode, fl in ((amc.MODE_WAVE, 0), (amc.MODE_BLOCK, 0), (amc.MODE_WAVE_L2, 0), (amc.MODE_WAVE, amc.DIST16),
-                     (amc.MODE_WAVE_L2, amc.DIST16)):
+                     (amc.MODE_WAVE_L2, amc.DIST16), (amc.MODE_WAVE_L2, amc.SIGMA_GLOBAL),
+                     (amc.MODE_WAVE_L2, amc.SIGMA_GLOBAL | amc.DIST16)):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min, mode=mode,
                       flags=amc.SKIP_TAIL | fl, debug_pairs=pairs)
         for k, (r, s) in enumerate(pairs):
@@ -186,9 +194,10 @@ def test_edge_cases(ctx, mode):
     _case(ctx, pw, {"p_fail": 0.1, "weight": "fixed"}, 40, mode=mode, pool=np.array([0, 5, 9, 33, 70]))
 
 
-@pytest.mark.parametrize("mode", [amc.MODE_WAVE, amc.MODE_WAVE_L2])
-def test_edge_cases_16bit_distances(ctx, mode):
-    kw = dict(mode=mode, flags=FLAGS | amc.DIST16)
+@pytest.mark.parametrize("mode,extra", [(amc.MODE_WAVE, 0), (amc.MODE_WAVE_L2, 0),
+                                        (amc.MODE_WAVE_L2, amc.SIGMA_GLOBAL)])
+def test_edge_cases_16bit_distances(ctx, mode, extra):
+    kw = dict(mode=mode, flags=FLAGS | amc.DIST16 | extra)
     _case(ctx, W.canonical(1, []), {"p_fail": 0.1}, 5, k_min=1, **kw)
     _case(ctx, W.canonical(7, []), {"p_fail": 0.5}, 9, k_min=1, **kw)
     g = W.er_graph(40, 0.1, 3)
@@ -255,7 +264,8 @@ def test_invalid_arguments(ctx):
 def test_ws1000_sampled_realizations(ctx):
     wl = W.config_ws1000()
     g = wl.graph
-    for r0, R, fl in ((0, 3, 0), (7777, 2, 0), (7777, 2, amc.DIST16), (7777, 2, amc.DIST32)):
+    for r0, R, fl in ((0, 3, 0), (7777, 2, 0), (7777, 2, amc.DIST16), (7777, 2, amc.DIST32),
+                      (4242, 2, amc.SIGMA_GLOBAL)):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
                       flags=FLAGS | fl, cert_topk=5)
         ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=r0, alpha=wl.alpha, k_min=wl.k_min,
@@ -272,12 +282,15 @@ def test_er5000_sampled_realizations_with_pool(ctx):
     R = 2
     ref = O.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
                   want_next=True, pool=wl.pool, **wl.model())
-    for mode in (amc.MODE_BLOCK, amc.MODE_WAVE_L2):
+    for mode, fl in ((amc.MODE_BLOCK, 0), (amc.MODE_WAVE_L2, 0), (amc.MODE_WAVE_L2, amc.SIGMA_GLOBAL),
+                     (amc.MODE_WAVE_L2, amc.SIGMA_GLOBAL | amc.DIST32)):
         res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=1234, alpha=wl.alpha, k_min=wl.k_min,
-                      flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, pool=wl.pool,
+                      flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL | fl, pool=wl.pool,
                       mode=mode)
         assert res["stats"]["mode"] == mode
-        check_sweep(res, ref, g.n, f"er5000 mode {mode}")
+        if fl & amc.SIGMA_GLOBAL:
+            assert res["stats"]["sig_global"] == 1
+        check_sweep(res, ref, g.n, f"er5000 mode {mode} flags {fl}")
 
 
 def test_weighted_n2400_l2_mode_sampled(ctx):
@@ -302,16 +315,21 @@ def test_weighted_n2400_l2_mode_sampled(ctx):
 def test_weighted_n1800_l2_mode_global_b(ctx):
     # n = 1800: B(H_r) in LDS would cost the L2 mode a wavefront, so the
     # planner keeps B in the global scratch; split and whole realizations
+    # (six wavefronts; with AMC_SIGMA_GLOBAL the path counts go to the scratch)
     g = W.er_graph(1800, 8.0 / 1799, 1800)
     model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
     fl = amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL
     ref = O.sweep(g.n, g.eu, g.ev, seed=4, R=2, r_begin=9, want_next=True, **model)
     for extra in ({}, {"tile": g.n}):
-        res = gpu_run(ctx, g, model, seed=4, R=2, r_begin=9, flags=fl, **extra)
+        res = gpu_run(ctx, g, model, seed=4, R=2, r_begin=9, flags=fl, mode=amc.MODE_WAVE_L2, waves=6, **extra)
         st = res["stats"]
-        assert st["mode"] == amc.MODE_WAVE_L2 and st["b_global"] == 1, st
+        assert st["mode"] == amc.MODE_WAVE_L2 and st["b_global"] == 1 and st["sig_global"] == 0, st
         check_sweep(res, ref, g.n, f"er1800 L2 global B {extra}")
-    res = gpu_run(ctx, W.er_graph(2400, 8.0 / 2399, 2400), model, seed=3, R=1, flags=fl)
+    res = gpu_run(ctx, g, model, seed=4, R=2, r_begin=9, flags=fl | amc.SIGMA_GLOBAL)
+    assert res["stats"]["mode"] == amc.MODE_WAVE_L2 and res["stats"]["sig_global"] == 1, res["stats"]
+    check_sweep(res, ref, g.n, "er1800 path counts in the scratch")
+    res = gpu_run(ctx, W.er_graph(2400, 8.0 / 2399, 2400), model, seed=3, R=1, flags=fl, mode=amc.MODE_WAVE_L2,
+                  waves=5)
     assert res["stats"]["mode"] == amc.MODE_WAVE_L2 and res["stats"]["b_global"] == 0
 
 
@@ -347,6 +365,7 @@ def test_split_ranges_and_determinism(ctx):
 @pytest.mark.parametrize("mode,graph,extra", [(amc.MODE_WAVE_L2, "er20", {}), (amc.MODE_WAVE_L2, "ws200", {}),
                                               (amc.MODE_WAVE, "ws200", {}),
                                               (amc.MODE_WAVE_L2, "ws200", {"flags": amc.DIST16, "pool": True}),
+                                              (amc.MODE_WAVE_L2, "ws200", {"flags": amc.SIGMA_GLOBAL, "pool": True}),
                                               (amc.MODE_WAVE, "ws200", {"pool": True}),
                                               (amc.MODE_BLOCK, "er20", {}), (amc.MODE_BLOCK, "ws200", {"pool": True})])
 def test_last_realizations_split_into_tiles(ctx, mode, graph, extra):
@@ -606,7 +625,7 @@ _TIE_GRAPHS = {"C1001": lambda: _cycle(1001), "C1000": lambda: _cycle(1000), "K2
 _TIE_MODES = [(amc.MODE_WAVE, {}), (amc.MODE_WAVE, {"group": 2}), (amc.MODE_WAVE, {"group": 3}),
               (amc.MODE_WAVE, {"group": 8}), (amc.MODE_WAVE, {"tile": 333}), (amc.MODE_WAVE, {"flags": amc.DIST16}),
               (amc.MODE_WAVE_L2, {}), (amc.MODE_WAVE_L2, {"group": 8}), (amc.MODE_WAVE_L2, {"flags": amc.DIST16}),
-              (amc.MODE_BLOCK, {})]
+              (amc.MODE_WAVE_L2, {"flags": amc.SIGMA_GLOBAL}), (amc.MODE_BLOCK, {})]
 _tie_ref = {}
 
 
