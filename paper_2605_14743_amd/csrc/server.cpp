@@ -49,9 +49,16 @@ constexpr int kMaxBypass = 8;
 constexpr int kMaxMembers = 64;        // queries in one epoch launch
 constexpr int kLanes = 3;              // epochs in flight at once
 constexpr double kEpochMs = 30.0;       // work budget of one epoch
-constexpr double kItemMs = 15.0;        // target duration of one work item on one workgroup
-// initial guess of a variant's rate, in work units (sources x (surviving
-// slots + vertices)) per millisecond on the whole chip; refined per epoch
+constexpr double kItemMs = 10.0;        // target duration of one work item on one workgroup
+// rate of one wavefront in work units (sources x (surviving slots +
+// vertices)) per millisecond, measured on MI355X in the L2 mode (ws1000: 1e7
+// sources of 10.5 k units in 400 ms on 256 x 11 wavefronts); a
+// workgroup-per-source workgroup counts as kBlockWaves wavefronts (er5000:
+// 3.0 M sources/s of 41 k units on 256 workgroups)
+constexpr double kWaveRate = 9.0e4;
+constexpr double kBlockWaves = 5.0;
+// a variant's starting rate in the same units for the whole chip is
+// kWaveRate x wavefronts x CUs; it is refined from each epoch's events
 constexpr double kRate0 = 2.0e8;
 }  // namespace
 
@@ -104,7 +111,7 @@ struct Lane {
 
 struct Variant {
     int mode = 0, weighted = 0, group = 0, adj_bytes = 0, dist16 = 0, anchored = 0, waves = 0;   // dist16: bit 1 = path counts in scratch
-    double rate = kRate0;
+    double rate = kRate0, rate0 = kRate0;   // estimated and modelled chip-wide work units per ms
 };
 
 struct Server {
@@ -162,6 +169,11 @@ struct Server {
         cv.notify_all();
     }
 
+    // Work units one workgroup of this plan processes per millisecond.
+    static double wg_rate(const Plan &pl) {
+        return kWaveRate * (pl.mode == AMC_MODE_BLOCK ? kBlockWaves : (double)std::max(1, pl.waves));
+    }
+
     int variant_of(const Plan &pl) {
         const int key[7] = {pl.mode, pl.weighted ? 1 : 0, pl.mode == AMC_MODE_BLOCK ? 0 : pl.group,
                             (int)pl.adj_bytes, (pl.dist16 ? 1 : 0) | (pl.sig_global ? 2 : 0), pl.anchored ? 1 : 0,
@@ -180,6 +192,7 @@ struct Server {
         v->dist16 = key[4];
         v->anchored = key[5];
         v->waves = key[6];
+        v->rate = v->rate0 = wg_rate(pl) * std::max(1, ctx->cu_count);
         variants.push_back(std::move(v));
         return (int)variants.size() - 1;
     }
@@ -235,13 +248,14 @@ struct Server {
         // work of one source: its surviving slots and vertices (expected)
         const double wps = 2.0 * (double)g->m * (1.0 - std::min(1.0, std::max(0.0, r->model.p_fail))) + g->n;
         if (q.tile <= 0) {
+            // items short enough that a query arriving later waits for at
+            // most about one item per workgroup before its own epoch starts
             Plan p0;
             int rc = validate(g, &r->model, &q);
             if (rc == AMC_OK) rc = plan(ctx, g, &r->model, &q, &p0);
             if (rc != AMC_OK) return rc;
-            const double per_wg = kRate0 / std::max(1, ctx->cu_count);
-            const int cap = (int)std::max(1.0, std::floor(kItemMs * per_wg / std::max(wps, 1.0)));
-            q.tile = std::max(1, std::min(p0.tile, std::max(cap, p0.waves)));
+            const int cap = (int)std::max(1.0, std::floor(kItemMs * wg_rate(p0) / std::max(wps, 1.0)));
+            q.tile = std::max(1, std::min(p0.tile, std::max(cap, p0.mode == AMC_MODE_BLOCK ? 1 : p0.waves)));
         }
         int rc = qr_init(R, ctx, g, &r->model, &q);
         if (rc != AMC_OK) return rc;
@@ -397,10 +411,13 @@ struct Server {
     void epoch_done(Lane &L) {
         float ms = 0.f;
         if (L.variant >= 0 && hipEventElapsedTime(&ms, L.start, L.end) == hipSuccess && ms > 0.f && L.work > 0.0) {
-            // lanes share the chip: an epoch's own rate is above its share
+            // an epoch's rate while it shares the chip with other lanes is a
+            // lower bound of the variant's; the estimate moves a third of the
+            // way and stays within a factor of 4 of the model
             Variant &V = *variants[L.variant];
-            const double r = std::min(8.0 * kRate0, std::max(kRate0 / 64.0, 2.0 * L.work / ms));
-            V.rate = 0.7 * V.rate + 0.3 * r;
+            const double model = V.rate0;
+            const double r = std::min(4.0 * model, std::max(model / 4.0, L.work / ms));
+            V.rate = 0.67 * V.rate + 0.33 * r;
         }
         (void)hipGetLastError();
         L.busy = false;
