@@ -554,12 +554,13 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         const double e_best = std::max(e_lds, e_l2);
         // the workgroup-per-source mode, where it fits, wins once few
         // sources stay in flight (measured on MI355X, ER degree 8: unit
-        // weights n = 4000, 3 L2 wavefronts 2.4 vs 3.2 M/s; weighted n =
-        // 5000, 2 L2 wavefronts 1.05 vs 1.02 M/s)
+        // weights n = 2400, 5 L2 wavefronts 6.6 vs 6.8 M/s, n = 4000, 3 L2
+        // wavefronts 2.3 vs 4.8 M/s; weighted n = 5000, 2 L2 wavefronts 1.05
+        // vs 1.14 M/s)
         const uint32_t block_lds = lds_bytes_block(n, 1024);
         const bool block_fits = !force_sg &&
             block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_staging_bytes(n);
-        const double block_below = pl->weighted ? 1.8 : 3.0;
+        const double block_below = pl->weighted ? 1.8 : 4.0;
         if (e_best > 0.0 && (!block_fits || e_best >= block_below))
             mode = e_lds >= e_l2 ? AMC_MODE_WAVE : AMC_MODE_WAVE_L2;
         else mode = AMC_MODE_BLOCK;
@@ -591,7 +592,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;
-        pl->scratch_words = (uint32_t)block_scratch_words(n, g->m);
+        pl->scratch_words = (uint32_t)block_scratch_words(n, g->m, pl->weighted);
     }
     // sources per work item: whole realizations when there are enough of
     // them to fill the device, otherwise split the sources
@@ -636,7 +637,7 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     b += (8 + 4 + 4) * R * n + 4 * R;
     if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + 3 * 8 * 16 * n;
     // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
-    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m),
+    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true),
                                            l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u, kMaxWaves));
     b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;

@@ -49,8 +49,13 @@ __host__ __device__ inline BlockLayout block_layout(int n) {
     return L;
 }
 
-template <bool WEIGHTED>
-__device__ void block_source(const SweepParams &P, const uint32_t *rp, const uint32_t *adj, double *B,
+// 32-bit words of the realized adjacency (2m entries plus padding).
+__host__ __device__ inline size_t block_adj_words(int64_t m, uint32_t adj_bytes) {
+    return ((2 * (size_t)m + kAdjPad) * adj_bytes + 3) / 4;
+}
+
+template <bool WEIGHTED, typename ADJ>
+__device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ *adj, double *B,
                              uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctl,
                              uint32_t *tmp, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
     const int n = P.n;
@@ -97,7 +102,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
             const uint32_t first = beg + (uint32_t)sub;
             uint32_t nxt[kBU];
 #pragma unroll
-            for (int k = 0; k < kBU; ++k) nxt[k] = adj[first + kBG * k];
+            for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + kBG * k];
             for (uint32_t t = 0; t < maxtrips; t += kBU) {
                 uint32_t cur[kBU], u[kBU], w[kBU], du[kBU], old[kBU];
                 bool pred[kBU], rel[kBU], found[kBU];
@@ -105,7 +110,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
                 for (int k = 0; k < kBU; ++k) cur[k] = nxt[k];
                 if (t + kBU < maxtrips) {
 #pragma unroll
-                    for (int k = 0; k < kBU; ++k) nxt[k] = adj[first + kBG * (t + kBU + k)];
+                    for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + kBG * (t + kBU + k)];
                 }
                 // a slot past the vertex's list reads vertex 0 with weight
                 // kNoEdge (fails both tests)
@@ -254,7 +259,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
                 for (uint32_t t = 0; t < trips; t += kBU) {
                     uint32_t a[kBU], u[kBU], du[kBU];
 #pragma unroll
-                    for (int k = 0; k < kBU; ++k) a[k] = adj[first + kBG * (t + k)];
+                    for (int k = 0; k < kBU; ++k) a[k] = (uint32_t)adj[first + kBG * (t + k)];
 #pragma unroll
                     for (int k = 0; k < kBU; ++k) u[k] = (t + k < trips) ? (a[k] & 0xFFFFu) : 0u;
 #pragma unroll
@@ -280,7 +285,10 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const uin
     }
 }
 
-template <bool WEIGHTED>
+// ADJ: the realized adjacency entry, uint32_t (weight << 16 | neighbour) or,
+// with unit weights, uint16_t (the neighbour alone), which halves the
+// per-workgroup scratch the traversal reads so that it stays in the L2.
+template <bool WEIGHTED, typename ADJ>
 __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[2 * kMaxWaves];
@@ -328,18 +336,20 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         double *B = (double *)(smem + L.B);
         uint16_t *comp = (uint16_t *)(smem + L.comp);
         uint16_t *csize = (uint16_t *)(smem + L.csize);
-        // per-workgroup global scratch: (n+1) words unused, adjacency (2m
-        // plus padding), component centres (2 n)
+        // per-workgroup global scratch: the realized adjacency (2m plus
+        // padding entries), then the component centres (2 n words), which
+        // also absorb the reads past the last vertex's slots
         uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
         uint32_t *rp = (uint32_t *)(smem + L.rp);
-        uint32_t *adj = gs + (n + 1);
+        ADJ *adj = to_global((ADJ *)gs);
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
         RS.wmax = RS.cmax + n;
-        uint32_t *tail4 = adj + 2 * (size_t)P.m + kAdjPad;
+        uint32_t *tail4 = gs + block_adj_words(P.m, (uint32_t)sizeof(ADJ));
         RS.ccen = (int32_t *)tail4;
         RS.wcen = RS.ccen + n;
 
+        // entries (w << 16) | neighbour; a 16-bit entry keeps the neighbour
         stage_realization(P, r, rp, adj, 16u, (uint16_t *)smem, scan_tmp);
         for (int v = tid; v < n; v += nthr) B[v] = 0.0;
         __syncthreads();
@@ -348,7 +358,7 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         for (int s = s_lo; s < s_hi; ++s) {
             int cs = 0, sz = 0;
             const int slot = P.n_dbg ? debug_slot(P, r, s) : -1;
-            block_source<WEIGHTED>(P, rp, adj, B, dist, sig, ord, aux, ctl, scan_tmp, s, slot, cs, sz, ovf);
+            block_source<WEIGHTED, ADJ>(P, rp, adj, B, dist, sig, ord, aux, ctl, scan_tmp, s, slot, cs, sz, ovf);
             if (tid == 0) {
                 comp[s] = (uint16_t)cs;
                 csize[s] = (uint16_t)(sz & 0xFFFF);
@@ -396,25 +406,25 @@ uint32_t lds_bytes_block(int n, int threads) {
 // Bytes at the start of the LDS that the per-edge staging may use (below rp).
 uint32_t block_staging_bytes(int n) { return block_layout(n).rp; }
 
-size_t block_scratch_words(int n, int64_t m) {
-    return (size_t)(n + 1) + 2 * (size_t)m + kAdjPad + 2 * (size_t)n + 64;
+size_t block_scratch_words(int n, int64_t m, bool weighted) {
+    return block_adj_words(m, weighted ? 4u : 2u) + 2 * (size_t)n + 64;
 }
 
 hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
                               hipStream_t st) {
     if (weighted)
-        hipLaunchKernelGGL(sweep_block_kernel<true>, dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<true, uint32_t>), dim3(blocks), dim3(threads), lds, st, LC);
     else
-        hipLaunchKernelGGL(sweep_block_kernel<false>, dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<false, uint16_t>), dim3(blocks), dim3(threads), lds, st, LC);
     return hipGetLastError();
 }
 
 hipError_t set_sweep_block_attrs(int max_lds) {
-    hipError_t e = hipFuncSetAttribute((const void *)sweep_block_kernel<true>,
+    hipError_t e = hipFuncSetAttribute((const void *)sweep_block_kernel<true, uint32_t>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)sweep_block_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               max_lds);
+    return hipFuncSetAttribute((const void *)sweep_block_kernel<false, uint16_t>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
 }  // namespace amc
