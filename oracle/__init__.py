@@ -131,7 +131,7 @@ class _BootOut(C.Structure):
 
 def _declare(L):
     P = C.POINTER
-    L.or_w1.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_double),
+    L.or_w1.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32), P(C.c_uint32), P(C.c_double), P(C.c_double),
                         P(C.c_double)]
     L.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
     L.or_philox4x32_10.restype = None
@@ -434,16 +434,19 @@ def bootstrap(next_table, *, replicates=100, level=0.95, eta=None, s=None, seed=
     return out
 
 
-def w1(n, eu, ev, p, q):
-    """Wasserstein-1 between profiles p and q (n each) on the hop metric of the
-    graph (eu, ev): the cheapest transshipment of p - q over its edges."""
+def w1(n, eu, ev, p, q, cost=None):
+    """Wasserstein-1 between profiles p and q (n each) on the shortest-path
+    metric of the graph (eu, ev) with unit edge lengths (the hop metric) or
+    the integer lengths `cost`: the cheapest transshipment of p - q over its
+    edges."""
     eu = np.ascontiguousarray(eu, dtype=np.int32)
     ev = np.ascontiguousarray(ev, dtype=np.int32)
     p = np.ascontiguousarray(p, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
+    c = None if cost is None else np.ascontiguousarray(cost, dtype=np.uint32)
     out = C.c_double(0.0)
-    _check(lib().or_w1(int(n), len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), _ptr(p, C.c_double),
-                       _ptr(q, C.c_double), C.byref(out)), "w1")
+    _check(lib().or_w1(int(n), len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), _ptr(c, C.c_uint32),
+                       _ptr(p, C.c_double), _ptr(q, C.c_double), C.byref(out)), "w1")
     return float(out.value)
 
 

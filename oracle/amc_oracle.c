@@ -1438,17 +1438,18 @@ done:
 }
 
 /* ------------------------------------------------------------------------
- * Wasserstein-1 between two profiles on the shortest-path (hop) metric of the
- * base topology (robust experiment of Section 9.1; W1 as an integral
- * probability metric over 1-Lipschitz functions, Section 4).
+ * Wasserstein-1 between two profiles on the shortest-path metric of the base
+ * topology (robust experiment of Section 9.1; W1 as an integral probability
+ * metric over 1-Lipschitz functions, Section 4), with every edge of length 1
+ * (hop metric, cost == NULL) or of the positive integer length cost[e].
  *
  * On a graph metric W1(p, q) is the cost of the cheapest flow that moves the
- * surplus p - q over the edges at cost 1 per unit and edge (the transshipment
- * form of the transport problem).  It is computed by successive shortest
- * paths: every round runs Bellman-Ford from all nodes with remaining surplus
- * over the residual graph (an edge carrying flow f from u to v offers v -> u at
- * cost -1 for up to f, and u -> v at cost +1 without limit; a flow-free edge
- * offers both directions at +1), takes the nearest node with remaining
+ * surplus p - q over the edges at cost c_e per unit on edge e (the
+ * transshipment form of the transport problem).  It is computed by successive
+ * shortest paths: every round runs Bellman-Ford from all nodes with remaining
+ * surplus over the residual graph (an edge carrying flow f from u to v offers
+ * v -> u at cost -c_e for up to f, and u -> v at cost +c_e without limit; a
+ * flow-free edge offers both directions at +c_e), takes the nearest node with remaining
  * deficit (smallest index among the nearest), and pushes along the
  * predecessor path the largest amount that neither overdraws the surplus,
  * the deficit, nor a cancelled flow.  Augmenting along shortest paths keeps
@@ -1456,7 +1457,8 @@ done:
  * Returns OR_E_ARG for a disconnected graph with unbalanced components or an
  * exhausted round budget.
  * ---------------------------------------------------------------------- */
-int or_w1(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const double *p, const double *q, double *w1)
+int or_w1(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const uint32_t *cost, const double *p,
+          const double *q, double *w1)
 {
     double *ex = (double *)malloc(sizeof(double) * (size_t)n);
     double *f = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
@@ -1483,8 +1485,9 @@ int or_w1(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const doub
             changed = 0;
             for (e = 0; e < m; ++e) {
                 const int32_t a = eu[e], b = ev[e];
-                const int64_t c_ab = f[e] < 0.0 ? -1 : 1;   /* a -> b */
-                const int64_t c_ba = f[e] > 0.0 ? -1 : 1;   /* b -> a */
+                const int64_t c = cost ? (int64_t)cost[e] : 1;
+                const int64_t c_ab = f[e] < 0.0 ? -c : c;   /* a -> b */
+                const int64_t c_ba = f[e] > 0.0 ? -c : c;   /* b -> a */
                 if (dist[a] < INF && dist[a] + c_ab < dist[b]) { dist[b] = dist[a] + c_ab; pred[b] = 2 * e; changed = 1; }
                 if (dist[b] < INF && dist[b] + c_ba < dist[a]) { dist[a] = dist[b] + c_ba; pred[a] = 2 * e + 1; changed = 1; }
             }
@@ -1514,7 +1517,7 @@ int or_w1(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, const doub
         ex[t] += th;
     }
     *w1 = 0.0;
-    for (e = 0; e < m; ++e) *w1 += fabs(f[e]);
+    for (e = 0; e < m; ++e) *w1 += (cost ? (double)cost[e] : 1.0) * fabs(f[e]);
 out:
     free(ex); free(f); free(dist); free(pred);
     return rc;

@@ -133,3 +133,63 @@ def test_unbalanced_components_are_rejected():
         O.w1(4, eu, ev, np.array([1.0, 0, 0, 0]), np.array([0, 0, 1.0, 0]))
     # balanced components are fine: each moves inside its own component
     assert O.w1(4, eu, ev, np.array([0.5, 0, 0.5, 0]), np.array([0, 0.5, 0, 0.5])) == pytest.approx(1.0)
+
+
+# --------------------------------------------------------------------------- weighted ground metric
+def weighted_distances(n, eu, ev, c):
+    A = coo_matrix((c.astype(float), (eu, ev)), shape=(n, n)).tocsr()
+    return shortest_path(A, directed=False)
+
+
+def test_weighted_path_and_tree_closed_forms():
+    """On a tree every unit of the mass below an edge crosses it once:
+    W1 = sum over edges of c_e |mass below e|."""
+    rng = np.random.default_rng(5)
+    for n in (2, 9, 64):
+        eu = np.arange(n - 1, dtype=np.int32)
+        ev = eu + 1
+        c = rng.integers(1, 12, n - 1).astype(np.uint32)
+        p, q = random_profile(n, rng), random_profile(n, rng)
+        expect = (c * np.abs(np.cumsum(p - q)[:-1])).sum()
+        assert O.w1(n, eu, ev, p, q, cost=c) == pytest.approx(expect, rel=1e-13, abs=1e-16)
+    n = 120
+    parent = np.array([-1] + [int(rng.integers(0, v)) for v in range(1, n)])
+    eu, ev = parent[1:].astype(np.int32), np.arange(1, n, dtype=np.int32)
+    c = rng.integers(1, 31, n - 1).astype(np.uint32)
+    order = np.lexsort((ev, eu))
+    p, q = random_profile(n, rng), random_profile(n, rng)
+    below = p - q
+    for v in range(n - 1, 0, -1):
+        below[parent[v]] += below[v]
+    expect = (c * np.abs(below[1:])).sum()
+    assert O.w1(n, eu[order], ev[order], p, q, cost=c[order]) == pytest.approx(expect, rel=1e-12, abs=1e-16)
+
+
+def test_weighted_transport_lp():
+    """Transport problem over the weighted all-pairs distances (scipy's
+    Dijkstra and HiGHS), on graphs with cycles where paths of fewer hops can
+    be longer."""
+    rng = np.random.default_rng(6)
+    for trial in range(6):
+        n = int(rng.integers(6, 26))
+        eu, ev = connected_graph(n, int(rng.integers(0, 2 * n)), rng)
+        c = rng.integers(1, 32, len(eu)).astype(np.uint32)
+        D = weighted_distances(n, eu, ev, c)
+        p, q = random_profile(n, rng), random_profile(n, rng)
+        A_eq = np.vstack([np.kron(np.eye(n), np.ones(n)), np.kron(np.ones(n), np.eye(n))])
+        lp = linprog(D.ravel(), A_eq=A_eq, b_eq=np.concatenate([p, q]), bounds=(0, None), method="highs")
+        assert lp.status == 0
+        assert O.w1(n, eu, ev, p, q, cost=c) == pytest.approx(lp.fun, rel=1e-9, abs=1e-12)
+        # unit lengths give the hop metric back
+        assert O.w1(n, eu, ev, p, q, cost=np.ones(len(eu), np.uint32)) == pytest.approx(O.w1(n, eu, ev, p, q),
+                                                                                          rel=1e-13)
+
+
+def test_weighted_point_masses():
+    rng = np.random.default_rng(7)
+    n = 30
+    eu, ev = connected_graph(n, 25, rng)
+    c = rng.integers(1, 9, len(eu)).astype(np.uint32)
+    D = weighted_distances(n, eu, ev, c)
+    for u, v in ((0, 29), (4, 11), (20, 2)):
+        assert O.w1(n, eu, ev, np.eye(n)[u], np.eye(n)[v], cost=c) == D[u, v]
