@@ -374,9 +374,11 @@ AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *
  *    actual |N* - N0 - N0 E N0|;
  *  - with a base topology (m > 0 edges eu, ev, canonical as for
  *    amc_graph_create, connected, n <= AMC_MAX_W1_N): the Wasserstein-1
- *    distance W1(b(P), b0) of every sample on the hop metric of that topology
- *    (robust experiment of Section 9.1), computed exactly as the cheapest
- *    transshipment of b(P) - b0 over its edges at unit cost, and the AFC at
+ *    distance W1(b(P), b0) of every sample on the shortest-path metric of
+ *    that topology (robust experiments of Sections 9.1 and 9.2) -- every edge
+ *    of length 1 (the hop metric) or, with w, of the integer length w[e] in
+ *    [1, 65535] (e.g. the fixed weights of the graph) -- computed exactly as
+ *    the cheapest transshipment of b(P) - b0 over its edges, and the AFC at
  *    the W1 maximiser.
  * Errors: AMC_E_INVALID_ARG for a bad size, range or edge list, a
  * disconnected topology, or a Q0 row that does not absorb; AMC_E_UNSUPPORTED
@@ -393,6 +395,7 @@ typedef struct amc_robust_query {
     uint64_t seed;
     int64_t m;                  /* edges of the base topology for W1 (0 = no W1)  */
     const int32_t *eu, *ev;     /* m each, eu < ev, lexicographically increasing   */
+    const uint32_t *w;          /* m edge lengths in [1, 65535], or NULL for the hop metric */
 } amc_robust_query;
 
 typedef struct amc_robust_result {

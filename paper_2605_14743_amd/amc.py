@@ -75,7 +75,7 @@ class TrajResult(C.Structure):
 class RobustQuery(C.Structure):
     _fields_ = [("s", _P(C.c_double)), ("f", _P(C.c_double)), ("samples", C.c_int32), ("delta", C.c_double),
                 ("r_min", C.c_double), ("seed", C.c_uint64), ("m", C.c_int64), ("eu", _P(C.c_int32)),
-                ("ev", _P(C.c_int32))]
+                ("ev", _P(C.c_int32)), ("w", _P(C.c_uint32))]
 
 
 class RobustResult(C.Structure):
@@ -574,8 +574,8 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
 
 def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.05, seed=0, topology=None) -> dict:
     """amc_robust: transition reward-AFCs, sampled admissible kernels with their KL / TV
-    (and, with topology = (eu, ev), W1) maximisers, and the first-order sensitivity with its
-    remainder (Sections 5.1, 5.4, 6.4, 9.1)."""
+    (and, with topology = (eu, ev) or (eu, ev, edge lengths), W1) maximisers, and the
+    first-order sensitivity with its remainder (Sections 5.1, 5.4, 6.4, 9.1, 9.2)."""
     Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
     n = Q0.shape[0]
     q = RobustQuery()
@@ -594,6 +594,10 @@ def robust(ctx: Context, Q0, *, s=None, f=None, samples=16, delta=0.5, r_min=0.0
         ev = np.ascontiguousarray(topology[1], dtype=np.int32)
         keep += [eu, ev]
         q.m, q.eu, q.ev = len(eu), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32)
+        if len(topology) > 2 and topology[2] is not None:
+            wa = np.ascontiguousarray(topology[2], dtype=np.uint32)
+            keep.append(wa)
+            q.w = _ptr(wa, C.c_uint32)
     arr = {"b0": np.zeros(n), "kl": np.zeros(max(samples, 1)), "tv": np.zeros(max(samples, 1)), "b_kl": np.zeros(n),
            "b_tv": np.zeros(n), "b_lin": np.zeros(n), "w1": np.zeros(max(samples, 1)), "b_w1": np.zeros(n)}
     res = RobustResult()

@@ -50,8 +50,8 @@ hipError_t robust_gemm(int n, const double *A, const double *B, double *C, hipSt
 hipError_t robust_rem_bound(const unsigned long long *norms, double *out, hipStream_t st);
 hipError_t robust_trans_rewards(int n, const double *Q, const double *f, double *psw, double *pimp, hipStream_t st);
 size_t w1_lds_bytes(int n);
-hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *rp, const int32_t *inc,
-                     int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
+hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const uint32_t *len, const int32_t *rp,
+                     const int32_t *inc, int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
                      hipStream_t st);
 
 // Anchored r-hop neighbourhoods (LDS mode only).

@@ -67,6 +67,7 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
             const int32_t a = q->eu[e], b = q->ev[e];
             if (a < 0 || b >= n || a >= b) return AMC_E_INVALID_ARG;
             if (e > 0 && (q->eu[e - 1] > a || (q->eu[e - 1] == a && q->ev[e - 1] >= b))) return AMC_E_INVALID_ARG;
+            if (q->w && (q->w[e] < 1u || q->w[e] > 65535u)) return AMC_E_INVALID_ARG;
         }
         rp.assign((size_t)n + 1, 0);
         for (int64_t e = 0; e < m; ++e) {
@@ -145,7 +146,9 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
     int32_t *dev_ = w1_on && m > 0 ? (int32_t *)alloc(4 * (size_t)m) : nullptr;
     int32_t *drp = w1_on ? (int32_t *)alloc(4 * ((size_t)n + 1)) : nullptr;
     int32_t *dinc = w1_on && m > 0 ? (int32_t *)alloc(8 * (size_t)m) : nullptr;
-    if (w1_on && (!w1 || !bw1 || !drp || (m > 0 && (!fscr || !deu || !dev_ || !dinc)))) return AMC_E_OOM;
+    uint32_t *dlen = w1_on && m > 0 && q->w ? (uint32_t *)alloc(4 * (size_t)m) : nullptr;
+    if (w1_on && (!w1 || !bw1 || !drp || (m > 0 && (!fscr || !deu || !dev_ || !dinc || (q->w && !dlen)))))
+        return AMC_E_OOM;
     int32_t *top = (int32_t *)alloc(4 * 16);
     int *args = (int *)alloc(16), *err = (int *)alloc(16);
     unsigned long long *norms = (unsigned long long *)alloc(8 * 4);
@@ -162,6 +165,7 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
             HIPCHK(hipMemcpyAsync(deu, q->eu, 4 * (size_t)m, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(dev_, q->ev, 4 * (size_t)m, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(dinc, inc.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
+            if (dlen) HIPCHK(hipMemcpyAsync(dlen, q->w, 4 * (size_t)m, hipMemcpyHostToDevice, st));
         }
     }
     HIPCHK(fill_u32(err, 4, 0u, st));
@@ -199,7 +203,8 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
     }
     for (int k0 = 0; w1_on && k0 < S; k0 += Wt) {
         const int nb = std::min(Wt, S - k0);
-        HIPCHK(robust_w1(n, (int)m, deu, dev_, drp, dinc, nb, brows + (size_t)k0 * n, b0, fscr, w1 + k0, err, st));
+        HIPCHK(robust_w1(n, (int)m, deu, dev_, dlen, drp, dinc, nb, brows + (size_t)k0 * n, b0, fscr, w1 + k0, err,
+                         st));
     }
     if (S > 0) {
         HIPCHK(robust_argmax(S, kl, args, st));

@@ -1,5 +1,6 @@
-// w1.hip -- Wasserstein-1 between AFC profiles on the hop metric of the base
-// topology, one workgroup per sampled profile.
+// w1.hip -- Wasserstein-1 between AFC profiles on the shortest-path metric of
+// the base topology (unit edge lengths, or given integer lengths), one
+// workgroup per sampled profile.
 //
 // Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
 // Uncertainty: An Absorbing Markov Chain Approach" (robust experiment of
@@ -7,11 +8,12 @@
 // topology as ground metric; W1 as an integral probability metric, Section 4).
 //
 // On a graph metric, W1(p, q) is the cost of the cheapest flow that moves the
-// surplus p - q over the edges at cost 1 per unit and edge.  The workgroup
-// solves that transshipment by successive shortest paths, in phases:
+// surplus p - q over the edges at cost c_e per unit on edge e (c_e = 1 for the
+// hop metric).  The workgroup solves that transshipment by successive
+// shortest paths, in phases:
 //   - the residual graph: an edge carrying flow f from u to v offers v -> u at
-//     cost -1 (capacity f) and u -> v at cost +1; a flow-free edge offers both
-//     directions at +1;
+//     cost -c_e (capacity f) and u -> v at cost +c_e; a flow-free edge offers
+//     both directions at +c_e;
 //   - a phase labels every node with (distance, hops) from the nodes with
 //     surplus, by parallel Bellman-Ford passes over the edges with 64-bit LDS
 //     minima on the packed label until a pass changes nothing (at most n + 1
@@ -28,7 +30,7 @@
 //     leaves the labels a feasible potential (the reverse of a realising arc
 //     realises the label back), so every later path of length D* is still a
 //     shortest one; a deficit node whose walk fails is left to the next phase.
-// W1 is the sum of |flow| over the edges once no surplus or no deficit is
+// W1 is the sum of c_e |flow| over the edges once no surplus or no deficit is
 // left.  Every loop has a bound; exceeding one sets bit 4 of *err.
 #include "amc_dev.hpp"
 #include "amc_kernels.hpp"
@@ -39,6 +41,7 @@ namespace {
 
 constexpr int kW1Threads = 256;
 constexpr uint64_t kNoLabel = ~0ull;
+// distances of simple walks stay within (n - 1) * 65535 < 2^31 for n <= 3000
 constexpr uint64_t kDistBias = 1ull << 31;
 
 __device__ __forceinline__ uint64_t w1_label(int64_t dist, uint32_t hops) {
@@ -53,13 +56,15 @@ __device__ __forceinline__ int w1_sign(double f) { return f > 0.0 ? 1 : (f < 0.0
 
 }  // namespace
 
-// CACHED: the edge ends (packed 16 + 16 bits) and the signs of the flows sit
-// in LDS next to the per-node arrays (when they fit), otherwise the ends are
-// read from HBM and the signs from the flows.
+// CACHED: the edge ends (packed 16 + 16 bits), the signs of the flows and the
+// edge lengths (16 bits, when given) sit in LDS next to the per-node arrays
+// (when they fit), otherwise the ends and lengths are read from HBM and the
+// signs from the flows.  len = nullptr: every edge has length 1.
 template <bool CACHED>
 __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *eu, const int32_t *ev,
-                                                   const int32_t *rp, const int32_t *inc, const double *P,
-                                                   const double *q, double *fscr, double *w1, int *err) {
+                                                   const uint32_t *len, const int32_t *rp, const int32_t *inc,
+                                                   const double *P, const double *q, double *fscr, double *w1,
+                                                   int *err) {
     extern __shared__ double w1_smem[];
     double *ex = w1_smem;                                   // n: remaining surplus (> 0) / deficit (< 0)
     uint64_t *key = (uint64_t *)(ex + n);                   // n: packed (distance, hops) labels
@@ -67,6 +72,7 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     uint8_t *tried = (uint8_t *)(path + n);                 // n: deficit nodes whose walk failed this phase
     uint32_t *ends = (uint32_t *)(tried + ((n + 3) & ~3));  // m (CACHED): eu | ev << 16
     int8_t *sgn = (int8_t *)(ends + (CACHED ? m : 0));      // m (CACHED): sign of the flow
+    uint16_t *lens = (uint16_t *)(sgn + (CACHED ? ((m + 1) & ~1) : 0));   // m (CACHED, len given): lengths
     __shared__ int s_any_src, s_any_snk, s_changed, s_stop, s_pushed;
     __shared__ uint64_t s_best;
     __shared__ uint32_t s_sink;
@@ -80,11 +86,15 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
         if constexpr (CACHED) {
             ends[e] = (uint32_t)eu[e] | ((uint32_t)ev[e] << 16);
             sgn[e] = 0;
+            if (len) lens[e] = (uint16_t)len[e];
         }
     }
     auto end_a = [&](int e) { return CACHED ? (int)(ends[e] & 0xFFFFu) : eu[e]; };
     auto end_b = [&](int e) { return CACHED ? (int)(ends[e] >> 16) : ev[e]; };
     auto sign_of = [&](int e) { return CACHED ? (int)sgn[e] : w1_sign(f[e]); };
+    auto len_of = [&](int e) -> int64_t { return len ? (CACHED ? (int64_t)lens[e] : (int64_t)len[e]) : 1; };
+    // cost of crossing edge e (flow sign sg) from its first endpoint (fwd) or its second
+    auto arc_cost = [&](int e, int sg, bool fwd) { return w1_cost(sg, fwd) * len_of(e); };
     if (tid == 0) s_stop = 0;
     __syncthreads();
     const long max_phases = 16L * ((long)n + m) + 16;
@@ -126,11 +136,11 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
                 const int sg = sign_of(e);
                 const uint64_t ka = key[a], kb = key[b];
                 if (ka != kNoLabel) {
-                    const uint64_t c = w1_label(w1_dist(ka) + w1_cost(sg, true), (uint32_t)ka + 1u);
+                    const uint64_t c = w1_label(w1_dist(ka) + arc_cost(e, sg, true), (uint32_t)ka + 1u);
                     if (c < kb && atomicMin((unsigned long long *)&key[b], (unsigned long long)c) > c) ch = true;
                 }
                 if (kb != kNoLabel) {
-                    const uint64_t c = w1_label(w1_dist(kb) + w1_cost(sg, false), (uint32_t)kb + 1u);
+                    const uint64_t c = w1_label(w1_dist(kb) + arc_cost(e, sg, false), (uint32_t)kb + 1u);
                     if (c < ka && atomicMin((unsigned long long *)&key[a], (unsigned long long)c) > c) ch = true;
                 }
             }
@@ -175,9 +185,9 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
             const int sg = sign_of(e);
             const uint64_t ka = key[a], kb = key[b];
             if (ka != kNoLabel && kb != kNoLabel) {
-                if (w1_label(w1_dist(ka) + w1_cost(sg, true), (uint32_t)ka + 1u) == kb)
+                if (w1_label(w1_dist(ka) + arc_cost(e, sg, true), (uint32_t)ka + 1u) == kb)
                     atomicMin(&pred[b], 2u * (uint32_t)e);
-                if (w1_label(w1_dist(kb) + w1_cost(sg, false), (uint32_t)kb + 1u) == ka)
+                if (w1_label(w1_dist(kb) + arc_cost(e, sg, false), (uint32_t)kb + 1u) == ka)
                     atomicMin(&pred[a], 2u * (uint32_t)e + 1u);
             }
         }
@@ -217,7 +227,7 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
                     const bool fwd = (arc & 1u) == 0u;           // eu -> ev arrives at x
                     const int y = fwd ? end_a(e) : end_b(e);
                     const uint64_t ky = key[y];
-                    if (w1_label(w1_dist(ky) + w1_cost(sign_of(e), fwd), (uint32_t)ky + 1u) != key[x]) {
+                    if (w1_label(w1_dist(ky) + arc_cost(e, sign_of(e), fwd), (uint32_t)ky + 1u) != key[x]) {
                         ok = false;                               // a push changed this arc's cost
                         break;
                     }
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
     }
     __syncthreads();
     double acc = 0.0;
-    for (int e = tid; e < m; e += kW1Threads) acc += fabs(f[e]);
+    for (int e = tid; e < m; e += kW1Threads) acc += (double)len_of(e) * fabs(f[e]);
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((tid & 63) == 0) s_part[tid >> 6] = acc;
     __syncthreads();
@@ -272,16 +282,17 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
 
 size_t w1_lds_bytes(int n) { return 20 * (size_t)n + (((size_t)n + 3) & ~(size_t)3); }
 
-hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *rp, const int32_t *inc,
-                     int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
+hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const uint32_t *len, const int32_t *rp,
+                     const int32_t *inc, int batch, const double *P, const double *q, double *fscr, double *w1, int *err,
                      hipStream_t st) {
-    const size_t cached = w1_lds_bytes(n) + 5 * (size_t)m;
+    // cached layout: ends u32[m] | signs i8[m] (rounded up to even) | lengths u16[m]
+    const size_t cached = w1_lds_bytes(n) + 4 * (size_t)m + (((size_t)m + 1) & ~(size_t)1) + (len ? 2 * (size_t)m : 0);
     if (cached <= 64000)
-        hipLaunchKernelGGL(k_w1<true>, dim3(batch), dim3(kW1Threads), cached, st, n, m, eu, ev, rp, inc, P, q, fscr,
-                           w1, err);
+        hipLaunchKernelGGL(k_w1<true>, dim3(batch), dim3(kW1Threads), cached, st, n, m, eu, ev, len, rp, inc, P, q,
+                           fscr, w1, err);
     else
-        hipLaunchKernelGGL(k_w1<false>, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, rp, inc, P,
-                           q, fscr, w1, err);
+        hipLaunchKernelGGL(k_w1<false>, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, len, rp, inc,
+                           P, q, fscr, w1, err);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """GPU parity of the Wasserstein-1 leg of the robust tail (amc_robust with a
-base topology; robust experiment of Section 9.1) against the oracle: W1 of
+base topology, on the hop metric or on integer edge lengths; robust
+experiments of Sections 9.1 and 9.2) against the oracle: W1 of
 every sampled profile from b0 within 1e-11 of the largest (two exact
 transshipment solvers that push along different shortest paths), the
 maximiser identical unless the two largest are that close, and the AFC at
@@ -45,14 +46,14 @@ def connected_graph(n, extra, seed):
     return e[:, 0], e[:, 1]
 
 
-def oracle_w1(Q0, eu, ev, samples, delta, r_min, seed, only=None):
+def oracle_w1(Q0, eu, ev, samples, delta, r_min, seed, only=None, cost=None):
     n = Q0.shape[0]
     s = np.full(n, 1.0 / n)
     b0 = O.chain(Q0, s)["b"]
     out = {}
     for k in (range(samples) if only is None else only):
         bk = O.chain(O.perturbed_kernel(Q0, seed, k, delta, r_min), s)["b"]
-        out[k] = (O.w1(n, eu, ev, bk, b0), bk)
+        out[k] = (O.w1(n, eu, ev, bk, b0, cost=cost), bk)
     return out
 
 
@@ -156,3 +157,77 @@ def test_topology_arguments(ctx):
     # no samples: nothing to measure, no maximiser
     g = amc.robust(ctx, Q0, samples=0, topology=(eu, ev))
     assert g["w1_arg"] == -1
+
+
+# ---- integer edge lengths (the weighted ground metric) ----
+
+@pytest.mark.parametrize("n,extra,samples,w_hi", [(7, 4, 12, 9), (64, 40, 12, 100), (130, 300, 12, 65535),
+                                                  (20, 10, 130, 3)])
+def test_weighted_random_topologies(ctx, n, extra, samples, w_hi):
+    Q0 = random_kernel(n, n + 1)
+    eu, ev = connected_graph(n, extra, n + 1)
+    w = np.random.default_rng(n).integers(1, w_hi + 1, len(eu)).astype(np.uint32)
+    say(f"[gpu] robust w1 weighted n={n} m={len(eu)} lengths 1..{w_hi} samples={samples}")
+    g = amc.robust(ctx, Q0, samples=samples, delta=0.4, r_min=0.05, seed=n, topology=(eu, ev, w))
+    o = oracle_w1(Q0, eu, ev, samples, 0.4, 0.05, n, cost=w)
+    check(g, o, f"weighted n={n}")
+    g0 = amc.robust(ctx, Q0, samples=samples, delta=0.4, r_min=0.05, seed=n, topology=(eu, ev))
+    assert np.array_equal(g0["kl"], g["kl"]) and np.array_equal(g0["tv"], g["tv"])
+    # every length at least 1: never below the hop metric, never above w_hi times it
+    assert np.all(g["w1"] >= g0["w1"] * (1 - 1e-12)) and np.all(g["w1"] <= w_hi * g0["w1"] * (1 + 1e-12))
+
+
+def test_unit_lengths_are_the_hop_metric(ctx):
+    n = 64
+    Q0 = random_kernel(n, 4)
+    eu, ev = connected_graph(n, 40, 4)
+    say("[gpu] robust w1 with explicit unit lengths")
+    g1 = amc.robust(ctx, Q0, samples=12, delta=0.4, r_min=0.05, seed=4,
+                    topology=(eu, ev, np.ones(len(eu), np.uint32)))
+    g0 = amc.robust(ctx, Q0, samples=12, delta=0.4, r_min=0.05, seed=4, topology=(eu, ev))
+    assert np.array_equal(g1["w1"], g0["w1"]) and g1["w1_arg"] == g0["w1_arg"]
+
+
+@pytest.mark.parametrize("n", [50, 2500])
+def test_weighted_path_closed_form(ctx, n):
+    # on a path with lengths w_i, W1 = sum_i w_i |cumulative difference up to i|;
+    # n = 2500 takes the kernel that reads ends, lengths and signs from HBM
+    Q0 = random_kernel(n, 11, density=0.5 if n < 100 else 0.004)
+    eu = np.arange(n - 1, dtype=np.int32)
+    ev = eu + 1
+    w = np.random.default_rng(n).integers(1, 1000, n - 1).astype(np.uint32)
+    samples = 8 if n < 100 else 3
+    say(f"[gpu] robust w1 on a weighted path of {n} vertices")
+    g = amc.robust(ctx, Q0, samples=samples, delta=0.5, r_min=0.05, seed=6, topology=(eu, ev, w))
+    if n < 100:
+        o = oracle_w1(Q0, eu, ev, samples, 0.5, 0.05, 6, cost=w)
+        check(g, o, "weighted path")
+    k = g["w1_arg"]
+    expect = (w * np.abs(np.cumsum(g["b_w1"] - g["b0"])[:-1])).sum()
+    assert g["w1"][k] == pytest.approx(expect, rel=1e-10)
+
+
+def test_cooc77_fixed_weights(ctx):
+    # the 77-node weighted co-occurrence stand-in with its own fixed weights as
+    # the ground metric, on the kernel estimated from its run
+    wl = W.config_cooc77()
+    gr = wl.graph
+    G = amc.Graph(ctx, gr.n, gr.eu, gr.ev, gr.w0)
+    res = amc.run(ctx, G, wl.model(), seed=wl.seed, R=2000, alpha=wl.alpha, k_min=wl.k_min)
+    G.close()
+    say("[gpu] robust w1 on the cooc77 kernel with its weights, 40 samples")
+    g = amc.robust(ctx, res["Q"], samples=40, delta=0.5, r_min=0.05, seed=2, topology=(gr.eu, gr.ev, gr.w0))
+    o = oracle_w1(res["Q"], gr.eu, gr.ev, 40, 0.5, 0.05, 2, cost=gr.w0)
+    check(g, o, "cooc77 weighted")
+
+
+def test_edge_length_arguments(ctx):
+    n = 6
+    Q0 = random_kernel(n, 1)
+    eu, ev = connected_graph(n, 2, 1)
+    for bad in (0, 65536):
+        w = np.ones(len(eu), np.uint32)
+        w[len(eu) // 2] = bad
+        with pytest.raises(amc.AmcError) as ei:
+            amc.robust(ctx, Q0, samples=3, topology=(eu, ev, w))
+        assert ei.value.rc == amc.E_INVALID_ARG
