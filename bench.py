@@ -503,9 +503,10 @@ def run_traj(args):
     print(json.dumps(out), flush=True)
 
 
-def serve_trace(amc, trace, ctx_budget: int = 0) -> dict:
+def serve_trace(amc, trace, ctx_budget: int = 0, progress: bool = False) -> dict:
     """Runs a trace [(arrival_s, Workload)] through amc_submit; latency of a
-    query = its finish time - its submit time."""
+    query = its finish time - its submit time.  progress: a stderr line
+    about every 20 s of waiting, with the queries completed so far."""
     import torch
     ctx = amc.Context(0, budget_bytes=ctx_budget)
     graphs = [amc.Graph(ctx, wl.graph.n, wl.graph.eu, wl.graph.ev) for _, wl in trace]
@@ -519,7 +520,15 @@ def serve_trace(amc, trace, ctx_budget: int = 0) -> dict:
         reqs.append(amc.Request(ctx, G, wl.model(), seed=wl.seed, R=wl.R, alpha=wl.alpha, k_min=wl.k_min,
                                 cert_topk=5, eps=wl.eps, r_lower=wl.r_lower))
     lat, spans = [], []
-    for r in reqs:
+    t_note = time.perf_counter()
+    for i, r in enumerate(reqs):
+        while progress and not r.poll():
+            time.sleep(0.05)
+            if time.perf_counter() - t_note > 20.0:
+                t_note = time.perf_counter()
+                done = sum(x.poll() for x in reqs)
+                print(f"# serving: {done} of {len(reqs)} queries completed at {t_note - t0:.0f} s", file=sys.stderr,
+                      flush=True)
         r.wait()
         t = r.times()
         lat.append(t[2] - t[0])
@@ -552,7 +561,7 @@ def run_serve(args):
     from paper_2605_14743_amd import workloads as W
 
     trace = W.serving_trace(count=args.queries, rate=args.rate, seed=0, n_hi=args.n_hi, logR_hi=args.logR_hi)
-    res = serve_trace(amc, trace)
+    res = serve_trace(amc, trace, progress=True)
     out = {"metric": "realization-sources/sec", "n_gpus": 1, "rate": args.rate, "data": "synthetic",
            "higher_is_better": True, **res,
            "config": {"workload": "poisson-serving", "n_hi": args.n_hi, "logR_hi": args.logR_hi}}

@@ -8,23 +8,29 @@
 // Per work item (realization r, tile of sources) the workgroup realizes the
 // edges of r (Section 3.1) into its scratch, then runs the sources one after
 // another.  A source is a level-synchronous traversal: the current frontier
-// (vertices at the same distance, settled) is spread over groups of G lanes;
-// each group pulls the exact path count of its vertex from its predecessors
-// and relaxes the vertex's edges; newly reached vertices are appended to the
-// queue with one LDS atomic per wavefront (ballot + prefix).  With integer
+// (vertices at the same distance, settled) is spread over groups of G lanes
+// (one lane per vertex when the frontier fills the workgroup, else two or
+// four); each group pulls the exact path count of its vertex from its
+// predecessors and relaxes the vertex's edges; newly reached vertices are
+// appended to the queue with one LDS atomic per wavefront and block of slots
+// (ballot + prefix).  With unit weights a wide new level is ordered by degree
+// so that a wavefront's lanes walk lists of about one length.  With integer
 // weights the unsettled reached vertices wait in a fringe and the next
 // distance is the fringe minimum (distance buckets).  The reverse pass walks
 // the equal-distance segments backwards and accumulates the dependencies of
 // the Section 3.1 betweenness into B(H_r) held in LDS; the reduction and the
 // counting are the same as in the LDS mode.
+#include <type_traits>
+
 #include "amc_dev.hpp"
 #include "amc_kernels.hpp"
 #include "sweep_common.hpp"
 
 namespace amc {
 
-constexpr int kBG = 4;   // lanes per vertex in the block mode
-constexpr int kBU = 4;   // adjacency slots per lane and trip
+constexpr int kBU = 4;          // adjacency slots per lane and trip
+constexpr int kSortMin = 512;    // unit weights: levels at least this large are ordered by degree
+constexpr int kDegClasses = 8;   // degree classes of that order: ceil(degree / 4), the last one open
 
 // LDS: dist u32[n] | sig u64[n] | ord u16[n] | aux u16[n] | B f64[n] | comp
 // u16[n] | csize u16[n] | rp u32[n+1] (the realized row offsets: every
@@ -54,14 +60,94 @@ __host__ __device__ inline size_t block_adj_words(int64_t m, uint32_t adj_bytes)
     return ((2 * (size_t)m + kAdjPad) * adj_bytes + 3) / 4;
 }
 
+// Appends the found[k] lanes of U slots to the queue whose tail is *ctr (LDS)
+// with one atomic per wavefront; pos[k] is the position of slot k's entry.
+template <int U>
+__device__ __forceinline__ void block_append(uint32_t *ctr, const bool (&found)[U], uint32_t (&pos)[U]) {
+    uint64_t m[U];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        m[k] = __ballot(found[k]);
+        tot += (uint32_t)__popcll(m[k]);
+    }
+    if (tot == 0) return;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(ctr, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        pos[k] = base + rank_lt(m[k]);
+        base += (uint32_t)__popcll(m[k]);
+    }
+}
+
+// Reorders q[0, cnt) (one BFS level) by degree class min(ceil(deg / 4),
+// kDegClasses - 1), buf[0, cnt) as the copy, so that the lanes of a
+// wavefront walk adjacency lists of about one length; cls[0, 2 kDegClasses)
+// are counters.  The order inside a class is arbitrary: a level's vertices
+// are processed independently, so the traversal's results do not depend on
+// it.  Every thread of the workgroup calls it.
+__device__ void order_level_by_degree(uint16_t *q, uint16_t *buf, const uint32_t *rp, int cnt, uint32_t *cls) {
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+    if (tid < 2 * kDegClasses) cls[tid] = 0u;
+    __syncthreads();
+    for (int k0 = 0; k0 < cnt; k0 += nthr) {
+        const int k = k0 + tid;
+        int c = kDegClasses;   // none
+        if (k < cnt) {
+            const uint32_t v = q[k];
+            buf[k] = (uint16_t)v;
+            c = min((int)((rp[v + 1] - rp[v] + 3u) >> 2), kDegClasses - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kDegClasses; ++j) {
+            const uint64_t m = __ballot(c == j);
+            if (lane == 0 && m) atomicAdd(&cls[j], (uint32_t)__popcll(m));
+        }
+    }
+    __syncthreads();
+    uint32_t start[kDegClasses];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kDegClasses; ++j) {
+        start[j] = acc;
+        acc += cls[j];
+    }
+    for (int k0 = 0; k0 < cnt; k0 += nthr) {
+        const int k = k0 + tid;
+        int c = kDegClasses;
+        uint32_t v = 0;
+        if (k < cnt) {
+            v = buf[k];
+            c = min((int)((rp[v + 1] - rp[v] + 3u) >> 2), kDegClasses - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kDegClasses; ++j) {
+            const uint64_t m = __ballot(c == j);
+            if (m) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&cls[kDegClasses + j], (uint32_t)__popcll(m));
+                base = __builtin_amdgcn_readfirstlane(base);
+                if (c == j) q[start[j] + base + rank_lt(m)] = (uint16_t)v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Lanes per vertex for a level (or segment) of k vertices: one when the
+// level fills every lane of the workgroup, else two or four so that more
+// wavefronts share it.
+__device__ __forceinline__ int level_group(int k, int nthr) { return k >= nthr ? 1 : (k >= nthr / 2 ? 2 : 4); }
+
 template <bool WEIGHTED, typename ADJ>
 __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ *adj, double *B,
                              uint32_t *dist, unsigned long long *sig, uint16_t *ord, uint16_t *aux, uint32_t *ctl,
                              uint32_t *tmp, int s, int dbg_slot, int &comp_out, int &size_out, bool &ovf) {
     const int n = P.n;
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-    const int sub = tid % kBG, grp = tid / kBG, ngrp = nthr / kBG;
-    // ctl[0]: queue / fringe tail, ctl[1]: scratch scalar
+    // ctl[0]: queue / fringe tail
     for (int v = tid; v < n; v += nthr) dist[v] = kInf;
     __syncthreads();
     if (tid == 0) {
@@ -71,17 +157,19 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
         ctl[0] = WEIGHTED ? 0u : 1u;
     }
     __syncthreads();
-    int f_lo = 0, ord_end = 1, nseg = 0;
-    uint32_t D = 0;
-    for (;;) {
-        if (tid == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
-        ++nseg;
-        // one frontier sweep; groups of kBG lanes per vertex, each lane
-        // taking kBU of its vertex's slots per trip (loads issued together,
-        // the next trip's neighbour entries fetched while this one is used)
-        for (int base = f_lo; base < ord_end; base += ngrp) {
+
+    // one frontier sweep over ord[f_lo, f_hi) at distance D: groups of G
+    // lanes per vertex, each lane taking kBU of its vertex's slots per trip
+    // (loads issued together, the next trip's entries fetched while this one
+    // is used); a vertex pulls its exact path count from its predecessors and
+    // relaxes its edges, newly reached vertices are appended to the queue
+    // (unit weights: ord, the next level) or the fringe (aux)
+    auto relax_level = [&](auto gtag, int f_lo, int f_hi, uint32_t D) {
+        constexpr int G = decltype(gtag)::value;
+        const int sub = G == 1 ? 0 : tid % G, grp = tid / G, ngrp = nthr / G;
+        for (int base = f_lo; base < f_hi; base += ngrp) {
             const int idx = base + grp;
-            const bool mine = idx < ord_end;
+            const bool mine = idx < f_hi;
             unsigned long long acc = 0ull;
             int v = 0;
             uint32_t beg = 0, end = 0;
@@ -90,27 +178,21 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
                 beg = rp[v];
                 end = rp[v + 1];
             }
-            // iterate in lockstep across the wavefront so the append can ballot
             const uint32_t len = end - beg;
-            const uint32_t trips = len > (uint32_t)sub ? (len - (uint32_t)sub + kBG - 1) / kBG : 0u;
-            uint32_t maxtrips = trips;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const uint32_t o = __shfl_xor(maxtrips, off, 64);
-                maxtrips = o > maxtrips ? o : maxtrips;
-            }
+            const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
+            const uint32_t maxtrips = wave_max_fast(trips);
             const uint32_t first = beg + (uint32_t)sub;
             uint32_t nxt[kBU];
 #pragma unroll
-            for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + kBG * k];
+            for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + G * k];
             for (uint32_t t = 0; t < maxtrips; t += kBU) {
-                uint32_t cur[kBU], u[kBU], w[kBU], du[kBU], old[kBU];
+                uint32_t cur[kBU], u[kBU], w[kBU], du[kBU], old[kBU], pos[kBU];
                 bool pred[kBU], rel[kBU], found[kBU];
 #pragma unroll
                 for (int k = 0; k < kBU; ++k) cur[k] = nxt[k];
                 if (t + kBU < maxtrips) {
 #pragma unroll
-                    for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + kBG * (t + kBU + k)];
+                    for (int k = 0; k < kBU; ++k) nxt[k] = (uint32_t)adj[first + G * (t + kBU + k)];
                 }
                 // a slot past the vertex's list reads vertex 0 with weight
                 // kNoEdge (fails both tests)
@@ -138,29 +220,37 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
 #pragma unroll
                 for (int k = 0; k < kBU; ++k) old[k] = rel[k] ? atomicMin(&dist[u[k]], D + w[k]) : 0u;
 #pragma unroll
-                for (int k = 0; k < kBU; ++k) {
-                    found[k] = old[k] == kInf;   // a lane that does not relax keeps 0
-                    const uint32_t pos = wave_append(&ctl[0], found[k]);
-                    if (found[k]) {
-                        if (WEIGHTED) aux[pos] = (uint16_t)u[k];
-                        else ord[pos] = (uint16_t)u[k];
-                    }
-                }
-            }
+                for (int k = 0; k < kBU; ++k) found[k] = old[k] == kInf;   // a lane that does not relax keeps 0
+                block_append<kBU>(&ctl[0], found, pos);
 #pragma unroll
-            for (int off = 1; off < kBG; off <<= 1) {
-                const unsigned long long o = __shfl_xor(acc, off, 64);
-                const unsigned long long x = acc + o;
-                ovf |= x < acc;
-                acc = x;
+                for (int k = 0; k < kBU; ++k)
+                    if (found[k]) {
+                        if (WEIGHTED) aux[pos[k]] = (uint16_t)u[k];
+                        else ord[pos[k]] = (uint16_t)u[k];
+                    }
             }
+            if constexpr (G > 1) acc = group_sum_u64<G>(acc, ovf);
             if (mine && sub == 0 && v != s) sig[v] = acc;
         }
+    };
+
+    int f_lo = 0, ord_end = 1, nseg = 0;
+    uint32_t D = 0;
+    for (;;) {
+        if (tid == 0) aux[n - 1 - nseg] = (uint16_t)f_lo;
+        ++nseg;
+        const int G = level_group(ord_end - f_lo, nthr);
+        if (G == 1) relax_level(std::integral_constant<int, 1>{}, f_lo, ord_end, D);
+        else if (G == 2) relax_level(std::integral_constant<int, 2>{}, f_lo, ord_end, D);
+        else relax_level(std::integral_constant<int, 4>{}, f_lo, ord_end, D);
         __syncthreads();
         if (!WEIGHTED) {
             const int new_end = (int)ctl[0];
             __syncthreads();
             if (new_end == ord_end) break;
+            // the new level occupies ord[ord_end, new_end) and aux[0, new_end -
+            // ord_end) stays below the segment starts at aux[n - nseg, n)
+            if (new_end - ord_end >= kSortMin) order_level_by_degree(ord + ord_end, aux, rp, new_end - ord_end, tmp);
             f_lo = ord_end;
             ord_end = new_end;
             D += 1u;
@@ -240,10 +330,11 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
         }
         __syncthreads();
     }
-    // reverse pass over the equal-distance segments
-    for (int k = nseg - 1; k >= 0; --k) {
-        const int lo = aux[n - 1 - k];
-        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
+    // reverse pass over the equal-distance segments: a vertex sums c_u over
+    // its successors u (G lanes per vertex, as in the forward sweep)
+    auto accumulate_segment = [&](auto gtag, int lo, int hi) {
+        constexpr int G = decltype(gtag)::value;
+        const int sub = G == 1 ? 0 : tid % G, grp = tid / G, ngrp = nthr / G;
         for (int base = lo; base < hi; base += ngrp) {
             const int idx = base + grp;
             const bool mine = idx < hi;
@@ -254,12 +345,12 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
                 const uint32_t dv = dist[v];
                 const uint32_t beg = rp[v], end = rp[v + 1];
                 const uint32_t len = end - beg;
-                const uint32_t trips = len > (uint32_t)sub ? (len - (uint32_t)sub + kBG - 1) / kBG : 0u;
+                const uint32_t trips = G == 1 ? len : (len > (uint32_t)sub ? (len - (uint32_t)sub + G - 1) / G : 0u);
                 const uint32_t first = beg + (uint32_t)sub;
                 for (uint32_t t = 0; t < trips; t += kBU) {
                     uint32_t a[kBU], u[kBU], du[kBU];
 #pragma unroll
-                    for (int k = 0; k < kBU; ++k) a[k] = (uint32_t)adj[first + kBG * (t + k)];
+                    for (int k = 0; k < kBU; ++k) a[k] = (uint32_t)adj[first + G * (t + k)];
 #pragma unroll
                     for (int k = 0; k < kBU; ++k) u[k] = (t + k < trips) ? (a[k] & 0xFFFFu) : 0u;
 #pragma unroll
@@ -271,8 +362,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
                     }
                 }
             }
-#pragma unroll
-            for (int off = 1; off < kBG; off <<= 1) sum += __shfl_xor(sum, off, 64);
+            if constexpr (G > 1) sum = group_sum_f64<G>(sum);
             if (mine && sub == 0) {
                 const double sv = (double)sig[v];
                 const double delta = sv * sum;
@@ -281,6 +371,14 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
                 if (dbg_slot >= 0) P.dbg_delta[(size_t)dbg_slot * n + v] = delta;
             }
         }
+    };
+    for (int k = nseg - 1; k >= 0; --k) {
+        const int lo = aux[n - 1 - k];
+        const int hi = (k == nseg - 1) ? ord_end : (int)aux[n - 2 - k];
+        const int G = level_group(hi - lo, nthr);
+        if (G == 1) accumulate_segment(std::integral_constant<int, 1>{}, lo, hi);
+        else if (G == 2) accumulate_segment(std::integral_constant<int, 2>{}, lo, hi);
+        else accumulate_segment(std::integral_constant<int, 4>{}, lo, hi);
         __syncthreads();
     }
 }

@@ -293,6 +293,41 @@ def test_er5000_sampled_realizations_with_pool(ctx):
         check_sweep(res, ref, g.n, f"er5000 mode {mode} flags {fl}")
 
 
+def _er_with_hubs(n, p, hubs, spokes, seed):
+    # G(n, p) plus `hubs` vertices joined to `spokes` random others each
+    g = W.er_graph(n, p, seed)
+    rng = np.random.default_rng(seed)
+    pairs = set(zip(g.eu.tolist(), g.ev.tolist()))
+    for h in range(hubs):
+        for v in rng.choice(np.arange(hubs, n), spokes, replace=False).tolist():
+            pairs.add((h, v))
+    return W.canonical(n, sorted(pairs), name=f"er{n}+{hubs}hubs")
+
+
+@pytest.mark.parametrize("graph", ["er2000-unit", "hubs1500-unit", "er2000-w3"])
+@pytest.mark.parametrize("tile", [0, 700])
+def test_block_mode_wide_levels_against_oracle(ctx, graph, tile):
+    # levels of several hundred to over a thousand vertices: the workgroup
+    # mode walks them with one or two lanes per vertex and, with unit weights,
+    # orders each wide level by degree (the hubs fall in the open last
+    # class); weights 1..3 give wide equal-distance segments
+    if graph == "er2000-unit":
+        g, model = W.er_graph(2000, 8.0 / 1999, 7), {"p_fail": 0.1, "weight": "unit"}
+    elif graph == "hubs1500-unit":
+        g, model = _er_with_hubs(1500, 6.0 / 1499, 3, 300, 11), {"p_fail": 0.05, "weight": "unit"}
+    else:
+        g, model = W.er_graph(2000, 8.0 / 1999, 8), {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 3}
+    R = 5
+    kw = dict(seed=5, R=R, r_begin=321, alpha=0.15, k_min=5)
+    ref = O.sweep(g.n, g.eu, g.ev, want_next=True, **kw, **model)
+    q = dict(flags=FLAGS | amc.SKIP_TAIL, mode=amc.MODE_BLOCK, **kw)
+    if tile:
+        q["tile"] = tile
+    res = gpu_run(ctx, g, model, **q)
+    assert res["stats"]["mode"] == amc.MODE_BLOCK
+    check_sweep(res, ref, g.n, f"{graph} block tile {tile}")
+
+
 def test_weighted_n2400_l2_mode_sampled(ctx):
     # a graph whose realized adjacency leaves room for only two wavefronts in
     # LDS mode: the planner takes the L2 mode; two realizations split over
