@@ -18,12 +18,10 @@
 
 namespace amc {
 
-// Per-wavefront region: dist u32[n] | sig u64[n] | ord u16[n] | B f64[n] |
-// list u16[n] | mask u8[n].
+// Per-wavefront region: dist u32[n] | sig u64[n + 1] | ord u16[n] | B f64[n] |
+// list u16[n] | mask u8[n] (sig[n] stays 0, as in the sweep kernels).
 __host__ __device__ inline uint32_t anchored_b_offset(int n) {
-    const uint32_t un = (uint32_t)n;
-    const uint32_t sig_off = (4u * un + 7u) & ~7u;
-    return (sig_off + 8u * un + 2u * un + 7u) & ~7u;
+    return (wave_ord_offset(n, false) + 2u * (uint32_t)n + 7u) & ~7u;
 }
 __host__ __device__ inline uint32_t anchored_private_bytes(int n) {
     const uint32_t un = (uint32_t)n;
@@ -69,7 +67,7 @@ __global__ __launch_bounds__(1024) void anchored_kernel(LaunchCtl LC) {
         const uint32_t b_off = anchored_b_offset(n);
         uint32_t *dist = (uint32_t *)wmine;
         unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
-        uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+        uint16_t *ord = (uint16_t *)(wmine + wave_ord_offset(n, false));
         double *Bw = (double *)(wmine + b_off);
         const BAcc BA{Bw, nullptr, false};
         uint16_t *list = (uint16_t *)(wmine + b_off + 8u * (uint32_t)n);

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void sweep_wave_kernel(LaunchC
             ord = (uint16_t *)(wmine + sig_off);
         } else {
             sig = (unsigned long long *)(wmine + sig_off);
-            ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+            ord = (uint16_t *)(wmine + wave_ord_offset(n, D16));
         }
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)wbase;

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     const uint32_t sig_off = wave_sig_offset(n, D16);
     DT *dist = (DT *)wmine;
     unsigned long long *sig = (unsigned long long *)(wmine + sig_off);
-    uint16_t *ord = (uint16_t *)(wmine + sig_off + 8u * (uint32_t)n);
+    uint16_t *ord = (uint16_t *)(wmine + wave_ord_offset(n, D16));
 
     bool ovf = false;
     double rew = 0.0;

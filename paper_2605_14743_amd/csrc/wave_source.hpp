@@ -388,6 +388,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
     if (lane == 0) {
         dist[s] = (DT)0u;
         sig[s] = 1ull;
+        if constexpr (!SG) sig[n] = 0ull;
         ord[0] = (uint16_t)s | kSegMark;
         *ctr = WEIGHTED ? 0u : 1u;
     }
@@ -397,6 +398,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
     uint32_t D = 0;
     uint32_t kmin = kInf;
     uint32_t lmin = kInf;
+    const uint32_t zero = (uint32_t)n;   // sig[n] == 0
 
     // relaxations out of the batch ord[base, min(base + 64 / G, ord_end))
     auto relax_batch = [&](auto gtag, int base) {
@@ -465,11 +467,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    // read from a vertex in range either way (no branch), keep it if u precedes v
-                    const unsigned long long val = sig[pred[k] ? u[k] : (uint32_t)s];
-                    sg[k] = pred[k] ? val : 0ull;
-                }
+                for (int k = 0; k < U; ++k) sg[k] = sig[pred[k] ? u[k] : zero];   // no branch: 0 unless u precedes v
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) old[k] = rel[k] ? DO::issue_min(dist, u[k], D + w[k], wd[k]) : 0u;
@@ -623,11 +621,7 @@ __device__ void wave_source_lane(const SweepParams &P, const ADJ *rp, const ADJ 
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const bool succ = du[k] == dv + w[k];
-                    const unsigned long long val = sig[succ ? u[k] : (uint32_t)v];
-                    cu[k] = succ ? as_f64(val) : 0.0;
-                }
+                for (int k = 0; k < U; ++k) cu[k] = as_f64(sig[du[k] == dv + w[k] ? u[k] : zero]);   // 0.0 unless u succeeds v
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) sum += cu[k];                       // u succeeds v: c_u
@@ -689,13 +683,17 @@ __device__ __forceinline__ void run_source(const SweepParams &P, const ADJ *rp, 
 }
 
 // Per-wavefront region of the sweep and trajectory kernels: dist DT[n] |
-// sig u64[n] | ord u16[n]; with the path counts in global memory (sg) just
-// dist DT[n] | ord u16[n].
+// sig u64[n + 1] | ord u16[n] (sig[n] stays 0: the slot a path-count load
+// reads for a neighbour that is not a predecessor / successor); with the
+// path counts in global memory (sg) just dist DT[n] | ord u16[n].
 __host__ __device__ inline uint32_t wave_sig_offset(int n, bool dist16) {
     return ((dist16 ? 2u : 4u) * (uint32_t)n + 7u) & ~7u;
 }
+__host__ __device__ inline uint32_t wave_ord_offset(int n, bool dist16) {
+    return wave_sig_offset(n, dist16) + 8u * ((uint32_t)n + 1u);
+}
 __host__ __device__ inline uint32_t wave_private_bytes(int n, bool dist16, bool sg = false) {
-    return (wave_sig_offset(n, dist16) + (sg ? 2u : 10u) * (uint32_t)n + 15u) & ~15u;
+    return ((sg ? wave_sig_offset(n, dist16) : wave_ord_offset(n, dist16)) + 2u * (uint32_t)n + 15u) & ~15u;
 }
 // Bytes of one wavefront's path-count array in the workgroup's global scratch.
 __host__ __device__ inline uint32_t l2_sig_stride(int n) { return (8u * (uint32_t)n + 255u) & ~255u; }
