@@ -231,6 +231,11 @@ typedef struct amc_result {
     double *b_fb;               /* n: AFC of P^{W,fb}                             */
     double *b_cens;             /* n: censored profile, 0 on V_fb (Section 7.4)   */
     double E_T_fb, m_w_fb, c_fb;/* E_s[T], pool mass and mass off V_fb under P^{W,fb} */
+    /* certificates of the boundary pairs (cert_topk x (n-cert_topk), Section 5.5):
+     * bit 0: G_uv above the sharp threshold (eq. sharp-gap), so u ahead of v is
+     * certified; bit 1: the same with the support-restricted radii; bit 2: G_uv
+     * above the crude threshold 2 epsbar / r_lower^2 */
+    uint8_t *cert_ok;
 } amc_result;
 
 /* Context: one device, one stream, an HBM budget for admission (0 = free HBM). */

@@ -135,7 +135,7 @@ class Result(C.Structure):
                 ("epsbar_supp", C.c_double), ("admissible", C.c_int32), ("stats", Stats),
                 ("psi", _P(C.c_double)), ("psi_w", _P(C.c_double)), ("b_k", C.c_double), ("b_kw", C.c_double),
                 ("b_fb", _P(C.c_double)), ("b_cens", _P(C.c_double)), ("E_T_fb", C.c_double), ("m_w_fb", C.c_double),
-                ("c_fb", C.c_double)]
+                ("c_fb", C.c_double), ("cert_ok", _P(C.c_uint8))]
 
 
 _lib = None
@@ -349,7 +349,7 @@ def _alloc_result(n, q: Query, reuse=None):
         if k > 0:
             arr.update(top=np.zeros(k, np.int32), cert_v=np.zeros(n - k, np.int32),
                        cert_gap=np.zeros((k, n - k)), cert_sharp=np.zeros((k, n - k)),
-                       cert_sharp_supp=np.zeros((k, n - k)))
+                       cert_sharp_supp=np.zeros((k, n - k)), cert_ok=np.zeros((k, n - k), np.uint8))
     if q.n_debug > 0:
         arr.update(dbg_dist=np.zeros((q.n_debug, n), np.uint32), dbg_sigma=np.zeros((q.n_debug, n), np.uint64),
                    dbg_delta=np.zeros((q.n_debug, n)))
@@ -367,7 +367,7 @@ def _alloc_result(n, q: Query, reuse=None):
                 arr[key] = b
     res = Result()
     types = {np.dtype(np.uint32): C.c_uint32, np.dtype(np.int32): C.c_int32, np.dtype(np.float64): C.c_double,
-             np.dtype(np.uint64): C.c_uint64}
+             np.dtype(np.uint64): C.c_uint64, np.dtype(np.uint8): C.c_uint8}
     for key, a in arr.items():
         setattr(res, key, _ptr(a, types[a.dtype]))
     return res, arr

@@ -635,7 +635,7 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     b += 8 * n * 8 + 8 * (uint64_t)g->m + 4096;          // bsum, vectors, thresholds, control
     // partial-B exchange when realizations are split (upper bound)
     b += (8 + 4 + 4) * R * n + 4 * R;
-    if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + 3 * 8 * 16 * n;
+    if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + (3 * 8 + 1) * 16 * n + 1024;
     // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
     const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true),
                                            l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u, kMaxWaves));

@@ -94,7 +94,7 @@ hipError_t tail_visits(int n, const double *N, const double *s, double *mu, doub
                        double *scal, hipStream_t st);
 hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, const double *mu,
                              const int32_t *top, int32_t *cv, double eps, double r_lower, double *gap,
-                             double *sharp, double *sharp_supp, int *support, hipStream_t st);
+                             double *sharp, double *sharp_supp, uint8_t *ok, int *support, hipStream_t st);
 hipError_t tail_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi, hipStream_t st);
 
 // Bootstrap of b (Section 8.4).

@@ -225,6 +225,7 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
             RCHK(A.alloc(8 * pairs, &p)); T.gap = (double *)p;
             RCHK(A.alloc(8 * pairs, &p)); T.sharp = (double *)p;
             RCHK(A.alloc(8 * pairs, &p)); T.sharp_supp = (double *)p;
+            RCHK(A.alloc(pairs, &p)); T.cert_ok = (uint8_t *)p;
         }
         if (q->topk > 0) {
             RCHK(A.alloc(8 * 8, &p));
@@ -442,7 +443,7 @@ int qr_enqueue_tail(QueryRun &R, hipStream_t st, bool from_Q) {
     RCHK(tail_chain(n, R.P.counts, q.R, R.eta, T.Q, T.r, T.N, T.mu, T.b, T.s, T.f, nullptr, nullptr, q.r_lower,
                     q.cert_topk, T.top, T.scal, R.d_err, from_Q, st));
     HIPCHK(tail_certificates(n, q.cert_topk, T.Q, T.N, T.mu, T.top, T.cv, q.eps, q.r_lower, T.gap, T.sharp,
-                             T.sharp_supp, T.support, st));
+                             T.sharp_supp, T.cert_ok, T.support, st));
     if (R.cw && R.P.pool) {   // constrained kernel P^W (Section 7), same pipeline
         HIPCHK(tail_xi(n, R.cw, q.R, T.xi, st));
         RCHK(tail_chain(n, R.cw, q.R, R.eta, T.Qw, T.rw, T.Nw, T.muw, T.bw, T.s, T.f, R.P.pool, T.bbar, 0.0,
@@ -529,6 +530,7 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
             RCHK(copy_out(out->cert_gap, T.gap, 8 * pairs, st));
             RCHK(copy_out(out->cert_sharp, T.sharp, 8 * pairs, st));
             RCHK(copy_out(out->cert_sharp_supp, T.sharp_supp, 8 * pairs, st));
+            RCHK(copy_out(out->cert_ok, T.cert_ok, pairs, st));
         }
         if (T.bw) {
             RCHK(copy_out(out->b_w, T.bw, 8 * (size_t)n, st));
@@ -693,6 +695,7 @@ extern "C" int amc_chain(amc_ctx *ctx, int32_t n, const double *Q, const amc_que
         RCHK(A.alloc(8 * pairs, &p)); T.gap = (double *)p;
         RCHK(A.alloc(8 * pairs, &p)); T.sharp = (double *)p;
         RCHK(A.alloc(8 * pairs, &p)); T.sharp_supp = (double *)p;
+        RCHK(A.alloc(pairs, &p)); T.cert_ok = (uint8_t *)p;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return AMC_E_HIP;
     if (fill_u32(R.d_err, 4, 0u, st) != hipSuccess || fill_u32(T.support, 1, 0u, st) != hipSuccess) return AMC_E_HIP;

@@ -14,6 +14,7 @@ struct TailBufs {
     int32_t *top = nullptr, *cv = nullptr;
     int *support = nullptr;
     double *gap = nullptr, *sharp = nullptr, *sharp_supp = nullptr;
+    uint8_t *cert_ok = nullptr;
     // constrained kernel P^W
     double *Qw = nullptr, *Nw = nullptr, *rw = nullptr, *muw = nullptr, *bw = nullptr, *bbar = nullptr;
     double *xi = nullptr, *scal_w = nullptr;

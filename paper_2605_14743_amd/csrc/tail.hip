@@ -382,18 +382,26 @@ __global__ void k_cert_colmax(int n, int topk, const double *N, const int32_t *t
 
 // gap G_uv = mu_u - mu_v (eq. pm-gap) and the sharp thresholds (eq.
 // sharp-gap) from the column maxima held in `sharp`.
+// ok: bit 0 gap above the sharp threshold, bit 1 above the support-restricted
+// one, bit 2 above the crude threshold 2 n eps / r_lower^2 (strict: a gap
+// equal to its threshold certifies nothing)
 __global__ void k_certificates(int n, int topk, const double *mu, const int32_t *top, const int32_t *cv, double eps,
-                               double r_lower, const int *support, double *gap, double *sharp, double *sharp_supp) {
+                               double r_lower, const int *support, double *gap, double *sharp, double *sharp_supp,
+                               uint8_t *ok) {
     const int nc = n - topk;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)topk * nc) return;
     const int a = (int)(idx / nc), c = (int)(idx % nc);
     const double coef = (double)n * eps / r_lower;
     const double coef_supp = (double)(*support) * eps / r_lower;
+    const double crude = 2.0 * ((double)n * eps) / (r_lower * r_lower);
     const double mx = as_f64(((const unsigned long long *)sharp)[idx]);
-    gap[idx] = mu[top[a]] - mu[cv[c]];
-    sharp[idx] = coef * mx;
-    if (sharp_supp) sharp_supp[idx] = coef_supp * mx;
+    const double g = mu[top[a]] - mu[cv[c]];
+    const double sh = coef * mx, shs = coef_supp * mx;
+    gap[idx] = g;
+    sharp[idx] = sh;
+    if (sharp_supp) sharp_supp[idx] = shs;
+    if (ok) ok[idx] = (uint8_t)((g > sh ? 1u : 0u) | (g > shs ? 2u : 0u) | (g > crude ? 4u : 0u));
 }
 
 __global__ void k_xi(int n, const uint32_t *counts_w, uint32_t R, double *xi) {
@@ -457,7 +465,7 @@ hipError_t tail_visits(int n, const double *N, const double *s, double *mu, doub
 
 hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, const double *mu,
                              const int32_t *top, int32_t *cv, double eps, double r_lower, double *gap,
-                             double *sharp, double *sharp_supp, int *support, hipStream_t st) {
+                             double *sharp, double *sharp_supp, uint8_t *ok, int *support, hipStream_t st) {
     hipLaunchKernelGGL(k_support, dim3(n), dim3(256), 0, st, n, Q, support);
     if (topk > 0 && topk < n) {
         const int nc = n - topk;
@@ -470,7 +478,7 @@ hipError_t tail_certificates(int n, int topk, const double *Q, const double *N, 
         hipLaunchKernelGGL(k_cert_colmax, dim3(cols, slices), dim3(64), 0, st, n, topk, N, top, cv,
                            (unsigned long long *)sharp);
         hipLaunchKernelGGL(k_certificates, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, n, topk, mu,
-                           top, cv, eps, r_lower, support, gap, sharp, sharp_supp);
+                           top, cv, eps, r_lower, support, gap, sharp, sharp_supp, ok);
     }
     return hipGetLastError();
 }

@@ -466,6 +466,15 @@ def test_chain_appendix_b(ctx, golden):
     assert res["cert_sharp"][0, 0] == pytest.approx(s21, rel=1e-12)
     assert res["cert_sharp"][0, 0] == pytest.approx(ref["sharp_thresholds"]["2,1"], abs=5e-5)
     assert res["cert_crude"] == pytest.approx(ref["crude_threshold"], abs=5e-5)
+    # which orders each threshold certifies, as printed for the three pairs:
+    # top-1 gives the pairs (2,1), (2,3); top-2 (nodes 2, 1) gives (2,3), (1,3)
+    res2 = amc.chain(ctx, Q0, s=np.array(ref["s"]), eps=ref["eps_entry"], r_lower=ref["r_min"], cert_topk=2)
+    assert list(res2["top"]) == [1, 0]
+    for r, pairs in ((res, [("2,1", 0, 0), ("2,3", 0, 1)]), (res2, [("2,3", 0, 0), ("1,3", 1, 0)])):
+        for name, a, c in pairs:
+            ok = int(r["cert_ok"][a, c])
+            assert bool(ok & 1) == ref["sharp_certifies"][name], name
+            assert bool(ok & 4) == ref["crude_certifies"][name], name
 
 
 @pytest.mark.parametrize("n", [1, 2, 31, 33, 64, 97, 300])
@@ -483,6 +492,12 @@ def test_chain_random_kernels(ctx, n):
     assert_close_norm(res["b"], o["b"], what="b")
     assert res["E_T"] == pytest.approx(o["ET"], rel=TOL)
     assert res["b_f"] == pytest.approx(float(o["b"] @ f), rel=1e-12)
+    # the certificate bits are the strict comparisons of the returned gaps and thresholds
+    if n > 1:
+        g, ok = res["cert_gap"], res["cert_ok"].astype(int)
+        assert np.array_equal(ok & 1, (g > res["cert_sharp"]).astype(int))
+        assert np.array_equal((ok >> 1) & 1, (g > res["cert_sharp_supp"]).astype(int))
+        assert np.array_equal((ok >> 2) & 1, (g > res["cert_crude"]).astype(int))
 
 
 # --------------------------------------------------------------------------- per-call weight resampling (Section 9.2)
