@@ -558,7 +558,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         // wavefronts 2.3 vs 4.8 M/s; weighted n = 5000, 2 L2 wavefronts 1.05
         // vs 1.14 M/s)
         const uint32_t block_lds = lds_bytes_block(n, 1024);
-        const bool block_fits = !force_sg &&
+        const bool block_fits = !force_sg && n <= 8191 &&
             block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_staging_bytes(n);
         const double block_below = pl->weighted ? 1.8 : 4.0;
         if (e_best > 0.0 && (!block_fits || e_best >= block_below))
@@ -589,6 +589,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         pl->lds = lds_bytes_block(n, pl->threads);
         if (pl->lds > (uint32_t)ctx->max_lds) return AMC_E_UNSUPPORTED;
         if (2ull * (uint64_t)g->m > block_staging_bytes(n)) return AMC_E_UNSUPPORTED;   // per-edge staging
+        if (n > 8191) return AMC_E_UNSUPPORTED;   // the degree order packs vertex ids into 13 bits
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;

@@ -30,7 +30,8 @@ namespace amc {
 
 constexpr int kBU = 4;          // adjacency slots per lane and trip
 constexpr int kSortMin = 512;    // unit weights: levels at least this large are ordered by degree
-constexpr int kDegClasses = 8;   // degree classes of that order: ceil(degree / 4), the last one open
+constexpr int kDegClasses = 4;   // degree classes of that order: 1-4, 5-8, 9-12, 13 or more
+static_assert(kDegClasses * 16 <= 64, "the class counters share one 64-bit word");
 
 // LDS: dist u32[n] | sig u64[n] | ord u16[n] | aux u16[n] | B f64[n] | comp
 // u16[n] | csize u16[n] | rp u32[n+1] (the realized row offsets: every
@@ -82,56 +83,70 @@ __device__ __forceinline__ void block_append(uint32_t *ctr, const bool (&found)[
     }
 }
 
-// Reorders q[0, cnt) (one BFS level) by degree class min(ceil(deg / 4),
-// kDegClasses - 1), buf[0, cnt) as the copy, so that the lanes of a
-// wavefront walk adjacency lists of about one length; cls[0, 2 kDegClasses)
-// are counters.  The order inside a class is arbitrary: a level's vertices
-// are processed independently, so the traversal's results do not depend on
-// it.  Every thread of the workgroup calls it.
-__device__ void order_level_by_degree(uint16_t *q, uint16_t *buf, const uint32_t *rp, int cnt, uint32_t *cls) {
+// Reorders q[0, cnt) (one BFS level) by degree class min((deg - 1) / 4,
+// kDegClasses - 1), buf[0, cnt) holding each entry with its class in bits
+// 13-15 (the workgroup mode stages at most 5103 vertices, so ids fit in 13
+// bits), so that the lanes of a wavefront walk adjacency lists of about one
+// length.  cls[0] counts the classes and cls[1] hands out their positions,
+// four 16-bit fields each (cnt < 2^13), so that a wavefront claims its share
+// of every class with one atomic.  The order inside a class is arbitrary: a
+// level's vertices are processed independently, so the traversal's results
+// do not depend on it.  Every thread of the workgroup calls it.
+__device__ void order_level_by_degree(uint16_t *q, uint16_t *buf, const uint32_t *rp, int cnt,
+                                      unsigned long long *cls) {
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
-    if (tid < 2 * kDegClasses) cls[tid] = 0u;
+    if (tid < 2) cls[tid] = 0ull;
     __syncthreads();
     for (int k0 = 0; k0 < cnt; k0 += nthr) {
         const int k = k0 + tid;
         int c = kDegClasses;   // none
         if (k < cnt) {
             const uint32_t v = q[k];
-            buf[k] = (uint16_t)v;
-            c = min((int)((rp[v + 1] - rp[v] + 3u) >> 2), kDegClasses - 1);
+            const uint32_t deg = rp[v + 1] - rp[v];   // >= 1: v was reached over an edge
+            c = min((int)((deg - 1u) >> 2), kDegClasses - 1);
+            buf[k] = (uint16_t)(v | ((uint32_t)c << 13));
         }
+        unsigned long long packed = 0ull;
 #pragma unroll
-        for (int j = 0; j < kDegClasses; ++j) {
-            const uint64_t m = __ballot(c == j);
-            if (lane == 0 && m) atomicAdd(&cls[j], (uint32_t)__popcll(m));
-        }
+        for (int j = 0; j < kDegClasses; ++j)
+            packed |= (unsigned long long)__popcll(__ballot(c == j)) << (16 * j);
+        if (lane == 0 && packed) atomicAdd(&cls[0], packed);
     }
     __syncthreads();
+    const unsigned long long tot = cls[0];
     uint32_t start[kDegClasses];
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < kDegClasses; ++j) {
         start[j] = acc;
-        acc += cls[j];
+        acc += (uint32_t)(tot >> (16 * j)) & 0xFFFFu;
     }
     for (int k0 = 0; k0 < cnt; k0 += nthr) {
         const int k = k0 + tid;
         int c = kDegClasses;
         uint32_t v = 0;
         if (k < cnt) {
-            v = buf[k];
-            c = min((int)((rp[v + 1] - rp[v] + 3u) >> 2), kDegClasses - 1);
+            const uint32_t e = buf[k];
+            v = e & 0x1FFFu;
+            c = (int)(e >> 13);
         }
+        uint64_t m[kDegClasses];
+        unsigned long long packed = 0ull;
 #pragma unroll
         for (int j = 0; j < kDegClasses; ++j) {
-            const uint64_t m = __ballot(c == j);
-            if (m) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&cls[kDegClasses + j], (uint32_t)__popcll(m));
-                base = __builtin_amdgcn_readfirstlane(base);
-                if (c == j) q[start[j] + base + rank_lt(m)] = (uint16_t)v;
-            }
+            m[j] = __ballot(c == j);
+            packed |= (unsigned long long)__popcll(m[j]) << (16 * j);
         }
+        unsigned long long base = 0ull;
+        if (lane == 0 && packed) base = atomicAdd(&cls[1], packed);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        base = ((unsigned long long)hi << 32) | lo;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int j = 0; j < kDegClasses; ++j)
+            if (c == j) pos = start[j] + ((uint32_t)(base >> (16 * j)) & 0xFFFFu) + rank_lt(m[j]);
+        if (k < cnt) q[pos] = (uint16_t)v;
     }
     __syncthreads();
 }
@@ -250,7 +265,8 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
             if (new_end == ord_end) break;
             // the new level occupies ord[ord_end, new_end) and aux[0, new_end -
             // ord_end) stays below the segment starts at aux[n - nseg, n)
-            if (new_end - ord_end >= kSortMin) order_level_by_degree(ord + ord_end, aux, rp, new_end - ord_end, tmp);
+            if (new_end - ord_end >= kSortMin)
+                order_level_by_degree(ord + ord_end, aux, rp, new_end - ord_end, (unsigned long long *)tmp);
             f_lo = ord_end;
             ord_end = new_end;
             D += 1u;
@@ -389,7 +405,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
 template <bool WEIGHTED, typename ADJ>
 __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ uint32_t scan_tmp[2 * kMaxWaves];
+    __shared__ __attribute__((aligned(8))) uint32_t scan_tmp[2 * kMaxWaves];
     __shared__ uint32_t ctl[4];
     __shared__ double red_f[kMaxWaves];
     __shared__ int red_i[kMaxWaves];
