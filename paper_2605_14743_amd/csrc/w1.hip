@@ -59,8 +59,9 @@ __device__ __forceinline__ int w1_sign(double f) { return f > 0.0 ? 1 : (f < 0.0
 // CACHED: the edge ends (packed 16 + 16 bits), the signs of the flows and the
 // edge lengths (16 bits, when given) sit in LDS next to the per-node arrays
 // (when they fit), otherwise the ends and lengths are read from HBM and the
-// signs from the flows.  len = nullptr: every edge has length 1.
-template <bool CACHED>
+// signs from the flows.  LEN: edge lengths len[] are given (otherwise every
+// edge has length 1 and len is not read).
+template <bool CACHED, bool LEN>
 __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *eu, const int32_t *ev,
                                                    const uint32_t *len, const int32_t *rp, const int32_t *inc,
                                                    const double *P, const double *q, double *fscr, double *w1,
@@ -86,13 +87,16 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
         if constexpr (CACHED) {
             ends[e] = (uint32_t)eu[e] | ((uint32_t)ev[e] << 16);
             sgn[e] = 0;
-            if (len) lens[e] = (uint16_t)len[e];
+            if constexpr (LEN) lens[e] = (uint16_t)len[e];
         }
     }
     auto end_a = [&](int e) { return CACHED ? (int)(ends[e] & 0xFFFFu) : eu[e]; };
     auto end_b = [&](int e) { return CACHED ? (int)(ends[e] >> 16) : ev[e]; };
     auto sign_of = [&](int e) { return CACHED ? (int)sgn[e] : w1_sign(f[e]); };
-    auto len_of = [&](int e) -> int64_t { return len ? (CACHED ? (int64_t)lens[e] : (int64_t)len[e]) : 1; };
+    auto len_of = [&](int e) -> int64_t {
+        if constexpr (!LEN) return 1;
+        else return CACHED ? (int64_t)lens[e] : (int64_t)len[e];
+    };
     // cost of crossing edge e (flow sign sg) from its first endpoint (fwd) or its second
     auto arc_cost = [&](int e, int sg, bool fwd) { return w1_cost(sg, fwd) * len_of(e); };
     if (tid == 0) s_stop = 0;
@@ -287,12 +291,10 @@ hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const u
                      hipStream_t st) {
     // cached layout: ends u32[m] | signs i8[m] (rounded up to even) | lengths u16[m]
     const size_t cached = w1_lds_bytes(n) + 4 * (size_t)m + (((size_t)m + 1) & ~(size_t)1) + (len ? 2 * (size_t)m : 0);
-    if (cached <= 64000)
-        hipLaunchKernelGGL(k_w1<true>, dim3(batch), dim3(kW1Threads), cached, st, n, m, eu, ev, len, rp, inc, P, q,
-                           fscr, w1, err);
-    else
-        hipLaunchKernelGGL(k_w1<false>, dim3(batch), dim3(kW1Threads), w1_lds_bytes(n), st, n, m, eu, ev, len, rp, inc,
-                           P, q, fscr, w1, err);
+    const bool c = cached <= 64000;
+    const uint32_t lds = c ? (uint32_t)cached : w1_lds_bytes(n);
+    auto kern = c ? (len ? k_w1<true, true> : k_w1<true, false>) : (len ? k_w1<false, true> : k_w1<false, false>);
+    hipLaunchKernelGGL(kern, dim3(batch), dim3(kW1Threads), lds, st, n, m, eu, ev, len, rp, inc, P, q, fscr, w1, err);
     return hipGetLastError();
 }
 
