@@ -25,10 +25,29 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t topk_lds_bytes(int n) {
     return (uint32_t)(8 * n + 8 * n + 4 * n + ((n + 15) & ~15));
 }
+// With ACC the workgroup also sums its realizations' step rewards per anchor
+// in LDS ([8n] psi | [8n] psi_w after the carve-up above) and adds them to
+// the global sums once at the end, instead of one global atomic per anchor
+// and realization (R atomics on each of n addresses); used while the
+// carve-up stays small enough for several workgroups per CU.
+constexpr int kTopkAccMaxN = 4000;
+__host__ __device__ inline uint32_t topk_acc_offset(int n) { return (topk_lds_bytes(n) + 15u) & ~15u; }
+__host__ __device__ inline uint32_t topk_lds_total(int n) {
+    return n <= kTopkAccMaxN ? topk_acc_offset(n) + 16u * (uint32_t)n : topk_lds_bytes(n);
+}
 
+template <bool ACC>
 __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int n = A.n, tid = threadIdx.x, nt = blockDim.x;
+    double *lpsi = ACC ? (double *)(smem + topk_acc_offset(n)) : nullptr;
+    double *lpsiw = ACC ? lpsi + n : nullptr;
+    if constexpr (ACC) {
+        for (int v = tid; v < n; v += nt) {
+            lpsi[v] = 0.0;
+            lpsiw[v] = 0.0;
+        }
+    }
     unsigned long long *cmax = (unsigned long long *)smem;
     double *gsum = (double *)smem;                        // aliases cmax after the ranking
     double *gsumw = (double *)(smem + 8 * (size_t)n);
@@ -91,8 +110,15 @@ __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
             const bool coin = (uint64_t)x.x < A.t_alpha;
             const bool valid = !coin && (uint32_t)csize[i] >= A.k_min;
             if (valid) {
-                global_add_f64(&A.psi[i], gsum[c]);
-                if (A.psi_w) global_add_f64(&A.psi_w[i], gsumw[c]);
+                // anchor i is always this thread's (a fixed stride over the
+                // anchors), so the LDS sums need no atomics
+                if constexpr (ACC) {
+                    lpsi[i] += gsum[c];
+                    lpsiw[i] += gsumw[c];
+                } else {
+                    global_add_f64(&A.psi[i], gsum[c]);
+                    if (A.psi_w) global_add_f64(&A.psi_w[i], gsumw[c]);
+                }
             }
             if (A.counts_w) {
                 const int nw = (valid && wsel[c] != kNone) ? (int)(wsel[c] & 0xFFFFu) : -1;
@@ -101,6 +127,12 @@ __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
             }
         }
         __syncthreads();
+    }
+    if constexpr (ACC) {
+        for (int i = tid; i < n; i += nt) {
+            if (lpsi[i] != 0.0) global_add_f64(&A.psi[i], lpsi[i]);
+            if (A.psi_w && lpsiw[i] != 0.0) global_add_f64(&A.psi_w[i], lpsiw[i]);
+        }
     }
 }
 
@@ -163,13 +195,19 @@ __global__ void k_censor(int n, const double *b, const uint8_t *fb_mask, double 
 
 // ---------------------------------------------------------------------------
 hipError_t set_topk_attrs(int max_lds) {
-    return hipFuncSetAttribute((const void *)k_topk_reduce, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    const hipError_t e =
+        hipFuncSetAttribute((const void *)k_topk_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_topk_reduce<false>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
-uint32_t topk_lds(int n) { return topk_lds_bytes(n); }
+uint32_t topk_lds(int n) { return topk_lds_total(n); }
 
 hipError_t launch_topk_reduce(const TopkArgs &A, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_topk_reduce, dim3(blocks), dim3(256), topk_lds_bytes(A.n), st, A);
+    if (A.n <= kTopkAccMaxN)
+        hipLaunchKernelGGL(k_topk_reduce<true>, dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
+    else
+        hipLaunchKernelGGL(k_topk_reduce<false>, dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
     return hipGetLastError();
 }
 
