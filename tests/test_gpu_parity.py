@@ -648,6 +648,26 @@ def test_ws1000_bench_plan_against_oracle(ctx):
         check_sweep(res, ref, g.n, f"ws1000 bench plan r0={r0}")
 
 
+def test_er5000_bench_plan_against_oracle(ctx):
+    # the n = 5000 unit-weight workload on its benchmark plan: the
+    # workgroup-per-source mode, 16 wavefronts, every source of a realization
+    # in one work item (its wide levels ordered by degree), with its pool;
+    # 40 whole realizations against the oracle over the same range
+    wl = W.config_er5000()
+    g = wl.graph
+    R = 40
+    res = gpu_run(ctx, g, wl.model(), seed=wl.seed, R=R, r_begin=4000, alpha=wl.alpha, k_min=wl.k_min,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, pool=wl.pool,
+                  mode=amc.MODE_BLOCK, tile=g.n)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_BLOCK and st["tile"] == g.n and st["waves"] == 16 and st["tail_split"] == 0, st
+    say(f"[cpu] oracle on er5000 R={R} in {P.workers()} threads")
+    ref = P.sweep(g.n, g.eu, g.ev, seed=wl.seed, R=R, r_begin=4000, alpha=wl.alpha, k_min=wl.k_min, want_next=True,
+                  pool=wl.pool, **wl.model())
+    check_sweep(res, ref, g.n, "er5000 bench plan")
+    assert st["near_band"] == ref["stats"]["near_band"]
+
+
 # --------------------------------------------------------------------------- exact ties with nonzero betweenness
 # Vertex-transitive graphs without failures: every vertex has the same B, so
 # every realization's centres are vertex 0 (the smallest index, Corollary on
