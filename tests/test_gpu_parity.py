@@ -304,7 +304,7 @@ def _er_with_hubs(n, p, hubs, spokes, seed):
     return W.canonical(n, sorted(pairs), name=f"er{n}+{hubs}hubs")
 
 
-@pytest.mark.parametrize("graph", ["er2000-unit", "hubs1500-unit", "er2000-w3"])
+@pytest.mark.parametrize("graph", ["er2000-unit", "hubs1500-unit", "er2000-w3", "er4000-w2"])
 @pytest.mark.parametrize("tile", [0, 700])
 def test_block_mode_wide_levels_against_oracle(ctx, graph, tile):
     # levels of several hundred to over a thousand vertices: the workgroup
@@ -315,8 +315,10 @@ def test_block_mode_wide_levels_against_oracle(ctx, graph, tile):
         g, model = W.er_graph(2000, 8.0 / 1999, 7), {"p_fail": 0.1, "weight": "unit"}
     elif graph == "hubs1500-unit":
         g, model = _er_with_hubs(1500, 6.0 / 1499, 3, 300, 11), {"p_fail": 0.05, "weight": "unit"}
-    else:
+    elif graph == "er2000-w3":
         g, model = W.er_graph(2000, 8.0 / 1999, 8), {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 3}
+    else:   # weights 1..2: equal-distance segments of over a thousand vertices
+        g, model = W.er_graph(4000, 8.0 / 3999, 9), {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 2}
     R = 5
     kw = dict(seed=5, R=R, r_begin=321, alpha=0.15, k_min=5)
     ref = O.sweep(g.n, g.eu, g.ev, want_next=True, **kw, **model)
