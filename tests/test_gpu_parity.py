@@ -348,6 +348,23 @@ def test_weighted_n2400_l2_mode_sampled(ctx):
     check_sweep(res1, ref, g.n, "er2400 L2 whole realizations")
 
 
+@pytest.mark.parametrize("n", [2400, 3000])
+def test_weighted_l2_whole_realizations_default_plan(ctx, n):
+    # the sizes that dominate the mixed batch, on the plan the planner picks
+    # for them (L2 mode, 16-bit distances, B in the scratch when that adds a
+    # wavefront), whole realizations
+    g = W.er_graph(n, 8.0 / (n - 1), n + 1)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    R = 12
+    res = gpu_run(ctx, g, model, seed=5, R=R, r_begin=901, tile=g.n, alpha=0.15, k_min=5,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_WAVE_L2 and st["tile"] == g.n, st
+    say(f"[cpu] oracle on er{n} R={R} in {P.workers()} threads")
+    ref = P.sweep(g.n, g.eu, g.ev, seed=5, R=R, r_begin=901, alpha=0.15, k_min=5, want_next=True, **model)
+    check_sweep(res, ref, g.n, f"er{n} L2 default plan")
+
+
 # --------------------------------------------------------------------------- systems properties
 def test_weighted_n1800_l2_mode_global_b(ctx):
     # n = 1800: B(H_r) in LDS would cost the L2 mode a wavefront, so the
