@@ -494,6 +494,9 @@ def run_traj(args):
         "kernel_ms": tr["sweep_ms"], "realization_sources_per_s": tr["sources"] / (tr["sweep_ms"] * 1e-3),
         "steps": tr["total_steps"], "mean_T": tr["total_steps"] / E, "max_T": int(tr["lengths"].max()),
         "truncated": tr["truncated"],
+        "layout": {"graph": "l2" if tr["mode"] == amc.MODE_WAVE_L2 else "lds",
+                   "b": "global" if tr["b_global"] else "lds", "dist_bits": 16 if tr["dist16"] else 32,
+                   "waves": tr["waves"]},
         "row_wise_R": R, "row_wise_E_T": row["E_T"],
         "b_hat_vs_row_b": {"max_abs": float(diff.max()), "l1": float(diff.sum()),
                            "b_row_max": float(row["b"].max())},

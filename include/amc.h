@@ -332,8 +332,18 @@ AMC_API int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model, c
  * estimates b_v(s) for s the law of x0, survival_t = #{T_e > t} / sum T the
  * weights w_t of the survival-weighted decomposition, reward_f / sum T the
  * node-reward AFC b . f, and switches / sum T the switching-rate reward.
- * Runs in the LDS sweep mode only (AMC_E_UNSUPPORTED beyond it). */
+ * Layouts: AMC_MODE_WAVE stages each step's realized graph in LDS;
+ * AMC_MODE_WAVE_L2 keeps it in a per-workgroup global scratch (L2-resident)
+ * with K(X_t;H) in LDS and B in LDS or in that scratch, for lane-per-vertex
+ * mappings (group 1 / 2 / 3); AMC_MODE_AUTO takes the layout that fits the
+ * most wavefronts per workgroup, weighted by their measured relative rates.
+ * Every layout produces identical results.  flags: AMC_WANT_PATHS;
+ * AMC_DIST16 / AMC_DIST32 fix the distance width; AMC_TRAJ_B_LDS /
+ * AMC_TRAJ_B_GLOBAL fix B's place in the L2 layout.  A graph that fits no
+ * layout returns AMC_E_UNSUPPORTED. */
 #define AMC_WANT_PATHS (1u << 0)
+#define AMC_TRAJ_B_LDS (1u << 1)
+#define AMC_TRAJ_B_GLOBAL (1u << 2)
 typedef struct amc_traj_query {
     uint64_t seed;
     int32_t episodes;           /* >= 1                                       */
@@ -343,8 +353,9 @@ typedef struct amc_traj_query {
     double tie_tau;             /* < 0 selects 1e-9                           */
     int32_t max_steps;          /* >= 1: cap on pre-absorption states          */
     const double *f;            /* node reward (n, >= 0) or NULL               */
-    uint32_t flags;             /* AMC_WANT_PATHS                              */
-    int32_t group, waves;       /* LDS-mode vertex mapping / wavefronts, 0 = engine */
+    uint32_t flags;             /* AMC_WANT_PATHS, AMC_DIST16 / 32, AMC_TRAJ_B_* */
+    int32_t group, waves;       /* vertex mapping / wavefronts, 0 = engine    */
+    int32_t mode;               /* AMC_MODE_AUTO, AMC_MODE_WAVE or AMC_MODE_WAVE_L2 */
 } amc_traj_query;
 
 typedef struct amc_traj_result {
@@ -359,6 +370,8 @@ typedef struct amc_traj_result {
     uint64_t sources;           /* single-source passes run (throughput unit)  */
     int32_t truncated;
     double sweep_ms;            /* HIP-event time of the trajectory kernel     */
+    int32_t mode, waves;        /* layout and wavefronts per workgroup used    */
+    int32_t dist16, b_global;   /* 16-bit distances; B in the global scratch  */
 } amc_traj_result;
 AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_traj_query *q,
                              amc_traj_result *out);

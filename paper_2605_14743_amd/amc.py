@@ -32,7 +32,7 @@ EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_s
            "amc_request_destroy", "amc_request_times", "amc_server_info", "amc_batch_create", "amc_batch_run", "amc_batch_info",
            "amc_batch_destroy", "amc_tune", "amc_trajectories", "amc_robust", "amc_bootstrap", "amc_chain",
            "amc_stability", "amc_sweep_static", "amc_strerror", "amc_version"]
-WANT_PATHS = 1
+WANT_PATHS, TRAJ_B_LDS, TRAJ_B_GLOBAL = 1, 2, 4
 
 _P = C.POINTER
 
@@ -62,14 +62,15 @@ class Query(C.Structure):
 class TrajQuery(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("episodes", C.c_int32), ("x0", _P(C.c_int32)), ("alpha", C.c_double),
                 ("k_min", C.c_uint32), ("tie_tau", C.c_double), ("max_steps", C.c_int32), ("f", _P(C.c_double)),
-                ("flags", C.c_uint32), ("group", C.c_int32), ("waves", C.c_int32)]
+                ("flags", C.c_uint32), ("group", C.c_int32), ("waves", C.c_int32), ("mode", C.c_int32)]
 
 
 class TrajResult(C.Structure):
     _fields_ = [("lengths", _P(C.c_int32)), ("paths", _P(C.c_int32)), ("visits", _P(C.c_uint64)),
                 ("b_hat", _P(C.c_double)), ("survival", _P(C.c_double)), ("reward_f", C.c_double),
                 ("switches", C.c_uint64), ("total_steps", C.c_uint64), ("sources", C.c_uint64),
-                ("truncated", C.c_int32), ("sweep_ms", C.c_double)]
+                ("truncated", C.c_int32), ("sweep_ms", C.c_double), ("mode", C.c_int32), ("waves", C.c_int32),
+                ("dist16", C.c_int32), ("b_global", C.c_int32)]
 
 
 class RobustQuery(C.Structure):
@@ -538,7 +539,7 @@ def footprint(graph: Graph, **query) -> int:
 
 
 def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0.15, k_min=5, tie_tau=-1.0,
-                 max_steps=1024, f=None, want_paths=False, group=0, waves=0) -> dict:
+                 max_steps=1024, f=None, want_paths=False, group=0, waves=0, mode=0, flags=0) -> dict:
     """amc_trajectories: episodes of the network process (Section 4.3) and the
     length-biased estimators (b_hat, survival weights, node-reward total)."""
     m, keep_m = make_model(**model)
@@ -552,8 +553,8 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
     if f is not None:
         fa = np.ascontiguousarray(f, dtype=np.float64)
         q.f = _ptr(fa, C.c_double)
-    q.flags = WANT_PATHS if want_paths else 0
-    q.group, q.waves = int(group), int(waves)
+    q.flags = (WANT_PATHS if want_paths else 0) | int(flags)
+    q.group, q.waves, q.mode = int(group), int(waves), int(mode)
     arr = {"lengths": np.zeros(E, np.int32), "visits": np.zeros(n, np.uint64), "b_hat": np.zeros(n),
            "survival": np.zeros(max(int(max_steps), 1))}
     if want_paths:
@@ -566,7 +567,7 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
     out = dict(arr)
     for key in ("reward_f", "sweep_ms"):
         out[key] = float(getattr(res, key))
-    for key in ("switches", "total_steps", "sources", "truncated"):
+    for key in ("switches", "total_steps", "sources", "truncated", "mode", "waves", "dist16", "b_global"):
         out[key] = int(getattr(res, key))
     del keep_m, fa
     return out

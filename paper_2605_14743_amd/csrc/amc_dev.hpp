@@ -124,6 +124,8 @@ struct TrajArgs {
     unsigned long long *ctr;    // switches, total steps, truncated, sources run
     unsigned int *work;
     int *err;
+    uint32_t *bscratch;         // L2 layout: per-workgroup scratch (realized graph), else nullptr
+    uint64_t bscratch_words;    // 32-bit words per workgroup
 };
 
 // One sweep launch serves one or several queries: the launch's work items are

@@ -62,7 +62,12 @@ hipError_t launch_anchored(const LaunchCtl &LC, bool weighted, uint32_t adj_byte
 
 // Trajectory simulator (LDS mode only).
 hipError_t set_traj_attrs(int max_lds);
-hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int group, uint32_t adj_bytes, int blocks,
+// L2 placements of the trajectory kernel (realized graph in a per-workgroup
+// global scratch): LDS bytes before the wavefront regions, i.e. B(H) f64[n]
+// unless b_global, and the component list u16[n].  place: 0 = LDS layout,
+// 1 = L2 with B in LDS, 2 = L2 with B in the scratch.
+uint32_t traj_l2_lds_base(int n, bool b_global);
+hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int place, int group, uint32_t adj_bytes, int blocks,
                        int waves, uint32_t lds, hipStream_t st);
 hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,
                           const unsigned long long *visits, const unsigned long long *ctr, uint32_t *hist,

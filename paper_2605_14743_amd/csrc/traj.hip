@@ -10,7 +10,10 @@
 // also yields the component K(X_t;H)), and when |K| >= k_min every wavefront
 // takes further sources of K; the band maximiser of B over K is X_{t+1}.
 // Visits, lengths, node rewards and switches feed the length-biased
-// estimators of the uniform-step equivalence.
+// estimators of the uniform-step equivalence.  Placement PL: 0 stages the
+// realized graph in LDS; 1 and 2 keep it in a per-workgroup global scratch
+// (L2-resident, as in the sweep's L2 mode), which leaves room for more
+// wavefronts, with B(H) in LDS (1) or in that scratch as well (2).
 #include <type_traits>
 
 #include "amc_dev.hpp"
@@ -20,9 +23,16 @@
 
 namespace amc {
 
-template <bool WEIGHTED, int G, typename ADJ, bool D16>
+// LDS bytes before the wavefront regions in the L2 placements: B (unless it
+// is global) and the component list u16[n]
+__host__ __device__ inline uint32_t traj_l2_base(int n, bool b_global) {
+    return ((b_global ? 0u : l2_lds_b_bytes(n)) + 2u * (uint32_t)n + 15u) & ~15u;
+}
+
+template <bool WEIGHTED, int G, typename ADJ, bool D16, int PL>
 __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     using DT = typename std::conditional<D16, uint16_t, uint32_t>::type;
+    constexpr bool GL = PL != 0, BG = PL == 2;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t scan_tmp[kMaxWaves];
     __shared__ uint32_t wctr[kMaxWaves];
@@ -33,13 +43,29 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     const SweepParams &P = *T.desc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6, nt = blockDim.x;
     const int n = P.n;
-    const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
-    ADJ *rp = (ADJ *)(smem + L.rp);
-    ADJ *adj = (ADJ *)(smem + L.adj);
-    double *B = (double *)(smem + L.B);
-    const BAcc BA{B, nullptr, false};
-    uint16_t *list = (uint16_t *)(smem + L.comp);        // K(X_t;H), in wavefront 0's visit order
-    unsigned char *wbase = smem + L.waves;
+    ADJ *rp, *adj;
+    double *B;
+    uint16_t *list;                                      // K(X_t;H), in wavefront 0's visit order
+    unsigned char *wbase;
+    if constexpr (GL) {
+        const L2Layout L = l2_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+        unsigned char *gs = (unsigned char *)(T.bscratch + (size_t)blockIdx.x * T.bscratch_words);
+        rp = to_global((ADJ *)(gs + L.rp));
+        adj = to_global((ADJ *)(gs + L.adj));
+        B = BG ? to_global((double *)(gs + L.B)) : (double *)smem;
+        list = (uint16_t *)(smem + (BG ? 0u : l2_lds_b_bytes(n)));
+        wbase = smem + traj_l2_base(n, BG);
+    } else {
+        const WaveLayout L = wave_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+        rp = (ADJ *)(smem + L.rp);
+        adj = (ADJ *)(smem + L.adj);
+        B = (double *)(smem + L.B);
+        list = (uint16_t *)(smem + L.comp);
+        wbase = smem + L.waves;
+    }
+    // with B in global memory the wavefronts add with device atomics (at L2)
+    // and the maximiser reads past the vector L1
+    const BAcc BA{BG ? nullptr : B, BG ? B : nullptr, BG};
     unsigned char *wmine = wbase + wave * P.wave_bytes;
     const uint32_t sig_off = wave_sig_offset(n, D16);
     DT *dist = (DT *)wmine;
@@ -69,12 +95,15 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
             int nx = -1;
             if ((uint64_t)c.x >= P.t_alpha) {                // no stop: a fresh network state
                 stage_realization(P, (uint32_t)e, rp, adj, P.shift, (uint16_t *)wbase, scan_tmp, stream);
-                for (int v = tid; v < n; v += nt) B[v] = 0.0;
+                for (int v = tid; v < n; v += nt) {
+                    if constexpr (BG) st_global(&B[v], 0.0);
+                    else B[v] = 0.0;
+                }
                 __syncthreads();
                 if (wave == 0) {
                     int cs = 0, sz = 0;
-                    run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[0], x, -1, cs,
-                                                        sz, ovf);
+                    run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[0], x, -1, cs,
+                                                         sz, ovf);
                     for (int k = lane; k < sz; k += 64) list[k] = ord[k] & kVertexMask;
                     if (lane == 0) size_sh = sz;
                 }
@@ -83,13 +112,13 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                 if ((uint32_t)sz >= P.k_min) {
                     for (int k = 1 + wave; k < sz; k += nwaves) {
                         int cs = 0, zz = 0;
-                        run_source<WEIGHTED, G, ADJ, false, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[wave],
-                                                            (int)list[k], -1, cs, zz, ovf);
+                        run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[wave],
+                                                             (int)list[k], -1, cs, zz, ovf);
                     }
                     __syncthreads();
                     // tie-broken maximiser of B over K(X_t;H) (eq. local-center)
                     double mx = 0.0;
-                    for (int k = tid; k < sz; k += nt) mx = fmax(mx, B[list[k]]);
+                    for (int k = tid; k < sz; k += nt) mx = fmax(mx, ld_coh<BG>(&B[list[k]]));
                     mx = wave_max_f64(mx);
                     if (lane == 0) red_f[wave] = mx;
                     __syncthreads();
@@ -99,7 +128,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                     int best = 0x7FFFFFFF;
                     for (int k = tid; k < sz; k += nt) {
                         const int v = list[k];
-                        if (mx - B[v] <= band && v < best) best = v;
+                        if (mx - ld_coh<BG>(&B[v]) <= band && v < best) best = v;
                     }
                     best = wave_min_i32(best);
                     if (lane == 0) red_i[wave] = best;
@@ -166,29 +195,48 @@ __global__ void k_traj_estimates(int n, int max_steps, const unsigned long long 
 }
 
 // ---------------------------------------------------------------------------
-template <bool W, int G, typename ADJ, bool D16>
+uint32_t traj_l2_lds_base(int n, bool b_global) { return traj_l2_base(n, b_global); }
+
+template <bool W, int G, typename ADJ, bool D16, int PL>
 static hipError_t launch_tt(const TrajArgs &T, int blocks, int waves, uint32_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((traj_kernel<W, G, ADJ, D16>), dim3(blocks), dim3(64 * waves), lds, st, T);
+    hipLaunchKernelGGL((traj_kernel<W, G, ADJ, D16, PL>), dim3(blocks), dim3(64 * waves), lds, st, T);
     return hipGetLastError();
 }
 
-template <bool W, typename ADJ, bool D16>
-static hipError_t launch_tg(const TrajArgs &T, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
+template <bool W, typename ADJ, bool D16, int PL>
+static hipError_t launch_l2(const TrajArgs &T, int group, int blocks, int waves, uint32_t lds, hipStream_t st) {
     switch (group) {
-        case 1: return launch_tt<W, 1, ADJ, D16>(T, blocks, waves, lds, st);
-        case 2: return launch_tt<W, 2, ADJ, D16>(T, blocks, waves, lds, st);
-        case 3: return launch_tt<W, 3, ADJ, D16>(T, blocks, waves, lds, st);
-        case 4: return launch_tt<W, 4, ADJ, D16>(T, blocks, waves, lds, st);
-        case 16: return launch_tt<W, 16, ADJ, D16>(T, blocks, waves, lds, st);
-        default: return launch_tt<W, 8, ADJ, D16>(T, blocks, waves, lds, st);
+        case 1: return launch_tt<W, 1, ADJ, D16, PL>(T, blocks, waves, lds, st);
+        case 2: return launch_tt<W, 2, ADJ, D16, PL>(T, blocks, waves, lds, st);
+        case 3: return launch_tt<W, 3, ADJ, D16, PL>(T, blocks, waves, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// the L2 placements exist for the lane-per-vertex mappings (1, 2, 3)
+template <bool W, typename ADJ, bool D16>
+static hipError_t launch_tg(const TrajArgs &T, int place, int group, int blocks, int waves, uint32_t lds,
+                            hipStream_t st) {
+    if (place == 1) return launch_l2<W, ADJ, D16, 1>(T, group, blocks, waves, lds, st);
+    if (place == 2) return launch_l2<W, ADJ, D16, 2>(T, group, blocks, waves, lds, st);
+    switch (group) {
+        case 1: return launch_tt<W, 1, ADJ, D16, 0>(T, blocks, waves, lds, st);
+        case 2: return launch_tt<W, 2, ADJ, D16, 0>(T, blocks, waves, lds, st);
+        case 3: return launch_tt<W, 3, ADJ, D16, 0>(T, blocks, waves, lds, st);
+        case 4: return launch_tt<W, 4, ADJ, D16, 0>(T, blocks, waves, lds, st);
+        case 16: return launch_tt<W, 16, ADJ, D16, 0>(T, blocks, waves, lds, st);
+        default: return launch_tt<W, 8, ADJ, D16, 0>(T, blocks, waves, lds, st);
     }
 }
 
 template <bool W, typename ADJ, bool D16>
 static hipError_t attrs_t(int max_lds) {
-    const void *ks[] = {(const void *)traj_kernel<W, 1, ADJ, D16>, (const void *)traj_kernel<W, 2, ADJ, D16>,
-                        (const void *)traj_kernel<W, 3, ADJ, D16>, (const void *)traj_kernel<W, 4, ADJ, D16>,
-                        (const void *)traj_kernel<W, 8, ADJ, D16>, (const void *)traj_kernel<W, 16, ADJ, D16>};
+    const void *ks[] = {(const void *)traj_kernel<W, 1, ADJ, D16, 0>, (const void *)traj_kernel<W, 2, ADJ, D16, 0>,
+                        (const void *)traj_kernel<W, 3, ADJ, D16, 0>, (const void *)traj_kernel<W, 4, ADJ, D16, 0>,
+                        (const void *)traj_kernel<W, 8, ADJ, D16, 0>, (const void *)traj_kernel<W, 16, ADJ, D16, 0>,
+                        (const void *)traj_kernel<W, 1, ADJ, D16, 1>, (const void *)traj_kernel<W, 2, ADJ, D16, 1>,
+                        (const void *)traj_kernel<W, 3, ADJ, D16, 1>, (const void *)traj_kernel<W, 1, ADJ, D16, 2>,
+                        (const void *)traj_kernel<W, 2, ADJ, D16, 2>, (const void *)traj_kernel<W, 3, ADJ, D16, 2>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
@@ -212,19 +260,19 @@ hipError_t set_traj_attrs(int max_lds) {
 }
 
 template <bool D16>
-static hipError_t launch_td(const TrajArgs &T, bool weighted, int group, uint32_t adj_bytes, int blocks, int waves,
-                            uint32_t lds, hipStream_t st) {
+static hipError_t launch_td(const TrajArgs &T, bool weighted, int place, int group, uint32_t adj_bytes, int blocks,
+                            int waves, uint32_t lds, hipStream_t st) {
     if (adj_bytes == 2)
-        return weighted ? launch_tg<true, uint16_t, D16>(T, group, blocks, waves, lds, st)
-                        : launch_tg<false, uint16_t, D16>(T, group, blocks, waves, lds, st);
-    return weighted ? launch_tg<true, uint32_t, D16>(T, group, blocks, waves, lds, st)
-                    : launch_tg<false, uint32_t, D16>(T, group, blocks, waves, lds, st);
+        return weighted ? launch_tg<true, uint16_t, D16>(T, place, group, blocks, waves, lds, st)
+                        : launch_tg<false, uint16_t, D16>(T, place, group, blocks, waves, lds, st);
+    return weighted ? launch_tg<true, uint32_t, D16>(T, place, group, blocks, waves, lds, st)
+                    : launch_tg<false, uint32_t, D16>(T, place, group, blocks, waves, lds, st);
 }
 
-hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int group, uint32_t adj_bytes, int blocks,
-                       int waves, uint32_t lds, hipStream_t st) {
-    return dist16 ? launch_td<true>(T, weighted, group, adj_bytes, blocks, waves, lds, st)
-                  : launch_td<false>(T, weighted, group, adj_bytes, blocks, waves, lds, st);
+hipError_t launch_traj(const TrajArgs &T, bool weighted, bool dist16, int place, int group, uint32_t adj_bytes,
+                       int blocks, int waves, uint32_t lds, hipStream_t st) {
+    return dist16 ? launch_td<true>(T, weighted, place, group, adj_bytes, blocks, waves, lds, st)
+                  : launch_td<false>(T, weighted, place, group, adj_bytes, blocks, waves, lds, st);
 }
 
 hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *lengths,

@@ -1,6 +1,7 @@
 // traj_host.cpp -- host side of the trajectory simulator (Section 4.3): argument
-// checks, the LDS-mode plan, device buffers, one persistent launch and the
-// length-biased estimators.
+// checks, the layout plan (realized graph in LDS or in a per-workgroup L2
+// scratch), device buffers, one persistent launch and the length-biased
+// estimators.
 //
 // Paper: Bao, Kontou, Vogiatzis, "Betweenness-Central Nodes Under
 // Uncertainty: An Absorbing Markov Chain Approach".
@@ -34,8 +35,14 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     if (!ctx || !g || g->ctx != ctx || !model || !tq || !out || !out->lengths || !out->visits)
         return AMC_E_INVALID_ARG;
     const int n = g->n;
-    if (tq->episodes < 1 || !tq->x0 || tq->max_steps < 1 || (tq->flags & ~AMC_WANT_PATHS)) return AMC_E_INVALID_ARG;
-    if ((tq->flags & AMC_WANT_PATHS) && !out->paths) return AMC_E_INVALID_ARG;
+    const uint32_t known = AMC_WANT_PATHS | AMC_DIST16 | AMC_DIST32 | AMC_TRAJ_B_LDS | AMC_TRAJ_B_GLOBAL;
+    if (tq->episodes < 1 || !tq->x0 || tq->max_steps < 1 || (tq->flags & ~known)) return AMC_E_INVALID_ARG;
+    if ((tq->flags & AMC_DIST16) && (tq->flags & AMC_DIST32)) return AMC_E_INVALID_ARG;
+    if ((tq->flags & AMC_TRAJ_B_LDS) && (tq->flags & AMC_TRAJ_B_GLOBAL)) return AMC_E_INVALID_ARG;
+    if (tq->mode != AMC_MODE_AUTO && tq->mode != AMC_MODE_WAVE && tq->mode != AMC_MODE_WAVE_L2)
+        return AMC_E_INVALID_ARG;
+    const bool b_forced = (tq->flags & (AMC_TRAJ_B_LDS | AMC_TRAJ_B_GLOBAL)) != 0;
+    if (b_forced && tq->mode == AMC_MODE_WAVE) return AMC_E_INVALID_ARG;
     for (int e = 0; e < tq->episodes; ++e)
         if (tq->x0[e] < 0 || tq->x0[e] >= n) return AMC_E_INVALID_ARG;
     if (tq->f)
@@ -51,16 +58,89 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     q.tie_tau = tq->tie_tau;
     q.floor_eta = -1.0;
     q.r_lower = 0.05;
-    q.flags = AMC_SKIP_TAIL;
+    q.flags = AMC_SKIP_TAIL | (tq->flags & (AMC_DIST16 | AMC_DIST32));
     q.mode = AMC_MODE_WAVE;
     q.group = tq->group;
-    q.waves = tq->waves;
+    q.waves = tq->mode == AMC_MODE_WAVE_L2 || b_forced ? 0 : tq->waves;
 
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return AMC_E_HIP;
     hipStream_t st = ctx->stream;
     QueryRun R;
-    RCHK(qr_init(R, ctx, g, model, &q));
+    // the sweep planner's LDS mode gives the graph encoding (adjacency entry,
+    // vertex mapping) and the LDS layout; a graph beyond it takes the
+    // encoding of the L2 mode
+    bool lds_ok = true;
+    int rc = qr_init(R, ctx, g, model, &q);
+    if (rc == AMC_E_UNSUPPORTED && tq->mode != AMC_MODE_WAVE) {
+        q.mode = AMC_MODE_WAVE_L2;
+        q.waves = 0;
+        rc = qr_init(R, ctx, g, model, &q);
+        lds_ok = false;
+    }
+    if (rc != AMC_OK) return rc;
+    int place = 0;
+    {
+        // L2 placements: the realized graph in the workgroup's global
+        // scratch, K(X_t;H) and (place 1) B(H) in LDS; the wavefront regions
+        // stage the edge weights (2 m bytes).  Lane-per-vertex mappings only.
+        // Rate of a wavefront relative to one of the LDS layout with 32-bit
+        // distances (measured on MI355X, ws1000, 5000 episodes): 0.98 with B
+        // in LDS, 0.86 with B in the scratch (the maximiser reads it past the
+        // vector L1 every step), 0.77 for 16-bit distances.
+        Plan &pl = R.pl;
+        const bool lane_map = pl.group == 1 || pl.group == 2 || pl.group == 3;
+        const int max_w = pl.group == 3 ? 8 : kMaxWaves;
+        const bool d16_ok = (uint64_t)n * model_wmax(g, &R.md) < 0xFFFFull && !(tq->flags & AMC_DIST32);
+        int l2_w = 0, l2_place = 0;
+        bool l2_d16 = false;
+        uint32_t l2_lds = 0, l2_wb = 0;
+        double e_l2 = 0.0;
+        if (tq->mode != AMC_MODE_WAVE && lane_map && tq->waves <= max_w) {
+            for (int bg = 0; bg < 2; ++bg) {
+                if ((bg && (tq->flags & AMC_TRAJ_B_LDS)) || (!bg && (tq->flags & AMC_TRAJ_B_GLOBAL))) continue;
+                for (int d = 0; d < 2; ++d) {
+                    if ((d && !d16_ok) || (!d && (tq->flags & AMC_DIST16))) continue;
+                    uint32_t wb = 0;
+                    (void)lds_bytes_wave_l2(n, 1, d != 0, true, false, &wb);   // one wavefront's region
+                    const uint32_t base = traj_l2_lds_base(n, bg != 0);
+                    int fw = 0;
+                    for (int w = 2; w <= (tq->waves > 0 ? tq->waves : max_w); ++w) {
+                        if (base + wb * (uint32_t)w > (uint32_t)ctx->max_lds) break;
+                        if ((uint64_t)wb * (uint64_t)w < 2ull * (uint64_t)g->m) continue;
+                        fw = w;
+                    }
+                    if (tq->waves > 0 && fw != tq->waves) fw = 0;
+                    const double e = fw * (bg ? 0.86 : 0.98) * (d ? 0.77 : 1.0);
+                    if (fw >= 2 && e > e_l2) {
+                        e_l2 = e;
+                        l2_w = fw;
+                        l2_place = bg ? 2 : 1;
+                        l2_d16 = d != 0;
+                        l2_lds = base + wb * (uint32_t)fw;
+                        l2_wb = wb;
+                    }
+                }
+            }
+        }
+        const double e_lds = lds_ok ? pl.waves * (pl.dist16 ? 0.77 : 1.0) : 0.0;
+        const bool use_l2 = l2_w > 0 && (tq->mode == AMC_MODE_WAVE_L2 || b_forced || e_l2 > e_lds);
+        if (!use_l2 && (!lds_ok || tq->mode == AMC_MODE_WAVE_L2 || b_forced)) return AMC_E_UNSUPPORTED;
+        if (use_l2) {
+            place = l2_place;
+            pl.mode = AMC_MODE_WAVE_L2;
+            pl.waves = l2_w;
+            pl.threads = 64 * l2_w;
+            pl.dist16 = l2_d16;
+            pl.lds = l2_lds;
+            pl.wave_bytes = l2_wb;
+            pl.b_global = place == 2;
+            pl.sig_global = false;
+            pl.scratch_words = (uint32_t)l2_scratch_words(n, pl.adj_cap, pl.adj_bytes, 0);
+        } else {
+            pl.mode = AMC_MODE_WAVE;
+        }
+    }
     struct Guard {
         QueryRun &r;
         hipStream_t s;
@@ -110,6 +190,11 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     const Plan &pl = R.pl;
     const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl.lds, 1u));
     const int blocks = (int)std::min<uint64_t>((uint64_t)E, (uint64_t)ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
+    if (place) {
+        T.bscratch_words = pl.scratch_words;
+        RCHK(A.alloc(4 * (size_t)pl.scratch_words * (size_t)blocks, &p));
+        T.bscratch = (uint32_t *)p;
+    }
     hipEvent_t ev[2];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {
@@ -120,7 +205,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
         }
     } evg{ev};
     HIPCHK(hipEventRecord(ev[0], st));
-    HIPCHK(launch_traj(T, pl.weighted, pl.dist16, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st));
+    HIPCHK(launch_traj(T, pl.weighted, pl.dist16, place, pl.group, pl.adj_bytes, blocks, pl.waves, pl.lds, st));
     HIPCHK(hipEventRecord(ev[1], st));
     HIPCHK(traj_estimates(n, E, S, T.lengths, T.visits, T.ctr, hist, b_hat, surv, st));
 
@@ -144,5 +229,9 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     out->truncated = (int32_t)hc[2];
     out->sources = hc[3];
     out->sweep_ms = ms;
+    out->mode = pl.mode;
+    out->waves = pl.waves;
+    out->dist16 = pl.dist16 ? 1 : 0;
+    out->b_global = place == 2 ? 1 : 0;
     return AMC_OK;
 }

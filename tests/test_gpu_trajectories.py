@@ -1,6 +1,8 @@
 """GPU parity of the trajectory simulator (Section 4.3) against the CPU oracle,
 through the C-ABI: episode paths, lengths, visits, switches, truncation and
-the survival weights bit-exact; the node-reward total within 1e-12."""
+the survival weights bit-exact; the node-reward total within 1e-12.  Every
+layout is covered: the realized graph in LDS, or in the workgroup's global
+scratch with B(H) in LDS or in that scratch, 32- and 16-bit distances."""
 import sys
 
 import numpy as np
@@ -79,28 +81,91 @@ def test_unit_weights_truncation_and_crossroads(ctx):
     check(res, ref, "crossroads")
 
 
-def test_ws1000_sampled_episodes(ctx):
+LAYOUTS = {
+    "lds": dict(mode=amc.MODE_WAVE),
+    "l2-b-lds": dict(mode=amc.MODE_WAVE_L2, flags=amc.TRAJ_B_LDS | amc.DIST32),
+    "l2-b-global": dict(mode=amc.MODE_WAVE_L2, flags=amc.TRAJ_B_GLOBAL | amc.DIST32),
+    "l2-b-global-d16": dict(mode=amc.MODE_WAVE_L2, flags=amc.TRAJ_B_GLOBAL | amc.DIST16),
+    "l2-b-lds-d16": dict(mode=amc.MODE_WAVE_L2, flags=amc.TRAJ_B_LDS | amc.DIST16),
+}
+
+
+def check_layout(res, layout):
+    spec = LAYOUTS[layout]
+    assert res["mode"] == spec["mode"], layout
+    if spec["mode"] == amc.MODE_WAVE_L2:
+        assert res["b_global"] == int("b-global" in layout), layout
+        assert res["dist16"] == int(layout.endswith("d16")), layout
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_ws1000_sampled_episodes(ctx, layout):
     wl = W.config_ws1000()
     g = wl.graph
     res, ref = both(ctx, g, wl.model(), x0=np.array([0, 17, 512, 999]), seed=wl.seed, alpha=wl.alpha,
-                    k_min=wl.k_min, max_steps=6)
-    check(res, ref, "ws1000")
+                    k_min=wl.k_min, max_steps=6, **LAYOUTS[layout])
+    check(res, ref, f"ws1000 {layout}")
+    check_layout(res, layout)
+
+
+@pytest.mark.parametrize("layout", ["l2-b-lds", "l2-b-global", "l2-b-lds-d16"])
+@pytest.mark.parametrize("group", [1, 2, 3])
+def test_er20_l2_layouts(ctx, layout, group):
+    # every wavefront count up to the 16 a workgroup holds sees a component
+    # of at most 20 sources; the fixed group covers each lane mapping
+    wl = W.config_er20()
+    g = wl.graph
+    x0 = np.arange(300) % g.n
+    f = np.linspace(0.5, 2.0, g.n)
+    res, ref = both(ctx, g, wl.model(), x0=x0, seed=13, f=f, group=group, **LAYOUTS[layout])
+    check(res, ref, f"er20 {layout} group {group}")
+    check_layout(res, layout)
+
+
+def test_graph_beyond_the_lds_layout(ctx):
+    # n = 3500, mean degree 8, weights 1..10: the LDS layout does not hold the
+    # realized graph and two wavefront regions, the L2 layout holds three
+    g = W.er_graph(3500, 8.0 / 3499, 21)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    res, ref = both(ctx, g, model, x0=np.array([0, 1750, 3499]), seed=5, alpha=0.3, max_steps=3)
+    check(res, ref, "er3500 automatic layout")
+    assert res["mode"] == amc.MODE_WAVE_L2 and res["waves"] >= 2
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    with pytest.raises(amc.AmcError) as ei:
+        amc.trajectories(ctx, G, model, x0=[0], mode=amc.MODE_WAVE)
+    assert ei.value.rc == amc.E_UNSUPPORTED
+    G.close()
 
 
 def test_trajectory_arguments(ctx):
     g = W.er_graph(12, 0.4, 1)
     G = amc.Graph(ctx, g.n, g.eu, g.ev)
     for bad in ({"x0": [0, 12]}, {"x0": [-1]}, {"x0": [1], "max_steps": 0}, {"x0": [1], "alpha": 0.0},
-                {"x0": [1], "f": -np.ones(12)}):
+                {"x0": [1], "f": -np.ones(12)}, {"x0": [1], "mode": amc.MODE_BLOCK},
+                {"x0": [1], "flags": amc.DIST16 | amc.DIST32}, {"x0": [1], "flags": amc.TRAJ_B_LDS | amc.TRAJ_B_GLOBAL},
+                {"x0": [1], "mode": amc.MODE_WAVE, "flags": amc.TRAJ_B_GLOBAL}, {"x0": [1], "flags": 1 << 20}):
         kw = dict(bad)
         x0 = kw.pop("x0")
         with pytest.raises(amc.AmcError) as ei:
             amc.trajectories(ctx, G, {"p_fail": 0.1}, x0=x0, **kw)
         assert ei.value.rc == amc.E_INVALID_ARG, bad
     G.close()
-    big = W.config_er5000().graph                       # beyond the LDS mode
-    H = amc.Graph(ctx, big.n, big.eu, big.ev)
+    # a path of 7000 vertices: two wavefront regions and the component list
+    # exceed the LDS in every layout
+    n = 7000
+    H = amc.Graph(ctx, n, np.arange(n - 1), np.arange(1, n))
     with pytest.raises(amc.AmcError) as ei:
         amc.trajectories(ctx, H, {"p_fail": 0.1, "weight": "unit"}, x0=[0])
     assert ei.value.rc == amc.E_UNSUPPORTED
     H.close()
+
+
+def test_er5000_l2_layout(ctx):
+    # the n = 5000 workload graph (unit weights) fits only the L2 layout with
+    # B in the global scratch, with two wavefronts
+    wl = W.config_er5000()
+    g = wl.graph
+    res, ref = both(ctx, g, {"p_fail": 0.1, "weight": "unit"}, x0=np.array([0, 4999]), seed=3, alpha=0.3,
+                    max_steps=2)
+    check(res, ref, "er5000")
+    assert (res["mode"], res["b_global"], res["waves"]) == (amc.MODE_WAVE_L2, 1, 2)
