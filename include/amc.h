@@ -337,6 +337,9 @@ AMC_API int amc_tune(amc_ctx *ctx, const amc_graph *g, const amc_model *model, c
  * with K(X_t;H) in LDS and B in LDS or in that scratch, for lane-per-vertex
  * mappings (group 1 / 2 / 3); AMC_MODE_AUTO takes the layout that fits the
  * most wavefronts per workgroup, weighted by their measured relative rates.
+ * In the L2 layout a step's sources after X_t are open to workgroups that
+ * have run out of episodes (they read the step's realized graph from the
+ * owner's scratch), so the last long episodes do not run alone.
  * Every layout produces identical results.  flags: AMC_WANT_PATHS;
  * AMC_DIST16 / AMC_DIST32 fix the distance width; AMC_TRAJ_B_LDS /
  * AMC_TRAJ_B_GLOBAL fix B's place in the L2 layout.  A graph that fits no
@@ -372,6 +375,8 @@ typedef struct amc_traj_result {
     double sweep_ms;            /* HIP-event time of the trajectory kernel     */
     int32_t mode, waves;        /* layout and wavefronts per workgroup used    */
     int32_t dist16, b_global;   /* 16-bit distances; B in the global scratch  */
+    uint64_t shared_sources;    /* L2 layout: sources of a step run by workgroups
+                                   that had run out of episodes               */
 } amc_traj_result;
 AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *model, const amc_traj_query *q,
                              amc_traj_result *out);

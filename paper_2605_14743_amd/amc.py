@@ -70,7 +70,7 @@ class TrajResult(C.Structure):
                 ("b_hat", _P(C.c_double)), ("survival", _P(C.c_double)), ("reward_f", C.c_double),
                 ("switches", C.c_uint64), ("total_steps", C.c_uint64), ("sources", C.c_uint64),
                 ("truncated", C.c_int32), ("sweep_ms", C.c_double), ("mode", C.c_int32), ("waves", C.c_int32),
-                ("dist16", C.c_int32), ("b_global", C.c_int32)]
+                ("dist16", C.c_int32), ("b_global", C.c_int32), ("shared_sources", C.c_uint64)]
 
 
 class RobustQuery(C.Structure):
@@ -567,7 +567,8 @@ def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0
     out = dict(arr)
     for key in ("reward_f", "sweep_ms"):
         out[key] = float(getattr(res, key))
-    for key in ("switches", "total_steps", "sources", "truncated", "mode", "waves", "dist16", "b_global"):
+    for key in ("switches", "total_steps", "sources", "truncated", "mode", "waves", "dist16", "b_global",
+                "shared_sources"):
         out[key] = int(getattr(res, key))
     del keep_m, fa
     return out

@@ -121,11 +121,19 @@ struct TrajArgs {
     int32_t *paths;             // episodes x max_steps or nullptr
     unsigned long long *visits; // n
     double *reward;             // sum of f(X_t)
-    unsigned long long *ctr;    // switches, total steps, truncated, sources run
-    unsigned int *work;
+    unsigned long long *ctr;    // switches, total steps, truncated, sources run, sources run by other workgroups
+    unsigned int *work;         // [0] next episode, [1] episodes ended
     int *err;
     uint32_t *bscratch;         // L2 layout: per-workgroup scratch (realized graph), else nullptr
     uint64_t bscratch_words;    // 32-bit words per workgroup
+    // shared steps (L2 layout): per workgroup a claim word (epoch << 32 |
+    // |K| << 16 | next source) and a completion word (sources other
+    // workgroups ran << 32 | sources done), the step's K(X_t;H) and the B(H)
+    // contributions of the sources other workgroups ran
+    unsigned long long *share;  // 2 per workgroup
+    unsigned long long *open;   // bit b: workgroup b's step has unclaimed sources ((blocks + 63) / 64 words)
+    int32_t *glist;             // n per workgroup
+    double *hb;                 // n per workgroup
 };
 
 // One sweep launch serves one or several queries: the launch's work items are

@@ -13,7 +13,15 @@
 // estimators of the uniform-step equivalence.  Placement PL: 0 stages the
 // realized graph in LDS; 1 and 2 keep it in a per-workgroup global scratch
 // (L2-resident, as in the sweep's L2 mode), which leaves room for more
-// wavefronts, with B(H) in LDS (1) or in that scratch as well (2).
+// wavefronts, with B(H) in LDS (1) or in that scratch as well (2).  In the L2
+// placements a step's sources after X_t are shared: the owner publishes the
+// step (epoch, |K|) in a claim word, its wavefronts and those of workgroups
+// that have run out of episodes claim sources from it by atomic adds (a
+// claim is the add's old value: step and source), the latter read the
+// owner's realized graph from its scratch and add their B(H) terms into a
+// per-owner global array that the owner merges before the maximiser.  The
+// owner waits only for claimed sources, so every wait ends without any
+// assumption on which workgroups are resident.
 #include <type_traits>
 
 #include "amc_dev.hpp"
@@ -22,6 +30,11 @@
 #include "wave_source.hpp"
 
 namespace amc {
+
+// Polls of the owner's wait for claimed sources (about 4 s at 2.4 GHz) after
+// which the step is abandoned with error bit 2: claimed sources always end,
+// so reaching it means the completion word was not seen.
+constexpr uint32_t kShareSpinLimit = 1u << 26;
 
 // LDS bytes before the wavefront regions in the L2 placements: B (unless it
 // is global) and the component list u16[n]
@@ -38,7 +51,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
     __shared__ uint32_t wctr[kMaxWaves];
     __shared__ double red_f[kMaxWaves];
     __shared__ int red_i[kMaxWaves];
-    __shared__ int ep_sh, size_sh, nx_sh;
+    __shared__ int ep_sh, size_sh, nx_sh, helped_sh;
 
     const SweepParams &P = *T.desc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6, nt = blockDim.x;
@@ -74,7 +87,8 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
 
     bool ovf = false;
     double rew = 0.0;
-    unsigned long long sw = 0, tot = 0, trunc = 0, units = 0;
+    unsigned long long sw = 0, tot = 0, trunc = 0, units = 0, shared = 0;
+    uint32_t epoch = 1;                                  // this workgroup's next published step
     for (;;) {
         if (tid == 0) ep_sh = (int)atomicAdd(T.work, 1u);
         __syncthreads();
@@ -99,21 +113,95 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
                     if constexpr (BG) st_global(&B[v], 0.0);
                     else B[v] = 0.0;
                 }
+                // L2 placements: the realized graph (and a global B) are
+                // complete at L2 before any wavefront reads them or adds into B
+                if constexpr (GL) __threadfence();
                 __syncthreads();
                 if (wave == 0) {
                     int cs = 0, sz = 0;
                     run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[0], x, -1, cs,
                                                          sz, ovf);
-                    for (int k = lane; k < sz; k += 64) list[k] = ord[k] & kVertexMask;
+                    for (int k = lane; k < sz; k += 64) {
+                        const uint16_t v = ord[k] & kVertexMask;
+                        list[k] = v;
+                        if constexpr (GL) T.glist[(size_t)blockIdx.x * n + k] = (int32_t)v;
+                    }
                     if (lane == 0) size_sh = sz;
                 }
+                if constexpr (GL) __threadfence();               // K(X_t;H) in memory before the step opens
                 __syncthreads();
                 const int sz = size_sh;
                 if ((uint32_t)sz >= P.k_min) {
-                    for (int k = 1 + wave; k < sz; k += nwaves) {
-                        int cs = 0, zz = 0;
-                        run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord, &wctr[wave],
-                                                             (int)list[k], -1, cs, zz, ovf);
+                    if constexpr (GL) {
+                        unsigned long long *claim = T.share + 2 * blockIdx.x, *done = claim + 1;
+                        unsigned long long *open_w = T.open + (blockIdx.x >> 6);
+                        const unsigned long long open_bit = 1ull << (blockIdx.x & 63u);
+                        if (tid == 0) {
+                            __hip_atomic_store(done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __threadfence();                 // graph, K and cleared sums before the claims open
+                            __hip_atomic_store(claim,
+                                               ((unsigned long long)epoch << 32) |
+                                                   ((unsigned long long)sz << 16) | 1ull,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (sz > 1) atomicOr(open_w, open_bit);   // a hint for the helpers
+                        }
+                        __syncthreads();
+                        // the next claim is issued before a source runs, so its
+                        // latency hides behind the source's first loads
+                        auto claim_k = [&]() -> unsigned int {
+                            unsigned int v = 0;
+                            if (lane == 0) v = (unsigned int)(atomicAdd(claim, 1ull) & 0xFFFFull);
+                            return v;
+                        };
+                        unsigned int k = __builtin_amdgcn_readfirstlane(claim_k());
+                        while (k < (unsigned int)sz) {
+                            const unsigned int kn = claim_k();
+                            int cs = 0, zz = 0;
+                            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord,
+                                                                 &wctr[wave], (int)list[k], -1, cs, zz, ovf);
+                            if (lane == 0) atomicAdd(done, 1ull);
+                            k = __builtin_amdgcn_readfirstlane(kn);
+                        }
+                        // every source is claimed: withdraw the hint (complete
+                        // with the fence, before the next step sets it again)
+                        if (lane == 0 && k == (unsigned int)sz) atomicAnd(open_w, ~open_bit);
+                        __threadfence();                     // this workgroup's global B atomics are complete
+                        __syncthreads();
+                        if (tid == 0) {                      // sources other workgroups claimed
+                            unsigned long long d;
+                            uint32_t spins = 0;
+                            while (((d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                                    0xFFFFFFFFull) < (unsigned long long)(sz - 1)) {
+                                if (++spins == kShareSpinLimit) {
+                                    atomicOr(T.err, 2);
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(2);
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            helped_sh = (int)(d >> 32);
+                            shared += d >> 32;
+                        }
+                        __syncthreads();
+                        if (helped_sh > 0) {
+                            double *hb = T.hb + (size_t)blockIdx.x * n;
+                            for (int v = tid; v < n; v += nt) {
+                                const double h = ld_coh<true>(&hb[v]);
+                                if (h != 0.0) {
+                                    if constexpr (BG) st_global(&B[v], ld_coh<true>(&B[v]) + h);
+                                    else B[v] += h;
+                                    st_global(&hb[v], 0.0);
+                                }
+                            }
+                            __threadfence();
+                        }
+                        ++epoch;
+                    } else {
+                        for (int k = 1 + wave; k < sz; k += nwaves) {
+                            int cs = 0, zz = 0;
+                            run_source<WEIGHTED, G, ADJ, GL, DT>(P, rp, adj, P.shift, BA, dist, sig, ord,
+                                                                 &wctr[wave], (int)list[k], -1, cs, zz, ovf);
+                        }
                     }
                     __syncthreads();
                     // tie-broken maximiser of B over K(X_t;H) (eq. local-center)
@@ -159,7 +247,87 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
         }
         if (T.paths)
             for (int k = t + tid; k < T.max_steps; k += nt) T.paths[(size_t)e * T.max_steps + k] = -1;
+        if (tid == 0) atomicAdd(&T.work[1], 1u);
         __syncthreads();
+    }
+    if constexpr (GL) {
+        // out of episodes: every wavefront runs sources of other workgroups'
+        // open steps until all episodes have ended
+        const int nb = (int)gridDim.x;
+        const L2Layout L = l2_layout(n, P.adj_cap, (uint32_t)sizeof(ADJ));
+        const int nwords = (nb + 63) >> 6;
+        int start = (int)((blockIdx.x * 7u + (uint32_t)wave * 131u) % (uint32_t)nb);
+        int idle = 0;
+        int last_b = -1;
+        unsigned int last_ep = 0;
+        for (;;) {
+            unsigned int ended = 0;
+            if (lane == 0) ended = __hip_atomic_load(&T.work[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__builtin_amdgcn_readfirstlane(ended) >= (unsigned int)T.episodes) break;
+            // an owner with unclaimed sources, from the hint words: the first
+            // set bit at or after `start`, else the first set bit
+            int found = -1;
+            for (int j = 0; j < nwords && found < 0; j += 64) {
+                unsigned long long w = 0;
+                if (j + lane < nwords)
+                    w = __hip_atomic_load(T.open + j + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int base = (j + lane) << 6;
+                int after = 0x7FFFFFFF, first = 0x7FFFFFFF;
+                if (w) {
+                    first = base + (int)__builtin_ctzll(w);
+                    const int sh = start - base;
+                    const unsigned long long hi = sh <= 0 ? w : (sh >= 64 ? 0ull : (w >> sh) << sh);
+                    if (hi) after = base + (int)__builtin_ctzll(hi);
+                }
+                after = wave_min_i32(after);
+                first = wave_min_i32(first);
+                if (after != 0x7FFFFFFF) found = after;
+                else if (first != 0x7FFFFFFF) found = first;
+            }
+            if (found < 0 || found >= nb) {
+                if (idle < 8) ++idle;
+                for (int z = 0; z < idle; ++z) __builtin_amdgcn_s_sleep(16);   // back off while nothing is open
+                continue;
+            }
+            idle = 0;
+            unsigned long long *claim = T.share + 2 * found;
+            unsigned int got = 0, kk = 0, ep_w = 0;
+            if (lane == 0) {
+                // a plain add after a check: the old value names the step and
+                // the source this wavefront now owns (a later step of the same
+                // owner is as good); an add that lands past |K| is lost, at
+                // most one per wavefront and step, so `next` stays below 2^16
+                const unsigned long long w = __hip_atomic_load(claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((w & 0xFFFFull) < ((w >> 16) & 0xFFFFull)) {
+                    const unsigned long long old = atomicAdd(claim, 1ull);
+                    if ((old & 0xFFFFull) < ((old >> 16) & 0xFFFFull)) {
+                        got = 1;
+                        kk = (unsigned int)(old & 0xFFFFull);
+                        ep_w = (unsigned int)(old >> 32);
+                    }
+                }
+            }
+            const bool ok = __builtin_amdgcn_readfirstlane(got) != 0;
+            start = ok ? found : (found + 1) % nb;           // an exhausted step: look past it
+            if (!ok) continue;
+            const int k = (int)__builtin_amdgcn_readfirstlane(kk);
+            const unsigned int ep = __builtin_amdgcn_readfirstlane(ep_w);
+            if (found != last_b || ep != last_ep) {          // first source of this step: see its graph and K
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                last_b = found;
+                last_ep = ep;
+            }
+            const int s = (int)ld_coh<true>(&T.glist[(size_t)found * n + k]);
+            unsigned char *gs = (unsigned char *)(T.bscratch + (size_t)found * T.bscratch_words);
+            const ADJ *orp = to_global((ADJ *)(gs + L.rp));
+            const ADJ *oadj = to_global((ADJ *)(gs + L.adj));
+            const BAcc HB{nullptr, T.hb + (size_t)found * n, true};
+            int cs = 0, zz = 0;
+            run_source<WEIGHTED, G, ADJ, GL, DT>(P, orp, oadj, P.shift, HB, dist, sig, ord, &wctr[wave], s, -1, cs,
+                                                 zz, ovf);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0) atomicAdd(claim + 1, (1ull << 32) | 1ull);
+        }
     }
     const bool any_ovf = __ballot(ovf) != 0ull;
     if (lane == 0 && any_ovf) atomicOr(T.err, 1);
@@ -169,6 +337,7 @@ __global__ __launch_bounds__(G == 3 ? 512 : 1024) void traj_kernel(TrajArgs T) {
         atomicAdd(&T.ctr[1], tot);
         atomicAdd(&T.ctr[2], trunc);
         atomicAdd(&T.ctr[3], units);
+        if (shared) atomicAdd(&T.ctr[4], shared);
     }
 }
 

@@ -172,7 +172,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     }
     RCHK(A.alloc(8 * (size_t)n, &p)); T.visits = (unsigned long long *)p;
     RCHK(A.alloc(8, &p)); T.reward = (double *)p;
-    RCHK(A.alloc(8 * 4, &p)); T.ctr = (unsigned long long *)p;
+    RCHK(A.alloc(8 * 5, &p)); T.ctr = (unsigned long long *)p;
     RCHK(A.alloc(16, &p)); T.work = (unsigned int *)p;
     RCHK(A.alloc(16, &p)); T.err = (int *)p;
     uint32_t *hist;
@@ -182,7 +182,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     RCHK(A.alloc(8 * (size_t)S, &p)); surv = (double *)p;
     HIPCHK(fill_u32(T.visits, 2 * (size_t)n, 0u, st));
     HIPCHK(fill_u32(T.reward, 2, 0u, st));
-    HIPCHK(fill_u32(T.ctr, 8, 0u, st));
+    HIPCHK(fill_u32(T.ctr, 10, 0u, st));
     HIPCHK(fill_u32(T.work, 4, 0u, st));
     HIPCHK(fill_u32(T.err, 4, 0u, st));
     HIPCHK(fill_u32(hist, (size_t)S + 1, 0u, st));
@@ -191,9 +191,25 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl.lds, 1u));
     const int blocks = (int)std::min<uint64_t>((uint64_t)E, (uint64_t)ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
     if (place) {
+        // the claim word's 16-bit source field holds |K| plus at most one lost
+        // add per wavefront of the launch
+        if ((uint64_t)blocks * (uint64_t)pl.waves + (uint64_t)n + kMaxWaves >= 0x10000ull) return AMC_E_UNSUPPORTED;
         T.bscratch_words = pl.scratch_words;
         RCHK(A.alloc(4 * (size_t)pl.scratch_words * (size_t)blocks, &p));
         T.bscratch = (uint32_t *)p;
+        // shared steps: claim and completion words, K and the helpers' B sums
+        RCHK(A.alloc(16 * (size_t)blocks, &p));
+        T.share = (unsigned long long *)p;
+        const size_t open_words = ((size_t)blocks + 63) / 64;
+        RCHK(A.alloc(8 * open_words, &p));
+        T.open = (unsigned long long *)p;
+        HIPCHK(fill_u32(T.open, 2 * open_words, 0u, st));
+        RCHK(A.alloc(4 * (size_t)n * blocks, &p));
+        T.glist = (int32_t *)p;
+        RCHK(A.alloc(8 * (size_t)n * blocks, &p));
+        T.hb = (double *)p;
+        HIPCHK(fill_u32(T.share, 4 * (size_t)blocks, 0u, st));
+        HIPCHK(fill_u32(T.hb, 2 * (size_t)n * blocks, 0u, st));
     }
     hipEvent_t ev[2];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -210,9 +226,9 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     HIPCHK(traj_estimates(n, E, S, T.lengths, T.visits, T.ctr, hist, b_hat, surv, st));
 
     int herr = 0;
-    unsigned long long hc[4] = {0, 0, 0, 0};
+    unsigned long long hc[5] = {0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(&herr, T.err, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hc, T.ctr, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hc, T.ctr, 8 * 5, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&out->reward_f, T.reward, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(out->lengths, T.lengths, 4 * (size_t)E, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(out->visits, T.visits, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
@@ -221,6 +237,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     if (out->survival) HIPCHK(hipMemcpyAsync(out->survival, surv, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (herr & 1) return AMC_E_SIGMA_OVERFLOW;
+    if (herr & 2) return AMC_E_HIP;   // a shared step's completion was not seen in time
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
     if (!tq->f) out->reward_f = 0.0;
@@ -228,6 +245,7 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     out->total_steps = hc[1];
     out->truncated = (int32_t)hc[2];
     out->sources = hc[3];
+    out->shared_sources = hc[4];
     out->sweep_ms = ms;
     out->mode = pl.mode;
     out->waves = pl.waves;

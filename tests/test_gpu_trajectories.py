@@ -108,6 +108,22 @@ def test_ws1000_sampled_episodes(ctx, layout):
     check_layout(res, layout)
 
 
+@pytest.mark.parametrize("layout", ["l2-b-lds", "l2-b-global"])
+def test_shared_steps_ws1000(ctx, layout):
+    # eight ws1000 episodes on eight workgroups: the workgroups whose episodes
+    # end first run sources of the steps still open, reading the owner's
+    # realized graph and adding into its B through the shared sums
+    wl = W.config_ws1000()
+    g = wl.graph
+    res, ref = both(ctx, g, wl.model(), x0=np.arange(0, 1000, 125), seed=wl.seed + 3, alpha=wl.alpha,
+                    k_min=wl.k_min, max_steps=12, **LAYOUTS[layout])
+    check(res, ref, f"ws1000 shared steps {layout}")
+    check_layout(res, layout)
+    say(f"[gpu] lengths {res['lengths'].tolist()} shared sources {res['shared_sources']} of {res['sources']}")
+    if res["lengths"].max() >= res["lengths"].min() + 2:
+        assert res["shared_sources"] > 0
+
+
 @pytest.mark.parametrize("layout", ["l2-b-lds", "l2-b-global", "l2-b-lds-d16"])
 @pytest.mark.parametrize("group", [1, 2, 3])
 def test_er20_l2_layouts(ctx, layout, group):
