@@ -387,6 +387,8 @@ def run_bench(args):
                             "batched_sweep_ms_same_R": rb["stats"]["sweep_ms"],
                             "batched_over_plain": value / pv, "target": PLAIN_TARGET,
                             "target_met": value / pv >= PLAIN_TARGET}
+    if args.traj_leg > 0:
+        out["trajectories"] = traj_leg(ctx, amc, wl, G, args.traj_leg, args.max_steps, last["E_T"])
     G.close()
     if args.er5000 and args.workload == "ws1000":
         out["er5000"] = er5000_leg(ctx, amc)
@@ -459,6 +461,25 @@ def run_batch(args):
         G.close()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def traj_leg(ctx, amc, wl, G, E, max_steps, row_E_T):
+    """Bounded trajectory leg of the bench line: E episodes of the network
+    process on the workload graph (Section 4.3), X_0 stratified over the
+    vertices, after a 256-episode warm-up."""
+    g = wl.graph
+    x0 = np.arange(E) % g.n
+    kw = dict(seed=wl.seed + 1, x0=x0, alpha=wl.alpha, k_min=wl.k_min, max_steps=max_steps)
+    amc.trajectories(ctx, G, wl.model(), **dict(kw, x0=x0[:min(E, 256)]))
+    tr = amc.trajectories(ctx, G, wl.model(), **kw)
+    ms = tr["sweep_ms"]
+    return {"episodes": E, "kernel_ms": ms, "episodes_per_s": E / (ms * 1e-3),
+            "realization_sources_per_s": tr["sources"] / (ms * 1e-3), "steps": tr["total_steps"],
+            "mean_T": tr["total_steps"] / E, "row_wise_E_T": row_E_T, "max_T": int(tr["lengths"].max()),
+            "shared_sources": tr["shared_sources"],
+            "layout": {"graph": "l2" if tr["mode"] == amc.MODE_WAVE_L2 else "lds",
+                       "b": "global" if tr["b_global"] else "lds", "dist_bits": 16 if tr["dist16"] else 32,
+                       "waves": tr["waves"]}}
 
 
 def run_traj(args):
@@ -597,9 +618,14 @@ def main():
     ap.add_argument("--clique-pool", dest="clique_pool", type=int, default=0,
                     help="with --topk: pool = the best 3-cliques by degree sum, with the fallback inside it")
     ap.add_argument("--traj", type=int, default=0, help="run the trajectory simulator with this many episodes")
-    ap.add_argument("--robust", type=int, default=0, help="also run the robust tail with this many sampled kernels")
-    ap.add_argument("--bootstrap", type=int, default=0, help="also bootstrap b with this many replicates")
-    ap.add_argument("--stability", type=int, default=0, help="also check the Top-k set at R/2 and R for this k")
+    ap.add_argument("--robust", type=int, default=-1,
+                    help="also run the robust tail with this many sampled kernels (-1: 100 on ws1000, else 0)")
+    ap.add_argument("--bootstrap", type=int, default=-1,
+                    help="also bootstrap b with this many replicates (-1: 100 on ws1000, else 0)")
+    ap.add_argument("--stability", type=int, default=-1,
+                    help="also check the Top-k set at R/2 and R for this k (-1: 10 on ws1000, else 0)")
+    ap.add_argument("--traj-leg", dest="traj_leg", type=int, default=-1,
+                    help="episodes of the trajectory leg of the bench line (-1: 5000 on ws1000, else 0)")
     ap.add_argument("--max-steps", dest="max_steps", type=int, default=512)
     ap.add_argument("--copy-mib", dest="copy_mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
@@ -612,6 +638,9 @@ def main():
     ap.add_argument("--n-hi", dest="n_hi", type=int, default=4000)
     ap.add_argument("--logR-hi", dest="logR_hi", type=int, default=14)
     args = ap.parse_args()
+    for name, dflt in (("robust", 100), ("bootstrap", 100), ("stability", 10), ("traj_leg", 5000)):
+        if getattr(args, name) < 0:
+            setattr(args, name, dflt if args.workload == "ws1000" and not args.traj else 0)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep would shard across "
               f"GPUs by realization range, with one all-reduce of the counts).", file=sys.stderr)
