@@ -60,7 +60,9 @@ extern "C" int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_mode
     q.r_lower = 0.05;
     q.flags = AMC_SKIP_TAIL | (tq->flags & (AMC_DIST16 | AMC_DIST32));
     q.mode = AMC_MODE_WAVE;
-    q.group = tq->group;
+    // the L2 layout exists for one lane per vertex (1 / 2 / 3): a request for
+    // it without a mapping takes one lane per vertex
+    q.group = tq->group == 0 && tq->mode == AMC_MODE_WAVE_L2 ? 1 : tq->group;
     q.waves = tq->mode == AMC_MODE_WAVE_L2 || b_forced ? 0 : tq->waves;
 
     std::lock_guard<std::mutex> lk(ctx->mu);

@@ -138,6 +138,16 @@ def test_er20_l2_layouts(ctx, layout, group):
     check_layout(res, layout)
 
 
+def test_l2_request_on_a_small_graph(ctx):
+    # n = 20 defaults to eight lanes per vertex; asking for the L2 layout
+    # without a mapping takes one lane per vertex
+    wl = W.config_er20()
+    g = wl.graph
+    res, ref = both(ctx, g, wl.model(), x0=np.arange(100) % g.n, seed=17, mode=amc.MODE_WAVE_L2)
+    check(res, ref, "er20 L2 default mapping")
+    assert res["mode"] == amc.MODE_WAVE_L2
+
+
 def test_graph_beyond_the_lds_layout(ctx):
     # n = 3500, mean degree 8, weights 1..10: the LDS layout does not hold the
     # realized graph and two wavefront regions, the L2 layout holds three
