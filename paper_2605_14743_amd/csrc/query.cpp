@@ -276,12 +276,12 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
 // second descriptor over the same counts and tables, each split into tiles
 // of at most n / 16 sources (their partial B rows meet in an exchange buffer
 // as in any split realization).  Items are handed out in order, so the short
-// tiles come last.
+// tiles come last.  With the rows kept for the finite-k Top-k stage, the
+// tail's tiles assemble their rows in place in the kept rows.
 int qr_split_tail(QueryRun &R, hipStream_t st) {
     const amc_query &q = R.q;
     Plan &pl = R.pl;
-    if ((q.flags & AMC_PLAIN_LAUNCH) || pl.anchored || pl.tiles_per_r != 1 || R.P.keep_rows || R.P.n_dbg)
-        return AMC_OK;
+    if ((q.flags & AMC_PLAIN_LAUNCH) || pl.anchored || pl.tiles_per_r != 1 || R.P.n_dbg) return AMC_OK;
     const uint32_t B = (uint32_t)pl.blocks, Rn = q.R;
     if (B < 2 || Rn <= B) return AMC_OK;
     // the partial last round, plus one full round when there are enough
@@ -304,10 +304,17 @@ int qr_split_tail(QueryRun &R, hipStream_t st) {
     if (P2.center_global) P2.center_global += R0;
     if (P2.next_table) P2.next_table += (size_t)R0 * n;
     if (P2.next_table_w) P2.next_table_w += (size_t)R0 * n;
-    RCHK(A.alloc(8 * (size_t)tail * n, &p)); P2.Bg = (double *)p;
-    RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.compg = (int32_t *)p;
-    RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.sizeg = (int32_t *)p;
-    RCHK(A.alloc(4 * (size_t)tail, &p)); P2.done = (unsigned int *)p;
+    if (R.P.keep_rows) {
+        P2.Bg = R.P.Bg + (size_t)R0 * n;
+        P2.compg = R.P.compg + (size_t)R0 * n;
+        P2.sizeg = R.P.sizeg + (size_t)R0 * n;
+        P2.done = R.P.done + R0;
+    } else {
+        RCHK(A.alloc(8 * (size_t)tail * n, &p)); P2.Bg = (double *)p;
+        RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.compg = (int32_t *)p;
+        RCHK(A.alloc(4 * (size_t)tail * n, &p)); P2.sizeg = (int32_t *)p;
+        RCHK(A.alloc(4 * (size_t)tail, &p)); P2.done = (unsigned int *)p;
+    }
     const SweepParams descs[2] = {R.P, P2};
     RCHK(dev_copy_in(A, descs, sizeof(descs), st, &p));
     R.d_desc = (SweepParams *)p;

@@ -92,6 +92,31 @@ def test_er20_topk_rewards_selector_and_fallback(ctx, mode, extra):
         assert res["stats"]["topk_ms"] > 0.0
 
 
+@pytest.mark.parametrize("mode,graph", [(amc.MODE_WAVE_L2, "ws200"), (amc.MODE_WAVE, "ws200"),
+                                        (amc.MODE_BLOCK, "er20"), (amc.MODE_WAVE_L2, "er20")])
+def test_last_realizations_split_into_kept_rows(ctx, mode, graph):
+    # whole realizations (tile = n) with R = workgroups + 37 and a finite k:
+    # the last 37 realizations run split into tiles that assemble their
+    # B(H_r) rows and labels in place in the rows the Top-k stage reads
+    g = W.config_er20().graph if graph == "er20" else W.ws_graph(200, 6, 0.1, 1)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 6}
+    pool = np.arange(3, g.n, 7)
+    gamma = 0.5 + 1.5 * np.random.default_rng(5).random(g.n)
+    G = amc.Graph(ctx, g.n, g.eu, g.ev)
+    probe = amc.run(ctx, G, model, seed=3, R=32768, mode=mode, tile=g.n, topk=3, pool=pool, gamma=gamma,
+                    flags=amc.SKIP_TAIL)                                 # the same plan as the run below
+    G.close()
+    blocks = probe["stats"]["blocks"]
+    if blocks >= 32768:
+        pytest.skip("more workgroup slots than the probe's realizations")
+    R = blocks + 37
+    res, ref = run_both(ctx, g, model, R, topk=3, pool=pool, gamma=gamma, seed=3, mode=mode, tile=g.n)
+    st = res["stats"]
+    assert st["tail_split"] == 37 and st["tail_tiles"] >= 2, st
+    check(res, ref, R, f"{graph} mode {mode} kept rows")
+    assert np.array_equal(res["counts"], ref["counts"])
+
+
 def test_unit_values_and_no_pool(ctx):
     wl = W.config_er20()
     g = wl.graph
