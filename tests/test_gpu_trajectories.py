@@ -148,6 +148,21 @@ def test_l2_request_on_a_small_graph(ctx):
     assert res["mode"] == amc.MODE_WAVE_L2
 
 
+@pytest.mark.parametrize("layout", ["l2-b-lds", "l2-b-global"])
+def test_fixed_weights_and_truncation_l2(ctx, layout):
+    # the graph's own weights (1 .. 40) and episodes cut at four states, in
+    # both L2 placements: truncated episodes are prefixes, as in the LDS one
+    base = W.ws_graph(300, 6, 0.2, 9)
+    w0 = (np.random.default_rng(9).integers(1, 41, len(base.eu))).astype(np.uint32)
+    g = W.canonical(base.n, np.stack([base.eu, base.ev], axis=1), w0=w0, name="ws300-fixed")
+    x0 = np.arange(0, 300, 7)
+    res, ref = both(ctx, g, {"p_fail": 0.08, "weight": "fixed"}, x0=x0, seed=21, alpha=0.05, max_steps=4,
+                    group=1, **LAYOUTS[layout])
+    check(res, ref, f"ws300 fixed weights {layout}")
+    check_layout(res, layout)
+    assert res["truncated"] > 0
+
+
 def test_graph_beyond_the_lds_layout(ctx):
     # n = 3500, mean degree 8, weights 1..10: the LDS layout does not hold the
     # realized graph and two wavefront regions, the L2 layout holds three
