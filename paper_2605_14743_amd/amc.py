@@ -541,7 +541,11 @@ def footprint(graph: Graph, **query) -> int:
 def trajectories(ctx: Context, graph: Graph, model: dict, *, seed=0, x0, alpha=0.15, k_min=5, tie_tau=-1.0,
                  max_steps=1024, f=None, want_paths=False, group=0, waves=0, mode=0, flags=0) -> dict:
     """amc_trajectories: episodes of the network process (Section 4.3) and the
-    length-biased estimators (b_hat, survival weights, node-reward total)."""
+    length-biased estimators (b_hat, survival weights, node-reward total).
+    mode: MODE_AUTO, MODE_WAVE (realized graph in LDS) or MODE_WAVE_L2 (in the
+    workgroup's L2 scratch, steps shared with idle workgroups); flags may add
+    TRAJ_B_LDS / TRAJ_B_GLOBAL and DIST16 / DIST32.  The result reports the
+    layout used (mode, waves, dist16, b_global) and shared_sources."""
     m, keep_m = make_model(**model)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     E = len(x0)
