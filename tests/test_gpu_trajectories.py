@@ -124,6 +124,37 @@ def test_shared_steps_ws1000(ctx, layout):
         assert res["shared_sources"] > 0
 
 
+def test_ws1000_placements_agree_at_scale(ctx):
+    # 2000 episodes on all 256 workgroups: the steps shared with workgroups
+    # out of episodes (a large share in the last rounds) leave every episode,
+    # visit count, switch and node-reward total as the LDS placement has them,
+    # whose episodes the oracle pins on samples
+    wl = W.config_ws1000()
+    g = wl.graph
+    G = amc.Graph(ctx, g.n, g.eu, g.ev, g.w0)
+    x0 = np.arange(2000) % g.n
+    f = np.linspace(0.0, 1.0, g.n)
+    kw = dict(seed=wl.seed + 7, x0=x0, alpha=wl.alpha, k_min=wl.k_min, max_steps=256, f=f)
+    runs = {}
+    try:
+        for layout in ("lds", "l2-b-lds", "l2-b-global"):
+            say(f"[gpu] ws1000 2000 episodes {layout}")
+            runs[layout] = amc.trajectories(ctx, G, wl.model(), **kw, **LAYOUTS[layout])
+    finally:
+        G.close()
+    base = runs["lds"]
+    assert base["shared_sources"] == 0
+    for layout in ("l2-b-lds", "l2-b-global"):
+        r = runs[layout]
+        check_layout(r, layout)
+        assert r["shared_sources"] > 0, layout
+        assert np.array_equal(r["lengths"], base["lengths"]), layout
+        assert np.array_equal(r["visits"], base["visits"]), layout
+        for key in ("switches", "total_steps", "sources", "truncated"):
+            assert r[key] == base[key], (layout, key)
+        assert r["reward_f"] == pytest.approx(base["reward_f"], rel=1e-12), layout
+
+
 @pytest.mark.parametrize("layout", ["l2-b-lds", "l2-b-global", "l2-b-lds-d16"])
 @pytest.mark.parametrize("group", [1, 2, 3])
 def test_er20_l2_layouts(ctx, layout, group):
