@@ -329,7 +329,7 @@ def run_bench(args):
             out["topk_stage"].update({"clique_pool": args.clique_pool, "fb_node": int(q["fb_node"]),
                                       "m_w_fb": last["m_w_fb"], "c_fb": last["c_fb"], "E_T_fb": last["E_T_fb"],
                                       "top5_b_fb": np.argsort(-last["b_fb"], kind="stable")[:5].tolist()})
-    if args.robust > 0:
+    def robust_leg():
         # robust tail on the estimated kernel: (samples + 2) Gauss-Jordan
         # inversions (2 n^3 flops each) and two n x n products (2 n^3 each);
         # node values: the multi-reward value of the robust experiment
@@ -344,23 +344,31 @@ def run_bench(args):
                             topology=(g.eu, g.ev))
             w1 = {"w1_max": float(rw["w1"].max()), "w1_arg": rw["w1_arg"], "kl_arg": rw["kl_arg"],
                   "w1_ms": rw["tail_ms"] - rb["tail_ms"]}
-        out["robust_tail"] = {"samples": args.robust, "ms": rb["tail_ms"], "fp64_TFLOPs": flops / (rb["tail_ms"] * 1e-3)
-                              / 1e12, "peak_fp64_TFLOPs": 78.6, "kl_max": float(rb["kl"].max()),
-                              "tv_max": float(rb["tv"].max()), "norm_N0E": rb["norm_N0E"],
-                              "rem_bound": rb["rem_bound"], "rem_actual": rb["rem_actual"],
-                              "b_switch": rb["b_sw"], "b_improve": rb["b_imp"], **w1}
-    if args.bootstrap > 0:
+        return {"samples": args.robust, "ms": rb["tail_ms"], "fp64_TFLOPs": flops / (rb["tail_ms"] * 1e-3)
+                / 1e12, "peak_fp64_TFLOPs": 78.6, "kl_max": float(rb["kl"].max()),
+                "tv_max": float(rb["tv"].max()), "norm_N0E": rb["norm_N0E"],
+                "rem_bound": rb["rem_bound"], "rem_actual": rb["rem_actual"],
+                "b_switch": rb["b_sw"], "b_improve": rb["b_imp"], **w1}
+
+    if args.robust > 0:
+        secondary(out, "robust_tail", robust_leg)
+
+    def bootstrap_leg():
         # bootstrap of b from this run's draws (outside the timed region): B
         # replicates of n R redrawn indices, B + 1 Gauss-Jordan inversions
         nt = amc.run(ctx, G, model, **dict(q, flags=q.get("flags", 0) | amc.WANT_NEXT_TABLE))["next_table"]
         amc.bootstrap(ctx, nt, replicates=2, seed=1, want_reps=False)
         bs = amc.bootstrap(ctx, nt, replicates=args.bootstrap, seed=1, want_reps=False)
         flops = (args.bootstrap + 1) * 2.0 * g.n ** 3
-        out["bootstrap"] = {"replicates": args.bootstrap, "ms": bs["ms"],
-                            "fp64_TFLOPs": flops / (bs["ms"] * 1e-3) / 1e12, "peak_fp64_TFLOPs": 78.6,
-                            "median_sd_over_b": float(np.median(bs["sd"] / np.maximum(bs["b0"], 1e-300))),
-                            "widest_interval": float((bs["hi"] - bs["lo"]).max())}
-    if args.stability > 0:
+        return {"replicates": args.bootstrap, "ms": bs["ms"],
+                "fp64_TFLOPs": flops / (bs["ms"] * 1e-3) / 1e12, "peak_fp64_TFLOPs": 78.6,
+                "median_sd_over_b": float(np.median(bs["sd"] / np.maximum(bs["b0"], 1e-300))),
+                "widest_interval": float((bs["hi"] - bs["lo"]).max())}
+
+    if args.bootstrap > 0:
+        secondary(out, "bootstrap", bootstrap_leg)
+
+    def stability_leg():
         # rank-stability check: Top-k by b at M = R / 2 and at 2M = R
         qs = {k: v for k, v in q.items()
               if k not in ("pool", "reward", "topk", "gamma", "flags", "cert_topk", "fb_node")}
@@ -368,9 +376,12 @@ def run_bench(args):
         if args.dist32:
             qs["flags"] = amc.DIST32
         sb = amc.stability(ctx, G, model, k=args.stability, **qs)
-        out["stability"] = {"k": args.stability, "M": qs["R"], "same_set": sb["same_set"], "overlap": sb["overlap"],
-                            "max_abs_diff": sb["max_abs_diff"], "sweep_ms": sb["sweep_ms"],
-                            "top_M": sb["top_M"].tolist(), "top_2M": sb["top_2M"].tolist()}
+        return {"k": args.stability, "M": qs["R"], "same_set": sb["same_set"], "overlap": sb["overlap"],
+                "max_abs_diff": sb["max_abs_diff"], "sweep_ms": sb["sweep_ms"],
+                "top_M": sb["top_M"].tolist(), "top_2M": sb["top_2M"].tolist()}
+
+    if args.stability > 0:
+        secondary(out, "stability", stability_leg)
     if args.plain_R > 0:
         qp = dict(q, R=args.plain_R, flags=amc.PLAIN_LAUNCH | amc.SKIP_TAIL)
         amc.run(ctx, G, model, **qp)
@@ -388,7 +399,7 @@ def run_bench(args):
                             "batched_over_plain": value / pv, "target": PLAIN_TARGET,
                             "target_met": value / pv >= PLAIN_TARGET}
     if args.traj_leg > 0:
-        out["trajectories"] = traj_leg(ctx, amc, wl, G, args.traj_leg, args.max_steps, last["E_T"])
+        secondary(out, "trajectories", lambda: traj_leg(ctx, amc, wl, G, args.traj_leg, args.max_steps, last["E_T"]))
     G.close()
     if args.er5000 and args.workload == "ws1000":
         out["er5000"] = er5000_leg(ctx, amc)
@@ -461,6 +472,16 @@ def run_batch(args):
         G.close()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def secondary(out: dict, key: str, leg) -> None:
+    """Runs a secondary leg of the bench line; an error is recorded under its
+    key (the headline line is still printed), not hidden."""
+    try:
+        out[key] = leg()
+    except Exception as e:  # noqa: BLE001 -- recorded in the line
+        print(f"# {key} leg failed: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
+        out[key] = {"error": f"{type(e).__name__}: {e}"}
 
 
 def traj_leg(ctx, amc, wl, G, E, max_steps, row_E_T):

@@ -81,3 +81,17 @@ def test_cpu_baseline_all_cores():
     many = bench.cpu_baseline("er20", 2, 0.2)
     assert many["kind"] == "oracle" and many["cores"] == 2 and many["value"] > 0 and many["cpu_model"]
     assert 1 <= bench.cpu_cores() <= 16
+
+
+def test_secondary_leg_failure_is_recorded():
+    # a failing secondary leg leaves its error in the line instead of ending
+    # the run before the headline is printed
+    out = {}
+    bench.secondary(out, "ok_leg", lambda: {"value": 1})
+
+    def broken():
+        raise RuntimeError("device says no")
+
+    bench.secondary(out, "broken_leg", broken)
+    assert out["ok_leg"] == {"value": 1}
+    assert out["broken_leg"] == {"error": "RuntimeError: device says no"}
