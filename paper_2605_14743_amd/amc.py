@@ -21,7 +21,7 @@ WEIGHT_UNIT, WEIGHT_UNIFORM_INT, WEIGHT_FIXED, WEIGHT_TABLE = 0, 1, 2, 3
 MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK, DIST32, DIST16 = \
     1, 2, 4, 8, 16, 32, 64, 128, 256, 512
-SIGMA_GLOBAL = 1024
+SIGMA_GLOBAL, STATE_GLOBAL = 1024, 2048
 MAX_TOPK, MAX_TOPK_N = 64, 7000
 MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
 MAX_W1_N = 3000
@@ -120,7 +120,7 @@ class Stats(C.Structure):
                 ("waves", C.c_int32), ("tile", C.c_int32), ("blocks", C.c_int32), ("lds_bytes", C.c_int32),
                 ("launches", C.c_int32), ("group", C.c_int32), ("adj_bytes", C.c_int32), ("topk_ms", C.c_double),
                 ("dist_bytes", C.c_int32), ("b_global", C.c_int32), ("tail_split", C.c_int32),
-                ("tail_tiles", C.c_int32), ("sig_global", C.c_int32)]
+                ("tail_tiles", C.c_int32), ("sig_global", C.c_int32), ("state_global", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -384,6 +384,9 @@ int validate(const amc_graph *g, const amc_model *md, const amc_query *q) {
     }
     if (q->hop_radius < 0) return AMC_E_INVALID_ARG;
     if ((q->flags & AMC_DIST32) && (q->flags & AMC_DIST16)) return AMC_E_INVALID_ARG;
+    if ((q->flags & AMC_STATE_GLOBAL) &&
+        ((q->flags & AMC_SIGMA_GLOBAL) || q->hop_radius > 0 || (q->mode != AMC_MODE_AUTO && q->mode != AMC_MODE_BLOCK)))
+        return AMC_E_INVALID_ARG;
     if (q->hop_radius > 0) {
         if (q->topk > 0 || (q->flags & (AMC_WANT_CENTER | AMC_WANT_BSUM | AMC_WANT_DEBUG | AMC_PLAIN_LAUNCH)) ||
             (q->mode != AMC_MODE_AUTO && q->mode != AMC_MODE_WAVE))
@@ -549,6 +552,8 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     for (int pc = 2; pc < kPlaces; ++pc)
         if (eff(pc, width(pc)) > eff(l2_pc, width(l2_pc))) l2_pc = pc;
     int mode = q->mode;
+    const bool force_gs = (q->flags & AMC_STATE_GLOBAL) != 0;
+    if (mode == AMC_MODE_AUTO && force_gs) mode = AMC_MODE_BLOCK;
     if (mode == AMC_MODE_AUTO) {
         const double e_lds = eff(0, width(0)), e_l2 = eff(l2_pc, width(l2_pc));
         const double e_best = std::max(e_lds, e_l2);
@@ -569,6 +574,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     pl->scratch_words = 0;
     pl->b_global = false;
     pl->sig_global = false;
+    pl->state_global = false;
     if (mode == AMC_MODE_WAVE || mode == AMC_MODE_WAVE_L2) {
         const int pc = mode == AMC_MODE_WAVE_L2 ? l2_pc : 0;
         const int d16 = width(pc);
@@ -586,19 +592,25 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     } else {
         pl->dist16 = false;
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
-        pl->lds = lds_bytes_block(n, pl->threads);
-        if (pl->lds > (uint32_t)ctx->max_lds) return AMC_E_UNSUPPORTED;
-        if (2ull * (uint64_t)g->m > block_staging_bytes(n)) return AMC_E_UNSUPPORTED;   // per-edge staging
-        if (n > 8191) return AMC_E_UNSUPPORTED;   // the degree order packs vertex ids into 13 bits
+        // the per-source state stays in LDS where it fits, else it moves to
+        // the workgroup's global scratch (or when the caller asks)
+        pl->state_global = force_gs || lds_bytes_block(n, pl->threads) > (uint32_t)ctx->max_lds;
+        pl->lds = pl->state_global ? 0u : lds_bytes_block(n, pl->threads);
+        // per-edge staging below the row offsets, in either placement
+        if (2ull * (uint64_t)g->m > block_staging_bytes(n)) return AMC_E_UNSUPPORTED;
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;
-        pl->scratch_words = (uint32_t)block_scratch_words(n, g->m, pl->weighted);
+        const size_t words = block_scratch_words(n, g->m, pl->weighted, pl->state_global);
+        if (words > 0xFFFFFFFFull) return AMC_E_UNSUPPORTED;
+        pl->scratch_words = (uint32_t)words;
     }
     // sources per work item: whole realizations when there are enough of
     // them to fill the device, otherwise split the sources
     uint32_t blocks_per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl->lds, 1u));
     if (mode != AMC_MODE_WAVE) blocks_per_cu = std::min(blocks_per_cu, kMaxScratchBlocksPerCu);
+    // workgroups of 16 wavefronts: two per CU are resident at most
+    if (pl->state_global) blocks_per_cu = std::min(blocks_per_cu, 2u);
     const uint64_t slots = (uint64_t)ctx->cu_count * blocks_per_cu;
     int tile = q->tile;
     if (q->flags & AMC_PLAIN_LAUNCH) tile = mode == AMC_MODE_BLOCK ? 1 : pl->waves;
@@ -638,7 +650,8 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     b += (8 + 4 + 4) * R * n + 4 * R;
     if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + (3 * 8 + 1) * 16 * n + 1024;
     // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
-    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true),
+    const bool gs = (q->flags & AMC_STATE_GLOBAL) || lds_bytes_block((int)n, 1024) > (uint32_t)g->ctx->max_lds;
+    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true, gs),
                                            l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u, kMaxWaves));
     b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;

@@ -24,9 +24,11 @@ hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool d
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);
 uint32_t block_staging_bytes(int n);
-size_t block_scratch_words(int n, int64_t m, bool weighted);
-hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
-                              hipStream_t st);
+// state_global: the per-source state (distances, path counts, order, B,
+// labels, row offsets) in the workgroup's scratch instead of LDS
+size_t block_scratch_words(int n, int64_t m, bool weighted, bool state_global = false);
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, bool state_global, int blocks, int threads,
+                              uint32_t lds, hipStream_t st);
 
 hipError_t set_sweep_wave_attrs(int max_lds);
 hipError_t set_sweep_block_attrs(int max_lds);

@@ -19,7 +19,12 @@
 // distance is the fringe minimum (distance buckets).  The reverse pass walks
 // the equal-distance segments backwards and accumulates the dependencies of
 // the Section 3.1 betweenness into B(H_r) held in LDS; the reduction and the
-// counting are the same as in the LDS mode.
+// counting are the same as in the LDS mode.  GS: the same carve-up lives in
+// the workgroup's global scratch instead of LDS (graphs whose per-source
+// state exceeds the LDS, up to 65535 vertices); all of it is read and written
+// by the one workgroup, whose global accesses a barrier orders as it does its
+// LDS accesses, so the code is the same.  Levels are ordered by degree only
+// while vertex ids fit the 13 bits that order packs them into.
 #include <type_traits>
 
 #include "amc_dev.hpp"
@@ -31,6 +36,7 @@ namespace amc {
 constexpr int kBU = 4;          // adjacency slots per lane and trip
 constexpr int kSortMin = 512;    // unit weights: levels at least this large are ordered by degree
 constexpr int kDegClasses = 4;   // degree classes of that order: 1-4, 5-8, 9-12, 13 or more
+constexpr int kSortMaxN = 8191;  // the order packs vertex ids into 13 bits
 static_assert(kDegClasses * 16 <= 64, "the class counters share one 64-bit word");
 
 // LDS: dist u32[n] | sig u64[n] | ord u16[n] | aux u16[n] | B f64[n] | comp
@@ -265,7 +271,7 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
             if (new_end == ord_end) break;
             // the new level occupies ord[ord_end, new_end) and aux[0, new_end -
             // ord_end) stays below the segment starts at aux[n - nseg, n)
-            if (new_end - ord_end >= kSortMin)
+            if (new_end - ord_end >= kSortMin && n <= kSortMaxN)
                 order_level_by_degree(ord + ord_end, aux, rp, new_end - ord_end, (unsigned long long *)tmp);
             f_lo = ord_end;
             ord_end = new_end;
@@ -402,7 +408,13 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
 // ADJ: the realized adjacency entry, uint32_t (weight << 16 | neighbour) or,
 // with unit weights, uint16_t (the neighbour alone), which halves the
 // per-workgroup scratch the traversal reads so that it stays in the L2.
-template <bool WEIGHTED, typename ADJ>
+// Words of the per-workgroup scratch before the GS state region: the realized
+// adjacency, then the component centres (2 n words) and 64 words of slack.
+__host__ __device__ inline size_t block_gs_state_words(int n, int64_t m, uint32_t adj_bytes) {
+    return (block_adj_words(m, adj_bytes) + 2 * (size_t)n + 64 + 3) & ~(size_t)3;
+}
+
+template <bool WEIGHTED, typename ADJ, bool GS>
 __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ __attribute__((aligned(8))) uint32_t scan_tmp[2 * kMaxWaves];
@@ -443,28 +455,32 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
 
         const int n = P.n;
         const BlockLayout L = block_layout(n);
-        uint32_t *dist = (uint32_t *)(smem + L.dist);
-        unsigned long long *sig = (unsigned long long *)(smem + L.sig);
-        uint16_t *ord = (uint16_t *)(smem + L.ord);
-        uint16_t *aux = (uint16_t *)(smem + L.aux);
-        double *B = (double *)(smem + L.B);
-        uint16_t *comp = (uint16_t *)(smem + L.comp);
-        uint16_t *csize = (uint16_t *)(smem + L.csize);
         // per-workgroup global scratch: the realized adjacency (2m plus
         // padding entries), then the component centres (2 n words), which
-        // also absorb the reads past the last vertex's slots
+        // also absorb the reads past the last vertex's slots; with GS the
+        // state region follows
         uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
-        uint32_t *rp = (uint32_t *)(smem + L.rp);
+        unsigned char *st;
+        if constexpr (GS) st = (unsigned char *)to_global(gs + block_gs_state_words(n, P.m, (uint32_t)sizeof(ADJ)));
+        else st = smem;
+        uint32_t *dist = (uint32_t *)(st + L.dist);
+        unsigned long long *sig = (unsigned long long *)(st + L.sig);
+        uint16_t *ord = (uint16_t *)(st + L.ord);
+        uint16_t *aux = (uint16_t *)(st + L.aux);
+        double *B = (double *)(st + L.B);
+        uint16_t *comp = (uint16_t *)(st + L.comp);
+        uint16_t *csize = (uint16_t *)(st + L.csize);
+        uint32_t *rp = (uint32_t *)(st + L.rp);
         ADJ *adj = to_global((ADJ *)gs);
         ReduceScratch RS;
-        RS.cmax = (unsigned long long *)smem;              // aliases dist/sig (free during the reduction)
+        RS.cmax = (unsigned long long *)st;                // aliases dist/sig (free during the reduction)
         RS.wmax = RS.cmax + n;
         uint32_t *tail4 = gs + block_adj_words(P.m, (uint32_t)sizeof(ADJ));
         RS.ccen = (int32_t *)tail4;
         RS.wcen = RS.ccen + n;
 
         // entries (w << 16) | neighbour; a 16-bit entry keeps the neighbour
-        stage_realization(P, r, rp, adj, 16u, (uint16_t *)smem, scan_tmp);
+        stage_realization(P, r, rp, adj, 16u, (uint16_t *)st, scan_tmp);
         for (int v = tid; v < n; v += nthr) B[v] = 0.0;
         __syncthreads();
 
@@ -520,25 +536,38 @@ uint32_t lds_bytes_block(int n, int threads) {
 // Bytes at the start of the LDS that the per-edge staging may use (below rp).
 uint32_t block_staging_bytes(int n) { return block_layout(n).rp; }
 
-size_t block_scratch_words(int n, int64_t m, bool weighted) {
-    return block_adj_words(m, weighted ? 4u : 2u) + 2 * (size_t)n + 64;
+size_t block_scratch_words(int n, int64_t m, bool weighted, bool state_global) {
+    const uint32_t ab = weighted ? 4u : 2u;
+    if (!state_global) return block_adj_words(m, ab) + 2 * (size_t)n + 64;
+    return block_gs_state_words(n, m, ab) + block_layout(n).total / 4;
 }
 
-hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
-                              hipStream_t st) {
+template <bool GS>
+static hipError_t launch_block_t(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
+                                 hipStream_t st) {
     if (weighted)
-        hipLaunchKernelGGL((sweep_block_kernel<true, uint32_t>), dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<true, uint32_t, GS>), dim3(blocks), dim3(threads), lds, st, LC);
     else
-        hipLaunchKernelGGL((sweep_block_kernel<false, uint16_t>), dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<false, uint16_t, GS>), dim3(blocks), dim3(threads), lds, st, LC);
     return hipGetLastError();
 }
 
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, bool state_global, int blocks, int threads,
+                              uint32_t lds, hipStream_t st) {
+    return state_global ? launch_block_t<true>(LC, weighted, blocks, threads, lds, st)
+                        : launch_block_t<false>(LC, weighted, blocks, threads, lds, st);
+}
+
 hipError_t set_sweep_block_attrs(int max_lds) {
-    hipError_t e = hipFuncSetAttribute((const void *)sweep_block_kernel<true, uint32_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)sweep_block_kernel<false, uint16_t>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    const void *ks[] = {(const void *)sweep_block_kernel<true, uint32_t, false>,
+                        (const void *)sweep_block_kernel<false, uint16_t, false>,
+                        (const void *)sweep_block_kernel<true, uint32_t, true>,
+                        (const void *)sweep_block_kernel<false, uint16_t, true>};
+    for (const void *k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace amc

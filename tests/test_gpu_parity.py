@@ -748,3 +748,54 @@ def test_symmetric_ties_every_mode(ctx, graph, weights):
         res = gpu_run(ctx, g, model, flags=fl, mode=mode, **kw, **extra)
         assert res["stats"]["mode"] == mode
         check_sweep(res, ref, g.n, f"{graph} {weights} mode {mode} {extra}")
+
+
+# --------------------------------------------------------------------------- state in the global scratch
+@pytest.mark.parametrize("graph,model,extra", [
+    ("er20", {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 5}, {}),
+    ("er20", {"p_fail": 0.1, "weight": "unit"}, {"tile": 7}),
+    ("ws200", {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 6}, {"pool": True}),
+    ("er2000", {"p_fail": 0.1, "weight": "unit"}, {}),
+    ("er2000", {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 3}, {"tile": 700}),
+])
+def test_workgroup_mode_state_in_global_scratch(ctx, graph, model, extra):
+    # the workgroup-per-source mode with every source's state in the global
+    # scratch (forced here on graphs whose state fits LDS) against the oracle
+    g = {"er20": lambda: W.config_er20().graph, "ws200": lambda: W.ws_graph(200, 6, 0.1, 1),
+         "er2000": lambda: W.er_graph(2000, 8.0 / 1999, 7)}[graph]()
+    extra = dict(extra)
+    pool = np.arange(3, g.n, 7) if extra.pop("pool", False) else None
+    R = 40 if g.n >= 2000 else 300
+    res = gpu_run(ctx, g, model, seed=5, R=R, alpha=0.15, k_min=5, flags=FLAGS | amc.STATE_GLOBAL,
+                  pool=pool, **extra)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1 and st["lds_bytes"] == 0, st
+    ref = (P if g.n >= 2000 else O).sweep(g.n, g.eu, g.ev, seed=5, R=R, alpha=0.15, k_min=5, want_next=True,
+                                          pool=pool, **oracle_model(model, g))
+    check_sweep(res, ref, g.n, f"{graph} state in global scratch {extra}")
+    t = O.tail(ref["counts"], R)
+    assert_close_norm(res["b"], t["b"], what="b")
+
+
+def test_graph_beyond_every_lds_layout_runs_with_global_state(ctx):
+    # n = 9000 (unit weights): no wavefront layout and no LDS workgroup layout
+    # holds it; the planner moves the workgroup mode's state to the global
+    # scratch.  One realization against the oracle (split into tiles), and
+    # sampled sources' distances, path counts and dependencies
+    g = W.er_graph(9000, 8.0 / 8999, 90)
+    model = {"p_fail": 0.1, "weight": "unit"}
+    pairs = [(0, 0), (0, 4500), (0, 8999)]
+    res = gpu_run(ctx, g, model, seed=3, R=1, alpha=0.15, k_min=5,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, debug_pairs=pairs)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1, st
+    for k, (r, s) in enumerate(pairs):
+        alive, w = O.realize(g.n, g.eu, g.ev, 3, r, **model)
+        d, sg, dl = O.sssp(g.n, g.eu, g.ev, alive, w, True, s)
+        dd = np.where(d == np.iinfo(np.uint64).max, 0xFFFFFFFF, d).astype(np.uint32)
+        assert np.array_equal(res["dbg_dist"][k], dd), (r, s)
+        assert np.array_equal(res["dbg_sigma"][k], sg), (r, s)
+        assert_rel(res["dbg_delta"][k], dl, what=f"delta {(r, s)}")
+    say(f"[cpu] oracle on n={g.n} R=1")
+    ref = O.sweep(g.n, g.eu, g.ev, seed=3, R=1, alpha=0.15, k_min=5, want_next=True, **model)
+    check_sweep(res, ref, g.n, "n=9000 global state")
