@@ -96,10 +96,12 @@ extern "C" {
                                          source and anchored kernels keep 32-bit entries. */
 #define AMC_STATE_GLOBAL (1u << 11)   /* workgroup-per-source mode with the whole per-source state
                                          (distances, path counts, visit order, B(H_r), labels, realized
-                                         row offsets) in the per-workgroup global scratch instead of LDS;
-                                         the planner takes it by itself when no other mode fits (graphs
-                                         up to 65535 vertices).  Mode AUTO or BLOCK, not with
-                                         AMC_SIGMA_GLOBAL or hop_radius.  Results are identical. */
+                                         row offsets) in the per-workgroup global scratch instead of LDS.
+                                         Without the flag the planner moves the state there by itself
+                                         when no other mode fits (graphs up to 65535 vertices), keeping
+                                         distances and row offsets in LDS while they fit (8 n bytes).
+                                         Mode AUTO or BLOCK, not with AMC_SIGMA_GLOBAL or hop_radius.
+                                         Results are identical. */
 #define AMC_SIGMA_GLOBAL (1u << 10)   /* L2 mode with every wavefront's path counts in the per-workgroup
                                          global scratch instead of LDS (more sources in flight on large
                                          graphs); needs a lane-per-vertex mapping (group 0 .. 3) and
@@ -200,7 +202,8 @@ typedef struct amc_stats {
     int32_t tail_split;         /* last realizations run split into tiles (R mod blocks), 0 = none */
     int32_t tail_tiles;         /* tiles per such realization                                   */
     int32_t sig_global;         /* L2 mode: 1 = path counts in the global scratch, 0 = in LDS    */
-    int32_t state_global;       /* workgroup mode: 1 = per-source state in the global scratch    */
+    int32_t state_global;       /* workgroup mode: per-source state 0 = in LDS, 1 = in the global
+                                   scratch but for distances and row offsets, 2 = all in the scratch */
 } amc_stats;
 
 /* Caller-owned host buffers; NULL pointers are skipped. */

@@ -562,9 +562,15 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
         // weights n = 2400, 5 L2 wavefronts 6.6 vs 6.8 M/s, n = 4000, 3 L2
         // wavefronts 2.3 vs 4.8 M/s; weighted n = 5000, 2 L2 wavefronts 1.05
         // vs 1.14 M/s)
+        // with unit weights the mode also counts as fitting with its state in
+        // the global scratch but distances and row offsets in LDS (measured on
+        // MI355X, ER degree 8: n = 5400 1.99 vs 1.39 M/s for two L2
+        // wavefronts, n = 6000 1.68 vs 1.12; weighted graphs gain little or
+        // lose: n = 5400 0.86 vs 0.99, n = 6000 0.80 vs 0.77)
         const uint32_t block_lds = lds_bytes_block(n, 1024);
-        const bool block_fits = !force_sg && n <= 8191 &&
-            block_lds <= (uint32_t)ctx->max_lds && 2ull * (uint64_t)g->m <= block_staging_bytes(n);
+        const uint32_t mx = (uint32_t)ctx->max_lds;
+        const bool block_fits = !force_sg && 2ull * (uint64_t)g->m <= block_staging_bytes(n) &&
+            (block_lds <= mx || (!pl->weighted && lds_bytes_block_hybrid(n) <= mx));
         const double block_below = pl->weighted ? 1.8 : 4.0;
         if (e_best > 0.0 && (!block_fits || e_best >= block_below))
             mode = e_lds >= e_l2 ? AMC_MODE_WAVE : AMC_MODE_WAVE_L2;
@@ -574,7 +580,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     pl->scratch_words = 0;
     pl->b_global = false;
     pl->sig_global = false;
-    pl->state_global = false;
+    pl->state_place = 0;
     if (mode == AMC_MODE_WAVE || mode == AMC_MODE_WAVE_L2) {
         const int pc = mode == AMC_MODE_WAVE_L2 ? l2_pc : 0;
         const int d16 = width(pc);
@@ -592,16 +598,23 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     } else {
         pl->dist16 = false;
         pl->threads = q->waves > 0 ? 64 * q->waves : 1024;
-        // the per-source state stays in LDS where it fits, else it moves to
-        // the workgroup's global scratch (or when the caller asks)
-        pl->state_global = force_gs || lds_bytes_block(n, pl->threads) > (uint32_t)ctx->max_lds;
-        pl->lds = pl->state_global ? 0u : lds_bytes_block(n, pl->threads);
+        // the per-source state stays in LDS where it fits; otherwise it moves
+        // to the workgroup's global scratch, keeping the distances and row
+        // offsets (the most used arrays) in LDS where those fit; all of it
+        // when the caller asks
+        const uint32_t mx = (uint32_t)ctx->max_lds;
+        pl->state_place = force_gs ? 2 : lds_bytes_block(n, pl->threads) <= mx ? 0
+                                   : lds_bytes_block_hybrid(n) <= mx      ? 1
+                                                                            : 2;
+        pl->lds = pl->state_place == 0   ? lds_bytes_block(n, pl->threads)
+                  : pl->state_place == 1 ? lds_bytes_block_hybrid(n)
+                                         : 0u;
         // per-edge staging below the row offsets, in either placement
         if (2ull * (uint64_t)g->m > block_staging_bytes(n)) return AMC_E_UNSUPPORTED;
         pl->waves = pl->threads / 64;
         pl->wave_bytes = 0;
         pl->adj_cap = adj_cap;
-        const size_t words = block_scratch_words(n, g->m, pl->weighted, pl->state_global);
+        const size_t words = block_scratch_words(n, g->m, pl->weighted, pl->state_place);
         if (words > 0xFFFFFFFFull) return AMC_E_UNSUPPORTED;
         pl->scratch_words = (uint32_t)words;
     }
@@ -610,7 +623,7 @@ int plan(const amc_ctx *ctx, const amc_graph *g, const amc_model *md, const amc_
     uint32_t blocks_per_cu = std::max<uint32_t>(1u, (uint32_t)ctx->max_lds / std::max<uint32_t>(pl->lds, 1u));
     if (mode != AMC_MODE_WAVE) blocks_per_cu = std::min(blocks_per_cu, kMaxScratchBlocksPerCu);
     // workgroups of 16 wavefronts: two per CU are resident at most
-    if (pl->state_global) blocks_per_cu = std::min(blocks_per_cu, 2u);
+    if (pl->state_place) blocks_per_cu = std::min(blocks_per_cu, 2u);
     const uint64_t slots = (uint64_t)ctx->cu_count * blocks_per_cu;
     int tile = q->tile;
     if (q->flags & AMC_PLAIN_LAUNCH) tile = mode == AMC_MODE_BLOCK ? 1 : pl->waves;
@@ -651,7 +664,7 @@ extern "C" int amc_footprint(const amc_graph *g, const amc_query *q, uint64_t *b
     if (!(q->flags & AMC_SKIP_TAIL)) b += (q->pool_size > 0 ? 4 : 2) * 8 * n * n + (3 * 8 + 1) * 16 * n + 1024;
     // per-workgroup scratch of the block and L2 modes (4-byte entries, upper bound)
     const bool gs = (q->flags & AMC_STATE_GLOBAL) || lds_bytes_block((int)n, 1024) > (uint32_t)g->ctx->max_lds;
-    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true, gs),
+    const uint64_t sw = std::max<uint64_t>(block_scratch_words((int)n, g->m, true, gs ? 2 : 0),
                                            l2_scratch_words((int)n, (uint32_t)(2 * g->m) + kAdjPad, 4u, kMaxWaves));
     b += 4 * (uint64_t)g->ctx->cu_count * kMaxScratchBlocksPerCu * sw;
     if (q->n_debug > 0) b += (uint64_t)q->n_debug * n * 20;

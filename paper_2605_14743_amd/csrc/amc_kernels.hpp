@@ -24,10 +24,13 @@ hipError_t launch_sweep_wave(const LaunchCtl &LC, bool weighted, bool l2, bool d
 // Workgroup-per-(r, s) sweep with frontier queues (graphs beyond the LDS mode).
 uint32_t lds_bytes_block(int n, int threads);
 uint32_t block_staging_bytes(int n);
-// state_global: the per-source state (distances, path counts, order, B,
-// labels, row offsets) in the workgroup's scratch instead of LDS
-size_t block_scratch_words(int n, int64_t m, bool weighted, bool state_global = false);
-hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, bool state_global, int blocks, int threads,
+// state_place: where the per-source state (distances, path counts, order,
+// B, labels, row offsets) lives: 0 LDS, 1 the workgroup's scratch except the
+// distances and row offsets (lds_bytes_block_hybrid bytes of LDS), 2 all in
+// the workgroup's scratch
+uint32_t lds_bytes_block_hybrid(int n);
+size_t block_scratch_words(int n, int64_t m, bool weighted, int state_place = 0);
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int state_place, int blocks, int threads,
                               uint32_t lds, hipStream_t st);
 
 hipError_t set_sweep_wave_attrs(int max_lds);

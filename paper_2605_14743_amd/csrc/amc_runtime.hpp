@@ -55,7 +55,8 @@ struct Plan {
     bool dist16 = false;            // 16-bit distance entries in the wavefront regions
     bool b_global = false;          // L2 mode: B(H_r) in the global scratch instead of LDS
     bool sig_global = false;        // L2 mode: path counts in the global scratch instead of LDS
-    bool state_global = false;      // workgroup mode: per-source state in the global scratch instead of LDS
+    int state_place = 0;            // workgroup mode: per-source state in LDS (0), in the global scratch
+                                    // but for distances and row offsets (1), all in the scratch (2)
 };
 
 // Private copies of the arrays a query points to (inputs are never retained):

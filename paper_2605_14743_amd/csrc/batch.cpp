@@ -115,11 +115,11 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
     // per-source placement (distance width, path counts in LDS or scratch)
     // is part of the key
     struct Key {
-        int mode, weighted, group, adj_bytes, waves, anchored, dist16, sig_global, state_global;
+        int mode, weighted, group, adj_bytes, waves, anchored, dist16, sig_global, state_place;
         bool operator==(const Key &o) const {
             return mode == o.mode && weighted == o.weighted && group == o.group && adj_bytes == o.adj_bytes &&
                    waves == o.waves && anchored == o.anchored && dist16 == o.dist16 && sig_global == o.sig_global &&
-                   state_global == o.state_global;
+                   state_place == o.state_place;
         }
     };
     std::vector<Key> keys;
@@ -137,7 +137,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         }
         if (pl.anchored) w = pl.waves;
         Key k{pl.mode, pl.weighted ? 1 : 0, per_wave ? pl.group : 0, (int)pl.adj_bytes, w,
-              pl.anchored ? 1 : 0, pl.dist16 ? 1 : 0, pl.sig_global ? 1 : 0, pl.state_global ? 1 : 0};
+              pl.anchored ? 1 : 0, pl.dist16 ? 1 : 0, pl.sig_global ? 1 : 0, pl.state_place};
         size_t gi = 0;
         while (gi < keys.size() && !(keys[gi] == k)) ++gi;
         if (gi == keys.size()) {
@@ -238,7 +238,7 @@ int build(amc_batch *b, int32_t count, const amc_graph *const *graphs, const amc
         hipError_t e = G.pl.anchored
                            ? launch_anchored(LC, G.pl.weighted, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st)
                        : G.pl.mode == AMC_MODE_BLOCK
-                           ? launch_sweep_block(LC, G.pl.weighted, G.pl.state_global, G.blocks, G.pl.threads,
+                           ? launch_sweep_block(LC, G.pl.weighted, G.pl.state_place, G.blocks, G.pl.threads,
                                                 G.pl.lds, st)
                            : launch_sweep_wave(LC, G.pl.weighted, G.pl.mode == AMC_MODE_WAVE_L2, G.pl.dist16, G.pl.sig_global,
                                                G.pl.group, G.pl.adj_bytes, G.blocks, G.pl.waves, G.pl.lds, st);

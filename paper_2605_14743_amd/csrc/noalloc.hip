@@ -137,7 +137,7 @@ extern "C" int amc_sweep_static(amc_ctx *ctx, const amc_graph *g, const amc_mode
         stats->dist_bytes = R.pl.dist16 ? 2 : 4;
         stats->b_global = R.pl.b_global ? 1 : 0;
         stats->sig_global = R.pl.sig_global ? 1 : 0;
-        stats->state_global = R.pl.state_global ? 1 : 0;
+        stats->state_global = R.pl.state_place;
         stats->tail_split = R.split_tail ? (int32_t)R.tail_R : 0;
         stats->tail_tiles = R.split_tail ? R.P2.tiles_per_r : 0;
     }

@@ -366,7 +366,7 @@ static hipError_t launch_plan(const Plan &pl, const LaunchCtl &LC, int blocks, h
         return launch_sweep_wave(LC, pl.weighted, pl.mode == AMC_MODE_WAVE_L2, pl.dist16, pl.sig_global, pl.group,
                                  pl.adj_bytes,
                                  blocks, pl.waves, pl.lds, st);
-    return launch_sweep_block(LC, pl.weighted, pl.state_global, blocks, pl.threads, pl.lds, st);
+    return launch_sweep_block(LC, pl.weighted, pl.state_place, blocks, pl.threads, pl.lds, st);
 }
 
 int qr_enqueue_sweep(QueryRun &R, hipStream_t st) {
@@ -514,7 +514,7 @@ int qr_finish(QueryRun &R, amc_result *out, hipStream_t st) {
         out->stats.dist_bytes = R.pl.dist16 ? 2 : 4;
         out->stats.b_global = R.pl.b_global ? 1 : 0;
         out->stats.sig_global = R.pl.sig_global ? 1 : 0;
-        out->stats.state_global = R.pl.state_global ? 1 : 0;
+        out->stats.state_global = R.pl.state_place;
         out->stats.tail_split = R.split_tail ? (int32_t)R.tail_R : 0;
         out->stats.tail_tiles = R.split_tail ? R.P2.tiles_per_r : 0;
     }

@@ -179,7 +179,7 @@ struct Server {
     int variant_of(const Plan &pl) {
         const int key[7] = {pl.mode, pl.weighted ? 1 : 0, pl.mode == AMC_MODE_BLOCK ? 0 : pl.group,
                             (int)pl.adj_bytes,
-                            (pl.dist16 ? 1 : 0) | (pl.sig_global ? 2 : 0) | (pl.state_global ? 4 : 0),
+                            (pl.dist16 ? 1 : 0) | (pl.sig_global ? 2 : 0) | (pl.state_place << 2),
                             pl.anchored ? 1 : 0,
                             pl.mode == AMC_MODE_BLOCK ? pl.threads / 64 : pl.waves};
         for (size_t i = 0; i < variants.size(); ++i) {
@@ -375,7 +375,7 @@ struct Server {
             const hipError_t e =
                 p0.anchored ? launch_anchored(LC, p0.weighted, p0.adj_bytes, blocks, waves, lds, L.stream)
                 : p0.mode == AMC_MODE_BLOCK
-                    ? launch_sweep_block(LC, p0.weighted, p0.state_global, blocks, threads, lds, L.stream)
+                    ? launch_sweep_block(LC, p0.weighted, p0.state_place, blocks, threads, lds, L.stream)
                     : launch_sweep_wave(LC, p0.weighted, p0.mode == AMC_MODE_WAVE_L2, p0.dist16, p0.sig_global, p0.group,
                                         p0.adj_bytes, blocks, waves, lds, L.stream);
             ok = e == hipSuccess && hipEventRecord(L.end, L.stream) == hipSuccess;

@@ -19,12 +19,14 @@
 // distance is the fringe minimum (distance buckets).  The reverse pass walks
 // the equal-distance segments backwards and accumulates the dependencies of
 // the Section 3.1 betweenness into B(H_r) held in LDS; the reduction and the
-// counting are the same as in the LDS mode.  GS: the same carve-up lives in
-// the workgroup's global scratch instead of LDS (graphs whose per-source
-// state exceeds the LDS, up to 65535 vertices); all of it is read and written
-// by the one workgroup, whose global accesses a barrier orders as it does its
-// LDS accesses, so the code is the same.  Levels are ordered by degree only
-// while vertex ids fit the 13 bits that order packs them into.
+// counting are the same as in the LDS mode.  Placement PL of that state:
+// 0 in LDS; 2 in the workgroup's global scratch (graphs whose per-source
+// state exceeds the LDS, up to 65535 vertices); 1 as 2 but with the
+// distances and the realized row offsets (the most used arrays) in LDS.  All
+// of the state is read and written by the one workgroup, whose global
+// accesses a barrier orders as it does its LDS accesses, so the code is the
+// same.  Levels are ordered by degree only while vertex ids fit the 13 bits
+// that order packs them into.
 #include <type_traits>
 
 #include "amc_dev.hpp"
@@ -408,13 +410,19 @@ __device__ void block_source(const SweepParams &P, const uint32_t *rp, const ADJ
 // ADJ: the realized adjacency entry, uint32_t (weight << 16 | neighbour) or,
 // with unit weights, uint16_t (the neighbour alone), which halves the
 // per-workgroup scratch the traversal reads so that it stays in the L2.
-// Words of the per-workgroup scratch before the GS state region: the realized
-// adjacency, then the component centres (2 n words) and 64 words of slack.
+// Words of the per-workgroup scratch before the global state region: the
+// realized adjacency, then the component centres (2 n words) and 64 words of
+// slack.
 __host__ __device__ inline size_t block_gs_state_words(int n, int64_t m, uint32_t adj_bytes) {
     return (block_adj_words(m, adj_bytes) + 2 * (size_t)n + 64 + 3) & ~(size_t)3;
 }
+// Placement 1: LDS bytes of dist u32[n] | rp u32[n+1].
+__host__ __device__ inline uint32_t block_hybrid_rp(int n) { return (4u * (uint32_t)n + 15u) & ~15u; }
+__host__ __device__ inline uint32_t block_hybrid_lds(int n) {
+    return (block_hybrid_rp(n) + 4u * ((uint32_t)n + 1u) + 15u) & ~15u;
+}
 
-template <bool WEIGHTED, typename ADJ, bool GS>
+template <bool WEIGHTED, typename ADJ, int PL>
 __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ __attribute__((aligned(8))) uint32_t scan_tmp[2 * kMaxWaves];
@@ -461,16 +469,16 @@ __global__ __launch_bounds__(1024) void sweep_block_kernel(LaunchCtl LC) {
         // state region follows
         uint32_t *gs = LC.bscratch + (size_t)blockIdx.x * LC.bscratch_words;
         unsigned char *st;
-        if constexpr (GS) st = (unsigned char *)to_global(gs + block_gs_state_words(n, P.m, (uint32_t)sizeof(ADJ)));
+        if constexpr (PL != 0) st = (unsigned char *)to_global(gs + block_gs_state_words(n, P.m, (uint32_t)sizeof(ADJ)));
         else st = smem;
-        uint32_t *dist = (uint32_t *)(st + L.dist);
+        uint32_t *dist = PL == 1 ? (uint32_t *)smem : (uint32_t *)(st + L.dist);
         unsigned long long *sig = (unsigned long long *)(st + L.sig);
         uint16_t *ord = (uint16_t *)(st + L.ord);
         uint16_t *aux = (uint16_t *)(st + L.aux);
         double *B = (double *)(st + L.B);
         uint16_t *comp = (uint16_t *)(st + L.comp);
         uint16_t *csize = (uint16_t *)(st + L.csize);
-        uint32_t *rp = (uint32_t *)(st + L.rp);
+        uint32_t *rp = PL == 1 ? (uint32_t *)(smem + block_hybrid_rp(n)) : (uint32_t *)(st + L.rp);
         ADJ *adj = to_global((ADJ *)gs);
         ReduceScratch RS;
         RS.cmax = (unsigned long long *)st;                // aliases dist/sig (free during the reduction)
@@ -536,33 +544,38 @@ uint32_t lds_bytes_block(int n, int threads) {
 // Bytes at the start of the LDS that the per-edge staging may use (below rp).
 uint32_t block_staging_bytes(int n) { return block_layout(n).rp; }
 
-size_t block_scratch_words(int n, int64_t m, bool weighted, bool state_global) {
+uint32_t lds_bytes_block_hybrid(int n) { return block_hybrid_lds(n); }
+
+size_t block_scratch_words(int n, int64_t m, bool weighted, int state_place) {
     const uint32_t ab = weighted ? 4u : 2u;
-    if (!state_global) return block_adj_words(m, ab) + 2 * (size_t)n + 64;
+    if (state_place == 0) return block_adj_words(m, ab) + 2 * (size_t)n + 64;
     return block_gs_state_words(n, m, ab) + block_layout(n).total / 4;
 }
 
-template <bool GS>
+template <int PL>
 static hipError_t launch_block_t(const LaunchCtl &LC, bool weighted, int blocks, int threads, uint32_t lds,
                                  hipStream_t st) {
     if (weighted)
-        hipLaunchKernelGGL((sweep_block_kernel<true, uint32_t, GS>), dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<true, uint32_t, PL>), dim3(blocks), dim3(threads), lds, st, LC);
     else
-        hipLaunchKernelGGL((sweep_block_kernel<false, uint16_t, GS>), dim3(blocks), dim3(threads), lds, st, LC);
+        hipLaunchKernelGGL((sweep_block_kernel<false, uint16_t, PL>), dim3(blocks), dim3(threads), lds, st, LC);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, bool state_global, int blocks, int threads,
+hipError_t launch_sweep_block(const LaunchCtl &LC, bool weighted, int state_place, int blocks, int threads,
                               uint32_t lds, hipStream_t st) {
-    return state_global ? launch_block_t<true>(LC, weighted, blocks, threads, lds, st)
-                        : launch_block_t<false>(LC, weighted, blocks, threads, lds, st);
+    if (state_place == 1) return launch_block_t<1>(LC, weighted, blocks, threads, lds, st);
+    if (state_place == 2) return launch_block_t<2>(LC, weighted, blocks, threads, lds, st);
+    return launch_block_t<0>(LC, weighted, blocks, threads, lds, st);
 }
 
 hipError_t set_sweep_block_attrs(int max_lds) {
-    const void *ks[] = {(const void *)sweep_block_kernel<true, uint32_t, false>,
-                        (const void *)sweep_block_kernel<false, uint16_t, false>,
-                        (const void *)sweep_block_kernel<true, uint32_t, true>,
-                        (const void *)sweep_block_kernel<false, uint16_t, true>};
+    const void *ks[] = {(const void *)sweep_block_kernel<true, uint32_t, 0>,
+                        (const void *)sweep_block_kernel<false, uint16_t, 0>,
+                        (const void *)sweep_block_kernel<true, uint32_t, 1>,
+                        (const void *)sweep_block_kernel<false, uint16_t, 1>,
+                        (const void *)sweep_block_kernel<true, uint32_t, 2>,
+                        (const void *)sweep_block_kernel<false, uint16_t, 2>};
     for (const void *k : ks) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;

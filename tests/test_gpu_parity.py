@@ -769,7 +769,7 @@ def test_workgroup_mode_state_in_global_scratch(ctx, graph, model, extra):
     res = gpu_run(ctx, g, model, seed=5, R=R, alpha=0.15, k_min=5, flags=FLAGS | amc.STATE_GLOBAL,
                   pool=pool, **extra)
     st = res["stats"]
-    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1 and st["lds_bytes"] == 0, st
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 2 and st["lds_bytes"] == 0, st
     ref = (P if g.n >= 2000 else O).sweep(g.n, g.eu, g.ev, seed=5, R=R, alpha=0.15, k_min=5, want_next=True,
                                           pool=pool, **oracle_model(model, g))
     check_sweep(res, ref, g.n, f"{graph} state in global scratch {extra}")
@@ -780,15 +780,16 @@ def test_workgroup_mode_state_in_global_scratch(ctx, graph, model, extra):
 def test_graph_beyond_every_lds_layout_runs_with_global_state(ctx):
     # n = 9000 (unit weights): no wavefront layout and no LDS workgroup layout
     # holds it; the planner moves the workgroup mode's state to the global
-    # scratch.  One realization against the oracle (split into tiles), and
-    # sampled sources' distances, path counts and dependencies
+    # scratch, distances and row offsets staying in LDS.  One realization
+    # against the oracle (split into tiles), and sampled sources' distances,
+    # path counts and dependencies
     g = W.er_graph(9000, 8.0 / 8999, 90)
     model = {"p_fail": 0.1, "weight": "unit"}
     pairs = [(0, 0), (0, 4500), (0, 8999)]
     res = gpu_run(ctx, g, model, seed=3, R=1, alpha=0.15, k_min=5,
                   flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL, debug_pairs=pairs)
     st = res["stats"]
-    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1, st
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1 and st["lds_bytes"] > 0, st
     for k, (r, s) in enumerate(pairs):
         alive, w = O.realize(g.n, g.eu, g.ev, 3, r, **model)
         d, sg, dl = O.sssp(g.n, g.eu, g.ev, alive, w, True, s)
@@ -799,3 +800,18 @@ def test_graph_beyond_every_lds_layout_runs_with_global_state(ctx):
     say(f"[cpu] oracle on n={g.n} R=1")
     ref = O.sweep(g.n, g.eu, g.ev, seed=3, R=1, alpha=0.15, k_min=5, want_next=True, **model)
     check_sweep(res, ref, g.n, "n=9000 global state")
+
+
+def test_weighted_workgroup_mode_beyond_lds_keeps_distances_in_lds(ctx):
+    # weighted n = 6000 asked for in the workgroup mode: its 28 n bytes of
+    # state exceed the LDS, distances and row offsets (8 n) stay there; two
+    # realizations against the oracle
+    g = W.er_graph(6000, 8.0 / 5999, 60)
+    model = {"p_fail": 0.1, "weight": "uniform", "w_lo": 1, "w_hi": 10}
+    res = gpu_run(ctx, g, model, seed=4, R=2, alpha=0.15, k_min=5, mode=amc.MODE_BLOCK,
+                  flags=amc.WANT_NEXT_TABLE | amc.WANT_CENTER | amc.WANT_BSUM | amc.SKIP_TAIL)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1, st
+    say(f"[cpu] oracle on n={g.n} R=2 in {P.workers()} threads")
+    ref = P.sweep(g.n, g.eu, g.ev, seed=4, R=2, alpha=0.15, k_min=5, want_next=True, **model)
+    check_sweep(res, ref, g.n, "weighted n=6000 hybrid placement")
