@@ -815,3 +815,22 @@ def test_weighted_workgroup_mode_beyond_lds_keeps_distances_in_lds(ctx):
     say(f"[cpu] oracle on n={g.n} R=2 in {P.workers()} threads")
     ref = P.sweep(g.n, g.eu, g.ev, seed=4, R=2, alpha=0.15, k_min=5, want_next=True, **model)
     check_sweep(res, ref, g.n, "weighted n=6000 hybrid placement")
+
+
+def test_tail_at_n9000(ctx):
+    # the FP64 tail of a 9000-vertex query (N is 9000 x 9000): N inverts I - Q
+    # on sampled columns, mu = s N for the uniform s, E[T] = sum mu and
+    # b = mu / E[T], all from the returned Q and N
+    n = 9000
+    g = W.er_graph(n, 8.0 / (n - 1), 90)
+    res = gpu_run(ctx, g, {"p_fail": 0.1, "weight": "unit"}, seed=3, R=8, alpha=0.15, k_min=5, flags=amc.WANT_N)
+    st = res["stats"]
+    assert st["mode"] == amc.MODE_BLOCK and st["state_global"] == 1, st
+    Q, N, mu, b = res["Q"], res["N"], res["mu"], res["b"]
+    cols = np.random.default_rng(9).choice(n, 16, replace=False)
+    resid = N[:, cols] - Q @ N[:, cols]
+    resid[cols, np.arange(len(cols))] -= 1.0
+    assert np.abs(resid).max() <= 1e-10 * max(np.abs(N).max(), 1.0)
+    assert_close_norm(mu, np.full(n, 1.0 / n) @ N, tol=1e-10, what="mu = s N")
+    assert abs(res["E_T"] - mu.sum()) <= 1e-10 * mu.sum()
+    assert_close_norm(b, mu / mu.sum(), tol=1e-10, what="b")
