@@ -184,7 +184,7 @@ typedef struct amc_query {
 } amc_query;
 
 #define AMC_MAX_TOPK 64
-#define AMC_MAX_TOPK_N 7000
+#define AMC_MAX_TOPK_N 65535   /* the graph limit: past the LDS the stage's arrays go to global memory */
 
 /* Counters of one run.  units = R n (one (r, s) pass each); sum_nK, sum_AK and
  * sum_DK add, over every (r, s), the reached vertices |K(s;H_r)|, the surviving

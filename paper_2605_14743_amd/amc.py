@@ -22,7 +22,7 @@ MODE_AUTO, MODE_WAVE, MODE_BLOCK, MODE_WAVE_L2 = 0, 1, 2, 3
 WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LAUNCH, FALLBACK, DIST32, DIST16 = \
     1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 SIGMA_GLOBAL, STATE_GLOBAL = 1024, 2048
-MAX_TOPK, MAX_TOPK_N = 64, 7000
+MAX_TOPK, MAX_TOPK_N = 64, 65535
 MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
 MAX_W1_N = 3000
 STATIC_SCRATCH_BYTES = 64 << 20

@@ -108,6 +108,8 @@ struct TopkArgs {
     double *psi, *psi_w;        // n: step-reward sums (psi_w nullptr without a pool)
     uint32_t *counts_w;         // n x (n+1) finite-k pool selector counts, or nullptr
     int32_t *next_table_w;      // R x n or nullptr
+    unsigned char *gscr;        // per-workgroup arrays in global memory (graphs whose arrays exceed
+    uint64_t gscr_bytes;        // the LDS), else nullptr; bytes per workgroup
 };
 
 // Trajectory simulator (one workgroup per episode).

@@ -81,6 +81,9 @@ hipError_t traj_estimates(int n, int episodes, int max_steps, const int32_t *len
 // Finite-k Top-k stage and its tail pieces.
 hipError_t set_topk_attrs(int max_lds);
 uint32_t topk_lds(int n);
+// bytes per workgroup of the Top-k arrays in global memory (when topk_lds(n)
+// exceeds the LDS; TopkArgs.gscr set)
+uint64_t topk_global_bytes(int n);
 hipError_t launch_topk_reduce(const TopkArgs &A, int blocks, hipStream_t st);
 hipError_t tail_div(int n, const double *x, double d, double *y, hipStream_t st);
 hipError_t tail_reward_afc(int n, const double *mu, const double *scal, const double *psi, double *out,

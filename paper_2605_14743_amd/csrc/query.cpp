@@ -167,6 +167,16 @@ int qr_alloc(QueryRun &R, hipStream_t st) {
             RCHK(dev_copy_in(A, q->gamma, 8 * (size_t)n, st, &p));
             R.T.gamma = (double *)p;
         }
+        // the Top-k stage's workgroups: their arrays in LDS where they fit,
+        // else in global memory (two workgroups per CU)
+        const bool gm = topk_lds(n) > (uint32_t)R.ctx->max_lds;
+        const uint32_t per_cu =
+            gm ? 2u : std::max<uint32_t>(1u, (uint32_t)R.ctx->max_lds / std::max<uint32_t>(topk_lds(n), 1u));
+        R.T.topk_blocks = (int)std::min<uint64_t>(Rn, (uint64_t)R.ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
+        if (gm) {
+            RCHK(A.alloc(topk_global_bytes(n) * (size_t)R.T.topk_blocks, &p));
+            R.T.topk_gscr = (unsigned char *)p;
+        }
     }
     if (R.pl.tiles_per_r > 1 || P.keep_rows) {
         RCHK(A.alloc(8 * (size_t)Rn * n, &p)); P.Bg = (double *)p;
@@ -433,9 +443,9 @@ int qr_enqueue_post(QueryRun &R, hipStream_t st) {
     A.psi_w = R.T.psi_w;
     A.counts_w = R.cw;
     A.next_table_w = R.ntw;
-    const uint32_t per_cu = std::max<uint32_t>(1u, (uint32_t)R.ctx->max_lds / std::max<uint32_t>(topk_lds(A.n), 1u));
-    const int blocks = (int)std::min<uint64_t>(A.R, (uint64_t)R.ctx->cu_count * std::min<uint32_t>(per_cu, 8u));
-    HIPCHK(launch_topk_reduce(A, blocks, st));
+    A.gscr = R.T.topk_gscr;
+    A.gscr_bytes = topk_global_bytes(A.n);
+    HIPCHK(launch_topk_reduce(A, R.T.topk_blocks, st));
     // estimated expected step rewards: the sums over the R draws / R
     HIPCHK(tail_div(A.n, R.T.psi, (double)A.R, R.T.psi_hat, st));
     if (R.T.psi_w) HIPCHK(tail_div(A.n, R.T.psi_w, (double)A.R, R.T.psi_w_hat, st));

@@ -23,6 +23,8 @@ struct TailBufs {
     double *psi = nullptr, *psi_w = nullptr;      // sums over draws (sweep stage)
     double *gamma = nullptr;
     double *psi_hat = nullptr, *psi_w_hat = nullptr, *scal_k = nullptr;
+    unsigned char *topk_gscr = nullptr;          // Top-k stage arrays in global memory, or nullptr
+    int topk_blocks = 0;
     uint32_t *counts_fb = nullptr;
     uint8_t *fb_mask = nullptr;
     double *Qf = nullptr, *Nf = nullptr, *rf = nullptr, *muf = nullptr, *bf = nullptr, *bcens = nullptr;

@@ -36,9 +36,15 @@ __host__ __device__ inline uint32_t topk_lds_total(int n) {
     return n <= kTopkAccMaxN ? topk_acc_offset(n) + 16u * (uint32_t)n : topk_lds_bytes(n);
 }
 
-template <bool ACC>
+// GM: the carve-up lives in a per-workgroup global array instead of LDS
+// (graphs whose arrays exceed the LDS); the workgroup alone reads and writes
+// it, and a barrier orders its global accesses as it does its LDS ones.
+template <bool ACC, bool GM>
 __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    static_assert(!(ACC && GM), "the LDS step-reward sums go with the LDS carve-up");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_base[];
+    unsigned char *smem = lds_base;
+    if constexpr (GM) smem = (unsigned char *)to_global(A.gscr + (size_t)blockIdx.x * A.gscr_bytes);
     const int n = A.n, tid = threadIdx.x, nt = blockDim.x;
     double *lpsi = ACC ? (double *)(smem + topk_acc_offset(n)) : nullptr;
     double *lpsiw = ACC ? lpsi + n : nullptr;
@@ -195,19 +201,26 @@ __global__ void k_censor(int n, const double *b, const uint8_t *fb_mask, double 
 
 // ---------------------------------------------------------------------------
 hipError_t set_topk_attrs(int max_lds) {
-    const hipError_t e =
-        hipFuncSetAttribute((const void *)k_topk_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_topk_reduce<false>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    const void *ks[] = {(const void *)k_topk_reduce<true, false>, (const void *)k_topk_reduce<false, false>,
+                        (const void *)k_topk_reduce<false, true>};
+    for (const void *k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 uint32_t topk_lds(int n) { return topk_lds_total(n); }
 
+uint64_t topk_global_bytes(int n) { return ((uint64_t)topk_lds_bytes(n) + 255u) & ~255ull; }
+
 hipError_t launch_topk_reduce(const TopkArgs &A, int blocks, hipStream_t st) {
-    if (A.n <= kTopkAccMaxN)
-        hipLaunchKernelGGL(k_topk_reduce<true>, dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
+    if (A.gscr)
+        hipLaunchKernelGGL((k_topk_reduce<false, true>), dim3(blocks), dim3(256), 0, st, A);
+    else if (A.n <= kTopkAccMaxN)
+        hipLaunchKernelGGL((k_topk_reduce<true, false>), dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
     else
-        hipLaunchKernelGGL(k_topk_reduce<false>, dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
+        hipLaunchKernelGGL((k_topk_reduce<false, false>), dim3(blocks), dim3(256), topk_lds_total(A.n), st, A);
     return hipGetLastError();
 }
 

@@ -180,9 +180,18 @@ def test_topk_invalid_arguments(ctx):
             amc.run(ctx, G, {"p_fail": 0.1}, R=4, **bad)
         assert ei.value.rc == amc.E_INVALID_ARG, bad
     G.close()
-    big = W.er_graph(amc.MAX_TOPK_N + 1, 4.0 / amc.MAX_TOPK_N, 2)
-    H = amc.Graph(ctx, big.n, big.eu, big.ev)
-    with pytest.raises(amc.AmcError) as ei:
-        amc.run(ctx, H, {"p_fail": 0.1}, R=1, topk=2, flags=amc.SKIP_TAIL)
-    assert ei.value.rc == amc.E_UNSUPPORTED
-    H.close()
+
+
+def test_topk_beyond_the_lds(ctx):
+    # n = 9000: the Top-k stage's arrays (21 n bytes) exceed the LDS and live
+    # in global memory per workgroup (the sweep itself runs with its state in
+    # the scratch, distances and row offsets in LDS); one realization against
+    # the oracle
+    g = W.er_graph(9000, 8.0 / 8999, 91)
+    pool = np.arange(5, g.n, 97)
+    gamma = 0.5 + 1.5 * np.random.default_rng(6).random(g.n)
+    res, ref = run_both(ctx, g, {"p_fail": 0.1, "weight": "unit"}, 1, topk=4, pool=pool, gamma=gamma, seed=2,
+                        tail=False)
+    assert res["stats"]["state_global"] == 1, res["stats"]
+    check(res, ref, 1, "n=9000 global Top-k arrays")
+    assert np.array_equal(res["counts"], ref["counts"])
