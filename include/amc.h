@@ -418,7 +418,7 @@ AMC_API int amc_trajectories(amc_ctx *ctx, const amc_graph *g, const amc_model *
  * for n > AMC_MAX_W1_N with a topology, or when the W1 solver exceeds its
  * iteration bounds; AMC_E_SINGULAR, AMC_E_OOM, AMC_E_HIP as for amc_run.
  * Output arrays are caller-owned host buffers (NULL = skip). */
-#define AMC_MAX_W1_N 3000
+#define AMC_MAX_W1_N 7500
 typedef struct amc_robust_query {
     const double *s;            /* initial distribution (n) or NULL for uniform  */
     const double *f;            /* node values (n, >= 0) or NULL (no transition rewards) */

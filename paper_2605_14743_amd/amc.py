@@ -24,7 +24,7 @@ WANT_N, WANT_BSUM, WANT_NEXT_TABLE, WANT_CENTER, WANT_DEBUG, SKIP_TAIL, PLAIN_LA
 SIGMA_GLOBAL, STATE_GLOBAL = 1024, 2048
 MAX_TOPK, MAX_TOPK_N = 64, 65535
 MAX_BOOT_REPLICATES, MAX_BOOT_N = 4096, 16383
-MAX_W1_N = 3000
+MAX_W1_N = 7500
 STATIC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = ["amc_ctx_create", "amc_ctx_destroy", "amc_ctx_set_stream", "amc_ctx_stream", "amc_graph_create",

@@ -15,6 +15,10 @@
 
 using namespace amc;
 
+namespace amc {
+hipError_t set_w1_attrs(int max_lds);   // w1.hip
+}
+
 #define HIPCHK(expr)                          \
     do {                                      \
         if ((expr) != hipSuccess) {           \
@@ -62,7 +66,7 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
     std::vector<int32_t> rp, inc;
     if (q->m < 0 || (want_w1 && (!q->eu || !q->ev || m > 0x7FFFFFFF))) return AMC_E_INVALID_ARG;
     if (want_w1) {
-        if (n > AMC_MAX_W1_N) return AMC_E_UNSUPPORTED;
+        if (n > AMC_MAX_W1_N || w1_lds_bytes(n) > (size_t)ctx->max_lds) return AMC_E_UNSUPPORTED;
         for (int64_t e = 0; e < m; ++e) {
             const int32_t a = q->eu[e], b = q->ev[e];
             if (a < 0 || b >= n || a >= b) return AMC_E_INVALID_ARG;
@@ -201,6 +205,7 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
         HIPCHK(robust_normalize_rows(n, nb, mub, brows + (size_t)k0 * n, st));
         HIPCHK(robust_divergence(n, nb, brows + (size_t)k0 * n, b0, kl + k0, tv + k0, st));
     }
+    if (w1_on) HIPCHK(set_w1_attrs(ctx->max_lds));
     for (int k0 = 0; w1_on && k0 < S; k0 += Wt) {
         const int nb = std::min(Wt, S - k0);
         HIPCHK(robust_w1(n, (int)m, deu, dev_, dlen, drp, dinc, nb, brows + (size_t)k0 * n, b0, fscr, w1 + k0, err,

@@ -41,7 +41,8 @@ namespace {
 
 constexpr int kW1Threads = 256;
 constexpr uint64_t kNoLabel = ~0ull;
-// distances of simple walks stay within (n - 1) * 65535 < 2^31 for n <= 3000
+// distances of simple walks stay within (n - 1) * 65535 < 2^31 (n <= 32768;
+// the LDS arrays of 21 n bytes bound n well below that)
 constexpr uint64_t kDistBias = 1ull << 31;
 
 __device__ __forceinline__ uint64_t w1_label(int64_t dist, uint32_t hops) {
@@ -285,6 +286,18 @@ __global__ __launch_bounds__(kW1Threads) void k_w1(int n, int m, const int32_t *
 }
 
 size_t w1_lds_bytes(int n) { return 20 * (size_t)n + (((size_t)n + 3) & ~(size_t)3); }
+
+// The solver's LDS arrays may use the device's whole LDS (past the default
+// 64 KB of dynamic LDS).
+hipError_t set_w1_attrs(int max_lds) {
+    const void *ks[] = {(const void *)k_w1<true, true>, (const void *)k_w1<true, false>,
+                        (const void *)k_w1<false, true>, (const void *)k_w1<false, false>};
+    for (const void *kf : ks) {
+        const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t robust_w1(int n, int m, const int32_t *eu, const int32_t *ev, const uint32_t *len, const int32_t *rp,
                      const int32_t *inc, int batch, const double *P, const double *q, double *fscr, double *w1, int *err,

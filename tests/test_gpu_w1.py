@@ -207,6 +207,32 @@ def test_weighted_path_closed_form(ctx, n):
     assert g["w1"][k] == pytest.approx(expect, rel=1e-10)
 
 
+@pytest.mark.parametrize("n,weighted", [(3500, True), (6000, True), (amc.MAX_W1_N, False)])
+def test_tree_closed_form_past_64k_lds(ctx, n, weighted):
+    # on a tree every edge carries the net mass of the subtree below it, so
+    # W1 = sum over edges of w_e |sum of p - q over that subtree|; from n = 3500
+    # on the solver's node arrays alone take more than 64 KB of LDS
+    rng = np.random.default_rng(n)
+    par = np.array([int(rng.integers(0, v)) for v in range(1, n)], np.int64)   # random recursive tree
+    order = np.lexsort((np.arange(1, n), par))
+    eu = par[order].astype(np.int32)
+    ev = np.arange(1, n, dtype=np.int32)[order]
+    w = rng.integers(1, 1000, n - 1).astype(np.uint32) if weighted else np.ones(n - 1, np.uint32)
+    Q0 = random_kernel(n, 12, density=0.004)
+    say(f"[gpu] robust w1 on a random tree of {n} vertices, weighted={weighted}")
+    topo = (eu, ev, w) if weighted else (eu, ev)
+    g = amc.robust(ctx, Q0, samples=3, delta=0.5, r_min=0.05, seed=7, topology=topo)
+    k = g["w1_arg"]
+    sub = g["b_w1"] - g["b0"]
+    for v in range(n - 1, 0, -1):          # parents precede their children
+        sub[par[v - 1]] += sub[v]
+    wv = np.empty(n)
+    wv[ev] = w
+    expect = (wv[1:] * np.abs(sub[1:])).sum()
+    assert g["w1"][k] == pytest.approx(expect, rel=1e-10)
+    assert np.all(g["w1"] >= g["tv"] * (1 - 1e-12))
+
+
 def test_cooc77_fixed_weights(ctx):
     # the 77-node weighted co-occurrence stand-in with its own fixed weights as
     # the ground metric, on the kernel estimated from its run
