@@ -135,13 +135,24 @@ __global__ void k_gather_row(int n, const double *rows, const int *idx, double *
     if (j < n) dst[j] = rows[(size_t)(*idx) * n + j];
 }
 
-// y = x M (row vector times matrix), one thread per column.
-__global__ void k_vecmat(int n, const double *x, const double *M, double *y) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// y = x M (row vector times matrix).  A workgroup per 64 columns, lane = column: each of its kVecWaves
+// wavefronts sums every kVecWaves-th row in order and the partial sums are
+// added in wavefront order.
+constexpr int kVecWaves = 16;
+__global__ __launch_bounds__(64 * kVecWaves) void k_vecmat(int n, const double *x, const double *M, double *y) {
+    __shared__ double part[kVecWaves][64];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc += x[i] * M[(size_t)i * n + j];
-    y[j] = acc;
+    if (j < n)
+        for (int i = wave; i < n; i += kVecWaves) acc += x[i] * M[(size_t)i * n + j];
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && j < n) {
+        double t = 0.0;
+        for (int w = 0; w < kVecWaves; ++w) t += part[w][lane];
+        y[j] = t;
+    }
 }
 
 // b_lin = b0 + v / (mu0 1) - b0 (v 1) / (mu0 1)  (single workgroup).
@@ -307,7 +318,7 @@ hipError_t robust_gather_row(int n, const double *rows, const int *idx, double *
 }
 
 hipError_t robust_vecmat(int n, const double *x, const double *M, double *y, hipStream_t st) {
-    hipLaunchKernelGGL(k_vecmat, dim3((n + 255) / 256), dim3(256), 0, st, n, x, M, y);
+    hipLaunchKernelGGL(k_vecmat, dim3((n + 63) / 64), dim3(64 * kVecWaves), 0, st, n, x, M, y);
     return hipGetLastError();
 }
 

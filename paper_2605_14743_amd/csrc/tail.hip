@@ -127,14 +127,22 @@ __global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
         X[i][j] = (i < kb && c < n) ? A[(size_t)(k0 + i) * n + c] : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < NB * PT; t += blockDim.x) {
-        const int i = t / PT, j = t % PT;
-        const int c = j0 + j;
-        if (i >= kb || c >= n || (c >= k0 && c < k0 + kb)) continue;
-        double acc = 0.0;
-        for (int p = 0; p < kb; ++p) acc += Dv[i][p] * X[p][j];
-        A[(size_t)(k0 + i) * n + c] = acc;
+    // thread (ty, tx): column tx, rows ty + RS q; X[p][tx] read once per p
+    constexpr int RS = 256 / PT, RQ = NB / RS;
+    const int tx = (int)threadIdx.x % PT, ty = (int)threadIdx.x / PT;
+    double acc[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
+    for (int p = 0; p < kb; ++p) {
+        const double xv = X[p][tx];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) acc[q] += Dv[ty + RS * q][p] * xv;
     }
+    const int c = j0 + tx;
+    if (c >= n || (c >= k0 && c < k0 + kb)) return;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (ty + RS * q < kb) A[(size_t)(k0 + ty + RS * q) * n + c] = acc[q];
 }
 
 // (c) trailing update A[i, j] -= A[i, k] A[k, j] for i, j outside the block
@@ -158,6 +166,18 @@ __global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+    // the lane's entries of the output tile are loaded first, so that their
+    // latency overlaps the panel staging and the products
+    double old[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + rw + 16 * a + 4 * r + lk, j = j0 + cw + 16 * b + li;
+                old[a][b][r] = (i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
+            }
     for (int c0 = 0; c0 < kb; c0 += KC) {
         const int kc = min(KC, kb - c0);
         if (c0 > 0) __syncthreads();   // the previous slice is consumed
@@ -192,7 +212,7 @@ __global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + rw + 16 * a + 4 * r + lk, j = j0 + cw + 16 * b + li;
                 if (i >= n || j >= n || (i >= k0 && i < k0 + kb) || (j >= k0 && j < k0 + kb)) continue;
-                A[(size_t)i * n + j] -= acc[a][b][r];
+                A[(size_t)i * n + j] = old[a][b][r] - acc[a][b][r];
             }
 }
 
@@ -213,26 +233,47 @@ __global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
         X[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < PT * NB; t += blockDim.x) {
-        const int i = t / NB, j = t % NB;
-        const int row = i0 + i;
-        if (row >= n || j >= kb || (row >= k0 && row < k0 + kb)) continue;
-        double acc = 0.0;
-        for (int p = 0; p < kb; ++p) acc += X[i][p] * Dv[p][j];
-        A[(size_t)row * n + k0 + j] = -acc;
+    // thread (ty, tx): column tx, rows ty + RS q; Dv[p][tx] read once per p
+    constexpr int RS = 256 / NB, RQ = PT / RS;
+    const int tx = (int)threadIdx.x % NB, ty = (int)threadIdx.x / NB;
+    double acc[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
+    for (int p = 0; p < kb; ++p) {
+        const double dv = Dv[p][tx];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) acc[q] += X[ty + RS * q][p] * dv;
+    }
+    if (tx >= kb) return;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int row = i0 + ty + RS * q;
+        if (row < n && (row < k0 || row >= k0 + kb)) A[(size_t)row * n + k0 + tx] = -acc[q];
     }
 }
 
-// mu = s N (eq. visits): one thread per column, rows summed in order; a
+// mu = s N (eq. visits): a workgroup per 64 columns, lane = column; its
+// kVisitWaves wavefronts each sum every kVisitWaves-th row in order, and the
+// partial sums are added in wavefront order (a fixed summation order); a
 // batch of matrices N + y * stride gives mu + y * n, y = blockIdx.y.
-__global__ void k_visits(int n, const double *N, const double *s, double *mu, size_t stride) {
+constexpr int kVisitWaves = 16;
+__global__ __launch_bounds__(64 * kVisitWaves) void k_visits(int n, const double *N, const double *s, double *mu,
+                                                            size_t stride) {
+    __shared__ double part[kVisitWaves][64];
     N += (size_t)blockIdx.y * stride;
     mu += (size_t)blockIdx.y * n;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc += s[i] * N[(size_t)i * n + j];
-    mu[j] = acc;
+    if (j < n)
+        for (int i = wave; i < n; i += kVisitWaves) acc += s[i] * N[(size_t)i * n + j];
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && j < n) {
+        double t = 0.0;
+        for (int w = 0; w < kVisitWaves; ++w) t += part[w][lane];
+        mu[j] = t;
+    }
 }
 
 // Single-workgroup reductions: E_s[T] = mu 1, b = mu / E_s[T], b . f, pool mass,
@@ -451,14 +492,14 @@ hipError_t tail_invert(int n, double *A, int *err, hipStream_t st) {
 
 hipError_t tail_visits_batched(int n, const double *N, size_t stride, int batch, const double *s, double *mu,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256, batch), dim3(256), 0, st, n, N, s, mu, stride);
+    hipLaunchKernelGGL(k_visits, dim3((n + 63) / 64, batch), dim3(64 * kVisitWaves), 0, st, n, N, s, mu, stride);
     return hipGetLastError();
 }
 
 hipError_t tail_visits(int n, const double *N, const double *s, double *mu, double *b, const double *f,
                        const uint8_t *pool, double *b_bar, const double *r, double r_lower, int topk, int32_t *top,
                        double *scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_visits, dim3((n + 255) / 256), dim3(256), 0, st, n, N, s, mu, (size_t)0);
+    hipLaunchKernelGGL(k_visits, dim3((n + 63) / 64), dim3(64 * kVisitWaves), 0, st, n, N, s, mu, (size_t)0);
     hipLaunchKernelGGL(k_afc, dim3(1), dim3(1024), 0, st, n, mu, b, f, pool, b_bar, r, r_lower, topk, top, scal);
     return hipGetLastError();
 }
