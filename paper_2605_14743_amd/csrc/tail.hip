@@ -152,12 +152,26 @@ __global__ void k_gj_rowpanel(int n, double *A, size_t stride, int k0) {
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 product and holds
 // D[4 r + l / 16][l % 16] in item r), the panel staged KC columns at a time.
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t stride, int k0) {
-    A += (size_t)blockIdx.z * stride;
+// Workgroups are dispatched to the XCDs in turn (linear id mod 8): for the
+// first batch - batch % 8 matrices every tile of a matrix goes to one XCD, so
+// that its panels are fetched into one L2 only; the rest follow in order.
+__global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t stride, int k0, int batch) {
+    const uint32_t tiles = (uint32_t)(n + TT - 1) / TT, T = tiles * tiles, L = blockIdx.x;
+    const uint32_t grouped = T * ((uint32_t)batch & ~7u);
+    uint32_t z, t;
+    if (L < grouped) {
+        const uint32_t slot = L >> 3;
+        z = (slot / T) * 8u + (L & 7u);
+        t = slot % T;
+    } else {
+        z = ((uint32_t)batch & ~7u) + (L - grouped) / T;
+        t = (L - grouped) % T;
+    }
+    A += (size_t)z * stride;
     __shared__ double Ap[TT][KC + 1];
     __shared__ double Bp[KC][TT + 1];
     const int kb = min(NB, n - k0);
-    const int i0 = blockIdx.y * TT, j0 = blockIdx.x * TT;
+    const int i0 = (int)(t / tiles) * TT, j0 = (int)(t % tiles) * TT;
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int rw = (wave >> 1) * 32, cw = (wave & 1) * 32;     // the wavefront's quadrant
     const int li = lane & 15, lk = lane >> 4;
@@ -480,7 +494,8 @@ hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *
     for (int k0 = 0; k0 < n; k0 += NB) {
         hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, k0, err);
         hipLaunchKernelGGL(k_gj_rowpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
-        hipLaunchKernelGGL(k_gj_update_mfma, dim3(tiles, tiles, batch), dim3(256), 0, st, n, A, stride, k0);
+        hipLaunchKernelGGL(k_gj_update_mfma, dim3((unsigned)((size_t)tiles * tiles * batch)), dim3(256), 0, st, n, A,
+                           stride, k0, batch);
         hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
     return hipGetLastError();
