@@ -20,6 +20,12 @@ namespace amc {
 
 constexpr uint32_t kBootStream = 0x80000004u;
 
+// u32 words before the staged row in k_boot_rows' LDS (the counts, n + 1,
+// rounded up to 16 bytes), and the largest LDS it stages within (the default
+// dynamic LDS of a launch).
+__host__ __device__ inline uint32_t boot_stage_offset(int n) { return ((uint32_t)n + 1u + 3u) & ~3u; }
+constexpr size_t kBootStageMaxLds = 65536;
+
 // next table R x n (int32, -1 = bottom) -> row-major n x R (uint16, next + 1,
 // 0 = bottom), so that every row's R outcomes are contiguous.  32 x 32 tiles
 // through LDS keep both sides coalesced.
@@ -41,17 +47,25 @@ __global__ void k_boot_transpose(int n, uint32_t R, const int32_t *nt, uint16_t 
 // Workgroup (i, z): counts of row i in replicate beta0 + z (or of the draws
 // themselves when ident), then row i of A_z = I - Q* with the floor rule of the
 // estimated kernel (a row that never absorbed gets P_i,bottom = eta and its
-// transient part scaled by 1 - eta, when eta > 0).
+// transient part scaled by 1 - eta, when eta > 0).  STAGE: the row's R
+// outcomes are first copied to LDS (coalesced), so that the random draws
+// gather from LDS instead of touching a cache line per lane.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_boot_rows(int n, uint32_t R, const uint16_t *tr, uint64_t seed,
                                                    uint32_t beta0, int ident, double eta, double *A,
                                                    size_t stride) {
-    extern __shared__ uint32_t cnt[];   // n + 1 (index n = bottom)
+    extern __shared__ uint32_t cnt[];   // n + 1 (index n = bottom), then (STAGE) the row's R outcomes
     const int i = blockIdx.x;
     const uint32_t beta = beta0 + blockIdx.y;
     A += (size_t)blockIdx.y * stride + (size_t)i * n;
     for (int j = threadIdx.x; j <= n; j += blockDim.x) cnt[j] = 0u;
-    __syncthreads();
     const uint16_t *row = tr + (size_t)i * R;
+    if constexpr (STAGE) {
+        uint16_t *lrow = (uint16_t *)(cnt + boot_stage_offset(n));
+        for (uint32_t t = threadIdx.x; t < R; t += blockDim.x) lrow[t] = row[t];
+        row = lrow;
+    }
+    __syncthreads();
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (ident) {
         for (uint32_t t = threadIdx.x; t < R; t += blockDim.x) {
@@ -147,9 +161,13 @@ hipError_t boot_transpose(int n, uint32_t R, const int32_t *nt, uint16_t *tr, hi
 
 hipError_t boot_rows(int n, uint32_t R, const uint16_t *tr, uint64_t seed, uint32_t beta0, int batch, bool ident,
                      double eta, double *A, size_t stride, hipStream_t st) {
-    const size_t lds = 4 * ((size_t)n + 1);
-    hipLaunchKernelGGL(k_boot_rows, dim3(n, batch), dim3(256), lds, st, n, R, tr, seed, beta0, ident ? 1 : 0, eta, A,
-                       stride);
+    const size_t staged = 4 * (size_t)boot_stage_offset(n) + 2 * (size_t)R;
+    if (!ident && staged <= kBootStageMaxLds)
+        hipLaunchKernelGGL(k_boot_rows<true>, dim3(n, batch), dim3(256), staged, st, n, R, tr, seed, beta0, 0, eta, A,
+                           stride);
+    else
+        hipLaunchKernelGGL(k_boot_rows<false>, dim3(n, batch), dim3(256), 4 * ((size_t)n + 1), st, n, R, tr, seed,
+                           beta0, ident ? 1 : 0, eta, A, stride);
     return hipGetLastError();
 }
 
