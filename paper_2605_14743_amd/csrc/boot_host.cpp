@@ -69,8 +69,8 @@ extern "C" int amc_bootstrap(amc_ctx *ctx, int32_t n, uint32_t R, const int32_t 
         }
     } guard{A, st};
     const size_t nn = (size_t)n * n;
-    // replicates are inverted in groups of up to 64 (at most 1 GiB of matrices)
-    int Bt = std::min(B, 64);
+    // replicates are inverted in groups of up to 128 (at most 1 GiB of matrices)
+    int Bt = std::min(B, 128);
     while (Bt > 1 && (size_t)Bt * nn * 8 > (size_t(1) << 30)) Bt /= 2;
     void *p;
     auto alloc = [&](size_t bytes) -> void * { return A.alloc(bytes, &p) == AMC_OK ? p : nullptr; };

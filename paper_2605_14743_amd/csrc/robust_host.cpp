@@ -131,8 +131,8 @@ extern "C" int amc_robust(amc_ctx *ctx, int32_t n, const double *Q0, const amc_r
     double *blin = (double *)alloc(8 * (size_t)n), *bkl = (double *)alloc(8 * (size_t)n), *btv = (double *)alloc(8 * (size_t)n);
     double *scal = (double *)alloc(8 * 8), *rsc = (double *)alloc(8 * 8);
     double *brows = (double *)alloc(8 * (size_t)std::max(S, 1) * n);
-    // sampled kernels are inverted in groups of up to 64 (at most 1 GiB of matrices)
-    int Bt = std::max(1, std::min(S, 64));
+    // sampled kernels are inverted in groups of up to 128 (at most 1 GiB of matrices)
+    int Bt = std::max(1, std::min(S, 128));
     while (Bt > 1 && (size_t)Bt * nn * 8 > (size_t(1) << 30)) Bt /= 2;
     double *Wb = S > 0 ? (double *)alloc(8 * nn * (size_t)Bt) : nullptr;
     double *mub = S > 0 ? (double *)alloc(8 * (size_t)n * Bt) : nullptr;
