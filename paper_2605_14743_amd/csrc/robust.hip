@@ -201,44 +201,58 @@ __global__ void k_rowabs(int n, const double *A, unsigned long long *out) {
     if (tid == 0) atomicMax(out, as_u64(red[0]));
 }
 
-// C = A B for n x n row-major FP64 matrices: 64 x 64 output tile per
-// workgroup of 256 threads (4 x 4 per thread), K in steps of 16 through LDS.
+// C = A B for n x n row-major FP64 matrices on the FP64 matrix cores: a
+// 64 x 64 output tile per workgroup of 256 threads, each wavefront a 32 x 32
+// quadrant as 2 x 2 blocks of v_mfma_f64_16x16x4 (lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 product and
+// holds D[4 r + l / 16][l % 16] in item r), K staged 32 at a time through LDS
+// (zero past n, so a partial last step is exact).
+typedef double gemm_f64x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_gemm(int n, const double *A, const double *B, double *C) {
-    __shared__ double As[64][17];
-    __shared__ double Bs[16][65];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        for (int t = threadIdx.x; t < 64 * 16; t += 256) {
-            const int r = t / 16, c = t % 16;
+    constexpr int GT = 64, GK = 32;
+    __shared__ double As[GT][GK + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int rw = (wave >> 1) * 32, cw = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    gemm_f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = gemm_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += GK) {
+        if (k0 > 0) __syncthreads();   // the previous slice is consumed
+        for (int t = threadIdx.x; t < GT * GK; t += blockDim.x) {
+            const int r = t / GK, c = t % GK;
             As[r][c] = (i0 + r < n && k0 + c < n) ? A[(size_t)(i0 + r) * n + k0 + c] : 0.0;
-            const int r2 = t / 64, c2 = t % 64;
+            const int r2 = t / GT, c2 = t % GT;
             Bs[r2][c2] = (k0 + r2 < n && j0 + c2 < n) ? B[(size_t)(k0 + r2) * n + j0 + c2] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            double a[4], b[4];
+        for (int p = 0; p < GK; p += 4) {
+            double af[2], bf[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[ty + 16 * q][k];
-                b[q] = Bs[k][tx + 16 * q];
-            }
+            for (int a = 0; a < 2; ++a) af[a] = As[rw + 16 * a + li][p + lk];
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[p + lk][cw + 16 * b + li];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + ty + 16 * p, j = j0 + tx + 16 * q;
-            if (i < n && j < n) C[(size_t)i * n + j] = acc[p][q];
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + rw + 16 * a + 4 * r + lk, j = j0 + cw + 16 * b + li;
+                if (i < n && j < n) C[(size_t)i * n + j] = acc[a][b][r];
+            }
 }
 
 // Transition rewards per row: switching sum_{j != i} Q_ij, improvement
