@@ -39,7 +39,7 @@ namespace amc {
 
 namespace {
 
-constexpr int kW1Threads = 256;
+constexpr int kW1Threads = 1024;
 constexpr uint64_t kNoLabel = ~0ull;
 // distances of simple walks stay within (n - 1) * 65535 < 2^31 (n <= 32768;
 // the LDS arrays of 21 n bytes bound n well below that)
