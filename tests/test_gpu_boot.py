@@ -69,10 +69,12 @@ def compare(g, o, what):
 
 
 @pytest.mark.parametrize("n,R,B,level", [(1, 5, 3, 0.9), (12, 300, 40, 0.9), (70, 301, 70, 0.95),
-                                         (33, 64, 1, 0.5), (130, 1001, 129, 0.8)])
+                                         (33, 64, 1, 0.5), (130, 1001, 129, 0.8), (20, 40001, 6, 0.9)])
 def test_random_tables(ctx, n, R, B, level):
     # several 32 x 32 transpose tiles with ragged edges, R not a multiple of 4,
-    # B past one group of 64 matrices, B = 1
+    # B past one group of 128 matrices, B = 1; R = 40001: a row's outcomes
+    # (2 R bytes) no longer fit the LDS next to the counts, so the redraw
+    # gathers from the cache
     nt = draws_from_kernel(random_kernel(n, n), R, R)
     say(f"[gpu] bootstrap n={n} R={R} B={B} level={level}")
     g = amc.bootstrap(ctx, nt, replicates=B, level=level, seed=n + R)
