@@ -81,26 +81,30 @@ __global__ __launch_bounds__(kDiagThreads) void k_gj_diag(int n, double *A, size
         M[ii[r]][jj[r]] = x[r];
     }
     __syncthreads();
+    // a thread's entries share one column (kDiagThreads is a multiple of NB),
+    // so the pivot row is read and scaled once per step
+    static_assert(kDiagThreads % NB == 0, "one column per thread");
+    const int jc = jj[0];
     for (int p = 0; p < kb; ++p) {
         const double piv = M[p][p];
-        double row[PER], col[PER];
+        const double rowv = M[p][jc];
+        double col[PER];
 #pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            row[r] = M[p][jj[r]];
-            col[r] = M[ii[r]][p];
-        }
+        for (int r = 0; r < PER; ++r) col[r] = M[ii[r]][p];
         __syncthreads();   // every read of step p is done before its writes
         if (piv == 0.0) {
             if (threadIdx.x == 0) atomicOr(err, 2);
             return;
         }
         const double d = 1.0 / piv;
+        const double rowd = rowv * d;
+        const bool pc = jc == p;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            if (ii[r] == p) x[r] = jj[r] == p ? d : row[r] * d;   // pivot row scaled, pivot replaced by its inverse
-            else if (jj[r] == p) x[r] = -col[r] * d;             // pivot column
-            else x[r] -= col[r] * (row[r] * d);                  // the rest, against the scaled pivot row
-            M[ii[r]][jj[r]] = x[r];
+            if (ii[r] == p) x[r] = pc ? d : rowd;    // pivot row scaled, pivot replaced by its inverse
+            else if (pc) x[r] = -col[r] * d;         // pivot column
+            else x[r] -= col[r] * rowd;              // the rest, against the scaled pivot row
+            M[ii[r]][jc] = x[r];
         }
         __syncthreads();
     }
