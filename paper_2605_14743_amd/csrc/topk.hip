@@ -36,6 +36,9 @@ __host__ __device__ inline uint32_t topk_lds_total(int n) {
     return n <= kTopkAccMaxN ? topk_acc_offset(n) + 16u * (uint32_t)n : topk_lds_bytes(n);
 }
 
+// Anchors per thread whose selector counts are kept as runs in registers.
+constexpr int kRunSlots = 4;
+
 // GM: the carve-up lives in a per-workgroup global array instead of LDS
 // (graphs whose arrays exceed the LDS); the workgroup alone reads and writes
 // it, and a barrier orders its global accesses as it does its LDS ones.
@@ -61,6 +64,14 @@ __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
     uint32_t *wsel = cband;                               // aliases cband after the ranking
     uint8_t *rank = smem + 20 * (size_t)n;
 
+    // selector counts of the thread's first kRunSlots anchors, as runs of
+    // equal selections over the workgroup's realizations (one atomic per run)
+    uint32_t run_col[kRunSlots], run_len[kRunSlots];
+#pragma unroll
+    for (int q = 0; q < kRunSlots; ++q) {
+        run_col[q] = 0u;
+        run_len[q] = 0u;
+    }
     for (uint32_t rl = blockIdx.x; rl < A.R; rl += gridDim.x) {
         const double *B = A.Bg + (size_t)rl * n;
         const int32_t *comp = A.compg + (size_t)rl * n;
@@ -110,14 +121,15 @@ __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
             }
         }
         __syncthreads();
-        for (int i = tid; i < n; i += nt) {
+        // anchor i is always this thread's (a fixed stride over the anchors):
+        // the LDS sums need no atomics, and the first kRunSlots anchors of
+        // the thread keep their selector count as a run in registers
+        auto anchor = [&](int i, uint32_t *run_col, uint32_t *run_len) {
             const int c = comp[i];
             const u32x4 x = philox10({r, (uint32_t)i, 0xFFFFFFFFu, 1u}, A.key0, A.key1);
             const bool coin = (uint64_t)x.x < A.t_alpha;
             const bool valid = !coin && (uint32_t)csize[i] >= A.k_min;
             if (valid) {
-                // anchor i is always this thread's (a fixed stride over the
-                // anchors), so the LDS sums need no atomics
                 if constexpr (ACC) {
                     lpsi[i] += gsum[c];
                     lpsiw[i] += gsumw[c];
@@ -128,11 +140,30 @@ __global__ __launch_bounds__(256) void k_topk_reduce(TopkArgs A) {
             }
             if (A.counts_w) {
                 const int nw = (valid && wsel[c] != kNone) ? (int)(wsel[c] & 0xFFFFu) : -1;
-                atomicAdd(&A.counts_w[(size_t)i * (n + 1) + (nw >= 0 ? nw : n)], 1u);
+                const uint32_t col = nw >= 0 ? (uint32_t)nw : (uint32_t)n;
+                if (run_col) {
+                    if (*run_len > 0u && *run_col != col)
+                        atomicAdd(&A.counts_w[(size_t)i * (n + 1) + *run_col], *run_len);
+                    *run_len = *run_col == col ? *run_len + 1u : 1u;
+                    *run_col = col;
+                } else {
+                    atomicAdd(&A.counts_w[(size_t)i * (n + 1) + col], 1u);
+                }
                 if (A.next_table_w) A.next_table_w[(size_t)rl * n + i] = nw;
             }
-        }
+        };
+#pragma unroll
+        for (int q = 0; q < kRunSlots; ++q)
+            if (tid + q * nt < n) anchor(tid + q * nt, &run_col[q], &run_len[q]);
+        for (int i = tid + kRunSlots * nt; i < n; i += nt) anchor(i, nullptr, nullptr);
         __syncthreads();
+    }
+    if (A.counts_w) {
+#pragma unroll
+        for (int q = 0; q < kRunSlots; ++q) {
+            const int i = tid + q * nt;
+            if (i < n && run_len[q] > 0u) atomicAdd(&A.counts_w[(size_t)i * (n + 1) + run_col[q]], run_len[q]);
+        }
     }
     if constexpr (ACC) {
         for (int i = tid; i < n; i += nt) {
