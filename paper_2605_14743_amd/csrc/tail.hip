@@ -64,10 +64,8 @@ __global__ void k_from_Q(int n, const double *Q, double *r, double *A) {
 // Gauss-Jordan without pivoting); flags a zero pivot.  Each thread holds
 // NB * NB / kDiagThreads entries of the block (padded with the identity,
 // which every pivot step leaves unchanged) in registers across the pivots.
-__global__ __launch_bounds__(kDiagThreads) void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+__device__ __forceinline__ void gj_diag_body(int n, double *A, int k0, int *err, double (*M)[NB + 1]) {
     constexpr int PER = NB * NB / kDiagThreads;
-    A += (size_t)blockIdx.z * stride;
-    __shared__ double M[NB][NB + 1];
     const int kb = min(NB, n - k0);
     int ii[PER], jj[PER];
     double x[PER];
@@ -111,6 +109,10 @@ __global__ __launch_bounds__(kDiagThreads) void k_gj_diag(int n, double *A, size
 #pragma unroll
     for (int r = 0; r < PER; ++r)
         if (ii[r] < kb && jj[r] < kb) A[(size_t)(k0 + ii[r]) * n + k0 + jj[r]] = x[r];
+}
+__global__ __launch_bounds__(kDiagThreads) void k_gj_diag(int n, double *A, size_t stride, int k0, int *err) {
+    __shared__ double M[NB][NB + 1];
+    gj_diag_body(n, A + (size_t)blockIdx.z * stride, k0, err, M);
 }
 
 // (b) row panel: A[k, j] <- Dinv A[k, j] for columns j outside the block
@@ -235,24 +237,24 @@ __global__ __launch_bounds__(256) void k_gj_update_mfma(int n, double *A, size_t
 }
 
 // (d) column panel: A[i, k] <- -A[i, k] Dinv for rows i outside the block
-// (PT rows per workgroup).
-__global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
-    A += (size_t)blockIdx.z * stride;
-    __shared__ double Dv[NB][NB + 1];
-    __shared__ double X[PT][NB + 1];
+// (PT rows per workgroup of THREADS threads).
+template <int THREADS>
+__device__ __forceinline__ void gj_colpanel_body(int n, double *A, int k0, int tile, double (*Dv)[NB + 1],
+                                                 double (*X)[NB + 1]) {
     const int kb = min(NB, n - k0);
-    const int i0 = blockIdx.x * PT;
-    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int i0 = tile * PT;
+    for (int t = threadIdx.x; t < NB * NB; t += THREADS) {
         const int i = t / NB, j = t % NB;
         Dv[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
     }
-    for (int t = threadIdx.x; t < PT * NB; t += blockDim.x) {
+    for (int t = threadIdx.x; t < PT * NB; t += THREADS) {
         const int i = t / NB, p = t % NB;
         X[i][p] = (i0 + i < n && p < kb) ? A[(size_t)(i0 + i) * n + k0 + p] : 0.0;
     }
     __syncthreads();
     // thread (ty, tx): column tx, rows ty + RS q; Dv[p][tx] read once per p
-    constexpr int RS = 256 / NB, RQ = PT / RS;
+    constexpr int RS = THREADS / NB, RQ = PT / RS;
+    static_assert(THREADS % NB == 0 && PT % RS == 0, "whole rows per thread");
     const int tx = (int)threadIdx.x % NB, ty = (int)threadIdx.x / NB;
     double acc[RQ];
 #pragma unroll
@@ -268,6 +270,27 @@ __global__ void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
         const int row = i0 + ty + RS * q;
         if (row < n && (row < k0 || row >= k0 + kb)) A[(size_t)row * n + k0 + tx] = -acc[q];
     }
+}
+__global__ __launch_bounds__(256) void k_gj_colpanel(int n, double *A, size_t stride, int k0) {
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double X[PT][NB + 1];
+    gj_colpanel_body<256>(n, A + (size_t)blockIdx.z * stride, k0, blockIdx.x, Dv, X);
+}
+
+// (d) of step k0 together with (a) of step k0 + NB, in one launch: the column
+// panel writes columns k0 .. k0 + NB - 1 and the next diagonal block lies in
+// columns from k0 + NB on, so the two are independent, and the panel's
+// workgroups run beside the latency-bound block inversion (the last
+// workgroup of each matrix).
+__global__ __launch_bounds__(kDiagThreads) void k_gj_colpanel_diag(int n, double *A, size_t stride, int k0,
+                                                                   int *err) {
+    __shared__ double S[(NB + PT) * (NB + 1)];
+    A += (size_t)blockIdx.z * stride;
+    if (blockIdx.x == gridDim.x - 1)
+        gj_diag_body(n, A, k0 + NB, err, (double (*)[NB + 1])S);
+    else
+        gj_colpanel_body<kDiagThreads>(n, A, k0, blockIdx.x, (double (*)[NB + 1])S,
+                                       (double (*)[NB + 1])(S + NB * (NB + 1)));
 }
 
 // mu = s N (eq. visits): a workgroup per 64 columns, lane = column; its
@@ -495,12 +518,16 @@ hipError_t tail_kernel_from_Q(int n, const double *Q, double *r, double *A, hipS
 
 hipError_t tail_invert_batched(int n, double *A, size_t stride, int batch, int *err, hipStream_t st) {
     const int tiles = (n + TT - 1) / TT, ptiles = (n + PT - 1) / PT;
+    hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, 0, err);
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1, 1, batch), dim3(kDiagThreads), 0, st, n, A, stride, k0, err);
         hipLaunchKernelGGL(k_gj_rowpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
         hipLaunchKernelGGL(k_gj_update_mfma, dim3((unsigned)((size_t)tiles * tiles * batch)), dim3(256), 0, st, n, A,
                            stride, k0, batch);
-        hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
+        if (k0 + NB < n)
+            hipLaunchKernelGGL(k_gj_colpanel_diag, dim3(ptiles + 1, 1, batch), dim3(kDiagThreads), 0, st, n, A,
+                               stride, k0, err);
+        else
+            hipLaunchKernelGGL(k_gj_colpanel, dim3(ptiles, 1, batch), dim3(256), 0, st, n, A, stride, k0);
     }
     return hipGetLastError();
 }
